@@ -1,0 +1,182 @@
+/*
+ * sky.h - C ABI of the MI355X (gfx950) damped-gradient Skyrme solver.
+ *
+ * One static iteration of nuclear DFT on an equidistant periodic grid, as in
+ * Afibuzzaman, Schuetrumpf & Aktulga, "Scalable Nuclear Density Functional
+ * Theory with Sky3D" (Sec. 2, Fig. 1): h*psi with FFT derivatives, the
+ * damped gradient step (Eq. dampstep), overlap and subspace-Hamiltonian
+ * matrices (Eqs. normmatrix, hammatrix), orthonormalisation plus
+ * diagonalisation (Sec. 3.3.2-3.3.3), densities (Eqs. rho, curr, tau) and
+ * the Skyrme + Coulomb mean field (Eq. Skyrme, Sec. 2.2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Precision: all state and field data are IEEE binary64; states are
+ *   complex128 (interleaved re, im).
+ * - State layout: [state][spin][z][y][x], x fastest, spin 0 = up.  One state
+ *   of species q holds V = 2*n^3 complex values.  Field layout: [z][y][x].
+ * - Grid: cubic, n points per axis, n in {8, 16, 24, 32, 48, 64}, spacing dx
+ *   (fm), periodic; point i sits at i*dx.
+ * - Pointers named *_dev are device pointers on the device that is current
+ *   when sky_create is called; host pointers are named otherwise.  The caller
+ *   owns every buffer it passes in.  All bulk device memory of a context lives
+ *   in the caller's workspace (sky_workspace_size / sky_create); the library
+ *   allocates no device memory of its own and never frees caller memory.
+ * - Streams: every call enqueues its work on the stream given to sky_create
+ *   and returns without waiting, except sky_init_box, sky_orthonormalize and
+ *   sky_iterate, which wait for the stream (they read small results on the
+ *   host: convergence norms, particle number, residuals).
+ * - Errors: functions return SKY_OK (0) or a positive status on success and
+ *   a negative SKY_ERR_* code on failure; sky_last_error() then describes the
+ *   failure (per host thread).  No C++ exception crosses this interface.
+ * - Thread safety: one context per host thread; concurrent calls on one
+ *   context are not allowed.
+ */
+#ifndef SKY_H
+#define SKY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SKY_OK = 0,
+  SKY_NOT_CONVERGED = 1,            /* sky_iterate: max_iter reached above tol  */
+  SKY_ERR_INVALID = -1,             /* bad argument                             */
+  SKY_ERR_UNSUPPORTED_GRID = -2,    /* n not in {8,16,24,32,48,64}              */
+  SKY_ERR_WORKSPACE = -3,           /* workspace too small or misaligned        */
+  SKY_ERR_HIP = -4,                 /* a HIP runtime call failed                */
+  SKY_ERR_NOT_POSITIVE_DEFINITE = -5, /* overlap matrix not positive definite   */
+  SKY_ERR_NAN = -6                  /* non-finite residual or energy            */
+};
+
+enum { SKY_NEUTRON = 0, SKY_PROTON = 1 };
+
+/* Box, force and damping of one solve.  Skyrme parameters in the usual
+ * units: t0 MeV fm^3, t1 t2 MeV fm^5, t3 MeV fm^(3+3 alpha), W0 MeV fm^5,
+ * hb2m_* = hbar^2/2m in MeV fm^2, e2 = e^2 in MeV fm (0 switches Coulomb
+ * off).  damp_x0 is the step delta and damp_e0 the energy E0 (MeV) of the
+ * damping operator delta / (T + E0) of Eq. dampstep. */
+typedef struct {
+  int32_t n;                        /* grid points per axis                     */
+  double dx;                        /* grid spacing, fm                         */
+  int32_t n_neutrons, n_protons;    /* occupied states per species (v^2 = 1)    */
+  double t0, t1, t2, t3, x0, x1, x2, x3, alpha, W0;
+  double hb2m_n, hb2m_p, e2;
+  double damp_x0, damp_e0;
+} sky_box_desc;
+
+typedef struct {
+  int32_t iters;          /* iterations performed by this call                 */
+  double residual;        /* Delta-eps (MeV, Eq. convergence) of the states     */
+                          /* entering the last iteration                        */
+  double energy;          /* total energy after the last iteration, MeV         */
+  double energy_per_a;    /* energy / (N + Z)                                   */
+  int32_t jacobi_sweeps;  /* eigensolver sweeps of the last iteration (n + p)   */
+} sky_report;
+
+/* Views into the context's device buffers (sky_get_view). */
+enum {
+  SKY_VIEW_PSI = 0,       /* orthonormal states of species q, [n_q][2][n^3] c128 */
+  SKY_VIEW_HPSI = 1,      /* h psi of the last iteration                         */
+  SKY_VIEW_PHI = 2,       /* damped (non-orthonormal) states                     */
+  SKY_VIEW_HPHI = 3,      /* h phi                                              */
+  SKY_VIEW_DENS = 4,      /* 11 fields rho,tau,Jx,Jy,Jz,sx,sy,sz,jx,jy,jz [n^3]  */
+  SKY_VIEW_MEANFIELD = 5, /* 5 fields U,B,Wx,Wy,Wz of species q [n^3] f64        */
+  SKY_VIEW_COULOMB = 6,   /* Coulomb potential [n^3] f64 (q ignored)             */
+  SKY_VIEW_ENERGY = 7,    /* 8 f64: kin, rho, rho^(2+a), rho*tau, rho*lap rho,   */
+                          /* spin-orbit, Coulomb, total (MeV) (q ignored)        */
+  SKY_VIEW_EPS = 8,       /* Rayleigh quotients <psi|h|psi> of species q [n_q]   */
+  SKY_VIEW_RITZ = 9,      /* ascending subspace eigenvalues of species q [n_q]   */
+  SKY_VIEW_R2 = 10,       /* ||h psi - eps psi||^2 of species q [n_q]            */
+  /* Subspace matrices of the last sky_orthonormalize / iteration, complex128
+   * [n_q][n_q] row-major, valid for the species q of that call:          */
+  SKY_VIEW_OVERLAP = 11,  /* I = <phi|phi> (Eq. normmatrix)                      */
+  SKY_VIEW_HSUB = 12,     /* H = <phi|h phi> (Eq. hammatrix); unset by Loewdin   */
+  SKY_VIEW_EVEC = 13,     /* eigenvectors (columns) of H' (or of I for Loewdin)  */
+  SKY_VIEW_UMAT = 14      /* combined transform U, psi = phi U                   */
+};
+
+typedef struct sky_ctx sky_ctx;
+
+/* Bytes of device workspace a context for `d` needs (256-byte aligned). */
+int sky_workspace_size(const sky_box_desc* d, size_t* bytes);
+
+/* Create a context.  workspace_dev: caller-owned device buffer of at least
+ * sky_workspace_size bytes, 256-byte aligned, alive until sky_destroy.
+ * stream: hipStream_t (NULL = the default stream).  Errors: INVALID,
+ * UNSUPPORTED_GRID, WORKSPACE. */
+int sky_create(const sky_box_desc* d, void* workspace_dev, size_t bytes, void* stream,
+               sky_ctx** out);
+
+/* Fig. 1 step 1 (Sec. 2.2: trial plane waves for periodic systems): take
+ * caller trial states raw_n_dev [n_neutrons][2][n^3] and raw_p_dev
+ * [n_protons][2][n^3] (complex128, need not be orthonormal; read only),
+ * orthonormalise them by Loewdin's C = I^(-1/2) (Eqs. Loewedin, orthmatvec),
+ * then build densities, mean field and energy.  Waits for the stream.
+ * Errors: INVALID, NOT_POSITIVE_DEFINITE (linearly dependent states), HIP. */
+int sky_init_box(sky_ctx* c, const void* raw_n_dev, const void* raw_p_dev);
+
+/* h psi for `nstates` states of species q with the context's current mean
+ * field (Sec. 2.2: kinetic + Skyrme + Coulomb, FFT derivatives):
+ *   h psi = U psi - sum_m d_m(B d_m psi) + (i/2) sum_m [A_m d_m psi + d_m(A_m psi)],
+ *   A_m = (W x sigma)_m.
+ * psi_dev, hpsi_dev: [nstates][2][n^3] c128, must not overlap.  eps_dev (may
+ * be NULL): receives Re <psi|h psi> per state (f64, nstates).  Asynchronous. */
+int sky_apply_h(sky_ctx* c, int32_t q, const void* psi_dev, void* hpsi_dev, int32_t nstates,
+                double* eps_dev);
+
+/* Damped gradient step, Eq. dampstep:
+ *   phi = psi - x0 F^-1[ F(h psi - eps psi) / (E0 + hb2m_q |k|^2) ],
+ * eps_dev: <psi|h psi> per state (from sky_apply_h).  r2_dev (f64, nstates)
+ * receives ||h psi - eps psi||^2, the per-state term of Eq. convergence.
+ * phi_dev must not overlap psi_dev or hpsi_dev.  Asynchronous. */
+int sky_damped_step(sky_ctx* c, int32_t q, const void* psi_dev, const void* hpsi_dev,
+                    const double* eps_dev, void* phi_dev, int32_t nstates, double* r2_dev);
+
+/* Orthonormalise (and diagonalise) the n_q states phi_dev of species q into
+ * psi_out_dev (must not overlap phi_dev).
+ * hphi_dev != NULL: Sec. 3.3.2-3.3.3 as a generalised Rayleigh-Ritz step:
+ *   I = <phi|phi>, H = <phi|h phi> (lower triangles, Fig. 3), I = L L^H,
+ *   H' = L^-1 H L^-H = Z diag(lam) Z^H (ascending), psi = phi (L^-H Z);
+ *   ritz_dev (may be NULL) receives lam (f64, n_q).
+ * hphi_dev == NULL: Loewdin, psi = phi I^(-1/2).
+ * Waits for the stream.  Errors: NOT_POSITIVE_DEFINITE, HIP. */
+int sky_orthonormalize(sky_ctx* c, int32_t q, const void* phi_dev, const void* hphi_dev,
+                       void* psi_out_dev, double* ritz_dev);
+
+/* Fig. 1 steps 4a-4b and the energy: densities rho, tau, J (+ spin and
+ * current diagnostics) of the context's current states of both species
+ * (Eqs. rho, curr, tau with v^2 = 1), mean fields U, B, W, the Coulomb
+ * potential and the total energy.  Asynchronous. */
+int sky_densities(sky_ctx* c);
+
+/* Run up to max_iter damped-gradient iterations (Fig. 1 steps 2-5) on the
+ * context's states.  tol_mev > 0: stop once Delta-eps <= tol_mev (returns
+ * SKY_OK), else SKY_NOT_CONVERGED after max_iter; tol_mev <= 0: run exactly
+ * max_iter iterations.  report (host, may be NULL) is filled.  Waits for the
+ * stream.  Errors: NAN, NOT_POSITIVE_DEFINITE, HIP. */
+int sky_iterate(sky_ctx* c, int32_t max_iter, double tol_mev, sky_report* report);
+
+/* Device pointer and element count (complex or f64 elements, see SKY_VIEW_*)
+ * of one of the context's buffers.  The memory stays owned by the caller's
+ * workspace. */
+int sky_get_view(sky_ctx* c, int32_t what, int32_t q, void** ptr_dev, int64_t* count);
+
+/* Wait for all work of the context's stream. */
+int sky_sync(sky_ctx* c);
+
+/* Description of the last failure on this host thread ("" if none). */
+const char* sky_last_error(void);
+
+/* Free host-side state of the context (not the caller's workspace). */
+void sky_destroy(sky_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKY_H */

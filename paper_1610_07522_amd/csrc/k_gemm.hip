@@ -1,0 +1,300 @@
+// Dense complex FP64 products on the FP64 matrix cores (MFMA 16x16x4).
+//
+// Sec. 3.3.1: the overlap I = <phi|phi> and subspace Hamiltonian
+// H = <phi|h phi> are inner products of all state pairs, computed for the
+// lower triangle only (Fig. 3).  Sec. 3.3.3: the orthonormalised, diagonal
+// states are built with one product psi = phi (C Z) (step 3e).
+//
+// One workgroup (4 waves, 2x2) owns a 64x64 complex output tile; each wave a
+// 32x32 tile = 2x2 MFMA blocks, with separate real/imaginary accumulators.
+// Operand tiles of KC complex values along the contraction are staged in LDS
+// as [row][k] for A (M x K) and [col][k] for B (N x K).
+#include "sky_kernels.h"
+
+namespace sky {
+
+namespace {
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int TM = 64;      // tile rows / cols
+constexpr int KC = 16;      // contraction chunk (complex)
+constexpr int KP = KC + 1;  // padded LDS row
+constexpr int GT = 256;     // threads
+
+struct Acc {
+  d4 re[2][2], im[2][2];
+};
+
+__device__ inline void acc_zero(Acc& a) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      a.re[i][j] = d4{0, 0, 0, 0};
+      a.im[i][j] = d4{0, 0, 0, 0};
+    }
+}
+
+// acc += op(A tile) * B tile^T over KC, where A is conjugated if CONJA.
+// sA[row][k], sB[col][k] (complex as double2).
+template <bool CONJA>
+__device__ inline void mfma_tile(Acc& acc, const double2* sA, const double2* sB, int wm, int wn,
+                                 int lane) {
+  const int r = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < KC; kk += 4) {
+    double2 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a[i] = sA[(wm * 32 + i * 16 + r) * KP + kk + kq];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) b[j] = sB[(wn * 32 + j * 16 + r) * KP + kk + kq];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const double ai = CONJA ? -a[i].y : a[i].y;
+        // (ar + i ai)(br + i bi) = ar br - ai bi + i (ar bi + ai br)
+        acc.re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, acc.re[i][j], 0, 0, 0);
+        acc.re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, b[j].y, acc.re[i][j], 0, 0, 0);
+        acc.im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].y, acc.im[i][j], 0, 0, 0);
+        acc.im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b[j].x, acc.im[i][j], 0, 0, 0);
+      }
+  }
+}
+
+// Element (row, col) within the 64x64 tile held by this lane for block
+// (i, j), register e.  The FP64 16x16x4 MFMA of gfx950 returns output row
+// 4*e + lane/16, column lane%16 in register e of each lane (measured):
+// row = wm*32 + i*16 + 4*e + lane/16, col = wn*32 + j*16 + lane%16.
+template <typename F>
+__device__ inline void acc_foreach(const Acc& acc, int wm, int wn, int lane, F f) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int row = wm * 32 + i * 16 + 4 * e + (lane >> 4);
+        int col = wn * 32 + j * 16 + (lane & 15);
+        f(row, col, acc.re[i][j][e], acc.im[i][j][e]);
+      }
+}
+
+// Lower-triangle tile pair number p -> (ta, tb), ta >= tb.
+__device__ inline void tri_pair(int p, int& ta, int& tb) {
+  int a = int((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+  while ((a + 1) * (a + 2) / 2 <= p) ++a;
+  while (a * (a + 1) / 2 > p) --a;
+  ta = a;
+  tb = p - a * (a + 1) / 2;
+}
+
+// ----------------------------------------------------------- overlap (lower)
+// part[(z*npair + pair)*split + s][64*64] = sum over chunk s of conj(A) B^T.
+__global__ void __launch_bounds__(GT)
+k_overlap_lower(const double2* __restrict__ A, const double2* __restrict__ B0,
+                const double2* __restrict__ B1, int m, long k, int split, double2* __restrict__ part) {
+  __shared__ double2 sA[TM * KP];
+  __shared__ double2 sB[TM * KP];
+  const int npair = gridDim.x;
+  const int pair = blockIdx.x, s = blockIdx.y, z = blockIdx.z;
+  const double2* B = z ? B1 : B0;
+  int ta, tb;
+  tri_pair(pair, ta, tb);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const long nck = k / KC;
+  const long c0 = nck * s / split, c1 = nck * (s + 1) / split;
+  // loader: thread -> (row, 4 consecutive complex)
+  const int lrow = tid >> 2, lk = (tid & 3) * 4;
+  const int ga = ta * TM + lrow, gb = tb * TM + lrow;
+  Acc acc;
+  acc_zero(acc);
+  for (long c = c0; c < c1; ++c) {
+    const long k0 = c * KC + lk;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      sA[lrow * KP + lk + e] = ga < m ? A[size_t(ga) * k + k0 + e] : make_double2(0, 0);
+      sB[lrow * KP + lk + e] = gb < m ? B[size_t(gb) * k + k0 + e] : make_double2(0, 0);
+    }
+    __syncthreads();
+    mfma_tile<true>(acc, sA, sB, wm, wn, lane);
+    __syncthreads();
+  }
+  double2* out = part + (size_t(z) * npair + pair) * split * TM * TM + size_t(s) * TM * TM;
+  acc_foreach(acc, wm, wn, lane, [&](int row, int col, double re, double im) {
+    out[row * TM + col] = make_double2(re, im);
+  });
+}
+
+// C[a][b] = scale * sum_s part[..][s][..] for the lower tiles.
+__global__ void k_overlap_reduce(const double2* __restrict__ part, int npair, int split, int m,
+                                 double scale, double2* __restrict__ C0, double2* __restrict__ C1) {
+  const int pair = blockIdx.x, z = blockIdx.y;
+  double2* C = z ? C1 : C0;
+  int ta, tb;
+  tri_pair(pair, ta, tb);
+  const double2* p = part + (size_t(z) * npair + pair) * split * TM * TM;
+  for (int e = threadIdx.x; e < TM * TM; e += blockDim.x) {
+    int row = ta * TM + e / TM, col = tb * TM + e % TM;
+    if (row >= m || col >= m) continue;
+    double re = 0.0, im = 0.0;
+    for (int s = 0; s < split; ++s) {
+      double2 v = p[size_t(s) * TM * TM + e];
+      re += v.x;
+      im += v.y;
+    }
+    C[size_t(row) * m + col] = make_double2(scale * re, scale * im);
+  }
+}
+
+__global__ void k_hermitian_fill(double2* __restrict__ C, int m) {
+  const int row = blockIdx.y * 16 + threadIdx.y, col = blockIdx.x * 16 + threadIdx.x;
+  if (row >= m || col >= m) return;
+  if (col > row) {
+    double2 v = C[size_t(col) * m + row];
+    C[size_t(row) * m + col] = make_double2(v.x, -v.y);
+  } else if (col == row) {
+    C[size_t(row) * m + col].y = 0.0;
+  }
+}
+
+// ----------------------------------------------------------- combine
+// Y[b][v] = sum_a U[a][b] X[a][v]: M = b (rows of Y), N = v, K = a.
+__global__ void __launch_bounds__(GT)
+k_combine(const double2* __restrict__ X, const double2* __restrict__ U, double2* __restrict__ Y,
+          int m, long k) {
+  __shared__ double2 sA[TM * KP];   // [b][a]
+  __shared__ double2 sB[TM * KP];   // [v][a]
+  const long v0 = long(blockIdx.x) * TM;
+  const int b0 = blockIdx.y * TM;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  // loader: thread -> (a within chunk = tid/16, 4 consecutive columns)
+  const int la = tid >> 4, lc = (tid & 15) * 4;
+  Acc acc;
+  acc_zero(acc);
+  for (int a0 = 0; a0 < m; a0 += KC) {
+    const int a = a0 + la;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int b = b0 + lc + e;
+      sA[(lc + e) * KP + la] = (a < m && b < m) ? U[size_t(a) * m + b] : make_double2(0, 0);
+      sB[(lc + e) * KP + la] = (a < m) ? X[size_t(a) * k + v0 + lc + e] : make_double2(0, 0);
+    }
+    __syncthreads();
+    mfma_tile<false>(acc, sA, sB, wm, wn, lane);
+    __syncthreads();
+  }
+  acc_foreach(acc, wm, wn, lane, [&](int row, int col, double re, double im) {
+    const int b = b0 + row;
+    if (b < m) Y[size_t(b) * k + v0 + col] = make_double2(re, im);
+  });
+}
+
+// ----------------------------------------------------------- square products
+// C = op(A) op(B), op 0 = N, 1 = conjugate transpose; all m x m row-major.
+template <int OPA, int OPB>
+__global__ void __launch_bounds__(GT)
+k_gemm_square(const double2* __restrict__ A, const double2* __restrict__ B,
+              double2* __restrict__ C, int m) {
+  __shared__ double2 sA[TM * KP];   // [row][k] of op(A)
+  __shared__ double2 sB[TM * KP];   // [col][k] of op(B)
+  const int r0 = blockIdx.y * TM, c0 = blockIdx.x * TM;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  Acc acc;
+  acc_zero(acc);
+  for (int k0 = 0; k0 < m; k0 += KC) {
+    for (int e = tid; e < TM * KC; e += GT) {
+      // element (row or col index t, contraction index kk)
+      int t = e / KC, kk = e % KC;
+      int kg = k0 + kk;
+      // op(A)[r][kg]
+      {
+        int r = r0 + t;
+        double2 v = make_double2(0, 0);
+        if (r < m && kg < m) {
+          if (OPA == 0) v = A[size_t(r) * m + kg];
+          else { v = A[size_t(kg) * m + r]; v.y = -v.y; }
+        }
+        sA[t * KP + kk] = v;
+      }
+      // op(B)[kg][c]
+      {
+        int c = c0 + t;
+        double2 v = make_double2(0, 0);
+        if (c < m && kg < m) {
+          if (OPB == 0) v = B[size_t(kg) * m + c];
+          else { v = B[size_t(c) * m + kg]; v.y = -v.y; }
+        }
+        sB[t * KP + kk] = v;
+      }
+    }
+    __syncthreads();
+    mfma_tile<false>(acc, sA, sB, wm, wn, lane);
+    __syncthreads();
+  }
+  acc_foreach(acc, wm, wn, lane, [&](int row, int col, double re, double im) {
+    const int r = r0 + row, c = c0 + col;
+    if (r < m && c < m) C[size_t(r) * m + c] = make_double2(re, im);
+  });
+}
+
+int overlap_split(int m, long k) {
+  const int nt = (m + TM - 1) / TM;
+  const int npair = nt * (nt + 1) / 2;
+  long nck = k / KC;
+  int split = (2048 + 2 * npair - 1) / (2 * npair);
+  if (split < 1) split = 1;
+  if (split > nck) split = int(nck);
+  if (split > 64) split = 64;
+  return split;
+}
+}  // namespace
+
+size_t overlap_scratch_bytes(int m, long k) {
+  const int nt = (m + TM - 1) / TM;
+  const int npair = nt * (nt + 1) / 2;
+  return size_t(overlap_split(m, k)) * 2 * npair * TM * TM * sizeof(double2);
+}
+
+void overlap_lower(const void* A, const void* B0, const void* B1, int m, long k, double scale,
+                   void* C0, void* C1, void* part, hipStream_t st) {
+  if (m <= 0) return;
+  const int nt = (m + TM - 1) / TM;
+  const int npair = nt * (nt + 1) / 2;
+  const int split = overlap_split(m, k);
+  const int nz = B1 ? 2 : 1;
+  hipLaunchKernelGGL(k_overlap_lower, dim3(npair, split, nz), dim3(GT), 0, st,
+                     (const double2*)A, (const double2*)B0, (const double2*)B1, m, k, split,
+                     (double2*)part);
+  hipLaunchKernelGGL(k_overlap_reduce, dim3(npair, nz), dim3(256), 0, st, (const double2*)part,
+                     npair, split, m, scale, (double2*)C0, (double2*)C1);
+}
+
+void hermitian_fill(void* C, int m, hipStream_t st) {
+  if (m <= 0) return;
+  dim3 grid((m + 15) / 16, (m + 15) / 16), block(16, 16);
+  hipLaunchKernelGGL(k_hermitian_fill, grid, block, 0, st, (double2*)C, m);
+}
+
+void combine(const void* X, const void* U, void* Y, int m, long k, hipStream_t st) {
+  if (m <= 0) return;
+  dim3 grid(unsigned(k / TM), (m + TM - 1) / TM);
+  hipLaunchKernelGGL(k_combine, grid, dim3(GT), 0, st, (const double2*)X, (const double2*)U,
+                     (double2*)Y, m, k);
+}
+
+void gemm_square(const void* A, int opA, const void* B, int opB, void* C, int m, hipStream_t st) {
+  if (m <= 0) return;
+  dim3 grid((m + TM - 1) / TM, (m + TM - 1) / TM);
+  auto a = (const double2*)A;
+  auto b = (const double2*)B;
+  auto c = (double2*)C;
+  if (opA == 0 && opB == 0) hipLaunchKernelGGL((k_gemm_square<0, 0>), grid, dim3(GT), 0, st, a, b, c, m);
+  else if (opA == 0 && opB == 1) hipLaunchKernelGGL((k_gemm_square<0, 1>), grid, dim3(GT), 0, st, a, b, c, m);
+  else if (opA == 1 && opB == 0) hipLaunchKernelGGL((k_gemm_square<1, 0>), grid, dim3(GT), 0, st, a, b, c, m);
+  else hipLaunchKernelGGL((k_gemm_square<1, 1>), grid, dim3(GT), 0, st, a, b, c, m);
+}
+
+}  // namespace sky

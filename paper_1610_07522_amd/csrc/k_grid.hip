@@ -1,0 +1,519 @@
+// Grid kernels on the spinor wave functions: h*psi, the damped gradient
+// step, and the local densities.  All are passes over lines of one axis
+// (fft_line.h); one workgroup takes LPW lines of one state (h, damping) or of
+// a chunk of states (densities).
+#include "fft_line.h"
+#include "sky_kernels.h"
+
+namespace sky {
+
+// Spin-orbit matrix A_dir = (W x sigma)_dir = ax*sx + ay*sy + az*sz.
+template <int DIR> __device__ inline void so_coeffs(double wx, double wy, double wz,
+                                                    double& ax, double& ay, double& az) {
+  if (DIR == 0) { ax = 0.0; ay = -wz; az = wy; }
+  else if (DIR == 1) { ax = wz; ay = 0.0; az = -wx; }
+  else { ax = -wy; ay = wx; az = 0.0; }
+}
+
+// (a.sigma) chi for a real 3-vector a.
+template <typename T> __device__ inline void sigma_apply(T ax, T ay, T az, cpx<T> u, cpx<T> d,
+                                                         cpx<T>& ou, cpx<T>& od) {
+  // [[az, ax - i ay], [ax + i ay, -az]]
+  cpx<T> xm = mk(ax, -ay), xp = mk(ax, ay);
+  ou = az * u + xm * d;
+  od = xp * u - az * d;
+}
+
+// Workgroup sum of one double per thread (blockDim <= 256), result in thread 0.
+__device__ inline double block_sum(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; ++w) s += red[w];
+  }
+  __syncthreads();
+  return s;
+}
+
+// ------------------------------------------------------------------ h * psi
+// One pass adds the DIR part of h:
+//   - D(B D psi) + (i/2) [A D psi + D(A psi)]  =  D g + (i/2) A D psi,
+//   g = -B D psi + (i/2) A psi,
+// plus U psi on the first pass.  The last pass also forms per-workgroup
+// partial sums of <psi|h psi> for the Rayleigh quotients.
+template <typename T, int N, int DIR, bool FIRST, bool LAST>
+__global__ void __launch_bounds__(LineCfg<N>::THREADS)
+k_h_pass(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPtrs mf,
+         GridArgs g, double* __restrict__ eps_part) {
+  using C = LineCfg<N>;
+  using F = LineFFT<T, N, 2>;
+  constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> Ybuf[C::LPW * F::YSIZE];
+  __shared__ double red[4];
+  load_twiddles<T, N>(tw);
+
+  int line, j;
+  thread_role<N, DIR>(threadIdx.x, line, j);
+  const int L = blockIdx.x * C::LPW + line;
+  int base, stride, a, b;
+  line_geom<N, DIR>(L, base, stride, a, b);
+  const size_t soff = size_t(blockIdx.y) * 2 * N3;
+  const cpx<T>* p = psi + soff;
+  cpx<T>* hp = hpsi + soff;
+  cpx<T>* Y = Ybuf + line * F::YSIZE;
+  const T kunit = T(g.kunit);
+
+  cpx<T> v[2][R1], d[2][R1];
+  if (j < R2) {
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1) {
+      int r = base + (j + R2 * j1) * stride;
+      v[0][j1] = p[r];
+      v[1][j1] = p[N3 + r];
+      d[0][j1] = v[0][j1];
+      d[1][j1] = v[1][j1];
+    }
+  }
+  F::deriv(d, Y, j, tw, kunit);
+
+  // g (into d) and the accumulated local terms (into acc)
+  cpx<T> acc[2][R1];
+  if (j < R2) {
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1) {
+      int r = base + (j + R2 * j1) * stride;
+      T B = T(mf.B[r]);
+      double ax, ay, az;
+      so_coeffs<DIR>(mf.W[r], mf.W[N3 + r], mf.W[2 * N3 + r], ax, ay, az);
+      cpx<T> au, ad, bu, bd;
+      sigma_apply<T>(T(ax), T(ay), T(az), d[0][j1], d[1][j1], au, ad);     // A D psi
+      sigma_apply<T>(T(ax), T(ay), T(az), v[0][j1], v[1][j1], bu, bd);     // A psi
+      acc[0][j1] = T(0.5) * mul_i(au);
+      acc[1][j1] = T(0.5) * mul_i(ad);
+      if (FIRST) {
+        T U = T(mf.U[r]);
+        acc[0][j1] = acc[0][j1] + U * v[0][j1];
+        acc[1][j1] = acc[1][j1] + U * v[1][j1];
+      }
+      d[0][j1] = T(0.5) * mul_i(bu) - B * d[0][j1];
+      d[1][j1] = T(0.5) * mul_i(bd) - B * d[1][j1];
+    }
+  }
+  F::deriv(d, Y, j, tw, kunit);
+
+  double dot = 0.0;
+  if (j < R2) {
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1) {
+      int r = base + (j + R2 * j1) * stride;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        cpx<T> t = acc[s][j1] + d[s][j1];
+        if (!FIRST) t = t + hp[s * N3 + r];
+        hp[s * N3 + r] = t;
+        if (LAST) dot += double(v[s][j1].re) * double(t.re) + double(v[s][j1].im) * double(t.im);
+      }
+    }
+  }
+  if (LAST && eps_part != nullptr) {
+    double sum = block_sum(dot, red);
+    if (threadIdx.x == 0) eps_part[size_t(blockIdx.y) * gridDim.x + blockIdx.x] = sum * g.dV;
+  }
+}
+
+// Sum the per-workgroup partials of each state: out[s] = sum_t part[s][t].
+__global__ void k_sum_partials(const double* __restrict__ part, int ntile, int nstate,
+                               double* __restrict__ out) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nstate) return;
+  double acc = 0.0;
+  for (int t = 0; t < ntile; ++t) acc += part[size_t(s) * ntile + t];
+  out[s] = acc;
+}
+
+// ------------------------------------------------------------------ damping
+// phi = psi - F^-1[ x0 F(h psi - eps psi) / (E0 + hb2m |k|^2) ], done as
+// forward x, forward y, (forward z, filter, inverse z), inverse y, inverse x,
+// in place in the phi buffer.  The first pass also forms ||r||^2 partials.
+struct DampArgs {
+  double x0, e0, hb2m;
+};
+
+// pass 0: r = h psi - eps psi, forward FFT along x, store spectrum.
+template <typename T, int N>
+__global__ void __launch_bounds__(LineCfg<N>::THREADS)
+k_damp_fwd_x(const cpx<T>* __restrict__ psi, const cpx<T>* __restrict__ hpsi,
+             const double* __restrict__ eps, cpx<T>* __restrict__ out, GridArgs g,
+             double* __restrict__ r2_part) {
+  using C = LineCfg<N>;
+  using F = LineFFT<T, N, 2>;
+  constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> Ybuf[C::LPW * F::YSIZE];
+  __shared__ double red[4];
+  load_twiddles<T, N>(tw);
+  int line, j;
+  thread_role<N, 0>(threadIdx.x, line, j);
+  const int L = blockIdx.x * C::LPW + line;
+  int base, stride, a, b;
+  line_geom<N, 0>(L, base, stride, a, b);
+  const size_t soff = size_t(blockIdx.y) * 2 * N3;
+  const T e = T(eps[blockIdx.y]);
+  cpx<T> va[2][R1], vb[2][R2];
+  double r2 = 0.0;
+  if (j < R2) {
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1) {
+      int r = base + (j + R2 * j1) * stride;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        cpx<T> h = hpsi[soff + s * N3 + r], p = psi[soff + s * N3 + r];
+        cpx<T> res = h - e * p;
+        r2 += double(res.re) * double(res.re) + double(res.im) * double(res.im);
+        va[s][j1] = res;
+      }
+    }
+  }
+  F::forward(va, vb, Ybuf + line * F::YSIZE, j, tw);
+  if (j < R1) {
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) {
+      int r = base + (j + R1 * k2) * stride;
+      out[soff + r] = vb[0][k2];
+      out[soff + N3 + r] = vb[1][k2];
+    }
+  }
+  double sum = block_sum(r2, red);
+  if (threadIdx.x == 0) r2_part[size_t(blockIdx.y) * gridDim.x + blockIdx.x] = sum * g.dV;
+}
+
+// forward (INV = false) or inverse (INV = true) FFT along y, in place.
+template <typename T, int N, bool INV>
+__global__ void __launch_bounds__(LineCfg<N>::THREADS)
+k_damp_y(cpx<T>* __restrict__ buf) {
+  using C = LineCfg<N>;
+  using F = LineFFT<T, N, 2>;
+  constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> Ybuf[C::LPW * F::YSIZE];
+  load_twiddles<T, N>(tw);
+  int line, j;
+  thread_role<N, 1>(threadIdx.x, line, j);
+  const int L = blockIdx.x * C::LPW + line;
+  int base, stride, a, b;
+  line_geom<N, 1>(L, base, stride, a, b);
+  cpx<T>* p = buf + size_t(blockIdx.y) * 2 * N3;
+  cpx<T> va[2][R1], vb[2][R2];
+  cpx<T>* Y = Ybuf + line * F::YSIZE;
+  if (!INV) {
+    if (j < R2)
+#pragma unroll
+      for (int j1 = 0; j1 < R1; ++j1)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) va[s][j1] = p[s * N3 + base + (j + R2 * j1) * stride];
+    F::forward(va, vb, Y, j, tw);
+    if (j < R1)
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) p[s * N3 + base + (j + R1 * k2) * stride] = vb[s][k2];
+  } else {
+    if (j < R1)
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) vb[s][k2] = p[s * N3 + base + (j + R1 * k2) * stride];
+    F::inverse(vb, va, Y, j, tw);
+    if (j < R2)
+#pragma unroll
+      for (int j1 = 0; j1 < R1; ++j1)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) p[s * N3 + base + (j + R2 * j1) * stride] = va[s][j1];
+  }
+}
+
+// forward FFT along z, multiply by x0 / (E0 + hb2m |k|^2), inverse along z.
+// The line's x and y indices are frequency indices at this point.
+template <typename T, int N>
+__global__ void __launch_bounds__(LineCfg<N>::THREADS)
+k_damp_z(cpx<T>* __restrict__ buf, GridArgs g, DampArgs d) {
+  using C = LineCfg<N>;
+  using F = LineFFT<T, N, 2>;
+  constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> Ybuf[C::LPW * F::YSIZE];
+  load_twiddles<T, N>(tw);
+  int line, j;
+  thread_role<N, 2>(threadIdx.x, line, j);
+  const int L = blockIdx.x * C::LPW + line;
+  int base, stride, a, b;
+  line_geom<N, 2>(L, base, stride, a, b);
+  cpx<T>* p = buf + size_t(blockIdx.y) * 2 * N3;
+  cpx<T>* Y = Ybuf + line * F::YSIZE;
+  cpx<T> va[2][R1], vb[2][R2];
+  if (j < R2)
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) va[s][j1] = p[s * N3 + base + (j + R2 * j1) * stride];
+  F::forward(va, vb, Y, j, tw);
+  if (j < R1) {
+    double kx = g.kunit * double(a < N / 2 ? a : a - N);
+    double ky = g.kunit * double(b < N / 2 ? b : b - N);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) {
+      int f = j + R1 * k2;
+      double kz = g.kunit * double(f < N / 2 ? f : f - N);
+      T m = T(d.x0 / (d.e0 + d.hb2m * (kx * kx + ky * ky + kz * kz)));
+#pragma unroll
+      for (int s = 0; s < 2; ++s) vb[s][k2] = m * vb[s][k2];
+    }
+  }
+  F::inverse(vb, va, Y, j, tw);
+  if (j < R2)
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) p[s * N3 + base + (j + R2 * j1) * stride] = va[s][j1];
+}
+
+// inverse FFT along x and phi = psi - (damped residual), in place in buf.
+template <typename T, int N>
+__global__ void __launch_bounds__(LineCfg<N>::THREADS)
+k_damp_inv_x(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ buf) {
+  using C = LineCfg<N>;
+  using F = LineFFT<T, N, 2>;
+  constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> Ybuf[C::LPW * F::YSIZE];
+  load_twiddles<T, N>(tw);
+  int line, j;
+  thread_role<N, 0>(threadIdx.x, line, j);
+  const int L = blockIdx.x * C::LPW + line;
+  int base, stride, a, b;
+  line_geom<N, 0>(L, base, stride, a, b);
+  const size_t soff = size_t(blockIdx.y) * 2 * N3;
+  cpx<T>* Y = Ybuf + line * F::YSIZE;
+  cpx<T> va[2][R1], vb[2][R2];
+  if (j < R1)
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) vb[s][k2] = buf[soff + s * N3 + base + (j + R1 * k2) * stride];
+  F::inverse(vb, va, Y, j, tw);
+  if (j < R2)
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        size_t r = soff + s * N3 + base + (j + R2 * j1) * stride;
+        buf[r] = psi[r] - va[s][j1];
+      }
+}
+
+// ------------------------------------------------------------------ densities
+// Pass DIR over a chunk of states accumulates, at every point, the terms of
+// rho, tau, J (and the diagnostics s, j) that need d/d(DIR) psi:
+//   x: rho, s_x, s_y, s_z, tau_x, j_x, J_y(x), J_z(x)          (slots 0..7)
+//   y: tau_y, j_y, J_x(y), J_z(y)                              (slots 8..11)
+//   z: tau_z, j_z, J_x(z), J_y(z)                              (slots 12..15)
+// with J_k = sum_lm eps_klm Im(psi^dag sigma_m d_l psi).  Partial sums per
+// state chunk go to part[chunk][slot][point] and are reduced in fixed order.
+template <typename T, int N, int DIR>
+__global__ void __launch_bounds__(LineCfg<N>::THREADS)
+k_dens_pass(const cpx<T>* __restrict__ psi, int nstate, int chunk, GridArgs g,
+            double* __restrict__ part) {
+  using C = LineCfg<N>;
+  using F = LineFFT<T, N, 2>;
+  constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
+  constexpr int NS = DIR == 0 ? 8 : 4;
+  constexpr int SLOT0 = DIR == 0 ? 0 : (DIR == 1 ? 8 : 12);
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> Ybuf[C::LPW * F::YSIZE];
+  load_twiddles<T, N>(tw);
+  int line, j;
+  thread_role<N, DIR>(threadIdx.x, line, j);
+  const int L = blockIdx.x * C::LPW + line;
+  int base, stride, a, b;
+  line_geom<N, DIR>(L, base, stride, a, b);
+  cpx<T>* Y = Ybuf + line * F::YSIZE;
+  const T kunit = T(g.kunit);
+
+  double acc[NS][R1];
+#pragma unroll
+  for (int q = 0; q < NS; ++q)
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1) acc[q][j1] = 0.0;
+
+  const int s0 = blockIdx.y * chunk;
+  const int s1 = min(nstate, s0 + chunk);
+  for (int st = s0; st < s1; ++st) {
+    const cpx<T>* p = psi + size_t(st) * 2 * N3;
+    cpx<T> v[2][R1], d[2][R1];
+    if (j < R2) {
+#pragma unroll
+      for (int j1 = 0; j1 < R1; ++j1) {
+        int r = base + (j + R2 * j1) * stride;
+        v[0][j1] = p[r];
+        v[1][j1] = p[N3 + r];
+        d[0][j1] = v[0][j1];
+        d[1][j1] = v[1][j1];
+      }
+    }
+    F::deriv(d, Y, j, tw, kunit);
+    if (j < R2) {
+#pragma unroll
+      for (int j1 = 0; j1 < R1; ++j1) {
+        cpx<T> u = v[0][j1], w = v[1][j1], du = d[0][j1], dw = d[1][j1];
+        // psi^dag sigma d psi for the three Pauli matrices
+        cpx<T> sx = conj(u) * dw + conj(w) * du;
+        cpx<T> sy = mul_i(conj(w) * du - conj(u) * dw);
+        cpx<T> sz = conj(u) * du - conj(w) * dw;
+        double tau = double(norm2(du)) + double(norm2(dw));
+        double cur = double((conj(u) * du).im) + double((conj(w) * dw).im);
+        if (DIR == 0) {
+          cpx<T> sxy = conj(u) * w;                 // psi^dag sigma psi pieces
+          acc[0][j1] += double(norm2(u)) + double(norm2(w));
+          acc[1][j1] += 2.0 * double(sxy.re);
+          acc[2][j1] += 2.0 * double(sxy.im);
+          acc[3][j1] += double(norm2(u)) - double(norm2(w));
+          acc[4][j1] += tau;
+          acc[5][j1] += cur;
+          acc[6][j1] -= double(sz.im);             // J_y += eps_yxz Im(sz) = -Im
+          acc[7][j1] += double(sy.im);             // J_z += eps_zxy Im(sy) = +Im
+        } else if (DIR == 1) {
+          acc[0][j1] += tau;
+          acc[1][j1] += cur;
+          acc[2][j1] += double(sz.im);             // J_x += eps_xyz Im(sz)
+          acc[3][j1] -= double(sx.im);             // J_z += eps_zyx Im(sx)
+        } else {
+          acc[0][j1] += tau;
+          acc[1][j1] += cur;
+          acc[2][j1] -= double(sy.im);             // J_x += eps_xzy Im(sy)
+          acc[3][j1] += double(sx.im);             // J_y += eps_yzx Im(sx)
+        }
+      }
+    }
+  }
+  if (j < R2) {
+    double* out = part + size_t(blockIdx.y) * 16 * N3;
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1) {
+      int r = base + (j + R2 * j1) * stride;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) out[size_t(SLOT0 + q) * N3 + r] = acc[q][j1];
+    }
+  }
+}
+
+// rho, tau, J[3], s[3], j[3] (11 fields) from the chunk partials.
+__global__ void k_dens_reduce(const double* __restrict__ part, int nchunk, int n3,
+                              double* __restrict__ dens) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n3) return;
+  double q[16];
+  for (int k = 0; k < 16; ++k) q[k] = 0.0;
+  for (int c = 0; c < nchunk; ++c) {
+    const double* p = part + size_t(c) * 16 * n3 + r;
+    for (int k = 0; k < 16; ++k) q[k] += p[size_t(k) * n3];
+  }
+  double* o = dens;
+  o[0 * n3 + r] = q[0];                       // rho
+  o[1 * n3 + r] = q[4] + q[8] + q[12];        // tau
+  o[2 * n3 + r] = q[10] + q[14];              // J_x
+  o[3 * n3 + r] = q[6] + q[15];               // J_y
+  o[4 * n3 + r] = q[7] + q[11];               // J_z
+  o[5 * n3 + r] = q[1];                       // s_x
+  o[6 * n3 + r] = q[2];                       // s_y
+  o[7 * n3 + r] = q[3];                       // s_z
+  o[8 * n3 + r] = q[5];                       // j_x
+  o[9 * n3 + r] = q[9];                       // j_y
+  o[10 * n3 + r] = q[13];                     // j_z
+}
+
+// ------------------------------------------------------------------ launchers
+template <int N> static int ntiles() { return N * N / LineCfg<N>::LPW; }
+
+template <typename T, int N>
+static void launch_apply_h(const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf,
+                           GridArgs g, double* eps_part, hipStream_t st) {
+  dim3 grid(ntiles<N>(), nstate), block(LineCfg<N>::THREADS);
+  auto p = reinterpret_cast<const cpx<T>*>(psi);
+  auto h = reinterpret_cast<cpx<T>*>(hpsi);
+  hipLaunchKernelGGL((k_h_pass<T, N, 0, true, false>), grid, block, 0, st, p, h, mf, g, nullptr);
+  hipLaunchKernelGGL((k_h_pass<T, N, 1, false, false>), grid, block, 0, st, p, h, mf, g, nullptr);
+  hipLaunchKernelGGL((k_h_pass<T, N, 2, false, true>), grid, block, 0, st, p, h, mf, g, eps_part);
+}
+
+int grid_ntiles(int n) {
+  int r = 0;
+  SKY_DISPATCH_N(n, r = ntiles<NN>());
+  return r;
+}
+
+void apply_h(int n, const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf, GridArgs g,
+             double* eps_part, double* eps, hipStream_t st) {
+  if (nstate <= 0) return;
+  SKY_DISPATCH_N(n, launch_apply_h<double, NN>(psi, hpsi, nstate, mf, g, eps_part, st));
+  if (eps_part && eps) {
+    int nt = grid_ntiles(n);
+    hipLaunchKernelGGL(k_sum_partials, dim3((nstate + 127) / 128), dim3(128), 0, st,
+                       (const double*)eps_part, nt, nstate, eps);
+  }
+}
+
+template <typename T, int N>
+static void launch_damp(const void* psi, const void* hpsi, const double* eps, void* phi,
+                        int nstate, GridArgs g, DampArgs d, double* r2_part, hipStream_t st) {
+  dim3 grid(ntiles<N>(), nstate), block(LineCfg<N>::THREADS);
+  auto p = reinterpret_cast<const cpx<T>*>(psi);
+  auto h = reinterpret_cast<const cpx<T>*>(hpsi);
+  auto o = reinterpret_cast<cpx<T>*>(phi);
+  hipLaunchKernelGGL((k_damp_fwd_x<T, N>), grid, block, 0, st, p, h, eps, o, g, r2_part);
+  hipLaunchKernelGGL((k_damp_y<T, N, false>), grid, block, 0, st, o);
+  hipLaunchKernelGGL((k_damp_z<T, N>), grid, block, 0, st, o, g, d);
+  hipLaunchKernelGGL((k_damp_y<T, N, true>), grid, block, 0, st, o);
+  hipLaunchKernelGGL((k_damp_inv_x<T, N>), grid, block, 0, st, p, o);
+}
+
+void damped_step(int n, const void* psi, const void* hpsi, const double* eps, void* phi,
+                 int nstate, GridArgs g, double x0, double e0, double hb2m, double* r2_part,
+                 double* r2, hipStream_t st) {
+  if (nstate <= 0) return;
+  DampArgs d{x0, e0, hb2m};
+  SKY_DISPATCH_N(n, launch_damp<double, NN>(psi, hpsi, eps, phi, nstate, g, d, r2_part, st));
+  int nt = grid_ntiles(n);
+  hipLaunchKernelGGL(k_sum_partials, dim3((nstate + 127) / 128), dim3(128), 0, st,
+                     (const double*)r2_part, nt, nstate, r2);
+}
+
+template <typename T, int N>
+static void launch_dens(const void* psi, int nstate, int chunk, int nchunk, GridArgs g,
+                        double* part, hipStream_t st) {
+  dim3 grid(ntiles<N>(), nchunk), block(LineCfg<N>::THREADS);
+  auto p = reinterpret_cast<const cpx<T>*>(psi);
+  hipLaunchKernelGGL((k_dens_pass<T, N, 0>), grid, block, 0, st, p, nstate, chunk, g, part);
+  hipLaunchKernelGGL((k_dens_pass<T, N, 1>), grid, block, 0, st, p, nstate, chunk, g, part);
+  hipLaunchKernelGGL((k_dens_pass<T, N, 2>), grid, block, 0, st, p, nstate, chunk, g, part);
+}
+
+void densities(int n, const void* psi, int nstate, int nchunk_max, GridArgs g, double* part,
+               double* dens, hipStream_t st) {
+  const int n3 = n * n * n;
+  if (nstate <= 0) {
+    zero(dens, size_t(11) * n3, st);
+    return;
+  }
+  int chunk = (nstate + nchunk_max - 1) / nchunk_max;
+  int nchunk = (nstate + chunk - 1) / chunk;
+  SKY_DISPATCH_N(n, launch_dens<double, NN>(psi, nstate, chunk, nchunk, g, part, st));
+  hipLaunchKernelGGL(k_dens_reduce, dim3((n3 + 255) / 256), dim3(256), 0, st,
+                     (const double*)part, nchunk, n3, dens);
+}
+
+}  // namespace sky

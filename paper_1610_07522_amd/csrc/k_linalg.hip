@@ -1,0 +1,580 @@
+// Dense FP64 Hermitian linear algebra of the subspace step (Sec. 3.3.2):
+// Cholesky factor of the overlap and its inverse (the orthonormalising
+// transform), and a Hermitian eigensolver for the subspace Hamiltonian.
+//
+// The eigensolver is a blocked two-sided Jacobi method: the matrix is cut
+// into 32-wide blocks, block pairs are visited in round-robin order, each
+// 64x64 pair sub-matrix is diagonalised inside one workgroup (cyclic Jacobi
+// in LDS), and the resulting unitaries are applied to the whole matrix and
+// to the eigenvector accumulator.  Jacobi suits this step because the
+// subspace Hamiltonian is nearly diagonal after the first iterations, and
+// every round is fully parallel.
+#include <vector>
+#include <algorithm>
+
+#include "sky_kernels.h"
+
+namespace sky {
+
+namespace {
+constexpr int CB = 64;    // Cholesky block
+constexpr int JB = 32;    // Jacobi block (pair sub-problem = 2*JB)
+constexpr int JP = 2 * JB;
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cmulc(double2 a, double2 b) {  // a * conj(b)
+  return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ inline double2 cconjmul(double2 a, double2 b) {  // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ inline double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+
+// ------------------------------------------------------------------ Cholesky
+// Factor the kw x kw diagonal block at (k0, k0) in LDS and invert it:
+// A[k0.., k0..] <- L_kk (lower), Dinv <- L_kk^-1 (CB x CB, lower).
+__global__ void __launch_bounds__(256)
+k_chol_diag(double2* __restrict__ A, int m, int k0, double2* __restrict__ Dinv, int* info) {
+  __shared__ double2 S[CB][CB + 1];
+  __shared__ double2 X[CB][CB + 1];
+  __shared__ int bad;
+  const int kw = min(CB, m - k0);
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < CB * CB; e += blockDim.x) {
+    int i = e / CB, j = e % CB;
+    S[i][j] = (i < kw && j < kw) ? A[size_t(k0 + i) * m + k0 + j] : make_double2(0, 0);
+    X[i][j] = make_double2(0, 0);
+  }
+  __syncthreads();
+  for (int j = 0; j < kw; ++j) {
+    if (tid == 0) {
+      double d = S[j][j].x;
+      if (!(d > 0.0)) { bad = 1; d = 1.0; }
+      S[j][j] = make_double2(sqrt(d), 0.0);
+    }
+    __syncthreads();
+    const double inv = 1.0 / S[j][j].x;
+    for (int i = j + 1 + tid; i < kw; i += blockDim.x) S[i][j] = cscale(inv, S[i][j]);
+    __syncthreads();
+    // trailing update of the lower part: S[i][l] -= L[i][j] conj(L[l][j]), i >= l > j
+    const int w = kw - j - 1;
+    for (int e = tid; e < w * w; e += blockDim.x) {
+      int i = j + 1 + e / w, l = j + 1 + e % w;
+      if (l <= i) S[i][l] = csub(S[i][l], cmulc(S[i][j], S[l][j]));
+    }
+    __syncthreads();
+  }
+  // inverse of L by columns: X[i][c] = (delta_ic - sum_{c<=l<i} L[i][l] X[l][c]) / L[i][i]
+  if (tid < kw) {
+    const int c = tid;
+    for (int i = c; i < kw; ++i) {
+      double2 s = make_double2(i == c ? 1.0 : 0.0, 0.0);
+      for (int l = c; l < i; ++l) s = csub(s, cmul(S[i][l], X[l][c]));
+      X[i][c] = cscale(1.0 / S[i][i].x, s);
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < CB * CB; e += blockDim.x) {
+    int i = e / CB, j = e % CB;
+    if (i < kw && j < kw) {
+      A[size_t(k0 + i) * m + k0 + j] = (j <= i) ? S[i][j] : make_double2(0, 0);
+    }
+    Dinv[e] = X[i][j];
+  }
+  if (tid == 0 && bad) atomicExch(info, 1);
+}
+
+// Panel below the diagonal block: L[i][k0..] = A[i][k0..] * L_kk^-H, for
+// the 64-row block starting at row r0 = k0 + kw + blockIdx.x * CB.
+__global__ void __launch_bounds__(256)
+k_chol_panel(double2* __restrict__ A, int m, int k0, const double2* __restrict__ Dinv) {
+  __shared__ double2 P[CB][CB + 1];
+  __shared__ double2 D[CB][CB + 1];
+  const int kw = min(CB, m - k0);
+  const int r0 = k0 + kw + blockIdx.x * CB;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < CB * CB; e += blockDim.x) {
+    int i = e / CB, j = e % CB;
+    P[i][j] = (r0 + i < m && j < kw) ? A[size_t(r0 + i) * m + k0 + j] : make_double2(0, 0);
+    D[i][j] = Dinv[e];
+  }
+  __syncthreads();
+  // out[i][j] = sum_l P[i][l] conj(D[j][l])
+  for (int e = tid; e < CB * CB; e += blockDim.x) {
+    int i = e / CB, j = e % CB;
+    if (r0 + i >= m || j >= kw) continue;
+    double2 s = make_double2(0, 0);
+    for (int l = 0; l <= j; ++l) s = cadd(s, cmulc(P[i][l], D[j][l]));
+    A[size_t(r0 + i) * m + k0 + j] = s;
+  }
+}
+
+// Trailing update A[i][j] -= sum_l L[i][k0+l] conj(L[j][k0+l]) on the lower
+// tiles of the trailing matrix (tile pair number -> (ti, tj), ti >= tj).
+__global__ void __launch_bounds__(256)
+k_chol_update(double2* __restrict__ A, int m, int k0) {
+  __shared__ double2 Li[CB][CB + 1];
+  __shared__ double2 Lj[CB][CB + 1];
+  const int kw = min(CB, m - k0);
+  const int t0 = k0 + kw;
+  int p = blockIdx.x, a = 0;
+  while ((a + 1) * (a + 2) / 2 <= p) ++a;
+  const int ti = a, tj = p - a * (a + 1) / 2;
+  const int i0 = t0 + ti * CB, j0 = t0 + tj * CB;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < CB * CB; e += blockDim.x) {
+    int r = e / CB, l = e % CB;
+    Li[r][l] = (i0 + r < m && l < kw) ? A[size_t(i0 + r) * m + k0 + l] : make_double2(0, 0);
+    Lj[r][l] = (j0 + r < m && l < kw) ? A[size_t(j0 + r) * m + k0 + l] : make_double2(0, 0);
+  }
+  __syncthreads();
+  for (int e = tid; e < CB * CB; e += blockDim.x) {
+    int r = e / CB, c = e % CB;
+    int gi = i0 + r, gj = j0 + c;
+    if (gi >= m || gj >= m || gj > gi) continue;
+    double2 s = make_double2(0, 0);
+    for (int l = 0; l < kw; ++l) s = cadd(s, cmulc(Li[r][l], Lj[c][l]));
+    size_t idx = size_t(gi) * m + gj;
+    A[idx] = csub(A[idx], s);
+  }
+}
+
+// Block row ib of Linv (jb < ib):
+//   Linv[ib][jb] = -Dinv[ib] * sum_{kb=jb}^{ib-1} L[ib][kb] Linv[kb][jb]
+// one workgroup per jb; Linv[ib][ib] = Dinv[ib] is written by jb == ib.
+__global__ void __launch_bounds__(256)
+k_tri_inv_row(const double2* __restrict__ L, double2* __restrict__ Linv, int m, int ib,
+              const double2* __restrict__ Dinv_all) {
+  __shared__ double2 Sa[CB][CB + 1];
+  __shared__ double2 Sb[CB][CB + 1];
+  const int jb = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int r0 = ib * CB;
+  const double2* Di = Dinv_all + size_t(ib) * CB * CB;
+  if (jb == ib) {
+    for (int e = tid; e < CB * CB; e += blockDim.x) {
+      int r = e / CB, c = e % CB;
+      if (r0 + r < m && r0 + c < m) Linv[size_t(r0 + r) * m + r0 + c] = Di[e];
+    }
+    return;
+  }
+  double2 acc[16];
+  for (int q = 0; q < 16; ++q) acc[q] = make_double2(0, 0);
+  for (int kb = jb; kb < ib; ++kb) {
+    for (int e = tid; e < CB * CB; e += blockDim.x) {
+      int r = e / CB, c = e % CB;
+      Sa[r][c] = (r0 + r < m) ? L[size_t(r0 + r) * m + kb * CB + c] : make_double2(0, 0);
+      Sb[r][c] = (kb * CB + r < m && jb * CB + c < m) ? Linv[size_t(kb * CB + r) * m + jb * CB + c]
+                                                       : make_double2(0, 0);
+    }
+    __syncthreads();
+    for (int q = 0; q < 16; ++q) {
+      int e = tid + q * 256, r = e / CB, c = e % CB;
+      double2 s = acc[q];
+      for (int l = 0; l < CB; ++l) s = cadd(s, cmul(Sa[r][l], Sb[l][c]));
+      acc[q] = s;
+    }
+    __syncthreads();
+  }
+  for (int q = 0; q < 16; ++q) {
+    int e = tid + q * 256;
+    Sb[e / CB][e % CB] = acc[q];
+    Sa[e / CB][e % CB] = Di[e];
+  }
+  __syncthreads();
+  for (int q = 0; q < 16; ++q) {
+    int e = tid + q * 256, r = e / CB, c = e % CB;
+    double2 s = make_double2(0, 0);
+    for (int l = 0; l <= r; ++l) s = cadd(s, cmul(Sa[r][l], Sb[l][c]));
+    if (r0 + r < m && jb * CB + c < m) Linv[size_t(r0 + r) * m + jb * CB + c] = cscale(-1.0, s);
+  }
+}
+
+__global__ void k_zero_cpx(double2* __restrict__ p, size_t n) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = make_double2(0, 0);
+}
+
+__global__ void k_zero(double* __restrict__ p, size_t n) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// ------------------------------------------------------------------ Jacobi
+// Rotation of the 2x2 Hermitian [[a, r e^{i phi}], [r e^{-i phi}, b]]:
+// G = [[e^{i phi} c, e^{i phi} s], [-s, c]], G^H S G diagonal.
+struct Rot {
+  double c, s, er, ei;  // cos, sin, e^{i phi}
+};
+
+__device__ inline Rot make_rot(double a, double b, double2 apq) {
+  Rot g;
+  double r = sqrt(apq.x * apq.x + apq.y * apq.y);
+  if (r == 0.0 || r < 1e-300) {
+    g.c = 1.0; g.s = 0.0; g.er = 1.0; g.ei = 0.0;
+    return g;
+  }
+  g.er = apq.x / r;
+  g.ei = apq.y / r;
+  double zeta = (b - a) / (2.0 * r);
+  double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  g.c = 1.0 / sqrt(1.0 + t * t);
+  g.s = t * g.c;
+  return g;
+}
+
+// Round-robin partner pairs of round r among np players: pair i -> (p, q).
+__device__ inline void rr_pair(int np, int r, int i, int& p, int& q) {
+  const int n1 = np - 1;
+  p = (i == 0) ? 0 : ((i + r - 1) % n1) + 1;
+  q = ((n1 - i + r - 1) % n1) + 1;
+}
+
+// Diagonalise the 64x64 pair sub-matrix of blocks (P, Q) of A (ld = mp)
+// and write its unitary J (64x64, row-major, local index l < 32 -> block P).
+__global__ void __launch_bounds__(256)
+k_jacobi_pair(const double2* __restrict__ A, int mp, const int2* __restrict__ pairs,
+              double2* __restrict__ Jout, double tol, int max_inner) {
+  __shared__ double2 S[JP][JP + 1];
+  __shared__ double2 J[JP][JP + 1];
+  __shared__ Rot rot[JB];
+  __shared__ double red[4][2];
+  __shared__ int done;
+  const int2 pq = pairs[blockIdx.x];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < JP * JP; e += blockDim.x) {
+    int i = e / JP, j = e % JP;
+    int gi = (i < JB ? pq.x * JB + i : pq.y * JB + i - JB);
+    int gj = (j < JB ? pq.x * JB + j : pq.y * JB + j - JB);
+    S[i][j] = A[size_t(gi) * mp + gj];
+    J[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < max_inner; ++sweep) {
+    // convergence test on the sub-matrix
+    double off = 0.0, dia = 0.0;
+    for (int e = tid; e < JP * JP; e += blockDim.x) {
+      int i = e / JP, j = e % JP;
+      double v = S[i][j].x * S[i][j].x + S[i][j].y * S[i][j].y;
+      if (i == j) dia += v; else off += v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_down(off, o, 64);
+      dia += __shfl_down(dia, o, 64);
+    }
+    if ((tid & 63) == 0) { red[tid >> 6][0] = off; red[tid >> 6][1] = dia; }
+    __syncthreads();
+    if (tid == 0) {
+      double o = 0.0, d = 0.0;
+      for (int w = 0; w < 4; ++w) { o += red[w][0]; d += red[w][1]; }
+      done = (o <= tol * tol * d) || (o < 1e-300);
+    }
+    __syncthreads();
+    if (done) break;
+    for (int r = 0; r < JP - 1; ++r) {
+      if (tid < JB) {
+        int p, q;
+        rr_pair(JP, r, tid, p, q);
+        if (p > q) { int t = p; p = q; q = t; }
+        rot[tid] = make_rot(S[p][p].x, S[q][q].x, S[p][q]);
+      }
+      __syncthreads();
+      // S <- G^H S G on 2x2 blocks (pair u rows, pair v cols)
+      for (int e = tid; e < JB * JB; e += blockDim.x) {
+        int u = e / JB, v = e % JB;
+        int pu, qu, pv, qv;
+        rr_pair(JP, r, u, pu, qu);
+        rr_pair(JP, r, v, pv, qv);
+        if (pu > qu) { int t = pu; pu = qu; qu = t; }
+        if (pv > qv) { int t = pv; pv = qv; qv = t; }
+        Rot gu = rot[u], gv = rot[v];
+        double2 epu = make_double2(gu.er, gu.ei), epv = make_double2(gv.er, gv.ei);
+        double2 x00 = S[pu][pv], x01 = S[pu][qv], x10 = S[qu][pv], x11 = S[qu][qv];
+        // right multiply by G_v: col p' = e c col_p - s col_q ; col q' = e s col_p + c col_q
+        double2 y00 = csub(cscale(gv.c, cmul(x00, epv)), cscale(gv.s, x01));
+        double2 y01 = cadd(cscale(gv.s, cmul(x00, epv)), cscale(gv.c, x01));
+        double2 y10 = csub(cscale(gv.c, cmul(x10, epv)), cscale(gv.s, x11));
+        double2 y11 = cadd(cscale(gv.s, cmul(x10, epv)), cscale(gv.c, x11));
+        // left multiply by G_u^H: row p' = conj(e) c row_p - s row_q ; row q' = conj(e) s row_p + c row_q
+        S[pu][pv] = csub(cscale(gu.c, cmulc(y00, epu)), cscale(gu.s, y10));
+        S[pu][qv] = csub(cscale(gu.c, cmulc(y01, epu)), cscale(gu.s, y11));
+        S[qu][pv] = cadd(cscale(gu.s, cmulc(y00, epu)), cscale(gu.c, y10));
+        S[qu][qv] = cadd(cscale(gu.s, cmulc(y01, epu)), cscale(gu.c, y11));
+      }
+      // J <- J G
+      for (int e = tid; e < JP * JB; e += blockDim.x) {
+        int i = e / JB, v = e % JB;
+        int pv, qv;
+        rr_pair(JP, r, v, pv, qv);
+        if (pv > qv) { int t = pv; pv = qv; qv = t; }
+        Rot gv = rot[v];
+        double2 epv = make_double2(gv.er, gv.ei);
+        double2 x0 = J[i][pv], x1 = J[i][qv];
+        J[i][pv] = csub(cscale(gv.c, cmul(x0, epv)), cscale(gv.s, x1));
+        J[i][qv] = cadd(cscale(gv.s, cmul(x0, epv)), cscale(gv.c, x1));
+      }
+      __syncthreads();
+    }
+  }
+  double2* out = Jout + size_t(blockIdx.x) * JP * JP;
+  for (int e = tid; e < JP * JP; e += blockDim.x) out[e] = J[e / JP][e % JP];
+}
+
+// A[{Pu,Qu}][{Pv,Qv}] <- J_u^H A[..][..] J_v for all pair pairs (u, v).
+__global__ void __launch_bounds__(256)
+k_jacobi_apply_a(double2* __restrict__ A, int mp, const int2* __restrict__ pairs,
+                 const double2* __restrict__ Jall) {
+  __shared__ double2 X[JP][JP + 1];
+  __shared__ double2 M[JP][JP + 1];
+  const int u = blockIdx.y, v = blockIdx.x;
+  const int2 pu = pairs[u], pv = pairs[v];
+  const int tid = threadIdx.x;
+  auto gidx = [&](int2 p, int l) { return l < JB ? p.x * JB + l : p.y * JB + l - JB; };
+  const double2* Ju = Jall + size_t(u) * JP * JP;
+  const double2* Jv = Jall + size_t(v) * JP * JP;
+  for (int e = tid; e < JP * JP; e += blockDim.x) {
+    int i = e / JP, j = e % JP;
+    X[i][j] = A[size_t(gidx(pu, i)) * mp + gidx(pv, j)];
+    M[i][j] = Jv[e];
+  }
+  __syncthreads();
+  double2 y[16];
+  for (int q = 0; q < 16; ++q) {        // Y = X Jv
+    int e = tid + q * 256, i = e / JP, j = e % JP;
+    double2 s = make_double2(0, 0);
+    for (int l = 0; l < JP; ++l) s = cadd(s, cmul(X[i][l], M[l][j]));
+    y[q] = s;
+  }
+  __syncthreads();
+  for (int q = 0; q < 16; ++q) {
+    int e = tid + q * 256;
+    X[e / JP][e % JP] = y[q];
+    M[e / JP][e % JP] = Ju[e];
+  }
+  __syncthreads();
+  for (int q = 0; q < 16; ++q) {        // T = Ju^H Y
+    int e = tid + q * 256, i = e / JP, j = e % JP;
+    double2 s = make_double2(0, 0);
+    for (int l = 0; l < JP; ++l) s = cadd(s, cconjmul(M[l][i], X[l][j]));
+    A[size_t(gidx(pu, i)) * mp + gidx(pv, j)] = s;
+  }
+}
+
+// V[rows][{P,Q}] <- V[rows][{P,Q}] J for a 64-row block and one pair.
+__global__ void __launch_bounds__(256)
+k_jacobi_apply_v(double2* __restrict__ V, int mp, const int2* __restrict__ pairs,
+                 const double2* __restrict__ Jall) {
+  __shared__ double2 X[JP][JP + 1];
+  __shared__ double2 M[JP][JP + 1];
+  const int v = blockIdx.y, r0 = blockIdx.x * JP;
+  const int2 pv = pairs[v];
+  const int tid = threadIdx.x;
+  auto gcol = [&](int l) { return l < JB ? pv.x * JB + l : pv.y * JB + l - JB; };
+  const double2* Jv = Jall + size_t(v) * JP * JP;
+  for (int e = tid; e < JP * JP; e += blockDim.x) {
+    int i = e / JP, j = e % JP;
+    X[i][j] = (r0 + i < mp) ? V[size_t(r0 + i) * mp + gcol(j)] : make_double2(0, 0);
+    M[i][j] = Jv[e];
+  }
+  __syncthreads();
+  for (int q = 0; q < 16; ++q) {
+    int e = tid + q * 256, i = e / JP, j = e % JP;
+    double2 s = make_double2(0, 0);
+    for (int l = 0; l < JP; ++l) s = cadd(s, cmul(X[i][l], M[l][j]));
+    if (r0 + i < mp) V[size_t(r0 + i) * mp + gcol(j)] = s;
+  }
+}
+
+// Off-diagonal and diagonal squared norms of A (mp x mp), per block partials.
+__global__ void k_offnorm(const double2* __restrict__ A, int mp, double* __restrict__ part) {
+  __shared__ double red[4][2];
+  double off = 0.0, dia = 0.0;
+  const size_t n = size_t(mp) * mp;
+  for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+       e += size_t(gridDim.x) * blockDim.x) {
+    double2 a = A[e];
+    double v = a.x * a.x + a.y * a.y;
+    if (e / mp == e % mp) dia += v; else off += v;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    off += __shfl_down(off, o, 64);
+    dia += __shfl_down(dia, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) { red[threadIdx.x >> 6][0] = off; red[threadIdx.x >> 6][1] = dia; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double o = 0.0, d = 0.0;
+    for (int w = 0; w < 4; ++w) { o += red[w][0]; d += red[w][1]; }
+    part[2 * blockIdx.x] = o;
+    part[2 * blockIdx.x + 1] = d;
+  }
+}
+
+__global__ void k_offnorm_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  if (threadIdx.x) return;
+  double o = 0.0, d = 0.0;
+  for (int b = 0; b < nb; ++b) { o += part[2 * b]; d += part[2 * b + 1]; }
+  out[0] = o;
+  out[1] = d;
+}
+
+// Pad-copy A (m x m) into Ap (mp x mp) with zero coupling, V = identity.
+__global__ void k_jacobi_init(const double2* __restrict__ A, int m, double2* __restrict__ Ap,
+                              double2* __restrict__ V, int mp) {
+  size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= size_t(mp) * mp) return;
+  int i = int(e / mp), j = int(e % mp);
+  Ap[e] = (i < m && j < m) ? A[size_t(i) * m + j] : make_double2(0, 0);
+  V[e] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+}
+
+// Sort eigenvalues ascending (ties by index) and gather eigenvector columns.
+__global__ void k_jacobi_sort(const double2* __restrict__ Ap, const double2* __restrict__ V,
+                              int m, int mp, double* __restrict__ w, double2* __restrict__ Z) {
+  const int i = blockIdx.x;   // source column
+  const double wi = Ap[size_t(i) * mp + i].x;
+  __shared__ int rank_s;
+  if (threadIdx.x == 0) rank_s = 0;
+  __syncthreads();
+  int cnt = 0;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    double wj = Ap[size_t(j) * mp + j].x;
+    if (wj < wi || (wj == wi && j < i)) ++cnt;
+  }
+  atomicAdd(&rank_s, cnt);
+  __syncthreads();
+  const int rk = rank_s;
+  if (threadIdx.x == 0) w[rk] = wi;
+  for (int r = threadIdx.x; r < m; r += blockDim.x) Z[size_t(r) * m + rk] = V[size_t(r) * mp + i];
+}
+
+__global__ void k_scale_columns(double2* __restrict__ X, const double* __restrict__ d, int m) {
+  size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= size_t(m) * m) return;
+  double s = d[e % m];
+  X[e] = make_double2(s * X[e].x, s * X[e].y);
+}
+
+__global__ void k_inv_sqrt(double* __restrict__ w, int m, int* info) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  double v = w[i];
+  if (!(v > 0.0)) { atomicExch(info, 1); v = 1.0; }
+  w[i] = 1.0 / sqrt(v);
+}
+
+int jacobi_dims(int m, int& nb) {
+  nb = (m + JB - 1) / JB;
+  if (nb < 2) nb = 2;
+  if (nb & 1) ++nb;
+  return nb * JB;
+}
+}  // namespace
+
+void zero(double* p, size_t n, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_zero, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, p, n);
+}
+
+void cholesky_inverse(void* Av, void* Linvv, int m, void* work, int* info, hipStream_t st) {
+  if (m <= 0) return;
+  auto A = (double2*)Av;
+  auto Linv = (double2*)Linvv;
+  auto Dinv = (double2*)work;   // nblk * CB * CB
+  const int nblk = (m + CB - 1) / CB;
+  for (int kb = 0; kb < nblk; ++kb) {
+    const int k0 = kb * CB;
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, A, m, k0,
+                       Dinv + size_t(kb) * CB * CB, info);
+    const int rest = m - (k0 + min(CB, m - k0));
+    if (rest > 0) {
+      const int nb = (rest + CB - 1) / CB;
+      hipLaunchKernelGGL(k_chol_panel, dim3(nb), dim3(256), 0, st, A, m, k0,
+                         (const double2*)(Dinv + size_t(kb) * CB * CB));
+      hipLaunchKernelGGL(k_chol_update, dim3(nb * (nb + 1) / 2), dim3(256), 0, st, A, m, k0);
+    }
+  }
+  const size_t mm = size_t(m) * m;
+  hipLaunchKernelGGL(k_zero_cpx, dim3(unsigned((mm + 255) / 256)), dim3(256), 0, st, Linv, mm);
+  for (int ib = 0; ib < nblk; ++ib)
+    hipLaunchKernelGGL(k_tri_inv_row, dim3(ib + 1), dim3(256), 0, st, (const double2*)A, Linv, m,
+                       ib, (const double2*)Dinv);
+}
+
+size_t jacobi_scratch_bytes(int m) {
+  int nb;
+  const int mp = jacobi_dims(m, nb);
+  size_t b = 0;
+  b += 2 * size_t(mp) * mp * sizeof(double2);                 // Ap, V
+  b += size_t(nb / 2) * JP * JP * sizeof(double2);            // J
+  b += size_t(nb) * nb * sizeof(int2);                        // round-robin table
+  b += 4096 * sizeof(double);                                 // norm partials
+  return b + 1024;
+}
+
+int jacobi_eigh(void* Av, int m, double* w, void* Zv, void* work, double tol, int max_sweeps,
+                hipStream_t st) {
+  if (m <= 0) return 0;
+  int nb;
+  const int mp = jacobi_dims(m, nb);
+  const int np = nb / 2;
+  char* wp = (char*)work;
+  auto Ap = (double2*)wp; wp += size_t(mp) * mp * sizeof(double2);
+  auto V = (double2*)wp; wp += size_t(mp) * mp * sizeof(double2);
+  auto Jall = (double2*)wp; wp += size_t(np) * JP * JP * sizeof(double2);
+  auto pairs = (int2*)wp; wp += size_t(nb) * nb * sizeof(int2);
+  auto norms = (double*)wp;
+  // round-robin schedule of the block pairs, all rounds
+  std::vector<int2> sched(size_t(nb - 1) * np);
+  for (int r = 0; r < nb - 1; ++r)
+    for (int i = 0; i < np; ++i) {
+      const int n1 = nb - 1;
+      int p = (i == 0) ? 0 : ((i + r - 1) % n1) + 1;
+      int q = ((n1 - i + r - 1) % n1) + 1;
+      sched[size_t(r) * np + i] = make_int2(std::min(p, q), std::max(p, q));
+    }
+  hipMemcpyAsync(pairs, sched.data(), sched.size() * sizeof(int2), hipMemcpyHostToDevice, st);
+  const size_t mm = size_t(mp) * mp;
+  hipLaunchKernelGGL(k_jacobi_init, dim3(unsigned((mm + 255) / 256)), dim3(256), 0, st,
+                     (const double2*)Av, m, Ap, V, mp);
+  const int nrb = 256;
+  double host_norm[2];
+  int sweeps = 0;
+  for (; sweeps < max_sweeps; ++sweeps) {
+    hipLaunchKernelGGL(k_offnorm, dim3(nrb), dim3(256), 0, st, (const double2*)Ap, mp, norms);
+    hipLaunchKernelGGL(k_offnorm_final, dim3(1), dim3(64), 0, st, (const double*)norms, nrb,
+                       norms + 2 * nrb);
+    hipMemcpyAsync(host_norm, norms + 2 * nrb, 2 * sizeof(double), hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+    if (host_norm[0] <= tol * tol * host_norm[1] || host_norm[0] < 1e-300) break;
+    for (int r = 0; r < nb - 1; ++r) {
+      const int2* pr = pairs + size_t(r) * np;
+      hipLaunchKernelGGL(k_jacobi_pair, dim3(np), dim3(256), 0, st, (const double2*)Ap, mp, pr,
+                         Jall, tol * 0.1, 12);
+      hipLaunchKernelGGL(k_jacobi_apply_a, dim3(np, np), dim3(256), 0, st, Ap, mp, pr,
+                         (const double2*)Jall);
+      hipLaunchKernelGGL(k_jacobi_apply_v, dim3(mp / JP, np), dim3(256), 0, st, V, mp, pr,
+                         (const double2*)Jall);
+    }
+  }
+  hipLaunchKernelGGL(k_jacobi_sort, dim3(m), dim3(256), 0, st, (const double2*)Ap,
+                     (const double2*)V, m, mp, w, (double2*)Zv);
+  return sweeps;
+}
+
+void scale_columns(void* X, const double* d, int m, hipStream_t st) {
+  const size_t mm = size_t(m) * m;
+  hipLaunchKernelGGL(k_scale_columns, dim3(unsigned((mm + 255) / 256)), dim3(256), 0, st,
+                     (double2*)X, d, m);
+}
+
+void inv_sqrt(double* w, int m, int* info, hipStream_t st) {
+  hipLaunchKernelGGL(k_inv_sqrt, dim3((m + 255) / 256), dim3(256), 0, st, w, m, info);
+}
+
+}  // namespace sky

@@ -1,0 +1,422 @@
+// C ABI of the damped-gradient solver: context, workspace layout and the
+// static iteration of Fig. 1 (steps 2-5) of the paper.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sky.h"
+#include "sky_kernels.h"
+
+using namespace sky;
+
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return SKY_OK;
+  return fail(SKY_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool grid_ok(int n) {
+  return n == 8 || n == 16 || n == 24 || n == 32 || n == 48 || n == 64;
+}
+
+constexpr size_t ALIGN = 256;
+size_t al(size_t b) { return (b + ALIGN - 1) / ALIGN * ALIGN; }
+
+constexpr int DENS_CHUNKS = 32;   // state chunks of the density passes
+constexpr double JACOBI_TOL = 1e-14;
+constexpr int JACOBI_SWEEPS = 30;
+
+// Byte offsets of every buffer inside the caller's workspace.
+struct Layout {
+  size_t psi[2], hpsi[2], phi[2], hphi[2];
+  size_t eps[2], r2[2], ritz[2], tiles;
+  size_t matI, matH, matC, matL, matT, matHp, matZ, matU, wtmp, gemm_part, chol_work, jac_work;
+  size_t dens[2], der[2], mf[2], vc, fscratch, dens_part, epart, energy, info;
+  size_t total;
+};
+
+Layout plan(const sky_box_desc& d) {
+  Layout L{};
+  const size_t n3 = size_t(d.n) * d.n * d.n;
+  const size_t V = 2 * n3;
+  const int nq[2] = {d.n_neutrons, d.n_protons};
+  const int nmax = std::max(1, std::max(d.n_neutrons, d.n_protons));
+  const size_t c16 = 16;  // bytes per complex128
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += al(std::max<size_t>(bytes, 1));
+    return o;
+  };
+  for (int q = 0; q < 2; ++q) {
+    const size_t sb = size_t(nq[q]) * V * c16;
+    L.psi[q] = take(sb);
+    L.hpsi[q] = take(sb);
+    L.phi[q] = take(sb);
+    L.hphi[q] = take(sb);
+    L.eps[q] = take(sizeof(double) * nq[q]);
+    L.r2[q] = take(sizeof(double) * nq[q]);
+    L.ritz[q] = take(sizeof(double) * nq[q]);
+  }
+  const int ntile = grid_ntiles(d.n);
+  L.tiles = take(sizeof(double) * size_t(nmax) * ntile);
+  const size_t mm = size_t(nmax) * nmax * c16;
+  L.matI = take(mm);
+  L.matH = take(mm);
+  L.matC = take(mm);
+  L.matL = take(mm);
+  L.matT = take(mm);
+  L.matHp = take(mm);
+  L.matZ = take(mm);
+  L.matU = take(mm);
+  L.wtmp = take(sizeof(double) * nmax);
+  L.gemm_part = take(std::max(overlap_scratch_bytes(std::max(1, nq[0]), long(V)),
+                              overlap_scratch_bytes(std::max(1, nq[1]), long(V))));
+  L.chol_work = take(size_t((nmax + 63) / 64 + 1) * 64 * 64 * c16);
+  L.jac_work = take(jacobi_scratch_bytes(nmax));
+  for (int q = 0; q < 2; ++q) {
+    L.dens[q] = take(sizeof(double) * 11 * n3);
+    L.der[q] = take(sizeof(double) * 5 * n3);
+    L.mf[q] = take(sizeof(double) * 5 * n3);
+  }
+  L.vc = take(sizeof(double) * n3);
+  L.fscratch = take(c16 * n3);
+  L.dens_part = take(sizeof(double) * DENS_CHUNKS * 16 * n3);
+  L.epart = take(sizeof(double) * 7 * size_t(energy_nblocks(d.n)));
+  L.energy = take(sizeof(double) * 8);
+  L.info = take(sizeof(int) * 4);
+  L.total = off;
+  return L;
+}
+
+int validate(const sky_box_desc* d) {
+  if (!d) return fail(SKY_ERR_INVALID, "null descriptor");
+  if (!grid_ok(d->n)) return fail(SKY_ERR_UNSUPPORTED_GRID, "grid size must be one of 8,16,24,32,48,64");
+  if (!(d->dx > 0.0)) return fail(SKY_ERR_INVALID, "dx must be positive");
+  if (d->n_neutrons < 0 || d->n_protons < 0 || d->n_neutrons + d->n_protons == 0)
+    return fail(SKY_ERR_INVALID, "need at least one state");
+  const long V = 2L * d->n * d->n * d->n;
+  if (d->n_neutrons > V || d->n_protons > V) return fail(SKY_ERR_INVALID, "more states than grid points");
+  if (!(d->damp_e0 > 0.0)) return fail(SKY_ERR_INVALID, "damp_e0 must be positive");
+  return SKY_OK;
+}
+}  // namespace
+
+struct sky_ctx {
+  sky_box_desc d;
+  Layout lay;
+  char* ws;
+  hipStream_t st;
+  int n, n3;
+  long V;
+  int nq[2];
+  GridArgs g;
+  Skyrme sk;
+  int last_sweeps;
+
+  template <typename P = char> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
+  MeanFieldPtrs mfp(int q) const {
+    const double* m = at<double>(lay.mf[q]);
+    return MeanFieldPtrs{m, m + n3, m + 2 * n3};
+  }
+};
+
+namespace {
+int check_info(sky_ctx* c, const char* what) {
+  int info = 0;
+  int rc = hip_check(hipMemcpyAsync(&info, c->at<int>(c->lay.info), sizeof(int),
+                                    hipMemcpyDeviceToHost, c->st), "info copy");
+  if (rc) return rc;
+  rc = hip_check(hipStreamSynchronize(c->st), what);
+  if (rc) return rc;
+  if (info) return fail(SKY_ERR_NOT_POSITIVE_DEFINITE, std::string(what) + ": overlap not positive definite");
+  return SKY_OK;
+}
+
+// Generalised Rayleigh-Ritz on phi/hphi of species q -> psi_out (Sec. 3.3).
+int rayleigh_ritz(sky_ctx* c, int q, const void* phi, const void* hphi, void* psi_out,
+                  double* ritz) {
+  const int m = c->nq[q];
+  if (m == 0) return SKY_OK;
+  hipStream_t st = c->st;
+  void* I = c->at(c->lay.matI);
+  void* H = c->at(c->lay.matH);
+  void* Linv = c->at(c->lay.matL);
+  void* T = c->at(c->lay.matT);
+  void* Hp = c->at(c->lay.matHp);
+  void* Z = c->at(c->lay.matZ);
+  void* U = c->at(c->lay.matU);
+  int* info = c->at<int>(c->lay.info);
+  hipMemsetAsync(info, 0, sizeof(int), st);
+  // step 3a: I and H, lower triangles, then mirrored
+  overlap_lower(phi, phi, hphi, m, c->V, c->g.dV, I, H, c->at(c->lay.gemm_part), st);
+  hermitian_fill(I, m, st);
+  hermitian_fill(H, m, st);
+  // steps 3b-3c: I = L L^H, H' = L^-1 H L^-H, H' = Z lam Z^H
+  void* Lf = c->at(c->lay.matC);
+  hipMemcpyAsync(Lf, I, size_t(m) * m * 16, hipMemcpyDeviceToDevice, st);
+  cholesky_inverse(Lf, Linv, m, c->at(c->lay.chol_work), info, st);
+  gemm_square(Linv, 0, H, 0, T, m, st);
+  gemm_square(T, 0, Linv, 1, Hp, m, st);
+  hermitian_fill(Hp, m, st);   // exact Hermitian symmetry of H' before the eigensolver
+  int rc = check_info(c, "cholesky");
+  if (rc) return rc;
+  double* w = ritz ? ritz : c->at<double>(c->lay.ritz[q]);
+  c->last_sweeps += jacobi_eigh(Hp, m, w, Z, c->at(c->lay.jac_work), JACOBI_TOL, JACOBI_SWEEPS, st);
+  // steps 3d-3e: U = L^-H Z, psi = phi U
+  gemm_square(Linv, 1, Z, 0, U, m, st);
+  combine(phi, U, psi_out, m, c->V, st);
+  return SKY_OK;
+}
+
+int loewdin(sky_ctx* c, int q, const void* phi, void* psi_out) {
+  const int m = c->nq[q];
+  if (m == 0) return SKY_OK;
+  hipStream_t st = c->st;
+  void* I = c->at(c->lay.matI);
+  void* X = c->at(c->lay.matZ);
+  void* C = c->at(c->lay.matU);
+  double* w = c->at<double>(c->lay.ritz[q]);
+  int* info = c->at<int>(c->lay.info);
+  hipMemsetAsync(info, 0, sizeof(int), st);
+  overlap_lower(phi, phi, nullptr, m, c->V, c->g.dV, I, nullptr, c->at(c->lay.gemm_part), st);
+  hermitian_fill(I, m, st);
+  jacobi_eigh(I, m, w, X, c->at(c->lay.jac_work), JACOBI_TOL, JACOBI_SWEEPS, st);
+  // C = X diag(w^-1/2) X^H
+  double* wi = c->at<double>(c->lay.wtmp);
+  hipMemcpyAsync(c->at(c->lay.matT), X, size_t(m) * m * 16, hipMemcpyDeviceToDevice, st);
+  hipMemcpyAsync(wi, w, sizeof(double) * m, hipMemcpyDeviceToDevice, st);
+  inv_sqrt(wi, m, info, st);
+  scale_columns(c->at(c->lay.matT), wi, m, st);
+  gemm_square(c->at(c->lay.matT), 0, X, 1, C, m, st);
+  int rc = check_info(c, "loewdin");
+  if (rc) return rc;
+  combine(phi, C, psi_out, m, c->V, st);
+  return SKY_OK;
+}
+
+void fields(sky_ctx* c) {
+  hipStream_t st = c->st;
+  for (int q = 0; q < 2; ++q)
+    sky::densities(c->n, c->at(c->lay.psi[q]), c->nq[q], DENS_CHUNKS, c->g,
+                   c->at<double>(c->lay.dens_part), c->at<double>(c->lay.dens[q]), st);
+  mean_field(c->n, c->g, c->sk, c->at<double>(c->lay.dens[0]), c->at<double>(c->lay.dens[1]),
+             c->at<double>(c->lay.der[0]), c->at<double>(c->lay.der[1]),
+             c->at<double>(c->lay.mf[0]), c->at<double>(c->lay.mf[1]),
+             c->at<double>(c->lay.vc), c->at(c->lay.fscratch), c->at<double>(c->lay.epart),
+             c->at<double>(c->lay.energy), st);
+}
+}  // namespace
+
+extern "C" {
+
+int sky_workspace_size(const sky_box_desc* d, size_t* bytes) {
+  int rc = validate(d);
+  if (rc) return rc;
+  if (!bytes) return fail(SKY_ERR_INVALID, "null bytes");
+  *bytes = plan(*d).total;
+  return SKY_OK;
+}
+
+int sky_create(const sky_box_desc* d, void* workspace, size_t bytes, void* stream, sky_ctx** out) {
+  int rc = validate(d);
+  if (rc) return rc;
+  if (!out) return fail(SKY_ERR_INVALID, "null out");
+  Layout L = plan(*d);
+  if (!workspace || bytes < L.total) return fail(SKY_ERR_WORKSPACE, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(workspace) % ALIGN) return fail(SKY_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  sky_ctx* c = new sky_ctx();
+  c->d = *d;
+  c->lay = L;
+  c->ws = static_cast<char*>(workspace);
+  c->st = static_cast<hipStream_t>(stream);
+  c->n = d->n;
+  c->n3 = d->n * d->n * d->n;
+  c->V = 2L * c->n3;
+  c->nq[0] = d->n_neutrons;
+  c->nq[1] = d->n_protons;
+  c->g.dx = d->dx;
+  c->g.dV = d->dx * d->dx * d->dx;
+  c->g.kunit = 2.0 * M_PI / (d->n * d->dx);
+  const double t0 = d->t0, t1 = d->t1, t2 = d->t2, t3 = d->t3;
+  const double x0 = d->x0, x1 = d->x1, x2 = d->x2, x3 = d->x3;
+  // b-coefficients of the Skyrme functional (standard t/x -> b mapping)
+  c->sk.b0 = t0 * (1 + x0 / 2);
+  c->sk.b0p = t0 * (0.5 + x0);
+  c->sk.b1 = (t1 * (1 + x1 / 2) + t2 * (1 + x2 / 2)) / 4;
+  c->sk.b1p = (t1 * (0.5 + x1) - t2 * (0.5 + x2)) / 4;
+  c->sk.b2 = (3 * t1 * (1 + x1 / 2) - t2 * (1 + x2 / 2)) / 8;
+  c->sk.b2p = (3 * t1 * (0.5 + x1) + t2 * (0.5 + x2)) / 8;
+  c->sk.b3 = t3 * (1 + x3 / 2) / 4;
+  c->sk.b3p = t3 * (0.5 + x3) / 4;
+  c->sk.b4 = d->W0 / 2;
+  c->sk.b4p = d->W0 / 2;
+  c->sk.alpha = d->alpha;
+  c->sk.hb2m_n = d->hb2m_n;
+  c->sk.hb2m_p = d->hb2m_p;
+  c->sk.e2 = d->e2;
+  c->last_sweeps = 0;
+  *out = c;
+  return SKY_OK;
+}
+
+int sky_init_box(sky_ctx* c, const void* raw_n, const void* raw_p) {
+  if (!c) return fail(SKY_ERR_INVALID, "null context");
+  const void* raw[2] = {raw_n, raw_p};
+  for (int q = 0; q < 2; ++q) {
+    if (c->nq[q] == 0) continue;
+    if (!raw[q]) return fail(SKY_ERR_INVALID, "null trial states");
+    int rc = loewdin(c, q, raw[q], c->at(c->lay.psi[q]));
+    if (rc) return rc;
+  }
+  fields(c);
+  return hip_check(hipStreamSynchronize(c->st), "init");
+}
+
+int sky_apply_h(sky_ctx* c, int32_t q, const void* psi, void* hpsi, int32_t nstates,
+                double* eps) {
+  if (!c || q < 0 || q > 1 || !psi || !hpsi || nstates < 0) return fail(SKY_ERR_INVALID, "apply_h arguments");
+  if (nstates > c->nq[q]) return fail(SKY_ERR_INVALID, "apply_h: more states than the species holds");
+  apply_h(c->n, psi, hpsi, nstates, c->mfp(q), c->g, eps ? c->at<double>(c->lay.tiles) : nullptr, eps,
+          c->st);
+  return hip_check(hipGetLastError(), "apply_h launch");
+}
+
+int sky_damped_step(sky_ctx* c, int32_t q, const void* psi, const void* hpsi, const double* eps,
+                    void* phi, int32_t nstates, double* r2) {
+  if (!c || q < 0 || q > 1 || !psi || !hpsi || !eps || !phi || nstates < 0)
+    return fail(SKY_ERR_INVALID, "damped_step arguments");
+  if (nstates > c->nq[q]) return fail(SKY_ERR_INVALID, "damped_step: more states than the species holds");
+  double* r2o = r2 ? r2 : c->at<double>(c->lay.r2[q]);
+  const double hb = q ? c->d.hb2m_p : c->d.hb2m_n;
+  damped_step(c->n, psi, hpsi, eps, phi, nstates, c->g, c->d.damp_x0, c->d.damp_e0, hb,
+              c->at<double>(c->lay.tiles), r2o, c->st);
+  return hip_check(hipGetLastError(), "damped_step launch");
+}
+
+int sky_orthonormalize(sky_ctx* c, int32_t q, const void* phi, const void* hphi, void* psi_out,
+                       double* ritz) {
+  if (!c || q < 0 || q > 1 || !phi || !psi_out) return fail(SKY_ERR_INVALID, "orthonormalize arguments");
+  c->last_sweeps = 0;
+  int rc = hphi ? rayleigh_ritz(c, q, phi, hphi, psi_out, ritz) : loewdin(c, q, phi, psi_out);
+  if (rc) return rc;
+  return hip_check(hipStreamSynchronize(c->st), "orthonormalize");
+}
+
+int sky_densities(sky_ctx* c) {
+  if (!c) return fail(SKY_ERR_INVALID, "null context");
+  fields(c);
+  return hip_check(hipGetLastError(), "densities launch");
+}
+
+int sky_iterate(sky_ctx* c, int32_t max_iter, double tol, sky_report* rep) {
+  if (!c || max_iter < 0) return fail(SKY_ERR_INVALID, "iterate arguments");
+  hipStream_t st = c->st;
+  std::vector<double> r2h;
+  double de = 0.0;
+  int it = 0, status = SKY_OK;
+  for (; it < max_iter; ++it) {
+    c->last_sweeps = 0;
+    for (int q = 0; q < 2; ++q) {
+      const int m = c->nq[q];
+      if (m == 0) continue;
+      void* psi = c->at(c->lay.psi[q]);
+      void* hpsi = c->at(c->lay.hpsi[q]);
+      void* phi = c->at(c->lay.phi[q]);
+      void* hphi = c->at(c->lay.hphi[q]);
+      double* eps = c->at<double>(c->lay.eps[q]);
+      double* tiles = c->at<double>(c->lay.tiles);
+      // step 2: h psi, <h>, damped step, h phi
+      apply_h(c->n, psi, hpsi, m, c->mfp(q), c->g, tiles, eps, st);
+      const double hb = q ? c->d.hb2m_p : c->d.hb2m_n;
+      damped_step(c->n, psi, hpsi, eps, phi, m, c->g, c->d.damp_x0, c->d.damp_e0, hb, tiles,
+                  c->at<double>(c->lay.r2[q]), st);
+      apply_h(c->n, phi, hphi, m, c->mfp(q), c->g, nullptr, nullptr, st);
+      // steps 3a-3e
+      int rc = rayleigh_ritz(c, q, phi, hphi, psi, c->at<double>(c->lay.ritz[q]));
+      if (rc) return rc;
+    }
+    // steps 4a, 4b, 5
+    fields(c);
+    // Delta-eps of the states that entered this iteration (Eq. convergence)
+    double sum = 0.0;
+    int cnt = 0;
+    for (int q = 0; q < 2; ++q) {
+      r2h.resize(c->nq[q]);
+      if (c->nq[q] == 0) continue;
+      int rc = hip_check(hipMemcpyAsync(r2h.data(), c->at(c->lay.r2[q]), sizeof(double) * c->nq[q],
+                                        hipMemcpyDeviceToHost, st), "r2 copy");
+      if (rc) return rc;
+      rc = hip_check(hipStreamSynchronize(st), "iterate");
+      if (rc) return rc;
+      for (double v : r2h) sum += v;
+      cnt += c->nq[q];
+    }
+    de = std::sqrt(sum / std::max(1, cnt));
+    if (!std::isfinite(de)) return fail(SKY_ERR_NAN, "non-finite residual");
+    if (tol > 0.0 && de <= tol) { ++it; break; }
+  }
+  double e[8] = {0};
+  int rc = hip_check(hipMemcpyAsync(e, c->at(c->lay.energy), sizeof(e), hipMemcpyDeviceToHost, st),
+                     "energy copy");
+  if (rc) return rc;
+  rc = hip_check(hipStreamSynchronize(st), "iterate");
+  if (rc) return rc;
+  if (!std::isfinite(e[7])) return fail(SKY_ERR_NAN, "non-finite energy");
+  if (tol > 0.0 && !(de <= tol)) status = SKY_NOT_CONVERGED;
+  if (rep) {
+    rep->iters = it;
+    rep->residual = de;
+    rep->energy = e[7];
+    rep->energy_per_a = e[7] / double(c->nq[0] + c->nq[1]);
+    rep->jacobi_sweeps = c->last_sweeps;
+  }
+  return status;
+}
+
+int sky_get_view(sky_ctx* c, int32_t what, int32_t q, void** ptr, int64_t* count) {
+  if (!c || !ptr || !count) return fail(SKY_ERR_INVALID, "get_view arguments");
+  if (q < 0 || q > 1) return fail(SKY_ERR_INVALID, "species must be 0 or 1");
+  const int64_t st = int64_t(c->nq[q]) * c->V;
+  switch (what) {
+    case SKY_VIEW_PSI: *ptr = c->at(c->lay.psi[q]); *count = st; break;
+    case SKY_VIEW_HPSI: *ptr = c->at(c->lay.hpsi[q]); *count = st; break;
+    case SKY_VIEW_PHI: *ptr = c->at(c->lay.phi[q]); *count = st; break;
+    case SKY_VIEW_HPHI: *ptr = c->at(c->lay.hphi[q]); *count = st; break;
+    case SKY_VIEW_DENS: *ptr = c->at(c->lay.dens[q]); *count = 11LL * c->n3; break;
+    case SKY_VIEW_MEANFIELD: *ptr = c->at(c->lay.mf[q]); *count = 5LL * c->n3; break;
+    case SKY_VIEW_COULOMB: *ptr = c->at(c->lay.vc); *count = c->n3; break;
+    case SKY_VIEW_ENERGY: *ptr = c->at(c->lay.energy); *count = 8; break;
+    case SKY_VIEW_EPS: *ptr = c->at(c->lay.eps[q]); *count = c->nq[q]; break;
+    case SKY_VIEW_RITZ: *ptr = c->at(c->lay.ritz[q]); *count = c->nq[q]; break;
+    case SKY_VIEW_R2: *ptr = c->at(c->lay.r2[q]); *count = c->nq[q]; break;
+    case SKY_VIEW_OVERLAP: *ptr = c->at(c->lay.matI); *count = int64_t(c->nq[q]) * c->nq[q]; break;
+    case SKY_VIEW_HSUB: *ptr = c->at(c->lay.matH); *count = int64_t(c->nq[q]) * c->nq[q]; break;
+    case SKY_VIEW_EVEC: *ptr = c->at(c->lay.matZ); *count = int64_t(c->nq[q]) * c->nq[q]; break;
+    case SKY_VIEW_UMAT: *ptr = c->at(c->lay.matU); *count = int64_t(c->nq[q]) * c->nq[q]; break;
+    default: return fail(SKY_ERR_INVALID, "unknown view");
+  }
+  return SKY_OK;
+}
+
+int sky_sync(sky_ctx* c) {
+  if (!c) return fail(SKY_ERR_INVALID, "null context");
+  return hip_check(hipStreamSynchronize(c->st), "sync");
+}
+
+const char* sky_last_error(void) { return g_err.c_str(); }
+
+void sky_destroy(sky_ctx* c) { delete c; }
+
+}  // extern "C"

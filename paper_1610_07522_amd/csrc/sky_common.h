@@ -1,0 +1,65 @@
+// Common device/host definitions of the Sky3D damped-gradient library.
+//
+// Spinor layout everywhere: [state][spin][z][y][x], complex interleaved
+// (re, im), x fastest.  Real fields: [z][y][x].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+namespace sky {
+
+// ------------------------------------------------------------------ complex
+template <typename T> struct cpx {
+  T re, im;
+};
+
+template <typename T> __host__ __device__ inline cpx<T> mk(T r, T i) { return {r, i}; }
+template <typename T> __host__ __device__ inline cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> __host__ __device__ inline cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T> __host__ __device__ inline cpx<T> operator*(cpx<T> a, cpx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> __host__ __device__ inline cpx<T> operator*(T s, cpx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T> __host__ __device__ inline cpx<T> conj(cpx<T> a) { return {a.re, -a.im}; }
+// multiply by i
+template <typename T> __host__ __device__ inline cpx<T> mul_i(cpx<T> a) { return {-a.im, a.re}; }
+template <typename T> __host__ __device__ inline T norm2(cpx<T> a) { return a.re * a.re + a.im * a.im; }
+
+// ------------------------------------------------------------------ grids
+// Supported cubic grid sizes and their two-stage factorisation N = R1 * R2.
+template <int N> struct Fact;
+template <> struct Fact<8>  { static constexpr int R1 = 2, R2 = 4; };
+template <> struct Fact<16> { static constexpr int R1 = 4, R2 = 4; };
+template <> struct Fact<24> { static constexpr int R1 = 4, R2 = 6; };
+template <> struct Fact<32> { static constexpr int R1 = 4, R2 = 8; };
+template <> struct Fact<48> { static constexpr int R1 = 6, R2 = 8; };
+template <> struct Fact<64> { static constexpr int R1 = 8, R2 = 8; };
+
+// Box geometry and spectral constants handed to every kernel by value.
+struct GridArgs {
+  double dx;      // spacing (fm), equal on all axes
+  double dV;      // dx^3
+  double kunit;   // 2 pi / L
+};
+
+// Mean field of one species (device pointers, FP64 fields [z][y][x]).
+struct MeanFieldPtrs {
+  const double* U;
+  const double* B;
+  const double* W;   // [3][z][y][x]
+};
+
+}  // namespace sky
+
+#define SKY_DISPATCH_N(n, ...)                                 \
+  switch (n) {                                                 \
+    case 8:  { constexpr int NN = 8;  __VA_ARGS__; } break;    \
+    case 16: { constexpr int NN = 16; __VA_ARGS__; } break;    \
+    case 24: { constexpr int NN = 24; __VA_ARGS__; } break;    \
+    case 32: { constexpr int NN = 32; __VA_ARGS__; } break;    \
+    case 48: { constexpr int NN = 48; __VA_ARGS__; } break;    \
+    case 64: { constexpr int NN = 64; __VA_ARGS__; } break;    \
+    default: break;                                            \
+  }

@@ -1,0 +1,68 @@
+// Host-side launchers of the library's kernels (all enqueue on `st`).
+#pragma once
+
+#include "sky_common.h"
+
+namespace sky {
+
+// ---- grid kernels (k_grid.hip); states are complex128 [state][2][n^3]
+int grid_ntiles(int n);  // workgroups per state of one line pass
+void apply_h(int n, const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf, GridArgs g,
+             double* eps_part, double* eps, hipStream_t st);
+void damped_step(int n, const void* psi, const void* hpsi, const double* eps, void* phi,
+                 int nstate, GridArgs g, double x0, double e0, double hb2m, double* r2_part,
+                 double* r2, hipStream_t st);
+// dens = 11 fields [rho, tau, Jx, Jy, Jz, sx, sy, sz, jx, jy, jz][n^3];
+// part holds nchunk_max * 16 * n^3 doubles.
+void densities(int n, const void* psi, int nstate, int nchunk_max, GridArgs g, double* part,
+               double* dens, hipStream_t st);
+
+// ---- mean field and energy (k_fields.hip)
+struct Skyrme {
+  double b0, b0p, b1, b1p, b2, b2p, b3, b3p, b4, b4p, alpha;
+  double hb2m_n, hb2m_p, e2;
+};
+// dens[q] as produced by densities(); derived[q] = 5 fields [lap rho, d rho (3), div J];
+// mf[q] = 5 fields [U, B, Wx, Wy, Wz]; vc = Coulomb potential; scratch >= 4 n^3 complex.
+// epart: per-block energy partials, energy[8] = {kin, rho, rho3, tau, lap, so, coul, total}.
+void mean_field(int n, GridArgs g, const Skyrme& sk, const double* dens_n,
+                const double* dens_p, double* derived_n, double* derived_p, double* mf_n,
+                double* mf_p, double* vc, void* scratch, double* epart, double* energy,
+                hipStream_t st);
+int energy_nblocks(int n);
+
+// ---- dense complex matrices (k_gemm.hip); complex128, row-major
+// C[a][b] = scale * sum_v conj(A[a][v]) B[b][v] for b <= a (lower triangle),
+// for two right operands at once (B0 -> C0, B1 -> C1, B1 may be null).
+// part: split * 2 * ntile_pairs * 64*64 complex scratch.
+size_t overlap_scratch_bytes(int m, long k);
+void overlap_lower(const void* A, const void* B0, const void* B1, int m, long k, double scale,
+                   void* C0, void* C1, void* part, hipStream_t st);
+// Fill the upper triangle of Hermitian C from the lower one (and make the
+// diagonal real), in place.
+void hermitian_fill(void* C, int m, hipStream_t st);
+// Y[b][v] = sum_a U[a][b] X[a][v]   (psi = phi U), X: m x k, U: m x m (ld m)
+void combine(const void* X, const void* U, void* Y, int m, long k, hipStream_t st);
+// C = op(A) op(B), square m x m; opA/opB: 0 = N, 1 = conjugate transpose.
+void gemm_square(const void* A, int opA, const void* B, int opB, void* C, int m,
+                 hipStream_t st);
+
+// ---- dense FP64 linear algebra (k_linalg.hip)
+// Cholesky A = L L^H of Hermitian positive definite A (m x m, lower used),
+// then Linv = L^-1 (lower triangular, upper zeroed).  info[0] != 0 when a
+// pivot is not positive.  work >= m*m complex.
+void cholesky_inverse(void* A, void* Linv, int m, void* work, int* info, hipStream_t st);
+// Hermitian eigen-decomposition by blocked two-sided Jacobi: A (m x m, full
+// Hermitian, destroyed) -> eigenvalues w (ascending) and eigenvectors Z
+// (columns).  work: jacobi_scratch_bytes(m).
+size_t jacobi_scratch_bytes(int m);
+int jacobi_eigh(void* A, int m, double* w, void* Z, void* work, double tol, int max_sweeps,
+                hipStream_t st);
+// X <- X diag(d) (scale column b by d[b]), d real.
+void scale_columns(void* X, const double* d, int m, hipStream_t st);
+// w <- w^-1/2 elementwise (Loewdin), flags info if any w <= 0.
+void inv_sqrt(double* w, int m, int* info, hipStream_t st);
+// fill n doubles with zero (a kernel, so it can be captured in graphs)
+void zero(double* p, size_t n, hipStream_t st);
+
+}  // namespace sky

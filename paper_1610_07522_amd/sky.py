@@ -1,0 +1,206 @@
+"""Thin Python binding of the C ABI in ``include/sky.h`` (ctypes).
+
+Argument marshalling only: every step of the solver runs in ``libsky.so``.
+Device memory (the context workspace and any state buffers) comes from
+PyTorch tensors on a ROCm device; the library is handed raw pointers and the
+current HIP stream.  Importing this module does not need a GPU; loading the
+library does need the built ``libsky.so`` and raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsky.so")
+
+SKY_OK = 0
+SKY_NOT_CONVERGED = 1
+SKY_ERR_INVALID = -1
+SKY_ERR_UNSUPPORTED_GRID = -2
+SKY_ERR_WORKSPACE = -3
+SKY_ERR_HIP = -4
+SKY_ERR_NOT_POSITIVE_DEFINITE = -5
+SKY_ERR_NAN = -6
+
+VIEW = dict(psi=0, hpsi=1, phi=2, hphi=3, dens=4, meanfield=5, coulomb=6, energy=7,
+            eps=8, ritz=9, r2=10, overlap=11, hsub=12, evec=13, umat=14)
+_MATRIX_VIEWS = ("overlap", "hsub", "evec", "umat")
+
+# Symbols declared in include/sky.h, in order.
+EXPORTS = ("sky_workspace_size", "sky_create", "sky_init_box", "sky_apply_h",
+           "sky_damped_step", "sky_orthonormalize", "sky_densities", "sky_iterate",
+           "sky_get_view", "sky_sync", "sky_last_error", "sky_destroy")
+
+
+class BoxDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("dx", ctypes.c_double),
+                ("n_neutrons", ctypes.c_int32), ("n_protons", ctypes.c_int32),
+                ("t0", ctypes.c_double), ("t1", ctypes.c_double),
+                ("t2", ctypes.c_double), ("t3", ctypes.c_double),
+                ("x0", ctypes.c_double), ("x1", ctypes.c_double),
+                ("x2", ctypes.c_double), ("x3", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("W0", ctypes.c_double),
+                ("hb2m_n", ctypes.c_double), ("hb2m_p", ctypes.c_double),
+                ("e2", ctypes.c_double),
+                ("damp_x0", ctypes.c_double), ("damp_e0", ctypes.c_double)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("residual", ctypes.c_double),
+                ("energy", ctypes.c_double), ("energy_per_a", ctypes.c_double),
+                ("jacobi_sweeps", ctypes.c_int32)]
+
+
+class SkyError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"sky error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libsky.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            f"{path} not found: build the HIP library first "
+            "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(path)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    dp = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "sky_workspace_size": (ctypes.c_int, [ctypes.POINTER(BoxDesc), ctypes.POINTER(ctypes.c_size_t)]),
+        "sky_create": (ctypes.c_int, [ctypes.POINTER(BoxDesc), vp, ctypes.c_size_t, vp,
+                                      ctypes.POINTER(vp)]),
+        "sky_init_box": (ctypes.c_int, [vp, vp, vp]),
+        "sky_apply_h": (ctypes.c_int, [vp, i32, vp, vp, i32, vp]),
+        "sky_damped_step": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, i32, vp]),
+        "sky_orthonormalize": (ctypes.c_int, [vp, i32, vp, vp, vp, vp]),
+        "sky_densities": (ctypes.c_int, [vp]),
+        "sky_iterate": (ctypes.c_int, [vp, i32, dbl, ctypes.POINTER(Report)]),
+        "sky_get_view": (ctypes.c_int, [vp, i32, i32, ctypes.POINTER(vp),
+                                        ctypes.POINTER(ctypes.c_int64)]),
+        "sky_sync": (ctypes.c_int, [vp]),
+        "sky_last_error": (ctypes.c_char_p, []),
+        "sky_destroy": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _ = dp
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, ok=(SKY_OK,)) -> int:
+    if rc not in ok:
+        raise SkyError(rc, load().sky_last_error().decode())
+    return rc
+
+
+def desc_from_workload(w) -> BoxDesc:
+    """BoxDesc of a ``paper_1610_07522_amd.inputs.Workload``."""
+    p = w.params
+    return BoxDesc(w.n, w.dx, w.n_neutrons, w.n_protons, p["t0"], p["t1"], p["t2"], p["t3"],
+                   p["x0"], p["x1"], p["x2"], p["x3"], p["alpha"], p["W0"],
+                   p["hb2m_n"], p["hb2m_p"], p["e2"], w.damp_x0, w.damp_e0)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Box:
+    """One solver context over a torch-allocated workspace on ``device``."""
+
+    def __init__(self, desc: BoxDesc, device="cuda:0", stream=None):
+        import torch
+        self.lib = load()
+        self.desc = desc
+        self.device = torch.device(device)
+        nbytes = ctypes.c_size_t()
+        _check(self.lib.sky_workspace_size(ctypes.byref(desc), ctypes.byref(nbytes)))
+        self.nbytes = nbytes.value
+        self.ws = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self._pad = (-base) % 256
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        ctx = ctypes.c_void_p()
+        _check(self.lib.sky_create(ctypes.byref(desc), base + self._pad, self.nbytes,
+                                   stream.cuda_stream, ctypes.byref(ctx)))
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.sky_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- entry points
+    def init_box(self, raw_n, raw_p):
+        _check(self.lib.sky_init_box(self.ctx, _ptr(raw_n), _ptr(raw_p)))
+
+    def apply_h(self, q, psi, hpsi, nstates, eps=None):
+        _check(self.lib.sky_apply_h(self.ctx, q, _ptr(psi), _ptr(hpsi), nstates, _ptr(eps)))
+
+    def damped_step(self, q, psi, hpsi, eps, phi, nstates, r2=None):
+        _check(self.lib.sky_damped_step(self.ctx, q, _ptr(psi), _ptr(hpsi), _ptr(eps),
+                                        _ptr(phi), nstates, _ptr(r2)))
+
+    def orthonormalize(self, q, phi, hphi, psi_out, ritz=None):
+        _check(self.lib.sky_orthonormalize(self.ctx, q, _ptr(phi), _ptr(hphi), _ptr(psi_out),
+                                           _ptr(ritz)))
+
+    def densities(self):
+        _check(self.lib.sky_densities(self.ctx))
+
+    def iterate(self, max_iter: int, tol: float = 0.0) -> Dict[str, float]:
+        rep = Report()
+        rc = _check(self.lib.sky_iterate(self.ctx, max_iter, tol, ctypes.byref(rep)),
+                    ok=(SKY_OK, SKY_NOT_CONVERGED))
+        return dict(iters=rep.iters, residual=rep.residual, energy=rep.energy,
+                    energy_per_a=rep.energy_per_a, jacobi_sweeps=rep.jacobi_sweeps,
+                    converged=(rc == SKY_OK))
+
+    def sync(self):
+        _check(self.lib.sky_sync(self.ctx))
+
+    # -------------------------------------------------------------- views
+    def view(self, what: str, q: int = 0):
+        """A torch tensor aliasing one of the context's device buffers."""
+        import torch
+        ptr = ctypes.c_void_p()
+        cnt = ctypes.c_int64()
+        _check(self.lib.sky_get_view(self.ctx, VIEW[what], q, ctypes.byref(ptr),
+                                     ctypes.byref(cnt)))
+        is_state = what in ("psi", "hpsi", "phi", "hphi")
+        is_cpx = is_state or what in _MATRIX_VIEWS
+        dt = torch.complex128 if is_cpx else torch.float64
+        esize = 16 if is_cpx else 8
+        off = ptr.value - self.ws.data_ptr() if ptr.value else 0
+        t = self.ws[off:off + cnt.value * esize].view(dt)
+        n = self.desc.n
+        if is_state:
+            return t.view(-1, 2, n, n, n)
+        if what in ("dens", "meanfield"):
+            return t.view(-1, n, n, n)
+        if what == "coulomb":
+            return t.view(n, n, n)
+        if what in _MATRIX_VIEWS:
+            m = int(round(cnt.value ** 0.5))
+            return t.view(m, m)
+        return t

@@ -1,0 +1,84 @@
+"""The C-ABI library loads on the CPU, exports every symbol that
+include/sky.h declares, and validates its arguments without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1610_07522_amd import inputs, sky
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "sky.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sky_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(sky.LIB_PATH):
+        pytest.skip("libsky.so not built")
+    return sky.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert set(names) == set(sky.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def _desc(**kw):
+    d = sky.desc_from_workload(inputs.WORKLOADS["fermi16"])
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+def test_workspace_size_and_validation(lib):
+    nb = ctypes.c_size_t()
+    assert lib.sky_workspace_size(ctypes.byref(_desc()), ctypes.byref(nb)) == sky.SKY_OK
+    small = nb.value
+    assert lib.sky_workspace_size(ctypes.byref(_desc(n=32)), ctypes.byref(nb)) == sky.SKY_OK
+    assert nb.value > small
+    assert lib.sky_workspace_size(ctypes.byref(_desc(n=20)), ctypes.byref(nb)) == \
+        sky.SKY_ERR_UNSUPPORTED_GRID
+    assert b"grid" in lib.sky_last_error()
+    assert lib.sky_workspace_size(ctypes.byref(_desc(dx=0.0)), ctypes.byref(nb)) == \
+        sky.SKY_ERR_INVALID
+    assert lib.sky_workspace_size(ctypes.byref(_desc(n_neutrons=0, n_protons=0)),
+                                  ctypes.byref(nb)) == sky.SKY_ERR_INVALID
+    assert lib.sky_workspace_size(ctypes.byref(_desc(damp_e0=0.0)),
+                                  ctypes.byref(nb)) == sky.SKY_ERR_INVALID
+
+
+def test_create_rejects_small_or_misaligned_workspace(lib):
+    d = _desc()
+    nb = ctypes.c_size_t()
+    lib.sky_workspace_size(ctypes.byref(d), ctypes.byref(nb))
+    ctx = ctypes.c_void_p()
+    fake = 1 << 40   # never dereferenced: creation only records the pointer
+    assert lib.sky_create(ctypes.byref(d), fake, nb.value - 1, None, ctypes.byref(ctx)) == \
+        sky.SKY_ERR_WORKSPACE
+    assert lib.sky_create(ctypes.byref(d), fake + 8, nb.value, None, ctypes.byref(ctx)) == \
+        sky.SKY_ERR_WORKSPACE
+    assert lib.sky_create(ctypes.byref(d), fake, nb.value, None, ctypes.byref(ctx)) == sky.SKY_OK
+    # invalid species / null pointers are rejected before any device work
+    assert lib.sky_apply_h(ctx, 2, fake, fake, 1, None) == sky.SKY_ERR_INVALID
+    assert lib.sky_apply_h(ctx, 0, fake, fake, 9, None) == sky.SKY_ERR_INVALID
+    assert lib.sky_get_view(ctx, 99, 0, ctypes.byref(ctypes.c_void_p()),
+                            ctypes.byref(ctypes.c_int64())) == sky.SKY_ERR_INVALID
+    lib.sky_destroy(ctx)
+
+
+def test_workspace_holds_the_largest_workload(lib):
+    """48^3 x 2000 FP64 fits one MI355X (288 GB): four state arrays + rest."""
+    d = sky.desc_from_workload(inputs.WORKLOADS["rod48"])
+    nb = ctypes.c_size_t()
+    assert lib.sky_workspace_size(ctypes.byref(d), ctypes.byref(nb)) == sky.SKY_OK
+    states = 4 * 2000 * 2 * 48 ** 3 * 16
+    assert states <= nb.value < states * 1.3
+    assert nb.value < 288e9
