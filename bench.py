@@ -1,0 +1,211 @@
+#!/usr/bin/env python
+"""Damped-gradient iterations per second of the 48^3 x 2000-nucleon pasta box.
+
+One step = one full static iteration (Fig. 1 steps 2-5 of the paper) for
+both species: h psi, damped gradient step, h phi, overlap and subspace
+Hamiltonian GEMMs, Cholesky + Jacobi Rayleigh-Ritz, recombination GEMM,
+densities, mean field, Coulomb and energy.  Inputs are synthetic (seeded
+rod-perturbed plane waves, SLy4) and already resident in HBM when the timed
+region starts.  Prints one JSON line.
+
+The roofline entry is for the kernel with the most device time, timed with
+HIP events on the library's own stream; cpu_baseline is the FP64 numpy
+oracle timed on a bounded sample of the same iteration and scaled to a full
+iteration.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix and vector)
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def gemm_flops(m: int, v: int) -> dict:
+    """Algorithmic real flops per launch: complex MAC = 8 flops.
+    overlap: I and H lower triangles incl. diagonal; combine: psi = phi U."""
+    return dict(overlap_gemm=8.0 * 2 * (m * (m + 1) // 2) * v,
+                combine_gemm=8.0 * m * m * v)
+
+
+def roofline(timing: dict, w, steps: int) -> dict:
+    """Roofline object of the phase kernel with the most device time."""
+    v = 2 * w.n ** 3
+    cand = {}
+    for ph in ("overlap_gemm", "combine_gemm", "apply_h", "damp", "densities", "subspace"):
+        t = timing[ph]
+        cand[ph] = t["ms_n"] + t["ms_p"]
+    dom = max(cand, key=cand.get)
+    t = timing[dom]
+    m = w.n_neutrons
+    avg_ms = t["ms_n"] / max(1, t["launches_n"])
+    if dom in ("overlap_gemm", "combine_gemm"):
+        fl = gemm_flops(m, v)[dom]
+        ach = fl / (avg_ms * 1e-3) / 1e12
+        return dict(kernel=("k_overlap_lower" if dom == "overlap_gemm" else "k_combine"),
+                    bound="mfma", achieved=ach, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                    frac=ach / PEAK_FP64_TFLOPS, traffic=None,
+                    per_launch=dict(species="neutrons", m=m, k=v, flops=fl, avg_ms=avg_ms))
+    # grid passes: algorithmic bytes = read psi + write result (complex128)
+    nbytes = 2.0 * m * v * 16
+    ach = nbytes / (avg_ms * 1e-3) / 1e9
+    return dict(kernel=dom, bound="hbm", achieved=ach, peak=PEAK_HBM_GBS, unit="GB/s",
+                frac=ach / PEAK_HBM_GBS, traffic=None,
+                per_launch=dict(species="neutrons", m=m, bytes=nbytes, avg_ms=avg_ms))
+
+
+def cpu_baseline(w, budget_states: int = 8, k_slice: int = 32) -> dict:
+    """FP64 oracle on the host, bounded sample, scaled to one full iteration.
+
+    Per-state work (h psi twice, damping, densities) is timed on
+    ``budget_states`` states per species and scaled by N_q / budget; the
+    overlap/H and recombination products on 1/k_slice of the grid
+    (contraction length) and scaled by k_slice; mean field and the dense
+    Rayleigh-Ritz (Cholesky, eigh) of both species run in full.
+    """
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import Grid
+    from oracle import physics as ph
+    from oracle import solver as so
+    from paper_1610_07522_amd import inputs
+
+    cores = int(os.environ.get("SKY_ORACLE_THREADS", "0")) or len(os.sched_getaffinity(0))
+    os.environ["SKY_ORACLE_THREADS"] = str(cores)
+    g = Grid(w.n, w.dx)
+    v = 2 * w.n ** 3
+    sub = inputs.Workload("sample", w.n, w.dx, budget_states, budget_states, w.init,
+                          seed=w.seed, amp=w.amp, noise=w.noise)
+    rn, rp = inputs.raw_states(sub)
+    t = {}
+    with threadpool_limits(limits=cores):
+        t0 = time.perf_counter()
+        dn, dp = ph.densities(rn, g), ph.densities(rp, g)
+        t["densities"] = (time.perf_counter() - t0) * w.n_states / (2 * budget_states)
+        t0 = time.perf_counter()
+        mn, mp, vc = ph.mean_field(dn, dp, g, w.params)
+        ph.energy(dn, dp, g, w.params, vc)
+        t["meanfield"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for raw, mf in ((rn, mn), (rp, mp)):
+            h = ph.apply_h(raw, mf, g)
+            eps, r, _ = so.rayleigh_and_residual(raw, h, g)
+            phi = raw - so.damping(r, g, mf.hb2m, w.damp_x0, w.damp_e0)
+            ph.apply_h(phi, mf, g)
+        t["per_state"] = (time.perf_counter() - t0) * w.n_states / (2 * budget_states)
+        rng = np.random.default_rng(0)
+        kk = v // k_slice
+        t_gemm = 0.0
+        t_rr = 0.0
+        for m in (w.n_neutrons, w.n_protons):
+            a = rng.standard_normal((m, kk)) + 1j * rng.standard_normal((m, kk))
+            b = rng.standard_normal((m, kk)) + 1j * rng.standard_normal((m, kk))
+            t0 = time.perf_counter()
+            I = g.dV * (a.conj() @ a.T)
+            H = g.dV * (a.conj() @ b.T)
+            U = np.eye(m, dtype=complex) + 1e-3 * I / max(1.0, abs(I).max())
+            (U.T @ a)
+            t_gemm += (time.perf_counter() - t0) * k_slice
+            Ih = a.conj() @ a.T / kk + np.eye(m)
+            Hh = 0.5 * (H + H.conj().T)
+            t0 = time.perf_counter()
+            so.rayleigh_ritz(Ih, Hh)
+            t_rr += time.perf_counter() - t0
+        t["gemm"] = t_gemm
+        t["rayleigh_ritz"] = t_rr
+    sec = sum(t.values())
+    sample = (f"{budget_states}+{budget_states} states for the per-state phases (scaled x"
+              f"{w.n_states / (2 * budget_states):.0f}), 1/{k_slice} of the grid for the "
+              f"overlap/H/recombination products (scaled x{k_slice}), full mean field and "
+              f"full dense Rayleigh-Ritz of both species; est. {sec:.1f} s per iteration")
+    return dict(value=1.0 / sec, unit="iter/s", cores=cores, kind="oracle", sample=sample,
+                seconds_per_iter=sec, parts_s={k: round(x, 3) for k, x in t.items()})
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rod48")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1610_07522_amd import inputs, sky
+
+    w = inputs.WORKLOADS[args.workload]
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    log(f"workload {w.name}: {w.n}^3, {w.n_neutrons} n + {w.n_protons} p; generating inputs")
+    t0 = time.perf_counter()
+    raw_n, raw_p = inputs.raw_states(w)
+    dn = torch.from_numpy(raw_n).to(dev)
+    dp = torch.from_numpy(raw_p).to(dev)
+    del raw_n, raw_p
+    log(f"inputs on device in {time.perf_counter() - t0:.1f} s; building context")
+    box = sky.Box(sky.desc_from_workload(w), device=dev)
+    t0 = time.perf_counter()
+    box.init_box(dn, dp)
+    torch.cuda.synchronize()
+    del dn, dp
+    log(f"init (Loewdin, densities, mean field) {time.perf_counter() - t0:.1f} s")
+    for i in range(args.warmup):
+        rep = box.iterate(1)
+        log(f"warmup {i + 1}/{args.warmup}: residual {rep['residual']:.4e} E {rep['energy']:.6f}")
+    box.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    for i in range(args.steps):
+        reps.append(box.iterate(1))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timing = box.timing()
+    box.set_timing(False)
+    log(f"timed {args.steps} steps in {elapsed:.3f} s; last residual "
+        f"{reps[-1]['residual']:.4e} E/A {reps[-1]['energy_per_a']:.6f}")
+    phases = {k: round((v["ms_n"] + v["ms_p"]) / args.steps, 3) for k, v in timing.items()}
+    out = dict(
+        metric="damped-gradient iterations/s, 48^3 box, 2000 nucleons",
+        value=args.steps / elapsed, unit="iter/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=1e3 * elapsed / args.steps, higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+        config=dict(workload=(f"{w.name}: {w.n}^3 grid, dx {w.dx} fm, {w.n_neutrons} n + "
+                              f"{w.n_protons} p, rod-perturbed plane waves, SLy4, "
+                              f"complex128 states, FP64 throughout"),
+                    grid=w.n, nucleons=w.n_states, precision="fp64"),
+        roofline=roofline(timing, w, args.steps),
+        phases_ms_per_iter=phases,
+        residual=reps[-1]["residual"], energy_per_a=reps[-1]["energy_per_a"],
+    )
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

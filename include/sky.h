@@ -100,6 +100,18 @@ enum {
   SKY_VIEW_UMAT = 14      /* combined transform U, psi = phi U                   */
 };
 
+/* Timed phases of one iteration (sky_set_timing / sky_get_timing). */
+enum {
+  SKY_PHASE_APPLY_H = 0,       /* h psi and h phi (Fig. 1 step 2)                 */
+  SKY_PHASE_DAMP = 1,          /* damped gradient step (Eq. dampstep)             */
+  SKY_PHASE_OVERLAP_GEMM = 2,  /* the I/H GEMM kernel alone (step 3a)             */
+  SKY_PHASE_SUBSPACE = 3,      /* I/H reduction, Cholesky, H', eigensolver, U     */
+  SKY_PHASE_COMBINE_GEMM = 4,  /* psi = phi U GEMM kernel (step 3e)               */
+  SKY_PHASE_DENSITIES = 5,     /* rho, tau, J (step 4a)                           */
+  SKY_PHASE_MEANFIELD = 6,     /* mean field, Coulomb, energy (steps 4b, 5)       */
+  SKY_NPHASE = 7
+};
+
 typedef struct sky_ctx sky_ctx;
 
 /* Bytes of device workspace a context for `d` needs (256-byte aligned). */
@@ -165,6 +177,17 @@ int sky_iterate(sky_ctx* c, int32_t max_iter, double tol_mev, sky_report* report
  * of one of the context's buffers.  The memory stays owned by the caller's
  * workspace. */
 int sky_get_view(sky_ctx* c, int32_t what, int32_t q, void** ptr_dev, int64_t* count);
+
+/* Phase timing of sky_iterate: enable != 0 starts recording HIP event pairs
+ * on the context stream around every phase (and resets the accumulators);
+ * enable == 0 stops.  Waits for the stream. */
+int sky_set_timing(sky_ctx* c, int32_t enable);
+
+/* Accumulated device time (ms) and number of timed launches per phase and
+ * species since sky_set_timing: ms[2*phase + q], launches[2*phase + q]
+ * (host arrays of 2*SKY_NPHASE; launches may be NULL; phases that are not
+ * per species use q = 0).  Waits for the stream. */
+int sky_get_timing(sky_ctx* c, double* ms, int64_t* launches);
 
 /* Wait for all work of the context's stream. */
 int sky_sync(sky_ctx* c);

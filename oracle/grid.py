@@ -18,11 +18,13 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 
 import numpy as np
 import scipy.fft as sfft
 
-_WORKERS = -1  # all host cores for scipy.fft
+# threads of scipy.fft (SKY_ORACLE_THREADS, default: every core of the process)
+_WORKERS = int(os.environ.get("SKY_ORACLE_THREADS", "0")) or -1
 
 
 @dataclasses.dataclass(frozen=True)

@@ -27,7 +27,7 @@ from typing import Dict, Tuple
 import numpy as np
 import scipy.fft as sfft
 
-from .grid import Grid, deriv, deriv_real, laplacian_real
+from .grid import _WORKERS, Grid, deriv, deriv_real, laplacian_real
 
 # Pauli matrices sigma_x, sigma_y, sigma_z
 SIGMA = np.array([[[0, 1], [1, 0]],
@@ -99,11 +99,11 @@ def coulomb(rho_p: np.ndarray, g: Grid, e2: float) -> np.ndarray:
     V_C(k) = 4 pi e^2 rho_p(k) / |k|^2 for k != 0, and 0 at k = 0.
     """
     k2 = g.k2()
-    fk = sfft.fftn(rho_p, workers=-1)
+    fk = sfft.fftn(rho_p, workers=_WORKERS)
     with np.errstate(divide="ignore", invalid="ignore"):
         mult = np.where(k2 > 0.0, 4.0 * math.pi * e2 / np.where(k2 > 0, k2, 1.0),
                         0.0)
-    return sfft.ifftn(fk * mult, workers=-1).real
+    return sfft.ifftn(fk * mult, workers=_WORKERS).real
 
 
 @dataclasses.dataclass

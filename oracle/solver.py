@@ -30,7 +30,7 @@ from typing import Dict, List, Optional
 import numpy as np
 import scipy.fft as sfft
 
-from .grid import Grid
+from .grid import _WORKERS, Grid
 from .physics import (Densities, MeanField, apply_h, densities, energy,
                       mean_field)
 
@@ -76,9 +76,9 @@ def rayleigh_ritz(I: np.ndarray, H: np.ndarray):
 def damping(r: np.ndarray, g: Grid, hb2m: float, x0: float, e0: float
             ) -> np.ndarray:
     """x0 * F^-1[ F(r) / (E0 + hb2m |k|^2) ] per spinor component (Eq. dampstep)."""
-    fk = sfft.fftn(r, axes=(-3, -2, -1), workers=-1)
+    fk = sfft.fftn(r, axes=(-3, -2, -1), workers=_WORKERS)
     fk *= x0 / (e0 + hb2m * g.k2())
-    return sfft.ifftn(fk, axes=(-3, -2, -1), workers=-1)
+    return sfft.ifftn(fk, axes=(-3, -2, -1), workers=_WORKERS)
 
 
 def rayleigh_and_residual(psi: np.ndarray, hpsi: np.ndarray, g: Grid):

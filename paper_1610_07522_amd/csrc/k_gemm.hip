@@ -259,15 +259,17 @@ size_t overlap_scratch_bytes(int m, long k) {
 }
 
 void overlap_lower(const void* A, const void* B0, const void* B1, int m, long k, double scale,
-                   void* C0, void* C1, void* part, hipStream_t st) {
+                   void* C0, void* C1, void* part, hipStream_t st, hipEvent_t* ev) {
   if (m <= 0) return;
   const int nt = (m + TM - 1) / TM;
   const int npair = nt * (nt + 1) / 2;
   const int split = overlap_split(m, k);
   const int nz = B1 ? 2 : 1;
+  if (ev) hipEventRecord(ev[0], st);
   hipLaunchKernelGGL(k_overlap_lower, dim3(npair, split, nz), dim3(GT), 0, st,
                      (const double2*)A, (const double2*)B0, (const double2*)B1, m, k, split,
                      (double2*)part);
+  if (ev) hipEventRecord(ev[1], st);
   hipLaunchKernelGGL(k_overlap_reduce, dim3(npair, nz), dim3(256), 0, st, (const double2*)part,
                      npair, split, m, scale, (double2*)C0, (double2*)C1);
 }

@@ -214,15 +214,19 @@ struct Rot {
 
 __device__ inline Rot make_rot(double a, double b, double2 apq) {
   Rot g;
-  double r = sqrt(apq.x * apq.x + apq.y * apq.y);
-  if (r == 0.0 || r < 1e-300) {
+  // |a_pq| by a scaled hypot: the plain sqrt(x^2 + y^2) underflows for the
+  // ~1e-160 couplings that quadratic convergence produces, which would give
+  // |e^{i phi}| != 1 and a non-unitary rotation.  Couplings below 1e-18 of
+  // the diagonal scale are treated as converged (no rotation).
+  const double r = hypot(apq.x, apq.y);
+  if (!(r > 1e-18 * (fabs(a) + fabs(b))) || r < 1e-250) {
     g.c = 1.0; g.s = 0.0; g.er = 1.0; g.ei = 0.0;
     return g;
   }
   g.er = apq.x / r;
   g.ei = apq.y / r;
   double zeta = (b - a) / (2.0 * r);
-  double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
   g.c = 1.0 / sqrt(1.0 + t * t);
   g.s = t * g.c;
   return g;

@@ -124,6 +124,13 @@ struct sky_ctx {
   GridArgs g;
   Skyrme sk;
   int last_sweeps;
+  // phase timing: HIP event pairs on the context stream
+  struct Mark { int phase, q; hipEvent_t a, b; };
+  bool timing = false;
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> pool;
+  double ms[SKY_NPHASE][2] = {};
+  int64_t cnt[SKY_NPHASE][2] = {};
 
   template <typename P = char> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
   MeanFieldPtrs mfp(int q) const {
@@ -133,6 +140,44 @@ struct sky_ctx {
 };
 
 namespace {
+hipEvent_t take_event(sky_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  hipEventCreate(&e);
+  return e;
+}
+
+// Start a timed phase; returns the mark index or -1 when timing is off.
+int t_begin(sky_ctx* c, int phase, int q) {
+  if (!c->timing) return -1;
+  sky_ctx::Mark m{phase, q, take_event(c), take_event(c)};
+  hipEventRecord(m.a, c->st);
+  c->marks.push_back(m);
+  return int(c->marks.size()) - 1;
+}
+
+void t_end(sky_ctx* c, int idx) {
+  if (idx >= 0) hipEventRecord(c->marks[idx].b, c->st);
+}
+
+// After the stream has been synchronised: accumulate and recycle events.
+void t_flush(sky_ctx* c) {
+  for (auto& m : c->marks) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, m.a, m.b) == hipSuccess) {
+      c->ms[m.phase][m.q] += t;
+      c->cnt[m.phase][m.q] += 1;
+    }
+    c->pool.push_back(m.a);
+    c->pool.push_back(m.b);
+  }
+  c->marks.clear();
+}
+
 int check_info(sky_ctx* c, const char* what) {
   int info = 0;
   int rc = hip_check(hipMemcpyAsync(&info, c->at<int>(c->lay.info), sizeof(int),
@@ -160,7 +205,16 @@ int rayleigh_ritz(sky_ctx* c, int q, const void* phi, const void* hphi, void* ps
   int* info = c->at<int>(c->lay.info);
   hipMemsetAsync(info, 0, sizeof(int), st);
   // step 3a: I and H, lower triangles, then mirrored
-  overlap_lower(phi, phi, hphi, m, c->V, c->g.dV, I, H, c->at(c->lay.gemm_part), st);
+  int tm = -1;
+  hipEvent_t ev[2];
+  if (c->timing) {
+    tm = t_begin(c, SKY_PHASE_OVERLAP_GEMM, q);   // events re-recorded around the kernel
+    ev[0] = c->marks[tm].a;
+    ev[1] = c->marks[tm].b;
+  }
+  overlap_lower(phi, phi, hphi, m, c->V, c->g.dV, I, H, c->at(c->lay.gemm_part), st,
+                c->timing ? ev : nullptr);
+  const int ts = t_begin(c, SKY_PHASE_SUBSPACE, q);
   hermitian_fill(I, m, st);
   hermitian_fill(H, m, st);
   // steps 3b-3c: I = L L^H, H' = L^-1 H L^-H, H' = Z lam Z^H
@@ -176,7 +230,10 @@ int rayleigh_ritz(sky_ctx* c, int q, const void* phi, const void* hphi, void* ps
   c->last_sweeps += jacobi_eigh(Hp, m, w, Z, c->at(c->lay.jac_work), JACOBI_TOL, JACOBI_SWEEPS, st);
   // steps 3d-3e: U = L^-H Z, psi = phi U
   gemm_square(Linv, 1, Z, 0, U, m, st);
+  t_end(c, ts);
+  const int tc = t_begin(c, SKY_PHASE_COMBINE_GEMM, q);
   combine(phi, U, psi_out, m, c->V, st);
+  t_end(c, tc);
   return SKY_OK;
 }
 
@@ -208,14 +265,19 @@ int loewdin(sky_ctx* c, int q, const void* phi, void* psi_out) {
 
 void fields(sky_ctx* c) {
   hipStream_t st = c->st;
-  for (int q = 0; q < 2; ++q)
+  for (int q = 0; q < 2; ++q) {
+    const int td = t_begin(c, SKY_PHASE_DENSITIES, q);
     sky::densities(c->n, c->at(c->lay.psi[q]), c->nq[q], DENS_CHUNKS, c->g,
                    c->at<double>(c->lay.dens_part), c->at<double>(c->lay.dens[q]), st);
+    t_end(c, td);
+  }
+  const int tmf = t_begin(c, SKY_PHASE_MEANFIELD, 0);
   mean_field(c->n, c->g, c->sk, c->at<double>(c->lay.dens[0]), c->at<double>(c->lay.dens[1]),
              c->at<double>(c->lay.der[0]), c->at<double>(c->lay.der[1]),
              c->at<double>(c->lay.mf[0]), c->at<double>(c->lay.mf[1]),
              c->at<double>(c->lay.vc), c->at(c->lay.fscratch), c->at<double>(c->lay.epart),
              c->at<double>(c->lay.energy), st);
+  t_end(c, tmf);
 }
 }  // namespace
 
@@ -338,11 +400,17 @@ int sky_iterate(sky_ctx* c, int32_t max_iter, double tol, sky_report* rep) {
       double* eps = c->at<double>(c->lay.eps[q]);
       double* tiles = c->at<double>(c->lay.tiles);
       // step 2: h psi, <h>, damped step, h phi
+      int t0 = t_begin(c, SKY_PHASE_APPLY_H, q);
       apply_h(c->n, psi, hpsi, m, c->mfp(q), c->g, tiles, eps, st);
+      t_end(c, t0);
       const double hb = q ? c->d.hb2m_p : c->d.hb2m_n;
+      int t1 = t_begin(c, SKY_PHASE_DAMP, q);
       damped_step(c->n, psi, hpsi, eps, phi, m, c->g, c->d.damp_x0, c->d.damp_e0, hb, tiles,
                   c->at<double>(c->lay.r2[q]), st);
+      t_end(c, t1);
+      int t2 = t_begin(c, SKY_PHASE_APPLY_H, q);
       apply_h(c->n, phi, hphi, m, c->mfp(q), c->g, nullptr, nullptr, st);
+      t_end(c, t2);
       // steps 3a-3e
       int rc = rayleigh_ritz(c, q, phi, hphi, psi, c->at<double>(c->lay.ritz[q]));
       if (rc) return rc;
@@ -363,6 +431,7 @@ int sky_iterate(sky_ctx* c, int32_t max_iter, double tol, sky_report* rep) {
       for (double v : r2h) sum += v;
       cnt += c->nq[q];
     }
+    t_flush(c);
     de = std::sqrt(sum / std::max(1, cnt));
     if (!std::isfinite(de)) return fail(SKY_ERR_NAN, "non-finite residual");
     if (tol > 0.0 && de <= tol) { ++it; break; }
@@ -410,6 +479,30 @@ int sky_get_view(sky_ctx* c, int32_t what, int32_t q, void** ptr, int64_t* count
   return SKY_OK;
 }
 
+int sky_set_timing(sky_ctx* c, int32_t enable) {
+  if (!c) return fail(SKY_ERR_INVALID, "null context");
+  int rc = hip_check(hipStreamSynchronize(c->st), "set_timing");
+  if (rc) return rc;
+  t_flush(c);
+  c->timing = enable != 0;
+  for (int p = 0; p < SKY_NPHASE; ++p)
+    for (int q = 0; q < 2; ++q) { c->ms[p][q] = 0.0; c->cnt[p][q] = 0; }
+  return SKY_OK;
+}
+
+int sky_get_timing(sky_ctx* c, double* ms, int64_t* launches) {
+  if (!c || !ms) return fail(SKY_ERR_INVALID, "get_timing arguments");
+  int rc = hip_check(hipStreamSynchronize(c->st), "get_timing");
+  if (rc) return rc;
+  t_flush(c);
+  for (int p = 0; p < SKY_NPHASE; ++p)
+    for (int q = 0; q < 2; ++q) {
+      ms[2 * p + q] = c->ms[p][q];
+      if (launches) launches[2 * p + q] = c->cnt[p][q];
+    }
+  return SKY_OK;
+}
+
 int sky_sync(sky_ctx* c) {
   if (!c) return fail(SKY_ERR_INVALID, "null context");
   return hip_check(hipStreamSynchronize(c->st), "sync");
@@ -417,6 +510,12 @@ int sky_sync(sky_ctx* c) {
 
 const char* sky_last_error(void) { return g_err.c_str(); }
 
-void sky_destroy(sky_ctx* c) { delete c; }
+void sky_destroy(sky_ctx* c) {
+  if (!c) return;
+  hipStreamSynchronize(c->st);
+  for (auto& m : c->marks) { hipEventDestroy(m.a); hipEventDestroy(m.b); }
+  for (auto e : c->pool) hipEventDestroy(e);
+  delete c;
+}
 
 }  // extern "C"

@@ -36,8 +36,9 @@ int energy_nblocks(int n);
 // for two right operands at once (B0 -> C0, B1 -> C1, B1 may be null).
 // part: split * 2 * ntile_pairs * 64*64 complex scratch.
 size_t overlap_scratch_bytes(int m, long k);
+// ev (may be null): events recorded right before / after the GEMM kernel.
 void overlap_lower(const void* A, const void* B0, const void* B1, int m, long k, double scale,
-                   void* C0, void* C1, void* part, hipStream_t st);
+                   void* C0, void* C1, void* part, hipStream_t st, hipEvent_t* ev = nullptr);
 // Fill the upper triangle of Hermitian C from the lower one (and make the
 // diagonal real), in place.
 void hermitian_fill(void* C, int m, hipStream_t st);

@@ -31,7 +31,10 @@ _MATRIX_VIEWS = ("overlap", "hsub", "evec", "umat")
 # Symbols declared in include/sky.h, in order.
 EXPORTS = ("sky_workspace_size", "sky_create", "sky_init_box", "sky_apply_h",
            "sky_damped_step", "sky_orthonormalize", "sky_densities", "sky_iterate",
-           "sky_get_view", "sky_sync", "sky_last_error", "sky_destroy")
+           "sky_get_view", "sky_set_timing", "sky_get_timing", "sky_sync",
+           "sky_last_error", "sky_destroy")
+PHASES = ("apply_h", "damp", "overlap_gemm", "subspace", "combine_gemm", "densities",
+          "meanfield")
 
 
 class BoxDesc(ctypes.Structure):
@@ -86,6 +89,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "sky_iterate": (ctypes.c_int, [vp, i32, dbl, ctypes.POINTER(Report)]),
         "sky_get_view": (ctypes.c_int, [vp, i32, i32, ctypes.POINTER(vp),
                                         ctypes.POINTER(ctypes.c_int64)]),
+        "sky_set_timing": (ctypes.c_int, [vp, i32]),
+        "sky_get_timing": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_int64)]),
         "sky_sync": (ctypes.c_int, [vp]),
         "sky_last_error": (ctypes.c_char_p, []),
         "sky_destroy": (None, [vp]),
@@ -178,6 +184,18 @@ class Box:
 
     def sync(self):
         _check(self.lib.sky_sync(self.ctx))
+
+    def set_timing(self, enable: bool):
+        _check(self.lib.sky_set_timing(self.ctx, 1 if enable else 0))
+
+    def timing(self) -> Dict[str, Dict[str, float]]:
+        """Per phase and species: accumulated device ms and launch counts."""
+        n = 2 * len(PHASES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        _check(self.lib.sky_get_timing(self.ctx, ms, cnt))
+        return {p: dict(ms_n=ms[2 * i], ms_p=ms[2 * i + 1], launches_n=cnt[2 * i],
+                        launches_p=cnt[2 * i + 1]) for i, p in enumerate(PHASES)}
 
     # -------------------------------------------------------------- views
     def view(self, what: str, q: int = 0):

@@ -11,6 +11,8 @@ CASES = {
     "n24_13p7_rod": inputs.small_workload("n24", 24, 13, 7, init="rod", seed=31, noise=0.05),
     "n8_5p3": inputs.small_workload("n8", 8, 5, 3, init="slab", seed=32, noise=0.2),
     "n32_70p33_slab": inputs.small_workload("n32", 32, 70, 33, init="slab", seed=33, noise=0.02),
+    # pasta density 0.018 fm^-3: several Cholesky blocks and Jacobi block pairs
+    "n24_200p50_rod": inputs.small_workload("n24r", 24, 200, 50, init="rod", seed=2, noise=0.0),
 }
 
 

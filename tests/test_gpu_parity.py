@@ -155,7 +155,7 @@ def test_rayleigh_ritz(torch_mod, case):
 
 
 ITERS = {"n16_8p8": (1, 10, 50), "n24_13p7_rod": (1, 5), "n8_5p3": (1, 10, 40),
-         "n32_70p33_slab": (1, 3)}
+         "n32_70p33_slab": (1, 3), "n24_200p50_rod": (1, 3)}
 
 
 @pytest.mark.parametrize("case", list(CASES))
