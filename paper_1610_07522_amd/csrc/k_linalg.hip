@@ -20,6 +20,10 @@ namespace {
 constexpr int CB = 64;    // Cholesky block
 constexpr int JB = 32;    // Jacobi block (pair sub-problem = 2*JB)
 constexpr int JP = 2 * JB;
+// Cyclic sweeps per pair sub-problem and round.  The pair tolerance is 100x
+// tighter than the global one so that the ~(n/32)^2/2 converged pair blocks
+// together stay below the global off-diagonal bound.
+constexpr int JACOBI_INNER = 3;
 
 __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -241,14 +245,15 @@ __device__ inline void rr_pair(int np, int r, int i, int& p, int& q) {
 
 // Diagonalise the 64x64 pair sub-matrix of blocks (P, Q) of A (ld = mp)
 // and write its unitary J (64x64, row-major, local index l < 32 -> block P).
-__global__ void __launch_bounds__(256)
+constexpr int JT = 1024;   // threads of a pair sub-problem workgroup
+__global__ void __launch_bounds__(JT)
 k_jacobi_pair(const double2* __restrict__ A, int mp, const int2* __restrict__ pairs,
-              double2* __restrict__ Jout, double tol, int max_inner) {
+              double2* __restrict__ Jout, int* __restrict__ rotated, double tol, int max_inner) {
   __shared__ double2 S[JP][JP + 1];
   __shared__ double2 J[JP][JP + 1];
   __shared__ Rot rot[JB];
-  __shared__ double red[4][2];
-  __shared__ int done;
+  __shared__ double red[JT / 64][2];
+  __shared__ int done, any_rot;
   const int2 pq = pairs[blockIdx.x];
   const int tid = threadIdx.x;
   for (int e = tid; e < JP * JP; e += blockDim.x) {
@@ -258,6 +263,7 @@ k_jacobi_pair(const double2* __restrict__ A, int mp, const int2* __restrict__ pa
     S[i][j] = A[size_t(gi) * mp + gj];
     J[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
+  if (tid == 0) any_rot = 0;
   __syncthreads();
   for (int sweep = 0; sweep < max_inner; ++sweep) {
     // convergence test on the sub-matrix
@@ -275,11 +281,12 @@ k_jacobi_pair(const double2* __restrict__ A, int mp, const int2* __restrict__ pa
     __syncthreads();
     if (tid == 0) {
       double o = 0.0, d = 0.0;
-      for (int w = 0; w < 4; ++w) { o += red[w][0]; d += red[w][1]; }
+      for (int w = 0; w < JT / 64; ++w) { o += red[w][0]; d += red[w][1]; }
       done = (o <= tol * tol * d) || (o < 1e-300);
     }
     __syncthreads();
     if (done) break;
+    if (tid == 0) any_rot = 1;
     for (int r = 0; r < JP - 1; ++r) {
       if (tid < JB) {
         int p, q;
@@ -325,17 +332,26 @@ k_jacobi_pair(const double2* __restrict__ A, int mp, const int2* __restrict__ pa
       __syncthreads();
     }
   }
+  __syncthreads();
+  if (tid == 0) rotated[blockIdx.x] = any_rot;
+  if (!any_rot) return;   // J = identity: the apply kernels skip this pair
   double2* out = Jout + size_t(blockIdx.x) * JP * JP;
   for (int e = tid; e < JP * JP; e += blockDim.x) out[e] = J[e / JP][e % JP];
 }
 
-// A[{Pu,Qu}][{Pv,Qv}] <- J_u^H A[..][..] J_v for all pair pairs (u, v).
+// A[{Pu,Qu}][{Pv,Qv}] <- J_u^H A[..][..] J_v for the pair pairs u >= v (block
+// number -> (u, v)); the mirrored block (v, u) gets the conjugate transpose,
+// since A stays Hermitian.  Pairs whose J is the identity are skipped.
 __global__ void __launch_bounds__(256)
 k_jacobi_apply_a(double2* __restrict__ A, int mp, const int2* __restrict__ pairs,
-                 const double2* __restrict__ Jall) {
+                 const double2* __restrict__ Jall, const int* __restrict__ rotated) {
   __shared__ double2 X[JP][JP + 1];
   __shared__ double2 M[JP][JP + 1];
-  const int u = blockIdx.y, v = blockIdx.x;
+  int b = blockIdx.x, u = 0;
+  while ((u + 1) * (u + 2) / 2 <= b) ++u;
+  const int v = b - u * (u + 1) / 2;
+  const int ru = rotated[u], rv = rotated[v];
+  if (!ru && !rv) return;
   const int2 pu = pairs[u], pv = pairs[v];
   const int tid = threadIdx.x;
   auto gidx = [&](int2 p, int l) { return l < JB ? p.x * JB + l : p.y * JB + l - JB; };
@@ -344,38 +360,52 @@ k_jacobi_apply_a(double2* __restrict__ A, int mp, const int2* __restrict__ pairs
   for (int e = tid; e < JP * JP; e += blockDim.x) {
     int i = e / JP, j = e % JP;
     X[i][j] = A[size_t(gidx(pu, i)) * mp + gidx(pv, j)];
-    M[i][j] = Jv[e];
+    if (rv) M[i][j] = Jv[e];
   }
   __syncthreads();
   double2 y[16];
-  for (int q = 0; q < 16; ++q) {        // Y = X Jv
-    int e = tid + q * 256, i = e / JP, j = e % JP;
-    double2 s = make_double2(0, 0);
-    for (int l = 0; l < JP; ++l) s = cadd(s, cmul(X[i][l], M[l][j]));
-    y[q] = s;
+  if (rv) {
+    for (int q = 0; q < 16; ++q) {        // Y = X Jv
+      int e = tid + q * 256, i = e / JP, j = e % JP;
+      double2 s = make_double2(0, 0);
+      for (int l = 0; l < JP; ++l) s = cadd(s, cmul(X[i][l], M[l][j]));
+      y[q] = s;
+    }
+  } else {
+    for (int q = 0; q < 16; ++q) {
+      int e = tid + q * 256;
+      y[q] = X[e / JP][e % JP];
+    }
   }
   __syncthreads();
   for (int q = 0; q < 16; ++q) {
     int e = tid + q * 256;
     X[e / JP][e % JP] = y[q];
-    M[e / JP][e % JP] = Ju[e];
+    if (ru) M[e / JP][e % JP] = Ju[e];
   }
   __syncthreads();
   for (int q = 0; q < 16; ++q) {        // T = Ju^H Y
     int e = tid + q * 256, i = e / JP, j = e % JP;
-    double2 s = make_double2(0, 0);
-    for (int l = 0; l < JP; ++l) s = cadd(s, cconjmul(M[l][i], X[l][j]));
+    double2 s;
+    if (ru) {
+      s = make_double2(0, 0);
+      for (int l = 0; l < JP; ++l) s = cadd(s, cconjmul(M[l][i], X[l][j]));
+    } else {
+      s = X[i][j];
+    }
     A[size_t(gidx(pu, i)) * mp + gidx(pv, j)] = s;
+    if (u != v) A[size_t(gidx(pv, j)) * mp + gidx(pu, i)] = make_double2(s.x, -s.y);
   }
 }
 
 // V[rows][{P,Q}] <- V[rows][{P,Q}] J for a 64-row block and one pair.
 __global__ void __launch_bounds__(256)
 k_jacobi_apply_v(double2* __restrict__ V, int mp, const int2* __restrict__ pairs,
-                 const double2* __restrict__ Jall) {
+                 const double2* __restrict__ Jall, const int* __restrict__ rotated) {
   __shared__ double2 X[JP][JP + 1];
   __shared__ double2 M[JP][JP + 1];
   const int v = blockIdx.y, r0 = blockIdx.x * JP;
+  if (!rotated[v]) return;
   const int2 pv = pairs[v];
   const int tid = threadIdx.x;
   auto gcol = [&](int l) { return l < JB ? pv.x * JB + l : pv.y * JB + l - JB; };
@@ -517,6 +547,7 @@ size_t jacobi_scratch_bytes(int m) {
   b += 2 * size_t(mp) * mp * sizeof(double2);                 // Ap, V
   b += size_t(nb / 2) * JP * JP * sizeof(double2);            // J
   b += size_t(nb) * nb * sizeof(int2);                        // round-robin table
+  b += size_t(nb) * sizeof(int) + 256;                        // rotated flags
   b += 4096 * sizeof(double);                                 // norm partials
   return b + 1024;
 }
@@ -532,6 +563,7 @@ int jacobi_eigh(void* Av, int m, double* w, void* Zv, void* work, double tol, in
   auto V = (double2*)wp; wp += size_t(mp) * mp * sizeof(double2);
   auto Jall = (double2*)wp; wp += size_t(np) * JP * JP * sizeof(double2);
   auto pairs = (int2*)wp; wp += size_t(nb) * nb * sizeof(int2);
+  auto rotated = (int*)wp; wp += size_t(nb) * sizeof(int) + 256;
   auto norms = (double*)wp;
   // round-robin schedule of the block pairs, all rounds
   std::vector<int2> sched(size_t(nb - 1) * np);
@@ -558,12 +590,12 @@ int jacobi_eigh(void* Av, int m, double* w, void* Zv, void* work, double tol, in
     if (host_norm[0] <= tol * tol * host_norm[1] || host_norm[0] < 1e-300) break;
     for (int r = 0; r < nb - 1; ++r) {
       const int2* pr = pairs + size_t(r) * np;
-      hipLaunchKernelGGL(k_jacobi_pair, dim3(np), dim3(256), 0, st, (const double2*)Ap, mp, pr,
-                         Jall, tol * 0.1, 12);
-      hipLaunchKernelGGL(k_jacobi_apply_a, dim3(np, np), dim3(256), 0, st, Ap, mp, pr,
-                         (const double2*)Jall);
+      hipLaunchKernelGGL(k_jacobi_pair, dim3(np), dim3(JT), 0, st, (const double2*)Ap, mp, pr,
+                         Jall, rotated, tol * 1e-2, JACOBI_INNER);
+      hipLaunchKernelGGL(k_jacobi_apply_a, dim3(np * (np + 1) / 2), dim3(256), 0, st, Ap, mp, pr,
+                         (const double2*)Jall, (const int*)rotated);
       hipLaunchKernelGGL(k_jacobi_apply_v, dim3(mp / JP, np), dim3(256), 0, st, V, mp, pr,
-                         (const double2*)Jall);
+                         (const double2*)Jall, (const int*)rotated);
     }
   }
   hipLaunchKernelGGL(k_jacobi_sort, dim3(m), dim3(256), 0, st, (const double2*)Ap,
