@@ -2,7 +2,9 @@
 """Damped-gradient iterations per second of the 48^3 x 2000-nucleon pasta box.
 
 One step = one full static iteration (Fig. 1 steps 2-5 of the paper) for
-both species: h psi, damped gradient step, h phi, overlap and subspace
+both species, in the mixed-precision form by default (complex64 states, FP32
+FFTs and h psi, split-BF16 MFMA GEMMs, FP64 subspace solve), with the FP64
+form timed on the same box for comparison: h psi, damped gradient step, h phi, overlap and subspace
 Hamiltonian GEMMs, Cholesky + Jacobi Rayleigh-Ritz, recombination GEMM,
 densities, mean field, Coulomb and energy.  Inputs are synthetic (seeded
 rod-perturbed plane waves, SLy4) and already resident in HBM when the timed
@@ -26,7 +28,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix and vector)
+PEAK_BF16_TFLOPS = 2500.0    # MI355X dense BF16 matrix
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
+SPLIT_PRODUCTS = 6           # BF16 products per real product in the mixed GEMMs
 
 
 def log(msg: str) -> None:
@@ -40,31 +44,35 @@ def gemm_flops(m: int, v: int) -> dict:
                 combine_gemm=8.0 * m * m * v)
 
 
-def roofline(timing: dict, w) -> dict:
+def roofline(timing: dict, w, mixed: bool) -> dict:
     """Roofline of the costlier of the two single-kernel GEMM phases (the
-    I/H overlap GEMM or the recombination GEMM), neutron launches."""
+    I/H overlap GEMM or the recombination GEMM), neutron launches.  FP64:
+    8 flops per complex MAC against the FP64 peak; mixed: the BF16 flops the
+    split algorithm issues (6 split products x 8 per complex MAC) against the
+    BF16 peak."""
     v = 2 * w.n ** 3
     m = w.n_neutrons
     dom = max(("overlap_gemm", "combine_gemm"),
               key=lambda k: timing[k]["ms_n"] + timing[k]["ms_p"])
     t = timing[dom]
     avg_ms = t["ms_n"] / max(1, t["launches_n"])
-    fl = gemm_flops(m, v)[dom]
+    fl = gemm_flops(m, v)[dom] * (SPLIT_PRODUCTS if mixed else 1)
+    peak = PEAK_BF16_TFLOPS if mixed else PEAK_FP64_TFLOPS
     ach = fl / (avg_ms * 1e-3) / 1e12
-    return dict(kernel=("k_overlap_lower" if dom == "overlap_gemm" else "k_combine"),
-                bound="mfma", achieved=ach, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                frac=ach / PEAK_FP64_TFLOPS, traffic=None,
+    name = ("k_overlap_lower" if dom == "overlap_gemm" else "k_combine") + ("_mixed" if mixed else "")
+    return dict(kernel=name, bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s",
+                frac=ach / peak, traffic=None, dtype=("bf16x3-split" if mixed else "fp64"),
                 per_launch=dict(species="neutrons", m=m, k=v, flops=fl, avg_ms=avg_ms))
 
 
-def h_phase_hbm(timing: dict, w) -> dict:
+def h_phase_hbm(timing: dict, w, mixed: bool) -> dict:
     """Algorithmic HBM rate of one h*psi application (read psi, write h psi),
     neutron launches (three line-pass kernels per application)."""
     v = 2 * w.n ** 3
     m = w.n_neutrons
     t = timing["apply_h"]
     avg_ms = t["ms_n"] / max(1, t["launches_n"])
-    nbytes = 2.0 * m * v * 16
+    nbytes = 2.0 * m * v * (8 if mixed else 16)
     ach = nbytes / (avg_ms * 1e-3) / 1e9
     return dict(phase="apply_h (k_h_pass x3)", bound="hbm", achieved=ach, peak=PEAK_HBM_GBS,
                 unit="GB/s", frac=ach / PEAK_HBM_GBS, bytes_per_launch=nbytes, avg_ms=avg_ms)
@@ -145,6 +153,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rod48")
+    ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
+    ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -168,43 +178,61 @@ def main() -> int:
     dn = torch.from_numpy(raw_n).to(dev)
     dp = torch.from_numpy(raw_p).to(dev)
     del raw_n, raw_p
-    log(f"inputs on device in {time.perf_counter() - t0:.1f} s; building context")
-    box = sky.Box(sky.desc_from_workload(w), device=dev)
-    t0 = time.perf_counter()
-    box.init_box(dn, dp)
-    torch.cuda.synchronize()
-    del dn, dp
-    log(f"init (Loewdin, densities, mean field) {time.perf_counter() - t0:.1f} s")
-    for i in range(args.warmup):
-        rep = box.iterate(1)
-        log(f"warmup {i + 1}/{args.warmup}: residual {rep['residual']:.4e} E {rep['energy']:.6f}")
-    box.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reps = []
-    for i in range(args.steps):
-        reps.append(box.iterate(1))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    timing = box.timing()
-    box.set_timing(False)
-    log(f"timed {args.steps} steps in {elapsed:.3f} s; last residual "
-        f"{reps[-1]['residual']:.4e} E/A {reps[-1]['energy_per_a']:.6f}")
+    log(f"inputs on device in {time.perf_counter() - t0:.1f} s")
+
+    def run(precision: int):
+        box = sky.Box(sky.desc_from_workload(w, precision=precision), device=dev)
+        t0 = time.perf_counter()
+        box.init_box(dn, dp)
+        torch.cuda.synchronize()
+        tag = "mixed" if precision else "fp64"
+        log(f"[{tag}] init (Loewdin, densities, mean field) {time.perf_counter() - t0:.1f} s")
+        for i in range(args.warmup):
+            rep = box.iterate(1)
+            log(f"[{tag}] warmup {i + 1}/{args.warmup}: residual {rep['residual']:.4e} "
+                f"E {rep['energy']:.6f}")
+        box.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = [box.iterate(1) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        timing = box.timing()
+        box.set_timing(False)
+        box.close()
+        del box
+        torch.cuda.empty_cache()
+        log(f"[{tag}] timed {args.steps} steps in {elapsed:.3f} s; last residual "
+            f"{reps[-1]['residual']:.4e} E/A {reps[-1]['energy_per_a']:.6f}")
+        return elapsed, timing, reps
+
+    mixed = args.precision == "mixed"
+    elapsed, timing, reps = run(sky.SKY_MIXED if mixed else sky.SKY_FP64)
     phases = {k: round((v["ms_n"] + v["ms_p"]) / args.steps, 3) for k, v in timing.items()}
     out = dict(
         metric="damped-gradient iterations/s, 48^3 box, 2000 nucleons",
         value=args.steps / elapsed, unit="iter/s", n_gpus=1, steps=args.steps,
         warmup=args.warmup, ms_per_step=1e3 * elapsed / args.steps, higher_is_better=True,
-        scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+        scaling="weak", vs_baseline=None,
+        dtype=("mixed: c64 states, f32 FFT/h*psi, bf16x3-split MFMA GEMMs with f32->f64 "
+               "accumulation, f64 subspace solve and sums") if mixed else "f64",
+        data="synthetic",
         config=dict(workload=(f"{w.name}: {w.n}^3 grid, dx {w.dx} fm, {w.n_neutrons} n + "
-                              f"{w.n_protons} p, rod-perturbed plane waves, SLy4, "
-                              f"complex128 states, FP64 throughout"),
-                    grid=w.n, nucleons=w.n_states, precision="fp64"),
-        roofline=roofline(timing, w),
-        h_phase_hbm=h_phase_hbm(timing, w),
+                              f"{w.n_protons} p, rod-perturbed plane waves, SLy4"),
+                    grid=w.n, nucleons=w.n_states, precision=args.precision),
+        roofline=roofline(timing, w, mixed),
+        h_phase_hbm=h_phase_hbm(timing, w, mixed),
         phases_ms_per_iter=phases,
         residual=reps[-1]["residual"], energy_per_a=reps[-1]["energy_per_a"],
     )
+    if mixed and not args.no_fp64_compare:
+        e64, t64, r64 = run(sky.SKY_FP64)
+        out["fp64_form"] = dict(value=args.steps / e64, ms_per_step=1e3 * e64 / args.steps,
+                                speedup_mixed=(args.steps / elapsed) / (args.steps / e64),
+                                phases_ms_per_iter={k: round((v["ms_n"] + v["ms_p"]) / args.steps, 3)
+                                                    for k, v in t64.items()},
+                                energy_per_a=r64[-1]["energy_per_a"])
+    del dn, dp
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w)

@@ -11,8 +11,16 @@
  *
  * Conventions shared by every entry point
  * ---------------------------------------
- * - Precision: all state and field data are IEEE binary64; states are
- *   complex128 (interleaved re, im).
+ * - Precision (sky_box_desc.precision): SKY_FP64 keeps every state in
+ *   complex128 and every operation in binary64.  SKY_MIXED keeps the states
+ *   in complex64, runs FFTs and h*psi in binary32, forms the overlap,
+ *   subspace-Hamiltonian and recombination products from a three-way BF16
+ *   split on the matrix cores with FP32 accumulation folded into FP64, and
+ *   keeps the Cholesky, eigensolver, densities, mean field and energy sums
+ *   in binary64.  Reductions (<h>, residuals, densities) are binary64 in both
+ *   modes.  State pointers passed to the per-step calls must have the
+ *   context's current precision (sky_get_precision): complex128 or complex64.
+ *   Fields and subspace matrices are always binary64 / complex128.
  * - State layout: [state][spin][z][y][x], x fastest, spin 0 = up.  One state
  *   of species q holds V = 2*n^3 complex values.  Field layout: [z][y][x].
  * - Grid: cubic, n points per axis, n in {8, 16, 24, 32, 48, 64}, spacing dx
@@ -54,6 +62,7 @@ enum {
 };
 
 enum { SKY_NEUTRON = 0, SKY_PROTON = 1 };
+enum { SKY_FP64 = 0, SKY_MIXED = 1 };
 
 /* Box, force and damping of one solve.  Skyrme parameters in the usual
  * units: t0 MeV fm^3, t1 t2 MeV fm^5, t3 MeV fm^(3+3 alpha), W0 MeV fm^5,
@@ -67,6 +76,9 @@ typedef struct {
   double t0, t1, t2, t3, x0, x1, x2, x3, alpha, W0;
   double hb2m_n, hb2m_p, e2;
   double damp_x0, damp_e0;
+  int32_t precision;                /* SKY_FP64 or SKY_MIXED                    */
+  double ladder_tol;                /* SKY_MIXED: switch to FP64 once Delta-eps */
+                                    /* <= ladder_tol (MeV); <= 0 never          */
 } sky_box_desc;
 
 typedef struct {
@@ -76,11 +88,13 @@ typedef struct {
   double energy;          /* total energy after the last iteration, MeV         */
   double energy_per_a;    /* energy / (N + Z)                                   */
   int32_t jacobi_sweeps;  /* eigensolver sweeps of the last iteration (n + p)   */
+  int32_t precision;      /* precision of the states after the call             */
 } sky_report;
 
 /* Views into the context's device buffers (sky_get_view). */
 enum {
-  SKY_VIEW_PSI = 0,       /* orthonormal states of species q, [n_q][2][n^3] c128 */
+  SKY_VIEW_PSI = 0,       /* orthonormal states of species q, [n_q][2][n^3]      */
+                          /* (complex128, or complex64 in mixed precision)      */
   SKY_VIEW_HPSI = 1,      /* h psi of the last iteration                         */
   SKY_VIEW_PHI = 2,       /* damped (non-orthonormal) states                     */
   SKY_VIEW_HPHI = 3,      /* h phi                                              */
@@ -126,9 +140,11 @@ int sky_create(const sky_box_desc* d, void* workspace_dev, size_t bytes, void* s
 
 /* Fig. 1 step 1 (Sec. 2.2: trial plane waves for periodic systems): take
  * caller trial states raw_n_dev [n_neutrons][2][n^3] and raw_p_dev
- * [n_protons][2][n^3] (complex128, need not be orthonormal; read only),
- * orthonormalise them by Loewdin's C = I^(-1/2) (Eqs. Loewedin, orthmatvec),
- * then build densities, mean field and energy.  Waits for the stream.
+ * [n_protons][2][n^3] (complex128 in both precisions, need not be
+ * orthonormal; read only), orthonormalise them in binary64 by Loewdin's
+ * C = I^(-1/2) (Eqs. Loewedin, orthmatvec), round them to complex64 under
+ * SKY_MIXED, then build densities, mean field and energy.  Waits for the
+ * stream.
  * Errors: INVALID, NOT_POSITIVE_DEFINITE (linearly dependent states), HIP. */
 int sky_init_box(sky_ctx* c, const void* raw_n_dev, const void* raw_p_dev);
 
@@ -167,7 +183,9 @@ int sky_orthonormalize(sky_ctx* c, int32_t q, const void* phi_dev, const void* h
 int sky_densities(sky_ctx* c);
 
 /* Run up to max_iter damped-gradient iterations (Fig. 1 steps 2-5) on the
- * context's states.  tol_mev > 0: stop once Delta-eps <= tol_mev (returns
+ * context's states.  Under SKY_MIXED with ladder_tol > 0 the context switches
+ * itself to binary64 states after the first iteration whose Delta-eps is
+ * <= ladder_tol and continues in FP64 (the precision ladder).  tol_mev > 0: stop once Delta-eps <= tol_mev (returns
  * SKY_OK), else SKY_NOT_CONVERGED after max_iter; tol_mev <= 0: run exactly
  * max_iter iterations.  report (host, may be NULL) is filled.  Waits for the
  * stream.  Errors: NAN, NOT_POSITIVE_DEFINITE, HIP. */
@@ -188,6 +206,9 @@ int sky_set_timing(sky_ctx* c, int32_t enable);
  * (host arrays of 2*SKY_NPHASE; launches may be NULL; phases that are not
  * per species use q = 0).  Waits for the stream. */
 int sky_get_timing(sky_ctx* c, double* ms, int64_t* launches);
+
+/* Current precision of the context's states (SKY_FP64 or SKY_MIXED). */
+int sky_get_precision(sky_ctx* c, int32_t* precision);
 
 /* Wait for all work of the context's stream. */
 int sky_sync(sky_ctx* c);

@@ -23,7 +23,8 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-Wno-unused-result"]
 
-SOURCES = ["k_grid.hip", "k_fields.hip", "k_gemm.hip", "k_linalg.hip", "sky_api.cpp"]
+SOURCES = ["k_grid.hip", "k_fields.hip", "k_gemm.hip", "k_gemm_mixed.hip", "k_linalg.hip",
+           "sky_api.cpp"]
 
 
 def _compile(src: str) -> str:

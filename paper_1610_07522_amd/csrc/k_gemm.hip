@@ -5,79 +5,19 @@
 // lower triangle only (Fig. 3).  Sec. 3.3.3: the orthonormalised, diagonal
 // states are built with one product psi = phi (C Z) (step 3e).
 //
-// One workgroup (4 waves, 2x2) owns a 64x64 complex output tile; each wave a
-// 32x32 tile = 2x2 MFMA blocks, with separate real/imaginary accumulators.
-// Operand tiles of KC complex values along the contraction are staged in LDS
-// as [row][k] for A (M x K) and [col][k] for B (N x K).
+// Tiles, operand staging and the three-product complex scheme are in
+// mfma_f64.h.
+#include "mfma_f64.h"
 #include "sky_kernels.h"
 
 namespace sky {
 
 namespace {
-typedef double d4 __attribute__((ext_vector_type(4)));
-constexpr int TM = 64;      // tile rows / cols
-constexpr int KC = 16;      // contraction chunk (complex)
-constexpr int KP = KC + 1;  // padded LDS row
-constexpr int GT = 256;     // threads
-
-struct Acc {
-  d4 re[2][2], im[2][2];
-};
-
-__device__ inline void acc_zero(Acc& a) {
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      a.re[i][j] = d4{0, 0, 0, 0};
-      a.im[i][j] = d4{0, 0, 0, 0};
-    }
-}
-
-// acc += op(A tile) * B tile^T over KC, where A is conjugated if CONJA.
-// sA[row][k], sB[col][k] (complex as double2).
-template <bool CONJA>
-__device__ inline void mfma_tile(Acc& acc, const double2* sA, const double2* sB, int wm, int wn,
-                                 int lane) {
-  const int r = lane & 15, kq = lane >> 4;
-#pragma unroll
-  for (int kk = 0; kk < KC; kk += 4) {
-    double2 a[2], b[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) a[i] = sA[(wm * 32 + i * 16 + r) * KP + kk + kq];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) b[j] = sB[(wn * 32 + j * 16 + r) * KP + kk + kq];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const double ai = CONJA ? -a[i].y : a[i].y;
-        // (ar + i ai)(br + i bi) = ar br - ai bi + i (ar bi + ai br)
-        acc.re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, acc.re[i][j], 0, 0, 0);
-        acc.re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, b[j].y, acc.re[i][j], 0, 0, 0);
-        acc.im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].y, acc.im[i][j], 0, 0, 0);
-        acc.im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b[j].x, acc.im[i][j], 0, 0, 0);
-      }
-  }
-}
-
-// Element (row, col) within the 64x64 tile held by this lane for block
-// (i, j), register e.  The FP64 16x16x4 MFMA of gfx950 returns output row
-// 4*e + lane/16, column lane%16 in register e of each lane (measured):
-// row = wm*32 + i*16 + 4*e + lane/16, col = wn*32 + j*16 + lane%16.
-template <typename F>
-__device__ inline void acc_foreach(const Acc& acc, int wm, int wn, int lane, F f) {
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int row = wm * 32 + i * 16 + 4 * e + (lane >> 4);
-        int col = wn * 32 + j * 16 + (lane & 15);
-        f(row, col, acc.re[i][j][e], acc.im[i][j][e]);
-      }
-}
+using mfma::Acc;
+using mfma::GT;
+using mfma::KC;
+using mfma::KP;
+using mfma::TM;
 
 // Lower-triangle tile pair number p -> (ta, tb), ta >= tb.
 __device__ inline void tri_pair(int p, int& ta, int& tb) {
@@ -108,7 +48,7 @@ k_overlap_lower(const double2* __restrict__ A, const double2* __restrict__ B0,
   const int lrow = tid >> 2, lk = (tid & 3) * 4;
   const int ga = ta * TM + lrow, gb = tb * TM + lrow;
   Acc acc;
-  acc_zero(acc);
+  mfma::zero(acc);
   for (long c = c0; c < c1; ++c) {
     const long k0 = c * KC + lk;
 #pragma unroll
@@ -117,11 +57,11 @@ k_overlap_lower(const double2* __restrict__ A, const double2* __restrict__ B0,
       sB[lrow * KP + lk + e] = gb < m ? B[size_t(gb) * k + k0 + e] : make_double2(0, 0);
     }
     __syncthreads();
-    mfma_tile<true>(acc, sA, sB, wm, wn, lane);
+    mfma::tile<true>(acc, sA, sB, wm, wn, lane);
     __syncthreads();
   }
   double2* out = part + (size_t(z) * npair + pair) * split * TM * TM + size_t(s) * TM * TM;
-  acc_foreach(acc, wm, wn, lane, [&](int row, int col, double re, double im) {
+  mfma::foreach(acc, wm, wn, lane, [&](int row, int col, double re, double im) {
     out[row * TM + col] = make_double2(re, im);
   });
 }
@@ -172,7 +112,7 @@ k_combine(const double2* __restrict__ X, const double2* __restrict__ U, double2*
   // loader: thread -> (a within chunk = tid/16, 4 consecutive columns)
   const int la = tid >> 4, lc = (tid & 15) * 4;
   Acc acc;
-  acc_zero(acc);
+  mfma::zero(acc);
   for (int a0 = 0; a0 < m; a0 += KC) {
     const int a = a0 + la;
 #pragma unroll
@@ -182,10 +122,10 @@ k_combine(const double2* __restrict__ X, const double2* __restrict__ U, double2*
       sB[(lc + e) * KP + la] = (a < m) ? X[size_t(a) * k + v0 + lc + e] : make_double2(0, 0);
     }
     __syncthreads();
-    mfma_tile<false>(acc, sA, sB, wm, wn, lane);
+    mfma::tile<false>(acc, sA, sB, wm, wn, lane);
     __syncthreads();
   }
-  acc_foreach(acc, wm, wn, lane, [&](int row, int col, double re, double im) {
+  mfma::foreach(acc, wm, wn, lane, [&](int row, int col, double re, double im) {
     const int b = b0 + row;
     if (b < m) Y[size_t(b) * k + v0 + col] = make_double2(re, im);
   });
@@ -203,7 +143,7 @@ k_gemm_square(const double2* __restrict__ A, const double2* __restrict__ B,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   Acc acc;
-  acc_zero(acc);
+  mfma::zero(acc);
   for (int k0 = 0; k0 < m; k0 += KC) {
     for (int e = tid; e < TM * KC; e += GT) {
       // element (row or col index t, contraction index kk)
@@ -231,10 +171,10 @@ k_gemm_square(const double2* __restrict__ A, const double2* __restrict__ B,
       }
     }
     __syncthreads();
-    mfma_tile<false>(acc, sA, sB, wm, wn, lane);
+    mfma::tile<false>(acc, sA, sB, wm, wn, lane);
     __syncthreads();
   }
-  acc_foreach(acc, wm, wn, lane, [&](int row, int col, double re, double im) {
+  mfma::foreach(acc, wm, wn, lane, [&](int row, int col, double re, double im) {
     const int r = r0 + row, c = c0 + col;
     if (r < m && c < m) C[size_t(r) * m + c] = make_double2(re, im);
   });
@@ -270,6 +210,11 @@ void overlap_lower(const void* A, const void* B0, const void* B1, int m, long k,
                      (const double2*)A, (const double2*)B0, (const double2*)B1, m, k, split,
                      (double2*)part);
   if (ev) hipEventRecord(ev[1], st);
+  overlap_reduce(part, npair, split, m, scale, C0, C1, nz, st);
+}
+
+void overlap_reduce(const void* part, int npair, int split, int m, double scale, void* C0,
+                    void* C1, int nz, hipStream_t st) {
   hipLaunchKernelGGL(k_overlap_reduce, dim3(npair, nz), dim3(256), 0, st, (const double2*)part,
                      npair, split, m, scale, (double2*)C0, (double2*)C1);
 }

@@ -436,6 +436,28 @@ __global__ void k_dens_reduce(const double* __restrict__ part, int nchunk, int n
   o[10 * n3 + r] = q[13];                     // j_z
 }
 
+// ------------------------------------------------------------------ conversion
+__global__ void k_c128_to_c64(const double2* __restrict__ a, float2* __restrict__ b, size_t n) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = make_float2(float(a[i].x), float(a[i].y));
+}
+__global__ void k_c64_to_c128(const float2* __restrict__ a, double2* __restrict__ b, size_t n) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = make_double2(double(a[i].x), double(a[i].y));
+}
+
+void convert_states(const void* src, int src_prec, void* dst, int dst_prec, size_t n,
+                    hipStream_t st) {
+  if (n == 0) return;
+  const unsigned nb = unsigned((n + 255) / 256);
+  if (src_prec == 0 && dst_prec == 1)
+    hipLaunchKernelGGL(k_c128_to_c64, dim3(nb), dim3(256), 0, st, (const double2*)src, (float2*)dst, n);
+  else if (src_prec == 1 && dst_prec == 0)
+    hipLaunchKernelGGL(k_c64_to_c128, dim3(nb), dim3(256), 0, st, (const float2*)src, (double2*)dst, n);
+  else
+    hipMemcpyAsync(dst, src, n * (src_prec == 0 ? 16 : 8), hipMemcpyDeviceToDevice, st);
+}
+
 // ------------------------------------------------------------------ launchers
 template <int N> static int ntiles() { return N * N / LineCfg<N>::LPW; }
 
@@ -456,10 +478,11 @@ int grid_ntiles(int n) {
   return r;
 }
 
-void apply_h(int n, const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf, GridArgs g,
-             double* eps_part, double* eps, hipStream_t st) {
+void apply_h(int n, int prec, const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf,
+             GridArgs g, double* eps_part, double* eps, hipStream_t st) {
   if (nstate <= 0) return;
-  SKY_DISPATCH_N(n, launch_apply_h<double, NN>(psi, hpsi, nstate, mf, g, eps_part, st));
+  if (prec == 0) SKY_DISPATCH_N(n, launch_apply_h<double, NN>(psi, hpsi, nstate, mf, g, eps_part, st))
+  else SKY_DISPATCH_N(n, launch_apply_h<float, NN>(psi, hpsi, nstate, mf, g, eps_part, st))
   if (eps_part && eps) {
     int nt = grid_ntiles(n);
     hipLaunchKernelGGL(k_sum_partials, dim3((nstate + 127) / 128), dim3(128), 0, st,
@@ -481,12 +504,13 @@ static void launch_damp(const void* psi, const void* hpsi, const double* eps, vo
   hipLaunchKernelGGL((k_damp_inv_x<T, N>), grid, block, 0, st, p, o);
 }
 
-void damped_step(int n, const void* psi, const void* hpsi, const double* eps, void* phi,
-                 int nstate, GridArgs g, double x0, double e0, double hb2m, double* r2_part,
-                 double* r2, hipStream_t st) {
+void damped_step(int n, int prec, const void* psi, const void* hpsi, const double* eps,
+                 void* phi, int nstate, GridArgs g, double x0, double e0, double hb2m,
+                 double* r2_part, double* r2, hipStream_t st) {
   if (nstate <= 0) return;
   DampArgs d{x0, e0, hb2m};
-  SKY_DISPATCH_N(n, launch_damp<double, NN>(psi, hpsi, eps, phi, nstate, g, d, r2_part, st));
+  if (prec == 0) SKY_DISPATCH_N(n, launch_damp<double, NN>(psi, hpsi, eps, phi, nstate, g, d, r2_part, st))
+  else SKY_DISPATCH_N(n, launch_damp<float, NN>(psi, hpsi, eps, phi, nstate, g, d, r2_part, st))
   int nt = grid_ntiles(n);
   hipLaunchKernelGGL(k_sum_partials, dim3((nstate + 127) / 128), dim3(128), 0, st,
                      (const double*)r2_part, nt, nstate, r2);
@@ -502,8 +526,8 @@ static void launch_dens(const void* psi, int nstate, int chunk, int nchunk, Grid
   hipLaunchKernelGGL((k_dens_pass<T, N, 2>), grid, block, 0, st, p, nstate, chunk, g, part);
 }
 
-void densities(int n, const void* psi, int nstate, int nchunk_max, GridArgs g, double* part,
-               double* dens, hipStream_t st) {
+void densities(int n, int prec, const void* psi, int nstate, int nchunk_max, GridArgs g,
+               double* part, double* dens, hipStream_t st) {
   const int n3 = n * n * n;
   if (nstate <= 0) {
     zero(dens, size_t(11) * n3, st);
@@ -511,7 +535,8 @@ void densities(int n, const void* psi, int nstate, int nchunk_max, GridArgs g, d
   }
   int chunk = (nstate + nchunk_max - 1) / nchunk_max;
   int nchunk = (nstate + chunk - 1) / chunk;
-  SKY_DISPATCH_N(n, launch_dens<double, NN>(psi, nstate, chunk, nchunk, g, part, st));
+  if (prec == 0) SKY_DISPATCH_N(n, launch_dens<double, NN>(psi, nstate, chunk, nchunk, g, part, st))
+  else SKY_DISPATCH_N(n, launch_dens<float, NN>(psi, nstate, chunk, nchunk, g, part, st))
   hipLaunchKernelGGL(k_dens_reduce, dim3((n3 + 255) / 256), dim3(256), 0, st,
                      (const double*)part, nchunk, n3, dens);
 }

@@ -12,14 +12,17 @@
 #include <vector>
 #include <algorithm>
 
+#include "mfma_f64.h"
 #include "sky_kernels.h"
 
 namespace sky {
 
 namespace {
 constexpr int CB = 64;    // Cholesky block
-constexpr int JB = 32;    // Jacobi block (pair sub-problem = 2*JB)
+constexpr int JB = 16;    // Jacobi block (pair sub-problem = 2*JB)
 constexpr int JP = 2 * JB;
+constexpr int JE = JP * JP / 256;   // pair-matrix elements per thread (256 threads)
+constexpr int RV = 64;              // rows of V per workgroup in the V update
 // Cyclic sweeps per pair sub-problem and round.  The pair tolerance is 100x
 // tighter than the global one so that the ~(n/32)^2/2 converged pair blocks
 // together stay below the global off-diagonal bound.
@@ -148,16 +151,19 @@ k_chol_update(double2* __restrict__ A, int m, int k0) {
   }
 }
 
-// Block row ib of Linv (jb < ib):
-//   Linv[ib][jb] = -Dinv[ib] * sum_{kb=jb}^{ib-1} L[ib][kb] Linv[kb][jb]
+// Block row ib of Linv (jb < ib), on the FP64 matrix cores:
+//   Linv[ib][jb] = -Dinv[ib] * S,  S = sum_{kb=jb}^{ib-1} L[ib][kb] Linv[kb][jb]
 // one workgroup per jb; Linv[ib][ib] = Dinv[ib] is written by jb == ib.
 __global__ void __launch_bounds__(256)
 k_tri_inv_row(const double2* __restrict__ L, double2* __restrict__ Linv, int m, int ib,
               const double2* __restrict__ Dinv_all) {
-  __shared__ double2 Sa[CB][CB + 1];
-  __shared__ double2 Sb[CB][CB + 1];
+  using namespace mfma;
+  __shared__ double2 sA[TM * KP];
+  __shared__ double2 sB[TM * KP];
+  __shared__ double2 Ssh[CB][CB + 1];
   const int jb = blockIdx.x;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
   const int r0 = ib * CB;
   const double2* Di = Dinv_all + size_t(ib) * CB * CB;
   if (jb == ib) {
@@ -167,36 +173,40 @@ k_tri_inv_row(const double2* __restrict__ L, double2* __restrict__ Linv, int m, 
     }
     return;
   }
-  double2 acc[16];
-  for (int q = 0; q < 16; ++q) acc[q] = make_double2(0, 0);
+  Acc acc;
+  zero(acc);
   for (int kb = jb; kb < ib; ++kb) {
-    for (int e = tid; e < CB * CB; e += blockDim.x) {
-      int r = e / CB, c = e % CB;
-      Sa[r][c] = (r0 + r < m) ? L[size_t(r0 + r) * m + kb * CB + c] : make_double2(0, 0);
-      Sb[r][c] = (kb * CB + r < m && jb * CB + c < m) ? Linv[size_t(kb * CB + r) * m + jb * CB + c]
-                                                       : make_double2(0, 0);
+    for (int kc = 0; kc < CB; kc += KC) {
+      for (int e = tid; e < TM * KC; e += GT) {
+        const int t = e / KC, k = e % KC;
+        const int col = kb * CB + kc + k;            // < m since kb < ib
+        sA[t * KP + k] = (r0 + t < m) ? L[size_t(r0 + t) * m + col] : make_double2(0, 0);
+        sB[t * KP + k] = Linv[size_t(col) * m + jb * CB + t];
+      }
+      __syncthreads();
+      tile<false>(acc, sA, sB, wm, wn, lane);
+      __syncthreads();
     }
-    __syncthreads();
-    for (int q = 0; q < 16; ++q) {
-      int e = tid + q * 256, r = e / CB, c = e % CB;
-      double2 s = acc[q];
-      for (int l = 0; l < CB; ++l) s = cadd(s, cmul(Sa[r][l], Sb[l][c]));
-      acc[q] = s;
-    }
-    __syncthreads();
   }
-  for (int q = 0; q < 16; ++q) {
-    int e = tid + q * 256;
-    Sb[e / CB][e % CB] = acc[q];
-    Sa[e / CB][e % CB] = Di[e];
-  }
+  foreach(acc, wm, wn, lane, [&](int row, int col, double re, double im) {
+    Ssh[row][col] = make_double2(re, im);
+  });
   __syncthreads();
-  for (int q = 0; q < 16; ++q) {
-    int e = tid + q * 256, r = e / CB, c = e % CB;
-    double2 s = make_double2(0, 0);
-    for (int l = 0; l <= r; ++l) s = cadd(s, cmul(Sa[r][l], Sb[l][c]));
-    if (r0 + r < m && jb * CB + c < m) Linv[size_t(r0 + r) * m + jb * CB + c] = cscale(-1.0, s);
+  zero(acc);
+  for (int kc = 0; kc < CB; kc += KC) {
+    for (int e = tid; e < TM * KC; e += GT) {
+      const int t = e / KC, k = e % KC;
+      sA[t * KP + k] = Di[t * CB + kc + k];
+      sB[t * KP + k] = Ssh[kc + k][t];
+    }
+    __syncthreads();
+    tile<false>(acc, sA, sB, wm, wn, lane);
+    __syncthreads();
   }
+  foreach(acc, wm, wn, lane, [&](int row, int col, double re, double im) {
+    if (r0 + row < m && jb * CB + col < m)
+      Linv[size_t(r0 + row) * m + jb * CB + col] = make_double2(-re, -im);
+  });
 }
 
 __global__ void k_zero_cpx(double2* __restrict__ p, size_t n) {
@@ -245,7 +255,7 @@ __device__ inline void rr_pair(int np, int r, int i, int& p, int& q) {
 
 // Diagonalise the 64x64 pair sub-matrix of blocks (P, Q) of A (ld = mp)
 // and write its unitary J (64x64, row-major, local index l < 32 -> block P).
-constexpr int JT = 1024;   // threads of a pair sub-problem workgroup
+constexpr int JT = 256;    // threads of a pair sub-problem workgroup
 __global__ void __launch_bounds__(JT)
 k_jacobi_pair(const double2* __restrict__ A, int mp, const int2* __restrict__ pairs,
               double2* __restrict__ Jout, int* __restrict__ rotated, double tol, int max_inner) {
@@ -363,28 +373,28 @@ k_jacobi_apply_a(double2* __restrict__ A, int mp, const int2* __restrict__ pairs
     if (rv) M[i][j] = Jv[e];
   }
   __syncthreads();
-  double2 y[16];
+  double2 y[JE];
   if (rv) {
-    for (int q = 0; q < 16; ++q) {        // Y = X Jv
+    for (int q = 0; q < JE; ++q) {        // Y = X Jv
       int e = tid + q * 256, i = e / JP, j = e % JP;
       double2 s = make_double2(0, 0);
       for (int l = 0; l < JP; ++l) s = cadd(s, cmul(X[i][l], M[l][j]));
       y[q] = s;
     }
   } else {
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < JE; ++q) {
       int e = tid + q * 256;
       y[q] = X[e / JP][e % JP];
     }
   }
   __syncthreads();
-  for (int q = 0; q < 16; ++q) {
+  for (int q = 0; q < JE; ++q) {
     int e = tid + q * 256;
     X[e / JP][e % JP] = y[q];
     if (ru) M[e / JP][e % JP] = Ju[e];
   }
   __syncthreads();
-  for (int q = 0; q < 16; ++q) {        // T = Ju^H Y
+  for (int q = 0; q < JE; ++q) {        // T = Ju^H Y
     int e = tid + q * 256, i = e / JP, j = e % JP;
     double2 s;
     if (ru) {
@@ -398,26 +408,26 @@ k_jacobi_apply_a(double2* __restrict__ A, int mp, const int2* __restrict__ pairs
   }
 }
 
-// V[rows][{P,Q}] <- V[rows][{P,Q}] J for a 64-row block and one pair.
+// V[rows][{P,Q}] <- V[rows][{P,Q}] J for an RV-row block and one pair.
 __global__ void __launch_bounds__(256)
 k_jacobi_apply_v(double2* __restrict__ V, int mp, const int2* __restrict__ pairs,
                  const double2* __restrict__ Jall, const int* __restrict__ rotated) {
-  __shared__ double2 X[JP][JP + 1];
+  __shared__ double2 X[RV][JP + 1];
   __shared__ double2 M[JP][JP + 1];
-  const int v = blockIdx.y, r0 = blockIdx.x * JP;
+  const int v = blockIdx.y, r0 = blockIdx.x * RV;
   if (!rotated[v]) return;
   const int2 pv = pairs[v];
   const int tid = threadIdx.x;
   auto gcol = [&](int l) { return l < JB ? pv.x * JB + l : pv.y * JB + l - JB; };
   const double2* Jv = Jall + size_t(v) * JP * JP;
-  for (int e = tid; e < JP * JP; e += blockDim.x) {
+  for (int e = tid; e < RV * JP; e += blockDim.x) {
     int i = e / JP, j = e % JP;
     X[i][j] = (r0 + i < mp) ? V[size_t(r0 + i) * mp + gcol(j)] : make_double2(0, 0);
-    M[i][j] = Jv[e];
   }
+  for (int e = tid; e < JP * JP; e += blockDim.x) M[e / JP][e % JP] = Jv[e];
   __syncthreads();
-  for (int q = 0; q < 16; ++q) {
-    int e = tid + q * 256, i = e / JP, j = e % JP;
+  for (int e = tid; e < RV * JP; e += blockDim.x) {
+    int i = e / JP, j = e % JP;
     double2 s = make_double2(0, 0);
     for (int l = 0; l < JP; ++l) s = cadd(s, cmul(X[i][l], M[l][j]));
     if (r0 + i < mp) V[size_t(r0 + i) * mp + gcol(j)] = s;
@@ -594,7 +604,7 @@ int jacobi_eigh(void* Av, int m, double* w, void* Zv, void* work, double tol, in
                          Jall, rotated, tol * 1e-2, JACOBI_INNER);
       hipLaunchKernelGGL(k_jacobi_apply_a, dim3(np * (np + 1) / 2), dim3(256), 0, st, Ap, mp, pr,
                          (const double2*)Jall, (const int*)rotated);
-      hipLaunchKernelGGL(k_jacobi_apply_v, dim3(mp / JP, np), dim3(256), 0, st, V, mp, pr,
+      hipLaunchKernelGGL(k_jacobi_apply_v, dim3((mp + RV - 1) / RV, np), dim3(256), 0, st, V, mp, pr,
                          (const double2*)Jall, (const int*)rotated);
     }
   }

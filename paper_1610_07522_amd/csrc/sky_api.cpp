@@ -39,7 +39,8 @@ constexpr int JACOBI_SWEEPS = 30;
 
 // Byte offsets of every buffer inside the caller's workspace.
 struct Layout {
-  size_t psi[2], hpsi[2], phi[2], hphi[2];
+  size_t psi[2], hpsi[2], phi[2], hphi[2];          // complex128 states
+  size_t psi32[2], hpsi32[2], phi32[2], hphi32[2];  // complex64 states (mixed only)
   size_t eps[2], r2[2], ritz[2], tiles;
   size_t matI, matH, matC, matL, matT, matHp, matZ, matU, wtmp, gemm_part, chol_work, jac_work;
   size_t dens[2], der[2], mf[2], vc, fscratch, dens_part, epart, energy, info;
@@ -59,12 +60,18 @@ Layout plan(const sky_box_desc& d) {
     off += al(std::max<size_t>(bytes, 1));
     return o;
   };
+  const bool mixed = d.precision == SKY_MIXED;
   for (int q = 0; q < 2; ++q) {
     const size_t sb = size_t(nq[q]) * V * c16;
     L.psi[q] = take(sb);
     L.hpsi[q] = take(sb);
     L.phi[q] = take(sb);
     L.hphi[q] = take(sb);
+    const size_t sb32 = mixed ? sb / 2 : 0;
+    L.psi32[q] = take(sb32);
+    L.hpsi32[q] = take(sb32);
+    L.phi32[q] = take(sb32);
+    L.hphi32[q] = take(sb32);
     L.eps[q] = take(sizeof(double) * nq[q]);
     L.r2[q] = take(sizeof(double) * nq[q]);
     L.ritz[q] = take(sizeof(double) * nq[q]);
@@ -81,8 +88,12 @@ Layout plan(const sky_box_desc& d) {
   L.matZ = take(mm);
   L.matU = take(mm);
   L.wtmp = take(sizeof(double) * nmax);
-  L.gemm_part = take(std::max(overlap_scratch_bytes(std::max(1, nq[0]), long(V)),
-                              overlap_scratch_bytes(std::max(1, nq[1]), long(V))));
+  size_t gp = 0;
+  for (int q = 0; q < 2; ++q) {
+    gp = std::max(gp, overlap_scratch_bytes(std::max(1, nq[q]), long(V)));
+    if (mixed) gp = std::max(gp, overlap_scratch_bytes_mixed(std::max(1, nq[q]), long(V)));
+  }
+  L.gemm_part = take(gp);
   L.chol_work = take(size_t((nmax + 63) / 64 + 1) * 64 * 64 * c16);
   L.jac_work = take(jacobi_scratch_bytes(nmax));
   for (int q = 0; q < 2; ++q) {
@@ -109,6 +120,8 @@ int validate(const sky_box_desc* d) {
   const long V = 2L * d->n * d->n * d->n;
   if (d->n_neutrons > V || d->n_protons > V) return fail(SKY_ERR_INVALID, "more states than grid points");
   if (!(d->damp_e0 > 0.0)) return fail(SKY_ERR_INVALID, "damp_e0 must be positive");
+  if (d->precision != SKY_FP64 && d->precision != SKY_MIXED)
+    return fail(SKY_ERR_INVALID, "precision must be SKY_FP64 or SKY_MIXED");
   return SKY_OK;
 }
 }  // namespace
@@ -121,9 +134,12 @@ struct sky_ctx {
   int n, n3;
   long V;
   int nq[2];
+  int prec;            // current: 0 = FP64 states, 1 = mixed (complex64 states)
   GridArgs g;
   Skyrme sk;
   int last_sweeps;
+  int64_t iter_count = 0;     // iterations run on this context
+  int64_t switched_at = -1;   // iteration after which the ladder switched to FP64
   // phase timing: HIP event pairs on the context stream
   struct Mark { int phase, q; hipEvent_t a, b; };
   bool timing = false;
@@ -133,6 +149,11 @@ struct sky_ctx {
   int64_t cnt[SKY_NPHASE][2] = {};
 
   template <typename P = char> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
+  // state buffers of the current precision
+  char* psi(int q) const { return at(prec ? lay.psi32[q] : lay.psi[q]); }
+  char* hpsi(int q) const { return at(prec ? lay.hpsi32[q] : lay.hpsi[q]); }
+  char* phi(int q) const { return at(prec ? lay.phi32[q] : lay.phi[q]); }
+  char* hphi(int q) const { return at(prec ? lay.hphi32[q] : lay.hphi[q]); }
   MeanFieldPtrs mfp(int q) const {
     const double* m = at<double>(lay.mf[q]);
     return MeanFieldPtrs{m, m + n3, m + 2 * n3};
@@ -212,8 +233,12 @@ int rayleigh_ritz(sky_ctx* c, int q, const void* phi, const void* hphi, void* ps
     ev[0] = c->marks[tm].a;
     ev[1] = c->marks[tm].b;
   }
-  overlap_lower(phi, phi, hphi, m, c->V, c->g.dV, I, H, c->at(c->lay.gemm_part), st,
-                c->timing ? ev : nullptr);
+  if (c->prec)
+    overlap_lower_mixed(phi, phi, hphi, m, c->V, c->g.dV, I, H, c->at(c->lay.gemm_part), st,
+                        c->timing ? ev : nullptr);
+  else
+    overlap_lower(phi, phi, hphi, m, c->V, c->g.dV, I, H, c->at(c->lay.gemm_part), st,
+                  c->timing ? ev : nullptr);
   const int ts = t_begin(c, SKY_PHASE_SUBSPACE, q);
   hermitian_fill(I, m, st);
   hermitian_fill(H, m, st);
@@ -232,7 +257,8 @@ int rayleigh_ritz(sky_ctx* c, int q, const void* phi, const void* hphi, void* ps
   gemm_square(Linv, 1, Z, 0, U, m, st);
   t_end(c, ts);
   const int tc = t_begin(c, SKY_PHASE_COMBINE_GEMM, q);
-  combine(phi, U, psi_out, m, c->V, st);
+  if (c->prec) combine_mixed(phi, U, psi_out, m, c->V, st);
+  else combine(phi, U, psi_out, m, c->V, st);
   t_end(c, tc);
   return SKY_OK;
 }
@@ -247,7 +273,10 @@ int loewdin(sky_ctx* c, int q, const void* phi, void* psi_out) {
   double* w = c->at<double>(c->lay.ritz[q]);
   int* info = c->at<int>(c->lay.info);
   hipMemsetAsync(info, 0, sizeof(int), st);
-  overlap_lower(phi, phi, nullptr, m, c->V, c->g.dV, I, nullptr, c->at(c->lay.gemm_part), st);
+  if (c->prec)
+    overlap_lower_mixed(phi, phi, nullptr, m, c->V, c->g.dV, I, nullptr, c->at(c->lay.gemm_part), st);
+  else
+    overlap_lower(phi, phi, nullptr, m, c->V, c->g.dV, I, nullptr, c->at(c->lay.gemm_part), st);
   hermitian_fill(I, m, st);
   jacobi_eigh(I, m, w, X, c->at(c->lay.jac_work), JACOBI_TOL, JACOBI_SWEEPS, st);
   // C = X diag(w^-1/2) X^H
@@ -259,7 +288,8 @@ int loewdin(sky_ctx* c, int q, const void* phi, void* psi_out) {
   gemm_square(c->at(c->lay.matT), 0, X, 1, C, m, st);
   int rc = check_info(c, "loewdin");
   if (rc) return rc;
-  combine(phi, C, psi_out, m, c->V, st);
+  if (c->prec) combine_mixed(phi, C, psi_out, m, c->V, st);
+  else combine(phi, C, psi_out, m, c->V, st);
   return SKY_OK;
 }
 
@@ -267,7 +297,7 @@ void fields(sky_ctx* c) {
   hipStream_t st = c->st;
   for (int q = 0; q < 2; ++q) {
     const int td = t_begin(c, SKY_PHASE_DENSITIES, q);
-    sky::densities(c->n, c->at(c->lay.psi[q]), c->nq[q], DENS_CHUNKS, c->g,
+    sky::densities(c->n, c->prec, c->psi(q), c->nq[q], DENS_CHUNKS, c->g,
                    c->at<double>(c->lay.dens_part), c->at<double>(c->lay.dens[q]), st);
     t_end(c, td);
   }
@@ -308,6 +338,7 @@ int sky_create(const sky_box_desc* d, void* workspace, size_t bytes, void* strea
   c->V = 2L * c->n3;
   c->nq[0] = d->n_neutrons;
   c->nq[1] = d->n_protons;
+  c->prec = d->precision == SKY_MIXED ? 1 : 0;
   c->g.dx = d->dx;
   c->g.dV = d->dx * d->dx * d->dx;
   c->g.kunit = 2.0 * M_PI / (d->n * d->dx);
@@ -336,12 +367,18 @@ int sky_create(const sky_box_desc* d, void* workspace, size_t bytes, void* strea
 int sky_init_box(sky_ctx* c, const void* raw_n, const void* raw_p) {
   if (!c) return fail(SKY_ERR_INVALID, "null context");
   const void* raw[2] = {raw_n, raw_p};
+  const int prec = c->d.precision == SKY_MIXED ? 1 : 0;
+  c->prec = 0;   // the initial orthonormalisation runs in FP64 in both modes
   for (int q = 0; q < 2; ++q) {
     if (c->nq[q] == 0) continue;
     if (!raw[q]) return fail(SKY_ERR_INVALID, "null trial states");
     int rc = loewdin(c, q, raw[q], c->at(c->lay.psi[q]));
     if (rc) return rc;
+    if (prec)
+      convert_states(c->at(c->lay.psi[q]), 0, c->at(c->lay.psi32[q]), 1,
+                     size_t(c->nq[q]) * c->V, c->st);
   }
+  c->prec = prec;
   fields(c);
   return hip_check(hipStreamSynchronize(c->st), "init");
 }
@@ -350,8 +387,8 @@ int sky_apply_h(sky_ctx* c, int32_t q, const void* psi, void* hpsi, int32_t nsta
                 double* eps) {
   if (!c || q < 0 || q > 1 || !psi || !hpsi || nstates < 0) return fail(SKY_ERR_INVALID, "apply_h arguments");
   if (nstates > c->nq[q]) return fail(SKY_ERR_INVALID, "apply_h: more states than the species holds");
-  apply_h(c->n, psi, hpsi, nstates, c->mfp(q), c->g, eps ? c->at<double>(c->lay.tiles) : nullptr, eps,
-          c->st);
+  apply_h(c->n, c->prec, psi, hpsi, nstates, c->mfp(q), c->g,
+          eps ? c->at<double>(c->lay.tiles) : nullptr, eps, c->st);
   return hip_check(hipGetLastError(), "apply_h launch");
 }
 
@@ -362,8 +399,8 @@ int sky_damped_step(sky_ctx* c, int32_t q, const void* psi, const void* hpsi, co
   if (nstates > c->nq[q]) return fail(SKY_ERR_INVALID, "damped_step: more states than the species holds");
   double* r2o = r2 ? r2 : c->at<double>(c->lay.r2[q]);
   const double hb = q ? c->d.hb2m_p : c->d.hb2m_n;
-  damped_step(c->n, psi, hpsi, eps, phi, nstates, c->g, c->d.damp_x0, c->d.damp_e0, hb,
-              c->at<double>(c->lay.tiles), r2o, c->st);
+  damped_step(c->n, c->prec, psi, hpsi, eps, phi, nstates, c->g, c->d.damp_x0, c->d.damp_e0,
+              hb, c->at<double>(c->lay.tiles), r2o, c->st);
   return hip_check(hipGetLastError(), "damped_step launch");
 }
 
@@ -393,23 +430,23 @@ int sky_iterate(sky_ctx* c, int32_t max_iter, double tol, sky_report* rep) {
     for (int q = 0; q < 2; ++q) {
       const int m = c->nq[q];
       if (m == 0) continue;
-      void* psi = c->at(c->lay.psi[q]);
-      void* hpsi = c->at(c->lay.hpsi[q]);
-      void* phi = c->at(c->lay.phi[q]);
-      void* hphi = c->at(c->lay.hphi[q]);
+      void* psi = c->psi(q);
+      void* hpsi = c->hpsi(q);
+      void* phi = c->phi(q);
+      void* hphi = c->hphi(q);
       double* eps = c->at<double>(c->lay.eps[q]);
       double* tiles = c->at<double>(c->lay.tiles);
       // step 2: h psi, <h>, damped step, h phi
       int t0 = t_begin(c, SKY_PHASE_APPLY_H, q);
-      apply_h(c->n, psi, hpsi, m, c->mfp(q), c->g, tiles, eps, st);
+      apply_h(c->n, c->prec, psi, hpsi, m, c->mfp(q), c->g, tiles, eps, st);
       t_end(c, t0);
       const double hb = q ? c->d.hb2m_p : c->d.hb2m_n;
       int t1 = t_begin(c, SKY_PHASE_DAMP, q);
-      damped_step(c->n, psi, hpsi, eps, phi, m, c->g, c->d.damp_x0, c->d.damp_e0, hb, tiles,
-                  c->at<double>(c->lay.r2[q]), st);
+      damped_step(c->n, c->prec, psi, hpsi, eps, phi, m, c->g, c->d.damp_x0, c->d.damp_e0, hb,
+                  tiles, c->at<double>(c->lay.r2[q]), st);
       t_end(c, t1);
       int t2 = t_begin(c, SKY_PHASE_APPLY_H, q);
-      apply_h(c->n, phi, hphi, m, c->mfp(q), c->g, nullptr, nullptr, st);
+      apply_h(c->n, c->prec, phi, hphi, m, c->mfp(q), c->g, nullptr, nullptr, st);
       t_end(c, t2);
       // steps 3a-3e
       int rc = rayleigh_ritz(c, q, phi, hphi, psi, c->at<double>(c->lay.ritz[q]));
@@ -434,6 +471,15 @@ int sky_iterate(sky_ctx* c, int32_t max_iter, double tol, sky_report* rep) {
     t_flush(c);
     de = std::sqrt(sum / std::max(1, cnt));
     if (!std::isfinite(de)) return fail(SKY_ERR_NAN, "non-finite residual");
+    // precision ladder: finish in FP64 once the mixed form has done its part
+    if (c->prec == 1 && c->d.ladder_tol > 0.0 && de <= c->d.ladder_tol) {
+      for (int q = 0; q < 2; ++q)
+        convert_states(c->at(c->lay.psi32[q]), 1, c->at(c->lay.psi[q]), 0,
+                       size_t(c->nq[q]) * c->V, st);
+      c->prec = 0;
+      fields(c);
+      c->switched_at = c->iter_count + it + 1;
+    }
     if (tol > 0.0 && de <= tol) { ++it; break; }
   }
   double e[8] = {0};
@@ -444,7 +490,9 @@ int sky_iterate(sky_ctx* c, int32_t max_iter, double tol, sky_report* rep) {
   if (rc) return rc;
   if (!std::isfinite(e[7])) return fail(SKY_ERR_NAN, "non-finite energy");
   if (tol > 0.0 && !(de <= tol)) status = SKY_NOT_CONVERGED;
+  c->iter_count += it;
   if (rep) {
+    rep->precision = c->prec ? SKY_MIXED : SKY_FP64;
     rep->iters = it;
     rep->residual = de;
     rep->energy = e[7];
@@ -459,10 +507,10 @@ int sky_get_view(sky_ctx* c, int32_t what, int32_t q, void** ptr, int64_t* count
   if (q < 0 || q > 1) return fail(SKY_ERR_INVALID, "species must be 0 or 1");
   const int64_t st = int64_t(c->nq[q]) * c->V;
   switch (what) {
-    case SKY_VIEW_PSI: *ptr = c->at(c->lay.psi[q]); *count = st; break;
-    case SKY_VIEW_HPSI: *ptr = c->at(c->lay.hpsi[q]); *count = st; break;
-    case SKY_VIEW_PHI: *ptr = c->at(c->lay.phi[q]); *count = st; break;
-    case SKY_VIEW_HPHI: *ptr = c->at(c->lay.hphi[q]); *count = st; break;
+    case SKY_VIEW_PSI: *ptr = c->psi(q); *count = st; break;
+    case SKY_VIEW_HPSI: *ptr = c->hpsi(q); *count = st; break;
+    case SKY_VIEW_PHI: *ptr = c->phi(q); *count = st; break;
+    case SKY_VIEW_HPHI: *ptr = c->hphi(q); *count = st; break;
     case SKY_VIEW_DENS: *ptr = c->at(c->lay.dens[q]); *count = 11LL * c->n3; break;
     case SKY_VIEW_MEANFIELD: *ptr = c->at(c->lay.mf[q]); *count = 5LL * c->n3; break;
     case SKY_VIEW_COULOMB: *ptr = c->at(c->lay.vc); *count = c->n3; break;
@@ -500,6 +548,12 @@ int sky_get_timing(sky_ctx* c, double* ms, int64_t* launches) {
       ms[2 * p + q] = c->ms[p][q];
       if (launches) launches[2 * p + q] = c->cnt[p][q];
     }
+  return SKY_OK;
+}
+
+int sky_get_precision(sky_ctx* c, int32_t* precision) {
+  if (!c || !precision) return fail(SKY_ERR_INVALID, "get_precision arguments");
+  *precision = c->prec ? SKY_MIXED : SKY_FP64;
   return SKY_OK;
 }
 

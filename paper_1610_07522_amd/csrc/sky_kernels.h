@@ -5,17 +5,21 @@
 
 namespace sky {
 
-// ---- grid kernels (k_grid.hip); states are complex128 [state][2][n^3]
+// ---- grid kernels (k_grid.hip); states are [state][2][n^3], complex128
+// (prec 0) or complex64 (prec 1); reductions are FP64 either way.
 int grid_ntiles(int n);  // workgroups per state of one line pass
-void apply_h(int n, const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf, GridArgs g,
-             double* eps_part, double* eps, hipStream_t st);
-void damped_step(int n, const void* psi, const void* hpsi, const double* eps, void* phi,
-                 int nstate, GridArgs g, double x0, double e0, double hb2m, double* r2_part,
-                 double* r2, hipStream_t st);
+void apply_h(int n, int prec, const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf,
+             GridArgs g, double* eps_part, double* eps, hipStream_t st);
+void damped_step(int n, int prec, const void* psi, const void* hpsi, const double* eps,
+                 void* phi, int nstate, GridArgs g, double x0, double e0, double hb2m,
+                 double* r2_part, double* r2, hipStream_t st);
 // dens = 11 fields [rho, tau, Jx, Jy, Jz, sx, sy, sz, jx, jy, jz][n^3];
 // part holds nchunk_max * 16 * n^3 doubles.
-void densities(int n, const void* psi, int nstate, int nchunk_max, GridArgs g, double* part,
-               double* dens, hipStream_t st);
+void densities(int n, int prec, const void* psi, int nstate, int nchunk_max, GridArgs g,
+               double* part, double* dens, hipStream_t st);
+// n complex values between precisions (0 = complex128, 1 = complex64).
+void convert_states(const void* src, int src_prec, void* dst, int dst_prec, size_t n,
+                    hipStream_t st);
 
 // ---- mean field and energy (k_fields.hip)
 struct Skyrme {
@@ -39,6 +43,16 @@ size_t overlap_scratch_bytes(int m, long k);
 // ev (may be null): events recorded right before / after the GEMM kernel.
 void overlap_lower(const void* A, const void* B0, const void* B1, int m, long k, double scale,
                    void* C0, void* C1, void* part, hipStream_t st, hipEvent_t* ev = nullptr);
+// FP64 reduction of split-K partials into the lower tiles of C0 (and C1).
+void overlap_reduce(const void* part, int npair, int split, int m, double scale, void* C0,
+                    void* C1, int nz, hipStream_t st);
+// Mixed precision (k_gemm_mixed.hip): complex64 operands, split-BF16 MFMA,
+// FP64 results for the overlap; complex64 output states for the combine.
+size_t overlap_scratch_bytes_mixed(int m, long k);
+void overlap_lower_mixed(const void* A, const void* B0, const void* B1, int m, long k,
+                         double scale, void* C0, void* C1, void* part, hipStream_t st,
+                         hipEvent_t* ev = nullptr);
+void combine_mixed(const void* X, const void* U, void* Y, int m, long k, hipStream_t st);
 // Fill the upper triangle of Hermitian C from the lower one (and make the
 // diagonal real), in place.
 void hermitian_fill(void* C, int m, hipStream_t st);

@@ -23,6 +23,8 @@ SKY_ERR_WORKSPACE = -3
 SKY_ERR_HIP = -4
 SKY_ERR_NOT_POSITIVE_DEFINITE = -5
 SKY_ERR_NAN = -6
+SKY_FP64 = 0
+SKY_MIXED = 1
 
 VIEW = dict(psi=0, hpsi=1, phi=2, hphi=3, dens=4, meanfield=5, coulomb=6, energy=7,
             eps=8, ritz=9, r2=10, overlap=11, hsub=12, evec=13, umat=14)
@@ -31,8 +33,8 @@ _MATRIX_VIEWS = ("overlap", "hsub", "evec", "umat")
 # Symbols declared in include/sky.h, in order.
 EXPORTS = ("sky_workspace_size", "sky_create", "sky_init_box", "sky_apply_h",
            "sky_damped_step", "sky_orthonormalize", "sky_densities", "sky_iterate",
-           "sky_get_view", "sky_set_timing", "sky_get_timing", "sky_sync",
-           "sky_last_error", "sky_destroy")
+           "sky_get_view", "sky_set_timing", "sky_get_timing", "sky_get_precision",
+           "sky_sync", "sky_last_error", "sky_destroy")
 PHASES = ("apply_h", "damp", "overlap_gemm", "subspace", "combine_gemm", "densities",
           "meanfield")
 
@@ -47,13 +49,14 @@ class BoxDesc(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("W0", ctypes.c_double),
                 ("hb2m_n", ctypes.c_double), ("hb2m_p", ctypes.c_double),
                 ("e2", ctypes.c_double),
-                ("damp_x0", ctypes.c_double), ("damp_e0", ctypes.c_double)]
+                ("damp_x0", ctypes.c_double), ("damp_e0", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("ladder_tol", ctypes.c_double)]
 
 
 class Report(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("residual", ctypes.c_double),
                 ("energy", ctypes.c_double), ("energy_per_a", ctypes.c_double),
-                ("jacobi_sweeps", ctypes.c_int32)]
+                ("jacobi_sweeps", ctypes.c_int32), ("precision", ctypes.c_int32)]
 
 
 class SkyError(RuntimeError):
@@ -92,6 +95,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "sky_set_timing": (ctypes.c_int, [vp, i32]),
         "sky_get_timing": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_int64)]),
+        "sky_get_precision": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int32)]),
         "sky_sync": (ctypes.c_int, [vp]),
         "sky_last_error": (ctypes.c_char_p, []),
         "sky_destroy": (None, [vp]),
@@ -111,12 +115,13 @@ def _check(rc: int, ok=(SKY_OK,)) -> int:
     return rc
 
 
-def desc_from_workload(w) -> BoxDesc:
+def desc_from_workload(w, precision: int = SKY_FP64, ladder_tol: float = 0.0) -> BoxDesc:
     """BoxDesc of a ``paper_1610_07522_amd.inputs.Workload``."""
     p = w.params
     return BoxDesc(w.n, w.dx, w.n_neutrons, w.n_protons, p["t0"], p["t1"], p["t2"], p["t3"],
                    p["x0"], p["x1"], p["x2"], p["x3"], p["alpha"], p["W0"],
-                   p["hb2m_n"], p["hb2m_p"], p["e2"], w.damp_x0, w.damp_e0)
+                   p["hb2m_n"], p["hb2m_p"], p["e2"], w.damp_x0, w.damp_e0,
+                   precision, ladder_tol)
 
 
 def _ptr(t) -> Optional[int]:
@@ -180,7 +185,12 @@ class Box:
                     ok=(SKY_OK, SKY_NOT_CONVERGED))
         return dict(iters=rep.iters, residual=rep.residual, energy=rep.energy,
                     energy_per_a=rep.energy_per_a, jacobi_sweeps=rep.jacobi_sweeps,
-                    converged=(rc == SKY_OK))
+                    precision=rep.precision, converged=(rc == SKY_OK))
+
+    def precision(self) -> int:
+        p = ctypes.c_int32()
+        _check(self.lib.sky_get_precision(self.ctx, ctypes.byref(p)))
+        return p.value
 
     def sync(self):
         _check(self.lib.sky_sync(self.ctx))
@@ -209,6 +219,8 @@ class Box:
         is_cpx = is_state or what in _MATRIX_VIEWS
         dt = torch.complex128 if is_cpx else torch.float64
         esize = 16 if is_cpx else 8
+        if is_state and self.precision() == SKY_MIXED:
+            dt, esize = torch.complex64, 8
         off = ptr.value - self.ws.data_ptr() if ptr.value else 0
         t = self.ws[off:off + cnt.value * esize].view(dt)
         n = self.desc.n

@@ -1,0 +1,150 @@
+"""Mixed-precision form (complex64 states, FP32 FFT and h*psi, split-BF16
+MFMA products with FP32 accumulation folded into FP64, FP64 subspace solve)
+against the FP64 oracle.
+
+The oracle gets the same complex64-rounded inputs, widened exactly to
+complex128, so each bar measures only the mixed arithmetic.  Bars derive from
+the FP32 unit roundoff u = 2^-24 ~ 6e-8:
+* split-BF16 products keep six of nine split terms (dropped terms O(u)) and
+  accumulate in FP32 over 256 elements before folding into FP64: relative
+  error a few u of the largest entry -> 1e-6;
+* an FP32 spectral derivative loses ~log2(n) u -> h*psi, densities and the
+  damped step within 2e-5 of their max-norm (two derivatives per direction,
+  three directions, FP32 pointwise algebra);
+* the energy is a difference of kinetic and potential parts ~50x larger
+  than the total in a pasta box, so per-iteration energy error is bounded by
+  a few hundred u times the sum of |parts|.
+"""
+import numpy as np
+import pytest
+
+from oracle import Grid
+from oracle import physics as ph
+from oracle import solver as so
+from paper_1610_07522_amd import inputs
+
+from gpu_util import CASES, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+MIXED_CASES = ["n16_8p8", "n24_13p7_rod", "n32_70p33_slab", "n24_200p50_rod"]
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _box(w, ladder_tol=0.0):
+    from paper_1610_07522_amd import sky
+    return sky.Box(sky.desc_from_workload(w, precision=sky.SKY_MIXED, ladder_tol=ladder_tol))
+
+
+def _c64(x):
+    return x.astype(np.complex64)
+
+
+@pytest.mark.parametrize("case", MIXED_CASES)
+def test_mixed_overlap_and_loewdin(torch_mod, case):
+    torch = torch_mod
+    w = CASES[case]
+    raw = [_c64(r) for r in inputs.raw_states(w)]
+    g = Grid(w.n, w.dx)
+    box = _box(w)
+    for q in range(2):
+        m = raw[q].shape[0]
+        out = torch.empty(raw[q].shape, dtype=torch.complex64, device="cuda:0")
+        box.orthonormalize(q, to_dev(raw[q]), None, out)
+        ref64 = raw[q].astype(np.complex128)
+        I_ref = so.overlap(ref64, ref64, g)
+        assert rel_err(to_host(box.view("overlap", q)), I_ref) <= 1e-6, (case, q)
+        o = to_host(out).astype(np.complex128)
+        G = so.overlap(o, o, g)
+        assert np.abs(G - np.eye(m)).max() <= 2e-6, (case, q)
+        assert rel_err(o, so.loewdin(ref64, g)) <= 2e-5, (case, q)
+
+
+@pytest.mark.parametrize("case", MIXED_CASES)
+def test_mixed_fields_h_and_damping(torch_mod, case):
+    torch = torch_mod
+    w = CASES[case]
+    raw = [_c64(r) for r in inputs.raw_states(w)]
+    ref = [r.astype(np.complex128) for r in raw]
+    g = Grid(w.n, w.dx)
+    box = _box(w)
+    for q in range(2):
+        box.view("psi", q).copy_(to_dev(raw[q]))
+    box.densities()
+    box.sync()
+    dn, dp = ph.densities(ref[0], g), ph.densities(ref[1], g)
+    mn, mp, vc = ph.mean_field(dn, dp, g, w.params)
+    E = ph.energy(dn, dp, g, w.params, vc)
+    for q, d in ((0, dn), (1, dp)):
+        gd = to_host(box.view("dens", q))
+        assert rel_err(gd[0], d.rho) <= 2e-6, (case, q)
+        assert rel_err(gd[1], d.tau) <= 2e-5, (case, q)
+    parts = sum(abs(E[k]) for k in ("kin", "rho", "rho3", "tau", "lap", "so", "coul"))
+    assert abs(to_host(box.view("energy"))[7] - E["total"]) <= 300 * U32 * parts, case
+    for q, mf in ((0, mn), (1, mp)):
+        m = raw[q].shape[0]
+        psi, hpsi, phi = box.view("psi", q), box.view("hpsi", q), box.view("phi", q)
+        eps = torch.zeros(m, dtype=torch.float64, device="cuda:0")
+        r2 = torch.zeros(m, dtype=torch.float64, device="cuda:0")
+        box.apply_h(q, psi, hpsi, m, eps)
+        box.damped_step(q, psi, hpsi, eps, phi, m, r2)
+        box.sync()
+        h_ref = ph.apply_h(ref[q], mf, g)
+        e_ref, r_ref, r2_ref = so.rayleigh_and_residual(ref[q], h_ref, g)
+        phi_ref = ref[q] - so.damping(r_ref, g, mf.hb2m, w.damp_x0, w.damp_e0)
+        assert rel_err(to_host(hpsi), h_ref) <= 2e-5, (case, q)
+        assert rel_err(to_host(eps), e_ref) <= 2e-5, (case, q)
+        assert rel_err(to_host(phi), phi_ref) <= 2e-6, (case, q)
+
+
+@pytest.mark.parametrize("case", ["n16_8p8", "n24_200p50_rod"])
+def test_mixed_trajectory_tracks_fp64(torch_mod, case):
+    """Mixed iterations stay within FP32-level distance of the FP64 oracle
+    trajectory started from the same raw states."""
+    w = CASES[case]
+    raw = inputs.raw_states(w)
+    g = Grid(w.n, w.dx)
+    st = so.initial_state(*raw, g, w.params, w.damp_x0, w.damp_e0)
+    box = _box(w)
+    box.init_box(to_dev(raw[0]), to_dev(raw[1]))
+    for it in range(5):
+        rep = box.iterate(1)
+        ro = so.iterate(st)
+        assert rep["precision"] == 1
+        parts = sum(abs(st.E[k]) for k in ("kin", "rho", "rho3", "tau", "lap", "so", "coul"))
+        assert abs(rep["energy"] - st.E["total"]) <= 1000 * U32 * parts * (it + 1), (case, it)
+        assert abs(rep["residual"] - ro.de) <= 1e-4 * max(1.0, ro.de), (case, it)
+        for q in range(2):
+            assert rel_err(to_host(box.view("ritz", q)), ro.ritz[q]) <= 1e-5, (case, it, q)
+
+
+def test_precision_ladder_switches_to_fp64(torch_mod):
+    """With ladder_tol above the starting residual the context switches to
+    FP64 after the first iteration, and then tracks the FP64 oracle at the
+    FP64 bar relative to where it switched."""
+    w = CASES["n16_8p8"]
+    raw = inputs.raw_states(w)
+    g = Grid(w.n, w.dx)
+    box = _box(w, ladder_tol=1e3)
+    box.init_box(to_dev(raw[0]), to_dev(raw[1]))
+    assert box.precision() == 1
+    rep = box.iterate(1)
+    assert rep["precision"] == 0 and box.precision() == 0
+    assert box.view("psi", 0).dtype.itemsize == 16
+    st = so.initial_state(*raw, g, w.params, w.damp_x0, w.damp_e0)
+    so.iterate(st)
+    e1 = rep["energy"]
+    # the FP64 continuation from the mixed first iterate stays close to the oracle
+    rep = box.iterate(5)
+    for _ in range(5):
+        so.iterate(st)
+    parts = sum(abs(st.E[k]) for k in ("kin", "rho", "rho3", "tau", "lap", "so", "coul"))
+    assert abs(rep["energy"] - st.E["total"]) <= 1000 * U32 * parts, (e1, rep, st.E)
