@@ -3,7 +3,7 @@
 
 One step = one full static iteration (Fig. 1 steps 2-5 of the paper) for
 both species, in the mixed-precision form by default (complex64 states, FP32
-FFTs and h psi, split-BF16 MFMA GEMMs, FP64 subspace solve), with the FP64
+FFTs and h psi, split-FP16 MFMA GEMMs, FP64 subspace solve), with the FP64
 form timed on the same box for comparison: h psi, damped gradient step, h phi, overlap and subspace
 Hamiltonian GEMMs, Cholesky + Jacobi Rayleigh-Ritz, recombination GEMM,
 densities, mean field, Coulomb and energy.  Inputs are synthetic (seeded
@@ -28,9 +28,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix and vector)
-PEAK_BF16_TFLOPS = 2500.0    # MI355X dense BF16 matrix
+PEAK_F16_TFLOPS = 2500.0     # MI355X dense FP16 / BF16 matrix
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
-SPLIT_PRODUCTS = 6           # BF16 products per real product in the mixed GEMMs
+SPLIT_PRODUCTS = 3           # FP16 products per real product in the mixed GEMMs
 
 
 def log(msg: str) -> None:
@@ -47,9 +47,9 @@ def gemm_flops(m: int, v: int) -> dict:
 def roofline(timing: dict, w, mixed: bool) -> dict:
     """Roofline of the costlier of the two single-kernel GEMM phases (the
     I/H overlap GEMM or the recombination GEMM), neutron launches.  FP64:
-    8 flops per complex MAC against the FP64 peak; mixed: the BF16 flops the
-    split algorithm issues (6 split products x 8 per complex MAC) against the
-    BF16 peak."""
+    8 flops per complex MAC against the FP64 peak; mixed: the FP16 flops the
+    split algorithm issues (3 split products x 8 per complex MAC) against the
+    FP16 peak."""
     v = 2 * w.n ** 3
     m = w.n_neutrons
     dom = max(("overlap_gemm", "combine_gemm"),
@@ -57,11 +57,14 @@ def roofline(timing: dict, w, mixed: bool) -> dict:
     t = timing[dom]
     avg_ms = t["ms_n"] / max(1, t["launches_n"])
     fl = gemm_flops(m, v)[dom] * (SPLIT_PRODUCTS if mixed else 1)
-    peak = PEAK_BF16_TFLOPS if mixed else PEAK_FP64_TFLOPS
+    peak = PEAK_F16_TFLOPS if mixed else PEAK_FP64_TFLOPS
     ach = fl / (avg_ms * 1e-3) / 1e12
-    name = ("k_overlap_lower" if dom == "overlap_gemm" else "k_combine") + ("_mixed" if mixed else "")
+    if mixed:
+        name = "k_overlap_planes" if dom == "overlap_gemm" else "k_combine_planes"
+    else:
+        name = "k_overlap_lower" if dom == "overlap_gemm" else "k_combine"
     return dict(kernel=name, bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s",
-                frac=ach / peak, traffic=None, dtype=("bf16x3-split" if mixed else "fp64"),
+                frac=ach / peak, traffic=None, dtype=("fp16x2-split" if mixed else "fp64"),
                 per_launch=dict(species="neutrons", m=m, k=v, flops=fl, avg_ms=avg_ms))
 
 
@@ -214,7 +217,7 @@ def main() -> int:
         value=args.steps / elapsed, unit="iter/s", n_gpus=1, steps=args.steps,
         warmup=args.warmup, ms_per_step=1e3 * elapsed / args.steps, higher_is_better=True,
         scaling="weak", vs_baseline=None,
-        dtype=("mixed: c64 states, f32 FFT/h*psi, bf16x3-split MFMA GEMMs with f32->f64 "
+        dtype=("mixed: c64 states, f32 FFT/h*psi, fp16x2-split MFMA GEMMs with f32->f64 "
                "accumulation, f64 subspace solve and sums") if mixed else "f64",
         data="synthetic",
         config=dict(workload=(f"{w.name}: {w.n}^3 grid, dx {w.dx} fm, {w.n_neutrons} n + "

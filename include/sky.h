@@ -14,8 +14,9 @@
  * - Precision (sky_box_desc.precision): SKY_FP64 keeps every state in
  *   complex128 and every operation in binary64.  SKY_MIXED keeps the states
  *   in complex64, runs FFTs and h*psi in binary32, forms the overlap,
- *   subspace-Hamiltonian and recombination products from a three-way BF16
- *   split on the matrix cores with FP32 accumulation folded into FP64, and
+ *   subspace-Hamiltonian and recombination products from a two-term FP16
+ *   split (one power-of-two scale per operand matrix) on the matrix cores
+ *   with FP32 accumulation folded into FP64, and
  *   keeps the Cholesky, eigensolver, densities, mean field and energy sums
  *   in binary64.  Reductions (<h>, residuals, densities) are binary64 in both
  *   modes.  State pointers passed to the per-step calls must have the
@@ -123,7 +124,8 @@ enum {
   SKY_PHASE_COMBINE_GEMM = 4,  /* psi = phi U GEMM kernel (step 3e)               */
   SKY_PHASE_DENSITIES = 5,     /* rho, tau, J (step 4a)                           */
   SKY_PHASE_MEANFIELD = 6,     /* mean field, Coulomb, energy (steps 4b, 5)       */
-  SKY_NPHASE = 7
+  SKY_PHASE_SPLIT = 7,         /* FP16 split planes of phi, h phi (mixed only)    */
+  SKY_NPHASE = 8
 };
 
 typedef struct sky_ctx sky_ctx;

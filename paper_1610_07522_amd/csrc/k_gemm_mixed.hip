@@ -1,15 +1,23 @@
-// Mixed-precision subspace products: complex64 operands on the BF16 matrix
-// cores (v_mfma_f32_16x16x32_bf16) with the three-way BF16 split.
+// Mixed-precision subspace products: complex64 operands on the FP16 matrix
+// cores of gfx950 (v_mfma_f32_16x16x32_f16) with a two-term FP16 split.
 //
-// Every FP32 component x is split once, while a tile is staged in LDS, into
-// x = x0 + x1 + x2 (BF16 each, round to nearest even; the residuals are
-// exact in FP32).  A real product x*y keeps the six terms
-// x0y0 + x0y1 + x1y0 + x0y2 + x2y0 + x1y1, which carries FP32 accuracy
-// (the dropped terms are O(2^-24) relative).  MFMA accumulation is FP32 over
-// runs of FLUSH*KB contraction elements, then folded into FP64 registers;
-// split-K partials are reduced in FP64.  Output of the overlap products is
-// FP64 (it feeds the FP64 Cholesky / eigensolver); the recombination writes
-// complex64 states.
+// Each operand matrix gets one power-of-two scale 2^S, chosen from its largest
+// component so that every scaled component is below 2^14.  Each scaled FP32
+// component x is split once, in HBM, into x = h + l + r with h = fp16(x) and
+// l = fp16(x - h) (round to nearest even; x - h is exact in FP32), so
+// |r| <= 2^-22 |x| while h is normal and |r| <= 2^-25 below that (2^-39 of
+// the largest component).  A real product keeps h h' + h l' + l h'; the
+// dropped l l' is O(2^-22) relative.  The split planes hold (re h, re l,
+// im h, im l) as FP16 bit patterns: 8 bytes per complex element, the size of
+// the complex64 operand, and the GEMMs stage their tiles with plain 16-byte
+// copies.  MFMA accumulation is FP32 over runs of FLUSH*KB contraction
+// elements, folded into FP64 registers; split-K partials are reduced in FP64
+// and the scales are removed exactly in FP64.  The overlap products are
+// written in FP64 (they feed the FP64 Cholesky factorisation and
+// eigensolver); the recombination writes complex64 states.
+//
+// Workgroups are mapped to tiles so that the eight XCDs (workgroup i runs on
+// XCD i mod 8) each stream their own slice of the data through their own L2.
 //
 // Sec. 3.3.1 (I and H, lower triangles, Fig. 3) and Sec. 3.3.3 (psi = phi U).
 #include "sky_kernels.h"
@@ -17,59 +25,94 @@
 namespace sky {
 
 namespace {
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 constexpr int TM = 64;       // output tile
 constexpr int KB = 32;       // contraction elements per MFMA step
 constexpr int FLUSH = 8;     // steps accumulated in FP32 before folding into FP64
-constexpr int NP = 6;        // split planes: (part re/im) x (split 0..2)
-constexpr int RS = KB + 8;   // padded LDS row (bf16 elements); 80 bytes
+constexpr int NP = 4;        // split planes: (part re/im) x (split h/l)
+constexpr int RS = KB + 8;   // padded LDS row (fp16 elements); 80 bytes
 constexpr int GT = 256;
+constexpr int NXCD = 8;      // XCDs of the MI355X
 
-// BF16 round-to-nearest-even of x, returned as the bit pattern.
-__device__ inline unsigned short bf16_bits(float x) {
-  unsigned int u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ inline float bf16_value(unsigned short b) { return __uint_as_float(((unsigned int)b) << 16); }
-
-// x -> three BF16 parts (bit patterns).
-__device__ inline void split3(float x, unsigned short& s0, unsigned short& s1, unsigned short& s2) {
-  s0 = bf16_bits(x);
-  float r1 = x - bf16_value(s0);
-  s1 = bf16_bits(r1);
-  float r2 = r1 - bf16_value(s1);
-  s2 = bf16_bits(r2);
+// Scale exponent S of a matrix whose largest |component| has the float bit
+// pattern mx: max * 2^S lies in [2^13, 2^14).
+__device__ inline int scale_exp(unsigned int mx) {
+  const float m = __uint_as_float(mx);
+  if (!(m > 0.0f) || m > 3.0e38f) return 0;
+  int e;
+  frexpf(m, &e);
+  return 14 - e;
 }
 
-// Plane index: part (0 re, 1 im) * 3 + split.
-__device__ inline int plane(int part, int s) { return part * 3 + s; }
+__device__ inline unsigned short f16_bits(_Float16 h) { return __builtin_bit_cast(unsigned short, h); }
 
-// LDS tile: [plane][row][RS] bf16 bit patterns.
+// x -> (h, l) FP16 bit patterns (x already scaled).
+__device__ inline void split2(float x, unsigned short& h, unsigned short& l) {
+  const _Float16 a = (_Float16)x;
+  const _Float16 b = (_Float16)(x - (float)a);
+  h = f16_bits(a);
+  l = f16_bits(b);
+}
+
+// Plane index: part (0 re, 1 im) * 2 + split (0 h, 1 l).
+__device__ inline int plane(int part, int s) { return part * 2 + s; }
+
+// Splits of 8 consecutive elements as four 16-byte vectors (one per plane).
+__device__ inline void split8(const float2 (&z)[8], int S, u4 (&w)[NP]) {
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    unsigned short a[2][2], b[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      split2(ldexpf(z[2 * h + u].x, S), a[u][0], a[u][1]);
+      split2(ldexpf(z[2 * h + u].y, S), b[u][0], b[u][1]);
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      w[plane(0, s)][h] = (unsigned int)a[0][s] | ((unsigned int)a[1][s] << 16);
+      w[plane(1, s)][h] = (unsigned int)b[0][s] | ((unsigned int)b[1][s] << 16);
+    }
+  }
+}
+
+// LDS tile: [plane][row][RS] fp16 bit patterns.
 struct Tile {
   unsigned short v[NP][TM][RS];
 };
 
-// Store the splits of complex value z at (row, k) of a tile.
-__device__ inline void put(Tile& t, int row, int k, float2 z) {
-  unsigned short a0, a1, a2, b0, b1, b2;
-  split3(z.x, a0, a1, a2);
-  split3(z.y, b0, b1, b2);
-  t.v[0][row][k] = a0; t.v[1][row][k] = a1; t.v[2][row][k] = a2;
-  t.v[3][row][k] = b0; t.v[4][row][k] = b1; t.v[5][row][k] = b2;
+// One thread's share of a 64-row x KB tile: row tid/4, 8 elements at (tid%4)*8.
+struct Frag {
+  u4 v[NP];
+};
+
+__device__ inline void gload(Frag& f, const unsigned short* __restrict__ P, size_t psz, long ld,
+                             int row0, int R, long k0, int tid) {
+  const int row = tid >> 2, kk = (tid & 3) * 8;
+  const bool ok = row0 + row < R;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    f.v[p] = u4{0, 0, 0, 0};
+    if (ok) f.v[p] = *reinterpret_cast<const u4*>(P + p * psz + size_t(row0 + row) * ld + k0 + kk);
+  }
 }
 
-__device__ inline bf8 ld8(const Tile& t, int p, int row, int k8) {
-  u4 u = *reinterpret_cast<const u4*>(&t.v[p][row][k8]);
-  return __builtin_bit_cast(bf8, u);
+__device__ inline void sstore(Tile& t, const Frag& f, int tid) {
+  const int row = tid >> 2, kk = (tid & 3) * 8;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) *reinterpret_cast<u4*>(&t.v[p][row][kk]) = f.v[p];
 }
-__device__ inline bf8 neg8(bf8 x) {
+
+__device__ inline h8 ld8(const Tile& t, int p, int row, int k8) {
+  u4 u = *reinterpret_cast<const u4*>(&t.v[p][row][k8]);
+  return __builtin_bit_cast(h8, u);
+}
+__device__ inline h8 neg8(h8 x) {
   u4 u = __builtin_bit_cast(u4, x);
   u ^= u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
-  return __builtin_bit_cast(bf8, u);
+  return __builtin_bit_cast(h8, u);
 }
 
 struct Acc32 {
@@ -108,45 +151,48 @@ __device__ inline void fold(Acc64& d, Acc32& s) {
     }
 }
 
-#define MF(a, b, c) c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0)
+#define MF(a, b, c) c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0)
 
 // acc += op(A) B^T over one KB step; A rows = tile rows of sA, B cols = rows
-// of sB; op(A) = conj(A) if CONJA.  Six split products per real product.
+// of sB; op(A) = conj(A) if CONJA.  Three split products per real product.
+// MFMA operands: lane l supplies 8 consecutive contraction elements starting
+// at 8*(l/16) of row (or column) l%16.
 template <bool CONJA>
 __device__ inline void step(Acc32& acc, const Tile& sA, const Tile& sB, int wm, int wn, int lane) {
   const int r = lane & 15, k8 = (lane >> 4) * 8;
-  bf8 ar[2][3], ai[2][3], br[2][3], bi[2][3];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      ar[i][s] = ld8(sA, plane(0, s), wm * 32 + i * 16 + r, k8);
-      ai[i][s] = ld8(sA, plane(1, s), wm * 32 + i * 16 + r, k8);
-      if (CONJA) ai[i][s] = neg8(ai[i][s]);
-    }
+  h8 br[2][2], bi[2][2];
 #pragma unroll
   for (int j = 0; j < 2; ++j)
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
+    for (int s = 0; s < 2; ++s) {
       br[j][s] = ld8(sB, plane(0, s), wn * 32 + j * 16 + r, k8);
       bi[j][s] = ld8(sB, plane(1, s), wn * 32 + j * 16 + r, k8);
     }
-  // split pairs (p, q): 00 01 10 02 20 11
-  constexpr int P[6] = {0, 0, 1, 0, 2, 1};
-  constexpr int Q[6] = {0, 1, 0, 2, 0, 1};
+  // split pairs (p, q): hh, hl, lh
+  constexpr int P[3] = {0, 0, 1};
+  constexpr int Q[3] = {0, 1, 0};
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 2; ++i) {
+    h8 ar[2], ai[2], an[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      ar[s] = ld8(sA, plane(0, s), wm * 32 + i * 16 + r, k8);
+      ai[s] = ld8(sA, plane(1, s), wm * 32 + i * 16 + r, k8);
+      if (CONJA) ai[s] = neg8(ai[s]);
+      an[s] = neg8(ai[s]);
+    }
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int t = 0; t < 6; ++t) {
+      for (int t = 0; t < 3; ++t) {
         const int p = P[t], q = Q[t];
         // re += ar br - ai bi ; im += ar bi + ai br   (ai already negated for conj)
-        MF(ar[i][p], br[j][q], acc.re[i][j]);
-        MF(neg8(ai[i][p]), bi[j][q], acc.re[i][j]);
-        MF(ar[i][p], bi[j][q], acc.im[i][j]);
-        MF(ai[i][p], br[j][q], acc.im[i][j]);
+        MF(ar[p], br[j][q], acc.re[i][j]);
+        MF(an[p], bi[j][q], acc.re[i][j]);
+        MF(ar[p], bi[j][q], acc.im[i][j]);
+        MF(ai[p], br[j][q], acc.im[i][j]);
       }
+  }
 }
 #undef MF
 
@@ -174,37 +220,155 @@ __device__ inline void tri_pair(int p, int& ta, int& tb) {
   tb = p - a * (a + 1) / 2;
 }
 
-// part[(z*npair + pair)*split + s][64*64] (FP64) = sum over chunk s of conj(A) B^T.
-__global__ void __launch_bounds__(GT)
-k_overlap_lower_mixed(const float2* __restrict__ A, const float2* __restrict__ B0,
-                      const float2* __restrict__ B1, int m, long k, int split,
-                      double2* __restrict__ part) {
+// ------------------------------------------------------------------ scales
+__global__ void k_clear_u32(unsigned int* __restrict__ w, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) w[i] = 0u;
+}
+
+// *mx = max(*mx, bits of the largest |component|) over n complex values
+// (complex128 inputs are first rounded to complex64, as the split rounds them).
+template <bool DOUBLE_IN>
+__global__ void __launch_bounds__(256)
+k_absmax(const void* __restrict__ xv, size_t n, unsigned int* __restrict__ mx) {
+  float m = 0.0f;
+  for (size_t i = size_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += size_t(gridDim.x) * 256) {
+    float a, b;
+    if (DOUBLE_IN) {
+      const double2 d = reinterpret_cast<const double2*>(xv)[i];
+      a = float(d.x);
+      b = float(d.y);
+    } else {
+      const float2 f = reinterpret_cast<const float2*>(xv)[i];
+      a = f.x;
+      b = f.y;
+    }
+    m = fmaxf(m, fmaxf(fabsf(a), fabsf(b)));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  __shared__ float wm[4];
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
+    atomicMax(mx, __float_as_uint(m));
+  }
+}
+
+// ------------------------------------------------------------------ split planes
+// Planes of an R x K complex64 matrix: P[p][r][k], row length K (K % 8 == 0).
+__global__ void __launch_bounds__(256)
+k_split_nt(const float2* __restrict__ x, int R, long K, const unsigned int* __restrict__ mx,
+           unsigned short* __restrict__ P) {
+  const long nk8 = K / 8;
+  const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= size_t(R) * nk8) return;
+  const int S = scale_exp(*mx);
+  const int r = int(t / nk8);
+  const long k0 = (t % nk8) * 8;
+  float2 z[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) z[e] = x[size_t(r) * K + k0 + e];
+  u4 w[NP];
+  split8(z, S, w);
+  const size_t psz = size_t(R) * K;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) *reinterpret_cast<u4*>(P + p * psz + size_t(r) * K + k0) = w[p];
+}
+
+// Transposed planes: input R x C (complex64 or, with DOUBLE_IN, complex128
+// rounded to complex64), output P[p][c][r] with row length ldr (rows r >= R
+// zero-filled up to ldr).
+template <bool DOUBLE_IN>
+__global__ void __launch_bounds__(256)
+k_split_t(const void* __restrict__ xv, int R, long C, long ldr, const unsigned int* __restrict__ mx,
+          unsigned short* __restrict__ P) {
+  __shared__ float2 T[64][65];
+  const long c0 = long(blockIdx.x) * 64;
+  const int r0 = blockIdx.y * 64;
+  const int tid = threadIdx.x;
+  const int S = scale_exp(*mx);
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int rr = e / 64, cc = e % 64;
+    float2 z = make_float2(0, 0);
+    if (r0 + rr < R && c0 + cc < C) {
+      if (DOUBLE_IN) {
+        double2 d = reinterpret_cast<const double2*>(xv)[size_t(r0 + rr) * C + c0 + cc];
+        z = make_float2(float(d.x), float(d.y));
+      } else {
+        z = reinterpret_cast<const float2*>(xv)[size_t(r0 + rr) * C + c0 + cc];
+      }
+    }
+    T[cc][rr] = z;
+  }
+  __syncthreads();
+  const size_t psz = size_t(C) * ldr;
+  for (int g = tid; g < 64 * 8; g += 256) {
+    const int cc = g / 8, rg = (g % 8) * 8;
+    if (c0 + cc >= C || r0 + rg >= ldr) continue;
+    float2 z[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) z[e] = T[cc][rg + e];
+    u4 w[NP];
+    split8(z, S, w);
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+      *reinterpret_cast<u4*>(P + p * psz + size_t(c0 + cc) * ldr + r0 + rg) = w[p];
+  }
+}
+
+// ------------------------------------------------------------------ products
+// part[((z*npair + pair)*split + s)][64*64] (FP64, unscaled) = the chunk-s
+// sum of conj(A) B^T over the lower tile pair; A, B0, B1 as planes
+// [p][m][k].  One-dimensional grid of split*npair*nz workgroups; with
+// split % 8 == 0, XCD x computes the chunks s = x mod 8, so that the tiles
+// of one chunk are shared through that XCD's L2.
+__global__ void __launch_bounds__(GT, 2)
+k_overlap_planes(const unsigned short* __restrict__ PA, const unsigned short* __restrict__ PB0,
+                 const unsigned short* __restrict__ PB1, const unsigned int* __restrict__ mxA,
+                 const unsigned int* __restrict__ mxB0, const unsigned int* __restrict__ mxB1,
+                 int m, long k, int npair, int split, int nz, double2* __restrict__ part) {
   __shared__ Tile sA, sB;
-  const int npair = gridDim.x;
-  const int pair = blockIdx.x, s = blockIdx.y, z = blockIdx.z;
-  const float2* B = z ? B1 : B0;
+  const int T = npair * nz;
+  const int w = blockIdx.x;
+  int s, r;
+  if (split % NXCD == 0) {
+    const int j = w / NXCD;
+    s = w % NXCD + NXCD * (j / T);
+    r = j % T;
+  } else {
+    s = w / T;
+    r = w % T;
+  }
+  const int pair = r / nz, z = r % nz;
+  const unsigned short* PB = z ? PB1 : PB0;
+  const int SAB = scale_exp(*mxA) + scale_exp(*(z ? mxB1 : mxB0));
   int ta, tb;
   tri_pair(pair, ta, tb);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const long nst = k / KB;
   const long c0 = nst * s / split, c1 = nst * (s + 1) / split;
-  // loader: thread -> (row = tid/4, 8 consecutive complex at (tid%4)*8)
-  const int lrow = tid >> 2, lk = (tid & 3) * 8;
-  const int ga = ta * TM + lrow, gb = tb * TM + lrow;
+  const size_t psz = size_t(m) * k;
   Acc32 acc;
   Acc64 tot;
   zero32(acc);
   zero64(tot);
   int nacc = 0;
+  Frag fa, fb;
+  if (c0 < c1) {
+    gload(fa, PA, psz, k, ta * TM, m, c0 * KB, tid);
+    gload(fb, PB, psz, k, tb * TM, m, c0 * KB, tid);
+  }
   for (long c = c0; c < c1; ++c) {
-    const long k0 = c * KB + lk;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      put(sA, lrow, lk + e, ga < m ? A[size_t(ga) * k + k0 + e] : make_float2(0, 0));
-      put(sB, lrow, lk + e, gb < m ? B[size_t(gb) * k + k0 + e] : make_float2(0, 0));
-    }
+    sstore(sA, fa, tid);
+    sstore(sB, fb, tid);
     __syncthreads();
+    if (c + 1 < c1) {
+      gload(fa, PA, psz, k, ta * TM, m, (c + 1) * KB, tid);
+      gload(fb, PB, psz, k, tb * TM, m, (c + 1) * KB, tid);
+    }
     step<true>(acc, sA, sB, wm, wn, lane);
     __syncthreads();
     if (++nacc == FLUSH) { fold(tot, acc); nacc = 0; }
@@ -212,40 +376,56 @@ k_overlap_lower_mixed(const float2* __restrict__ A, const float2* __restrict__ B
   fold(tot, acc);
   double2* out = part + (size_t(z) * npair + pair) * split * TM * TM + size_t(s) * TM * TM;
   foreach64(tot, wm, wn, lane, [&](int row, int col, double re, double im) {
-    out[row * TM + col] = make_double2(re, im);
+    out[row * TM + col] = make_double2(ldexp(re, -SAB), ldexp(im, -SAB));
   });
 }
 
-// Y[b][v] = sum_a U[a][b] X[a][v], X and Y complex64, U FP64 (m x m).
-__global__ void __launch_bounds__(GT)
-k_combine_mixed(const float2* __restrict__ X, const double2* __restrict__ U,
-                float2* __restrict__ Y, int m, long k) {
-  __shared__ Tile sA, sB;   // sA: [b][a], sB: [v][a]
-  const long v0 = long(blockIdx.x) * TM;
-  const int b0 = blockIdx.y * TM;
+// Y[b][v] = sum_a U[a][b] X[a][v] from the planes of U^T (rows b) and of X^T
+// (rows v), contraction length mpad (zero-padded), complex64 output.
+// One-dimensional grid of nv*nb workgroups (nv = k/64 column tiles, nb row
+// tiles); with nv % 8 == 0, XCD x computes the column tiles v = x mod 8, all
+// row tiles of one column tile in a row, so that each X^T tile is fetched
+// from HBM once.
+__global__ void __launch_bounds__(GT, 2)
+k_combine_planes(const unsigned short* __restrict__ PU, const unsigned short* __restrict__ PX,
+                 const unsigned int* __restrict__ mxU, const unsigned int* __restrict__ mxX,
+                 float2* __restrict__ Y, int m, long k, long mpad, int nb) {
+  __shared__ Tile sA, sB;
+  const long nv = k / TM;
+  const long w = blockIdx.x;
+  long vt;
+  int bt;
+  if (nv % NXCD == 0) {
+    const long j = w / NXCD;
+    vt = w % NXCD + NXCD * (j / nb);
+    bt = int(j % nb);
+  } else {
+    vt = w / nb;
+    bt = int(w % nb);
+  }
+  const long v0 = vt * TM;
+  const int b0 = bt * TM;
+  const int SUX = scale_exp(*mxU) + scale_exp(*mxX);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  // loader: thread -> (a within step = tid/8, 8 consecutive columns)
-  const int la = tid >> 3, lc = (tid & 7) * 8;
+  const size_t pszU = size_t(m) * mpad, pszX = size_t(k) * mpad;
+  const unsigned short* PXv = PX + size_t(v0) * mpad;
   Acc32 acc;
   Acc64 tot;
   zero32(acc);
   zero64(tot);
   int nacc = 0;
-  for (int a0 = 0; a0 < m; a0 += KB) {
-    const int a = a0 + la;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int b = b0 + lc + e;
-      float2 u = make_float2(0, 0);
-      if (a < m && b < m) {
-        double2 ud = U[size_t(a) * m + b];
-        u = make_float2(float(ud.x), float(ud.y));
-      }
-      put(sA, lc + e, la, u);
-      put(sB, lc + e, la, a < m ? X[size_t(a) * k + v0 + lc + e] : make_float2(0, 0));
-    }
+  Frag fa, fb;
+  gload(fa, PU, pszU, mpad, b0, m, 0, tid);
+  gload(fb, PXv, pszX, mpad, 0, TM, 0, tid);
+  for (long a0 = 0; a0 < mpad; a0 += KB) {
+    sstore(sA, fa, tid);
+    sstore(sB, fb, tid);
     __syncthreads();
+    if (a0 + KB < mpad) {
+      gload(fa, PU, pszU, mpad, b0, m, a0 + KB, tid);
+      gload(fb, PXv, pszX, mpad, 0, TM, a0 + KB, tid);
+    }
     step<false>(acc, sA, sB, wm, wn, lane);
     __syncthreads();
     if (++nacc == FLUSH) { fold(tot, acc); nacc = 0; }
@@ -253,18 +433,20 @@ k_combine_mixed(const float2* __restrict__ X, const double2* __restrict__ U,
   fold(tot, acc);
   foreach64(tot, wm, wn, lane, [&](int row, int col, double re, double im) {
     const int b = b0 + row;
-    if (b < m) Y[size_t(b) * k + v0 + col] = make_float2(float(re), float(im));
+    if (b < m) Y[size_t(b) * k + v0 + col] = make_float2(float(ldexp(re, -SUX)), float(ldexp(im, -SUX)));
   });
 }
 
 int overlap_split_mixed(int m, long k) {
   const int nt = (m + TM - 1) / TM;
   const int npair = nt * (nt + 1) / 2;
-  long nst = k / KB;
+  const long nst = k / KB;
   int split = (2048 + 2 * npair - 1) / (2 * npair);
-  if (split < 1) split = 1;
-  if (split > nst) split = int(nst);
   if (split > 64) split = 64;
+  if (split > nst) split = int(nst);
+  if (split < 1) split = 1;
+  // whole XCD rounds: a multiple of 8 chunks where the contraction allows
+  if (nst >= NXCD) split = split < NXCD ? NXCD : split - split % NXCD;
   return split;
 }
 }  // namespace
@@ -275,27 +457,68 @@ size_t overlap_scratch_bytes_mixed(int m, long k) {
   return size_t(overlap_split_mixed(m, k)) * 2 * npair * TM * TM * sizeof(double2);
 }
 
-void overlap_lower_mixed(const void* A, const void* B0, const void* B1, int m, long k,
-                         double scale, void* C0, void* C1, void* part, hipStream_t st,
-                         hipEvent_t* ev) {
+long planes_pad(int m) { return (long(m) + KB - 1) / KB * KB; }
+size_t planes_bytes_nt(int rows, long k) { return size_t(NP) * rows * k * 2; }
+size_t planes_bytes_t(int m, long cols) { return size_t(NP) * cols * planes_pad(m) * 2; }
+
+void plane_scale(const void* x, int x_is_c128, size_t n, unsigned int* mx, hipStream_t st) {
+  hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, st, mx, 1);
+  if (n == 0) return;
+  size_t nb = (n + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  if (x_is_c128)
+    hipLaunchKernelGGL(k_absmax<true>, dim3(unsigned(nb)), dim3(256), 0, st, x, n, mx);
+  else
+    hipLaunchKernelGGL(k_absmax<false>, dim3(unsigned(nb)), dim3(256), 0, st, x, n, mx);
+}
+
+void split_planes_nt(const void* x, int rows, long k, const unsigned int* mx, void* P,
+                     hipStream_t st) {
+  if (rows <= 0) return;
+  const size_t n = size_t(rows) * (k / 8);
+  hipLaunchKernelGGL(k_split_nt, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st,
+                     (const float2*)x, rows, k, mx, (unsigned short*)P);
+}
+
+void split_planes_t(const void* x, int x_is_c128, int rows, long cols, const unsigned int* mx,
+                    void* P, hipStream_t st) {
+  if (rows <= 0) return;
+  const long ldr = planes_pad(rows);
+  dim3 grid(unsigned((cols + 63) / 64), unsigned((ldr + 63) / 64));
+  if (x_is_c128)
+    hipLaunchKernelGGL((k_split_t<true>), grid, dim3(256), 0, st, x, rows, cols, ldr, mx,
+                       (unsigned short*)P);
+  else
+    hipLaunchKernelGGL((k_split_t<false>), grid, dim3(256), 0, st, x, rows, cols, ldr, mx,
+                       (unsigned short*)P);
+}
+
+void overlap_lower_planes(const void* PA, const void* PB0, const void* PB1,
+                          const unsigned int* mxA, const unsigned int* mxB0,
+                          const unsigned int* mxB1, int m, long k, double scale, void* C0,
+                          void* C1, void* part, hipStream_t st, hipEvent_t* ev) {
   if (m <= 0) return;
   const int nt = (m + TM - 1) / TM;
   const int npair = nt * (nt + 1) / 2;
   const int split = overlap_split_mixed(m, k);
-  const int nz = B1 ? 2 : 1;
+  const int nz = PB1 ? 2 : 1;
   if (ev) hipEventRecord(ev[0], st);
-  hipLaunchKernelGGL(k_overlap_lower_mixed, dim3(npair, split, nz), dim3(GT), 0, st,
-                     (const float2*)A, (const float2*)B0, (const float2*)B1, m, k, split,
-                     (double2*)part);
+  hipLaunchKernelGGL(k_overlap_planes, dim3(unsigned(split * npair * nz)), dim3(GT), 0, st,
+                     (const unsigned short*)PA, (const unsigned short*)PB0,
+                     (const unsigned short*)PB1, mxA, mxB0, PB1 ? mxB1 : mxB0, m, k, npair,
+                     split, nz, (double2*)part);
   if (ev) hipEventRecord(ev[1], st);
   overlap_reduce(part, npair, split, m, scale, C0, C1, nz, st);
 }
 
-void combine_mixed(const void* X, const void* U, void* Y, int m, long k, hipStream_t st) {
+void combine_planes(const void* PU, const void* PX, const unsigned int* mxU,
+                    const unsigned int* mxX, void* Y, int m, long k, hipStream_t st) {
   if (m <= 0) return;
-  dim3 grid(unsigned(k / TM), (m + TM - 1) / TM);
-  hipLaunchKernelGGL(k_combine_mixed, grid, dim3(GT), 0, st, (const float2*)X,
-                     (const double2*)U, (float2*)Y, m, k);
+  const int nb = (m + TM - 1) / TM;
+  const long nv = k / TM;
+  hipLaunchKernelGGL(k_combine_planes, dim3(unsigned(nv * nb)), dim3(GT), 0, st,
+                     (const unsigned short*)PU, (const unsigned short*)PX, mxU, mxX, (float2*)Y,
+                     m, k, planes_pad(m), nb);
 }
 
 }  // namespace sky

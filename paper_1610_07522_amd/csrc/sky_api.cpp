@@ -43,6 +43,7 @@ struct Layout {
   size_t psi32[2], hpsi32[2], phi32[2], hphi32[2];  // complex64 states (mixed only)
   size_t eps[2], r2[2], ritz[2], tiles;
   size_t matI, matH, matC, matL, matT, matHp, matZ, matU, wtmp, gemm_part, chol_work, jac_work;
+  size_t plA, plB, plT, plU, plS;                  // FP16 split planes, scales (mixed only)
   size_t dens[2], der[2], mf[2], vc, fscratch, dens_part, epart, energy, info;
   size_t total;
 };
@@ -94,6 +95,13 @@ Layout plan(const sky_box_desc& d) {
     if (mixed) gp = std::max(gp, overlap_scratch_bytes_mixed(std::max(1, nq[q]), long(V)));
   }
   L.gemm_part = take(gp);
+  // split planes of phi and h phi (rows = states), of phi^T and of U^T, shared
+  // by both species (one species is in flight at a time)
+  L.plA = take(mixed ? planes_bytes_nt(nmax, long(V)) : 0);
+  L.plB = take(mixed ? planes_bytes_nt(nmax, long(V)) : 0);
+  L.plT = take(mixed ? planes_bytes_t(nmax, long(V)) : 0);
+  L.plU = take(mixed ? planes_bytes_t(nmax, nmax) : 0);
+  L.plS = take(sizeof(unsigned int) * 4);   // largest |component| of phi, h phi, U
   L.chol_work = take(size_t((nmax + 63) / 64 + 1) * 64 * 64 * c16);
   L.jac_work = take(jacobi_scratch_bytes(nmax));
   for (int q = 0; q < 2; ++q) {
@@ -226,6 +234,17 @@ int rayleigh_ritz(sky_ctx* c, int q, const void* phi, const void* hphi, void* ps
   int* info = c->at<int>(c->lay.info);
   hipMemsetAsync(info, 0, sizeof(int), st);
   // step 3a: I and H, lower triangles, then mirrored
+  unsigned int* mx = c->at<unsigned int>(c->lay.plS);
+  if (c->prec) {
+    const int tp = t_begin(c, SKY_PHASE_SPLIT, q);
+    const size_t ne = size_t(m) * c->V;
+    plane_scale(phi, 0, ne, mx, st);
+    plane_scale(hphi, 0, ne, mx + 1, st);
+    split_planes_nt(phi, m, c->V, mx, c->at(c->lay.plA), st);
+    split_planes_nt(hphi, m, c->V, mx + 1, c->at(c->lay.plB), st);
+    split_planes_t(phi, 0, m, c->V, mx, c->at(c->lay.plT), st);
+    t_end(c, tp);
+  }
   int tm = -1;
   hipEvent_t ev[2];
   if (c->timing) {
@@ -234,8 +253,9 @@ int rayleigh_ritz(sky_ctx* c, int q, const void* phi, const void* hphi, void* ps
     ev[1] = c->marks[tm].b;
   }
   if (c->prec)
-    overlap_lower_mixed(phi, phi, hphi, m, c->V, c->g.dV, I, H, c->at(c->lay.gemm_part), st,
-                        c->timing ? ev : nullptr);
+    overlap_lower_planes(c->at(c->lay.plA), c->at(c->lay.plA), c->at(c->lay.plB), mx, mx, mx + 1,
+                         m, c->V, c->g.dV, I, H, c->at(c->lay.gemm_part), st,
+                         c->timing ? ev : nullptr);
   else
     overlap_lower(phi, phi, hphi, m, c->V, c->g.dV, I, H, c->at(c->lay.gemm_part), st,
                   c->timing ? ev : nullptr);
@@ -255,9 +275,14 @@ int rayleigh_ritz(sky_ctx* c, int q, const void* phi, const void* hphi, void* ps
   c->last_sweeps += jacobi_eigh(Hp, m, w, Z, c->at(c->lay.jac_work), JACOBI_TOL, JACOBI_SWEEPS, st);
   // steps 3d-3e: U = L^-H Z, psi = phi U
   gemm_square(Linv, 1, Z, 0, U, m, st);
+  if (c->prec) {
+    plane_scale(U, 1, size_t(m) * m, mx + 2, st);
+    split_planes_t(U, 1, m, m, mx + 2, c->at(c->lay.plU), st);
+  }
   t_end(c, ts);
   const int tc = t_begin(c, SKY_PHASE_COMBINE_GEMM, q);
-  if (c->prec) combine_mixed(phi, U, psi_out, m, c->V, st);
+  if (c->prec)
+    combine_planes(c->at(c->lay.plU), c->at(c->lay.plT), mx + 2, mx, psi_out, m, c->V, st);
   else combine(phi, U, psi_out, m, c->V, st);
   t_end(c, tc);
   return SKY_OK;
@@ -273,9 +298,14 @@ int loewdin(sky_ctx* c, int q, const void* phi, void* psi_out) {
   double* w = c->at<double>(c->lay.ritz[q]);
   int* info = c->at<int>(c->lay.info);
   hipMemsetAsync(info, 0, sizeof(int), st);
-  if (c->prec)
-    overlap_lower_mixed(phi, phi, nullptr, m, c->V, c->g.dV, I, nullptr, c->at(c->lay.gemm_part), st);
-  else
+  unsigned int* mx = c->at<unsigned int>(c->lay.plS);
+  if (c->prec) {
+    plane_scale(phi, 0, size_t(m) * c->V, mx, st);
+    split_planes_nt(phi, m, c->V, mx, c->at(c->lay.plA), st);
+    split_planes_t(phi, 0, m, c->V, mx, c->at(c->lay.plT), st);
+    overlap_lower_planes(c->at(c->lay.plA), c->at(c->lay.plA), nullptr, mx, mx, nullptr, m,
+                         c->V, c->g.dV, I, nullptr, c->at(c->lay.gemm_part), st);
+  } else
     overlap_lower(phi, phi, nullptr, m, c->V, c->g.dV, I, nullptr, c->at(c->lay.gemm_part), st);
   hermitian_fill(I, m, st);
   jacobi_eigh(I, m, w, X, c->at(c->lay.jac_work), JACOBI_TOL, JACOBI_SWEEPS, st);
@@ -288,8 +318,13 @@ int loewdin(sky_ctx* c, int q, const void* phi, void* psi_out) {
   gemm_square(c->at(c->lay.matT), 0, X, 1, C, m, st);
   int rc = check_info(c, "loewdin");
   if (rc) return rc;
-  if (c->prec) combine_mixed(phi, C, psi_out, m, c->V, st);
-  else combine(phi, C, psi_out, m, c->V, st);
+  if (c->prec) {
+    plane_scale(C, 1, size_t(m) * m, mx + 2, st);
+    split_planes_t(C, 1, m, m, mx + 2, c->at(c->lay.plU), st);
+    combine_planes(c->at(c->lay.plU), c->at(c->lay.plT), mx + 2, mx, psi_out, m, c->V, st);
+  } else {
+    combine(phi, C, psi_out, m, c->V, st);
+  }
   return SKY_OK;
 }
 

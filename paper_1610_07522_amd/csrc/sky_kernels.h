@@ -46,13 +46,31 @@ void overlap_lower(const void* A, const void* B0, const void* B1, int m, long k,
 // FP64 reduction of split-K partials into the lower tiles of C0 (and C1).
 void overlap_reduce(const void* part, int npair, int split, int m, double scale, void* C0,
                     void* C1, int nz, hipStream_t st);
-// Mixed precision (k_gemm_mixed.hip): complex64 operands, split-BF16 MFMA,
-// FP64 results for the overlap; complex64 output states for the combine.
+// Mixed precision (k_gemm_mixed.hip): complex64 operands split once into
+// FP16 planes (re h, re l, im h, im l; 8 bytes per complex) under a
+// power-of-two scale per matrix, FP16 MFMA with FP32 accumulation folded into
+// FP64.  plane_scale writes the bit pattern of the largest |component| of x
+// (n complex values) to *mx; the split and product calls read it there.
+// NT planes hold a rows x k matrix as [4][rows][k]; transposed planes of a
+// rows x cols matrix hold [4][cols][planes_pad(rows)] (zero-padded).
 size_t overlap_scratch_bytes_mixed(int m, long k);
-void overlap_lower_mixed(const void* A, const void* B0, const void* B1, int m, long k,
-                         double scale, void* C0, void* C1, void* part, hipStream_t st,
-                         hipEvent_t* ev = nullptr);
-void combine_mixed(const void* X, const void* U, void* Y, int m, long k, hipStream_t st);
+long planes_pad(int m);
+size_t planes_bytes_nt(int rows, long k);
+size_t planes_bytes_t(int m, long cols);
+void plane_scale(const void* x, int x_is_c128, size_t n, unsigned int* mx, hipStream_t st);
+void split_planes_nt(const void* x, int rows, long k, const unsigned int* mx, void* P,
+                     hipStream_t st);
+void split_planes_t(const void* x, int x_is_c128, int rows, long cols, const unsigned int* mx,
+                    void* P, hipStream_t st);
+// C0 = scale * conj(A) B0^T (and C1 with B1), lower 64-tiles, from NT planes.
+void overlap_lower_planes(const void* PA, const void* PB0, const void* PB1,
+                          const unsigned int* mxA, const unsigned int* mxB0,
+                          const unsigned int* mxB1, int m, long k, double scale, void* C0,
+                          void* C1, void* part, hipStream_t st, hipEvent_t* ev = nullptr);
+// Y[b][v] = sum_a U[a][b] X[a][v] from the transposed planes of U (m x m)
+// and of X (m x k).
+void combine_planes(const void* PU, const void* PX, const unsigned int* mxU,
+                    const unsigned int* mxX, void* Y, int m, long k, hipStream_t st);
 // Fill the upper triangle of Hermitian C from the lower one (and make the
 // diagonal real), in place.
 void hermitian_fill(void* C, int m, hipStream_t st);

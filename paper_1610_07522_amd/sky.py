@@ -36,7 +36,7 @@ EXPORTS = ("sky_workspace_size", "sky_create", "sky_init_box", "sky_apply_h",
            "sky_get_view", "sky_set_timing", "sky_get_timing", "sky_get_precision",
            "sky_sync", "sky_last_error", "sky_destroy")
 PHASES = ("apply_h", "damp", "overlap_gemm", "subspace", "combine_gemm", "densities",
-          "meanfield")
+          "meanfield", "split")
 
 
 class BoxDesc(ctypes.Structure):

@@ -1,13 +1,14 @@
-"""Mixed-precision form (complex64 states, FP32 FFT and h*psi, split-BF16
+"""Mixed-precision form (complex64 states, FP32 FFT and h*psi, split-FP16
 MFMA products with FP32 accumulation folded into FP64, FP64 subspace solve)
 against the FP64 oracle.
 
 The oracle gets the same complex64-rounded inputs, widened exactly to
 complex128, so each bar measures only the mixed arithmetic.  Bars derive from
 the FP32 unit roundoff u = 2^-24 ~ 6e-8:
-* split-BF16 products keep six of nine split terms (dropped terms O(u)) and
-  accumulate in FP32 over 256 elements before folding into FP64: relative
-  error a few u of the largest entry -> 1e-6;
+* split-FP16 products (x = h + l, |x - h - l| <= 2^-22 |x| = 4u|x| under
+  a power-of-two scale; h h' + h l' + l h', the dropped l l' <= 4u) accumulate
+  in FP32 over 256 elements before folding into FP64: relative error about
+  ten u of the largest entry -> 1e-6;
 * an FP32 spectral derivative loses ~log2(n) u -> h*psi, densities and the
   damped step within 2e-5 of their max-norm (two derivatives per direction,
   three directions, FP32 pointwise algebra);
