@@ -227,6 +227,8 @@ def main() -> int:
         h_phase_hbm=h_phase_hbm(timing, w, mixed),
         phases_ms_per_iter=phases,
         residual=reps[-1]["residual"], energy_per_a=reps[-1]["energy_per_a"],
+        eigensolver=dict(iters_per_step=[r["eig_iters"] for r in reps],
+                         jacobi_fallbacks=sum(r["eig_fallbacks"] for r in reps)),
     )
     if mixed and not args.no_fp64_compare:
         e64, t64, r64 = run(sky.SKY_FP64)

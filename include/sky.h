@@ -88,8 +88,12 @@ typedef struct {
                           /* entering the last iteration                        */
   double energy;          /* total energy after the last iteration, MeV         */
   double energy_per_a;    /* energy / (N + Z)                                   */
-  int32_t jacobi_sweeps;  /* eigensolver sweeps of the last iteration (n + p)   */
+  int32_t eig_iters;      /* subspace eigensolver iterations of the last        */
+                          /* iteration (n + p): refinement steps, or Jacobi     */
+                          /* sweeps where the refinement fell back              */
   int32_t precision;      /* precision of the states after the call             */
+  int32_t eig_fallbacks;  /* subspace eigensolves of this call that fell back   */
+                          /* from the refinement to the Jacobi solver           */
 } sky_report;
 
 /* Views into the context's device buffers (sky_get_view). */

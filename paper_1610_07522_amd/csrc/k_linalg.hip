@@ -12,12 +12,14 @@
 #include <vector>
 #include <algorithm>
 
+#include "jacobi_rot.h"
 #include "mfma_f64.h"
 #include "sky_kernels.h"
 
 namespace sky {
 
 namespace {
+using namespace jrot;
 constexpr int CB = 64;    // Cholesky block
 constexpr int JB = 16;    // Jacobi block (pair sub-problem = 2*JB)
 constexpr int JP = 2 * JB;
@@ -27,19 +29,6 @@ constexpr int RV = 64;              // rows of V per workgroup in the V update
 // tighter than the global one so that the ~(n/32)^2/2 converged pair blocks
 // together stay below the global off-diagonal bound.
 constexpr int JACOBI_INNER = 3;
-
-__device__ inline double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ inline double2 cmulc(double2 a, double2 b) {  // a * conj(b)
-  return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
-}
-__device__ inline double2 cconjmul(double2 a, double2 b) {  // conj(a) * b
-  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
-}
-__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ inline double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
 
 // ------------------------------------------------------------------ Cholesky
 // Factor the kw x kw diagonal block at (k0, k0) in LDS and invert it:
@@ -220,39 +209,6 @@ __global__ void k_zero(double* __restrict__ p, size_t n) {
 }
 
 // ------------------------------------------------------------------ Jacobi
-// Rotation of the 2x2 Hermitian [[a, r e^{i phi}], [r e^{-i phi}, b]]:
-// G = [[e^{i phi} c, e^{i phi} s], [-s, c]], G^H S G diagonal.
-struct Rot {
-  double c, s, er, ei;  // cos, sin, e^{i phi}
-};
-
-__device__ inline Rot make_rot(double a, double b, double2 apq) {
-  Rot g;
-  // |a_pq| by a scaled hypot: the plain sqrt(x^2 + y^2) underflows for the
-  // ~1e-160 couplings that quadratic convergence produces, which would give
-  // |e^{i phi}| != 1 and a non-unitary rotation.  Couplings below 1e-18 of
-  // the diagonal scale are treated as converged (no rotation).
-  const double r = hypot(apq.x, apq.y);
-  if (!(r > 1e-18 * (fabs(a) + fabs(b))) || r < 1e-250) {
-    g.c = 1.0; g.s = 0.0; g.er = 1.0; g.ei = 0.0;
-    return g;
-  }
-  g.er = apq.x / r;
-  g.ei = apq.y / r;
-  double zeta = (b - a) / (2.0 * r);
-  double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
-  g.c = 1.0 / sqrt(1.0 + t * t);
-  g.s = t * g.c;
-  return g;
-}
-
-// Round-robin partner pairs of round r among np players: pair i -> (p, q).
-__device__ inline void rr_pair(int np, int r, int i, int& p, int& q) {
-  const int n1 = np - 1;
-  p = (i == 0) ? 0 : ((i + r - 1) % n1) + 1;
-  q = ((n1 - i + r - 1) % n1) + 1;
-}
-
 // Diagonalise the 64x64 pair sub-matrix of blocks (P, Q) of A (ld = mp)
 // and write its unitary J (64x64, row-major, local index l < 32 -> block P).
 constexpr int JT = 256;    // threads of a pair sub-problem workgroup
@@ -611,6 +567,12 @@ int jacobi_eigh(void* Av, int m, double* w, void* Zv, void* work, double tol, in
   hipLaunchKernelGGL(k_jacobi_sort, dim3(m), dim3(256), 0, st, (const double2*)Ap,
                      (const double2*)V, m, mp, w, (double2*)Zv);
   return sweeps;
+}
+
+void eig_sort(const void* D, const void* V, int m, int ld, double* w, void* Z, hipStream_t st) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_jacobi_sort, dim3(m), dim3(256), 0, st, (const double2*)D, (const double2*)V,
+                     m, ld, w, (double2*)Z);
 }
 
 void scale_columns(void* X, const double* d, int m, hipStream_t st) {

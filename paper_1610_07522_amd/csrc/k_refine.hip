@@ -1,0 +1,572 @@
+// Hermitian eigensolver of the subspace Hamiltonian by eigenvector
+// refinement (Sec. 3.3.2, step 3b: H' = Z Lambda Z^H).
+//
+// After the first iterations of the damped-gradient method the orthonormalised
+// subspace Hamiltonian H' is close to diagonal: the previous states were its
+// Ritz vectors, and one damped step couples them only weakly.  Its spectrum
+// is full of (near-)degenerate multiplets, but the multiplets are small.  The
+// solver refines X (start X = 1) towards X^H X = 1, X^H H' X = diagonal with a
+// Newton-type update on FP64 matrix cores:
+//
+//   R = 1 - X^H X,  S = X^H H' X (both symmetrised),
+//   lam_i = Re S_ii / (1 - Re R_ii);
+//   sort by lam; cut the sorted order into contiguous clusters so that every
+//   pair (i, j) in different clusters is weakly coupled,
+//   |S_ij + lam R_ij| <= THETA |lam_j - lam_i| (both orientations);
+//   diagonalise each cluster block of (1 + R/2) S (1 + R/2) exactly (cyclic
+//   Jacobi in one workgroup, unitary W_c; B = blockdiag(W_c) in sorted order);
+//   in the rotated basis (S2 = B^H S B, R2 = B^H R B, lam2 from its diagonal)
+//   E_ab = (S2_ab + lam2_b R2_ab) / (lam2_b - lam2_a) across clusters,
+//   E_ab = R2_ab / 2 inside a cluster and for couplings at the rounding floor;
+//   X <- X P B (1 + E + E^2 / 2)   (P: sorted -> original order).
+//
+// The cross-cluster part of E is the first-order eigenvector correction and
+// the in-cluster part the first-order orthonormality correction; the E^2/2
+// term makes the update unitary to second order, so that the off-diagonal
+// norm and the orthonormality defect fall quadratically.  Convergence: the
+// relative off-diagonal Frobenius norm of S below tol and max |R_ij| below
+// ORTH_TOL.  A cluster wider than KMAX, a non-finite value or no convergence
+// within the iteration limit returns a failure, and the caller falls back to
+// the blocked Jacobi solver.
+#include <algorithm>
+#include <cmath>
+
+#include "jacobi_rot.h"
+#include "sky_kernels.h"
+
+namespace sky {
+
+namespace {
+using namespace jrot;
+
+constexpr int KMAX = 32;            // widest cluster diagonalised in one workgroup
+constexpr double THETA = 0.03;      // weak-coupling ratio |coupling| / |gap|
+constexpr double ORTH_TOL = 1e-13;  // max |(X^H X - 1)_ij| at convergence
+constexpr double E_CLAMP = 0.25;    // bound on one update coefficient
+constexpr double NOISE_ULPS = 8.0;   // coupling floor, in ulps of the rms eigenvalue
+constexpr int CHECK_BLOCKS = 256;
+
+// lam[i] = Re S_ii / (1 - Re R_ii)  (R may be null: R = 0)
+__global__ void k_ref_lambda(const double2* __restrict__ S, const double2* __restrict__ R, int m,
+                             double* __restrict__ lam) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const double r = R ? R[size_t(i) * m + i].x : 0.0;
+  lam[i] = S[size_t(i) * m + i].x / (1.0 - r);
+}
+
+// rank[i] = position of i in ascending (lam, index) order; order[rank] = i.
+__global__ void k_ref_rank(const double* __restrict__ lam, int m, int* __restrict__ rank,
+                           int* __restrict__ order) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const double li = lam[i];
+  int r = 0;
+  for (int j = 0; j < m; ++j) {
+    const double lj = lam[j];
+    r += (lj < li || (lj == li && j < i)) ? 1 : 0;
+  }
+  rank[i] = r;
+  order[r] = i;
+}
+
+// reach[rank[i]] = largest sorted position strongly coupled to i (or its own).
+__global__ void __launch_bounds__(256)
+k_ref_reach(const double2* __restrict__ S, const double2* __restrict__ R, const double* __restrict__ lam,
+            const int* __restrict__ rank, int m, double theta, int* __restrict__ reach) {
+  const int i = blockIdx.x;
+  const double li = lam[i];
+  const int ri = rank[i];
+  int best = ri;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    const int rj = rank[j];
+    if (rj <= best) continue;
+    const double lj = lam[j];
+    const double2 s = S[size_t(i) * m + j];
+    const double2 r = R ? R[size_t(i) * m + j] : make_double2(0.0, 0.0);
+    const double g1 = hypot(s.x + lj * r.x, s.y + lj * r.y);
+    const double g2 = hypot(s.x + li * r.x, s.y + li * r.y);
+    if (fmax(g1, g2) > theta * fabs(lj - li)) best = rj;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) best = max(best, __shfl_xor(best, o));
+  __shared__ int wb[4];
+  if ((threadIdx.x & 63) == 0) wb[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) reach[ri] = max(max(wb[0], wb[1]), max(wb[2], wb[3]));
+}
+
+// Contiguous clusters of sorted positions: a cut after position a when no
+// strong coupling crosses it (prefix max of reach == a).  Per position:
+// cstart (first position of its cluster), csize, cslot (index into the
+// cluster list, -1 for singletons).  The list holds (start, size) of every
+// cluster of two to KMAX positions; info[0] = list length, info[1] = widest
+// cluster found.
+// One workgroup of 1024 threads, chunked scans; pm (m ints) holds the
+// prefix maximum.
+__global__ void __launch_bounds__(1024)
+k_ref_clusters(const int* __restrict__ reach, int m, int* __restrict__ pm, int* __restrict__ cstart,
+               int* __restrict__ csize, int* __restrict__ cslot, int2* __restrict__ clist,
+               int* __restrict__ info) {
+  __shared__ int tmax[1024], tcut[1024];
+  __shared__ int ncl, widest;
+  const int t = threadIdx.x, T = blockDim.x;
+  const int chunk = (m + T - 1) / T;
+  const int a0 = min(m, t * chunk), a1 = min(m, a0 + chunk);
+  if (t == 0) { ncl = 0; widest = 1; }
+  // pass 1: chunk prefix max of reach
+  int mx = -1;
+  for (int a = a0; a < a1; ++a) mx = max(mx, reach[a]);
+  tmax[t] = mx;
+  __syncthreads();
+  if (t == 0)
+    for (int u = 1; u < T; ++u) tmax[u] = max(tmax[u], tmax[u - 1]);
+  __syncthreads();
+  // pass 2: cuts; last cut before each chunk
+  int run = t ? tmax[t - 1] : -1;
+  int lastcut = -1;
+  for (int a = a0; a < a1; ++a) {
+    run = max(run, reach[a]);
+    if (run == a) lastcut = a;
+    pm[a] = run;
+  }
+  tcut[t] = lastcut;
+  __syncthreads();
+  if (t == 0)
+    for (int u = 1; u < T; ++u) tcut[u] = max(tcut[u], tcut[u - 1]);
+  __syncthreads();
+  // pass 3: start of each position's cluster = last cut before it + 1
+  int prevcut = t ? tcut[t - 1] : -1;
+  for (int a = a0; a < a1; ++a) {
+    const bool cut = pm[a] == a;
+    const int st = prevcut + 1;
+    if (cut) {
+      const int k = a - st + 1;
+      atomicMax(&widest, k);
+      if (k > 1 && k <= KMAX) {
+        const int slot = atomicAdd(&ncl, 1);
+        clist[slot] = make_int2(st, k);
+        for (int b = st; b <= a; ++b) {
+          cstart[b] = st;
+          csize[b] = k;
+          cslot[b] = slot;
+        }
+      } else {
+        // singletons; a cluster wider than KMAX is only reported (info[1]),
+        // its members stay singletons so every later access stays in bounds
+        for (int b = st; b <= a; ++b) {
+          cstart[b] = b;
+          csize[b] = 1;
+          cslot[b] = -1;
+        }
+      }
+      prevcut = a;
+    }
+  }
+  __syncthreads();
+  if (t == 0) { info[0] = ncl; info[1] = widest; }
+}
+
+// W[c] (KMAX x KMAX, leading k x k block used) diagonalises the Hermitian
+// part of S on cluster c (rows and columns order[start .. start+k)), taken in
+// the first-order orthonormalised basis (1 + R/2): for an exactly degenerate
+// multiplet the metric defect lam R would otherwise decide the rotation.
+// Together with the in-cluster update term R/2 the transform of the cluster
+// is (1 + R/2) W.  Cyclic Jacobi in LDS, round-robin ordering, the same
+// rotations as the blocked solver's pair sub-problems.
+__global__ void __launch_bounds__(256)
+k_ref_cluster_eig(const double2* __restrict__ S, const double2* __restrict__ R, int m,
+                  const int* __restrict__ order, const int2* __restrict__ clist,
+                  const int* __restrict__ info, double2* __restrict__ W, double tol) {
+  const int c = blockIdx.x;
+  if (c >= info[0]) return;
+  const int2 cs = clist[c];
+  const int k = cs.y;
+  if (k > KMAX) return;   // reported through info[1]; the caller falls back
+  const int np = (k + 1) & ~1, nh = np / 2;
+  __shared__ double2 M[KMAX][KMAX + 1];
+  __shared__ double2 J[KMAX][KMAX + 1];
+  __shared__ double2 P[KMAX][KMAX + 1];
+  __shared__ Rot rot[KMAX / 2];
+  __shared__ int idx[KMAX];
+  __shared__ double red[4][2];
+  __shared__ int done;
+  const int tid = threadIdx.x;
+  if (tid < k) idx[tid] = order[cs.x + tid];
+  __syncthreads();
+  for (int e = tid; e < np * np; e += blockDim.x) {
+    const int i = e / np, j = e % np;
+    double2 v = make_double2(0.0, 0.0), rv = make_double2(0.0, 0.0);
+    if (i < k && j < k) {
+      const double2 a = S[size_t(idx[i]) * m + idx[j]], b = S[size_t(idx[j]) * m + idx[i]];
+      v = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+      if (R) {
+        const double2 c = R[size_t(idx[i]) * m + idx[j]], d = R[size_t(idx[j]) * m + idx[i]];
+        rv = make_double2(0.5 * (c.x + d.x), 0.5 * (c.y - d.y));
+      }
+    }
+    M[i][j] = v;
+    J[i][j] = rv;
+  }
+  __syncthreads();
+  if (R) {
+    // first-order Loewdin: M <- (1 + R/2) M (1 + R/2), the cluster block in
+    // the orthonormalised basis (R is the metric defect 1 - X^H X there)
+    for (int e = tid; e < np * np; e += blockDim.x) {
+      const int i = e / np, j = e % np;
+      double2 acc = M[i][j];
+      for (int l = 0; l < np; ++l) acc = cadd(acc, cscale(0.5, cmul(M[i][l], J[l][j])));
+      P[i][j] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < np * np; e += blockDim.x) {
+      const int i = e / np, j = e % np;
+      double2 acc = P[i][j];
+      for (int l = 0; l < np; ++l) acc = cadd(acc, cscale(0.5, cmul(J[i][l], P[l][j])));
+      M[i][j] = acc;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < np * np; e += blockDim.x) {
+    const int i = e / np, j = e % np;
+    J[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int e = tid; e < np * np; e += blockDim.x) {
+      const int i = e / np, j = e % np;
+      const double v = M[i][j].x * M[i][j].x + M[i][j].y * M[i][j].y;
+      if (i == j) dia += v; else off += v;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_down(off, o, 64);
+      dia += __shfl_down(dia, o, 64);
+    }
+    if ((tid & 63) == 0) { red[tid >> 6][0] = off; red[tid >> 6][1] = dia; }
+    __syncthreads();
+    if (tid == 0) {
+      const double o = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+      const double d = red[0][1] + red[1][1] + red[2][1] + red[3][1];
+      done = (o <= tol * tol * d) || (o < 1e-300);
+    }
+    __syncthreads();
+    if (done) break;
+    for (int r = 0; r < np - 1; ++r) {
+      if (tid < nh) {
+        int p, q;
+        rr_pair(np, r, tid, p, q);
+        if (p > q) { const int t = p; p = q; q = t; }
+        rot[tid] = make_rot(M[p][p].x, M[q][q].x, M[p][q]);
+      }
+      __syncthreads();
+      // M <- G^H M G on the 2x2 blocks (rotation u rows, rotation v columns)
+      for (int e = tid; e < nh * nh; e += blockDim.x) {
+        const int u = e / nh, v = e % nh;
+        int pu, qu, pv, qv;
+        rr_pair(np, r, u, pu, qu);
+        rr_pair(np, r, v, pv, qv);
+        if (pu > qu) { const int t = pu; pu = qu; qu = t; }
+        if (pv > qv) { const int t = pv; pv = qv; qv = t; }
+        const Rot gu = rot[u], gv = rot[v];
+        const double2 epu = make_double2(gu.er, gu.ei), epv = make_double2(gv.er, gv.ei);
+        const double2 x00 = M[pu][pv], x01 = M[pu][qv], x10 = M[qu][pv], x11 = M[qu][qv];
+        const double2 y00 = csub(cscale(gv.c, cmul(x00, epv)), cscale(gv.s, x01));
+        const double2 y01 = cadd(cscale(gv.s, cmul(x00, epv)), cscale(gv.c, x01));
+        const double2 y10 = csub(cscale(gv.c, cmul(x10, epv)), cscale(gv.s, x11));
+        const double2 y11 = cadd(cscale(gv.s, cmul(x10, epv)), cscale(gv.c, x11));
+        M[pu][pv] = csub(cscale(gu.c, cmulc(y00, epu)), cscale(gu.s, y10));
+        M[pu][qv] = csub(cscale(gu.c, cmulc(y01, epu)), cscale(gu.s, y11));
+        M[qu][pv] = cadd(cscale(gu.s, cmulc(y00, epu)), cscale(gu.c, y10));
+        M[qu][qv] = cadd(cscale(gu.s, cmulc(y01, epu)), cscale(gu.c, y11));
+      }
+      // J <- J G
+      for (int e = tid; e < np * nh; e += blockDim.x) {
+        const int i = e / nh, v = e % nh;
+        int pv, qv;
+        rr_pair(np, r, v, pv, qv);
+        if (pv > qv) { const int t = pv; pv = qv; qv = t; }
+        const Rot gv = rot[v];
+        const double2 epv = make_double2(gv.er, gv.ei);
+        const double2 x0 = J[i][pv], x1 = J[i][qv];
+        J[i][pv] = csub(cscale(gv.c, cmul(x0, epv)), cscale(gv.s, x1));
+        J[i][qv] = cadd(cscale(gv.s, cmul(x0, epv)), cscale(gv.c, x1));
+      }
+      __syncthreads();
+    }
+  }
+  double2* out = W + size_t(c) * KMAX * KMAX;
+  for (int e = tid; e < k * k; e += blockDim.x) out[(e / k) * KMAX + e % k] = J[e / k][e % k];
+}
+
+// sum_{s<ka, u<kb} conj(Wa[s][ta]) M[order[sa+s]][order[sb+u]] Wb[u][tb]
+// (a null W is the 1x1 identity of a singleton).
+__device__ inline double2 sandwich(const double2* __restrict__ M, int m, const int* __restrict__ order,
+                                   const double2* Wa, int sa, int ka, int ta,
+                                   const double2* Wb, int sb, int kb, int tb) {
+  double2 tot = make_double2(0.0, 0.0);
+  for (int s = 0; s < ka; ++s) {
+    const double2* row = M + size_t(order[sa + s]) * m;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int u = 0; u < kb; ++u) {
+      const double2 x = row[order[sb + u]];
+      acc = cadd(acc, Wb ? cmul(x, Wb[u * KMAX + tb]) : x);
+    }
+    tot = cadd(tot, Wa ? cconjmul(Wa[s * KMAX + ta], acc) : acc);
+  }
+  return tot;
+}
+
+struct Clusters {
+  const int *order, *cstart, *csize, *cslot;
+  const double2* W;
+  __device__ const double2* w(int a) const {
+    return cslot[a] >= 0 ? W + size_t(cslot[a]) * KMAX * KMAX : nullptr;
+  }
+};
+
+// lam2[a] = Re S2_aa / (1 - Re R2_aa) in the cluster-rotated sorted basis.
+__global__ void k_ref_lambda2(const double2* __restrict__ S, const double2* __restrict__ R, int m,
+                              Clusters cl, double* __restrict__ lam2) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= m) return;
+  const int s0 = cl.cstart[a], k = cl.csize[a];
+  const double2* Wa = cl.w(a);
+  const double s2 = sandwich(S, m, cl.order, Wa, s0, k, a - s0, Wa, s0, k, a - s0).x;
+  const double r2 = R ? sandwich(R, m, cl.order, Wa, s0, k, a - s0, Wa, s0, k, a - s0).x : 0.0;
+  lam2[a] = s2 / (1.0 - r2);
+}
+
+// E in the cluster-rotated sorted basis (m x m, row a, column b).  A pair of
+// different clusters whose coupling (both orientations) is at the rounding
+// floor tau of the products is converged: it gets the orthonormality term
+// only.  (Its first-order coefficient would be rounding noise over a gap
+// that can itself be at rounding level, e.g. an exact Kramers pair, and would
+// rotate the pair at random by up to THETA on every step.)
+__global__ void __launch_bounds__(256)
+k_ref_update(const double2* __restrict__ S, const double2* __restrict__ R, int m, Clusters cl,
+             const double* __restrict__ lam2, double tau, double2* __restrict__ E) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = blockIdx.y;
+  if (b >= m) return;
+  const int sa = cl.cstart[a], ka = cl.csize[a], sb = cl.cstart[b], kb = cl.csize[b];
+  const double2 *Wa = cl.w(a), *Wb = cl.w(b);
+  double2 e = make_double2(0.0, 0.0);
+  if (sa == sb) {
+    if (R) e = cscale(0.5, sandwich(R, m, cl.order, Wa, sa, ka, a - sa, Wb, sb, kb, b - sb));
+  } else {
+    const double2 s2 = sandwich(S, m, cl.order, Wa, sa, ka, a - sa, Wb, sb, kb, b - sb);
+    const double2 r2 = R ? sandwich(R, m, cl.order, Wa, sa, ka, a - sa, Wb, sb, kb, b - sb)
+                         : make_double2(0.0, 0.0);
+    const double2 gb = cadd(s2, cscale(lam2[b], r2)), ga = cadd(s2, cscale(lam2[a], r2));
+    const double den = lam2[b] - lam2[a];
+    if (fmax(hypot(gb.x, gb.y), hypot(ga.x, ga.y)) <= tau) {
+      e = cscale(0.5, r2);   // coupling at the rounding floor: orthonormality only
+    } else if (den != 0.0) {
+      e = cscale(1.0 / den, gb);
+      const double mag = hypot(e.x, e.y);
+      if (mag > E_CLAMP) e = cscale(E_CLAMP / mag, e);
+    }
+  }
+  E[size_t(a) * m + b] = e;
+}
+
+// Q[order[s]][b] = sum_{t in cluster(s)} W[s - c][t - c] (delta_tb + E_tb + E2_tb / 2)
+__global__ void __launch_bounds__(256)
+k_ref_build_q(const double2* __restrict__ E, const double2* __restrict__ E2, int m, Clusters cl,
+              double2* __restrict__ Q) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (b >= m) return;
+  const int c = cl.cstart[s], k = cl.csize[s];
+  const double2* Wc = cl.w(s);
+  double2 acc = make_double2(0.0, 0.0);
+  for (int t = 0; t < k; ++t) {
+    const size_t at = size_t(c + t) * m + b;
+    double2 q = cadd(E[at], cscale(0.5, E2[at]));
+    if (c + t == b) q.x += 1.0;
+    acc = cadd(acc, Wc ? cmul(Wc[(s - c) * KMAX + t], q) : q);
+  }
+  Q[size_t(cl.order[s]) * m + b] = acc;
+}
+
+// S <- (S + S^H) / 2 and R <- 1 - (G + G^H) / 2 in place (R holds G = X^H X
+// on entry), with per-block partial norms: off-diagonal and diagonal
+// Frobenius squares of S, max |R_ij|.  The products are Hermitian only up to
+// rounding, and the update divides the anti-Hermitian part by eigenvalue
+// gaps: without the symmetrisation it stalls the orthonormality near 1e-11.
+__global__ void __launch_bounds__(256)
+k_ref_check(double2* __restrict__ S, double2* __restrict__ R, int m, double* __restrict__ part) {
+  double off = 0.0, dia = 0.0, rmax = 0.0;
+  const size_t n = size_t(m) * m;
+  for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+       e += size_t(gridDim.x) * blockDim.x) {
+    const int i = int(e / m), j = int(e % m);
+    if (i < j) continue;
+    double rg;
+    if (i == j) {
+      const double sd = S[e].x;
+      S[e] = make_double2(sd, 0.0);
+      dia += sd * sd;
+      const double r = 1.0 - R[e].x;
+      R[e] = make_double2(r, 0.0);
+      rg = fabs(r);
+    } else {
+      const size_t et = size_t(j) * m + i;
+      const double2 a = S[e], b = S[et];
+      const double2 sv = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+      S[e] = sv;
+      S[et] = make_double2(sv.x, -sv.y);
+      off += 2.0 * (sv.x * sv.x + sv.y * sv.y);
+      const double2 ga = R[e], gb = R[et];
+      const double2 r = make_double2(-0.5 * (ga.x + gb.x), -0.5 * (ga.y - gb.y));
+      R[e] = r;
+      R[et] = make_double2(r.x, -r.y);
+      rg = hypot(r.x, r.y);
+    }
+    rmax = (rg > rmax || rg != rg) ? rg : rmax;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    off += __shfl_down(off, o, 64);
+    dia += __shfl_down(dia, o, 64);
+    const double t = __shfl_down(rmax, o, 64);
+    rmax = (t > rmax || t != t) ? t : rmax;
+  }
+  __shared__ double red[4][3];
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6][0] = off;
+    red[threadIdx.x >> 6][1] = dia;
+    red[threadIdx.x >> 6][2] = rmax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double o = 0.0, d = 0.0, r = 0.0;
+    for (int w = 0; w < 4; ++w) {
+      o += red[w][0];
+      d += red[w][1];
+      r = (red[w][2] > r || red[w][2] != red[w][2]) ? red[w][2] : r;
+    }
+    part[3 * blockIdx.x] = o;
+    part[3 * blockIdx.x + 1] = d;
+    part[3 * blockIdx.x + 2] = r;
+  }
+}
+
+__global__ void k_ref_check_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  if (threadIdx.x) return;
+  double o = 0.0, d = 0.0, r = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    o += part[3 * b];
+    d += part[3 * b + 1];
+    r = (part[3 * b + 2] > r || part[3 * b + 2] != part[3 * b + 2]) ? part[3 * b + 2] : r;
+  }
+  out[0] = o;
+  out[1] = d;
+  out[2] = r;
+}
+
+struct RefineWork {
+  double2 *mat[7], *W;
+  double *lam, *lam2, *part, *norms;
+  int *rank, *order, *reach, *pm, *cstart, *csize, *cslot, *info;
+  int2* clist;
+};
+
+size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
+RefineWork carve(void* work, int m) {
+  RefineWork r;
+  char* p = static_cast<char*>(work);
+  const size_t mm = al256(size_t(m) * m * sizeof(double2));
+  for (int i = 0; i < 7; ++i) { r.mat[i] = reinterpret_cast<double2*>(p); p += mm; }
+  r.W = reinterpret_cast<double2*>(p);
+  p += al256(size_t(m / 2 + 1) * KMAX * KMAX * sizeof(double2));
+  auto dbl = [&](size_t n) { double* q = reinterpret_cast<double*>(p); p += al256(n * sizeof(double)); return q; };
+  auto in = [&](size_t n) { int* q = reinterpret_cast<int*>(p); p += al256(n * sizeof(int)); return q; };
+  r.lam = dbl(m);
+  r.lam2 = dbl(m);
+  r.part = dbl(3 * CHECK_BLOCKS);
+  r.norms = dbl(4);
+  r.rank = in(m);
+  r.order = in(m);
+  r.reach = in(m);
+  r.pm = in(m);
+  r.cstart = in(m);
+  r.csize = in(m);
+  r.cslot = in(m);
+  r.info = in(4);
+  r.clist = reinterpret_cast<int2*>(p);
+  p += al256(size_t(m) * sizeof(int2));
+  return r;
+}
+}  // namespace
+
+size_t refine_scratch_bytes(int m) {
+  RefineWork r = carve(nullptr, m);
+  return size_t(reinterpret_cast<char*>(r.clist)) + al256(size_t(m) * sizeof(int2));
+}
+
+int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double tol, int maxit,
+                hipStream_t st) {
+  if (m <= 0) return 0;
+  RefineWork r = carve(work, m);
+  const double2* A = static_cast<const double2*>(Av);
+  double2 *X = r.mat[0], *Xn = r.mat[1], *Q = r.mat[2], *T = r.mat[3], *S = r.mat[4],
+          *R = r.mat[5], *E = r.mat[6];
+  const unsigned gm = unsigned((m + 255) / 256);
+  const size_t mm = size_t(m) * m;
+  const unsigned ncheck = unsigned(std::min<size_t>(CHECK_BLOCKS, (mm + 255) / 256));
+  Clusters cl{r.order, r.cstart, r.csize, r.cslot, r.W};
+  for (int it = 0;; ++it) {
+    const double2* Sp = A;
+    const double2* Rp = nullptr;
+    double tau = 0.0;
+    if (it > 0) {
+      gemm_square(X, 1, X, 0, R, m, st);
+      gemm_square(A, 0, X, 0, T, m, st);
+      gemm_square(X, 1, T, 0, S, m, st);
+      hipLaunchKernelGGL(k_ref_check, dim3(ncheck), dim3(256), 0, st, S, R, m, r.part);
+      hipLaunchKernelGGL(k_ref_check_final, dim3(1), dim3(64), 0, st, (const double*)r.part,
+                         int(ncheck), r.norms);
+      double h[3];
+      int hi[2];
+      hipMemcpyAsync(h, r.norms, sizeof(h), hipMemcpyDeviceToHost, st);
+      hipMemcpyAsync(hi, r.info, sizeof(hi), hipMemcpyDeviceToHost, st);
+      hipStreamSynchronize(st);
+      if (!(h[0] == h[0]) || !(h[1] == h[1]) || !(h[2] == h[2]) || hi[1] > KMAX) return -1;
+      if ((h[0] <= tol * tol * h[1] || h[0] < 1e-300) && h[2] <= ORTH_TOL) {
+        eig_sort(S, X, m, m, w, Z, st);
+        return it;
+      }
+      if (it >= maxit) return -1;
+      Sp = S;
+      Rp = R;
+      // rounding floor of the FP64 products: a few ulps of the rms eigenvalue
+      tau = NOISE_ULPS * 0x1p-52 * sqrt(h[1] / m);
+    }
+    hipLaunchKernelGGL(k_ref_lambda, dim3(gm), dim3(256), 0, st, Sp, Rp, m, r.lam);
+    hipLaunchKernelGGL(k_ref_rank, dim3(gm), dim3(256), 0, st, (const double*)r.lam, m, r.rank, r.order);
+    hipLaunchKernelGGL(k_ref_reach, dim3(m), dim3(256), 0, st, Sp, Rp, (const double*)r.lam,
+                       (const int*)r.rank, m, THETA, r.reach);
+    hipLaunchKernelGGL(k_ref_clusters, dim3(1), dim3(1024), 0, st, (const int*)r.reach, m, r.pm,
+                       r.cstart, r.csize, r.cslot, r.clist, r.info);
+    hipLaunchKernelGGL(k_ref_cluster_eig, dim3(unsigned(m / 2 + 1)), dim3(256), 0, st, Sp, Rp, m,
+                       (const int*)r.order, (const int2*)r.clist, (const int*)r.info, r.W, tol * 1e-2);
+    hipLaunchKernelGGL(k_ref_lambda2, dim3(gm), dim3(256), 0, st, Sp, Rp, m, cl, r.lam2);
+    hipLaunchKernelGGL(k_ref_update, dim3(gm, unsigned(m)), dim3(256), 0, st, Sp, Rp, m, cl,
+                       (const double*)r.lam2, tau, E);
+    gemm_square(E, 0, E, 0, T, m, st);
+    hipLaunchKernelGGL(k_ref_build_q, dim3(gm, unsigned(m)), dim3(256), 0, st, (const double2*)E,
+                       (const double2*)T, m, cl, Q);
+    if (it == 0) {
+      std::swap(X, Q);
+    } else {
+      gemm_square(X, 0, Q, 0, Xn, m, st);
+      std::swap(X, Xn);
+    }
+  }
+}
+
+}  // namespace sky

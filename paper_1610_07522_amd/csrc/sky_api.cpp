@@ -36,6 +36,7 @@ size_t al(size_t b) { return (b + ALIGN - 1) / ALIGN * ALIGN; }
 constexpr int DENS_CHUNKS = 32;   // state chunks of the density passes
 constexpr double JACOBI_TOL = 1e-12;   // relative off-diagonal Frobenius norm
 constexpr int JACOBI_SWEEPS = 30;
+constexpr int REFINE_ITERS = 10;     // refinement steps before the Jacobi fallback
 
 // Byte offsets of every buffer inside the caller's workspace.
 struct Layout {
@@ -43,6 +44,7 @@ struct Layout {
   size_t psi32[2], hpsi32[2], phi32[2], hphi32[2];  // complex64 states (mixed only)
   size_t eps[2], r2[2], ritz[2], tiles;
   size_t matI, matH, matC, matL, matT, matHp, matZ, matU, wtmp, gemm_part, chol_work, jac_work;
+  size_t ref_work;
   size_t plA, plB, plT, plU, plS;                  // FP16 split planes, scales (mixed only)
   size_t dens[2], der[2], mf[2], vc, fscratch, dens_part, epart, energy, info;
   size_t total;
@@ -104,6 +106,7 @@ Layout plan(const sky_box_desc& d) {
   L.plS = take(sizeof(unsigned int) * 4);   // largest |component| of phi, h phi, U
   L.chol_work = take(size_t((nmax + 63) / 64 + 1) * 64 * 64 * c16);
   L.jac_work = take(jacobi_scratch_bytes(nmax));
+  L.ref_work = take(refine_scratch_bytes(nmax));
   for (int q = 0; q < 2; ++q) {
     L.dens[q] = take(sizeof(double) * 11 * n3);
     L.der[q] = take(sizeof(double) * 5 * n3);
@@ -145,7 +148,8 @@ struct sky_ctx {
   int prec;            // current: 0 = FP64 states, 1 = mixed (complex64 states)
   GridArgs g;
   Skyrme sk;
-  int last_sweeps;
+  int last_sweeps;     // eigensolver iterations of the last iteration
+  int fallbacks;       // refinement -> Jacobi fallbacks in the current call
   int64_t iter_count = 0;     // iterations run on this context
   int64_t switched_at = -1;   // iteration after which the ladder switched to FP64
   // phase timing: HIP event pairs on the context stream
@@ -272,7 +276,12 @@ int rayleigh_ritz(sky_ctx* c, int q, const void* phi, const void* hphi, void* ps
   int rc = check_info(c, "cholesky");
   if (rc) return rc;
   double* w = ritz ? ritz : c->at<double>(c->lay.ritz[q]);
-  c->last_sweeps += jacobi_eigh(Hp, m, w, Z, c->at(c->lay.jac_work), JACOBI_TOL, JACOBI_SWEEPS, st);
+  int its = refine_eigh(Hp, m, w, Z, c->at(c->lay.ref_work), JACOBI_TOL, REFINE_ITERS, st);
+  if (its < 0) {   // a wide cluster or no convergence: blocked Jacobi from H'
+    ++c->fallbacks;
+    its = jacobi_eigh(Hp, m, w, Z, c->at(c->lay.jac_work), JACOBI_TOL, JACOBI_SWEEPS, st);
+  }
+  c->last_sweeps += its;
   // steps 3d-3e: U = L^-H Z, psi = phi U
   gemm_square(Linv, 1, Z, 0, U, m, st);
   if (c->prec) {
@@ -460,6 +469,7 @@ int sky_iterate(sky_ctx* c, int32_t max_iter, double tol, sky_report* rep) {
   std::vector<double> r2h;
   double de = 0.0;
   int it = 0, status = SKY_OK;
+  c->fallbacks = 0;
   for (; it < max_iter; ++it) {
     c->last_sweeps = 0;
     for (int q = 0; q < 2; ++q) {
@@ -532,7 +542,8 @@ int sky_iterate(sky_ctx* c, int32_t max_iter, double tol, sky_report* rep) {
     rep->residual = de;
     rep->energy = e[7];
     rep->energy_per_a = e[7] / double(c->nq[0] + c->nq[1]);
-    rep->jacobi_sweeps = c->last_sweeps;
+    rep->eig_iters = c->last_sweeps;
+    rep->eig_fallbacks = c->fallbacks;
   }
   return status;
 }

@@ -80,6 +80,18 @@ void combine(const void* X, const void* U, void* Y, int m, long k, hipStream_t s
 void gemm_square(const void* A, int opA, const void* B, int opB, void* C, int m,
                  hipStream_t st);
 
+// ---- eigenvector refinement (k_refine.hip)
+// Hermitian eigen-decomposition of a nearly diagonal A (m x m, not modified)
+// by Newton-type refinement with exact solves of near-degenerate clusters:
+// w ascending, Z columns.  Returns the refinement steps taken, or -1 when it
+// cannot finish (a cluster wider than its limit, a non-finite value, or more
+// than maxit steps); the caller then uses jacobi_eigh.  Converged when the
+// relative off-diagonal Frobenius norm of Z^H A Z is below tol and
+// max |Z^H Z - 1| below 1e-13.  Synchronises the stream once per step.
+size_t refine_scratch_bytes(int m);
+int refine_eigh(const void* A, int m, double* w, void* Z, void* work, double tol, int maxit,
+                hipStream_t st);
+
 // ---- dense FP64 linear algebra (k_linalg.hip)
 // Cholesky A = L L^H of Hermitian positive definite A (m x m, lower used),
 // then Linv = L^-1 (lower triangular, upper zeroed).  info[0] != 0 when a
@@ -91,6 +103,9 @@ void cholesky_inverse(void* A, void* Linv, int m, void* work, int* info, hipStre
 size_t jacobi_scratch_bytes(int m);
 int jacobi_eigh(void* A, int m, double* w, void* Z, void* work, double tol, int max_sweeps,
                 hipStream_t st);
+// w ascending (ties by index) from the diagonal of D (ld = ld) and Z the
+// matching columns of V (ld = ld), Z m x m.
+void eig_sort(const void* D, const void* V, int m, int ld, double* w, void* Z, hipStream_t st);
 // X <- X diag(d) (scale column b by d[b]), d real.
 void scale_columns(void* X, const double* d, int m, hipStream_t st);
 // w <- w^-1/2 elementwise (Loewdin), flags info if any w <= 0.

@@ -56,7 +56,8 @@ class BoxDesc(ctypes.Structure):
 class Report(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("residual", ctypes.c_double),
                 ("energy", ctypes.c_double), ("energy_per_a", ctypes.c_double),
-                ("jacobi_sweeps", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("eig_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("eig_fallbacks", ctypes.c_int32)]
 
 
 class SkyError(RuntimeError):
@@ -184,7 +185,8 @@ class Box:
         rc = _check(self.lib.sky_iterate(self.ctx, max_iter, tol, ctypes.byref(rep)),
                     ok=(SKY_OK, SKY_NOT_CONVERGED))
         return dict(iters=rep.iters, residual=rep.residual, energy=rep.energy,
-                    energy_per_a=rep.energy_per_a, jacobi_sweeps=rep.jacobi_sweeps,
+                    energy_per_a=rep.energy_per_a, eig_iters=rep.eig_iters,
+                    eig_fallbacks=rep.eig_fallbacks,
                     precision=rep.precision, converged=(rc == SKY_OK))
 
     def precision(self) -> int:
