@@ -208,6 +208,50 @@ __global__ void k_zero(double* __restrict__ p, size_t n) {
   if (i < n) p[i] = 0.0;
 }
 
+// ------------------------------------------------------------------ Loewdin series
+// D = A - 1 and per-block partial sums of |D_ij|^2.
+__global__ void __launch_bounds__(256)
+k_minus_identity(const double2* __restrict__ A, double2* __restrict__ D, int m,
+                 double* __restrict__ part) {
+  double acc = 0.0;
+  const size_t n = size_t(m) * m;
+  for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+       e += size_t(gridDim.x) * blockDim.x) {
+    double2 a = A[e];
+    if (e / m == e % m) a.x -= 1.0;
+    D[e] = a;
+    acc += a.x * a.x + a.y * a.y;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_sum_parts(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  if (threadIdx.x) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += part[b];
+  out[0] = s;
+}
+
+// P = a D + c 1
+__global__ void k_axpy_identity(const double2* __restrict__ D, double a, double c,
+                                double2* __restrict__ P, int m) {
+  const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= size_t(m) * m) return;
+  const double2 d = D[e];
+  P[e] = make_double2(a * d.x + ((e / m == e % m) ? c : 0.0), a * d.y);
+}
+
+// P += c 1
+__global__ void k_add_identity(double2* __restrict__ P, double c, int m) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) P[size_t(i) * m + i].x += c;
+}
+
 // ------------------------------------------------------------------ Jacobi
 // Diagonalise the 64x64 pair sub-matrix of blocks (P, Q) of A (ld = mp)
 // and write its unitary J (64x64, row-major, local index l < 32 -> block P).
@@ -573,6 +617,41 @@ void eig_sort(const void* D, const void* V, int m, int ld, double* w, void* Z, h
   if (m <= 0) return;
   hipLaunchKernelGGL(k_jacobi_sort, dim3(m), dim3(256), 0, st, (const double2*)D, (const double2*)V,
                      m, ld, w, (double2*)Z);
+}
+
+int loewdin_series(const void* Iv, void* Cv, void* Dv, void* Tv, int m, double max_dev,
+                   double* scratch, hipStream_t st) {
+  if (m <= 0) return 0;
+  auto D = (double2*)Dv;
+  const size_t mm = size_t(m) * m;
+  const int nb = int(std::min<size_t>(256, (mm + 255) / 256));
+  hipLaunchKernelGGL(k_minus_identity, dim3(nb), dim3(256), 0, st, (const double2*)Iv, D, m, scratch);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, (const double*)scratch, nb, scratch + nb);
+  double fro2 = 0.0;
+  hipMemcpyAsync(&fro2, scratch + nb, sizeof(double), hipMemcpyDeviceToHost, st);
+  hipStreamSynchronize(st);
+  const double f = sqrt(fro2);
+  if (!(f <= max_dev)) return 0;
+  // (1 + D)^-1/2 = sum_k c_k D^k, c_k = c_{k-1} (1 - 2k) / (2k); ||D||_2 <= f, so the
+  // tail after p terms is below |c_{p+1}| f^{p+1} / (1 - f); stop below 2^-56.
+  double c[16];
+  c[0] = 1.0;
+  for (int k = 1; k < 16; ++k) c[k] = c[k - 1] * (1.0 - 2.0 * k) / (2.0 * k);
+  int p = 1;
+  while (p < 14 && fabs(c[p + 1]) * pow(f, p + 1) / (1.0 - f) > 0x1p-56) ++p;
+  // Horner: P = c_{p-1} 1 + c_p D; P <- c_k 1 + D P for k = p-2 .. 0
+  auto C = (double2*)Cv, T = (double2*)Tv;
+  double2* cur = (p % 2) ? C : T;   // ping-pong so that the last product lands in C
+  double2* nxt = (p % 2) ? T : C;
+  const unsigned ge = unsigned((mm + 255) / 256);
+  hipLaunchKernelGGL(k_axpy_identity, dim3(ge), dim3(256), 0, st, (const double2*)D, c[p], c[p - 1],
+                     cur, m);
+  for (int k = p - 2; k >= 0; --k) {
+    gemm_square(D, 0, cur, 0, nxt, m, st);
+    hipLaunchKernelGGL(k_add_identity, dim3((m + 255) / 256), dim3(256), 0, st, nxt, c[k], m);
+    std::swap(cur, nxt);
+  }
+  return p;
 }
 
 void scale_columns(void* X, const double* d, int m, hipStream_t st) {

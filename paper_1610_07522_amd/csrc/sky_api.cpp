@@ -37,6 +37,8 @@ constexpr int DENS_CHUNKS = 32;   // state chunks of the density passes
 constexpr double JACOBI_TOL = 1e-12;   // relative off-diagonal Frobenius norm
 constexpr int JACOBI_SWEEPS = 30;
 constexpr int REFINE_ITERS = 10;     // refinement steps before the Jacobi fallback
+// ||I - 1||_F up to which I^-1/2 comes from its binomial series (<= 8 terms)
+constexpr double LOEWDIN_SERIES_MAX = 1e-2;
 
 // Byte offsets of every buffer inside the caller's workspace.
 struct Layout {
@@ -44,7 +46,7 @@ struct Layout {
   size_t psi32[2], hpsi32[2], phi32[2], hphi32[2];  // complex64 states (mixed only)
   size_t eps[2], r2[2], ritz[2], tiles;
   size_t matI, matH, matC, matL, matT, matHp, matZ, matU, wtmp, gemm_part, chol_work, jac_work;
-  size_t ref_work;
+  size_t ref_work, nrm;
   size_t plA, plB, plT, plU, plS;                  // FP16 split planes, scales (mixed only)
   size_t dens[2], der[2], mf[2], vc, fscratch, dens_part, epart, energy, info;
   size_t total;
@@ -107,6 +109,7 @@ Layout plan(const sky_box_desc& d) {
   L.chol_work = take(size_t((nmax + 63) / 64 + 1) * 64 * 64 * c16);
   L.jac_work = take(jacobi_scratch_bytes(nmax));
   L.ref_work = take(refine_scratch_bytes(nmax));
+  L.nrm = take(sizeof(double) * 512);
   for (int q = 0; q < 2; ++q) {
     L.dens[q] = take(sizeof(double) * 11 * n3);
     L.der[q] = take(sizeof(double) * 5 * n3);
@@ -266,12 +269,22 @@ int rayleigh_ritz(sky_ctx* c, int q, const void* phi, const void* hphi, void* ps
   const int ts = t_begin(c, SKY_PHASE_SUBSPACE, q);
   hermitian_fill(I, m, st);
   hermitian_fill(H, m, st);
-  // steps 3b-3c: I = L L^H, H' = L^-1 H L^-H, H' = Z lam Z^H
-  void* Lf = c->at(c->lay.matC);
-  hipMemcpyAsync(Lf, I, size_t(m) * m * 16, hipMemcpyDeviceToDevice, st);
-  cholesky_inverse(Lf, Linv, m, c->at(c->lay.chol_work), info, st);
-  gemm_square(Linv, 0, H, 0, T, m, st);
-  gemm_square(T, 0, Linv, 1, Hp, m, st);
+  // steps 3b-3c: an orthonormalising transform C (C^H I C = 1), H' = C^H H C,
+  // H' = Z lam Z^H.  Near the identity (every iteration after the start) C is
+  // Loewdin's I^-1/2 from its binomial series; otherwise C = L^-H with the
+  // Cholesky factor I = L L^H.
+  void* Cw = c->at(c->lay.matC);
+  const int terms = loewdin_series(I, Linv, Cw, T, m, LOEWDIN_SERIES_MAX,
+                                   c->at<double>(c->lay.nrm), st);
+  if (terms > 0) {   // C = I^-1/2 (Hermitian) in Linv
+    gemm_square(Linv, 0, H, 0, T, m, st);
+    gemm_square(T, 0, Linv, 0, Hp, m, st);
+  } else {           // Linv = L^-1, C = L^-H
+    hipMemcpyAsync(Cw, I, size_t(m) * m * 16, hipMemcpyDeviceToDevice, st);
+    cholesky_inverse(Cw, Linv, m, c->at(c->lay.chol_work), info, st);
+    gemm_square(Linv, 0, H, 0, T, m, st);
+    gemm_square(T, 0, Linv, 1, Hp, m, st);
+  }
   hermitian_fill(Hp, m, st);   // exact Hermitian symmetry of H' before the eigensolver
   int rc = check_info(c, "cholesky");
   if (rc) return rc;
@@ -282,8 +295,8 @@ int rayleigh_ritz(sky_ctx* c, int q, const void* phi, const void* hphi, void* ps
     its = jacobi_eigh(Hp, m, w, Z, c->at(c->lay.jac_work), JACOBI_TOL, JACOBI_SWEEPS, st);
   }
   c->last_sweeps += its;
-  // steps 3d-3e: U = L^-H Z, psi = phi U
-  gemm_square(Linv, 1, Z, 0, U, m, st);
+  // steps 3d-3e: U = C Z, psi = phi U
+  gemm_square(Linv, terms > 0 ? 0 : 1, Z, 0, U, m, st);
   if (c->prec) {
     plane_scale(U, 1, size_t(m) * m, mx + 2, st);
     split_planes_t(U, 1, m, m, mx + 2, c->at(c->lay.plU), st);

@@ -103,6 +103,14 @@ void cholesky_inverse(void* A, void* Linv, int m, void* work, int* info, hipStre
 size_t jacobi_scratch_bytes(int m);
 int jacobi_eigh(void* A, int m, double* w, void* Z, void* work, double tol, int max_sweeps,
                 hipStream_t st);
+// Loewdin transform C = I^-1/2 (Eqs. Loewedin/orthmatvec) of an overlap close
+// to the identity, by the binomial series of (1 + D)^-1/2, D = I - 1, in
+// Horner form on the FP64 matrix cores.  The number of terms p makes the
+// remainder (bounded through ||D||_2 <= ||D||_F) smaller than 2^-56.
+// Returns p, or 0 (nothing written to C) when ||D||_F > max_dev.  D and T
+// are m x m work matrices, scratch >= 257 doubles; synchronises the stream.
+int loewdin_series(const void* I, void* C, void* D, void* T, int m, double max_dev,
+                   double* scratch, hipStream_t st);
 // w ascending (ties by index) from the diagonal of D (ld = ld) and Z the
 // matching columns of V (ld = ld), Z m x m.
 void eig_sort(const void* D, const void* V, int m, int ld, double* w, void* Z, hipStream_t st);

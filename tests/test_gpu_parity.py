@@ -154,6 +154,39 @@ def test_rayleigh_ritz(torch_mod, case):
         assert rel_err(dg.rho, dr.rho) <= TOL and rel_err(dg.tau, dr.tau) <= TOL, case
 
 
+@pytest.mark.parametrize("case", ["n16_8p8", "n24_13p7_rod", "n24_200p50_rod"])
+def test_rayleigh_ritz_far_from_orthonormal(torch_mod, case):
+    """Rayleigh-Ritz of the raw trial states, whose overlap is far from the
+    identity: the orthonormalising transform comes from the Cholesky factor
+    (the binomial-series Loewdin transform only serves overlaps near 1).
+    Ritz values of the generalised problem, orthonormality and densities of
+    the new states against the oracle."""
+    torch = torch_mod
+    w = CASES[case]
+    raw = inputs.raw_states(w)
+    g = Grid(w.n, w.dx)
+    st = so.initial_state(*raw, g, w.params, w.damp_x0, w.damp_e0)
+    box = _box(w)
+    box.init_box(to_dev(raw[0]), to_dev(raw[1]))
+    for q in range(2):
+        m = raw[q].shape[0]
+        I_raw = so.overlap(raw[q], raw[q], g)
+        assert np.linalg.norm(I_raw - np.eye(m)) > 1e-2, case   # the Cholesky branch
+        phi = to_dev(raw[q])
+        hphi = torch.empty_like(phi)
+        box.apply_h(q, phi, hphi, m)
+        out = torch.empty_like(phi)
+        ritz = torch.zeros(m, dtype=torch.float64, device="cuda:0")
+        box.orthonormalize(q, phi, hphi, out, ritz)
+        hr = ph.apply_h(raw[q], st.mf[q], g)
+        U, lam = so.rayleigh_ritz(I_raw, so.overlap(raw[q], hr, g))
+        o = to_host(out)
+        assert rel_err(to_host(ritz), lam) <= TOL, case
+        np.testing.assert_allclose(so.overlap(o, o, g), np.eye(m), atol=1e-11)
+        dg, dr = ph.densities(o, g), ph.densities(so.combine(raw[q], U), g)
+        assert rel_err(dg.rho, dr.rho) <= TOL and rel_err(dg.tau, dr.tau) <= TOL, case
+
+
 ITERS = {"n16_8p8": (1, 10, 50), "n24_13p7_rod": (1, 5), "n8_5p3": (1, 10, 40),
          "n32_70p33_slab": (1, 3), "n24_200p50_rod": (1, 3)}
 
