@@ -3,112 +3,114 @@
 //
 // Sec. 2.2: h = kinetic + Skyrme mean field (Eq. Skyrme) + Coulomb, with the
 // Coulomb problem solved by FFTs; Fig. 1 step 4b.  The fields are small
-// (a few n^3 arrays), so each line transform here is one thread doing a
-// direct DFT of its line; the cost is negligible next to the per-state work.
+// (a few n^3 arrays).  A spectral first derivative (Nyquist zeroed) or
+// second derivative of a real field along one axis is a real circulant on
+// each grid line, so all of them are n-tap circular convolutions with taps
+// computed once per call; the Coulomb transform is a direct DFT pass per
+// axis with one thread per output element.
 #include "sky_kernels.h"
 
 namespace sky {
 
 namespace {
-constexpr int FL_THREADS = 32;  // lines per workgroup in the field kernels
 constexpr int E_THREADS = 256;  // threads per energy-reduction block
 constexpr int NTERM = 7;        // energy terms
-
-__device__ inline int line_base(int L, int n, int dir, int& a, int& b, int& stride) {
-  a = L % n;
-  b = L / n;
-  if (dir == 0) { stride = 1; return b * n * n + a * n; }
-  if (dir == 1) { stride = n; return b * n * n + a; }
-  stride = n * n;
-  return b * n + a;
-}
 
 __device__ inline double kval(int f, int n, double kunit) {
   return kunit * double(f < n / 2 ? f : f - n);
 }
 
-// Real field -> real field spectral op along `dir`:
-//   kind 0: multiply by i k (Nyquist zeroed)      -> first derivative
-//   kind 1: multiply by -k^2 (Nyquist kept)        -> second derivative
-// dst = (accumulate ? dst : 0) + Re F^-1[m(k) F src].
-__global__ void k_field_line(const double* __restrict__ src, double* __restrict__ dst, int n,
-                             int dir, int kind, double kunit, int accumulate) {
-  extern __shared__ double sh[];
-  const int L = blockIdx.x * FL_THREADS + threadIdx.x;
-  double* twr = sh;                      // n cos values
-  double* twi = sh + n;                  // n sin values (forward sign)
-  double* Xr = sh + 2 * n + threadIdx.x * 2 * n;
-  double* Xi = Xr + n;
-  for (int m = threadIdx.x; m < n; m += blockDim.x) {
-    double s, c;
-    sincospi(-2.0 * double(m) / double(n), &s, &c);
-    twr[m] = c;
-    twi[m] = s;
+// Taps of the line operators and the DFT twiddles, tab[4n]:
+//   c0[d] = (1/n) sum_k i k e^{2 pi i k d / n}   (Nyquist k zeroed): first derivative
+//   c1[d] = (1/n) sum_k -k^2 e^{2 pi i k d / n}  (Nyquist kept): second derivative
+// (both real: the multipliers are odd / even in k), tw[d] = e^{-2 pi i d / n}.
+// out[x] = sum_x' src[x'] c[(x - x') mod n] along a line.
+__global__ void k_field_tables(double* __restrict__ tab, int n, double kunit) {
+  const int d = threadIdx.x;
+  if (d >= n) return;
+  double a0 = 0.0, a1 = 0.0;
+  for (int k = 0; k < n; ++k) {
+    double sn, cs;
+    sincospi(2.0 * double((k * d) % n) / double(n), &sn, &cs);
+    const double kk = kval(k, n, kunit);
+    if (2 * k != n) a0 -= kk * sn;
+    a1 -= kk * kk * cs;
   }
-  __syncthreads();
-  if (L >= n * n) return;
-  int a, b, stride;
-  int base = line_base(L, n, dir, a, b, stride);
-  for (int k = 0; k < n; ++k) {          // forward DFT of a real line
-    double sr = 0.0, si = 0.0;
-    for (int x = 0; x < n; ++x) {
-      int m = (x * k) % n;
-      double v = src[base + x * stride];
-      sr += v * twr[m];
-      si += v * twi[m];
-    }
-    double kk = kval(k, n, kunit);
-    double mr, mi;                       // multiplier m(k) = mr + i mi
-    if (kind == 0) { mr = 0.0; mi = (k == n / 2) ? 0.0 : kk; }
-    else { mr = -kk * kk; mi = 0.0; }
-    Xr[k] = sr * mr - si * mi;
-    Xi[k] = sr * mi + si * mr;
-  }
-  const double inv_n = 1.0 / double(n);
-  for (int x = 0; x < n; ++x) {          // real part of the inverse DFT
-    double s = 0.0;
-    for (int k = 0; k < n; ++k) {
-      int m = (x * k) % n;
-      s += Xr[k] * twr[m] + Xi[k] * twi[m];  // Re[X conj(w)]
-    }
-    s *= inv_n;
-    double* o = dst + base + x * stride;
-    *o = accumulate ? *o + s : s;
-  }
+  tab[d] = a0 / double(n);
+  tab[n + d] = a1 / double(n);
+  double sn, cs;
+  sincospi(-2.0 * double(d) / double(n), &sn, &cs);
+  tab[2 * n + d] = cs;
+  tab[3 * n + d] = sn;
 }
 
-// In-place complex DFT of every line along `dir` (forward or inverse, the
-// inverse carrying 1/n).
-__global__ void k_field_fft(double2* __restrict__ buf, int n, int dir, int inverse) {
-  extern __shared__ double sh[];
-  const int L = blockIdx.x * FL_THREADS + threadIdx.x;
-  double* twr = sh;
-  double* twi = sh + n;
-  double* Xr = sh + 2 * n + threadIdx.x * 2 * n;
-  double* Xi = Xr + n;
-  for (int m = threadIdx.x; m < n; m += blockDim.x) {
-    double s, c;
-    sincospi(-2.0 * double(m) / double(n), &s, &c);
-    twr[m] = c;
-    twi[m] = inverse ? -s : s;
+// o = [lap rho, d rho/dx, d rho/dy, d rho/dz, div J] at every point.
+__global__ void __launch_bounds__(256)
+k_field_derivs(const double* __restrict__ rho, const double* __restrict__ J, double* __restrict__ o,
+               int n, const double* __restrict__ tab) {
+  __shared__ double c0[64], c1[64];
+  if (threadIdx.x < n) {
+    c0[threadIdx.x] = tab[threadIdx.x];
+    c1[threadIdx.x] = tab[n + threadIdx.x];
   }
   __syncthreads();
-  if (L >= n * n) return;
-  int a, b, stride;
-  int base = line_base(L, n, dir, a, b, stride);
-  for (int k = 0; k < n; ++k) {
-    double sr = 0.0, si = 0.0;
-    for (int x = 0; x < n; ++x) {
-      int m = (x * k) % n;
-      double2 v = buf[base + x * stride];
-      sr += v.x * twr[m] - v.y * twi[m];
-      si += v.x * twi[m] + v.y * twr[m];
-    }
-    Xr[k] = sr;
-    Xi[k] = si;
+  const int n2 = n * n, n3 = n2 * n;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n3) return;
+  const int x = p % n, y = (p / n) % n, z = p / n2;
+  const double* Jx = J;
+  const double* Jy = J + n3;
+  const double* Jz = J + 2 * n3;
+  double lap = 0.0, gx = 0.0, gy = 0.0, gz = 0.0, dj = 0.0;
+  const int bx = z * n2 + y * n, by = z * n2 + x, bz = y * n + x;
+  for (int j = 0; j < n; ++j) {
+    const int dx = x - j < 0 ? x - j + n : x - j;
+    const int dy = y - j < 0 ? y - j + n : y - j;
+    const int dz = z - j < 0 ? z - j + n : z - j;
+    const double rx = rho[bx + j], ry = rho[by + j * n], rz = rho[bz + j * n2];
+    lap += c1[dx] * rx + c1[dy] * ry + c1[dz] * rz;
+    gx += c0[dx] * rx;
+    gy += c0[dy] * ry;
+    gz += c0[dz] * rz;
+    dj += c0[dx] * Jx[bx + j] + c0[dy] * Jy[by + j * n] + c0[dz] * Jz[bz + j * n2];
+  }
+  o[p] = lap;
+  o[n3 + p] = gx;
+  o[2 * n3 + p] = gy;
+  o[3 * n3 + p] = gz;
+  o[4 * n3 + p] = dj;
+}
+
+// One axis of a 3D DFT: dst[.., k, ..] = s * sum_j src[.., j, ..] w^{+-k j}
+// (forward e^{-2 pi i k j / n}; inverse the conjugate and s = 1/n).
+__global__ void __launch_bounds__(256)
+k_dft_pass(const double2* __restrict__ src, double2* __restrict__ dst, int n, int dir, int inverse,
+           const double* __restrict__ tab) {
+  __shared__ double twr[64], twi[64];
+  if (threadIdx.x < n) {
+    twr[threadIdx.x] = tab[2 * n + threadIdx.x];
+    twi[threadIdx.x] = inverse ? -tab[3 * n + threadIdx.x] : tab[3 * n + threadIdx.x];
+  }
+  __syncthreads();
+  const int n2 = n * n, n3 = n2 * n;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n3) return;
+  const int x = p % n, y = (p / n) % n, z = p / n2;
+  int k, base, stride;
+  if (dir == 0) { k = x; base = z * n2 + y * n; stride = 1; }
+  else if (dir == 1) { k = y; base = z * n2 + x; stride = n; }
+  else { k = z; base = y * n + x; stride = n2; }
+  double sr = 0.0, si = 0.0;
+  int t = 0;   // (k * j) mod n
+  for (int j = 0; j < n; ++j) {
+    const double2 v = src[base + j * stride];
+    sr += v.x * twr[t] - v.y * twi[t];
+    si += v.x * twi[t] + v.y * twr[t];
+    t += k;
+    if (t >= n) t -= n;
   }
   const double sc = inverse ? 1.0 / double(n) : 1.0;
-  for (int k = 0; k < n; ++k) buf[base + k * stride] = make_double2(sc * Xr[k], sc * Xi[k]);
+  dst[p] = make_double2(sc * sr, sc * si);
 }
 
 __global__ void k_real_to_cpx(const double* __restrict__ src, double2* __restrict__ dst, int n3) {
@@ -202,21 +204,13 @@ __global__ void k_energy_final(const double* __restrict__ epart, int nblk, doubl
   out[NTERM] = tot;
 }
 
-void field_op(const double* src, double* dst, int n, int dir, int kind, double kunit,
-              int accumulate, hipStream_t st) {
-  size_t shm = sizeof(double) * (2 * n + FL_THREADS * 2 * n);
-  hipLaunchKernelGGL(k_field_line, dim3((n * n + FL_THREADS - 1) / FL_THREADS),
-                     dim3(FL_THREADS), shm, st, src, dst, n, dir, kind, kunit, accumulate);
-}
-
-void field_fft(double2* buf, int n, int dir, int inverse, hipStream_t st) {
-  size_t shm = sizeof(double) * (2 * n + FL_THREADS * 2 * n);
-  hipLaunchKernelGGL(k_field_fft, dim3((n * n + FL_THREADS - 1) / FL_THREADS), dim3(FL_THREADS),
-                     shm, st, buf, n, dir, inverse);
-}
 }  // namespace
 
 int energy_nblocks(int n) { return (n * n * n + E_THREADS - 1) / E_THREADS; }
+
+size_t mean_field_scratch_bytes(int n) {
+  return 2 * sizeof(double2) * size_t(n) * n * n + 4 * sizeof(double) * size_t(n);
+}
 
 void mean_field(int n, GridArgs g, const Skyrme& sk, const double* dens_n, const double* dens_p,
                 double* der_n, double* der_p, double* mf_n, double* mf_p, double* vc,
@@ -224,27 +218,25 @@ void mean_field(int n, GridArgs g, const Skyrme& sk, const double* dens_n, const
   const int n3 = n * n * n;
   const double* dens[2] = {dens_n, dens_p};
   double* der[2] = {der_n, der_p};
-  for (int q = 0; q < 2; ++q) {
-    const double* rho = dens[q];
-    const double* J = dens[q] + 2 * n3;
-    double* o = der[q];
-    // Laplacian: sum over axes of the -k^2 multiplier (Nyquist kept)
-    for (int m = 0; m < 3; ++m) field_op(rho, o, n, m, 1, g.kunit, m > 0, st);
-    // gradient (Nyquist zeroed)
-    for (int m = 0; m < 3; ++m) field_op(rho, o + (1 + m) * n3, n, m, 0, g.kunit, 0, st);
-    // divergence of J
-    for (int m = 0; m < 3; ++m) field_op(J + m * n3, o + 4 * n3, n, m, 0, g.kunit, m > 0, st);
-  }
+  double2* bufA = reinterpret_cast<double2*>(scratch);
+  double2* bufB = bufA + n3;
+  double* tab = reinterpret_cast<double*>(bufB + n3);
+  hipLaunchKernelGGL(k_field_tables, dim3(1), dim3(64), 0, st, tab, n, g.kunit);
+  const unsigned nb = unsigned((n3 + 255) / 256);
+  for (int q = 0; q < 2; ++q)   // lap rho (Nyquist kept), grad rho, div J (Nyquist zeroed)
+    hipLaunchKernelGGL(k_field_derivs, dim3(nb), dim3(256), 0, st, dens[q], dens[q] + 2 * n3,
+                       der[q], n, (const double*)tab);
   const double* vcp = nullptr;
   if (sk.e2 != 0.0) {
-    double2* buf = reinterpret_cast<double2*>(scratch);
-    hipLaunchKernelGGL(k_real_to_cpx, dim3((n3 + 255) / 256), dim3(256), 0, st, dens_p, buf, n3);
-    for (int m = 0; m < 3; ++m) field_fft(buf, n, m, 0, st);
-    hipLaunchKernelGGL(k_coulomb_mult, dim3((n3 + 255) / 256), dim3(256), 0, st, buf, n,
-                       g.kunit, sk.e2);
-    for (int m = 2; m >= 0; --m) field_fft(buf, n, m, 1, st);
-    hipLaunchKernelGGL(k_cpx_real_part, dim3((n3 + 255) / 256), dim3(256), 0, st,
-                       (const double2*)buf, vc, n3);
+    hipLaunchKernelGGL(k_real_to_cpx, dim3(nb), dim3(256), 0, st, dens_p, bufA, n3);
+    hipLaunchKernelGGL(k_dft_pass, dim3(nb), dim3(256), 0, st, (const double2*)bufA, bufB, n, 0, 0, (const double*)tab);
+    hipLaunchKernelGGL(k_dft_pass, dim3(nb), dim3(256), 0, st, (const double2*)bufB, bufA, n, 1, 0, (const double*)tab);
+    hipLaunchKernelGGL(k_dft_pass, dim3(nb), dim3(256), 0, st, (const double2*)bufA, bufB, n, 2, 0, (const double*)tab);
+    hipLaunchKernelGGL(k_coulomb_mult, dim3(nb), dim3(256), 0, st, bufB, n, g.kunit, sk.e2);
+    hipLaunchKernelGGL(k_dft_pass, dim3(nb), dim3(256), 0, st, (const double2*)bufB, bufA, n, 2, 1, (const double*)tab);
+    hipLaunchKernelGGL(k_dft_pass, dim3(nb), dim3(256), 0, st, (const double2*)bufA, bufB, n, 1, 1, (const double*)tab);
+    hipLaunchKernelGGL(k_dft_pass, dim3(nb), dim3(256), 0, st, (const double2*)bufB, bufA, n, 0, 1, (const double*)tab);
+    hipLaunchKernelGGL(k_cpx_real_part, dim3(nb), dim3(256), 0, st, (const double2*)bufA, vc, n3);
     vcp = vc;
   } else {
     zero(vc, n3, st);

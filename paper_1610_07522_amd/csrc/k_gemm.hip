@@ -133,51 +133,104 @@ k_combine(const double2* __restrict__ X, const double2* __restrict__ U, double2*
 
 // ----------------------------------------------------------- square products
 // C = op(A) op(B), op 0 = N, 1 = conjugate transpose; all m x m row-major.
+// Grid (column tiles, row tiles, split): workgroup z sums the contraction
+// chunks [nk z / split, nk (z+1) / split) and writes C + z m^2 (split > 1:
+// partials, reduced in order by k_sum_splits).  Each operand is loaded along
+// its contiguous index (op N of B and op H of A read rows of 64 columns), one
+// chunk ahead into registers.
 template <int OPA, int OPB>
 __global__ void __launch_bounds__(GT)
 k_gemm_square(const double2* __restrict__ A, const double2* __restrict__ B,
-              double2* __restrict__ C, int m) {
+              double2* __restrict__ C, int m, int split) {
   __shared__ double2 sA[TM * KP];   // [row][k] of op(A)
   __shared__ double2 sB[TM * KP];   // [col][k] of op(B)
-  const int r0 = blockIdx.y * TM, c0 = blockIdx.x * TM;
+  constexpr int NE = TM * KC / GT;  // elements per thread and operand
+  const int r0 = blockIdx.y * TM, c0 = blockIdx.x * TM, sp = blockIdx.z;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
+  const int nk = (m + KC - 1) / KC;
+  const int kc0 = int((long(nk) * sp) / split), kc1 = int((long(nk) * (sp + 1)) / split);
+  // (t, kk) of element q: t = tile row / column, kk = contraction index
+  auto idxA = [&](int q, int& t, int& kk) {
+    const int e = tid + q * GT;
+    if (OPA == 0) { t = e / KC; kk = e % KC; } else { t = e % TM; kk = e / TM; }
+  };
+  auto idxB = [&](int q, int& t, int& kk) {
+    const int e = tid + q * GT;
+    if (OPB == 0) { t = e % TM; kk = e / TM; } else { t = e / KC; kk = e % KC; }
+  };
+  double2 ra[NE], rb[NE];
+  auto load = [&](int kc) {
+    const int k0 = kc * KC;
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      int t, kk;
+      idxA(q, t, kk);
+      const int r = r0 + t, kg = k0 + kk;
+      double2 v = make_double2(0, 0);
+      if (r < m && kg < m) {
+        if (OPA == 0) v = A[size_t(r) * m + kg];
+        else { v = A[size_t(kg) * m + r]; v.y = -v.y; }
+      }
+      ra[q] = v;
+      idxB(q, t, kk);
+      const int c = c0 + t, kb = k0 + kk;
+      v = make_double2(0, 0);
+      if (c < m && kb < m) {
+        if (OPB == 0) v = B[size_t(kb) * m + c];
+        else { v = B[size_t(c) * m + kb]; v.y = -v.y; }
+      }
+      rb[q] = v;
+    }
+  };
   Acc acc;
   mfma::zero(acc);
-  for (int k0 = 0; k0 < m; k0 += KC) {
-    for (int e = tid; e < TM * KC; e += GT) {
-      // element (row or col index t, contraction index kk)
-      int t = e / KC, kk = e % KC;
-      int kg = k0 + kk;
-      // op(A)[r][kg]
-      {
-        int r = r0 + t;
-        double2 v = make_double2(0, 0);
-        if (r < m && kg < m) {
-          if (OPA == 0) v = A[size_t(r) * m + kg];
-          else { v = A[size_t(kg) * m + r]; v.y = -v.y; }
-        }
-        sA[t * KP + kk] = v;
-      }
-      // op(B)[kg][c]
-      {
-        int c = c0 + t;
-        double2 v = make_double2(0, 0);
-        if (c < m && kg < m) {
-          if (OPB == 0) v = B[size_t(kg) * m + c];
-          else { v = B[size_t(c) * m + kg]; v.y = -v.y; }
-        }
-        sB[t * KP + kk] = v;
-      }
+  if (kc0 < kc1) load(kc0);
+  for (int kc = kc0; kc < kc1; ++kc) {
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      int t, kk;
+      idxA(q, t, kk);
+      sA[t * KP + kk] = ra[q];
+      idxB(q, t, kk);
+      sB[t * KP + kk] = rb[q];
     }
     __syncthreads();
+    if (kc + 1 < kc1) load(kc + 1);
     mfma::tile<false>(acc, sA, sB, wm, wn, lane);
     __syncthreads();
   }
+  double2* out = C + size_t(sp) * m * m;
   mfma::foreach(acc, wm, wn, lane, [&](int row, int col, double re, double im) {
     const int r = r0 + row, c = c0 + col;
-    if (r < m && c < m) C[size_t(r) * m + c] = make_double2(re, im);
+    if (r < m && c < m) out[size_t(r) * m + c] = make_double2(re, im);
   });
+}
+
+// C[e] = sum_s part[s][e], in order.
+__global__ void k_sum_splits(const double2* __restrict__ part, int split, size_t n,
+                             double2* __restrict__ C) {
+  const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double2 acc = part[e];
+  for (int s = 1; s < split; ++s) {
+    const double2 v = part[size_t(s) * n + e];
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  C[e] = acc;
+}
+
+// Contraction splits of the square products: enough workgroups for ~4 per
+// CU (tile counts such as 625 = 25^2 otherwise leave a long last round).
+int square_split(int m) {
+  const int nt = (m + TM - 1) / TM;
+  const int nk = (m + KC - 1) / KC;
+  int split = (1024 + nt * nt - 1) / (nt * nt);
+  if (split > 8) split = 8;
+  if (split > nk / 2) split = nk / 2;
+  if (split < 1) split = 1;
+  return split;
 }
 
 int overlap_split(int m, long k) {
@@ -232,16 +285,28 @@ void combine(const void* X, const void* U, void* Y, int m, long k, hipStream_t s
                      (double2*)Y, m, k);
 }
 
-void gemm_square(const void* A, int opA, const void* B, int opB, void* C, int m, hipStream_t st) {
+size_t gemm_square_scratch_bytes(int m) {
+  const int split = square_split(m);
+  return split > 1 ? size_t(split) * m * m * sizeof(double2) : 0;
+}
+
+void gemm_square(const void* A, int opA, const void* B, int opB, void* C, int m, hipStream_t st,
+                 void* part) {
   if (m <= 0) return;
-  dim3 grid((m + TM - 1) / TM, (m + TM - 1) / TM);
+  const int split = part ? square_split(m) : 1;
+  dim3 grid((m + TM - 1) / TM, (m + TM - 1) / TM, split);
   auto a = (const double2*)A;
   auto b = (const double2*)B;
-  auto c = (double2*)C;
-  if (opA == 0 && opB == 0) hipLaunchKernelGGL((k_gemm_square<0, 0>), grid, dim3(GT), 0, st, a, b, c, m);
-  else if (opA == 0 && opB == 1) hipLaunchKernelGGL((k_gemm_square<0, 1>), grid, dim3(GT), 0, st, a, b, c, m);
-  else if (opA == 1 && opB == 0) hipLaunchKernelGGL((k_gemm_square<1, 0>), grid, dim3(GT), 0, st, a, b, c, m);
-  else hipLaunchKernelGGL((k_gemm_square<1, 1>), grid, dim3(GT), 0, st, a, b, c, m);
+  auto c = (double2*)(split > 1 ? part : C);
+  if (opA == 0 && opB == 0) hipLaunchKernelGGL((k_gemm_square<0, 0>), grid, dim3(GT), 0, st, a, b, c, m, split);
+  else if (opA == 0 && opB == 1) hipLaunchKernelGGL((k_gemm_square<0, 1>), grid, dim3(GT), 0, st, a, b, c, m, split);
+  else if (opA == 1 && opB == 0) hipLaunchKernelGGL((k_gemm_square<1, 0>), grid, dim3(GT), 0, st, a, b, c, m, split);
+  else hipLaunchKernelGGL((k_gemm_square<1, 1>), grid, dim3(GT), 0, st, a, b, c, m, split);
+  if (split > 1) {
+    const size_t n = size_t(m) * m;
+    hipLaunchKernelGGL(k_sum_splits, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st,
+                       (const double2*)part, split, n, (double2*)C);
+  }
 }
 
 }  // namespace sky

@@ -468,7 +468,7 @@ __global__ void k_ref_check_final(const double* __restrict__ part, int nb, doubl
 }
 
 struct RefineWork {
-  double2 *mat[7], *W;
+  double2 *mat[7], *W, *gpart;
   double *lam, *lam2, *part, *norms;
   int *rank, *order, *reach, *pm, *cstart, *csize, *cslot, *info;
   int2* clist;
@@ -499,13 +499,15 @@ RefineWork carve(void* work, int m) {
   r.info = in(4);
   r.clist = reinterpret_cast<int2*>(p);
   p += al256(size_t(m) * sizeof(int2));
+  r.gpart = reinterpret_cast<double2*>(p);
+  p += al256(gemm_square_scratch_bytes(m));
   return r;
 }
 }  // namespace
 
 size_t refine_scratch_bytes(int m) {
   RefineWork r = carve(nullptr, m);
-  return size_t(reinterpret_cast<char*>(r.clist)) + al256(size_t(m) * sizeof(int2));
+  return size_t(reinterpret_cast<char*>(r.gpart)) + al256(gemm_square_scratch_bytes(m));
 }
 
 int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double tol, int maxit,
@@ -524,9 +526,9 @@ int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double to
     const double2* Rp = nullptr;
     double tau = 0.0;
     if (it > 0) {
-      gemm_square(X, 1, X, 0, R, m, st);
-      gemm_square(A, 0, X, 0, T, m, st);
-      gemm_square(X, 1, T, 0, S, m, st);
+      gemm_square(X, 1, X, 0, R, m, st, r.gpart);
+      gemm_square(A, 0, X, 0, T, m, st, r.gpart);
+      gemm_square(X, 1, T, 0, S, m, st, r.gpart);
       hipLaunchKernelGGL(k_ref_check, dim3(ncheck), dim3(256), 0, st, S, R, m, r.part);
       hipLaunchKernelGGL(k_ref_check_final, dim3(1), dim3(64), 0, st, (const double*)r.part,
                          int(ncheck), r.norms);
@@ -557,13 +559,13 @@ int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double to
     hipLaunchKernelGGL(k_ref_lambda2, dim3(gm), dim3(256), 0, st, Sp, Rp, m, cl, r.lam2);
     hipLaunchKernelGGL(k_ref_update, dim3(gm, unsigned(m)), dim3(256), 0, st, Sp, Rp, m, cl,
                        (const double*)r.lam2, tau, E);
-    gemm_square(E, 0, E, 0, T, m, st);
+    gemm_square(E, 0, E, 0, T, m, st, r.gpart);
     hipLaunchKernelGGL(k_ref_build_q, dim3(gm, unsigned(m)), dim3(256), 0, st, (const double2*)E,
                        (const double2*)T, m, cl, Q);
     if (it == 0) {
       std::swap(X, Q);
     } else {
-      gemm_square(X, 0, Q, 0, Xn, m, st);
+      gemm_square(X, 0, Q, 0, Xn, m, st, r.gpart);
       std::swap(X, Xn);
     }
   }

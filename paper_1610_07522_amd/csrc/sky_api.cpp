@@ -46,7 +46,7 @@ struct Layout {
   size_t psi32[2], hpsi32[2], phi32[2], hphi32[2];  // complex64 states (mixed only)
   size_t eps[2], r2[2], ritz[2], tiles;
   size_t matI, matH, matC, matL, matT, matHp, matZ, matU, wtmp, gemm_part, chol_work, jac_work;
-  size_t ref_work, nrm;
+  size_t ref_work, nrm, sq_part;
   size_t plA, plB, plT, plU, plS;                  // FP16 split planes, scales (mixed only)
   size_t dens[2], der[2], mf[2], vc, fscratch, dens_part, epart, energy, info;
   size_t total;
@@ -108,15 +108,18 @@ Layout plan(const sky_box_desc& d) {
   L.plS = take(sizeof(unsigned int) * 4);   // largest |component| of phi, h phi, U
   L.chol_work = take(size_t((nmax + 63) / 64 + 1) * 64 * 64 * c16);
   L.jac_work = take(jacobi_scratch_bytes(nmax));
-  L.ref_work = take(refine_scratch_bytes(nmax));
+  // both species' sizes: the split-K scratch is not monotonic in the matrix size
+  L.ref_work = take(std::max(refine_scratch_bytes(std::max(1, nq[0])),
+                             refine_scratch_bytes(std::max(1, nq[1]))));
   L.nrm = take(sizeof(double) * 512);
+  L.sq_part = take(std::max(gemm_square_scratch_bytes(nq[0]), gemm_square_scratch_bytes(nq[1])));
   for (int q = 0; q < 2; ++q) {
     L.dens[q] = take(sizeof(double) * 11 * n3);
     L.der[q] = take(sizeof(double) * 5 * n3);
     L.mf[q] = take(sizeof(double) * 5 * n3);
   }
   L.vc = take(sizeof(double) * n3);
-  L.fscratch = take(c16 * n3);
+  L.fscratch = take(mean_field_scratch_bytes(d.n));
   L.dens_part = take(sizeof(double) * DENS_CHUNKS * 16 * n3);
   L.epart = take(sizeof(double) * 7 * size_t(energy_nblocks(d.n)));
   L.energy = take(sizeof(double) * 8);
@@ -274,16 +277,17 @@ int rayleigh_ritz(sky_ctx* c, int q, const void* phi, const void* hphi, void* ps
   // Loewdin's I^-1/2 from its binomial series; otherwise C = L^-H with the
   // Cholesky factor I = L L^H.
   void* Cw = c->at(c->lay.matC);
+  void* sq = c->at(c->lay.sq_part);
   const int terms = loewdin_series(I, Linv, Cw, T, m, LOEWDIN_SERIES_MAX,
-                                   c->at<double>(c->lay.nrm), st);
+                                   c->at<double>(c->lay.nrm), sq, st);
   if (terms > 0) {   // C = I^-1/2 (Hermitian) in Linv
-    gemm_square(Linv, 0, H, 0, T, m, st);
-    gemm_square(T, 0, Linv, 0, Hp, m, st);
+    gemm_square(Linv, 0, H, 0, T, m, st, sq);
+    gemm_square(T, 0, Linv, 0, Hp, m, st, sq);
   } else {           // Linv = L^-1, C = L^-H
     hipMemcpyAsync(Cw, I, size_t(m) * m * 16, hipMemcpyDeviceToDevice, st);
     cholesky_inverse(Cw, Linv, m, c->at(c->lay.chol_work), info, st);
-    gemm_square(Linv, 0, H, 0, T, m, st);
-    gemm_square(T, 0, Linv, 1, Hp, m, st);
+    gemm_square(Linv, 0, H, 0, T, m, st, sq);
+    gemm_square(T, 0, Linv, 1, Hp, m, st, sq);
   }
   hermitian_fill(Hp, m, st);   // exact Hermitian symmetry of H' before the eigensolver
   int rc = check_info(c, "cholesky");
@@ -296,7 +300,7 @@ int rayleigh_ritz(sky_ctx* c, int q, const void* phi, const void* hphi, void* ps
   }
   c->last_sweeps += its;
   // steps 3d-3e: U = C Z, psi = phi U
-  gemm_square(Linv, terms > 0 ? 0 : 1, Z, 0, U, m, st);
+  gemm_square(Linv, terms > 0 ? 0 : 1, Z, 0, U, m, st, sq);
   if (c->prec) {
     plane_scale(U, 1, size_t(m) * m, mx + 2, st);
     split_planes_t(U, 1, m, m, mx + 2, c->at(c->lay.plU), st);
@@ -337,7 +341,7 @@ int loewdin(sky_ctx* c, int q, const void* phi, void* psi_out) {
   hipMemcpyAsync(wi, w, sizeof(double) * m, hipMemcpyDeviceToDevice, st);
   inv_sqrt(wi, m, info, st);
   scale_columns(c->at(c->lay.matT), wi, m, st);
-  gemm_square(c->at(c->lay.matT), 0, X, 1, C, m, st);
+  gemm_square(c->at(c->lay.matT), 0, X, 1, C, m, st, c->at(c->lay.sq_part));
   int rc = check_info(c, "loewdin");
   if (rc) return rc;
   if (c->prec) {

@@ -27,13 +27,15 @@ struct Skyrme {
   double hb2m_n, hb2m_p, e2;
 };
 // dens[q] as produced by densities(); derived[q] = 5 fields [lap rho, d rho (3), div J];
-// mf[q] = 5 fields [U, B, Wx, Wy, Wz]; vc = Coulomb potential; scratch >= 4 n^3 complex.
+// mf[q] = 5 fields [U, B, Wx, Wy, Wz]; vc = Coulomb potential;
+// scratch >= 2 n^3 complex + 4 n doubles (mean_field_scratch_bytes).
 // epart: per-block energy partials, energy[8] = {kin, rho, rho3, tau, lap, so, coul, total}.
 void mean_field(int n, GridArgs g, const Skyrme& sk, const double* dens_n,
                 const double* dens_p, double* derived_n, double* derived_p, double* mf_n,
                 double* mf_p, double* vc, void* scratch, double* epart, double* energy,
                 hipStream_t st);
 int energy_nblocks(int n);
+size_t mean_field_scratch_bytes(int n);
 
 // ---- dense complex matrices (k_gemm.hip); complex128, row-major
 // C[a][b] = scale * sum_v conj(A[a][v]) B[b][v] for b <= a (lower triangle),
@@ -77,8 +79,11 @@ void hermitian_fill(void* C, int m, hipStream_t st);
 // Y[b][v] = sum_a U[a][b] X[a][v]   (psi = phi U), X: m x k, U: m x m (ld m)
 void combine(const void* X, const void* U, void* Y, int m, long k, hipStream_t st);
 // C = op(A) op(B), square m x m; opA/opB: 0 = N, 1 = conjugate transpose.
-void gemm_square(const void* A, int opA, const void* B, int opB, void* C, int m,
-                 hipStream_t st);
+// With part (>= gemm_square_scratch_bytes(m)) the contraction is split over
+// more workgroups and the FP64 partials are summed in a fixed order.
+size_t gemm_square_scratch_bytes(int m);
+void gemm_square(const void* A, int opA, const void* B, int opB, void* C, int m, hipStream_t st,
+                 void* part = nullptr);
 
 // ---- eigenvector refinement (k_refine.hip)
 // Hermitian eigen-decomposition of a nearly diagonal A (m x m, not modified)
@@ -108,9 +113,10 @@ int jacobi_eigh(void* A, int m, double* w, void* Z, void* work, double tol, int 
 // Horner form on the FP64 matrix cores.  The number of terms p makes the
 // remainder (bounded through ||D||_2 <= ||D||_F) smaller than 2^-56.
 // Returns p, or 0 (nothing written to C) when ||D||_F > max_dev.  D and T
-// are m x m work matrices, scratch >= 257 doubles; synchronises the stream.
+// are m x m work matrices, scratch >= 257 doubles, part the square-product
+// scratch (gemm_square); synchronises the stream.
 int loewdin_series(const void* I, void* C, void* D, void* T, int m, double max_dev,
-                   double* scratch, hipStream_t st);
+                   double* scratch, void* part, hipStream_t st);
 // w ascending (ties by index) from the diagonal of D (ld = ld) and Z the
 // matching columns of V (ld = ld), Z m x m.
 void eig_sort(const void* D, const void* V, int m, int ld, double* w, void* Z, hipStream_t st);
