@@ -10,11 +10,11 @@
 // dropped l l' is O(2^-22) relative.  The split planes hold (re h, re l,
 // im h, im l) as FP16 bit patterns: 8 bytes per complex element, the size of
 // the complex64 operand, and the GEMMs stage their tiles with plain 16-byte
-// copies.  MFMA accumulation is FP32 over runs of FLUSH*KB contraction
-// elements, folded into FP64 registers; split-K partials are reduced in FP64
-// and the scales are removed exactly in FP64.  The overlap products are
-// written in FP64 (they feed the FP64 Cholesky factorisation and
-// eigensolver); the recombination writes complex64 states.
+// copies.  MFMA accumulation is FP32 over each workgroup's contraction chunk
+// (at most CHUNK_MAX elements); the overlap's split-K chunks are summed in
+// FP64 and the scales removed exactly in FP64.  The overlap products are
+// written in FP64 (they feed the FP64 subspace solve); the recombination
+// (contraction = the state count) writes complex64 states.
 //
 // Workgroups are mapped to tiles so that the eight XCDs (workgroup i runs on
 // XCD i mod 8) each stream their own slice of the data through their own L2.
@@ -29,12 +29,9 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
-constexpr int TM = 64;       // output tile
 constexpr int KB = 32;       // contraction elements per MFMA step
-constexpr int FLUSH = 8;     // steps accumulated in FP32 before folding into FP64
 constexpr int NP = 4;        // split planes: (part re/im) x (split h/l)
 constexpr int RS = KB + 8;   // padded LDS row (fp16 elements); 80 bytes
-constexpr int GT = 256;
 constexpr int NXCD = 8;      // XCDs of the MI355X
 
 // Scale exponent S of a matrix whose largest |component| has the float bit
@@ -78,12 +75,25 @@ __device__ inline void split8(const float2 (&z)[8], int S, u4 (&w)[NP]) {
   }
 }
 
+// Output tiles of BT x BT per workgroup of 8 waves (4 x 2); each wave owns
+// 32 rows x 64 columns (2 x 4 blocks of 16 x 16).  The MFMA accumulates in
+// FP32 with a bias (its accumulator additions do not round to nearest: a
+// 13824-long contraction in one accumulator is off by ~1e-5), so the MFMA
+// accumulator is folded every FLUSH steps (256 contraction elements) into a
+// second FP32 accumulator by ordinary round-to-nearest additions, whose
+// errors are unbiased; workgroup chunks (at most CHUNK_MAX elements) are
+// summed in FP64 afterwards.
+constexpr int BT = 128;
+constexpr int BG = 512;
+constexpr int FLUSH = 8;
+constexpr long CHUNK_MAX = 16384;
+
 // LDS tile: [plane][row][RS] fp16 bit patterns.
 struct Tile {
-  unsigned short v[NP][TM][RS];
+  unsigned short v[NP][BT][RS];
 };
 
-// One thread's share of a 64-row x KB tile: row tid/4, 8 elements at (tid%4)*8.
+// One thread's share of a BT-row x KB tile: row tid/4, 8 elements at (tid%4)*8.
 struct Frag {
   u4 v[NP];
 };
@@ -115,39 +125,32 @@ __device__ inline h8 neg8(h8 x) {
   return __builtin_bit_cast(h8, u);
 }
 
-struct Acc32 {
-  f4 re[2][2], im[2][2];
-};
-struct Acc64 {
-  double re[2][2][4], im[2][2][4];
+struct Acc {
+  f4 re[2][4], im[2][4];   // MFMA accumulators
+  f4 hr[2][4], hi[2][4];   // folded sums
 };
 
-__device__ inline void zero32(Acc32& a) {
+__device__ inline void zero(Acc& a) {
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) { a.re[i][j] = f4{0, 0, 0, 0}; a.im[i][j] = f4{0, 0, 0, 0}; }
+    for (int j = 0; j < 4; ++j) {
+      a.re[i][j] = f4{0, 0, 0, 0};
+      a.im[i][j] = f4{0, 0, 0, 0};
+      a.hr[i][j] = f4{0, 0, 0, 0};
+      a.hi[i][j] = f4{0, 0, 0, 0};
+    }
 }
-__device__ inline void zero64(Acc64& a) {
+
+__device__ inline void fold(Acc& a) {
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) { a.re[i][j][e] = 0.0; a.im[i][j][e] = 0.0; }
-}
-__device__ inline void fold(Acc64& d, Acc32& s) {
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        d.re[i][j][e] += double(s.re[i][j][e]);
-        d.im[i][j][e] += double(s.im[i][j][e]);
-      }
-      s.re[i][j] = f4{0, 0, 0, 0};
-      s.im[i][j] = f4{0, 0, 0, 0};
+    for (int j = 0; j < 4; ++j) {
+      a.hr[i][j] += a.re[i][j];
+      a.hi[i][j] += a.im[i][j];
+      a.re[i][j] = f4{0, 0, 0, 0};
+      a.im[i][j] = f4{0, 0, 0, 0};
     }
 }
 
@@ -156,41 +159,41 @@ __device__ inline void fold(Acc64& d, Acc32& s) {
 // acc += op(A) B^T over one KB step; A rows = tile rows of sA, B cols = rows
 // of sB; op(A) = conj(A) if CONJA.  Three split products per real product.
 // MFMA operands: lane l supplies 8 consecutive contraction elements starting
-// at 8*(l/16) of row (or column) l%16.
+// at 8*(l/16) of row (or column) l%16.  The A fragments of the wave's two row
+// blocks stay in registers while the four column blocks stream past.
 template <bool CONJA>
-__device__ inline void step(Acc32& acc, const Tile& sA, const Tile& sB, int wm, int wn, int lane) {
+__device__ inline void step(Acc& acc, const Tile& sA, const Tile& sB, int wm, int wn, int lane) {
   const int r = lane & 15, k8 = (lane >> 4) * 8;
-  h8 br[2][2], bi[2][2];
+  h8 ar[2][2], ai[2][2];
 #pragma unroll
-  for (int j = 0; j < 2; ++j)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      br[j][s] = ld8(sB, plane(0, s), wn * 32 + j * 16 + r, k8);
-      bi[j][s] = ld8(sB, plane(1, s), wn * 32 + j * 16 + r, k8);
+      ar[i][s] = ld8(sA, plane(0, s), wm * 32 + i * 16 + r, k8);
+      ai[i][s] = ld8(sA, plane(1, s), wm * 32 + i * 16 + r, k8);
+      if (CONJA) ai[i][s] = neg8(ai[i][s]);
     }
   // split pairs (p, q): hh, hl, lh
   constexpr int P[3] = {0, 0, 1};
   constexpr int Q[3] = {0, 1, 0};
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    h8 ar[2], ai[2], an[2];
+  for (int j = 0; j < 4; ++j) {
+    h8 br[2], bi[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      ar[s] = ld8(sA, plane(0, s), wm * 32 + i * 16 + r, k8);
-      ai[s] = ld8(sA, plane(1, s), wm * 32 + i * 16 + r, k8);
-      if (CONJA) ai[s] = neg8(ai[s]);
-      an[s] = neg8(ai[s]);
+      br[s] = ld8(sB, plane(0, s), wn * 64 + j * 16 + r, k8);
+      bi[s] = ld8(sB, plane(1, s), wn * 64 + j * 16 + r, k8);
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
         const int p = P[t], q = Q[t];
         // re += ar br - ai bi ; im += ar bi + ai br   (ai already negated for conj)
-        MF(ar[p], br[j][q], acc.re[i][j]);
-        MF(an[p], bi[j][q], acc.re[i][j]);
-        MF(ar[p], bi[j][q], acc.im[i][j]);
-        MF(ai[p], br[j][q], acc.im[i][j]);
+        MF(ar[i][p], br[q], acc.re[i][j]);
+        MF(neg8(ai[i][p]), bi[q], acc.re[i][j]);
+        MF(ar[i][p], bi[q], acc.im[i][j]);
+        MF(ai[i][p], br[q], acc.im[i][j]);
       }
   }
 }
@@ -199,16 +202,16 @@ __device__ inline void step(Acc32& acc, const Tile& sA, const Tile& sB, int wm, 
 // Output element of register e of lane l in a 16x16 block (measured):
 // row 4*(l/16) + e, column l%16.
 template <typename F>
-__device__ inline void foreach64(const Acc64& acc, int wm, int wn, int lane, F f) {
+__device__ inline void foreach_out(const Acc& acc, int wm, int wn, int lane, F f) {
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int row = wm * 32 + i * 16 + 4 * (lane >> 4) + e;
-        const int col = wn * 32 + j * 16 + (lane & 15);
-        f(row, col, acc.re[i][j][e], acc.im[i][j][e]);
+        const int col = wn * 64 + j * 16 + (lane & 15);
+        f(row, col, acc.hr[i][j][e] + acc.re[i][j][e], acc.hi[i][j][e] + acc.im[i][j][e]);
       }
 }
 
@@ -319,16 +322,15 @@ k_split_t(const void* __restrict__ xv, int R, long C, long ldr, const unsigned i
 }
 
 // ------------------------------------------------------------------ products
-// part[((z*npair + pair)*split + s)][64*64] (FP64, unscaled) = the chunk-s
+// part[((z*npair + pair)*split + s)][BT*BT] (FP32, unscaled) = the chunk-s
 // sum of conj(A) B^T over the lower tile pair; A, B0, B1 as planes
 // [p][m][k].  One-dimensional grid of split*npair*nz workgroups; with
 // split % 8 == 0, XCD x computes the chunks s = x mod 8, so that the tiles
 // of one chunk are shared through that XCD's L2.
-__global__ void __launch_bounds__(GT, 2)
+__global__ void __launch_bounds__(BG, 1)
 k_overlap_planes(const unsigned short* __restrict__ PA, const unsigned short* __restrict__ PB0,
-                 const unsigned short* __restrict__ PB1, const unsigned int* __restrict__ mxA,
-                 const unsigned int* __restrict__ mxB0, const unsigned int* __restrict__ mxB1,
-                 int m, long k, int npair, int split, int nz, double2* __restrict__ part) {
+                 const unsigned short* __restrict__ PB1, int m, long k, int npair, int split,
+                 int nz, float2* __restrict__ part) {
   __shared__ Tile sA, sB;
   const int T = npair * nz;
   const int w = blockIdx.x;
@@ -343,7 +345,6 @@ k_overlap_planes(const unsigned short* __restrict__ PA, const unsigned short* __
   }
   const int pair = r / nz, z = r % nz;
   const unsigned short* PB = z ? PB1 : PB0;
-  const int SAB = scale_exp(*mxA) + scale_exp(*(z ? mxB1 : mxB0));
   int ta, tb;
   tri_pair(pair, ta, tb);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -351,47 +352,69 @@ k_overlap_planes(const unsigned short* __restrict__ PA, const unsigned short* __
   const long nst = k / KB;
   const long c0 = nst * s / split, c1 = nst * (s + 1) / split;
   const size_t psz = size_t(m) * k;
-  Acc32 acc;
-  Acc64 tot;
-  zero32(acc);
-  zero64(tot);
+  Acc acc;
+  zero(acc);
   int nacc = 0;
   Frag fa, fb;
   if (c0 < c1) {
-    gload(fa, PA, psz, k, ta * TM, m, c0 * KB, tid);
-    gload(fb, PB, psz, k, tb * TM, m, c0 * KB, tid);
+    gload(fa, PA, psz, k, ta * BT, m, c0 * KB, tid);
+    gload(fb, PB, psz, k, tb * BT, m, c0 * KB, tid);
   }
   for (long c = c0; c < c1; ++c) {
     sstore(sA, fa, tid);
     sstore(sB, fb, tid);
     __syncthreads();
     if (c + 1 < c1) {
-      gload(fa, PA, psz, k, ta * TM, m, (c + 1) * KB, tid);
-      gload(fb, PB, psz, k, tb * TM, m, (c + 1) * KB, tid);
+      gload(fa, PA, psz, k, ta * BT, m, (c + 1) * KB, tid);
+      gload(fb, PB, psz, k, tb * BT, m, (c + 1) * KB, tid);
     }
     step<true>(acc, sA, sB, wm, wn, lane);
     __syncthreads();
-    if (++nacc == FLUSH) { fold(tot, acc); nacc = 0; }
+    if (++nacc == FLUSH) { fold(acc); nacc = 0; }
   }
-  fold(tot, acc);
-  double2* out = part + (size_t(z) * npair + pair) * split * TM * TM + size_t(s) * TM * TM;
-  foreach64(tot, wm, wn, lane, [&](int row, int col, double re, double im) {
-    out[row * TM + col] = make_double2(ldexp(re, -SAB), ldexp(im, -SAB));
+  float2* out = part + (size_t(z) * npair + pair) * split * BT * BT + size_t(s) * BT * BT;
+  foreach_out(acc, wm, wn, lane, [&](int row, int col, float re, float im) {
+    out[row * BT + col] = make_float2(re, im);
   });
+}
+
+// C_z[a][b] = scale 2^-(S_A + S_Bz) sum_s part (FP64) on the lower tiles.
+__global__ void __launch_bounds__(256)
+k_overlap_reduce_planes(const float2* __restrict__ part, int npair, int split, int m, double scale,
+                        const unsigned int* __restrict__ mxA, const unsigned int* __restrict__ mxB0,
+                        const unsigned int* __restrict__ mxB1, double2* __restrict__ C0,
+                        double2* __restrict__ C1) {
+  const int pair = blockIdx.x, z = blockIdx.y;
+  double2* C = z ? C1 : C0;
+  const double sc = ldexp(scale, -(scale_exp(*mxA) + scale_exp(*(z ? mxB1 : mxB0))));
+  int ta, tb;
+  tri_pair(pair, ta, tb);
+  const float2* p = part + (size_t(z) * npair + pair) * split * BT * BT;
+  for (int e = threadIdx.x; e < BT * BT; e += blockDim.x) {
+    const int row = ta * BT + e / BT, col = tb * BT + e % BT;
+    if (row >= m || col >= m) continue;
+    double re = 0.0, im = 0.0;
+    for (int q = 0; q < split; ++q) {
+      const float2 v = p[size_t(q) * BT * BT + e];
+      re += double(v.x);
+      im += double(v.y);
+    }
+    C[size_t(row) * m + col] = make_double2(sc * re, sc * im);
+  }
 }
 
 // Y[b][v] = sum_a U[a][b] X[a][v] from the planes of U^T (rows b) and of X^T
 // (rows v), contraction length mpad (zero-padded), complex64 output.
-// One-dimensional grid of nv*nb workgroups (nv = k/64 column tiles, nb row
+// One-dimensional grid of nv*nb workgroups (nv = k/BT column tiles, nb row
 // tiles); with nv % 8 == 0, XCD x computes the column tiles v = x mod 8, all
 // row tiles of one column tile in a row, so that each X^T tile is fetched
 // from HBM once.
-__global__ void __launch_bounds__(GT, 2)
+__global__ void __launch_bounds__(BG, 1)
 k_combine_planes(const unsigned short* __restrict__ PU, const unsigned short* __restrict__ PX,
                  const unsigned int* __restrict__ mxU, const unsigned int* __restrict__ mxX,
                  float2* __restrict__ Y, int m, long k, long mpad, int nb) {
   __shared__ Tile sA, sB;
-  const long nv = k / TM;
+  const long nv = k / BT;
   const long w = blockIdx.x;
   long vt;
   int bt;
@@ -403,58 +426,59 @@ k_combine_planes(const unsigned short* __restrict__ PU, const unsigned short* __
     vt = w / nb;
     bt = int(w % nb);
   }
-  const long v0 = vt * TM;
-  const int b0 = bt * TM;
+  const long v0 = vt * BT;
+  const int b0 = bt * BT;
   const int SUX = scale_exp(*mxU) + scale_exp(*mxX);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const size_t pszU = size_t(m) * mpad, pszX = size_t(k) * mpad;
   const unsigned short* PXv = PX + size_t(v0) * mpad;
-  Acc32 acc;
-  Acc64 tot;
-  zero32(acc);
-  zero64(tot);
+  Acc acc;
+  zero(acc);
   int nacc = 0;
   Frag fa, fb;
   gload(fa, PU, pszU, mpad, b0, m, 0, tid);
-  gload(fb, PXv, pszX, mpad, 0, TM, 0, tid);
+  gload(fb, PXv, pszX, mpad, 0, BT, 0, tid);
   for (long a0 = 0; a0 < mpad; a0 += KB) {
     sstore(sA, fa, tid);
     sstore(sB, fb, tid);
     __syncthreads();
     if (a0 + KB < mpad) {
       gload(fa, PU, pszU, mpad, b0, m, a0 + KB, tid);
-      gload(fb, PXv, pszX, mpad, 0, TM, a0 + KB, tid);
+      gload(fb, PXv, pszX, mpad, 0, BT, a0 + KB, tid);
     }
     step<false>(acc, sA, sB, wm, wn, lane);
     __syncthreads();
-    if (++nacc == FLUSH) { fold(tot, acc); nacc = 0; }
+    if (++nacc == FLUSH) { fold(acc); nacc = 0; }
   }
-  fold(tot, acc);
-  foreach64(tot, wm, wn, lane, [&](int row, int col, double re, double im) {
+  foreach_out(acc, wm, wn, lane, [&](int row, int col, float re, float im) {
     const int b = b0 + row;
-    if (b < m) Y[size_t(b) * k + v0 + col] = make_float2(float(ldexp(re, -SUX)), float(ldexp(im, -SUX)));
+    if (b < m)
+      Y[size_t(b) * k + v0 + col] = make_float2(ldexpf(re, -SUX), ldexpf(im, -SUX));
   });
 }
 
 int overlap_split_mixed(int m, long k) {
-  const int nt = (m + TM - 1) / TM;
+  const int nt = (m + BT - 1) / BT;
   const int npair = nt * (nt + 1) / 2;
   const long nst = k / KB;
   int split = (2048 + 2 * npair - 1) / (2 * npair);
+  const long need = (k + CHUNK_MAX - 1) / CHUNK_MAX;   // FP32 chunk length bound
+  if (split < need) split = int(need);
   if (split > 64) split = 64;
   if (split > nst) split = int(nst);
   if (split < 1) split = 1;
   // whole XCD rounds: a multiple of 8 chunks where the contraction allows
-  if (nst >= NXCD) split = split < NXCD ? NXCD : split - split % NXCD;
+  if (nst >= NXCD) split = (split + NXCD - 1) / NXCD * NXCD;
+  if (split > nst) split = int(nst);
   return split;
 }
 }  // namespace
 
 size_t overlap_scratch_bytes_mixed(int m, long k) {
-  const int nt = (m + TM - 1) / TM;
+  const int nt = (m + BT - 1) / BT;
   const int npair = nt * (nt + 1) / 2;
-  return size_t(overlap_split_mixed(m, k)) * 2 * npair * TM * TM * sizeof(double2);
+  return size_t(overlap_split_mixed(m, k)) * 2 * npair * BT * BT * sizeof(float2);
 }
 
 long planes_pad(int m) { return (long(m) + KB - 1) / KB * KB; }
@@ -498,25 +522,26 @@ void overlap_lower_planes(const void* PA, const void* PB0, const void* PB1,
                           const unsigned int* mxB1, int m, long k, double scale, void* C0,
                           void* C1, void* part, hipStream_t st, hipEvent_t* ev) {
   if (m <= 0) return;
-  const int nt = (m + TM - 1) / TM;
+  const int nt = (m + BT - 1) / BT;
   const int npair = nt * (nt + 1) / 2;
   const int split = overlap_split_mixed(m, k);
   const int nz = PB1 ? 2 : 1;
   if (ev) hipEventRecord(ev[0], st);
-  hipLaunchKernelGGL(k_overlap_planes, dim3(unsigned(split * npair * nz)), dim3(GT), 0, st,
+  hipLaunchKernelGGL(k_overlap_planes, dim3(unsigned(split * npair * nz)), dim3(BG), 0, st,
                      (const unsigned short*)PA, (const unsigned short*)PB0,
-                     (const unsigned short*)PB1, mxA, mxB0, PB1 ? mxB1 : mxB0, m, k, npair,
-                     split, nz, (double2*)part);
+                     (const unsigned short*)PB1, m, k, npair, split, nz, (float2*)part);
   if (ev) hipEventRecord(ev[1], st);
-  overlap_reduce(part, npair, split, m, scale, C0, C1, nz, st);
+  hipLaunchKernelGGL(k_overlap_reduce_planes, dim3(npair, nz), dim3(256), 0, st,
+                     (const float2*)part, npair, split, m, scale, mxA, mxB0, PB1 ? mxB1 : mxB0,
+                     (double2*)C0, (double2*)C1);
 }
 
 void combine_planes(const void* PU, const void* PX, const unsigned int* mxU,
                     const unsigned int* mxX, void* Y, int m, long k, hipStream_t st) {
   if (m <= 0) return;
-  const int nb = (m + TM - 1) / TM;
-  const long nv = k / TM;
-  hipLaunchKernelGGL(k_combine_planes, dim3(unsigned(nv * nb)), dim3(GT), 0, st,
+  const int nb = (m + BT - 1) / BT;
+  const long nv = k / BT;
+  hipLaunchKernelGGL(k_combine_planes, dim3(unsigned(nv * nb)), dim3(BG), 0, st,
                      (const unsigned short*)PU, (const unsigned short*)PX, mxU, mxX, (float2*)Y,
                      m, k, planes_pad(m), nb);
 }

@@ -149,3 +149,31 @@ def test_precision_ladder_switches_to_fp64(torch_mod):
         so.iterate(st)
     parts = sum(abs(st.E[k]) for k in ("kin", "rho", "rho3", "tau", "lap", "so", "coul"))
     assert abs(rep["energy"] - st.E["total"]) <= 1000 * U32 * parts, (e1, rep, st.E)
+
+
+def test_mixed_overlap_fullsize(torch_mod):
+    """48^3 x 1600 neutrons, the bench configuration: sampled rows of the
+    split-FP16 overlap (FP32 accumulation over each split-K chunk of the
+    221184-long contraction, chunks summed in FP64) against complex128
+    products of the same complex64 states, at the 1e-6 bar."""
+    torch = torch_mod
+    w = inputs.WORKLOADS["rod48"]
+    rn, rp = inputs.raw_states(w)
+    box = _box(w)
+    box.init_box(to_dev(rn), to_dev(rp))
+    del rn, rp
+    q = 0
+    psi = box.view("psi", q)
+    m = psi.shape[0]
+    out = torch.empty_like(psi)
+    box.orthonormalize(q, psi, None, out)
+    box.sync()
+    I_gpu = box.view("overlap", q)
+    P = psi.reshape(m, -1).to(torch.complex128)
+    dV = w.dx ** 3
+    worst = 0.0
+    for r in range(0, m, 97):
+        ref = dV * torch.mv(P, P[r].conj())          # row r: dV sum_k conj(P[r,k]) P[b,k]
+        err = (I_gpu[r] - ref).abs().max().item() / ref.abs().max().item()
+        worst = max(worst, err)
+    assert worst <= 1e-6, worst
