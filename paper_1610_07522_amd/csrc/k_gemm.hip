@@ -7,6 +7,8 @@
 //
 // Tiles, operand staging and the three-product complex scheme are in
 // mfma_f64.h.
+#include <algorithm>
+
 #include "mfma_f64.h"
 #include "sky_kernels.h"
 
@@ -133,6 +135,8 @@ k_combine(const double2* __restrict__ X, const double2* __restrict__ U, double2*
 
 // ----------------------------------------------------------- square products
 // C = op(A) op(B), op 0 = N, 1 = conjugate transpose; all m x m row-major.
+// With lower, a product known to be Hermitian: only tiles on or below the
+// diagonal are computed, and the caller mirrors the strictly upper part.
 // Grid (column tiles, row tiles, split): workgroup z sums the contraction
 // chunks [nk z / split, nk (z+1) / split) and writes C + z m^2 (split > 1:
 // partials, reduced in order by k_sum_splits).  Each operand is loaded along
@@ -141,10 +145,11 @@ k_combine(const double2* __restrict__ X, const double2* __restrict__ U, double2*
 template <int OPA, int OPB>
 __global__ void __launch_bounds__(GT)
 k_gemm_square(const double2* __restrict__ A, const double2* __restrict__ B,
-              double2* __restrict__ C, int m, int split) {
+              double2* __restrict__ C, int m, int split, int lower) {
   __shared__ double2 sA[TM * KP];   // [row][k] of op(A)
   __shared__ double2 sB[TM * KP];   // [col][k] of op(B)
   constexpr int NE = TM * KC / GT;  // elements per thread and operand
+  if (lower && blockIdx.x > blockIdx.y) return;   // Hermitian product: lower tiles only
   const int r0 = blockIdx.y * TM, c0 = blockIdx.x * TM, sp = blockIdx.z;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -222,11 +227,13 @@ __global__ void k_sum_splits(const double2* __restrict__ part, int split, size_t
 }
 
 // Contraction splits of the square products: enough workgroups for ~4 per
-// CU (tile counts such as 625 = 25^2 otherwise leave a long last round).
-int square_split(int m) {
+// CU (tile counts such as 625 = 25^2 otherwise leave a long last round);
+// herm: only the nt (nt + 1) / 2 lower tiles are live.
+int square_split(int m, int herm) {
   const int nt = (m + TM - 1) / TM;
   const int nk = (m + KC - 1) / KC;
-  int split = (1024 + nt * nt - 1) / (nt * nt);
+  const int tiles = herm ? nt * (nt + 1) / 2 : nt * nt;
+  int split = (1024 + tiles - 1) / tiles;
   if (split > 8) split = 8;
   if (split > nk / 2) split = nk / 2;
   if (split < 1) split = 1;
@@ -286,27 +293,28 @@ void combine(const void* X, const void* U, void* Y, int m, long k, hipStream_t s
 }
 
 size_t gemm_square_scratch_bytes(int m) {
-  const int split = square_split(m);
+  const int split = std::max(square_split(m, 0), square_split(m, 1));
   return split > 1 ? size_t(split) * m * m * sizeof(double2) : 0;
 }
 
 void gemm_square(const void* A, int opA, const void* B, int opB, void* C, int m, hipStream_t st,
-                 void* part) {
+                 void* part, int herm) {
   if (m <= 0) return;
-  const int split = part ? square_split(m) : 1;
+  const int split = part ? square_split(m, herm) : 1;
   dim3 grid((m + TM - 1) / TM, (m + TM - 1) / TM, split);
   auto a = (const double2*)A;
   auto b = (const double2*)B;
   auto c = (double2*)(split > 1 ? part : C);
-  if (opA == 0 && opB == 0) hipLaunchKernelGGL((k_gemm_square<0, 0>), grid, dim3(GT), 0, st, a, b, c, m, split);
-  else if (opA == 0 && opB == 1) hipLaunchKernelGGL((k_gemm_square<0, 1>), grid, dim3(GT), 0, st, a, b, c, m, split);
-  else if (opA == 1 && opB == 0) hipLaunchKernelGGL((k_gemm_square<1, 0>), grid, dim3(GT), 0, st, a, b, c, m, split);
-  else hipLaunchKernelGGL((k_gemm_square<1, 1>), grid, dim3(GT), 0, st, a, b, c, m, split);
+  if (opA == 0 && opB == 0) hipLaunchKernelGGL((k_gemm_square<0, 0>), grid, dim3(GT), 0, st, a, b, c, m, split, herm);
+  else if (opA == 0 && opB == 1) hipLaunchKernelGGL((k_gemm_square<0, 1>), grid, dim3(GT), 0, st, a, b, c, m, split, herm);
+  else if (opA == 1 && opB == 0) hipLaunchKernelGGL((k_gemm_square<1, 0>), grid, dim3(GT), 0, st, a, b, c, m, split, herm);
+  else hipLaunchKernelGGL((k_gemm_square<1, 1>), grid, dim3(GT), 0, st, a, b, c, m, split, herm);
   if (split > 1) {
     const size_t n = size_t(m) * m;
     hipLaunchKernelGGL(k_sum_splits, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st,
                        (const double2*)part, split, n, (double2*)C);
   }
+  if (herm) hermitian_fill(C, m, st);
 }
 
 }  // namespace sky

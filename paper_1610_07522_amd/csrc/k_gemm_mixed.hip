@@ -379,18 +379,22 @@ k_overlap_planes(const unsigned short* __restrict__ PA, const unsigned short* __
 }
 
 // C_z[a][b] = scale 2^-(S_A + S_Bz) sum_s part (FP64) on the lower tiles.
+// Grid (npair * RCH, nz): workgroup x handles slice x % RCH of tile pair
+// x / RCH (BT*BT / RCH elements).
+constexpr int RCH = 16;
 __global__ void __launch_bounds__(256)
 k_overlap_reduce_planes(const float2* __restrict__ part, int npair, int split, int m, double scale,
                         const unsigned int* __restrict__ mxA, const unsigned int* __restrict__ mxB0,
                         const unsigned int* __restrict__ mxB1, double2* __restrict__ C0,
                         double2* __restrict__ C1) {
-  const int pair = blockIdx.x, z = blockIdx.y;
+  const int pair = blockIdx.x / RCH, slice = blockIdx.x % RCH, z = blockIdx.y;
   double2* C = z ? C1 : C0;
   const double sc = ldexp(scale, -(scale_exp(*mxA) + scale_exp(*(z ? mxB1 : mxB0))));
   int ta, tb;
   tri_pair(pair, ta, tb);
   const float2* p = part + (size_t(z) * npair + pair) * split * BT * BT;
-  for (int e = threadIdx.x; e < BT * BT; e += blockDim.x) {
+  constexpr int per = BT * BT / RCH;
+  for (int e = slice * per + threadIdx.x; e < (slice + 1) * per; e += blockDim.x) {
     const int row = ta * BT + e / BT, col = tb * BT + e % BT;
     if (row >= m || col >= m) continue;
     double re = 0.0, im = 0.0;
@@ -531,7 +535,7 @@ void overlap_lower_planes(const void* PA, const void* PB0, const void* PB1,
                      (const unsigned short*)PA, (const unsigned short*)PB0,
                      (const unsigned short*)PB1, m, k, npair, split, nz, (float2*)part);
   if (ev) hipEventRecord(ev[1], st);
-  hipLaunchKernelGGL(k_overlap_reduce_planes, dim3(npair, nz), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_overlap_reduce_planes, dim3(npair * RCH, nz), dim3(256), 0, st,
                      (const float2*)part, npair, split, m, scale, mxA, mxB0, PB1 ? mxB1 : mxB0,
                      (double2*)C0, (double2*)C1);
 }

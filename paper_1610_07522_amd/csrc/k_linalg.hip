@@ -647,7 +647,7 @@ int loewdin_series(const void* Iv, void* Cv, void* Dv, void* Tv, int m, double m
   hipLaunchKernelGGL(k_axpy_identity, dim3(ge), dim3(256), 0, st, (const double2*)D, c[p], c[p - 1],
                      cur, m);
   for (int k = p - 2; k >= 0; --k) {
-    gemm_square(D, 0, cur, 0, nxt, m, st, part);
+    gemm_square(D, 0, cur, 0, nxt, m, st, part, 1);   // a polynomial in D: Hermitian
     hipLaunchKernelGGL(k_add_identity, dim3((m + 255) / 256), dim3(256), 0, st, nxt, c[k], m);
     std::swap(cur, nxt);
   }

@@ -30,6 +30,7 @@
 // the blocked Jacobi solver.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "jacobi_rot.h"
 #include "sky_kernels.h"
@@ -43,13 +44,15 @@ constexpr int KMAX = 32;            // widest cluster diagonalised in one workgr
 constexpr double THETA = 0.03;      // weak-coupling ratio |coupling| / |gap|
 constexpr double ORTH_TOL = 1e-13;  // max |(X^H X - 1)_ij| at convergence
 constexpr double E_CLAMP = 0.25;    // bound on one update coefficient
+constexpr double E2_SKIP = 1e-8;      // max |E| below which E^2/2 is left out
 constexpr double NOISE_ULPS = 8.0;   // coupling floor, in ulps of the rms eigenvalue
 constexpr int CHECK_BLOCKS = 256;
 
-// lam[i] = Re S_ii / (1 - Re R_ii)  (R may be null: R = 0)
+// lam[i] = Re S_ii / (1 - Re R_ii)  (R may be null: R = 0); clears *emax.
 __global__ void k_ref_lambda(const double2* __restrict__ S, const double2* __restrict__ R, int m,
-                             double* __restrict__ lam) {
+                             double* __restrict__ lam, unsigned long long* __restrict__ emax) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *emax = 0ull;
   if (i >= m) return;
   const double r = R ? R[size_t(i) * m + i].x : 0.0;
   lam[i] = S[size_t(i) * m + i].x / (1.0 - r);
@@ -338,7 +341,8 @@ __global__ void k_ref_lambda2(const double2* __restrict__ S, const double2* __re
   lam2[a] = s2 / (1.0 - r2);
 }
 
-// E in the cluster-rotated sorted basis (m x m, row a, column b).  A pair of
+// E in the cluster-rotated sorted basis (m x m, row a, column b), and
+// *emax = max |E_ab|.  A pair of
 // different clusters whose coupling (both orientations) is at the rounding
 // floor tau of the products is converged: it gets the orthonormality term
 // only.  (Its first-order coefficient would be rounding noise over a gap
@@ -346,33 +350,42 @@ __global__ void k_ref_lambda2(const double2* __restrict__ S, const double2* __re
 // rotate the pair at random by up to THETA on every step.)
 __global__ void __launch_bounds__(256)
 k_ref_update(const double2* __restrict__ S, const double2* __restrict__ R, int m, Clusters cl,
-             const double* __restrict__ lam2, double tau, double2* __restrict__ E) {
+             const double* __restrict__ lam2, double tau, double2* __restrict__ E,
+             unsigned long long* __restrict__ emax) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   const int a = blockIdx.y;
-  if (b >= m) return;
-  const int sa = cl.cstart[a], ka = cl.csize[a], sb = cl.cstart[b], kb = cl.csize[b];
-  const double2 *Wa = cl.w(a), *Wb = cl.w(b);
-  double2 e = make_double2(0.0, 0.0);
-  if (sa == sb) {
-    if (R) e = cscale(0.5, sandwich(R, m, cl.order, Wa, sa, ka, a - sa, Wb, sb, kb, b - sb));
-  } else {
-    const double2 s2 = sandwich(S, m, cl.order, Wa, sa, ka, a - sa, Wb, sb, kb, b - sb);
-    const double2 r2 = R ? sandwich(R, m, cl.order, Wa, sa, ka, a - sa, Wb, sb, kb, b - sb)
-                         : make_double2(0.0, 0.0);
-    const double2 gb = cadd(s2, cscale(lam2[b], r2)), ga = cadd(s2, cscale(lam2[a], r2));
-    const double den = lam2[b] - lam2[a];
-    if (fmax(hypot(gb.x, gb.y), hypot(ga.x, ga.y)) <= tau) {
-      e = cscale(0.5, r2);   // coupling at the rounding floor: orthonormality only
-    } else if (den != 0.0) {
-      e = cscale(1.0 / den, gb);
-      const double mag = hypot(e.x, e.y);
-      if (mag > E_CLAMP) e = cscale(E_CLAMP / mag, e);
+  double mag = 0.0;
+  if (b < m) {
+    const int sa = cl.cstart[a], ka = cl.csize[a], sb = cl.cstart[b], kb = cl.csize[b];
+    const double2 *Wa = cl.w(a), *Wb = cl.w(b);
+    double2 e = make_double2(0.0, 0.0);
+    if (sa == sb) {
+      if (R) e = cscale(0.5, sandwich(R, m, cl.order, Wa, sa, ka, a - sa, Wb, sb, kb, b - sb));
+    } else {
+      const double2 s2 = sandwich(S, m, cl.order, Wa, sa, ka, a - sa, Wb, sb, kb, b - sb);
+      const double2 r2 = R ? sandwich(R, m, cl.order, Wa, sa, ka, a - sa, Wb, sb, kb, b - sb)
+                           : make_double2(0.0, 0.0);
+      const double2 gb = cadd(s2, cscale(lam2[b], r2)), ga = cadd(s2, cscale(lam2[a], r2));
+      const double den = lam2[b] - lam2[a];
+      if (fmax(hypot(gb.x, gb.y), hypot(ga.x, ga.y)) <= tau) {
+        e = cscale(0.5, r2);   // coupling at the rounding floor: orthonormality only
+      } else if (den != 0.0) {
+        e = cscale(1.0 / den, gb);
+        const double em = hypot(e.x, e.y);
+        if (em > E_CLAMP) e = cscale(E_CLAMP / em, e);
+      }
     }
+    E[size_t(a) * m + b] = e;
+    mag = hypot(e.x, e.y);
   }
-  E[size_t(a) * m + b] = e;
+  // largest |E_ab| (bit patterns of non-negative doubles order like integers)
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mag = fmax(mag, __shfl_xor(mag, o));
+  if ((threadIdx.x & 63) == 0) atomicMax(emax, (unsigned long long)__double_as_longlong(mag));
 }
 
 // Q[order[s]][b] = sum_{t in cluster(s)} W[s - c][t - c] (delta_tb + E_tb + E2_tb / 2)
+// (E2 null: the second-order term is below rounding and left out).
 __global__ void __launch_bounds__(256)
 k_ref_build_q(const double2* __restrict__ E, const double2* __restrict__ E2, int m, Clusters cl,
               double2* __restrict__ Q) {
@@ -384,7 +397,7 @@ k_ref_build_q(const double2* __restrict__ E, const double2* __restrict__ E2, int
   double2 acc = make_double2(0.0, 0.0);
   for (int t = 0; t < k; ++t) {
     const size_t at = size_t(c + t) * m + b;
-    double2 q = cadd(E[at], cscale(0.5, E2[at]));
+    double2 q = E2 ? cadd(E[at], cscale(0.5, E2[at])) : E[at];
     if (c + t == b) q.x += 1.0;
     acc = cadd(acc, Wc ? cmul(Wc[(s - c) * KMAX + t], q) : q);
   }
@@ -470,6 +483,7 @@ __global__ void k_ref_check_final(const double* __restrict__ part, int nb, doubl
 struct RefineWork {
   double2 *mat[7], *W, *gpart;
   double *lam, *lam2, *part, *norms;
+  unsigned long long* emax;
   int *rank, *order, *reach, *pm, *cstart, *csize, *cslot, *info;
   int2* clist;
 };
@@ -489,6 +503,7 @@ RefineWork carve(void* work, int m) {
   r.lam2 = dbl(m);
   r.part = dbl(3 * CHECK_BLOCKS);
   r.norms = dbl(4);
+  r.emax = reinterpret_cast<unsigned long long*>(dbl(1));
   r.rank = in(m);
   r.order = in(m);
   r.reach = in(m);
@@ -521,14 +536,15 @@ int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double to
   const size_t mm = size_t(m) * m;
   const unsigned ncheck = unsigned(std::min<size_t>(CHECK_BLOCKS, (mm + 255) / 256));
   Clusters cl{r.order, r.cstart, r.csize, r.cslot, r.W};
+  double off_prev = 1.0;   // relative off-diagonal norm of the last check
   for (int it = 0;; ++it) {
     const double2* Sp = A;
     const double2* Rp = nullptr;
     double tau = 0.0;
     if (it > 0) {
-      gemm_square(X, 1, X, 0, R, m, st, r.gpart);
+      gemm_square(X, 1, X, 0, R, m, st, r.gpart, 1);
       gemm_square(A, 0, X, 0, T, m, st, r.gpart);
-      gemm_square(X, 1, T, 0, S, m, st, r.gpart);
+      gemm_square(X, 1, T, 0, S, m, st, r.gpart, 1);
       hipLaunchKernelGGL(k_ref_check, dim3(ncheck), dim3(256), 0, st, S, R, m, r.part);
       hipLaunchKernelGGL(k_ref_check_final, dim3(1), dim3(64), 0, st, (const double*)r.part,
                          int(ncheck), r.norms);
@@ -538,6 +554,7 @@ int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double to
       hipMemcpyAsync(hi, r.info, sizeof(hi), hipMemcpyDeviceToHost, st);
       hipStreamSynchronize(st);
       if (!(h[0] == h[0]) || !(h[1] == h[1]) || !(h[2] == h[2]) || hi[1] > KMAX) return -1;
+      off_prev = h[1] > 0.0 ? sqrt(h[0] / h[1]) : 0.0;
       if ((h[0] <= tol * tol * h[1] || h[0] < 1e-300) && h[2] <= ORTH_TOL) {
         eig_sort(S, X, m, m, w, Z, st);
         return it;
@@ -548,7 +565,7 @@ int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double to
       // rounding floor of the FP64 products: a few ulps of the rms eigenvalue
       tau = NOISE_ULPS * 0x1p-52 * sqrt(h[1] / m);
     }
-    hipLaunchKernelGGL(k_ref_lambda, dim3(gm), dim3(256), 0, st, Sp, Rp, m, r.lam);
+    hipLaunchKernelGGL(k_ref_lambda, dim3(gm), dim3(256), 0, st, Sp, Rp, m, r.lam, r.emax);
     hipLaunchKernelGGL(k_ref_rank, dim3(gm), dim3(256), 0, st, (const double*)r.lam, m, r.rank, r.order);
     hipLaunchKernelGGL(k_ref_reach, dim3(m), dim3(256), 0, st, Sp, Rp, (const double*)r.lam,
                        (const int*)r.rank, m, THETA, r.reach);
@@ -558,10 +575,21 @@ int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double to
                        (const int*)r.order, (const int2*)r.clist, (const int*)r.info, r.W, tol * 1e-2);
     hipLaunchKernelGGL(k_ref_lambda2, dim3(gm), dim3(256), 0, st, Sp, Rp, m, cl, r.lam2);
     hipLaunchKernelGGL(k_ref_update, dim3(gm, unsigned(m)), dim3(256), 0, st, Sp, Rp, m, cl,
-                       (const double*)r.lam2, tau, E);
-    gemm_square(E, 0, E, 0, T, m, st, r.gpart);
+                       (const double*)r.lam2, tau, E, r.emax);
+    // E^2/2 matters while |E| > 1e-8 (below, it is under FP64 rounding of 1 + E);
+    // read |E| only once the previous step was already close
+    bool second = true;
+    if (off_prev < 1e-6) {
+      unsigned long long eb = 0;
+      hipMemcpyAsync(&eb, r.emax, sizeof(eb), hipMemcpyDeviceToHost, st);
+      hipStreamSynchronize(st);
+      double em;
+      std::memcpy(&em, &eb, sizeof(em));
+      second = !(em <= E2_SKIP);
+    }
+    if (second) gemm_square(E, 0, E, 0, T, m, st, r.gpart);
     hipLaunchKernelGGL(k_ref_build_q, dim3(gm, unsigned(m)), dim3(256), 0, st, (const double2*)E,
-                       (const double2*)T, m, cl, Q);
+                       second ? (const double2*)T : nullptr, m, cl, Q);
     if (it == 0) {
       std::swap(X, Q);
     } else {

@@ -282,12 +282,12 @@ int rayleigh_ritz(sky_ctx* c, int q, const void* phi, const void* hphi, void* ps
                                    c->at<double>(c->lay.nrm), sq, st);
   if (terms > 0) {   // C = I^-1/2 (Hermitian) in Linv
     gemm_square(Linv, 0, H, 0, T, m, st, sq);
-    gemm_square(T, 0, Linv, 0, Hp, m, st, sq);
+    gemm_square(T, 0, Linv, 0, Hp, m, st, sq, 1);
   } else {           // Linv = L^-1, C = L^-H
     hipMemcpyAsync(Cw, I, size_t(m) * m * 16, hipMemcpyDeviceToDevice, st);
     cholesky_inverse(Cw, Linv, m, c->at(c->lay.chol_work), info, st);
     gemm_square(Linv, 0, H, 0, T, m, st, sq);
-    gemm_square(T, 0, Linv, 1, Hp, m, st, sq);
+    gemm_square(T, 0, Linv, 1, Hp, m, st, sq, 1);
   }
   hermitian_fill(Hp, m, st);   // exact Hermitian symmetry of H' before the eigensolver
   int rc = check_info(c, "cholesky");
@@ -341,7 +341,7 @@ int loewdin(sky_ctx* c, int q, const void* phi, void* psi_out) {
   hipMemcpyAsync(wi, w, sizeof(double) * m, hipMemcpyDeviceToDevice, st);
   inv_sqrt(wi, m, info, st);
   scale_columns(c->at(c->lay.matT), wi, m, st);
-  gemm_square(c->at(c->lay.matT), 0, X, 1, C, m, st, c->at(c->lay.sq_part));
+  gemm_square(c->at(c->lay.matT), 0, X, 1, C, m, st, c->at(c->lay.sq_part), 1);
   int rc = check_info(c, "loewdin");
   if (rc) return rc;
   if (c->prec) {

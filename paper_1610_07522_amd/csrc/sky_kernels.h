@@ -80,10 +80,12 @@ void hermitian_fill(void* C, int m, hipStream_t st);
 void combine(const void* X, const void* U, void* Y, int m, long k, hipStream_t st);
 // C = op(A) op(B), square m x m; opA/opB: 0 = N, 1 = conjugate transpose.
 // With part (>= gemm_square_scratch_bytes(m)) the contraction is split over
-// more workgroups and the FP64 partials are summed in a fixed order.
+// more workgroups and the FP64 partials are summed in a fixed order.  herm:
+// the product is known to be Hermitian; only its lower tiles are computed and
+// the upper triangle is mirrored from them (C exactly Hermitian).
 size_t gemm_square_scratch_bytes(int m);
 void gemm_square(const void* A, int opA, const void* B, int opB, void* C, int m, hipStream_t st,
-                 void* part = nullptr);
+                 void* part = nullptr, int herm = 0);
 
 // ---- eigenvector refinement (k_refine.hip)
 // Hermitian eigen-decomposition of a nearly diagonal A (m x m, not modified)
