@@ -159,6 +159,9 @@ def main() -> int:
     ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1610_07522_amd",
+                                                         "tuning_mi355x.json"),
+                    help="autotuner cache (launch shapes); 'off' keeps the defaults")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -190,6 +193,12 @@ def main() -> int:
         torch.cuda.synchronize()
         tag = "mixed" if precision else "fp64"
         log(f"[{tag}] init (Loewdin, densities, mean field) {time.perf_counter() - t0:.1f} s")
+        tuning = None
+        if args.tune_cache != "off":
+            t0 = time.perf_counter()
+            tuning = box.autotune(args.tune_cache)
+            log(f"[{tag}] launch shapes {tuning} ({time.perf_counter() - t0:.1f} s)")
+            box.init_box(dn, dp)   # the tuner overwrote h psi and the subspace matrices
         for i in range(args.warmup):
             rep = box.iterate(1)
             log(f"[{tag}] warmup {i + 1}/{args.warmup}: residual {rep['residual']:.4e} "
@@ -207,10 +216,10 @@ def main() -> int:
         torch.cuda.empty_cache()
         log(f"[{tag}] timed {args.steps} steps in {elapsed:.3f} s; last residual "
             f"{reps[-1]['residual']:.4e} E/A {reps[-1]['energy_per_a']:.6f}")
-        return elapsed, timing, reps
+        return elapsed, timing, reps, tuning
 
     mixed = args.precision == "mixed"
-    elapsed, timing, reps = run(sky.SKY_MIXED if mixed else sky.SKY_FP64)
+    elapsed, timing, reps, tuning = run(sky.SKY_MIXED if mixed else sky.SKY_FP64)
     phases = {k: round((v["ms_n"] + v["ms_p"]) / args.steps, 3) for k, v in timing.items()}
     out = dict(
         metric="damped-gradient iterations/s, 48^3 box, 2000 nucleons",
@@ -229,9 +238,10 @@ def main() -> int:
         residual=reps[-1]["residual"], energy_per_a=reps[-1]["energy_per_a"],
         eigensolver=dict(iters_per_step=[r["eig_iters"] for r in reps],
                          jacobi_fallbacks=sum(r["eig_fallbacks"] for r in reps)),
+        launch_shapes=tuning,
     )
     if mixed and not args.no_fp64_compare:
-        e64, t64, r64 = run(sky.SKY_FP64)
+        e64, t64, r64, _ = run(sky.SKY_FP64)
         out["fp64_form"] = dict(value=args.steps / e64, ms_per_step=1e3 * e64 / args.steps,
                                 speedup_mixed=(args.steps / elapsed) / (args.steps / e64),
                                 phases_ms_per_iter={k: round((v["ms_n"] + v["ms_p"]) / args.steps, 3)

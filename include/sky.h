@@ -216,6 +216,33 @@ int sky_get_timing(sky_ctx* c, double* ms, int64_t* launches);
 /* Current precision of the context's states (SKY_FP64 or SKY_MIXED). */
 int sky_get_precision(sky_ctx* c, int32_t* precision);
 
+/* Launch shapes of the hot kernels (0 in a split field = the built-in
+ * default choice). */
+typedef struct {
+  int32_t h_lines;           /* grid lines (pencils) per workgroup of the h passes */
+  int32_t overlap_split[2];  /* split-K factor of the I/H product per species    */
+  int32_t square_split[2];   /* split-K factor of the subspace products          */
+  int32_t from_cache;        /* 1: every shape came from the cache file          */
+} sky_tuning;
+
+/* Autotuner.  Picks, for this box, the fastest of a few candidate launch
+ * shapes of the dominant kernels: the pencils per workgroup of the h passes
+ * (the FFT line kernels, keyed by grid size and precision), and the split-K
+ * factors of the overlap/Hamiltonian product and of the square subspace
+ * products (keyed by state count, grid points and precision).  Candidates
+ * are timed with HIP events on the context's own buffers: call after
+ * sky_init_box; the run overwrites h psi and the subspace matrices (the
+ * states are untouched).  Every candidate computes the same result up to
+ * the order of floating-point sums.  cache_path (may be NULL): a flat JSON
+ * object {"key": value}; shapes found there are used without timing, and
+ * newly timed ones are merged into it.  out (may be NULL) receives the
+ * shapes in use.  Synchronises the stream.  Errors: SKY_ERR_INVALID (null
+ * context, unwritable cache), SKY_ERR_HIP. */
+int sky_autotune(sky_ctx* c, const char* cache_path, sky_tuning* out);
+
+/* Launch shapes in use (defaults until sky_autotune). */
+int sky_get_tuning(sky_ctx* c, sky_tuning* out);
+
 /* Wait for all work of the context's stream. */
 int sky_sync(sky_ctx* c);
 

@@ -112,12 +112,14 @@ template <typename T, bool INV> struct DFT<T, 8, INV> {
 
 // ---------------------------------------------------------------- line engine
 // Launch shape of the line kernels for grid size N.
-template <int N> struct LineCfg {
+// Lines (pencils) per workgroup: LP = 0 picks the default, otherwise LP.
+template <int N, int LP = 0> struct LineCfg {
   static constexpr int R1 = Fact<N>::R1, R2 = Fact<N>::R2;
   static constexpr int RT = R1 > R2 ? R1 : R2;          // threads per line
-  static constexpr int LPW = (RT == 4) ? 64 : 32;       // lines per workgroup
+  static constexpr int LPW = LP ? LP : ((RT == 4) ? 64 : 32);   // lines per workgroup
   static constexpr int THREADS = RT * LPW;
   static_assert((N * N) % LPW == 0, "lines must tile the plane");
+  static_assert(THREADS <= 1024, "workgroup too large");
 };
 
 // FFT of S spinor components along one line, S in {1, 2}.
@@ -222,8 +224,8 @@ template <int N, int DIR> __device__ inline void line_geom(int L, int& base, int
 // Thread -> (line within workgroup, role j).  Along x the role varies
 // fastest so consecutive threads touch consecutive points; along y and z
 // the line varies fastest so consecutive threads touch consecutive x.
-template <int N, int DIR> __device__ inline void thread_role(int t, int& line, int& j) {
-  constexpr int RT = LineCfg<N>::RT, LPW = LineCfg<N>::LPW;
+template <int N, int DIR, int LP = 0> __device__ inline void thread_role(int t, int& line, int& j) {
+  constexpr int RT = LineCfg<N, LP>::RT, LPW = LineCfg<N, LP>::LPW;
   if (DIR == 0) { j = t % RT; line = t / RT; }
   else { j = t / LPW; line = t % LPW; }
 }

@@ -252,18 +252,32 @@ int overlap_split(int m, long k) {
 }
 }  // namespace
 
+// Split-K factors tried by the autotuner: half, default and double.
+int overlap_split_candidates(int m, long k, int* out) {
+  const int d = overlap_split(m, k);
+  const long nck = k / KC;
+  int n = 0;
+  for (int c : {d / 2, d, 2 * d})
+    if (c >= 1 && c <= 64 && c <= nck && (n == 0 || out[n - 1] != c)) out[n++] = c;
+  return n;
+}
+
 size_t overlap_scratch_bytes(int m, long k) {
   const int nt = (m + TM - 1) / TM;
   const int npair = nt * (nt + 1) / 2;
-  return size_t(overlap_split(m, k)) * 2 * npair * TM * TM * sizeof(double2);
+  int c[3];
+  const int nc = overlap_split_candidates(m, k, c);
+  int split = 1;
+  for (int i = 0; i < nc; ++i) split = std::max(split, c[i]);
+  return size_t(split) * 2 * npair * TM * TM * sizeof(double2);
 }
 
 void overlap_lower(const void* A, const void* B0, const void* B1, int m, long k, double scale,
-                   void* C0, void* C1, void* part, hipStream_t st, hipEvent_t* ev) {
+                   void* C0, void* C1, void* part, hipStream_t st, hipEvent_t* ev, int split_req) {
   if (m <= 0) return;
   const int nt = (m + TM - 1) / TM;
   const int npair = nt * (nt + 1) / 2;
-  const int split = overlap_split(m, k);
+  const int split = split_req > 0 ? split_req : overlap_split(m, k);
   const int nz = B1 ? 2 : 1;
   if (ev) hipEventRecord(ev[0], st);
   hipLaunchKernelGGL(k_overlap_lower, dim3(npair, split, nz), dim3(GT), 0, st,
@@ -292,15 +306,27 @@ void combine(const void* X, const void* U, void* Y, int m, long k, hipStream_t s
                      (double2*)Y, m, k);
 }
 
+// Split-K factors tried by the autotuner for square products of size m.
+int square_split_candidates(int m, int* out) {
+  const int nk = (m + KC - 1) / KC;
+  int n = 0;
+  for (int c : {1, 2, 4, 8})
+    if (c == 1 || c <= nk / 2) out[n++] = c;
+  return n;
+}
+
 size_t gemm_square_scratch_bytes(int m) {
-  const int split = std::max(square_split(m, 0), square_split(m, 1));
+  int c[4];
+  const int nc = square_split_candidates(m, c);
+  int split = std::max(square_split(m, 0), square_split(m, 1));
+  for (int i = 0; i < nc; ++i) split = std::max(split, c[i]);
   return split > 1 ? size_t(split) * m * m * sizeof(double2) : 0;
 }
 
 void gemm_square(const void* A, int opA, const void* B, int opB, void* C, int m, hipStream_t st,
-                 void* part, int herm) {
+                 void* part, int herm, int split_req) {
   if (m <= 0) return;
-  const int split = part ? square_split(m, herm) : 1;
+  const int split = !part ? 1 : (split_req > 0 ? split_req : square_split(m, herm));
   dim3 grid((m + TM - 1) / TM, (m + TM - 1) / TM, split);
   auto a = (const double2*)A;
   auto b = (const double2*)B;

@@ -479,10 +479,31 @@ int overlap_split_mixed(int m, long k) {
 }
 }  // namespace
 
+// Split-K factors tried by the autotuner: multiples of 8 (whole XCD rounds)
+// from the FP32 chunk-length bound up to 64, around the default.
+int overlap_split_candidates_mixed(int m, long k, int* out) {
+  const long nst = k / KB;
+  const int d = overlap_split_mixed(m, k);
+  if (nst < NXCD) { out[0] = d; return 1; }
+  const long need = (k + CHUNK_MAX - 1) / CHUNK_MAX;
+  int n = 0;
+  for (int c : {d / 2, d, 2 * d}) {
+    c = (c + NXCD - 1) / NXCD * NXCD;
+    if (c < need || c > 64 || c > nst) continue;
+    if (n == 0 || out[n - 1] != c) out[n++] = c;
+  }
+  if (n == 0) out[n++] = d;
+  return n;
+}
+
 size_t overlap_scratch_bytes_mixed(int m, long k) {
   const int nt = (m + BT - 1) / BT;
   const int npair = nt * (nt + 1) / 2;
-  return size_t(overlap_split_mixed(m, k)) * 2 * npair * BT * BT * sizeof(float2);
+  int c[3];
+  const int nc = overlap_split_candidates_mixed(m, k, c);
+  int split = overlap_split_mixed(m, k);
+  for (int i = 0; i < nc; ++i) split = split > c[i] ? split : c[i];
+  return size_t(split) * 2 * npair * BT * BT * sizeof(float2);
 }
 
 long planes_pad(int m) { return (long(m) + KB - 1) / KB * KB; }
@@ -524,11 +545,11 @@ void split_planes_t(const void* x, int x_is_c128, int rows, long cols, const uns
 void overlap_lower_planes(const void* PA, const void* PB0, const void* PB1,
                           const unsigned int* mxA, const unsigned int* mxB0,
                           const unsigned int* mxB1, int m, long k, double scale, void* C0,
-                          void* C1, void* part, hipStream_t st, hipEvent_t* ev) {
+                          void* C1, void* part, hipStream_t st, hipEvent_t* ev, int split_req) {
   if (m <= 0) return;
   const int nt = (m + BT - 1) / BT;
   const int npair = nt * (nt + 1) / 2;
-  const int split = overlap_split_mixed(m, k);
+  const int split = split_req > 0 ? split_req : overlap_split_mixed(m, k);
   const int nz = PB1 ? 2 : 1;
   if (ev) hipEventRecord(ev[0], st);
   hipLaunchKernelGGL(k_overlap_planes, dim3(unsigned(split * npair * nz)), dim3(BG), 0, st,

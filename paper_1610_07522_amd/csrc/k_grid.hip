@@ -45,11 +45,11 @@ __device__ inline double block_sum(double v, double* red) {
 //   g = -B D psi + (i/2) A psi,
 // plus U psi on the first pass.  The last pass also forms per-workgroup
 // partial sums of <psi|h psi> for the Rayleigh quotients.
-template <typename T, int N, int DIR, bool FIRST, bool LAST>
-__global__ void __launch_bounds__(LineCfg<N>::THREADS)
+template <typename T, int N, int DIR, bool FIRST, bool LAST, int LP>
+__global__ void __launch_bounds__((LineCfg<N, LP>::THREADS))
 k_h_pass(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPtrs mf,
          GridArgs g, double* __restrict__ eps_part) {
-  using C = LineCfg<N>;
+  using C = LineCfg<N, LP>;
   using F = LineFFT<T, N, 2>;
   constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
   __shared__ cpx<T> tw[N];
@@ -58,7 +58,7 @@ k_h_pass(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPtr
   load_twiddles<T, N>(tw);
 
   int line, j;
-  thread_role<N, DIR>(threadIdx.x, line, j);
+  thread_role<N, DIR, LP>(threadIdx.x, line, j);
   const int L = blockIdx.x * C::LPW + line;
   int base, stride, a, b;
   line_geom<N, DIR>(L, base, stride, a, b);
@@ -461,33 +461,68 @@ void convert_states(const void* src, int src_prec, void* dst, int dst_prec, size
 // ------------------------------------------------------------------ launchers
 template <int N> static int ntiles() { return N * N / LineCfg<N>::LPW; }
 
-template <typename T, int N>
-static void launch_apply_h(const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf,
-                           GridArgs g, double* eps_part, hipStream_t st) {
-  dim3 grid(ntiles<N>(), nstate), block(LineCfg<N>::THREADS);
+// Pencil counts the h passes can run with: half, default and double the
+// default lines per workgroup, where they tile the plane, fit 1024 threads
+// and (double precision, double lines) the LDS.
+template <int N> static constexpr bool lines_ok(int lp, int bytes_per_cpx) {
+  return lp > 0 && (N * N) % lp == 0 && LineCfg<N>::RT * lp <= 1024 &&
+         lp * (2 * Fact<N>::R1 * (Fact<N>::R2 + 1) + 1) * bytes_per_cpx <= 96 * 1024;
+}
+
+template <typename T, int N, int LP>
+static void launch_h_lp(const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf, GridArgs g,
+                        double* eps_part, hipStream_t st) {
+  dim3 grid(N * N / LineCfg<N, LP>::LPW, nstate), block(LineCfg<N, LP>::THREADS);
   auto p = reinterpret_cast<const cpx<T>*>(psi);
   auto h = reinterpret_cast<cpx<T>*>(hpsi);
-  hipLaunchKernelGGL((k_h_pass<T, N, 0, true, false>), grid, block, 0, st, p, h, mf, g, nullptr);
-  hipLaunchKernelGGL((k_h_pass<T, N, 1, false, false>), grid, block, 0, st, p, h, mf, g, nullptr);
-  hipLaunchKernelGGL((k_h_pass<T, N, 2, false, true>), grid, block, 0, st, p, h, mf, g, eps_part);
+  hipLaunchKernelGGL((k_h_pass<T, N, 0, true, false, LP>), grid, block, 0, st, p, h, mf, g, nullptr);
+  hipLaunchKernelGGL((k_h_pass<T, N, 1, false, false, LP>), grid, block, 0, st, p, h, mf, g, nullptr);
+  hipLaunchKernelGGL((k_h_pass<T, N, 2, false, true, LP>), grid, block, 0, st, p, h, mf, g, eps_part);
+}
+
+// lines: 0 = default; else one of h_pass_lines(n, prec).  Returns the tile
+// count (workgroups per state) used, or 0 if lines is not supported.
+template <typename T, int N>
+static int launch_apply_h(const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf, GridArgs g,
+                          double* eps_part, int lines, hipStream_t st) {
+  constexpr int D = LineCfg<N>::LPW;
+  constexpr int H = (D / 2 > 0 && lines_ok<N>(D / 2, sizeof(cpx<T>))) ? D / 2 : D;
+  constexpr int W = lines_ok<N>(2 * D, sizeof(cpx<T>)) ? 2 * D : D;
+  if (lines == 0 || lines == D) { launch_h_lp<T, N, D>(psi, hpsi, nstate, mf, g, eps_part, st); return N * N / D; }
+  if (lines == H) { launch_h_lp<T, N, H>(psi, hpsi, nstate, mf, g, eps_part, st); return N * N / H; }
+  if (lines == W) { launch_h_lp<T, N, W>(psi, hpsi, nstate, mf, g, eps_part, st); return N * N / W; }
+  return 0;
+}
+
+template <typename T, int N> static void lines_list(int* out) {
+  constexpr int D = LineCfg<N>::LPW;
+  out[0] = (D / 2 > 0 && lines_ok<N>(D / 2, sizeof(cpx<T>))) ? D / 2 : D;
+  out[1] = D;
+  out[2] = lines_ok<N>(2 * D, sizeof(cpx<T>)) ? 2 * D : D;
 }
 
 int grid_ntiles(int n) {
   int r = 0;
   SKY_DISPATCH_N(n, r = ntiles<NN>());
-  return r;
+  return 2 * r;   // room for the h passes at half the default lines per workgroup
 }
 
-void apply_h(int n, int prec, const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf,
-             GridArgs g, double* eps_part, double* eps, hipStream_t st) {
-  if (nstate <= 0) return;
-  if (prec == 0) SKY_DISPATCH_N(n, launch_apply_h<double, NN>(psi, hpsi, nstate, mf, g, eps_part, st))
-  else SKY_DISPATCH_N(n, launch_apply_h<float, NN>(psi, hpsi, nstate, mf, g, eps_part, st))
-  if (eps_part && eps) {
-    int nt = grid_ntiles(n);
+void h_pass_lines(int n, int prec, int* out) {
+  if (prec == 0) SKY_DISPATCH_N(n, lines_list<double, NN>(out))
+  else SKY_DISPATCH_N(n, lines_list<float, NN>(out))
+}
+
+int apply_h(int n, int prec, const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf,
+            GridArgs g, double* eps_part, double* eps, hipStream_t st, int lines) {
+  if (nstate <= 0) return 1;
+  int nt = 0;
+  if (prec == 0) SKY_DISPATCH_N(n, nt = (launch_apply_h<double, NN>(psi, hpsi, nstate, mf, g, eps_part, lines, st)))
+  else SKY_DISPATCH_N(n, nt = (launch_apply_h<float, NN>(psi, hpsi, nstate, mf, g, eps_part, lines, st)))
+  if (nt == 0) return 0;
+  if (eps_part && eps)
     hipLaunchKernelGGL(k_sum_partials, dim3((nstate + 127) / 128), dim3(128), 0, st,
                        (const double*)eps_part, nt, nstate, eps);
-  }
+  return 1;
 }
 
 template <typename T, int N>
@@ -511,7 +546,8 @@ void damped_step(int n, int prec, const void* psi, const void* hpsi, const doubl
   DampArgs d{x0, e0, hb2m};
   if (prec == 0) SKY_DISPATCH_N(n, launch_damp<double, NN>(psi, hpsi, eps, phi, nstate, g, d, r2_part, st))
   else SKY_DISPATCH_N(n, launch_damp<float, NN>(psi, hpsi, eps, phi, nstate, g, d, r2_part, st))
-  int nt = grid_ntiles(n);
+  int nt = 0;
+  SKY_DISPATCH_N(n, nt = ntiles<NN>());
   hipLaunchKernelGGL(k_sum_partials, dim3((nstate + 127) / 128), dim3(128), 0, st,
                      (const double*)r2_part, nt, nstate, r2);
 }

@@ -620,7 +620,7 @@ void eig_sort(const void* D, const void* V, int m, int ld, double* w, void* Z, h
 }
 
 int loewdin_series(const void* Iv, void* Cv, void* Dv, void* Tv, int m, double max_dev,
-                   double* scratch, void* part, hipStream_t st) {
+                   double* scratch, void* part, hipStream_t st, int sq_split) {
   if (m <= 0) return 0;
   auto D = (double2*)Dv;
   const size_t mm = size_t(m) * m;
@@ -647,7 +647,7 @@ int loewdin_series(const void* Iv, void* Cv, void* Dv, void* Tv, int m, double m
   hipLaunchKernelGGL(k_axpy_identity, dim3(ge), dim3(256), 0, st, (const double2*)D, c[p], c[p - 1],
                      cur, m);
   for (int k = p - 2; k >= 0; --k) {
-    gemm_square(D, 0, cur, 0, nxt, m, st, part, 1);   // a polynomial in D: Hermitian
+    gemm_square(D, 0, cur, 0, nxt, m, st, part, 1, sq_split);   // a polynomial in D: Hermitian
     hipLaunchKernelGGL(k_add_identity, dim3((m + 255) / 256), dim3(256), 0, st, nxt, c[k], m);
     std::swap(cur, nxt);
   }

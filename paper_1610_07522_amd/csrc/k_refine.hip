@@ -526,7 +526,7 @@ size_t refine_scratch_bytes(int m) {
 }
 
 int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double tol, int maxit,
-                hipStream_t st) {
+                hipStream_t st, int sq_split) {
   if (m <= 0) return 0;
   RefineWork r = carve(work, m);
   const double2* A = static_cast<const double2*>(Av);
@@ -542,9 +542,9 @@ int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double to
     const double2* Rp = nullptr;
     double tau = 0.0;
     if (it > 0) {
-      gemm_square(X, 1, X, 0, R, m, st, r.gpart, 1);
-      gemm_square(A, 0, X, 0, T, m, st, r.gpart);
-      gemm_square(X, 1, T, 0, S, m, st, r.gpart, 1);
+      gemm_square(X, 1, X, 0, R, m, st, r.gpart, 1, sq_split);
+      gemm_square(A, 0, X, 0, T, m, st, r.gpart, 0, sq_split);
+      gemm_square(X, 1, T, 0, S, m, st, r.gpart, 1, sq_split);
       hipLaunchKernelGGL(k_ref_check, dim3(ncheck), dim3(256), 0, st, S, R, m, r.part);
       hipLaunchKernelGGL(k_ref_check_final, dim3(1), dim3(64), 0, st, (const double*)r.part,
                          int(ncheck), r.norms);
@@ -587,13 +587,13 @@ int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double to
       std::memcpy(&em, &eb, sizeof(em));
       second = !(em <= E2_SKIP);
     }
-    if (second) gemm_square(E, 0, E, 0, T, m, st, r.gpart);
+    if (second) gemm_square(E, 0, E, 0, T, m, st, r.gpart, 0, sq_split);
     hipLaunchKernelGGL(k_ref_build_q, dim3(gm, unsigned(m)), dim3(256), 0, st, (const double2*)E,
                        second ? (const double2*)T : nullptr, m, cl, Q);
     if (it == 0) {
       std::swap(X, Q);
     } else {
-      gemm_square(X, 0, Q, 0, Xn, m, st, r.gpart);
+      gemm_square(X, 0, Q, 0, Xn, m, st, r.gpart, 0, sq_split);
       std::swap(X, Xn);
     }
   }

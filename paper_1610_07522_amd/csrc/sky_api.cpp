@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -156,6 +157,9 @@ struct sky_ctx {
   Skyrme sk;
   int last_sweeps;     // eigensolver iterations of the last iteration
   int fallbacks;       // refinement -> Jacobi fallbacks in the current call
+  // launch shapes (0 = the built-in default): h-pass lines per workgroup,
+  // overlap and square-product split-K factors per species
+  struct Tune { int lines = 0; int ovl[2] = {0, 0}; int sq[2] = {0, 0}; int from_cache = 0; } tune;
   int64_t iter_count = 0;     // iterations run on this context
   int64_t switched_at = -1;   // iteration after which the ladder switched to FP64
   // phase timing: HIP event pairs on the context stream
@@ -265,10 +269,10 @@ int rayleigh_ritz(sky_ctx* c, int q, const void* phi, const void* hphi, void* ps
   if (c->prec)
     overlap_lower_planes(c->at(c->lay.plA), c->at(c->lay.plA), c->at(c->lay.plB), mx, mx, mx + 1,
                          m, c->V, c->g.dV, I, H, c->at(c->lay.gemm_part), st,
-                         c->timing ? ev : nullptr);
+                         c->timing ? ev : nullptr, c->tune.ovl[q]);
   else
     overlap_lower(phi, phi, hphi, m, c->V, c->g.dV, I, H, c->at(c->lay.gemm_part), st,
-                  c->timing ? ev : nullptr);
+                  c->timing ? ev : nullptr, c->tune.ovl[q]);
   const int ts = t_begin(c, SKY_PHASE_SUBSPACE, q);
   hermitian_fill(I, m, st);
   hermitian_fill(H, m, st);
@@ -278,29 +282,30 @@ int rayleigh_ritz(sky_ctx* c, int q, const void* phi, const void* hphi, void* ps
   // Cholesky factor I = L L^H.
   void* Cw = c->at(c->lay.matC);
   void* sq = c->at(c->lay.sq_part);
+  const int sqs = c->tune.sq[q];
   const int terms = loewdin_series(I, Linv, Cw, T, m, LOEWDIN_SERIES_MAX,
-                                   c->at<double>(c->lay.nrm), sq, st);
+                                   c->at<double>(c->lay.nrm), sq, st, sqs);
   if (terms > 0) {   // C = I^-1/2 (Hermitian) in Linv
-    gemm_square(Linv, 0, H, 0, T, m, st, sq);
-    gemm_square(T, 0, Linv, 0, Hp, m, st, sq, 1);
+    gemm_square(Linv, 0, H, 0, T, m, st, sq, 0, sqs);
+    gemm_square(T, 0, Linv, 0, Hp, m, st, sq, 1, sqs);
   } else {           // Linv = L^-1, C = L^-H
     hipMemcpyAsync(Cw, I, size_t(m) * m * 16, hipMemcpyDeviceToDevice, st);
     cholesky_inverse(Cw, Linv, m, c->at(c->lay.chol_work), info, st);
-    gemm_square(Linv, 0, H, 0, T, m, st, sq);
-    gemm_square(T, 0, Linv, 1, Hp, m, st, sq, 1);
+    gemm_square(Linv, 0, H, 0, T, m, st, sq, 0, sqs);
+    gemm_square(T, 0, Linv, 1, Hp, m, st, sq, 1, sqs);
   }
   hermitian_fill(Hp, m, st);   // exact Hermitian symmetry of H' before the eigensolver
   int rc = check_info(c, "cholesky");
   if (rc) return rc;
   double* w = ritz ? ritz : c->at<double>(c->lay.ritz[q]);
-  int its = refine_eigh(Hp, m, w, Z, c->at(c->lay.ref_work), JACOBI_TOL, REFINE_ITERS, st);
+  int its = refine_eigh(Hp, m, w, Z, c->at(c->lay.ref_work), JACOBI_TOL, REFINE_ITERS, st, sqs);
   if (its < 0) {   // a wide cluster or no convergence: blocked Jacobi from H'
     ++c->fallbacks;
     its = jacobi_eigh(Hp, m, w, Z, c->at(c->lay.jac_work), JACOBI_TOL, JACOBI_SWEEPS, st);
   }
   c->last_sweeps += its;
   // steps 3d-3e: U = C Z, psi = phi U
-  gemm_square(Linv, terms > 0 ? 0 : 1, Z, 0, U, m, st, sq);
+  gemm_square(Linv, terms > 0 ? 0 : 1, Z, 0, U, m, st, sq, 0, sqs);
   if (c->prec) {
     plane_scale(U, 1, size_t(m) * m, mx + 2, st);
     split_planes_t(U, 1, m, m, mx + 2, c->at(c->lay.plU), st);
@@ -330,9 +335,11 @@ int loewdin(sky_ctx* c, int q, const void* phi, void* psi_out) {
     split_planes_nt(phi, m, c->V, mx, c->at(c->lay.plA), st);
     split_planes_t(phi, 0, m, c->V, mx, c->at(c->lay.plT), st);
     overlap_lower_planes(c->at(c->lay.plA), c->at(c->lay.plA), nullptr, mx, mx, nullptr, m,
-                         c->V, c->g.dV, I, nullptr, c->at(c->lay.gemm_part), st);
+                         c->V, c->g.dV, I, nullptr, c->at(c->lay.gemm_part), st, nullptr,
+                         c->tune.ovl[q]);
   } else
-    overlap_lower(phi, phi, nullptr, m, c->V, c->g.dV, I, nullptr, c->at(c->lay.gemm_part), st);
+    overlap_lower(phi, phi, nullptr, m, c->V, c->g.dV, I, nullptr, c->at(c->lay.gemm_part), st,
+                  nullptr, c->tune.ovl[q]);
   hermitian_fill(I, m, st);
   jacobi_eigh(I, m, w, X, c->at(c->lay.jac_work), JACOBI_TOL, JACOBI_SWEEPS, st);
   // C = X diag(w^-1/2) X^H
@@ -341,7 +348,7 @@ int loewdin(sky_ctx* c, int q, const void* phi, void* psi_out) {
   hipMemcpyAsync(wi, w, sizeof(double) * m, hipMemcpyDeviceToDevice, st);
   inv_sqrt(wi, m, info, st);
   scale_columns(c->at(c->lay.matT), wi, m, st);
-  gemm_square(c->at(c->lay.matT), 0, X, 1, C, m, st, c->at(c->lay.sq_part), 1);
+  gemm_square(c->at(c->lay.matT), 0, X, 1, C, m, st, c->at(c->lay.sq_part), 1, c->tune.sq[q]);
   int rc = check_info(c, "loewdin");
   if (rc) return rc;
   if (c->prec) {
@@ -370,7 +377,90 @@ void fields(sky_ctx* c) {
              c->at<double>(c->lay.energy), st);
   t_end(c, tmf);
 }
+// ------------------------------------------------------------------ autotuning
+// Flat JSON cache {"key": integer, ...}; keys name the operation, its sizes
+// and the precision.  Unreadable or absent files count as empty.
+std::vector<std::pair<std::string, int>> cache_read(const char* path) {
+  std::vector<std::pair<std::string, int>> kv;
+  if (!path) return kv;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return kv;
+  std::string txt;
+  char buf[4096];
+  size_t nread;
+  while ((nread = std::fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, nread);
+  std::fclose(f);
+  size_t i = 0;
+  while ((i = txt.find('"', i)) != std::string::npos) {
+    const size_t j = txt.find('"', i + 1);
+    if (j == std::string::npos) break;
+    const std::string key = txt.substr(i + 1, j - i - 1);
+    size_t k = txt.find(':', j);
+    if (k == std::string::npos) break;
+    ++k;
+    while (k < txt.size() && (txt[k] == ' ' || txt[k] == '\t' || txt[k] == '\n')) ++k;
+    char* end = nullptr;
+    const long v = std::strtol(txt.c_str() + k, &end, 10);
+    if (end != txt.c_str() + k) kv.emplace_back(key, int(v));
+    i = end ? size_t(end - txt.c_str()) : j + 1;
+  }
+  return kv;
+}
+
+bool cache_write(const char* path, const std::vector<std::pair<std::string, int>>& kv) {
+  if (!path) return true;
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  std::fprintf(f, "{\n");
+  for (size_t i = 0; i < kv.size(); ++i)
+    std::fprintf(f, "  \"%s\": %d%s\n", kv[i].first.c_str(), kv[i].second, i + 1 < kv.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  std::fclose(f);
+  return std::rename(tmp.c_str(), path) == 0;
+}
+
+int cache_get(const std::vector<std::pair<std::string, int>>& kv, const std::string& key) {
+  for (const auto& e : kv)
+    if (e.first == key) return e.second;
+  return 0;
+}
+
+void cache_put(std::vector<std::pair<std::string, int>>& kv, const std::string& key, int v) {
+  for (auto& e : kv)
+    if (e.first == key) { e.second = v; return; }
+  kv.emplace_back(key, v);
+}
+
+// Mean milliseconds of `reps` runs of op (after one untimed run).
+template <typename F> double time_op(hipStream_t st, int reps, F op) {
+  hipEvent_t a, b;
+  hipEventCreate(&a);
+  hipEventCreate(&b);
+  op();
+  hipEventRecord(a, st);
+  for (int r = 0; r < reps; ++r) op();
+  hipEventRecord(b, st);
+  hipEventSynchronize(b);
+  float ms = 0.0f;
+  hipEventElapsedTime(&ms, a, b);
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return double(ms) / reps;
+}
+
+// Fastest candidate of op(candidate).
+template <typename F> int pick(hipStream_t st, const int* cand, int nc, F op) {
+  int best = cand[0];
+  double tb = 1e300;
+  for (int i = 0; i < nc; ++i) {
+    const double t = time_op(st, 3, [&] { op(cand[i]); });
+    if (t < tb) { tb = t; best = cand[i]; }
+  }
+  return best;
+}
 }  // namespace
+
 
 extern "C" {
 
@@ -449,7 +539,7 @@ int sky_apply_h(sky_ctx* c, int32_t q, const void* psi, void* hpsi, int32_t nsta
   if (!c || q < 0 || q > 1 || !psi || !hpsi || nstates < 0) return fail(SKY_ERR_INVALID, "apply_h arguments");
   if (nstates > c->nq[q]) return fail(SKY_ERR_INVALID, "apply_h: more states than the species holds");
   apply_h(c->n, c->prec, psi, hpsi, nstates, c->mfp(q), c->g,
-          eps ? c->at<double>(c->lay.tiles) : nullptr, eps, c->st);
+          eps ? c->at<double>(c->lay.tiles) : nullptr, eps, c->st, c->tune.lines);
   return hip_check(hipGetLastError(), "apply_h launch");
 }
 
@@ -500,7 +590,7 @@ int sky_iterate(sky_ctx* c, int32_t max_iter, double tol, sky_report* rep) {
       double* tiles = c->at<double>(c->lay.tiles);
       // step 2: h psi, <h>, damped step, h phi
       int t0 = t_begin(c, SKY_PHASE_APPLY_H, q);
-      apply_h(c->n, c->prec, psi, hpsi, m, c->mfp(q), c->g, tiles, eps, st);
+      apply_h(c->n, c->prec, psi, hpsi, m, c->mfp(q), c->g, tiles, eps, st, c->tune.lines);
       t_end(c, t0);
       const double hb = q ? c->d.hb2m_p : c->d.hb2m_n;
       int t1 = t_begin(c, SKY_PHASE_DAMP, q);
@@ -508,7 +598,7 @@ int sky_iterate(sky_ctx* c, int32_t max_iter, double tol, sky_report* rep) {
                   tiles, c->at<double>(c->lay.r2[q]), st);
       t_end(c, t1);
       int t2 = t_begin(c, SKY_PHASE_APPLY_H, q);
-      apply_h(c->n, c->prec, phi, hphi, m, c->mfp(q), c->g, nullptr, nullptr, st);
+      apply_h(c->n, c->prec, phi, hphi, m, c->mfp(q), c->g, nullptr, nullptr, st, c->tune.lines);
       t_end(c, t2);
       // steps 3a-3e
       int rc = rayleigh_ritz(c, q, phi, hphi, psi, c->at<double>(c->lay.ritz[q]));
@@ -633,6 +723,106 @@ void sky_destroy(sky_ctx* c) {
   for (auto& m : c->marks) { hipEventDestroy(m.a); hipEventDestroy(m.b); }
   for (auto e : c->pool) hipEventDestroy(e);
   delete c;
+}
+
+int sky_autotune(sky_ctx* c, const char* cache_path, sky_tuning* out) {
+  if (!c) return fail(SKY_ERR_INVALID, "null context");
+  hipStream_t st = c->st;
+  int rc = hip_check(hipStreamSynchronize(st), "autotune");
+  if (rc) return rc;
+  auto kv = cache_read(cache_path);
+  const char* pr = c->prec ? "mixed" : "fp64";
+  const std::string klines = "h_lines/n" + std::to_string(c->n) + "/" + pr;
+  std::string kovl[2], ksq[2];
+  for (int q = 0; q < 2; ++q) {
+    kovl[q] = "overlap_split/m" + std::to_string(c->nq[q]) + "/k" + std::to_string(c->V) + "/" + pr;
+    ksq[q] = "square_split/m" + std::to_string(c->nq[q]);
+  }
+  int timed = 0;
+  // lines per workgroup of the h passes (species 0, or 1 if 0 is empty)
+  {
+    const int q = c->nq[0] > 0 ? 0 : 1;
+    int v = cache_get(kv, klines);
+    int cand[3];
+    h_pass_lines(c->n, c->prec, cand);
+    bool ok = false;
+    for (int i = 0; i < 3; ++i) ok = ok || cand[i] == v;
+    if (!ok) {
+      v = pick(st, cand, 3, [&](int lp) {
+        apply_h(c->n, c->prec, c->psi(q), c->hpsi(q), c->nq[q], c->mfp(q), c->g, nullptr, nullptr,
+                st, lp);
+      });
+      cache_put(kv, klines, v);
+      ++timed;
+    }
+    c->tune.lines = v;
+  }
+  for (int q = 0; q < 2; ++q) {
+    const int m = c->nq[q];
+    if (m == 0) continue;
+    // overlap split-K
+    int cand[3];
+    const int nc = c->prec ? overlap_split_candidates_mixed(m, c->V, cand)
+                           : overlap_split_candidates(m, c->V, cand);
+    int v = cache_get(kv, kovl[q]);
+    bool ok = false;
+    for (int i = 0; i < nc; ++i) ok = ok || cand[i] == v;
+    if (!ok) {
+      void* I = c->at(c->lay.matI);
+      void* H = c->at(c->lay.matH);
+      if (c->prec) {
+        unsigned int* mx = c->at<unsigned int>(c->lay.plS);
+        plane_scale(c->psi(q), 0, size_t(m) * c->V, mx, st);
+        split_planes_nt(c->psi(q), m, c->V, mx, c->at(c->lay.plA), st);
+        v = pick(st, cand, nc, [&](int sp) {
+          overlap_lower_planes(c->at(c->lay.plA), c->at(c->lay.plA), c->at(c->lay.plA), mx, mx, mx,
+                               m, c->V, c->g.dV, I, H, c->at(c->lay.gemm_part), st, nullptr, sp);
+        });
+      } else {
+        v = pick(st, cand, nc, [&](int sp) {
+          overlap_lower(c->psi(q), c->psi(q), c->psi(q), m, c->V, c->g.dV, I, H,
+                        c->at(c->lay.gemm_part), st, nullptr, sp);
+        });
+      }
+      cache_put(kv, kovl[q], v);
+      ++timed;
+    }
+    c->tune.ovl[q] = v;
+    // square-product split-K
+    int cs[4];
+    const int ns = square_split_candidates(m, cs);
+    v = cache_get(kv, ksq[q]);
+    ok = false;
+    for (int i = 0; i < ns; ++i) ok = ok || cs[i] == v;
+    if (!ok) {
+      v = pick(st, cs, ns, [&](int sp) {
+        gemm_square(c->at(c->lay.matI), 1, c->at(c->lay.matH), 0, c->at(c->lay.matT), m, st,
+                    c->at(c->lay.sq_part), 0, sp);
+      });
+      cache_put(kv, ksq[q], v);
+      ++timed;
+    }
+    c->tune.sq[q] = v;
+  }
+  rc = hip_check(hipStreamSynchronize(st), "autotune runs");
+  if (rc) return rc;
+  c->tune.from_cache = timed == 0;
+  if (timed && !cache_write(cache_path, kv)) return fail(SKY_ERR_INVALID, "cannot write the tuning cache");
+  return sky_get_tuning(c, out);
+}
+
+int sky_get_tuning(sky_ctx* c, sky_tuning* out) {
+  if (!c) return fail(SKY_ERR_INVALID, "null context");
+  if (!out) return SKY_OK;
+  int cand[3];
+  h_pass_lines(c->n, c->prec, cand);
+  out->h_lines = c->tune.lines ? c->tune.lines : cand[1];
+  for (int q = 0; q < 2; ++q) {
+    out->overlap_split[q] = c->tune.ovl[q];
+    out->square_split[q] = c->tune.sq[q];
+  }
+  out->from_cache = c->tune.from_cache;
+  return SKY_OK;
 }
 
 }  // extern "C"

@@ -8,8 +8,12 @@ namespace sky {
 // ---- grid kernels (k_grid.hip); states are [state][2][n^3], complex128
 // (prec 0) or complex64 (prec 1); reductions are FP64 either way.
 int grid_ntiles(int n);  // workgroups per state of one line pass
-void apply_h(int n, int prec, const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf,
-             GridArgs g, double* eps_part, double* eps, hipStream_t st);
+// lines: lines (pencils) per workgroup of the h passes, 0 = default, else one
+// of h_pass_lines(n, prec) (out[3]: half, default, double where possible).
+// Returns 0 if lines is not supported (nothing launched).
+void h_pass_lines(int n, int prec, int* out);
+int apply_h(int n, int prec, const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf,
+            GridArgs g, double* eps_part, double* eps, hipStream_t st, int lines = 0);
 void damped_step(int n, int prec, const void* psi, const void* hpsi, const double* eps,
                  void* phi, int nstate, GridArgs g, double x0, double e0, double hb2m,
                  double* r2_part, double* r2, hipStream_t st);
@@ -43,8 +47,11 @@ size_t mean_field_scratch_bytes(int n);
 // part: split * 2 * ntile_pairs * 64*64 complex scratch.
 size_t overlap_scratch_bytes(int m, long k);
 // ev (may be null): events recorded right before / after the GEMM kernel.
+// split_req > 0 overrides the split-K factor (one of overlap_split_candidates).
+int overlap_split_candidates(int m, long k, int* out);
 void overlap_lower(const void* A, const void* B0, const void* B1, int m, long k, double scale,
-                   void* C0, void* C1, void* part, hipStream_t st, hipEvent_t* ev = nullptr);
+                   void* C0, void* C1, void* part, hipStream_t st, hipEvent_t* ev = nullptr,
+                   int split_req = 0);
 // FP64 reduction of split-K partials into the lower tiles of C0 (and C1).
 void overlap_reduce(const void* part, int npair, int split, int m, double scale, void* C0,
                     void* C1, int nz, hipStream_t st);
@@ -65,10 +72,13 @@ void split_planes_nt(const void* x, int rows, long k, const unsigned int* mx, vo
 void split_planes_t(const void* x, int x_is_c128, int rows, long cols, const unsigned int* mx,
                     void* P, hipStream_t st);
 // C0 = scale * conj(A) B0^T (and C1 with B1), lower 64-tiles, from NT planes.
+// split_req > 0 overrides the split-K factor (one of overlap_split_candidates_mixed).
+int overlap_split_candidates_mixed(int m, long k, int* out);
 void overlap_lower_planes(const void* PA, const void* PB0, const void* PB1,
                           const unsigned int* mxA, const unsigned int* mxB0,
                           const unsigned int* mxB1, int m, long k, double scale, void* C0,
-                          void* C1, void* part, hipStream_t st, hipEvent_t* ev = nullptr);
+                          void* C1, void* part, hipStream_t st, hipEvent_t* ev = nullptr,
+                          int split_req = 0);
 // Y[b][v] = sum_a U[a][b] X[a][v] from the transposed planes of U (m x m)
 // and of X (m x k).
 void combine_planes(const void* PU, const void* PX, const unsigned int* mxU,
@@ -84,8 +94,10 @@ void combine(const void* X, const void* U, void* Y, int m, long k, hipStream_t s
 // the product is known to be Hermitian; only its lower tiles are computed and
 // the upper triangle is mirrored from them (C exactly Hermitian).
 size_t gemm_square_scratch_bytes(int m);
+// split_req > 0 overrides the split-K factor (one of square_split_candidates).
+int square_split_candidates(int m, int* out);
 void gemm_square(const void* A, int opA, const void* B, int opB, void* C, int m, hipStream_t st,
-                 void* part = nullptr, int herm = 0);
+                 void* part = nullptr, int herm = 0, int split_req = 0);
 
 // ---- eigenvector refinement (k_refine.hip)
 // Hermitian eigen-decomposition of a nearly diagonal A (m x m, not modified)
@@ -97,7 +109,7 @@ void gemm_square(const void* A, int opA, const void* B, int opB, void* C, int m,
 // max |Z^H Z - 1| below 1e-13.  Synchronises the stream once per step.
 size_t refine_scratch_bytes(int m);
 int refine_eigh(const void* A, int m, double* w, void* Z, void* work, double tol, int maxit,
-                hipStream_t st);
+                hipStream_t st, int sq_split = 0);
 
 // ---- dense FP64 linear algebra (k_linalg.hip)
 // Cholesky A = L L^H of Hermitian positive definite A (m x m, lower used),
@@ -118,7 +130,7 @@ int jacobi_eigh(void* A, int m, double* w, void* Z, void* work, double tol, int 
 // are m x m work matrices, scratch >= 257 doubles, part the square-product
 // scratch (gemm_square); synchronises the stream.
 int loewdin_series(const void* I, void* C, void* D, void* T, int m, double max_dev,
-                   double* scratch, void* part, hipStream_t st);
+                   double* scratch, void* part, hipStream_t st, int sq_split = 0);
 // w ascending (ties by index) from the diagonal of D (ld = ld) and Z the
 // matching columns of V (ld = ld), Z m x m.
 void eig_sort(const void* D, const void* V, int m, int ld, double* w, void* Z, hipStream_t st);

@@ -34,7 +34,7 @@ _MATRIX_VIEWS = ("overlap", "hsub", "evec", "umat")
 EXPORTS = ("sky_workspace_size", "sky_create", "sky_init_box", "sky_apply_h",
            "sky_damped_step", "sky_orthonormalize", "sky_densities", "sky_iterate",
            "sky_get_view", "sky_set_timing", "sky_get_timing", "sky_get_precision",
-           "sky_sync", "sky_last_error", "sky_destroy")
+           "sky_autotune", "sky_get_tuning", "sky_sync", "sky_last_error", "sky_destroy")
 PHASES = ("apply_h", "damp", "overlap_gemm", "subspace", "combine_gemm", "densities",
           "meanfield", "split")
 
@@ -58,6 +58,15 @@ class Report(ctypes.Structure):
                 ("energy", ctypes.c_double), ("energy_per_a", ctypes.c_double),
                 ("eig_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("eig_fallbacks", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("h_lines", ctypes.c_int32), ("overlap_split", ctypes.c_int32 * 2),
+                ("square_split", ctypes.c_int32 * 2), ("from_cache", ctypes.c_int32)]
+
+    def as_dict(self) -> Dict[str, object]:
+        return dict(h_lines=self.h_lines, overlap_split=list(self.overlap_split),
+                    square_split=list(self.square_split), from_cache=bool(self.from_cache))
 
 
 class SkyError(RuntimeError):
@@ -97,6 +106,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "sky_get_timing": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_int64)]),
         "sky_get_precision": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int32)]),
+        "sky_autotune": (ctypes.c_int, [vp, ctypes.c_char_p, ctypes.POINTER(Tuning)]),
+        "sky_get_tuning": (ctypes.c_int, [vp, ctypes.POINTER(Tuning)]),
         "sky_sync": (ctypes.c_int, [vp]),
         "sky_last_error": (ctypes.c_char_p, []),
         "sky_destroy": (None, [vp]),
@@ -193,6 +204,17 @@ class Box:
         p = ctypes.c_int32()
         _check(self.lib.sky_get_precision(self.ctx, ctypes.byref(p)))
         return p.value
+
+    def autotune(self, cache_path: Optional[str] = None) -> Dict[str, object]:
+        t = Tuning()
+        p = cache_path.encode() if cache_path else None
+        _check(self.lib.sky_autotune(self.ctx, p, ctypes.byref(t)))
+        return t.as_dict()
+
+    def tuning(self) -> Dict[str, object]:
+        t = Tuning()
+        _check(self.lib.sky_get_tuning(self.ctx, ctypes.byref(t)))
+        return t.as_dict()
 
     def sync(self):
         _check(self.lib.sky_sync(self.ctx))
