@@ -94,6 +94,8 @@ typedef struct {
   int32_t precision;      /* precision of the states after the call             */
   int32_t eig_fallbacks;  /* subspace eigensolves of this call that fell back   */
                           /* from the refinement to the Jacobi solver           */
+  int32_t precond_iters;  /* iterations of this call whose damped step used     */
+                          /* the learned gains (sky_precond_use)                */
 } sky_report;
 
 /* Views into the context's device buffers (sky_get_view). */
@@ -116,7 +118,12 @@ enum {
   SKY_VIEW_OVERLAP = 11,  /* I = <phi|phi> (Eq. normmatrix)                      */
   SKY_VIEW_HSUB = 12,     /* H = <phi|h phi> (Eq. hammatrix); unset by Loewdin   */
   SKY_VIEW_EVEC = 13,     /* eigenvectors (columns) of H' (or of I for Loewdin)  */
-  SKY_VIEW_UMAT = 14      /* combined transform U, psi = phi U                   */
+  SKY_VIEW_UMAT = 14,     /* combined transform U, psi = phi U                   */
+  SKY_VIEW_PC_PARAMS = 15,  /* learned damping: FP32 master parameters [P] (f32)   */
+  SKY_VIEW_PC_GRAD = 16,    /* gradient of the last loss evaluation [P] (f32)      */
+  SKY_VIEW_PC_SAMPLES = 17, /* sample rows [16384][6] f32: 4 features, target     */
+                            /* gain, weight (sky_precond_collect fills them)       */
+  SKY_VIEW_PC_GAINS = 18    /* gains [n_q][8] of the last learned step (f32)       */
 };
 
 /* Timed phases of one iteration (sky_set_timing / sky_get_timing). */
@@ -242,6 +249,39 @@ int sky_autotune(sky_ctx* c, const char* cache_path, sky_tuning* out);
 
 /* Launch shapes in use (defaults until sky_autotune). */
 int sky_get_tuning(sky_ctx* c, sky_tuning* out);
+
+/* Learned spectral preconditioner (an extension of Eq. dampstep, whose
+ * damping x0 / (E0 + T_k) is fixed in the paper).  The learned step scales
+ * the damping of state alpha in |k| shell s (8 equal |k| shells up to the
+ * zone corner) by g = 4 sigmoid(MLP(|k_s| / |k|max, <h>_alpha / E0,
+ * log10 share of the residual power in s, T(k_s) / E0)); the MLP is
+ * 4-128-128-128-1, ReLU, BF16 weights, FP32 accumulation.
+ *
+ * sky_precond_collect: training rows from the current states of species q
+ * (up to 32 sampled states x 8 shells): features, the target gains that
+ * minimise the first-order residual |r - sum_s g_s (h - <h>) d_s|^2 of the
+ * shell-restricted plain steps d_s, and the weights (residual share).
+ * Overwrites h psi; *total = rows held (at most 16384; once the end is
+ * reached, new rows overwrite the oldest from row 0).
+ * sky_precond_train: Adam (lr) over all rows, weighted mean square error of
+ * the gains; *loss = loss before the last update.
+ * sky_precond_loss_grad: loss of the first nsamples rows and its gradient
+ * (SKY_VIEW_PC_GRAD), parameters unchanged.
+ * sky_precond_set_rows: declare the first nrows sample rows valid (rows
+ * written by the caller through SKY_VIEW_PC_SAMPLES); 0 drops every row.
+ * sky_precond_use: sky_iterate then takes the learned step; when the
+ * residual Delta-eps after a learned step exceeds (1 + rise_tol) times the
+ * one before it, the next 10 iterations use the plain damping (rise_tol = 0:
+ * any rise; negative: never).  With retrain_every > 0, every retrain_every
+ * iterations sky_iterate also collects rows from both species and takes 20
+ * Adam steps (step size of the last sky_precond_train).  All synchronise
+ * the stream.
+ * Errors: SKY_ERR_INVALID (arguments, no rows, untrained network), SKY_ERR_HIP. */
+int sky_precond_collect(sky_ctx* c, int32_t q, int32_t* total);
+int sky_precond_train(sky_ctx* c, int32_t steps, double lr, double* loss);
+int sky_precond_loss_grad(sky_ctx* c, int32_t nsamples, double* loss);
+int sky_precond_set_rows(sky_ctx* c, int32_t nrows);
+int sky_precond_use(sky_ctx* c, int32_t enable, double rise_tol, int32_t retrain_every);
 
 /* Wait for all work of the context's stream. */
 int sky_sync(sky_ctx* c);

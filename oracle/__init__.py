@@ -11,4 +11,4 @@ library steps.  Where the paper is schematic the reading used is stated in
 the docstring of the function that takes it.
 """
 from .grid import Grid  # noqa: F401
-from . import grid, physics, solver  # noqa: F401
+from . import grid, physics, precond, solver  # noqa: F401

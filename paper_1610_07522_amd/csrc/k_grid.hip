@@ -239,15 +239,23 @@ k_damp_y(cpx<T>* __restrict__ buf) {
 
 // forward FFT along z, multiply by x0 / (E0 + hb2m |k|^2), inverse along z.
 // The line's x and y indices are frequency indices at this point.
-template <typename T, int N>
+//   MODE 0: plain damping.
+//   MODE 1: read only: add the state's spectral power per |k| shell,
+//           sum |F r(k)|^2 over both spinor components, to pow[state][shell].
+//   MODE 2: damping times gain[state][shell(k)] (learned preconditioner, or
+//           one-hot rows that restrict the step to one shell).
+template <typename T, int N, int MODE>
 __global__ void __launch_bounds__(LineCfg<N>::THREADS)
-k_damp_z(cpx<T>* __restrict__ buf, GridArgs g, DampArgs d) {
+k_damp_z(cpx<T>* __restrict__ buf, GridArgs g, DampArgs d, const float* __restrict__ gain,
+         double* __restrict__ pow) {
   using C = LineCfg<N>;
   using F = LineFFT<T, N, 2>;
   constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
   __shared__ cpx<T> tw[N];
   __shared__ cpx<T> Ybuf[C::LPW * F::YSIZE];
+  __shared__ double spow[PC_SHELLS];
   load_twiddles<T, N>(tw);
+  if (MODE == 1 && threadIdx.x < PC_SHELLS) spow[threadIdx.x] = 0.0;
   int line, j;
   thread_role<N, 2>(threadIdx.x, line, j);
   const int L = blockIdx.x * C::LPW + line;
@@ -262,17 +270,51 @@ k_damp_z(cpx<T>* __restrict__ buf, GridArgs g, DampArgs d) {
 #pragma unroll
       for (int s = 0; s < 2; ++s) va[s][j1] = p[s * N3 + base + (j + R2 * j1) * stride];
   F::forward(va, vb, Y, j, tw);
+  double lpow[PC_SHELLS];
+  if (MODE == 1)
+#pragma unroll
+    for (int s = 0; s < PC_SHELLS; ++s) lpow[s] = 0.0;
   if (j < R1) {
-    double kx = g.kunit * double(a < N / 2 ? a : a - N);
-    double ky = g.kunit * double(b < N / 2 ? b : b - N);
+    const int ia = a < N / 2 ? a : a - N, ib = b < N / 2 ? b : b - N;
+    double kx = g.kunit * double(ia);
+    double ky = g.kunit * double(ib);
 #pragma unroll
     for (int k2 = 0; k2 < R2; ++k2) {
       int f = j + R1 * k2;
-      double kz = g.kunit * double(f < N / 2 ? f : f - N);
-      T m = T(d.x0 / (d.e0 + d.hb2m * (kx * kx + ky * ky + kz * kz)));
+      const int ic = f < N / 2 ? f : f - N;
+      double kz = g.kunit * double(ic);
+      const double kk = kx * kx + ky * ky + kz * kz;
+      const int m2 = ia * ia + ib * ib + ic * ic;
+      if (MODE == 1) {
+        const int sh = k_shell(m2, N);
+        double pw = 0.0;
 #pragma unroll
-      for (int s = 0; s < 2; ++s) vb[s][k2] = m * vb[s][k2];
+        for (int s = 0; s < 2; ++s)
+          pw += double(vb[s][k2].re) * double(vb[s][k2].re) + double(vb[s][k2].im) * double(vb[s][k2].im);
+#pragma unroll
+        for (int s = 0; s < PC_SHELLS; ++s) lpow[s] += (s == sh) ? pw : 0.0;
+      } else {
+        double mm = d.x0 / (d.e0 + d.hb2m * kk);
+        if (MODE == 2) mm *= double(gain[size_t(blockIdx.y) * PC_SHELLS + k_shell(m2, N)]);
+        const T m = T(mm);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) vb[s][k2] = m * vb[s][k2];
+      }
     }
+  }
+  if (MODE == 1) {
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < PC_SHELLS; ++s) {
+      double v = lpow[s];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      if ((threadIdx.x & 63) == 0) atomicAdd(&spow[s], v);
+    }
+    __syncthreads();
+    if (threadIdx.x < PC_SHELLS)
+      atomicAdd(&pow[size_t(blockIdx.y) * PC_SHELLS + threadIdx.x], spow[threadIdx.x]);
+    return;
   }
   F::inverse(vb, va, Y, j, tw);
   if (j < R2)
@@ -525,31 +567,46 @@ int apply_h(int n, int prec, const void* psi, void* hpsi, int nstate, MeanFieldP
   return 1;
 }
 
+// stage 0: the whole step; 1: residual, forward x and y and (with shell_pow)
+// the shell powers, leaving the partial spectrum in phi; 2: the z filter
+// (with gain) and the inverse passes, continuing from stage 1.
 template <typename T, int N>
 static void launch_damp(const void* psi, const void* hpsi, const double* eps, void* phi,
-                        int nstate, GridArgs g, DampArgs d, double* r2_part, hipStream_t st) {
+                        int nstate, GridArgs g, DampArgs d, double* r2_part, const float* gain,
+                        double* shell_pow, int stage, hipStream_t st) {
   dim3 grid(ntiles<N>(), nstate), block(LineCfg<N>::THREADS);
   auto p = reinterpret_cast<const cpx<T>*>(psi);
   auto h = reinterpret_cast<const cpx<T>*>(hpsi);
   auto o = reinterpret_cast<cpx<T>*>(phi);
-  hipLaunchKernelGGL((k_damp_fwd_x<T, N>), grid, block, 0, st, p, h, eps, o, g, r2_part);
-  hipLaunchKernelGGL((k_damp_y<T, N, false>), grid, block, 0, st, o);
-  hipLaunchKernelGGL((k_damp_z<T, N>), grid, block, 0, st, o, g, d);
+  if (stage != 2) {
+    hipLaunchKernelGGL((k_damp_fwd_x<T, N>), grid, block, 0, st, p, h, eps, o, g, r2_part);
+    hipLaunchKernelGGL((k_damp_y<T, N, false>), grid, block, 0, st, o);
+    if (shell_pow)
+      hipLaunchKernelGGL((k_damp_z<T, N, 1>), grid, block, 0, st, o, g, d, nullptr, shell_pow);
+  }
+  if (stage == 1) return;
+  if (gain)
+    hipLaunchKernelGGL((k_damp_z<T, N, 2>), grid, block, 0, st, o, g, d, gain, nullptr);
+  else
+    hipLaunchKernelGGL((k_damp_z<T, N, 0>), grid, block, 0, st, o, g, d, nullptr, nullptr);
   hipLaunchKernelGGL((k_damp_y<T, N, true>), grid, block, 0, st, o);
   hipLaunchKernelGGL((k_damp_inv_x<T, N>), grid, block, 0, st, p, o);
 }
 
 void damped_step(int n, int prec, const void* psi, const void* hpsi, const double* eps,
                  void* phi, int nstate, GridArgs g, double x0, double e0, double hb2m,
-                 double* r2_part, double* r2, hipStream_t st) {
+                 double* r2_part, double* r2, hipStream_t st, const float* gain,
+                 double* shell_pow, int stage) {
   if (nstate <= 0) return;
   DampArgs d{x0, e0, hb2m};
-  if (prec == 0) SKY_DISPATCH_N(n, launch_damp<double, NN>(psi, hpsi, eps, phi, nstate, g, d, r2_part, st))
-  else SKY_DISPATCH_N(n, launch_damp<float, NN>(psi, hpsi, eps, phi, nstate, g, d, r2_part, st))
+  if (prec == 0) SKY_DISPATCH_N(n, launch_damp<double, NN>(psi, hpsi, eps, phi, nstate, g, d, r2_part, gain, shell_pow, stage, st))
+  else SKY_DISPATCH_N(n, launch_damp<float, NN>(psi, hpsi, eps, phi, nstate, g, d, r2_part, gain, shell_pow, stage, st))
+  if (stage == 2) return;
   int nt = 0;
   SKY_DISPATCH_N(n, nt = ntiles<NN>());
-  hipLaunchKernelGGL(k_sum_partials, dim3((nstate + 127) / 128), dim3(128), 0, st,
-                     (const double*)r2_part, nt, nstate, r2);
+  if (r2)
+    hipLaunchKernelGGL(k_sum_partials, dim3((nstate + 127) / 128), dim3(128), 0, st,
+                       (const double*)r2_part, nt, nstate, r2);
 }
 
 template <typename T, int N>

@@ -2,6 +2,7 @@
 // static iteration of Fig. 1 (steps 2-5) of the paper.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -35,6 +36,9 @@ constexpr size_t ALIGN = 256;
 size_t al(size_t b) { return (b + ALIGN - 1) / ALIGN * ALIGN; }
 
 constexpr int DENS_CHUNKS = 32;   // state chunks of the density passes
+constexpr int PC_CAP = 16384;     // sample rows of the learned preconditioner
+constexpr int PC_HOLD = 10;       // iterations on plain damping after a rise of the residual
+constexpr int PC_RETRAIN_STEPS = 20;   // Adam steps of each online training
 constexpr double JACOBI_TOL = 1e-12;   // relative off-diagonal Frobenius norm
 constexpr int JACOBI_SWEEPS = 30;
 constexpr int REFINE_ITERS = 10;     // refinement steps before the Jacobi fallback
@@ -48,6 +52,12 @@ struct Layout {
   size_t eps[2], r2[2], ritz[2], tiles;
   size_t matI, matH, matC, matL, matT, matHp, matZ, matU, wtmp, gemm_part, chol_work, jac_work;
   size_t ref_work, nrm, sq_part;
+  // learned preconditioner: parameters (FP32 master, BF16-rounded copy),
+  // gradient, Adam moments, sample rows, activations, shell powers, gains,
+  // sampled-state batch buffers
+  size_t pc_P, pc_Pb, pc_G, pc_M, pc_V, pc_S, pc_H[3], pc_D[3], pc_O, pc_dO, pc_X, pc_pow,
+      pc_gain, pc_dscr, pc_gram, pc_idx, pc_beps, pc_b[4];
+  int pc_nb;   // largest sampled-state batch (states x shells)
   size_t plA, plB, plT, plU, plS;                  // FP16 split planes, scales (mixed only)
   size_t dens[2], der[2], mf[2], vc, fscratch, dens_part, epart, energy, info;
   size_t total;
@@ -83,7 +93,8 @@ Layout plan(const sky_box_desc& d) {
     L.ritz[q] = take(sizeof(double) * nq[q]);
   }
   const int ntile = grid_ntiles(d.n);
-  L.tiles = take(sizeof(double) * size_t(nmax) * ntile);
+  L.pc_nb = std::min(precond_ns_max(), nmax) * PC_SHELLS;
+  L.tiles = take(sizeof(double) * size_t(std::max(nmax, L.pc_nb)) * ntile);
   const size_t mm = size_t(nmax) * nmax * c16;
   L.matI = take(mm);
   L.matH = take(mm);
@@ -113,6 +124,29 @@ Layout plan(const sky_box_desc& d) {
   L.ref_work = take(std::max(refine_scratch_bytes(std::max(1, nq[0])),
                              refine_scratch_bytes(std::max(1, nq[1]))));
   L.nrm = take(sizeof(double) * 512);
+  {
+    const size_t np = size_t(precond_nparams());
+    const size_t rows = std::max<size_t>(PC_CAP, size_t(nmax) * PC_SHELLS);
+    const size_t pw = size_t(std::max(nmax, L.pc_nb)) * PC_SHELLS;
+    L.pc_P = take(sizeof(float) * np);
+    L.pc_Pb = take(sizeof(float) * np);
+    L.pc_G = take(sizeof(float) * np);
+    L.pc_M = take(sizeof(float) * np);
+    L.pc_V = take(sizeof(float) * np);
+    L.pc_S = take(sizeof(float) * 6 * PC_CAP);
+    for (int i = 0; i < 3; ++i) L.pc_H[i] = take(sizeof(float) * 128 * size_t(PC_CAP));
+    for (int i = 0; i < 3; ++i) L.pc_D[i] = take(sizeof(float) * 128 * size_t(PC_CAP));
+    L.pc_O = take(sizeof(float) * rows);
+    L.pc_dO = take(sizeof(float) * rows);
+    L.pc_X = take(sizeof(float) * 6 * size_t(nmax) * PC_SHELLS);
+    L.pc_pow = take(sizeof(double) * pw);
+    L.pc_gain = take(sizeof(float) * pw);
+    L.pc_dscr = take(sizeof(double) * (PC_CAP / 256 + 4));
+    L.pc_gram = take(precond_gram_bytes(precond_ns_max()));
+    L.pc_idx = take(sizeof(int) * precond_ns_max());
+    L.pc_beps = take(sizeof(double) * L.pc_nb);
+    for (int i = 0; i < 4; ++i) L.pc_b[i] = take(c16 * size_t(L.pc_nb) * V);
+  }
   L.sq_part = take(std::max(gemm_square_scratch_bytes(nq[0]), gemm_square_scratch_bytes(nq[1])));
   for (int q = 0; q < 2; ++q) {
     L.dens[q] = take(sizeof(double) * 11 * n3);
@@ -160,6 +194,21 @@ struct sky_ctx {
   // launch shapes (0 = the built-in default): h-pass lines per workgroup,
   // overlap and square-product split-K factors per species
   struct Tune { int lines = 0; int ovl[2] = {0, 0}; int sq[2] = {0, 0}; int from_cache = 0; } tune;
+  // learned preconditioner state
+  int pc_count = 0;        // sample rows held
+  int pc_wr = 0;           // next row written by a collection (ring)
+  int pc_every = 0;        // iterations between online collections + training (0: none)
+  int pc_since = 0;
+  double pc_lr = 1e-3;     // Adam step of the last training call
+  int pc_step = 0;         // Adam steps taken
+  bool pc_trained = false;
+  bool pc_ready = false;   // network initialised (first sky_init_box)
+  bool pc_on = false;      // requested by sky_precond_use
+  double pc_rise = 0.0;     // relative rise of the residual that triggers the fallback
+  int pc_hold = 0;         // plain-damping iterations left after a residual rise
+  bool pc_last = false;    // the previous iteration used the learned damping
+  double de_prev = -1.0;   // residual of the previous iteration
+  int pc_iters = 0;        // iterations of the current call with the learned damping
   int64_t iter_count = 0;     // iterations run on this context
   int64_t switched_at = -1;   // iteration after which the ladder switched to FP64
   // phase timing: HIP event pairs on the context stream
@@ -377,6 +426,106 @@ void fields(sky_ctx* c) {
              c->at<double>(c->lay.energy), st);
   t_end(c, tmf);
 }
+// |k| at the corner of the Brillouin zone
+double kmax_of(const sky_ctx* c) { return std::sqrt(3.0) * (c->n / 2) * c->g.kunit; }
+
+// Damped step with the learned per-shell gains: forward passes and shell
+// powers, MLP inference of the gains, then the gained filter and inverses.
+void learned_damp(sky_ctx* c, int q, const void* psi, const void* hpsi, const double* eps,
+                  void* phi, int m, double* r2, hipStream_t st) {
+  const double hb = q ? c->d.hb2m_p : c->d.hb2m_n;
+  double* pw = c->at<double>(c->lay.pc_pow);
+  zero(pw, size_t(m) * PC_SHELLS, st);
+  damped_step(c->n, c->prec, psi, hpsi, eps, phi, m, c->g, c->d.damp_x0, c->d.damp_e0, hb,
+              c->at<double>(c->lay.tiles), r2, st, nullptr, pw, 1);
+  float* X = c->at<float>(c->lay.pc_X);
+  precond_features(pw, eps, 1, m, c->d.damp_e0, hb, kmax_of(c), X, st);
+  precond_forward(c->at<float>(c->lay.pc_Pb), X, m * PC_SHELLS, nullptr, nullptr, nullptr,
+                  c->at<float>(c->lay.pc_O), st);
+  precond_gains(c->at<float>(c->lay.pc_O), m * PC_SHELLS, c->at<float>(c->lay.pc_gain), st);
+  damped_step(c->n, c->prec, psi, hpsi, eps, phi, m, c->g, c->d.damp_x0, c->d.damp_e0, hb,
+              nullptr, nullptr, st, c->at<float>(c->lay.pc_gain), nullptr, 2);
+}
+
+// Training rows from the current states of species q: the shell powers and
+// features of up to NS_MAX evenly spaced states, their one-shell damped
+// directions d_s, h d_s and the target gains.  Rows go to a ring of PC_CAP
+// rows (a collection that does not fit at the end starts again at row 0).
+int pc_collect(sky_ctx* c, int q) {
+  hipStream_t st = c->st;
+  const int m = c->nq[q];
+  const int ns = std::min(precond_ns_max(), m);
+  if (ns <= 0) return SKY_OK;
+  const int nb = ns * PC_SHELLS;
+  if (c->pc_wr + nb > PC_CAP) c->pc_wr = 0;
+  std::vector<int> idx(ns);
+  for (int a = 0; a < ns; ++a) idx[a] = int((long(a) * m) / ns);
+  int* didx = c->at<int>(c->lay.pc_idx);
+  hipMemcpyAsync(didx, idx.data(), sizeof(int) * ns, hipMemcpyHostToDevice, st);
+  double* eps = c->at<double>(c->lay.eps[q]);
+  double* tiles = c->at<double>(c->lay.tiles);
+  apply_h(c->n, c->prec, c->psi(q), c->hpsi(q), m, c->mfp(q), c->g, tiles, eps, st,
+          c->tune.lines);
+  void* b0 = c->at(c->lay.pc_b[0]);   // psi copies
+  void* b1 = c->at(c->lay.pc_b[1]);   // h psi copies
+  void* b2 = c->at(c->lay.pc_b[2]);   // phi, then the shell directions d
+  void* b3 = c->at(c->lay.pc_b[3]);   // h d
+  double* beps = c->at<double>(c->lay.pc_beps);
+  float* onehot = c->at<float>(c->lay.pc_gain);
+  double* pw = c->at<double>(c->lay.pc_pow);
+  precond_gather(c->prec, c->psi(q), c->hpsi(q), eps, didx, ns, c->V, b0, b1, beps, onehot, st);
+  zero(pw, size_t(nb) * PC_SHELLS, st);
+  const double hb = q ? c->d.hb2m_p : c->d.hb2m_n;
+  damped_step(c->n, c->prec, b0, b1, beps, b2, nb, c->g, c->d.damp_x0, c->d.damp_e0, hb, tiles,
+              nullptr, st, onehot, pw, 0);
+  float* rows = c->at<float>(c->lay.pc_S) + size_t(c->pc_wr) * 6;
+  precond_features(pw, beps, PC_SHELLS, ns, c->d.damp_e0, hb, kmax_of(c), rows, st);
+  precond_dir(c->prec, b0, b2, size_t(nb) * c->V, st);
+  apply_h(c->n, c->prec, b2, b3, nb, c->mfp(q), c->g, nullptr, nullptr, st, c->tune.lines);
+  precond_targets(c->prec, b0, b1, b2, b3, beps, ns, c->V, c->at<double>(c->lay.pc_gram), rows,
+                  st);
+  int rc = hip_check(hipStreamSynchronize(st), "precond_collect");
+  if (rc) return rc;
+  c->pc_wr += nb;
+  c->pc_count = std::max(c->pc_count, c->pc_wr);
+  return SKY_OK;
+}
+
+double precond_wsum(sky_ctx* c) {
+  std::vector<float> rows(size_t(c->pc_count) * 6);
+  hipMemcpyAsync(rows.data(), c->at(c->lay.pc_S), sizeof(float) * rows.size(),
+                 hipMemcpyDeviceToHost, c->st);
+  hipStreamSynchronize(c->st);
+  double w = 0.0;
+  for (int b = 0; b < c->pc_count; ++b) w += rows[size_t(b) * 6 + 5];
+  return w > 0.0 ? w : 1.0;
+}
+
+double precond_pass(sky_ctx* c, double wsum, int want_loss) {
+  return precond_loss_grad(
+      c->at<float>(c->lay.pc_Pb), c->at<float>(c->lay.pc_S), c->pc_count, wsum,
+      c->at<float>(c->lay.pc_H[0]), c->at<float>(c->lay.pc_H[1]), c->at<float>(c->lay.pc_H[2]),
+      c->at<float>(c->lay.pc_O), c->at<float>(c->lay.pc_dO), c->at<float>(c->lay.pc_D[0]),
+      c->at<float>(c->lay.pc_D[1]), c->at<float>(c->lay.pc_D[2]), c->at<float>(c->lay.pc_G),
+      c->at<double>(c->lay.pc_dscr), want_loss, c->st);
+}
+
+// Adam over every held row; returns the loss before the last update.
+double pc_train(sky_ctx* c, int steps, double lr) {
+  const double w = precond_wsum(c);
+  double l = 0.0;
+  for (int s = 1; s <= steps; ++s) {
+    precond_round(c->at<float>(c->lay.pc_P), c->at<float>(c->lay.pc_Pb), c->st);
+    l = precond_pass(c, w, s == steps);
+    precond_adam(c->at<float>(c->lay.pc_P), c->at<float>(c->lay.pc_G), c->at<float>(c->lay.pc_M),
+                 c->at<float>(c->lay.pc_V), ++c->pc_step, float(lr), c->st);
+  }
+  precond_round(c->at<float>(c->lay.pc_P), c->at<float>(c->lay.pc_Pb), c->st);
+  c->pc_trained = true;
+  c->pc_lr = lr;
+  return l;
+}
+
 // ------------------------------------------------------------------ autotuning
 // Flat JSON cache {"key": integer, ...}; keys name the operation, its sizes
 // and the precision.  Unreadable or absent files count as empty.
@@ -519,6 +668,14 @@ int sky_init_box(sky_ctx* c, const void* raw_n, const void* raw_p) {
   if (!c) return fail(SKY_ERR_INVALID, "null context");
   const void* raw[2] = {raw_n, raw_p};
   const int prec = c->d.precision == SKY_MIXED ? 1 : 0;
+  if (!c->pc_ready) {   // learned preconditioner: initial network, Adam moments
+    const Layout& L = c->lay;
+    hipMemsetAsync(c->at(L.pc_M), 0, sizeof(float) * precond_nparams(), c->st);
+    hipMemsetAsync(c->at(L.pc_V), 0, sizeof(float) * precond_nparams(), c->st);
+    precond_init_params(c->at<float>(L.pc_P), 20161024u, c->st);
+    precond_round(c->at<float>(L.pc_P), c->at<float>(L.pc_Pb), c->st);
+    c->pc_ready = true;
+  }
   c->prec = 0;   // the initial orthonormalisation runs in FP64 in both modes
   for (int q = 0; q < 2; ++q) {
     if (c->nq[q] == 0) continue;
@@ -577,8 +734,10 @@ int sky_iterate(sky_ctx* c, int32_t max_iter, double tol, sky_report* rep) {
   double de = 0.0;
   int it = 0, status = SKY_OK;
   c->fallbacks = 0;
+  c->pc_iters = 0;
   for (; it < max_iter; ++it) {
     c->last_sweeps = 0;
+    const bool learned = c->pc_on && c->pc_trained && c->pc_hold == 0;
     for (int q = 0; q < 2; ++q) {
       const int m = c->nq[q];
       if (m == 0) continue;
@@ -594,8 +753,11 @@ int sky_iterate(sky_ctx* c, int32_t max_iter, double tol, sky_report* rep) {
       t_end(c, t0);
       const double hb = q ? c->d.hb2m_p : c->d.hb2m_n;
       int t1 = t_begin(c, SKY_PHASE_DAMP, q);
-      damped_step(c->n, c->prec, psi, hpsi, eps, phi, m, c->g, c->d.damp_x0, c->d.damp_e0, hb,
-                  tiles, c->at<double>(c->lay.r2[q]), st);
+      if (learned)
+        learned_damp(c, q, psi, hpsi, eps, phi, m, c->at<double>(c->lay.r2[q]), st);
+      else
+        damped_step(c->n, c->prec, psi, hpsi, eps, phi, m, c->g, c->d.damp_x0, c->d.damp_e0, hb,
+                    tiles, c->at<double>(c->lay.r2[q]), st);
       t_end(c, t1);
       int t2 = t_begin(c, SKY_PHASE_APPLY_H, q);
       apply_h(c->n, c->prec, phi, hphi, m, c->mfp(q), c->g, nullptr, nullptr, st, c->tune.lines);
@@ -623,6 +785,23 @@ int sky_iterate(sky_ctx* c, int32_t max_iter, double tol, sky_report* rep) {
     t_flush(c);
     de = std::sqrt(sum / std::max(1, cnt));
     if (!std::isfinite(de)) return fail(SKY_ERR_NAN, "non-finite residual");
+    // learned damping: back to the plain damping for PC_HOLD iterations when
+    // the residual rose after a learned step
+    if (c->pc_last && c->pc_rise >= 0.0 && c->de_prev >= 0.0 && de > (1.0 + c->pc_rise) * c->de_prev)
+      c->pc_hold = PC_HOLD;
+    else if (c->pc_hold > 0 && !learned) --c->pc_hold;
+    c->pc_last = learned;
+    c->pc_iters += learned ? 1 : 0;
+    c->de_prev = de;
+    // online training: fresh rows from both species, then a few Adam steps
+    if (c->pc_on && c->pc_every > 0 && ++c->pc_since >= c->pc_every) {
+      c->pc_since = 0;
+      for (int q = 0; q < 2; ++q) {
+        int rc = pc_collect(c, q);
+        if (rc) return rc;
+      }
+      pc_train(c, PC_RETRAIN_STEPS, c->pc_lr);
+    }
     // precision ladder: finish in FP64 once the mixed form has done its part
     if (c->prec == 1 && c->d.ladder_tol > 0.0 && de <= c->d.ladder_tol) {
       for (int q = 0; q < 2; ++q)
@@ -651,6 +830,7 @@ int sky_iterate(sky_ctx* c, int32_t max_iter, double tol, sky_report* rep) {
     rep->energy_per_a = e[7] / double(c->nq[0] + c->nq[1]);
     rep->eig_iters = c->last_sweeps;
     rep->eig_fallbacks = c->fallbacks;
+    rep->precond_iters = c->pc_iters;
   }
   return status;
 }
@@ -675,6 +855,10 @@ int sky_get_view(sky_ctx* c, int32_t what, int32_t q, void** ptr, int64_t* count
     case SKY_VIEW_HSUB: *ptr = c->at(c->lay.matH); *count = int64_t(c->nq[q]) * c->nq[q]; break;
     case SKY_VIEW_EVEC: *ptr = c->at(c->lay.matZ); *count = int64_t(c->nq[q]) * c->nq[q]; break;
     case SKY_VIEW_UMAT: *ptr = c->at(c->lay.matU); *count = int64_t(c->nq[q]) * c->nq[q]; break;
+    case SKY_VIEW_PC_PARAMS: *ptr = c->at(c->lay.pc_P); *count = precond_nparams(); break;
+    case SKY_VIEW_PC_GRAD: *ptr = c->at(c->lay.pc_G); *count = precond_nparams(); break;
+    case SKY_VIEW_PC_SAMPLES: *ptr = c->at(c->lay.pc_S); *count = 6LL * PC_CAP; break;
+    case SKY_VIEW_PC_GAINS: *ptr = c->at(c->lay.pc_gain); *count = int64_t(c->nq[q]) * PC_SHELLS; break;
     default: return fail(SKY_ERR_INVALID, "unknown view");
   }
   return SKY_OK;
@@ -822,6 +1006,55 @@ int sky_get_tuning(sky_ctx* c, sky_tuning* out) {
     out->square_split[q] = c->tune.sq[q];
   }
   out->from_cache = c->tune.from_cache;
+  return SKY_OK;
+}
+
+int sky_precond_collect(sky_ctx* c, int32_t q, int32_t* total) {
+  if (!c || q < 0 || q > 1) return fail(SKY_ERR_INVALID, "precond_collect arguments");
+  int rc = pc_collect(c, q);
+  if (rc) return rc;
+  if (total) *total = c->pc_count;
+  return SKY_OK;
+}
+
+int sky_precond_loss_grad(sky_ctx* c, int32_t nsamples, double* loss) {
+  if (!c || nsamples < 1 || nsamples > PC_CAP) return fail(SKY_ERR_INVALID, "precond_loss_grad arguments");
+  const int keep = c->pc_count;
+  c->pc_count = nsamples;
+  const double w = precond_wsum(c);
+  precond_round(c->at<float>(c->lay.pc_P), c->at<float>(c->lay.pc_Pb), c->st);
+  const double l = precond_pass(c, w, 1);
+  c->pc_count = keep;
+  if (loss) *loss = l;
+  return hip_check(hipStreamSynchronize(c->st), "precond_loss_grad");
+}
+
+int sky_precond_train(sky_ctx* c, int32_t steps, double lr, double* loss) {
+  if (!c || steps < 1 || !(lr > 0.0)) return fail(SKY_ERR_INVALID, "precond_train arguments");
+  if (c->pc_count < 1) return fail(SKY_ERR_INVALID, "precond_train: no samples collected");
+  const double l = pc_train(c, steps, lr);
+  if (loss) *loss = l;
+  return hip_check(hipStreamSynchronize(c->st), "precond_train");
+}
+
+int sky_precond_set_rows(sky_ctx* c, int32_t nrows) {
+  if (!c || nrows < 0 || nrows > PC_CAP) return fail(SKY_ERR_INVALID, "precond_set_rows arguments");
+  c->pc_count = nrows;
+  c->pc_wr = nrows;
+  return SKY_OK;
+}
+
+int sky_precond_use(sky_ctx* c, int32_t enable, double rise_tol, int32_t retrain_every) {
+  if (!c || !std::isfinite(rise_tol) || retrain_every < 0)
+    return fail(SKY_ERR_INVALID, "precond_use arguments");
+  if (enable && !c->pc_trained) return fail(SKY_ERR_INVALID, "precond_use: the network is not trained");
+  c->pc_on = enable != 0;
+  c->pc_rise = rise_tol;
+  c->pc_every = retrain_every;
+  c->pc_since = 0;
+  c->pc_hold = 0;
+  c->pc_last = false;
+  c->de_prev = -1.0;
   return SKY_OK;
 }
 

@@ -44,6 +44,20 @@ struct GridArgs {
   double kunit;   // 2 pi / L
 };
 
+// |k| shells of the learned preconditioner: S equal-width shells of |k| up
+// to the corner |k|max = sqrt(3) (N/2) kunit of the Brillouin zone.  With
+// k = kunit (a, b, c) and m2 = a^2 + b^2 + c^2, shell s >= j exactly when
+// |k| / |k|max >= j / S, i.e. 4 S^2 m2 >= 3 j^2 N^2: integer arithmetic, so
+// the shell of a mode does not depend on rounding.
+constexpr int PC_SHELLS = 8;
+__host__ __device__ inline int k_shell(int m2, int n) {
+  int s = 0;
+#pragma unroll
+  for (int j = 1; j < PC_SHELLS; ++j)
+    s += (3 * j * j * n * n <= 4 * PC_SHELLS * PC_SHELLS * m2) ? 1 : 0;
+  return s;
+}
+
 // Mean field of one species (device pointers, FP64 fields [z][y][x]).
 struct MeanFieldPtrs {
   const double* U;

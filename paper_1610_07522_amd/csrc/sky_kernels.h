@@ -14,9 +14,43 @@ int grid_ntiles(int n);  // workgroups per state of one line pass
 void h_pass_lines(int n, int prec, int* out);
 int apply_h(int n, int prec, const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf,
             GridArgs g, double* eps_part, double* eps, hipStream_t st, int lines = 0);
+// gain (optional, [state][PC_SHELLS]): multiplies the damping per |k| shell.
+// shell_pow (optional, [state][PC_SHELLS], accumulated: clear first): the
+// residual's spectral power per shell, from an extra read-only pass.
+// stage 0: whole step; 1: up to the shell powers (partial spectrum left in
+// phi, r2 formed); 2: the rest, continuing from stage 1 (gains decided in
+// between).
 void damped_step(int n, int prec, const void* psi, const void* hpsi, const double* eps,
                  void* phi, int nstate, GridArgs g, double x0, double e0, double hb2m,
-                 double* r2_part, double* r2, hipStream_t st);
+                 double* r2_part, double* r2, hipStream_t st, const float* gain = nullptr,
+                 double* shell_pow = nullptr, int stage = 0);
+
+// ---- learned preconditioner (k_precond.hip)
+int precond_nparams();
+int precond_ns_max();
+void precond_init_params(float* P_dev, unsigned seed, hipStream_t st);
+void precond_round(const float* P, float* Pb, hipStream_t st);
+void precond_forward(const float* Pb, const float* X, int B, float* H1, float* H2, float* H3,
+                     float* O, hipStream_t st);
+// rows [a*S + s][6] = (features, target, weight) of states a < ns; pow and eps
+// rows of state a at a*stride
+void precond_features(const double* pow, const double* eps, int stride, int ns, double e0,
+                      double hb2m, double kmax, float* X, hipStream_t st);
+void precond_gains(const float* O, int n, float* gain, hipStream_t st);
+// loss and parameter gradient G; dscratch >= B/256 + 2 doubles; want_loss:
+// synchronise and return the loss (else 0).
+double precond_loss_grad(const float* Pb, const float* S, int B, double wsum, float* H1,
+                         float* H2, float* H3, float* O, float* dO, float* D1, float* D2,
+                         float* D3, float* G, double* dscratch, int want_loss, hipStream_t st);
+void precond_adam(float* P, const float* G, float* M, float* V, int step, float lr,
+                  hipStream_t st);
+void precond_gather(int prec, const void* psi, const void* hpsi, const double* eps,
+                    const int* idx, int ns, long V, void* bpsi, void* bh, double* beps,
+                    float* onehot, hipStream_t st);
+void precond_dir(int prec, const void* bpsi, void* bphi, size_t n, hipStream_t st);
+size_t precond_gram_bytes(int ns);
+void precond_targets(int prec, const void* bpsi, const void* bh, const void* bd, const void* bhd,
+                     const double* beps, int ns, long V, double* part, float* S, hipStream_t st);
 // dens = 11 fields [rho, tau, Jx, Jy, Jz, sx, sy, sz, jx, jy, jz][n^3];
 // part holds nchunk_max * 16 * n^3 doubles.
 void densities(int n, int prec, const void* psi, int nstate, int nchunk_max, GridArgs g,

@@ -27,14 +27,19 @@ SKY_FP64 = 0
 SKY_MIXED = 1
 
 VIEW = dict(psi=0, hpsi=1, phi=2, hphi=3, dens=4, meanfield=5, coulomb=6, energy=7,
-            eps=8, ritz=9, r2=10, overlap=11, hsub=12, evec=13, umat=14)
+            eps=8, ritz=9, r2=10, overlap=11, hsub=12, evec=13, umat=14,
+            pc_params=15, pc_grad=16, pc_samples=17, pc_gains=18)
 _MATRIX_VIEWS = ("overlap", "hsub", "evec", "umat")
+_F32_VIEWS = ("pc_params", "pc_grad", "pc_samples", "pc_gains")
 
 # Symbols declared in include/sky.h, in order.
 EXPORTS = ("sky_workspace_size", "sky_create", "sky_init_box", "sky_apply_h",
            "sky_damped_step", "sky_orthonormalize", "sky_densities", "sky_iterate",
            "sky_get_view", "sky_set_timing", "sky_get_timing", "sky_get_precision",
-           "sky_autotune", "sky_get_tuning", "sky_sync", "sky_last_error", "sky_destroy")
+           "sky_autotune", "sky_get_tuning", "sky_precond_collect", "sky_precond_train",
+           "sky_precond_loss_grad", "sky_precond_set_rows", "sky_precond_use", "sky_sync",
+           "sky_last_error",
+           "sky_destroy")
 PHASES = ("apply_h", "damp", "overlap_gemm", "subspace", "combine_gemm", "densities",
           "meanfield", "split")
 
@@ -57,7 +62,7 @@ class Report(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("residual", ctypes.c_double),
                 ("energy", ctypes.c_double), ("energy_per_a", ctypes.c_double),
                 ("eig_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("eig_fallbacks", ctypes.c_int32)]
+                ("eig_fallbacks", ctypes.c_int32), ("precond_iters", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):
@@ -108,6 +113,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "sky_get_precision": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int32)]),
         "sky_autotune": (ctypes.c_int, [vp, ctypes.c_char_p, ctypes.POINTER(Tuning)]),
         "sky_get_tuning": (ctypes.c_int, [vp, ctypes.POINTER(Tuning)]),
+        "sky_precond_collect": (ctypes.c_int, [vp, i32, ctypes.POINTER(ctypes.c_int32)]),
+        "sky_precond_train": (ctypes.c_int, [vp, i32, dbl, dp]),
+        "sky_precond_loss_grad": (ctypes.c_int, [vp, i32, dp]),
+        "sky_precond_set_rows": (ctypes.c_int, [vp, i32]),
+        "sky_precond_use": (ctypes.c_int, [vp, i32, dbl, i32]),
         "sky_sync": (ctypes.c_int, [vp]),
         "sky_last_error": (ctypes.c_char_p, []),
         "sky_destroy": (None, [vp]),
@@ -197,7 +207,7 @@ class Box:
                     ok=(SKY_OK, SKY_NOT_CONVERGED))
         return dict(iters=rep.iters, residual=rep.residual, energy=rep.energy,
                     energy_per_a=rep.energy_per_a, eig_iters=rep.eig_iters,
-                    eig_fallbacks=rep.eig_fallbacks,
+                    eig_fallbacks=rep.eig_fallbacks, precond_iters=rep.precond_iters,
                     precision=rep.precision, converged=(rc == SKY_OK))
 
     def precision(self) -> int:
@@ -215,6 +225,27 @@ class Box:
         t = Tuning()
         _check(self.lib.sky_get_tuning(self.ctx, ctypes.byref(t)))
         return t.as_dict()
+
+    def precond_collect(self, q: int) -> int:
+        n = ctypes.c_int32()
+        _check(self.lib.sky_precond_collect(self.ctx, q, ctypes.byref(n)))
+        return n.value
+
+    def precond_train(self, steps: int, lr: float = 1e-3) -> float:
+        loss = ctypes.c_double()
+        _check(self.lib.sky_precond_train(self.ctx, steps, lr, ctypes.byref(loss)))
+        return loss.value
+
+    def precond_loss_grad(self, nsamples: int) -> float:
+        loss = ctypes.c_double()
+        _check(self.lib.sky_precond_loss_grad(self.ctx, nsamples, ctypes.byref(loss)))
+        return loss.value
+
+    def precond_set_rows(self, nrows: int):
+        _check(self.lib.sky_precond_set_rows(self.ctx, nrows))
+
+    def precond_use(self, enable: bool, rise_tol: float = 0.05, retrain_every: int = 0):
+        _check(self.lib.sky_precond_use(self.ctx, 1 if enable else 0, rise_tol, retrain_every))
 
     def sync(self):
         _check(self.lib.sky_sync(self.ctx))
@@ -245,6 +276,8 @@ class Box:
         esize = 16 if is_cpx else 8
         if is_state and self.precision() == SKY_MIXED:
             dt, esize = torch.complex64, 8
+        if what in _F32_VIEWS:
+            dt, esize = torch.float32, 4
         off = ptr.value - self.ws.data_ptr() if ptr.value else 0
         t = self.ws[off:off + cnt.value * esize].view(dt)
         n = self.desc.n
@@ -257,4 +290,8 @@ class Box:
         if what in _MATRIX_VIEWS:
             m = int(round(cnt.value ** 0.5))
             return t.view(m, m)
+        if what == "pc_samples":
+            return t.view(-1, 6)
+        if what == "pc_gains":
+            return t.view(-1, 8)
         return t
