@@ -250,6 +250,32 @@ int sky_autotune(sky_ctx* c, const char* cache_path, sky_tuning* out);
 /* Launch shapes in use (defaults until sky_autotune). */
 int sky_get_tuning(sky_ctx* c, sky_tuning* out);
 
+/* HIP graphs (Fig. 1 iteration, launch side).  With graphs on, sky_iterate
+ * captures the launch-only segments of an iteration once -- per species:
+ * h psi, damped step, h phi, I and H (steps 2, 3a); psi = phi U (3e); and
+ * the fields (4a, 4b, 5) -- and replays them; the host-driven subspace
+ * solve (3b-3d) and the residual read-back run between replays.  Results
+ * are those of the eager launches.  Graphs are dropped and recaptured when
+ * the precision ladder switches or sky_autotune changes a launch shape;
+ * phase timing (sky_set_timing) runs eagerly.  Needs a stream other than
+ * the null stream.  Errors: SKY_ERR_INVALID, SKY_ERR_HIP. */
+int sky_set_graphs(sky_ctx* c, int32_t enable);
+
+/* Batched uneven boxes: iterates nbox independent contexts (any grid
+ * sizes, state counts and precisions) until each one's Delta-eps <= tol
+ * (tol <= 0: exactly max_iter iterations each).  Boxes are assigned to
+ * nthreads host workers by longest-processing-time first on the cost of an
+ * iteration (m^2 V for the products, m V log V for the FFT passes); each
+ * worker owns a non-blocking HIP stream of default priority and runs its
+ * boxes with graphs on, so up to nthreads boxes share the GPU at a time.
+ * Every box stops at its own tolerance (per-box convergence mask).  reps[i]
+ * and status[i] receive what sky_iterate returns for box i (SKY_OK or
+ * SKY_NOT_CONVERGED, else an error code).  The contexts' own streams are
+ * synchronised first and restored afterwards; a context may not appear
+ * twice.  Returns SKY_OK, or the first box error (message names the box). */
+int sky_batch_iterate(sky_ctx* const* ctxs, int32_t nbox, int32_t nthreads, int32_t max_iter,
+                      double tol, sky_report* reps, int32_t* status);
+
 /* Learned spectral preconditioner (an extension of Eq. dampstep, whose
  * damping x0 / (E0 + T_k) is fixed in the paper).  The learned step scales
  * the damping of state alpha in |k| shell s (8 equal |k| shells up to the

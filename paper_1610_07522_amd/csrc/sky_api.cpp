@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/sky.h"
@@ -209,6 +210,16 @@ struct sky_ctx {
   bool pc_last = false;    // the previous iteration used the learned damping
   double de_prev = -1.0;   // residual of the previous iteration
   int pc_iters = 0;        // iterations of the current call with the learned damping
+  // HIP graphs of the launch-only segments of an iteration (per species:
+  // A plain / A learned, B; F = fields)
+  struct Graphs {
+    bool on = false;
+    int prec = -1;
+    int captures = 0;
+    hipGraphExec_t a[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipGraphExec_t b[2] = {nullptr, nullptr};
+    hipGraphExec_t f = nullptr;
+  } graphs;
   int64_t iter_count = 0;     // iterations run on this context
   int64_t switched_at = -1;   // iteration after which the ladder switched to FP64
   // phase timing: HIP event pairs on the context stream
@@ -281,22 +292,13 @@ int check_info(sky_ctx* c, const char* what) {
   return SKY_OK;
 }
 
-// Generalised Rayleigh-Ritz on phi/hphi of species q -> psi_out (Sec. 3.3).
-int rayleigh_ritz(sky_ctx* c, int q, const void* phi, const void* hphi, void* psi_out,
-                  double* ritz) {
+// Step 3a of species q: I and H (lower triangles by the GEMMs, then
+// mirrored).  Launches only, so that it can be captured in a graph.
+void subspace_matrices(sky_ctx* c, int q, const void* phi, const void* hphi) {
   const int m = c->nq[q];
-  if (m == 0) return SKY_OK;
   hipStream_t st = c->st;
   void* I = c->at(c->lay.matI);
   void* H = c->at(c->lay.matH);
-  void* Linv = c->at(c->lay.matL);
-  void* T = c->at(c->lay.matT);
-  void* Hp = c->at(c->lay.matHp);
-  void* Z = c->at(c->lay.matZ);
-  void* U = c->at(c->lay.matU);
-  int* info = c->at<int>(c->lay.info);
-  hipMemsetAsync(info, 0, sizeof(int), st);
-  // step 3a: I and H, lower triangles, then mirrored
   unsigned int* mx = c->at<unsigned int>(c->lay.plS);
   if (c->prec) {
     const int tp = t_begin(c, SKY_PHASE_SPLIT, q);
@@ -322,13 +324,27 @@ int rayleigh_ritz(sky_ctx* c, int q, const void* phi, const void* hphi, void* ps
   else
     overlap_lower(phi, phi, hphi, m, c->V, c->g.dV, I, H, c->at(c->lay.gemm_part), st,
                   c->timing ? ev : nullptr, c->tune.ovl[q]);
-  const int ts = t_begin(c, SKY_PHASE_SUBSPACE, q);
   hermitian_fill(I, m, st);
   hermitian_fill(H, m, st);
-  // steps 3b-3c: an orthonormalising transform C (C^H I C = 1), H' = C^H H C,
-  // H' = Z lam Z^H.  Near the identity (every iteration after the start) C is
-  // Loewdin's I^-1/2 from its binomial series; otherwise C = L^-H with the
-  // Cholesky factor I = L L^H.
+}
+
+// Steps 3b-3d of species q on the host-driven path: an orthonormalising
+// transform C (C^H I C = 1), H' = C^H H C = Z lam Z^H, U = C Z.  Near the
+// identity (every iteration after the start) C is Loewdin's I^-1/2 from its
+// binomial series; otherwise C = L^-H with the Cholesky factor I = L L^H.
+int subspace_solve(sky_ctx* c, int q, double* ritz) {
+  const int m = c->nq[q];
+  hipStream_t st = c->st;
+  void* I = c->at(c->lay.matI);
+  void* H = c->at(c->lay.matH);
+  void* Linv = c->at(c->lay.matL);
+  void* T = c->at(c->lay.matT);
+  void* Hp = c->at(c->lay.matHp);
+  void* Z = c->at(c->lay.matZ);
+  void* U = c->at(c->lay.matU);
+  int* info = c->at<int>(c->lay.info);
+  const int ts = t_begin(c, SKY_PHASE_SUBSPACE, q);
+  hipMemsetAsync(info, 0, sizeof(int), st);
   void* Cw = c->at(c->lay.matC);
   void* sq = c->at(c->lay.sq_part);
   const int sqs = c->tune.sq[q];
@@ -353,18 +369,36 @@ int rayleigh_ritz(sky_ctx* c, int q, const void* phi, const void* hphi, void* ps
     its = jacobi_eigh(Hp, m, w, Z, c->at(c->lay.jac_work), JACOBI_TOL, JACOBI_SWEEPS, st);
   }
   c->last_sweeps += its;
-  // steps 3d-3e: U = C Z, psi = phi U
   gemm_square(Linv, terms > 0 ? 0 : 1, Z, 0, U, m, st, sq, 0, sqs);
+  t_end(c, ts);
+  return SKY_OK;
+}
+
+// Step 3e of species q: psi = phi U (launches only).
+void subspace_combine(sky_ctx* c, int q, const void* phi, void* psi_out) {
+  const int m = c->nq[q];
+  hipStream_t st = c->st;
+  void* U = c->at(c->lay.matU);
+  unsigned int* mx = c->at<unsigned int>(c->lay.plS);
+  const int tc = t_begin(c, SKY_PHASE_COMBINE_GEMM, q);
   if (c->prec) {
     plane_scale(U, 1, size_t(m) * m, mx + 2, st);
     split_planes_t(U, 1, m, m, mx + 2, c->at(c->lay.plU), st);
-  }
-  t_end(c, ts);
-  const int tc = t_begin(c, SKY_PHASE_COMBINE_GEMM, q);
-  if (c->prec)
     combine_planes(c->at(c->lay.plU), c->at(c->lay.plT), mx + 2, mx, psi_out, m, c->V, st);
-  else combine(phi, U, psi_out, m, c->V, st);
+  } else {
+    combine(phi, U, psi_out, m, c->V, st);
+  }
   t_end(c, tc);
+}
+
+// Generalised Rayleigh-Ritz on phi/hphi of species q -> psi_out (Sec. 3.3).
+int rayleigh_ritz(sky_ctx* c, int q, const void* phi, const void* hphi, void* psi_out,
+                  double* ritz) {
+  if (c->nq[q] == 0) return SKY_OK;
+  subspace_matrices(c, q, phi, hphi);
+  int rc = subspace_solve(c, q, ritz);
+  if (rc) return rc;
+  subspace_combine(c, q, phi, psi_out);
   return SKY_OK;
 }
 
@@ -524,6 +558,74 @@ double pc_train(sky_ctx* c, int steps, double lr) {
   c->pc_trained = true;
   c->pc_lr = lr;
   return l;
+}
+
+// Step 2 and step 3a of species q: h psi and <h>, the damped step (plain or
+// learned), h phi, then I and H.  Launches only.
+void step_a(sky_ctx* c, int q, bool learned) {
+  const int m = c->nq[q];
+  hipStream_t st = c->st;
+  void* psi = c->psi(q);
+  void* hpsi = c->hpsi(q);
+  void* phi = c->phi(q);
+  void* hphi = c->hphi(q);
+  double* eps = c->at<double>(c->lay.eps[q]);
+  double* tiles = c->at<double>(c->lay.tiles);
+  int t0 = t_begin(c, SKY_PHASE_APPLY_H, q);
+  apply_h(c->n, c->prec, psi, hpsi, m, c->mfp(q), c->g, tiles, eps, st, c->tune.lines);
+  t_end(c, t0);
+  const double hb = q ? c->d.hb2m_p : c->d.hb2m_n;
+  int t1 = t_begin(c, SKY_PHASE_DAMP, q);
+  if (learned)
+    learned_damp(c, q, psi, hpsi, eps, phi, m, c->at<double>(c->lay.r2[q]), st);
+  else
+    damped_step(c->n, c->prec, psi, hpsi, eps, phi, m, c->g, c->d.damp_x0, c->d.damp_e0, hb,
+                tiles, c->at<double>(c->lay.r2[q]), st);
+  t_end(c, t1);
+  int t2 = t_begin(c, SKY_PHASE_APPLY_H, q);
+  apply_h(c->n, c->prec, phi, hphi, m, c->mfp(q), c->g, nullptr, nullptr, st, c->tune.lines);
+  t_end(c, t2);
+  subspace_matrices(c, q, phi, hphi);
+}
+
+void graphs_clear(sky_ctx* c) {
+  auto drop = [](hipGraphExec_t& g) { if (g) { hipGraphExecDestroy(g); g = nullptr; } };
+  for (int q = 0; q < 2; ++q) {
+    drop(c->graphs.a[q][0]);
+    drop(c->graphs.a[q][1]);
+    drop(c->graphs.b[q]);
+  }
+  drop(c->graphs.f);
+}
+
+// Runs body's launches: directly, or (graphs on, timing off) by replaying the
+// graph captured from body at its first use.  Graphs hold the context's
+// buffers, sizes, precision and launch shapes; they are dropped whenever one
+// of those changes.
+template <class Body>
+int run_segment(sky_ctx* c, hipGraphExec_t& exec, Body&& body) {
+  if (!c->graphs.on || c->timing) {
+    body();
+    return SKY_OK;
+  }
+  if (c->graphs.prec != c->prec) {
+    hipStreamSynchronize(c->st);
+    graphs_clear(c);
+    c->graphs.prec = c->prec;
+  }
+  if (!exec) {
+    hipGraph_t g = nullptr;
+    int rc = hip_check(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal), "graph capture");
+    if (rc) return rc;
+    body();
+    rc = hip_check(hipStreamEndCapture(c->st, &g), "graph capture");
+    if (rc) return rc;
+    rc = hip_check(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0), "graph instantiate");
+    hipGraphDestroy(g);
+    if (rc) return rc;
+    ++c->graphs.captures;
+  }
+  return hip_check(hipGraphLaunch(exec, c->st), "graph launch");
 }
 
 // ------------------------------------------------------------------ autotuning
@@ -739,49 +841,33 @@ int sky_iterate(sky_ctx* c, int32_t max_iter, double tol, sky_report* rep) {
     c->last_sweeps = 0;
     const bool learned = c->pc_on && c->pc_trained && c->pc_hold == 0;
     for (int q = 0; q < 2; ++q) {
-      const int m = c->nq[q];
-      if (m == 0) continue;
-      void* psi = c->psi(q);
-      void* hpsi = c->hpsi(q);
-      void* phi = c->phi(q);
-      void* hphi = c->hphi(q);
-      double* eps = c->at<double>(c->lay.eps[q]);
-      double* tiles = c->at<double>(c->lay.tiles);
-      // step 2: h psi, <h>, damped step, h phi
-      int t0 = t_begin(c, SKY_PHASE_APPLY_H, q);
-      apply_h(c->n, c->prec, psi, hpsi, m, c->mfp(q), c->g, tiles, eps, st, c->tune.lines);
-      t_end(c, t0);
-      const double hb = q ? c->d.hb2m_p : c->d.hb2m_n;
-      int t1 = t_begin(c, SKY_PHASE_DAMP, q);
-      if (learned)
-        learned_damp(c, q, psi, hpsi, eps, phi, m, c->at<double>(c->lay.r2[q]), st);
-      else
-        damped_step(c->n, c->prec, psi, hpsi, eps, phi, m, c->g, c->d.damp_x0, c->d.damp_e0, hb,
-                    tiles, c->at<double>(c->lay.r2[q]), st);
-      t_end(c, t1);
-      int t2 = t_begin(c, SKY_PHASE_APPLY_H, q);
-      apply_h(c->n, c->prec, phi, hphi, m, c->mfp(q), c->g, nullptr, nullptr, st, c->tune.lines);
-      t_end(c, t2);
-      // steps 3a-3e
-      int rc = rayleigh_ritz(c, q, phi, hphi, psi, c->at<double>(c->lay.ritz[q]));
+      if (c->nq[q] == 0) continue;
+      // step 2 and step 3a (graph segment A), steps 3b-3d on the host path,
+      // step 3e (segment B)
+      int rc = run_segment(c, c->graphs.a[q][learned ? 1 : 0], [&] { step_a(c, q, learned); });
+      if (rc) return rc;
+      rc = subspace_solve(c, q, c->at<double>(c->lay.ritz[q]));
+      if (rc) return rc;
+      rc = run_segment(c, c->graphs.b[q], [&] { subspace_combine(c, q, c->phi(q), c->psi(q)); });
       if (rc) return rc;
     }
     // steps 4a, 4b, 5
-    fields(c);
+    int rcf = run_segment(c, c->graphs.f, [&] { fields(c); });
+    if (rcf) return rcf;
     // Delta-eps of the states that entered this iteration (Eq. convergence)
-    double sum = 0.0;
-    int cnt = 0;
+    r2h.resize(size_t(c->nq[0]) + c->nq[1]);
     for (int q = 0; q < 2; ++q) {
-      r2h.resize(c->nq[q]);
       if (c->nq[q] == 0) continue;
-      int rc = hip_check(hipMemcpyAsync(r2h.data(), c->at(c->lay.r2[q]), sizeof(double) * c->nq[q],
-                                        hipMemcpyDeviceToHost, st), "r2 copy");
+      int rc = hip_check(hipMemcpyAsync(r2h.data() + (q ? c->nq[0] : 0), c->at(c->lay.r2[q]),
+                                        sizeof(double) * c->nq[q], hipMemcpyDeviceToHost, st),
+                         "r2 copy");
       if (rc) return rc;
-      rc = hip_check(hipStreamSynchronize(st), "iterate");
-      if (rc) return rc;
-      for (double v : r2h) sum += v;
-      cnt += c->nq[q];
     }
+    int rcs = hip_check(hipStreamSynchronize(st), "iterate");
+    if (rcs) return rcs;
+    double sum = 0.0;
+    for (double v : r2h) sum += v;
+    const int cnt = c->nq[0] + c->nq[1];
     t_flush(c);
     de = std::sqrt(sum / std::max(1, cnt));
     if (!std::isfinite(de)) return fail(SKY_ERR_NAN, "non-finite residual");
@@ -906,6 +992,7 @@ void sky_destroy(sky_ctx* c) {
   hipStreamSynchronize(c->st);
   for (auto& m : c->marks) { hipEventDestroy(m.a); hipEventDestroy(m.b); }
   for (auto e : c->pool) hipEventDestroy(e);
+  graphs_clear(c);
   delete c;
 }
 
@@ -992,6 +1079,8 @@ int sky_autotune(sky_ctx* c, const char* cache_path, sky_tuning* out) {
   if (rc) return rc;
   c->tune.from_cache = timed == 0;
   if (timed && !cache_write(cache_path, kv)) return fail(SKY_ERR_INVALID, "cannot write the tuning cache");
+  hipStreamSynchronize(c->st);
+  graphs_clear(c);   // launch shapes may have changed
   return sky_get_tuning(c, out);
 }
 
@@ -1055,6 +1144,87 @@ int sky_precond_use(sky_ctx* c, int32_t enable, double rise_tol, int32_t retrain
   c->pc_hold = 0;
   c->pc_last = false;
   c->de_prev = -1.0;
+  return SKY_OK;
+}
+
+int sky_set_graphs(sky_ctx* c, int32_t enable) {
+  if (!c) return fail(SKY_ERR_INVALID, "null context");
+  if (enable && !c->st) return fail(SKY_ERR_INVALID, "graph capture needs a stream other than the null stream");
+  int rc = hip_check(hipStreamSynchronize(c->st), "set_graphs");
+  if (rc) return rc;
+  graphs_clear(c);
+  c->graphs.on = enable != 0;
+  return SKY_OK;
+}
+
+int sky_batch_iterate(sky_ctx* const* ctxs, int32_t nbox, int32_t nthreads, int32_t max_iter,
+                      double tol, sky_report* reps, int32_t* status) {
+  if (!ctxs || nbox < 1 || nthreads < 1 || max_iter < 0 || !reps || !status)
+    return fail(SKY_ERR_INVALID, "batch_iterate arguments");
+  for (int i = 0; i < nbox; ++i) {
+    if (!ctxs[i]) return fail(SKY_ERR_INVALID, "batch_iterate: null context");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return fail(SKY_ERR_INVALID, "batch_iterate: a context appears twice");
+  }
+  int dev = 0;
+  int rc = hip_check(hipGetDevice(&dev), "batch_iterate");
+  if (rc) return rc;
+  // work issued earlier on the contexts' own streams completes first
+  rc = hip_check(hipDeviceSynchronize(), "batch_iterate");
+  if (rc) return rc;
+  // longest-processing-time assignment of boxes to workers by the cost of an
+  // iteration: the subspace products (m^2 V) and the FFT passes (m V log V)
+  const int nw = std::min(nthreads, nbox);
+  std::vector<std::pair<double, int>> cost(nbox);
+  for (int i = 0; i < nbox; ++i) {
+    const sky_ctx* c = ctxs[i];
+    double w = 0.0;
+    for (int q = 0; q < 2; ++q)
+      w += double(c->nq[q]) * double(c->V) * (double(c->nq[q]) + 40.0 * std::log2(double(c->V)));
+    cost[i] = {w, i};
+  }
+  std::sort(cost.begin(), cost.end(), [](auto& x, auto& y) { return x.first > y.first; });
+  std::vector<std::vector<int>> mine(nw);
+  std::vector<double> load(nw, 0.0);
+  for (auto& [w, i] : cost) {
+    const int k = int(std::min_element(load.begin(), load.end()) - load.begin());
+    mine[k].push_back(i);
+    load[k] += w;
+  }
+  std::vector<std::string> errs(nw);
+  auto worker = [&](int k) {
+    hipSetDevice(dev);
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      for (int i : mine[k]) status[i] = SKY_ERR_HIP;
+      errs[k] = "batch_iterate: stream creation failed";
+      return;
+    }
+    for (int i : mine[k]) {
+      sky_ctx* c = ctxs[i];
+      hipStream_t keep = c->st;
+      const bool keep_graphs = c->graphs.on;
+      c->st = s;
+      c->graphs.on = true;
+      std::memset(&reps[i], 0, sizeof(sky_report));
+      status[i] = sky_iterate(c, max_iter, tol, &reps[i]);
+      if (status[i] != SKY_OK && status[i] != SKY_NOT_CONVERGED && errs[k].empty()) errs[k] = g_err;
+      hipStreamSynchronize(s);
+      c->graphs.on = keep_graphs;
+      c->st = keep;
+    }
+    hipStreamDestroy(s);
+  };
+  std::vector<std::thread> pool;
+  for (int k = 1; k < nw; ++k) pool.emplace_back(worker, k);
+  worker(0);
+  for (auto& t : pool) t.join();
+  for (int i = 0; i < nbox; ++i)
+    if (status[i] != SKY_OK && status[i] != SKY_NOT_CONVERGED) {
+      std::string msg;
+      for (auto& e : errs) if (!e.empty()) { msg = e; break; }
+      return fail(status[i], "batch_iterate: box " + std::to_string(i) + ": " + msg);
+    }
   return SKY_OK;
 }
 

@@ -18,7 +18,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import Dict, Tuple
+from typing import Dict, List, Tuple
 
 import numpy as np
 
@@ -171,3 +171,26 @@ def small_workload(name: str, n: int, n_neutrons: int, n_protons: int,
     """A reduced box for fast tests (same force and damping as the others)."""
     return Workload(name, n, 1.0, n_neutrons, n_protons, init, seed=seed,
                     amp=amp if init != "plain" else 0.0, noise=noise)
+
+
+def batch_workloads(count: int = 64, seed: int = 3) -> List[Workload]:
+    """Independent uneven boxes: grid from {16, 24, 32}^3 at 1 fm spacing,
+    mean density uniform in [0.02, 0.06] fm^-3, nucleon number
+    A = round(density * L^3) clamped to [64, 512], proton fraction uniform in
+    [0.1, 0.5] (Z = round(fraction * A), at least 1), initial shape slab, rod
+    or random with equal odds, a seed of its own per box.  All draws come
+    from numpy's PCG64 seeded with ``seed``, box by box in the order grid,
+    density, fraction, shape, box seed."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.choice([16, 24, 32]))
+        rho = float(rng.uniform(0.02, 0.06))
+        frac = float(rng.uniform(0.1, 0.5))
+        init = str(rng.choice(["slab", "rod", "random"]))
+        bseed = int(rng.integers(0, 2 ** 31 - 1))
+        a = int(min(512, max(64, round(rho * n ** 3))))
+        z = max(1, int(round(frac * a)))
+        out.append(Workload(f"b{i:02d}_{n}_{a - z}n{z}p", n, 1.0, a - z, z, init, seed=bseed,
+                            noise=0.02))
+    return out

@@ -36,7 +36,8 @@ _F32_VIEWS = ("pc_params", "pc_grad", "pc_samples", "pc_gains")
 EXPORTS = ("sky_workspace_size", "sky_create", "sky_init_box", "sky_apply_h",
            "sky_damped_step", "sky_orthonormalize", "sky_densities", "sky_iterate",
            "sky_get_view", "sky_set_timing", "sky_get_timing", "sky_get_precision",
-           "sky_autotune", "sky_get_tuning", "sky_precond_collect", "sky_precond_train",
+           "sky_autotune", "sky_get_tuning", "sky_set_graphs", "sky_batch_iterate",
+           "sky_precond_collect", "sky_precond_train",
            "sky_precond_loss_grad", "sky_precond_set_rows", "sky_precond_use", "sky_sync",
            "sky_last_error",
            "sky_destroy")
@@ -113,6 +114,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "sky_get_precision": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int32)]),
         "sky_autotune": (ctypes.c_int, [vp, ctypes.c_char_p, ctypes.POINTER(Tuning)]),
         "sky_get_tuning": (ctypes.c_int, [vp, ctypes.POINTER(Tuning)]),
+        "sky_set_graphs": (ctypes.c_int, [vp, i32]),
+        "sky_batch_iterate": (ctypes.c_int, [ctypes.POINTER(vp), i32, i32, i32, dbl,
+                                             ctypes.POINTER(Report), ctypes.POINTER(ctypes.c_int32)]),
         "sky_precond_collect": (ctypes.c_int, [vp, i32, ctypes.POINTER(ctypes.c_int32)]),
         "sky_precond_train": (ctypes.c_int, [vp, i32, dbl, dp]),
         "sky_precond_loss_grad": (ctypes.c_int, [vp, i32, dp]),
@@ -148,6 +152,26 @@ def desc_from_workload(w, precision: int = SKY_FP64, ladder_tol: float = 0.0) ->
 
 def _ptr(t) -> Optional[int]:
     return None if t is None else t.data_ptr()
+
+
+def _report_dict(rep: Report, rc: int) -> Dict[str, float]:
+    return dict(iters=rep.iters, residual=rep.residual, energy=rep.energy,
+                energy_per_a=rep.energy_per_a, eig_iters=rep.eig_iters,
+                eig_fallbacks=rep.eig_fallbacks, precond_iters=rep.precond_iters,
+                precision=rep.precision, converged=(rc == SKY_OK))
+
+
+def batch_iterate(boxes, nthreads: int, max_iter: int, tol: float = 0.0):
+    """sky_batch_iterate over ``boxes`` (a list of Box): per-box report dicts."""
+    if not boxes:
+        return []
+    lib = boxes[0].lib
+    n = len(boxes)
+    ctxs = (ctypes.c_void_p * n)(*[b.ctx.value for b in boxes])
+    reps = (Report * n)()
+    st = (ctypes.c_int32 * n)()
+    _check(lib.sky_batch_iterate(ctxs, n, nthreads, max_iter, tol, reps, st))
+    return [_report_dict(reps[i], st[i]) for i in range(n)]
 
 
 class Box:
@@ -205,10 +229,7 @@ class Box:
         rep = Report()
         rc = _check(self.lib.sky_iterate(self.ctx, max_iter, tol, ctypes.byref(rep)),
                     ok=(SKY_OK, SKY_NOT_CONVERGED))
-        return dict(iters=rep.iters, residual=rep.residual, energy=rep.energy,
-                    energy_per_a=rep.energy_per_a, eig_iters=rep.eig_iters,
-                    eig_fallbacks=rep.eig_fallbacks, precond_iters=rep.precond_iters,
-                    precision=rep.precision, converged=(rc == SKY_OK))
+        return _report_dict(rep, rc)
 
     def precision(self) -> int:
         p = ctypes.c_int32()
@@ -225,6 +246,9 @@ class Box:
         t = Tuning()
         _check(self.lib.sky_get_tuning(self.ctx, ctypes.byref(t)))
         return t.as_dict()
+
+    def set_graphs(self, enable: bool):
+        _check(self.lib.sky_set_graphs(self.ctx, 1 if enable else 0))
 
     def precond_collect(self, q: int) -> int:
         n = ctypes.c_int32()
