@@ -212,6 +212,75 @@ def bench_batch(args) -> int:
     return 0
 
 
+def bench_to_residual(args) -> int:
+    """Iterations and wall time until Delta-eps <= tol on one workload, for
+    the mixed form, the FP64 form and the mixed form with the learned damping
+    (its sample collection and training counted in its time)."""
+    import torch
+
+    from paper_1610_07522_amd import inputs, sky
+
+    w = inputs.WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    rn, rp = inputs.raw_states(w)
+    dn, dp = torch.from_numpy(rn).to(dev), torch.from_numpy(rp).to(dev)
+    del rn, rp
+    tol = args.to_residual
+    results = {}
+    for mode in args.modes.split(","):
+        prec = sky.SKY_FP64 if mode == "fp64" else sky.SKY_MIXED
+        box = sky.Box(sky.desc_from_workload(w, precision=prec), device=dev)
+        box.init_box(dn, dp)
+        if args.tune_cache != "off":
+            box.autotune(args.tune_cache)
+            box.init_box(dn, dp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its, pc_its, rep = 0, 0, None
+        if mode == "learned":
+            rep = box.iterate(20)
+            its += 20
+            for _ in range(6):
+                box.precond_collect(0)
+                box.precond_collect(1)
+                rep = box.iterate(5)
+                its += 5
+            box.precond_collect(0)
+            box.precond_train(300, 1e-3)
+            box.precond_use(True, 0.05, 100)
+        traj = []
+        while its < args.max_iter:
+            # the tolerance counts from min_iter on: before the pasta structure has
+            # formed, Delta-eps dips below it and rises again
+            armed = its >= args.min_iter
+            chunk = min(100, args.max_iter - its) if armed else min(100, args.min_iter - its)
+            rep = box.iterate(chunk, tol if armed else 0.0)
+            its += rep["iters"]
+            pc_its += rep["precond_iters"]
+            traj.append([its, round(rep["residual"], 6), round(rep["energy"], 4)])
+            log(f"[{mode}] {its} iterations, residual {rep['residual']:.4e}, "
+                f"E {rep['energy']:.6f}, {time.perf_counter() - t0:.1f} s")
+            if armed and rep["converged"]:
+                break
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        results[mode] = dict(iterations=its, seconds=sec,
+                             converged=bool(rep["converged"] and rep["residual"] <= tol),
+                             residual=rep["residual"], energy=rep["energy"],
+                             learned_iterations=pc_its, trajectory=traj)
+        box.close()
+        del box
+        torch.cuda.empty_cache()
+    out = dict(metric=f"time to residual {tol:g}", workload=w.name, tol=tol,
+               min_iter=args.min_iter, max_iter=args.max_iter, results=results)
+    if "mixed" in results and "fp64" in results:
+        out["fp64_over_mixed_time"] = results["fp64"]["seconds"] / results["mixed"]["seconds"]
+    if "mixed" in results and "learned" in results:
+        out["plain_over_learned_time"] = results["mixed"]["seconds"] / results["learned"]["seconds"]
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,6 +295,15 @@ def main() -> int:
                     help="autotuner cache (launch shapes); 'off' keeps the defaults")
     ap.add_argument("--threads", type=int, default=16,
                     help="host workers of the batched driver (workload batch64)")
+    ap.add_argument("--to-residual", type=float, default=0.0,
+                    help="instead of iterations/s: iterations and time until Delta-eps <= this")
+    ap.add_argument("--modes", default="mixed,fp64,learned",
+                    help="forms run by --to-residual (mixed, fp64, learned)")
+    ap.add_argument("--max-iter", type=int, default=4000)
+    ap.add_argument("--min-iter", type=int, default=0,
+                    help="--to-residual: the tolerance is tested from this iteration on")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run three 1 GiB device-to-device copies (HBM counter scale)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -237,6 +315,19 @@ def main() -> int:
 
     from paper_1610_07522_amd import inputs, sky
 
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_bytes=4 << 28, copies=3)), flush=True)
+        return 0
+    if args.to_residual > 0:
+        if not torch.cuda.is_available():
+            print("bench.py needs a ROCm GPU", file=sys.stderr)
+            return 1
+        return bench_to_residual(args)
     if args.workload == "batch64":
         if not torch.cuda.is_available():
             print("bench.py needs a ROCm GPU", file=sys.stderr)

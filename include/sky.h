@@ -226,7 +226,12 @@ int sky_get_precision(sky_ctx* c, int32_t* precision);
 /* Launch shapes of the hot kernels (0 in a split field = the built-in
  * default choice). */
 typedef struct {
-  int32_t h_lines;           /* grid lines (pencils) per workgroup of the h passes */
+  int32_t h_lines;           /* h passes: grid lines (pencils) per workgroup of  */
+                             /* three line passes, or -1: the z pass by pencils */
+                             /* and x, y together on LDS z-slices               */
+  int32_t damp_xy;           /* damped step: 1 = x and y transforms on LDS       */
+                             /* z-slices (where they fit), 0 = line passes,     */
+                             /* -1 = the default (slices up to 32^3)            */
   int32_t overlap_split[2];  /* split-K factor of the I/H product per species    */
   int32_t square_split[2];   /* split-K factor of the subspace products          */
   int32_t from_cache;        /* 1: every shape came from the cache file          */
@@ -234,11 +239,12 @@ typedef struct {
 
 /* Autotuner.  Picks, for this box, the fastest of a few candidate launch
  * shapes of the dominant kernels: the pencils per workgroup of the h passes
+ * or their LDS-slice variant, the slice or line variant of the damped step
  * (the FFT line kernels, keyed by grid size and precision), and the split-K
  * factors of the overlap/Hamiltonian product and of the square subspace
  * products (keyed by state count, grid points and precision).  Candidates
  * are timed with HIP events on the context's own buffers: call after
- * sky_init_box; the run overwrites h psi and the subspace matrices (the
+ * sky_init_box; the run overwrites h psi, phi and the subspace matrices (the
  * states are untouched).  Every candidate computes the same result up to
  * the order of floating-point sums.  cache_path (may be NULL): a flat JSON
  * object {"key": value}; shapes found there are used without timing, and

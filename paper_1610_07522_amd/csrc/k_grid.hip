@@ -2,6 +2,8 @@
 // step, and the local densities.  All are passes over lines of one axis
 // (fft_line.h); one workgroup takes LPW lines of one state (h, damping) or of
 // a chunk of states (densities).
+#include <algorithm>
+
 #include "fft_line.h"
 #include "sky_kernels.h"
 
@@ -134,6 +136,294 @@ __global__ void k_sum_partials(const double* __restrict__ part, int ntile, int n
   double acc = 0.0;
   for (int t = 0; t < ntile; ++t) acc += part[size_t(s) * ntile + t];
   out[s] = acc;
+}
+
+// ------------------------------------------------------------------ xy planes
+// One workgroup holds a z-slice of one state (both spin components, N x N
+// points, rows padded to N + 1) in LDS and runs the x lines (rows) and the y
+// lines (columns) of a pass on it, so that x and y cost one read and one
+// write of the state instead of two each.  Threads: N lines x RT per line.
+// Used where slice and exchange buffers fit 80 KB of LDS (two workgroups per
+// CU): every grid in complex64 up to 48^3, complex128 up to 32^3.
+template <int N> struct PlaneCfg {
+  static constexpr int R1 = Fact<N>::R1, R2 = Fact<N>::R2;
+  static constexpr int RT = R1 > R2 ? R1 : R2;
+  static constexpr int THREADS = N * RT;
+  static constexpr int PITCH = N + 1;
+  static constexpr int SPIN = N * PITCH;   // one spin component of the slice
+};
+
+template <typename T, int N> constexpr bool plane_fits() {
+  return PlaneCfg<N>::THREADS <= 1024 &&
+         (2 * PlaneCfg<N>::SPIN + N * LineFFT<T, N, 2>::YSIZE + N) * sizeof(cpx<T>) <= 80 * 1024;
+}
+// Default use: measured on MI355X, the slices win up to 32^3 (damped step
+// 16% faster, h psi even or faster); at 48^3 their 80 KB of LDS leaves two
+// workgroups per CU and the line passes are faster.  The tuner decides per box.
+template <typename T, int N> constexpr bool plane_default() { return plane_fits<T, N>() && N <= 32; }
+
+// Deterministic workgroup sum of one double per thread (any blockDim), using
+// buf[blockDim.x] of LDS; the result is returned to thread 0.
+__device__ inline double tree_sum(double v, double* buf) {
+  buf[threadIdx.x] = v;
+  __syncthreads();
+  int n = blockDim.x;
+  while (n > 1) {
+    const int h = (n + 1) / 2;
+    if (threadIdx.x < n - h) buf[threadIdx.x] += buf[threadIdx.x + h];
+    __syncthreads();
+    n = h;
+  }
+  return buf[0];
+}
+
+// The DIR part of h on one line held by this thread (R1 points at grid
+// offsets r[j1]): D g + (i/2) A D psi with g = -B D psi + (i/2) A psi.
+template <typename T, int N, int DIR>
+__device__ inline void h_dir_line(const cpx<T> (&v)[2][Fact<N>::R1], cpx<T> (&out)[2][Fact<N>::R1],
+                                  const int (&r)[Fact<N>::R1], cpx<T>* Y, int j,
+                                  const cpx<T>* tw, T kunit, const MeanFieldPtrs& mf) {
+  using F = LineFFT<T, N, 2>;
+  constexpr int R1 = Fact<N>::R1, R2 = Fact<N>::R2, N3 = N * N * N;
+  cpx<T> d[2][R1];
+#pragma unroll
+  for (int j1 = 0; j1 < R1; ++j1) {
+    d[0][j1] = v[0][j1];
+    d[1][j1] = v[1][j1];
+  }
+  F::deriv(d, Y, j, tw, kunit);
+  if (j < R2) {
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1) {
+      const int q = r[j1];
+      const T B = T(mf.B[q]);
+      double ax, ay, az;
+      so_coeffs<DIR>(mf.W[q], mf.W[N3 + q], mf.W[2 * N3 + q], ax, ay, az);
+      cpx<T> au, ad, bu, bd;
+      sigma_apply<T>(T(ax), T(ay), T(az), d[0][j1], d[1][j1], au, ad);     // A D psi
+      sigma_apply<T>(T(ax), T(ay), T(az), v[0][j1], v[1][j1], bu, bd);     // A psi
+      out[0][j1] = T(0.5) * mul_i(au);
+      out[1][j1] = T(0.5) * mul_i(ad);
+      d[0][j1] = T(0.5) * mul_i(bu) - B * d[0][j1];
+      d[1][j1] = T(0.5) * mul_i(bd) - B * d[1][j1];
+    }
+  }
+  F::deriv(d, Y, j, tw, kunit);
+  if (j < R2) {
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1) {
+      out[0][j1] = out[0][j1] + d[0][j1];
+      out[1][j1] = out[1][j1] + d[1][j1];
+    }
+  }
+}
+
+// x and y parts of h psi on slice z = blockIdx.x of state blockIdx.y, added to
+// what hpsi holds (the z part and U psi); partial sums of <psi|h psi>.
+template <typename T, int N>
+__global__ void __launch_bounds__(PlaneCfg<N>::THREADS)
+k_h_plane(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPtrs mf, GridArgs g,
+          double* __restrict__ eps_part) {
+  using C = PlaneCfg<N>;
+  using F = LineFFT<T, N, 2>;
+  constexpr int R1 = C::R1, R2 = C::R2, RT = C::RT, PITCH = C::PITCH, SP = C::SPIN;
+  constexpr int N2 = N * N, N3 = N * N2;
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> P[2 * SP];
+  __shared__ cpx<T> Ybuf[N * F::YSIZE];
+  load_twiddles<T, N>(tw);
+  const int zoff = blockIdx.x * N2;
+  const size_t soff = size_t(blockIdx.y) * 2 * N3;
+  const cpx<T>* p = psi + soff;
+  cpx<T>* hp = hpsi + soff;
+  for (int i = threadIdx.x; i < 2 * N2; i += C::THREADS) {
+    const int s = i / N2, e = i - s * N2;
+    P[s * SP + (e / N) * PITCH + e % N] = p[s * N3 + zoff + e];
+  }
+  __syncthreads();
+  const T kunit = T(g.kunit);
+  // x lines: row ly, role jx (role fastest: consecutive threads, consecutive x)
+  const int jx = threadIdx.x % RT, ly = threadIdx.x / RT;
+  cpx<T> vx[2][R1], ax[2][R1];
+  int rx[R1];
+#pragma unroll
+  for (int j1 = 0; j1 < R1; ++j1) {
+    const int x = jx + R2 * j1;
+    rx[j1] = zoff + ly * N + x;
+    if (jx < R2) {
+      vx[0][j1] = P[ly * PITCH + x];
+      vx[1][j1] = P[SP + ly * PITCH + x];
+    }
+  }
+  h_dir_line<T, N, 0>(vx, ax, rx, Ybuf + ly * F::YSIZE, jx, tw, kunit, mf);
+  // y lines: column lx (line fastest: consecutive threads, consecutive x)
+  const int lx = threadIdx.x % N, jy = threadIdx.x / N;
+  cpx<T> vy[2][R1], ay[2][R1];
+  int ry[R1];
+#pragma unroll
+  for (int j1 = 0; j1 < R1; ++j1) {
+    const int y = jy + R2 * j1;
+    ry[j1] = zoff + y * N + lx;
+    if (jy < R2) {
+      vy[0][j1] = P[y * PITCH + lx];
+      vy[1][j1] = P[SP + y * PITCH + lx];
+    }
+  }
+  __syncthreads();
+  if (jx < R2) {
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1) {
+      P[ly * PITCH + jx + R2 * j1] = ax[0][j1];
+      P[SP + ly * PITCH + jx + R2 * j1] = ax[1][j1];
+    }
+  }
+  __syncthreads();
+  h_dir_line<T, N, 1>(vy, ay, ry, Ybuf + lx * F::YSIZE, jy, tw, kunit, mf);
+  double dot = 0.0;
+  if (jy < R2) {
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1) {
+      const int y = jy + R2 * j1;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const cpx<T> t = ay[s][j1] + P[s * SP + y * PITCH + lx] + hp[s * N3 + ry[j1]];
+        hp[s * N3 + ry[j1]] = t;
+        dot += double(vy[s][j1].re) * double(t.re) + double(vy[s][j1].im) * double(t.im);
+      }
+    }
+  }
+  if (eps_part != nullptr) {
+    __syncthreads();   // P is free again: reuse it for the reduction
+    const double sum = tree_sum(dot, reinterpret_cast<double*>(P));
+    if (threadIdx.x == 0) eps_part[size_t(blockIdx.y) * gridDim.x + blockIdx.x] = sum * g.dV;
+  }
+}
+
+// Damped step, first half: r = h psi - eps psi on slice z of state
+// blockIdx.y, forward FFTs along x and y, spectrum to out; ||r||^2 partials.
+template <typename T, int N>
+__global__ void __launch_bounds__(PlaneCfg<N>::THREADS)
+k_damp_fwd_xy(const cpx<T>* __restrict__ psi, const cpx<T>* __restrict__ hpsi,
+              const double* __restrict__ eps, cpx<T>* __restrict__ out, GridArgs g,
+              double* __restrict__ r2_part) {
+  using C = PlaneCfg<N>;
+  using F = LineFFT<T, N, 2>;
+  constexpr int R1 = C::R1, R2 = C::R2, RT = C::RT, PITCH = C::PITCH, SP = C::SPIN;
+  constexpr int N2 = N * N, N3 = N * N2;
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> P[2 * SP];
+  __shared__ cpx<T> Ybuf[N * F::YSIZE];
+  load_twiddles<T, N>(tw);
+  const int zoff = blockIdx.x * N2;
+  const size_t soff = size_t(blockIdx.y) * 2 * N3;
+  const T e = T(eps[blockIdx.y]);
+  double r2 = 0.0;
+  for (int i = threadIdx.x; i < 2 * N2; i += C::THREADS) {
+    const int s = i / N2, q = i - s * N2;
+    const size_t o = soff + s * N3 + zoff + q;
+    const cpx<T> res = hpsi[o] - e * psi[o];
+    r2 += double(res.re) * double(res.re) + double(res.im) * double(res.im);
+    P[s * SP + (q / N) * PITCH + q % N] = res;
+  }
+  __syncthreads();
+  {  // x lines, in place (row ly)
+    const int j = threadIdx.x % RT, ly = threadIdx.x / RT;
+    cpx<T> va[2][R1], vb[2][R2];
+    if (j < R2)
+#pragma unroll
+      for (int j1 = 0; j1 < R1; ++j1)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) va[s][j1] = P[s * SP + ly * PITCH + j + R2 * j1];
+    F::forward(va, vb, Ybuf + ly * F::YSIZE, j, tw);
+    if (j < R1)
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) P[s * SP + ly * PITCH + j + R1 * k2] = vb[s][k2];
+  }
+  __syncthreads();
+  {  // y lines, in place (column lx)
+    const int lx = threadIdx.x % N, j = threadIdx.x / N;
+    cpx<T> va[2][R1], vb[2][R2];
+    if (j < R2)
+#pragma unroll
+      for (int j1 = 0; j1 < R1; ++j1)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) va[s][j1] = P[s * SP + (j + R2 * j1) * PITCH + lx];
+    F::forward(va, vb, Ybuf + lx * F::YSIZE, j, tw);
+    if (j < R1)
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) P[s * SP + (j + R1 * k2) * PITCH + lx] = vb[s][k2];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2 * N2; i += C::THREADS) {
+    const int s = i / N2, q = i - s * N2;
+    out[soff + s * N3 + zoff + q] = P[s * SP + (q / N) * PITCH + q % N];
+  }
+  __syncthreads();   // P is free again: reuse it for the reduction
+  const double sum = tree_sum(r2, reinterpret_cast<double*>(P));
+  if (threadIdx.x == 0) r2_part[size_t(blockIdx.y) * gridDim.x + blockIdx.x] = sum * g.dV;
+}
+
+// Damped step, last half: inverse FFTs along y and x of slice z of the
+// filtered spectrum in buf, then phi = psi - result, in place.
+template <typename T, int N>
+__global__ void __launch_bounds__(PlaneCfg<N>::THREADS)
+k_damp_inv_xy(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ buf) {
+  using C = PlaneCfg<N>;
+  using F = LineFFT<T, N, 2>;
+  constexpr int R1 = C::R1, R2 = C::R2, RT = C::RT, PITCH = C::PITCH, SP = C::SPIN;
+  constexpr int N2 = N * N, N3 = N * N2;
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> P[2 * SP];
+  __shared__ cpx<T> Ybuf[N * F::YSIZE];
+  load_twiddles<T, N>(tw);
+  const int zoff = blockIdx.x * N2;
+  const size_t soff = size_t(blockIdx.y) * 2 * N3;
+  for (int i = threadIdx.x; i < 2 * N2; i += C::THREADS) {
+    const int s = i / N2, q = i - s * N2;
+    P[s * SP + (q / N) * PITCH + q % N] = buf[soff + s * N3 + zoff + q];
+  }
+  __syncthreads();
+  {  // y lines (column lx): frequencies -> positions
+    const int lx = threadIdx.x % N, j = threadIdx.x / N;
+    cpx<T> va[2][R1], vb[2][R2];
+    if (j < R1)
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) vb[s][k2] = P[s * SP + (j + R1 * k2) * PITCH + lx];
+    F::inverse(vb, va, Ybuf + lx * F::YSIZE, j, tw);
+    if (j < R2)
+#pragma unroll
+      for (int j1 = 0; j1 < R1; ++j1)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) P[s * SP + (j + R2 * j1) * PITCH + lx] = va[s][j1];
+  }
+  __syncthreads();
+  {  // x lines (row ly)
+    const int j = threadIdx.x % RT, ly = threadIdx.x / RT;
+    cpx<T> va[2][R1], vb[2][R2];
+    if (j < R1)
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) vb[s][k2] = P[s * SP + ly * PITCH + j + R1 * k2];
+    F::inverse(vb, va, Ybuf + ly * F::YSIZE, j, tw);
+    if (j < R2)
+#pragma unroll
+      for (int j1 = 0; j1 < R1; ++j1)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) P[s * SP + ly * PITCH + j + R2 * j1] = va[s][j1];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2 * N2; i += C::THREADS) {
+    const int s = i / N2, q = i - s * N2;
+    const size_t o = soff + s * N3 + zoff + q;
+    buf[o] = psi[o] - P[s * SP + (q / N) * PITCH + q % N];
+  }
 }
 
 // ------------------------------------------------------------------ damping
@@ -522,36 +812,81 @@ static void launch_h_lp(const void* psi, void* hpsi, int nstate, MeanFieldPtrs m
   hipLaunchKernelGGL((k_h_pass<T, N, 2, false, true, LP>), grid, block, 0, st, p, h, mf, g, eps_part);
 }
 
-// lines: 0 = default; else one of h_pass_lines(n, prec).  Returns the tile
-// count (workgroups per state) used, or 0 if lines is not supported.
+// z pass (with U psi) by line pencils, then the x and y parts on LDS slices.
+template <typename T, int N>
+static void launch_h_plane(const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf, GridArgs g,
+                           double* eps_part, hipStream_t st) {
+  constexpr int D = LineCfg<N>::LPW;
+  auto p = reinterpret_cast<const cpx<T>*>(psi);
+  auto h = reinterpret_cast<cpx<T>*>(hpsi);
+  hipLaunchKernelGGL((k_h_pass<T, N, 2, true, false, D>), dim3(N * N / D, nstate),
+                     dim3(LineCfg<N>::THREADS), 0, st, p, h, mf, g, nullptr);
+  hipLaunchKernelGGL((k_h_plane<T, N>), dim3(N, nstate), dim3(PlaneCfg<N>::THREADS), 0, st, p, h,
+                     mf, g, eps_part);
+}
+
+// lines: 0 = default, H_PLANE = x and y on LDS slices, else pencils per
+// workgroup of the three line passes (one of h_pass_lines).  Returns the
+// eps partials (workgroups) per state, or 0 if lines is not supported.
 template <typename T, int N>
 static int launch_apply_h(const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf, GridArgs g,
                           double* eps_part, int lines, hipStream_t st) {
   constexpr int D = LineCfg<N>::LPW;
   constexpr int H = (D / 2 > 0 && lines_ok<N>(D / 2, sizeof(cpx<T>))) ? D / 2 : D;
   constexpr int W = lines_ok<N>(2 * D, sizeof(cpx<T>)) ? 2 * D : D;
-  if (lines == 0 || lines == D) { launch_h_lp<T, N, D>(psi, hpsi, nstate, mf, g, eps_part, st); return N * N / D; }
+  constexpr bool PL = plane_fits<T, N>();
+  if (lines == 0) lines = plane_default<T, N>() ? H_PLANE : D;
+  if (lines == H_PLANE) {
+    if constexpr (PL) {
+      launch_h_plane<T, N>(psi, hpsi, nstate, mf, g, eps_part, st);
+      return N;
+    }
+    return 0;
+  }
+  if (lines == D) { launch_h_lp<T, N, D>(psi, hpsi, nstate, mf, g, eps_part, st); return N * N / D; }
   if (lines == H) { launch_h_lp<T, N, H>(psi, hpsi, nstate, mf, g, eps_part, st); return N * N / H; }
   if (lines == W) { launch_h_lp<T, N, W>(psi, hpsi, nstate, mf, g, eps_part, st); return N * N / W; }
   return 0;
 }
 
-template <typename T, int N> static void lines_list(int* out) {
+// Candidates of the tuner: the slice variant (where it fits), then half,
+// default and double pencils (deduplicated).  Returns the count.
+template <typename T, int N> static int lines_list(int* out) {
   constexpr int D = LineCfg<N>::LPW;
-  out[0] = (D / 2 > 0 && lines_ok<N>(D / 2, sizeof(cpx<T>))) ? D / 2 : D;
-  out[1] = D;
-  out[2] = lines_ok<N>(2 * D, sizeof(cpx<T>)) ? 2 * D : D;
+  int k = 0;
+  if (plane_fits<T, N>()) out[k++] = H_PLANE;
+  const int c[3] = {(D / 2 > 0 && lines_ok<N>(D / 2, sizeof(cpx<T>))) ? D / 2 : D, D,
+                    lines_ok<N>(2 * D, sizeof(cpx<T>)) ? 2 * D : D};
+  for (int i = 0; i < 3; ++i) {
+    bool dup = false;
+    for (int m = 0; m < k; ++m) dup = dup || out[m] == c[i];
+    if (!dup) out[k++] = c[i];
+  }
+  return k;
+}
+
+template <typename T, int N> static int lines_default() {
+  return plane_default<T, N>() ? H_PLANE : LineCfg<N>::LPW;
 }
 
 int grid_ntiles(int n) {
   int r = 0;
-  SKY_DISPATCH_N(n, r = ntiles<NN>());
-  return 2 * r;   // room for the h passes at half the default lines per workgroup
+  SKY_DISPATCH_N(n, r = std::max(2 * ntiles<NN>(), NN));
+  return r;   // room for the h passes at half the default pencils, or one per slice
 }
 
-void h_pass_lines(int n, int prec, int* out) {
-  if (prec == 0) SKY_DISPATCH_N(n, lines_list<double, NN>(out))
-  else SKY_DISPATCH_N(n, lines_list<float, NN>(out))
+int h_pass_lines(int n, int prec, int* out) {
+  int k = 0;
+  if (prec == 0) SKY_DISPATCH_N(n, k = (lines_list<double, NN>(out)))
+  else SKY_DISPATCH_N(n, k = (lines_list<float, NN>(out)))
+  return k;
+}
+
+int h_pass_default(int n, int prec) {
+  int v = 0;
+  if (prec == 0) SKY_DISPATCH_N(n, v = (lines_default<double, NN>()))
+  else SKY_DISPATCH_N(n, v = (lines_default<float, NN>()))
+  return v;
 }
 
 int apply_h(int n, int prec, const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf,
@@ -573,14 +908,21 @@ int apply_h(int n, int prec, const void* psi, void* hpsi, int nstate, MeanFieldP
 template <typename T, int N>
 static void launch_damp(const void* psi, const void* hpsi, const double* eps, void* phi,
                         int nstate, GridArgs g, DampArgs d, double* r2_part, const float* gain,
-                        double* shell_pow, int stage, hipStream_t st) {
+                        double* shell_pow, int stage, int xy, hipStream_t st) {
   dim3 grid(ntiles<N>(), nstate), block(LineCfg<N>::THREADS);
+  dim3 pgrid(N, nstate), pblock(PlaneCfg<N>::THREADS);
   auto p = reinterpret_cast<const cpx<T>*>(psi);
   auto h = reinterpret_cast<const cpx<T>*>(hpsi);
   auto o = reinterpret_cast<cpx<T>*>(phi);
+  const bool pl = plane_fits<T, N>() && (xy < 0 ? plane_default<T, N>() : xy != 0);
   if (stage != 2) {
-    hipLaunchKernelGGL((k_damp_fwd_x<T, N>), grid, block, 0, st, p, h, eps, o, g, r2_part);
-    hipLaunchKernelGGL((k_damp_y<T, N, false>), grid, block, 0, st, o);
+    if (pl) {
+      if constexpr (plane_fits<T, N>())
+        hipLaunchKernelGGL((k_damp_fwd_xy<T, N>), pgrid, pblock, 0, st, p, h, eps, o, g, r2_part);
+    } else {
+      hipLaunchKernelGGL((k_damp_fwd_x<T, N>), grid, block, 0, st, p, h, eps, o, g, r2_part);
+      hipLaunchKernelGGL((k_damp_y<T, N, false>), grid, block, 0, st, o);
+    }
     if (shell_pow)
       hipLaunchKernelGGL((k_damp_z<T, N, 1>), grid, block, 0, st, o, g, d, nullptr, shell_pow);
   }
@@ -589,21 +931,29 @@ static void launch_damp(const void* psi, const void* hpsi, const double* eps, vo
     hipLaunchKernelGGL((k_damp_z<T, N, 2>), grid, block, 0, st, o, g, d, gain, nullptr);
   else
     hipLaunchKernelGGL((k_damp_z<T, N, 0>), grid, block, 0, st, o, g, d, nullptr, nullptr);
-  hipLaunchKernelGGL((k_damp_y<T, N, true>), grid, block, 0, st, o);
-  hipLaunchKernelGGL((k_damp_inv_x<T, N>), grid, block, 0, st, p, o);
+  if (pl) {
+    if constexpr (plane_fits<T, N>())
+      hipLaunchKernelGGL((k_damp_inv_xy<T, N>), pgrid, pblock, 0, st, p, o);
+  } else {
+    hipLaunchKernelGGL((k_damp_y<T, N, true>), grid, block, 0, st, o);
+    hipLaunchKernelGGL((k_damp_inv_x<T, N>), grid, block, 0, st, p, o);
+  }
 }
 
 void damped_step(int n, int prec, const void* psi, const void* hpsi, const double* eps,
                  void* phi, int nstate, GridArgs g, double x0, double e0, double hb2m,
                  double* r2_part, double* r2, hipStream_t st, const float* gain,
-                 double* shell_pow, int stage) {
+                 double* shell_pow, int stage, int xy) {
   if (nstate <= 0) return;
   DampArgs d{x0, e0, hb2m};
-  if (prec == 0) SKY_DISPATCH_N(n, launch_damp<double, NN>(psi, hpsi, eps, phi, nstate, g, d, r2_part, gain, shell_pow, stage, st))
-  else SKY_DISPATCH_N(n, launch_damp<float, NN>(psi, hpsi, eps, phi, nstate, g, d, r2_part, gain, shell_pow, stage, st))
+  if (prec == 0) SKY_DISPATCH_N(n, launch_damp<double, NN>(psi, hpsi, eps, phi, nstate, g, d, r2_part, gain, shell_pow, stage, xy, st))
+  else SKY_DISPATCH_N(n, launch_damp<float, NN>(psi, hpsi, eps, phi, nstate, g, d, r2_part, gain, shell_pow, stage, xy, st))
   if (stage == 2) return;
   int nt = 0;
-  SKY_DISPATCH_N(n, nt = ntiles<NN>());
+  if (prec == 0)
+    SKY_DISPATCH_N(n, nt = (plane_fits<double, NN>() && (xy < 0 ? plane_default<double, NN>() : xy != 0)) ? NN : ntiles<NN>())
+  else
+    SKY_DISPATCH_N(n, nt = (plane_fits<float, NN>() && (xy < 0 ? plane_default<float, NN>() : xy != 0)) ? NN : ntiles<NN>())
   if (r2)
     hipLaunchKernelGGL(k_sum_partials, dim3((nstate + 127) / 128), dim3(128), 0, st,
                        (const double*)r2_part, nt, nstate, r2);

@@ -194,7 +194,13 @@ struct sky_ctx {
   int fallbacks;       // refinement -> Jacobi fallbacks in the current call
   // launch shapes (0 = the built-in default): h-pass lines per workgroup,
   // overlap and square-product split-K factors per species
-  struct Tune { int lines = 0; int ovl[2] = {0, 0}; int sq[2] = {0, 0}; int from_cache = 0; } tune;
+  struct Tune {
+    int lines = 0;
+    int damp_xy = -1;   // -1: the default for the grid and precision
+    int ovl[2] = {0, 0};
+    int sq[2] = {0, 0};
+    int from_cache = 0;
+  } tune;
   // learned preconditioner state
   int pc_count = 0;        // sample rows held
   int pc_wr = 0;           // next row written by a collection (ring)
@@ -471,14 +477,14 @@ void learned_damp(sky_ctx* c, int q, const void* psi, const void* hpsi, const do
   double* pw = c->at<double>(c->lay.pc_pow);
   zero(pw, size_t(m) * PC_SHELLS, st);
   damped_step(c->n, c->prec, psi, hpsi, eps, phi, m, c->g, c->d.damp_x0, c->d.damp_e0, hb,
-              c->at<double>(c->lay.tiles), r2, st, nullptr, pw, 1);
+              c->at<double>(c->lay.tiles), r2, st, nullptr, pw, 1, c->tune.damp_xy);
   float* X = c->at<float>(c->lay.pc_X);
   precond_features(pw, eps, 1, m, c->d.damp_e0, hb, kmax_of(c), X, st);
   precond_forward(c->at<float>(c->lay.pc_Pb), X, m * PC_SHELLS, nullptr, nullptr, nullptr,
                   c->at<float>(c->lay.pc_O), st);
   precond_gains(c->at<float>(c->lay.pc_O), m * PC_SHELLS, c->at<float>(c->lay.pc_gain), st);
   damped_step(c->n, c->prec, psi, hpsi, eps, phi, m, c->g, c->d.damp_x0, c->d.damp_e0, hb,
-              nullptr, nullptr, st, c->at<float>(c->lay.pc_gain), nullptr, 2);
+              nullptr, nullptr, st, c->at<float>(c->lay.pc_gain), nullptr, 2, c->tune.damp_xy);
 }
 
 // Training rows from the current states of species q: the shell powers and
@@ -511,7 +517,7 @@ int pc_collect(sky_ctx* c, int q) {
   zero(pw, size_t(nb) * PC_SHELLS, st);
   const double hb = q ? c->d.hb2m_p : c->d.hb2m_n;
   damped_step(c->n, c->prec, b0, b1, beps, b2, nb, c->g, c->d.damp_x0, c->d.damp_e0, hb, tiles,
-              nullptr, st, onehot, pw, 0);
+              nullptr, st, onehot, pw, 0, c->tune.damp_xy);
   float* rows = c->at<float>(c->lay.pc_S) + size_t(c->pc_wr) * 6;
   precond_features(pw, beps, PC_SHELLS, ns, c->d.damp_e0, hb, kmax_of(c), rows, st);
   precond_dir(c->prec, b0, b2, size_t(nb) * c->V, st);
@@ -580,7 +586,7 @@ void step_a(sky_ctx* c, int q, bool learned) {
     learned_damp(c, q, psi, hpsi, eps, phi, m, c->at<double>(c->lay.r2[q]), st);
   else
     damped_step(c->n, c->prec, psi, hpsi, eps, phi, m, c->g, c->d.damp_x0, c->d.damp_e0, hb,
-                tiles, c->at<double>(c->lay.r2[q]), st);
+                tiles, c->at<double>(c->lay.r2[q]), st, nullptr, nullptr, 0, c->tune.damp_xy);
   t_end(c, t1);
   int t2 = t_begin(c, SKY_PHASE_APPLY_H, q);
   apply_h(c->n, c->prec, phi, hphi, m, c->mfp(q), c->g, nullptr, nullptr, st, c->tune.lines);
@@ -675,6 +681,12 @@ int cache_get(const std::vector<std::pair<std::string, int>>& kv, const std::str
   for (const auto& e : kv)
     if (e.first == key) return e.second;
   return 0;
+}
+
+bool cache_has(const std::vector<std::pair<std::string, int>>& kv, const std::string& key) {
+  for (const auto& e : kv)
+    if (e.first == key) return true;
+  return false;
 }
 
 void cache_put(std::vector<std::pair<std::string, int>>& kv, const std::string& key, int v) {
@@ -810,7 +822,7 @@ int sky_damped_step(sky_ctx* c, int32_t q, const void* psi, const void* hpsi, co
   double* r2o = r2 ? r2 : c->at<double>(c->lay.r2[q]);
   const double hb = q ? c->d.hb2m_p : c->d.hb2m_n;
   damped_step(c->n, c->prec, psi, hpsi, eps, phi, nstates, c->g, c->d.damp_x0, c->d.damp_e0,
-              hb, c->at<double>(c->lay.tiles), r2o, c->st);
+              hb, c->at<double>(c->lay.tiles), r2o, c->st, nullptr, nullptr, 0, c->tune.damp_xy);
   return hip_check(hipGetLastError(), "damped_step launch");
 }
 
@@ -1004,6 +1016,7 @@ int sky_autotune(sky_ctx* c, const char* cache_path, sky_tuning* out) {
   auto kv = cache_read(cache_path);
   const char* pr = c->prec ? "mixed" : "fp64";
   const std::string klines = "h_lines/n" + std::to_string(c->n) + "/" + pr;
+  const std::string kdamp = "damp_xy/n" + std::to_string(c->n) + "/" + pr;
   std::string kovl[2], ksq[2];
   for (int q = 0; q < 2; ++q) {
     kovl[q] = "overlap_split/m" + std::to_string(c->nq[q]) + "/k" + std::to_string(c->V) + "/" + pr;
@@ -1014,12 +1027,12 @@ int sky_autotune(sky_ctx* c, const char* cache_path, sky_tuning* out) {
   {
     const int q = c->nq[0] > 0 ? 0 : 1;
     int v = cache_get(kv, klines);
-    int cand[3];
-    h_pass_lines(c->n, c->prec, cand);
+    int cand[4];
+    const int nl = h_pass_lines(c->n, c->prec, cand);
     bool ok = false;
-    for (int i = 0; i < 3; ++i) ok = ok || cand[i] == v;
+    for (int i = 0; i < nl; ++i) ok = ok || cand[i] == v;
     if (!ok) {
-      v = pick(st, cand, 3, [&](int lp) {
+      v = pick(st, cand, nl, [&](int lp) {
         apply_h(c->n, c->prec, c->psi(q), c->hpsi(q), c->nq[q], c->mfp(q), c->g, nullptr, nullptr,
                 st, lp);
       });
@@ -1027,6 +1040,22 @@ int sky_autotune(sky_ctx* c, const char* cache_path, sky_tuning* out) {
       ++timed;
     }
     c->tune.lines = v;
+    // x and y transforms of the damped step on LDS slices (1) or by pencils (0)
+    int dv = cache_has(kv, kdamp) ? cache_get(kv, kdamp) : -1;
+    if (cand[0] != H_PLANE) dv = 1;   // no slice variant on this grid: nothing to pick
+    if (dv != 0 && dv != 1) {
+      const int dc[2] = {1, 0};
+      const double hb = q ? c->d.hb2m_p : c->d.hb2m_n;
+      double* eps = c->at<double>(c->lay.eps[q]);
+      dv = pick(st, dc, 2, [&](int xy) {
+        damped_step(c->n, c->prec, c->psi(q), c->hpsi(q), eps, c->phi(q), c->nq[q], c->g,
+                    c->d.damp_x0, c->d.damp_e0, hb, c->at<double>(c->lay.tiles), nullptr, st,
+                    nullptr, nullptr, 0, xy);
+      });
+      cache_put(kv, kdamp, dv);
+      ++timed;
+    }
+    c->tune.damp_xy = dv;
   }
   for (int q = 0; q < 2; ++q) {
     const int m = c->nq[q];
@@ -1087,9 +1116,8 @@ int sky_autotune(sky_ctx* c, const char* cache_path, sky_tuning* out) {
 int sky_get_tuning(sky_ctx* c, sky_tuning* out) {
   if (!c) return fail(SKY_ERR_INVALID, "null context");
   if (!out) return SKY_OK;
-  int cand[3];
-  h_pass_lines(c->n, c->prec, cand);
-  out->h_lines = c->tune.lines ? c->tune.lines : cand[1];
+  out->h_lines = c->tune.lines ? c->tune.lines : h_pass_default(c->n, c->prec);
+  out->damp_xy = c->tune.damp_xy;
   for (int q = 0; q < 2; ++q) {
     out->overlap_split[q] = c->tune.ovl[q];
     out->square_split[q] = c->tune.sq[q];

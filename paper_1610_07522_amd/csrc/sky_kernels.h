@@ -7,23 +7,28 @@ namespace sky {
 
 // ---- grid kernels (k_grid.hip); states are [state][2][n^3], complex128
 // (prec 0) or complex64 (prec 1); reductions are FP64 either way.
-int grid_ntiles(int n);  // workgroups per state of one line pass
-// lines: lines (pencils) per workgroup of the h passes, 0 = default, else one
-// of h_pass_lines(n, prec) (out[3]: half, default, double where possible).
-// Returns 0 if lines is not supported (nothing launched).
-void h_pass_lines(int n, int prec, int* out);
+int grid_ntiles(int n);  // room for the per-state partials of one pass
+// lines: 0 = default; H_PLANE = z by line pencils, x and y on LDS z-slices;
+// else pencils per workgroup of the three line passes.  h_pass_lines fills
+// the supported values (out[4]) and returns their count; h_pass_default is
+// what 0 selects.  apply_h returns 0 if lines is not supported.
+constexpr int H_PLANE = -1;
+int h_pass_lines(int n, int prec, int* out);
+int h_pass_default(int n, int prec);
 int apply_h(int n, int prec, const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf,
             GridArgs g, double* eps_part, double* eps, hipStream_t st, int lines = 0);
 // gain (optional, [state][PC_SHELLS]): multiplies the damping per |k| shell.
 // shell_pow (optional, [state][PC_SHELLS], accumulated: clear first): the
 // residual's spectral power per shell, from an extra read-only pass.
+// xy: 1 = x and y transforms on LDS z-slices where they fit, 0 = line
+// passes, -1 = the default for the grid and precision.
 // stage 0: whole step; 1: up to the shell powers (partial spectrum left in
 // phi, r2 formed); 2: the rest, continuing from stage 1 (gains decided in
 // between).
 void damped_step(int n, int prec, const void* psi, const void* hpsi, const double* eps,
                  void* phi, int nstate, GridArgs g, double x0, double e0, double hb2m,
                  double* r2_part, double* r2, hipStream_t st, const float* gain = nullptr,
-                 double* shell_pow = nullptr, int stage = 0);
+                 double* shell_pow = nullptr, int stage = 0, int xy = -1);
 
 // ---- learned preconditioner (k_precond.hip)
 int precond_nparams();

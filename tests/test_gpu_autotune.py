@@ -46,7 +46,8 @@ def test_autotune_parity_and_cache(torch_mod, tmp_path, case, precision, tol):
     prec = "mixed" if precision else "fp64"
     assert stored[f"h_lines/n{w.n}/{prec}"] == t["h_lines"]
     assert stored[f"overlap_split/m{w.n_neutrons}/k{2 * w.n ** 3}/{prec}"] == t["overlap_split"][0]
-    assert t["h_lines"] in (16, 32, 64, 128) and all(s >= 1 for s in t["square_split"])
+    assert t["h_lines"] in (-1, 16, 32, 64, 128) and all(s >= 1 for s in t["square_split"])
+    assert t["damp_xy"] in (-1, 0, 1)
     r = box.iterate(3)
     assert abs(r["energy"] - r_ref["energy"]) <= tol * abs(r_ref["energy"]), (r, r_ref)
     assert rel_err(to_host(box.view("dens", 0))[0], rho_ref) <= tol
@@ -58,3 +59,52 @@ def test_autotune_parity_and_cache(torch_mod, tmp_path, case, precision, tol):
     assert t2["from_cache"]
     assert {k: v for k, v in t2.items() if k != "from_cache"} == \
         {k: v for k, v in t.items() if k != "from_cache"}
+
+
+@pytest.mark.parametrize("case,precision", [("n24_13p7_rod", 0), ("n32_70p33_slab", 0),
+                                            ("n16_8p8", 1), ("n24_13p7_rod", 1)])
+@pytest.mark.parametrize("h_lines,damp_xy", [(-1, 1), (0, 0)])
+def test_slice_and_pencil_variants_match_oracle(torch_mod, tmp_path, case, precision,
+                                                h_lines, damp_xy):
+    """h psi, <h> and the damped step in both layouts (x and y on LDS z-slices,
+    or three line passes), forced through the tuning cache, against the
+    oracle (FP64 1e-11; complex64 inputs 2e-5 on h psi, 2e-6 on the step)."""
+    import torch
+    from oracle import Grid
+    from oracle import physics as ph
+    from oracle import solver as so
+    w = CASES[case]
+    raw = inputs.raw_states(w)
+    box = _box(w, precision)
+    box.init_box(to_dev(raw[0]), to_dev(raw[1]))
+    prec = "mixed" if precision else "fp64"
+    lines = h_lines if h_lines else {8: 64, 16: 64, 24: 32, 32: 32, 48: 32}[w.n]
+    cache = tmp_path / "force.json"
+    cache.write_text(json.dumps({f"h_lines/n{w.n}/{prec}": lines,
+                                 f"damp_xy/n{w.n}/{prec}": damp_xy}))
+    t = box.autotune(str(cache))
+    assert t["h_lines"] == lines and t["damp_xy"] == damp_xy
+    g = Grid(w.n, w.dx)
+    q = 0
+    m = w.n_neutrons
+    # inputs: the raw states rounded to the working precision, fields from them
+    cdt = torch.complex64 if precision else torch.complex128
+    for s in range(2):
+        box.view("psi", s).copy_(to_dev(raw[s]).to(cdt))
+    box.densities()
+    xs = [to_host(box.view("psi", s)).astype(np.complex128) for s in range(2)]
+    dens = [ph.densities(xs[0], g), ph.densities(xs[1], g)]
+    mf = ph.mean_field(dens[0], dens[1], g, w.params)[q]
+    psi, hpsi, phi = box.view("psi", q), box.view("hpsi", q), box.view("phi", q)
+    eps = torch.empty(m, dtype=torch.float64, device=psi.device)
+    box.apply_h(q, psi, hpsi, m, eps)
+    box.damped_step(q, psi, hpsi, eps, phi, m)
+    torch.cuda.synchronize()
+    x = xs[q]
+    h_ref = ph.apply_h(x, mf, g)
+    e_ref, r_ref, _ = so.rayleigh_and_residual(x, h_ref, g)
+    phi_ref = x - so.damping(r_ref, g, mf.hb2m, w.damp_x0, w.damp_e0)
+    th, tp = (2e-5, 2e-6) if precision else (1e-11, 1e-11)
+    assert rel_err(to_host(hpsi), h_ref) <= th
+    assert rel_err(to_host(eps), e_ref) <= th
+    assert rel_err(to_host(phi), phi_ref) <= tp
