@@ -260,7 +260,15 @@ k_absmax(const void* __restrict__ xv, size_t n, unsigned int* __restrict__ mx) {
 }
 
 // ------------------------------------------------------------------ split planes
-// Planes of an R x K complex64 matrix: P[p][r][k], row length K (K % 8 == 0).
+// Row pitch of the NT planes: K + NT_PAD elements.  A state's plane row is
+// K * 2 bytes long (442 368 at 48^3, a multiple of 2^14); unpadded, the same
+// k offset of consecutive rows falls into 1 of 16 L2 sets, so the 128 rows
+// of a tile thrash the L2 (measured: 12x the unique bytes fetched).  One
+// extra 128-byte line per row spreads them over every set.
+constexpr long NT_PAD = 64;
+
+// Planes of an R x K complex64 matrix: P[p][r][k], row pitch K + NT_PAD
+// (K % 8 == 0; the pad is never read).
 __global__ void __launch_bounds__(256)
 k_split_nt(const float2* __restrict__ x, int R, long K, const unsigned int* __restrict__ mx,
            unsigned short* __restrict__ P) {
@@ -275,9 +283,10 @@ k_split_nt(const float2* __restrict__ x, int R, long K, const unsigned int* __re
   for (int e = 0; e < 8; ++e) z[e] = x[size_t(r) * K + k0 + e];
   u4 w[NP];
   split8(z, S, w);
-  const size_t psz = size_t(R) * K;
+  const long ld = K + NT_PAD;
+  const size_t psz = size_t(R) * ld;
 #pragma unroll
-  for (int p = 0; p < NP; ++p) *reinterpret_cast<u4*>(P + p * psz + size_t(r) * K + k0) = w[p];
+  for (int p = 0; p < NP; ++p) *reinterpret_cast<u4*>(P + p * psz + size_t(r) * ld + k0) = w[p];
 }
 
 // Transposed planes: input R x C (complex64 or, with DOUBLE_IN, complex128
@@ -351,22 +360,23 @@ k_overlap_planes(const unsigned short* __restrict__ PA, const unsigned short* __
   const int wm = wave >> 1, wn = wave & 1;
   const long nst = k / KB;
   const long c0 = nst * s / split, c1 = nst * (s + 1) / split;
-  const size_t psz = size_t(m) * k;
+  const long ld = k + NT_PAD;
+  const size_t psz = size_t(m) * ld;
   Acc acc;
   zero(acc);
   int nacc = 0;
   Frag fa, fb;
   if (c0 < c1) {
-    gload(fa, PA, psz, k, ta * BT, m, c0 * KB, tid);
-    gload(fb, PB, psz, k, tb * BT, m, c0 * KB, tid);
+    gload(fa, PA, psz, ld, ta * BT, m, c0 * KB, tid);
+    gload(fb, PB, psz, ld, tb * BT, m, c0 * KB, tid);
   }
   for (long c = c0; c < c1; ++c) {
     sstore(sA, fa, tid);
     sstore(sB, fb, tid);
     __syncthreads();
     if (c + 1 < c1) {
-      gload(fa, PA, psz, k, ta * BT, m, (c + 1) * KB, tid);
-      gload(fb, PB, psz, k, tb * BT, m, (c + 1) * KB, tid);
+      gload(fa, PA, psz, ld, ta * BT, m, (c + 1) * KB, tid);
+      gload(fb, PB, psz, ld, tb * BT, m, (c + 1) * KB, tid);
     }
     step<true>(acc, sA, sB, wm, wn, lane);
     __syncthreads();
@@ -507,7 +517,7 @@ size_t overlap_scratch_bytes_mixed(int m, long k) {
 }
 
 long planes_pad(int m) { return (long(m) + KB - 1) / KB * KB; }
-size_t planes_bytes_nt(int rows, long k) { return size_t(NP) * rows * k * 2; }
+size_t planes_bytes_nt(int rows, long k) { return size_t(NP) * rows * (k + NT_PAD) * 2; }
 size_t planes_bytes_t(int m, long cols) { return size_t(NP) * cols * planes_pad(m) * 2; }
 
 void plane_scale(const void* x, int x_is_c128, size_t n, unsigned int* mx, hipStream_t st) {
