@@ -33,6 +33,33 @@ PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
 SPLIT_PRODUCTS = 3           # FP16 products per real product in the mixed GEMMs
 
 
+# HBM bytes per neutron launch of the roofline kernels on the 48^3 x 1600
+# neutron box, from rocprofv3 --pmc runs of this script (FETCH_SIZE, then
+# WRITE_SIZE, in KiB per dispatch), scaled by what the same counters read for
+# a 1 GiB device copy (FETCH_SIZE x2, WRITE_SIZE x1).  A figure is reported
+# only while the kernel's source file still has the hash it was measured on.
+MEASURED_TRAFFIC = {
+    "k_overlap_planes": dict(fetch_kib=15.365e6, write_kib=768768.0, fetch_scale=2.0,
+                             write_scale=1.0, source="paper_1610_07522_amd/csrc/k_gemm_mixed.hip",
+                             sha256_16="e9518d326c666700"),
+    "k_combine_planes": dict(fetch_kib=8.9816e6, write_kib=2764800.0, fetch_scale=2.0,
+                             write_scale=1.0, source="paper_1610_07522_amd/csrc/k_gemm_mixed.hip",
+                             sha256_16="e9518d326c666700"),
+}
+
+
+def measured_traffic(kernel: str):
+    """Bytes per launch from MEASURED_TRAFFIC, or None if not measured or stale."""
+    import hashlib
+    e = MEASURED_TRAFFIC.get(kernel)
+    if e is None:
+        return None
+    with open(os.path.join(ROOT, e["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != e["sha256_16"]:
+            return None
+    return 1024.0 * (e["fetch_kib"] * e["fetch_scale"] + e["write_kib"] * e["write_scale"])
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -63,9 +90,12 @@ def roofline(timing: dict, w, mixed: bool) -> dict:
         name = "k_overlap_planes" if dom == "overlap_gemm" else "k_combine_planes"
     else:
         name = "k_overlap_lower" if dom == "overlap_gemm" else "k_combine"
+    traffic = measured_traffic(name) if w.name == "rod48" else None
     return dict(kernel=name, bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s",
-                frac=ach / peak, traffic=None, dtype=("fp16x2-split" if mixed else "fp64"),
-                per_launch=dict(species="neutrons", m=m, k=v, flops=fl, avg_ms=avg_ms))
+                frac=ach / peak, traffic=traffic, traffic_unit="bytes per launch",
+                dtype=("fp16x2-split" if mixed else "fp64"),
+                per_launch=dict(species="neutrons", m=m, k=v, flops=fl, avg_ms=avg_ms,
+                                unique_bytes=2.0 * m * v * (8 if mixed else 16)))
 
 
 def h_phase_hbm(timing: dict, w, mixed: bool) -> dict:
