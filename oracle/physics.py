@@ -59,7 +59,7 @@ def densities(psi: np.ndarray, g: Grid) -> Densities:
     J = np.zeros((3,) + shape)
     s = np.zeros((3,) + shape)
     j = np.zeros((3,) + shape)
-    chunk = max(1, int(2 ** 25 // max(1, psi[0].size)))
+    chunk = max(1, int(2 ** 25 // max(1, int(np.prod(psi.shape[1:])))))
     for a0 in range(0, psi.shape[0], chunk):
         p = psi[a0:a0 + chunk]                       # [a][spin][z][y][x]
         rho += (np.abs(p) ** 2).sum(axis=(0, 1))

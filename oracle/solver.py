@@ -35,16 +35,21 @@ from .physics import (Densities, MeanField, apply_h, densities, energy,
                       mean_field)
 
 
+def _rows(x: np.ndarray) -> np.ndarray:
+    """[state][spinor components] view (also for an empty species)."""
+    return x.reshape(x.shape[0], int(np.prod(x.shape[1:])))
+
+
 def overlap(a: np.ndarray, b: np.ndarray, g: Grid) -> np.ndarray:
     """M[alpha, beta] = <a_alpha | b_beta> (Eqs. normmatrix/hammatrix)."""
-    af = a.reshape(a.shape[0], -1)
-    bf = b.reshape(b.shape[0], -1)
+    af = _rows(a)
+    bf = _rows(b)
     return g.dV * (af.conj() @ bf.T)
 
 
 def combine(phi: np.ndarray, U: np.ndarray) -> np.ndarray:
     """psi_beta = sum_alpha phi_alpha U[alpha, beta] (Sec. 3.3.3, step 3e)."""
-    pf = phi.reshape(phi.shape[0], -1)
+    pf = _rows(phi)
     return (U.T @ pf).reshape((U.shape[1],) + phi.shape[1:])
 
 
@@ -83,11 +88,11 @@ def damping(r: np.ndarray, g: Grid, hb2m: float, x0: float, e0: float
 
 def rayleigh_and_residual(psi: np.ndarray, hpsi: np.ndarray, g: Grid):
     """eps_a = Re <psi_a|h psi_a>, r_a = h psi_a - eps_a psi_a, ||r_a||^2."""
-    pf = psi.reshape(psi.shape[0], -1)
-    hf = hpsi.reshape(hpsi.shape[0], -1)
+    pf = _rows(psi)
+    hf = _rows(hpsi)
     eps = g.dV * np.einsum("av,av->a", pf.conj(), hf).real
     r = hpsi - eps[:, None, None, None, None] * psi
-    rf = r.reshape(r.shape[0], -1)
+    rf = _rows(r)
     r2 = g.dV * (np.abs(rf) ** 2).sum(axis=1)
     return eps, r, r2
 

@@ -230,6 +230,7 @@ __global__ void k_sum_splits(const double2* __restrict__ part, int split, size_t
 // CU (tile counts such as 625 = 25^2 otherwise leave a long last round);
 // herm: only the nt (nt + 1) / 2 lower tiles are live.
 int square_split(int m, int herm) {
+  if (m <= 0) return 1;   // empty species: nothing to split
   const int nt = (m + TM - 1) / TM;
   const int nk = (m + KC - 1) / KC;
   const int tiles = herm ? nt * (nt + 1) / 2 : nt * nt;
@@ -241,6 +242,7 @@ int square_split(int m, int herm) {
 }
 
 int overlap_split(int m, long k) {
+  if (m <= 0) return 1;
   const int nt = (m + TM - 1) / TM;
   const int npair = nt * (nt + 1) / 2;
   long nck = k / KC;

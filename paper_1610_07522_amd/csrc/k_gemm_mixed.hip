@@ -473,6 +473,7 @@ k_combine_planes(const unsigned short* __restrict__ PU, const unsigned short* __
 }
 
 int overlap_split_mixed(int m, long k) {
+  if (m <= 0) return 1;
   const int nt = (m + BT - 1) / BT;
   const int npair = nt * (nt + 1) / 2;
   const long nst = k / KB;

@@ -82,3 +82,16 @@ def test_workspace_holds_the_largest_workload(lib):
     states = 4 * 2000 * 2 * 48 ** 3 * 16
     assert states <= nb.value < states * 1.3
     assert nb.value < 288e9
+
+
+@pytest.mark.parametrize("nn,npp,prec", [(10, 0, 0), (0, 7, 0), (1, 1, 0), (10, 0, 1), (0, 7, 1)])
+def test_workspace_plan_with_empty_or_single_species(lib, nn, npp, prec):
+    """An empty species or a single state plans a workspace and creates a
+    context (the plan once divided by the tile count of an empty species)."""
+    d = _desc(n_neutrons=nn, n_protons=npp, precision=prec)
+    nb = ctypes.c_size_t()
+    assert lib.sky_workspace_size(ctypes.byref(d), ctypes.byref(nb)) == sky.SKY_OK
+    ctx = ctypes.c_void_p()
+    fake = 1 << 40   # never dereferenced: creation only records the pointer
+    assert lib.sky_create(ctypes.byref(d), fake, nb.value, None, ctypes.byref(ctx)) == sky.SKY_OK
+    lib.sky_destroy(ctx)
