@@ -532,6 +532,10 @@ void plane_scale(const void* x, int x_is_c128, size_t n, unsigned int* mx, hipSt
     hipLaunchKernelGGL(k_absmax<false>, dim3(unsigned(nb)), dim3(256), 0, st, x, n, mx);
 }
 
+void clear_scales(unsigned int* mx, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, st, mx, n);
+}
+
 void split_planes_nt(const void* x, int rows, long k, const unsigned int* mx, void* P,
                      hipStream_t st) {
   if (rows <= 0) return;

@@ -41,6 +41,22 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
+// Largest |component| (real or imaginary part, as float) of the values this
+// workgroup wrote, merged into *amax as float bits (non-negative floats
+// order like their bit patterns).  Any blockDim; every thread must call it.
+__device__ inline void block_amax(float v, unsigned int* amax) {
+  __shared__ unsigned int smax;
+  if (threadIdx.x == 0) smax = 0u;
+  __syncthreads();
+  atomicMax(&smax, __float_as_uint(v));
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(amax, smax);
+}
+
+template <typename T> __device__ inline float cabs_max(cpx<T> z) {
+  return fmaxf(fabsf(float(z.re)), fabsf(float(z.im)));
+}
+
 // ------------------------------------------------------------------ h * psi
 // One pass adds the DIR part of h:
 //   - D(B D psi) + (i/2) [A D psi + D(A psi)]  =  D g + (i/2) A D psi,
@@ -50,7 +66,7 @@ __device__ inline double block_sum(double v, double* red) {
 template <typename T, int N, int DIR, bool FIRST, bool LAST, int LP>
 __global__ void __launch_bounds__((LineCfg<N, LP>::THREADS))
 k_h_pass(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPtrs mf,
-         GridArgs g, double* __restrict__ eps_part) {
+         GridArgs g, double* __restrict__ eps_part, unsigned int* __restrict__ amax) {
   using C = LineCfg<N, LP>;
   using F = LineFFT<T, N, 2>;
   constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
@@ -109,6 +125,7 @@ k_h_pass(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPtr
   F::deriv(d, Y, j, tw, kunit);
 
   double dot = 0.0;
+  float am = 0.0f;
   if (j < R2) {
 #pragma unroll
     for (int j1 = 0; j1 < R1; ++j1) {
@@ -119,6 +136,7 @@ k_h_pass(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPtr
         if (!FIRST) t = t + hp[s * N3 + r];
         hp[s * N3 + r] = t;
         if (LAST) dot += double(v[s][j1].re) * double(t.re) + double(v[s][j1].im) * double(t.im);
+        if (LAST) am = fmaxf(am, cabs_max(t));
       }
     }
   }
@@ -126,6 +144,7 @@ k_h_pass(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPtr
     double sum = block_sum(dot, red);
     if (threadIdx.x == 0) eps_part[size_t(blockIdx.y) * gridDim.x + blockIdx.x] = sum * g.dV;
   }
+  if (LAST && amax != nullptr) block_amax(am, amax);
 }
 
 // Sum the per-workgroup partials of each state: out[s] = sum_t part[s][t].
@@ -223,7 +242,7 @@ __device__ inline void h_dir_line(const cpx<T> (&v)[2][Fact<N>::R1], cpx<T> (&ou
 template <typename T, int N>
 __global__ void __launch_bounds__(PlaneCfg<N>::THREADS)
 k_h_plane(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPtrs mf, GridArgs g,
-          double* __restrict__ eps_part) {
+          double* __restrict__ eps_part, unsigned int* __restrict__ amax) {
   using C = PlaneCfg<N>;
   using F = LineFFT<T, N, 2>;
   constexpr int R1 = C::R1, R2 = C::R2, RT = C::RT, PITCH = C::PITCH, SP = C::SPIN;
@@ -280,6 +299,7 @@ k_h_plane(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPt
   __syncthreads();
   h_dir_line<T, N, 1>(vy, ay, ry, Ybuf + lx * F::YSIZE, jy, tw, kunit, mf);
   double dot = 0.0;
+  float am = 0.0f;
   if (jy < R2) {
 #pragma unroll
     for (int j1 = 0; j1 < R1; ++j1) {
@@ -289,6 +309,7 @@ k_h_plane(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPt
         const cpx<T> t = ay[s][j1] + P[s * SP + y * PITCH + lx] + hp[s * N3 + ry[j1]];
         hp[s * N3 + ry[j1]] = t;
         dot += double(vy[s][j1].re) * double(t.re) + double(vy[s][j1].im) * double(t.im);
+        am = fmaxf(am, cabs_max(t));
       }
     }
   }
@@ -297,6 +318,7 @@ k_h_plane(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPt
     const double sum = tree_sum(dot, reinterpret_cast<double*>(P));
     if (threadIdx.x == 0) eps_part[size_t(blockIdx.y) * gridDim.x + blockIdx.x] = sum * g.dV;
   }
+  if (amax != nullptr) block_amax(am, amax);
 }
 
 // Damped step, first half: r = h psi - eps psi on slice z of state
@@ -371,7 +393,8 @@ k_damp_fwd_xy(const cpx<T>* __restrict__ psi, const cpx<T>* __restrict__ hpsi,
 // filtered spectrum in buf, then phi = psi - result, in place.
 template <typename T, int N>
 __global__ void __launch_bounds__(PlaneCfg<N>::THREADS)
-k_damp_inv_xy(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ buf) {
+k_damp_inv_xy(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ buf,
+              unsigned int* __restrict__ amax) {
   using C = PlaneCfg<N>;
   using F = LineFFT<T, N, 2>;
   constexpr int R1 = C::R1, R2 = C::R2, RT = C::RT, PITCH = C::PITCH, SP = C::SPIN;
@@ -419,11 +442,15 @@ k_damp_inv_xy(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ buf) {
         for (int s = 0; s < 2; ++s) P[s * SP + ly * PITCH + j + R2 * j1] = va[s][j1];
   }
   __syncthreads();
+  float am = 0.0f;
   for (int i = threadIdx.x; i < 2 * N2; i += C::THREADS) {
     const int s = i / N2, q = i - s * N2;
     const size_t o = soff + s * N3 + zoff + q;
-    buf[o] = psi[o] - P[s * SP + (q / N) * PITCH + q % N];
+    const cpx<T> t = psi[o] - P[s * SP + (q / N) * PITCH + q % N];
+    buf[o] = t;
+    am = fmaxf(am, cabs_max(t));
   }
+  if (amax != nullptr) block_amax(am, amax);
 }
 
 // ------------------------------------------------------------------ damping
@@ -617,7 +644,8 @@ k_damp_z(cpx<T>* __restrict__ buf, GridArgs g, DampArgs d, const float* __restri
 // inverse FFT along x and phi = psi - (damped residual), in place in buf.
 template <typename T, int N>
 __global__ void __launch_bounds__(LineCfg<N>::THREADS)
-k_damp_inv_x(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ buf) {
+k_damp_inv_x(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ buf,
+             unsigned int* __restrict__ amax) {
   using C = LineCfg<N>;
   using F = LineFFT<T, N, 2>;
   constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
@@ -638,14 +666,18 @@ k_damp_inv_x(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ buf) {
 #pragma unroll
       for (int s = 0; s < 2; ++s) vb[s][k2] = buf[soff + s * N3 + base + (j + R1 * k2) * stride];
   F::inverse(vb, va, Y, j, tw);
+  float am = 0.0f;
   if (j < R2)
 #pragma unroll
     for (int j1 = 0; j1 < R1; ++j1)
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         size_t r = soff + s * N3 + base + (j + R2 * j1) * stride;
-        buf[r] = psi[r] - va[s][j1];
+        const cpx<T> t = psi[r] - va[s][j1];
+        buf[r] = t;
+        am = fmaxf(am, cabs_max(t));
       }
+  if (amax != nullptr) block_amax(am, amax);
 }
 
 // ------------------------------------------------------------------ densities
@@ -803,26 +835,29 @@ template <int N> static constexpr bool lines_ok(int lp, int bytes_per_cpx) {
 
 template <typename T, int N, int LP>
 static void launch_h_lp(const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf, GridArgs g,
-                        double* eps_part, hipStream_t st) {
+                        double* eps_part, unsigned int* amax, hipStream_t st) {
   dim3 grid(N * N / LineCfg<N, LP>::LPW, nstate), block(LineCfg<N, LP>::THREADS);
   auto p = reinterpret_cast<const cpx<T>*>(psi);
   auto h = reinterpret_cast<cpx<T>*>(hpsi);
-  hipLaunchKernelGGL((k_h_pass<T, N, 0, true, false, LP>), grid, block, 0, st, p, h, mf, g, nullptr);
-  hipLaunchKernelGGL((k_h_pass<T, N, 1, false, false, LP>), grid, block, 0, st, p, h, mf, g, nullptr);
-  hipLaunchKernelGGL((k_h_pass<T, N, 2, false, true, LP>), grid, block, 0, st, p, h, mf, g, eps_part);
+  hipLaunchKernelGGL((k_h_pass<T, N, 0, true, false, LP>), grid, block, 0, st, p, h, mf, g, nullptr,
+                     nullptr);
+  hipLaunchKernelGGL((k_h_pass<T, N, 1, false, false, LP>), grid, block, 0, st, p, h, mf, g, nullptr,
+                     nullptr);
+  hipLaunchKernelGGL((k_h_pass<T, N, 2, false, true, LP>), grid, block, 0, st, p, h, mf, g, eps_part,
+                     amax);
 }
 
 // z pass (with U psi) by line pencils, then the x and y parts on LDS slices.
 template <typename T, int N>
 static void launch_h_plane(const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf, GridArgs g,
-                           double* eps_part, hipStream_t st) {
+                           double* eps_part, unsigned int* amax, hipStream_t st) {
   constexpr int D = LineCfg<N>::LPW;
   auto p = reinterpret_cast<const cpx<T>*>(psi);
   auto h = reinterpret_cast<cpx<T>*>(hpsi);
   hipLaunchKernelGGL((k_h_pass<T, N, 2, true, false, D>), dim3(N * N / D, nstate),
-                     dim3(LineCfg<N>::THREADS), 0, st, p, h, mf, g, nullptr);
+                     dim3(LineCfg<N>::THREADS), 0, st, p, h, mf, g, nullptr, nullptr);
   hipLaunchKernelGGL((k_h_plane<T, N>), dim3(N, nstate), dim3(PlaneCfg<N>::THREADS), 0, st, p, h,
-                     mf, g, eps_part);
+                     mf, g, eps_part, amax);
 }
 
 // lines: 0 = default, H_PLANE = x and y on LDS slices, else pencils per
@@ -830,7 +865,7 @@ static void launch_h_plane(const void* psi, void* hpsi, int nstate, MeanFieldPtr
 // eps partials (workgroups) per state, or 0 if lines is not supported.
 template <typename T, int N>
 static int launch_apply_h(const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf, GridArgs g,
-                          double* eps_part, int lines, hipStream_t st) {
+                          double* eps_part, int lines, unsigned int* amax, hipStream_t st) {
   constexpr int D = LineCfg<N>::LPW;
   constexpr int H = (D / 2 > 0 && lines_ok<N>(D / 2, sizeof(cpx<T>))) ? D / 2 : D;
   constexpr int W = lines_ok<N>(2 * D, sizeof(cpx<T>)) ? 2 * D : D;
@@ -838,14 +873,14 @@ static int launch_apply_h(const void* psi, void* hpsi, int nstate, MeanFieldPtrs
   if (lines == 0) lines = plane_default<T, N>() ? H_PLANE : D;
   if (lines == H_PLANE) {
     if constexpr (PL) {
-      launch_h_plane<T, N>(psi, hpsi, nstate, mf, g, eps_part, st);
+      launch_h_plane<T, N>(psi, hpsi, nstate, mf, g, eps_part, amax, st);
       return N;
     }
     return 0;
   }
-  if (lines == D) { launch_h_lp<T, N, D>(psi, hpsi, nstate, mf, g, eps_part, st); return N * N / D; }
-  if (lines == H) { launch_h_lp<T, N, H>(psi, hpsi, nstate, mf, g, eps_part, st); return N * N / H; }
-  if (lines == W) { launch_h_lp<T, N, W>(psi, hpsi, nstate, mf, g, eps_part, st); return N * N / W; }
+  if (lines == D) { launch_h_lp<T, N, D>(psi, hpsi, nstate, mf, g, eps_part, amax, st); return N * N / D; }
+  if (lines == H) { launch_h_lp<T, N, H>(psi, hpsi, nstate, mf, g, eps_part, amax, st); return N * N / H; }
+  if (lines == W) { launch_h_lp<T, N, W>(psi, hpsi, nstate, mf, g, eps_part, amax, st); return N * N / W; }
   return 0;
 }
 
@@ -890,11 +925,12 @@ int h_pass_default(int n, int prec) {
 }
 
 int apply_h(int n, int prec, const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf,
-            GridArgs g, double* eps_part, double* eps, hipStream_t st, int lines) {
+            GridArgs g, double* eps_part, double* eps, hipStream_t st, int lines,
+            unsigned int* amax) {
   if (nstate <= 0) return 1;
   int nt = 0;
-  if (prec == 0) SKY_DISPATCH_N(n, nt = (launch_apply_h<double, NN>(psi, hpsi, nstate, mf, g, eps_part, lines, st)))
-  else SKY_DISPATCH_N(n, nt = (launch_apply_h<float, NN>(psi, hpsi, nstate, mf, g, eps_part, lines, st)))
+  if (prec == 0) SKY_DISPATCH_N(n, nt = (launch_apply_h<double, NN>(psi, hpsi, nstate, mf, g, eps_part, lines, amax, st)))
+  else SKY_DISPATCH_N(n, nt = (launch_apply_h<float, NN>(psi, hpsi, nstate, mf, g, eps_part, lines, amax, st)))
   if (nt == 0) return 0;
   if (eps_part && eps)
     hipLaunchKernelGGL(k_sum_partials, dim3((nstate + 127) / 128), dim3(128), 0, st,
@@ -908,7 +944,7 @@ int apply_h(int n, int prec, const void* psi, void* hpsi, int nstate, MeanFieldP
 template <typename T, int N>
 static void launch_damp(const void* psi, const void* hpsi, const double* eps, void* phi,
                         int nstate, GridArgs g, DampArgs d, double* r2_part, const float* gain,
-                        double* shell_pow, int stage, int xy, hipStream_t st) {
+                        double* shell_pow, int stage, int xy, unsigned int* amax, hipStream_t st) {
   dim3 grid(ntiles<N>(), nstate), block(LineCfg<N>::THREADS);
   dim3 pgrid(N, nstate), pblock(PlaneCfg<N>::THREADS);
   auto p = reinterpret_cast<const cpx<T>*>(psi);
@@ -933,21 +969,21 @@ static void launch_damp(const void* psi, const void* hpsi, const double* eps, vo
     hipLaunchKernelGGL((k_damp_z<T, N, 0>), grid, block, 0, st, o, g, d, nullptr, nullptr);
   if (pl) {
     if constexpr (plane_fits<T, N>())
-      hipLaunchKernelGGL((k_damp_inv_xy<T, N>), pgrid, pblock, 0, st, p, o);
+      hipLaunchKernelGGL((k_damp_inv_xy<T, N>), pgrid, pblock, 0, st, p, o, amax);
   } else {
     hipLaunchKernelGGL((k_damp_y<T, N, true>), grid, block, 0, st, o);
-    hipLaunchKernelGGL((k_damp_inv_x<T, N>), grid, block, 0, st, p, o);
+    hipLaunchKernelGGL((k_damp_inv_x<T, N>), grid, block, 0, st, p, o, amax);
   }
 }
 
 void damped_step(int n, int prec, const void* psi, const void* hpsi, const double* eps,
                  void* phi, int nstate, GridArgs g, double x0, double e0, double hb2m,
                  double* r2_part, double* r2, hipStream_t st, const float* gain,
-                 double* shell_pow, int stage, int xy) {
+                 double* shell_pow, int stage, int xy, unsigned int* amax) {
   if (nstate <= 0) return;
   DampArgs d{x0, e0, hb2m};
-  if (prec == 0) SKY_DISPATCH_N(n, launch_damp<double, NN>(psi, hpsi, eps, phi, nstate, g, d, r2_part, gain, shell_pow, stage, xy, st))
-  else SKY_DISPATCH_N(n, launch_damp<float, NN>(psi, hpsi, eps, phi, nstate, g, d, r2_part, gain, shell_pow, stage, xy, st))
+  if (prec == 0) SKY_DISPATCH_N(n, launch_damp<double, NN>(psi, hpsi, eps, phi, nstate, g, d, r2_part, gain, shell_pow, stage, xy, amax, st))
+  else SKY_DISPATCH_N(n, launch_damp<float, NN>(psi, hpsi, eps, phi, nstate, g, d, r2_part, gain, shell_pow, stage, xy, amax, st))
   if (stage == 2) return;
   int nt = 0;
   if (prec == 0)

@@ -300,7 +300,8 @@ int check_info(sky_ctx* c, const char* what) {
 
 // Step 3a of species q: I and H (lower triangles by the GEMMs, then
 // mirrored).  Launches only, so that it can be captured in a graph.
-void subspace_matrices(sky_ctx* c, int q, const void* phi, const void* hphi) {
+void subspace_matrices(sky_ctx* c, int q, const void* phi, const void* hphi,
+                       bool scales_ready = false) {
   const int m = c->nq[q];
   hipStream_t st = c->st;
   void* I = c->at(c->lay.matI);
@@ -309,8 +310,10 @@ void subspace_matrices(sky_ctx* c, int q, const void* phi, const void* hphi) {
   if (c->prec) {
     const int tp = t_begin(c, SKY_PHASE_SPLIT, q);
     const size_t ne = size_t(m) * c->V;
-    plane_scale(phi, 0, ne, mx, st);
-    plane_scale(hphi, 0, ne, mx + 1, st);
+    if (!scales_ready) {   // else the producers of phi and h phi merged them
+      plane_scale(phi, 0, ne, mx, st);
+      plane_scale(hphi, 0, ne, mx + 1, st);
+    }
     split_planes_nt(phi, m, c->V, mx, c->at(c->lay.plA), st);
     split_planes_nt(hphi, m, c->V, mx + 1, c->at(c->lay.plB), st);
     split_planes_t(phi, 0, m, c->V, mx, c->at(c->lay.plT), st);
@@ -472,7 +475,7 @@ double kmax_of(const sky_ctx* c) { return std::sqrt(3.0) * (c->n / 2) * c->g.kun
 // Damped step with the learned per-shell gains: forward passes and shell
 // powers, MLP inference of the gains, then the gained filter and inverses.
 void learned_damp(sky_ctx* c, int q, const void* psi, const void* hpsi, const double* eps,
-                  void* phi, int m, double* r2, hipStream_t st) {
+                  void* phi, int m, double* r2, hipStream_t st, unsigned int* amax = nullptr) {
   const double hb = q ? c->d.hb2m_p : c->d.hb2m_n;
   double* pw = c->at<double>(c->lay.pc_pow);
   zero(pw, size_t(m) * PC_SHELLS, st);
@@ -484,7 +487,8 @@ void learned_damp(sky_ctx* c, int q, const void* psi, const void* hpsi, const do
                   c->at<float>(c->lay.pc_O), st);
   precond_gains(c->at<float>(c->lay.pc_O), m * PC_SHELLS, c->at<float>(c->lay.pc_gain), st);
   damped_step(c->n, c->prec, psi, hpsi, eps, phi, m, c->g, c->d.damp_x0, c->d.damp_e0, hb,
-              nullptr, nullptr, st, c->at<float>(c->lay.pc_gain), nullptr, 2, c->tune.damp_xy);
+              nullptr, nullptr, st, c->at<float>(c->lay.pc_gain), nullptr, 2, c->tune.damp_xy,
+              amax);
 }
 
 // Training rows from the current states of species q: the shell powers and
@@ -577,21 +581,26 @@ void step_a(sky_ctx* c, int q, bool learned) {
   void* hphi = c->hphi(q);
   double* eps = c->at<double>(c->lay.eps[q]);
   double* tiles = c->at<double>(c->lay.tiles);
+  // mixed: the largest |component| of phi and h phi (split-plane scales) is
+  // merged by the kernels that write them
+  unsigned int* mx = c->prec ? c->at<unsigned int>(c->lay.plS) : nullptr;
+  if (mx) clear_scales(mx, 2, st);
   int t0 = t_begin(c, SKY_PHASE_APPLY_H, q);
   apply_h(c->n, c->prec, psi, hpsi, m, c->mfp(q), c->g, tiles, eps, st, c->tune.lines);
   t_end(c, t0);
   const double hb = q ? c->d.hb2m_p : c->d.hb2m_n;
   int t1 = t_begin(c, SKY_PHASE_DAMP, q);
   if (learned)
-    learned_damp(c, q, psi, hpsi, eps, phi, m, c->at<double>(c->lay.r2[q]), st);
+    learned_damp(c, q, psi, hpsi, eps, phi, m, c->at<double>(c->lay.r2[q]), st, mx);
   else
     damped_step(c->n, c->prec, psi, hpsi, eps, phi, m, c->g, c->d.damp_x0, c->d.damp_e0, hb,
-                tiles, c->at<double>(c->lay.r2[q]), st, nullptr, nullptr, 0, c->tune.damp_xy);
+                tiles, c->at<double>(c->lay.r2[q]), st, nullptr, nullptr, 0, c->tune.damp_xy, mx);
   t_end(c, t1);
   int t2 = t_begin(c, SKY_PHASE_APPLY_H, q);
-  apply_h(c->n, c->prec, phi, hphi, m, c->mfp(q), c->g, nullptr, nullptr, st, c->tune.lines);
+  apply_h(c->n, c->prec, phi, hphi, m, c->mfp(q), c->g, nullptr, nullptr, st, c->tune.lines,
+          mx ? mx + 1 : nullptr);
   t_end(c, t2);
-  subspace_matrices(c, q, phi, hphi);
+  subspace_matrices(c, q, phi, hphi, mx != nullptr);
 }
 
 void graphs_clear(sky_ctx* c) {

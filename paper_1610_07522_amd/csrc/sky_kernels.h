@@ -15,20 +15,25 @@ int grid_ntiles(int n);  // room for the per-state partials of one pass
 constexpr int H_PLANE = -1;
 int h_pass_lines(int n, int prec, int* out);
 int h_pass_default(int n, int prec);
+// amax (optional): the largest |component| of h psi is merged into it (float
+// bits; clear it first), as plane_scale would compute it.
 int apply_h(int n, int prec, const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf,
-            GridArgs g, double* eps_part, double* eps, hipStream_t st, int lines = 0);
+            GridArgs g, double* eps_part, double* eps, hipStream_t st, int lines = 0,
+            unsigned int* amax = nullptr);
 // gain (optional, [state][PC_SHELLS]): multiplies the damping per |k| shell.
 // shell_pow (optional, [state][PC_SHELLS], accumulated: clear first): the
 // residual's spectral power per shell, from an extra read-only pass.
 // xy: 1 = x and y transforms on LDS z-slices where they fit, 0 = line
-// passes, -1 = the default for the grid and precision.
+// passes, -1 = the default for the grid and precision.  amax (optional):
+// the largest |component| of phi is merged into it (stages 0 and 2).
 // stage 0: whole step; 1: up to the shell powers (partial spectrum left in
 // phi, r2 formed); 2: the rest, continuing from stage 1 (gains decided in
 // between).
 void damped_step(int n, int prec, const void* psi, const void* hpsi, const double* eps,
                  void* phi, int nstate, GridArgs g, double x0, double e0, double hb2m,
                  double* r2_part, double* r2, hipStream_t st, const float* gain = nullptr,
-                 double* shell_pow = nullptr, int stage = 0, int xy = -1);
+                 double* shell_pow = nullptr, int stage = 0, int xy = -1,
+                 unsigned int* amax = nullptr);
 
 // ---- learned preconditioner (k_precond.hip)
 int precond_nparams();
@@ -106,6 +111,8 @@ long planes_pad(int m);
 size_t planes_bytes_nt(int rows, long k);
 size_t planes_bytes_t(int m, long cols);
 void plane_scale(const void* x, int x_is_c128, size_t n, unsigned int* mx, hipStream_t st);
+// Zero n largest-|component| slots (before producers merge into them).
+void clear_scales(unsigned int* mx, int n, hipStream_t st);
 void split_planes_nt(const void* x, int rows, long k, const unsigned int* mx, void* P,
                      hipStream_t st);
 void split_planes_t(const void* x, int x_is_c128, int rows, long cols, const unsigned int* mx,
