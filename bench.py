@@ -259,7 +259,8 @@ def bench_to_residual(args) -> int:
     results = {}
     for mode in args.modes.split(","):
         prec = sky.SKY_FP64 if mode == "fp64" else sky.SKY_MIXED
-        box = sky.Box(sky.desc_from_workload(w, precision=prec), device=dev)
+        ladder = args.ladder if prec == sky.SKY_MIXED else 0.0
+        box = sky.Box(sky.desc_from_workload(w, precision=prec, ladder_tol=ladder), device=dev)
         box.init_box(dn, dp)
         if args.tune_cache != "off":
             box.autotune(args.tune_cache)
@@ -294,19 +295,34 @@ def bench_to_residual(args) -> int:
                 break
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
+        ritz = [box.view("ritz", q).cpu().tolist() for q in range(2)]
         results[mode] = dict(iterations=its, seconds=sec,
                              converged=bool(rep["converged"] and rep["residual"] <= tol),
                              residual=rep["residual"], energy=rep["energy"],
-                             learned_iterations=pc_its, trajectory=traj)
+                             precision_at_end="fp64" if rep["precision"] == 0 else "mixed",
+                             learned_iterations=pc_its, trajectory=traj, ritz=ritz)
         box.close()
         del box
         torch.cuda.empty_cache()
     out = dict(metric=f"time to residual {tol:g}", workload=w.name, tol=tol,
-               min_iter=args.min_iter, max_iter=args.max_iter, results=results)
+               min_iter=args.min_iter, max_iter=args.max_iter, ladder=args.ladder,
+               results=results)
     if "mixed" in results and "fp64" in results:
         out["fp64_over_mixed_time"] = results["fp64"]["seconds"] / results["mixed"]["seconds"]
     if "mixed" in results and "learned" in results:
         out["plain_over_learned_time"] = results["mixed"]["seconds"] / results["learned"]["seconds"]
+    if "fp64" in results:
+        import numpy as np
+        ref = results["fp64"]
+        for k, v in results.items():
+            if k == "fp64":
+                continue
+            v["energy_rel_diff_vs_fp64"] = abs(v["energy"] - ref["energy"]) / abs(ref["energy"])
+            v["max_sp_energy_diff_vs_fp64_MeV"] = max(
+                float(np.max(np.abs(np.sort(a) - np.sort(b)))) if len(a) else 0.0
+                for a, b in zip(v["ritz"], ref["ritz"]))
+    for v in results.values():
+        v.pop("ritz")
     print(json.dumps(out), flush=True)
     return 0
 
@@ -332,6 +348,8 @@ def main() -> int:
     ap.add_argument("--max-iter", type=int, default=4000)
     ap.add_argument("--min-iter", type=int, default=0,
                     help="--to-residual: the tolerance is tested from this iteration on")
+    ap.add_argument("--ladder", type=float, default=0.0,
+                    help="--to-residual: mixed forms switch to FP64 at this Delta-eps (0: never)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three 1 GiB device-to-device copies (HBM counter scale)")
     args = ap.parse_args()

@@ -45,6 +45,9 @@ constexpr int JACOBI_SWEEPS = 30;
 constexpr int REFINE_ITERS = 10;     // refinement steps before the Jacobi fallback
 // ||I - 1||_F up to which I^-1/2 comes from its binomial series (<= 8 terms)
 constexpr double LOEWDIN_SERIES_MAX = 1e-2;
+// relative precision of H' built from the split-FP16 overlap and Hamiltonian
+// matrices (their representation error is 2^-22 of the largest entries; x8)
+constexpr double MIXED_HP_NOISE = 0x1p-19;
 
 // Byte offsets of every buffer inside the caller's workspace.
 struct Layout {
@@ -372,7 +375,8 @@ int subspace_solve(sky_ctx* c, int q, double* ritz) {
   int rc = check_info(c, "cholesky");
   if (rc) return rc;
   double* w = ritz ? ritz : c->at<double>(c->lay.ritz[q]);
-  int its = refine_eigh(Hp, m, w, Z, c->at(c->lay.ref_work), JACOBI_TOL, REFINE_ITERS, st, sqs);
+  int its = refine_eigh(Hp, m, w, Z, c->at(c->lay.ref_work), JACOBI_TOL, REFINE_ITERS, st, sqs,
+                        c->prec ? MIXED_HP_NOISE : 0x1p-49);
   if (its < 0) {   // a wide cluster or no convergence: blocked Jacobi from H'
     ++c->fallbacks;
     its = jacobi_eigh(Hp, m, w, Z, c->at(c->lay.jac_work), JACOBI_TOL, JACOBI_SWEEPS, st);
@@ -915,6 +919,10 @@ int sky_iterate(sky_ctx* c, int32_t max_iter, double tol, sky_report* rep) {
         convert_states(c->at(c->lay.psi32[q]), 1, c->at(c->lay.psi[q]), 0,
                        size_t(c->nq[q]) * c->V, st);
       c->prec = 0;
+      // launch shapes were tuned for the mixed kernels: FP64 defaults from here
+      c->tune.lines = 0;
+      c->tune.damp_xy = -1;
+      c->tune.ovl[0] = c->tune.ovl[1] = 0;
       fields(c);
       c->switched_at = c->iter_count + it + 1;
     }

@@ -152,10 +152,13 @@ void gemm_square(const void* A, int opA, const void* B, int opB, void* C, int m,
 // cannot finish (a cluster wider than its limit, a non-finite value, or more
 // than maxit steps); the caller then uses jacobi_eigh.  Converged when the
 // relative off-diagonal Frobenius norm of Z^H A Z is below tol and
-// max |Z^H Z - 1| below 1e-13.  Synchronises the stream once per step.
+// max |Z^H Z - 1| below 1e-13.  noise: the relative precision of A's entries
+// (x its rms eigenvalue = the coupling floor below which entries are noise:
+// no clusters, no rotation, counted as converged); 8 ulps for A from FP64
+// products.  Synchronises the stream once per step.
 size_t refine_scratch_bytes(int m);
 int refine_eigh(const void* A, int m, double* w, void* Z, void* work, double tol, int maxit,
-                hipStream_t st, int sq_split = 0);
+                hipStream_t st, int sq_split = 0, double noise = 0x1p-49);
 
 // ---- dense FP64 linear algebra (k_linalg.hip)
 // Cholesky A = L L^H of Hermitian positive definite A (m x m, lower used),

@@ -73,6 +73,12 @@ WORKLOADS: Dict[str, Workload] = {
     "slab32": Workload("slab32", 32, 1.0, 640, 160, "slab", seed=1),
     # 48 fm pasta box, 1600 n + 400 p, rod perturbation (cylinders along z).
     "rod48": Workload("rod48", 48, 1.0, 1600, 400, "rod", seed=2),
+    # Saturation-density boxes (closed plane-wave shells, weak slab, small
+    # noise): uniform matter there is stable, so the iteration converges to
+    # Delta-eps 1e-9 in a few hundred iterations.  24 fm, 1030 n + 1030 p
+    # (shells |n|^2 <= 25), 0.149 fm^-3; 8 fm, 38 n + 38 p, 0.148 fm^-3.
+    "sat24": Workload("sat24", 24, 1.0, 1030, 1030, "slab", seed=4, amp=0.1, noise=0.02),
+    "sat8": Workload("sat8", 8, 1.0, 38, 38, "slab", seed=22, amp=0.1, noise=0.02),
 }
 
 
