@@ -368,7 +368,7 @@ k_ref_update(const double2* __restrict__ S, const double2* __restrict__ R, int m
       const double2 gb = cadd(s2, cscale(lam2[b], r2)), ga = cadd(s2, cscale(lam2[a], r2));
       const double den = lam2[b] - lam2[a];
       if (fmax(hypot(gb.x, gb.y), hypot(ga.x, ga.y)) <= tau) {
-        e = cscale(0.5, r2);   // coupling at the rounding floor: orthonormality only
+        e = cscale(0.5, r2);   // coupling at the noise floor: orthonormality only
       } else if (den != 0.0) {
         e = cscale(1.0 / den, gb);
         const double em = hypot(e.x, e.y);
@@ -432,7 +432,7 @@ k_ref_check(double2* __restrict__ S, double2* __restrict__ R, int m, double tau,
       const double2 sv = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
       S[e] = sv;
       S[et] = make_double2(sv.x, -sv.y);
-      // couplings at the noise floor of H' count as converged
+      // couplings at the noise floor of H' count as converged (not rotated)
       const double s2 = sv.x * sv.x + sv.y * sv.y;
       if (s2 > tau * tau) off += 2.0 * s2;
       const double2 ga = R[e], gb = R[et];
@@ -560,7 +560,9 @@ int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double to
   // are indistinguishable from the rounding of the products that formed H'
   // (8 ulps in FP64; the split-FP16 subspace matrices carry ~2^-22 of their
   // largest entries): they form no clusters, get only the orthonormality
-  // term and count as converged
+  // term and count as converged.  The residual of the outer iteration then
+  // levels off near tau times the square root of the couplings per state,
+  // which is where the precision ladder hands over to FP64.
   double tau = 0.0;
   {
     double d2 = 0.0;

@@ -46,8 +46,8 @@ constexpr int REFINE_ITERS = 10;     // refinement steps before the Jacobi fallb
 // ||I - 1||_F up to which I^-1/2 comes from its binomial series (<= 8 terms)
 constexpr double LOEWDIN_SERIES_MAX = 1e-2;
 // relative precision of H' built from the split-FP16 overlap and Hamiltonian
-// matrices (their representation error is 2^-22 of the largest entries; x8)
-constexpr double MIXED_HP_NOISE = 0x1p-19;
+// matrices (their representation error is 2^-22 of the largest entries; x2)
+constexpr double MIXED_HP_NOISE = 0x1p-21;
 
 // Byte offsets of every buffer inside the caller's workspace.
 struct Layout {
