@@ -177,3 +177,45 @@ def test_mixed_overlap_fullsize(torch_mod):
         err = (I_gpu[r] - ref).abs().max().item() / ref.abs().max().item()
         worst = max(worst, err)
     assert worst <= 1e-6, worst
+
+
+@pytest.mark.parametrize("ladder", [1e-4, 0.0])
+def test_mixed_matches_oracle_at_convergence(torch_mod, ladder):
+    """A saturation-density box (8^3, 38 n + 38 p) that converges: the mixed
+    form (with the precision ladder, to Delta-eps 1e-9; without it, 600
+    iterations, where its residual has levelled off) against the FP64 oracle
+    converged to Delta-eps 1e-9: total energy within 1e-6 relative, every
+    single-particle energy within 1e-5 MeV."""
+    w = inputs.WORKLOADS["sat8"]
+    raw = inputs.raw_states(w)
+    box = _box(w, ladder_tol=ladder)
+    box.init_box(to_dev(raw[0]), to_dev(raw[1]))
+    rep = box.iterate(3000, 1e-9) if ladder > 0 else box.iterate(600)
+    if ladder > 0:
+        assert rep["converged"] and rep["precision"] == 0
+    else:
+        assert rep["precision"] == 1 and rep["residual"] < 1e-3
+    e_ref, ritz_ref = _sat8_converged()
+    assert abs(rep["energy"] - e_ref) <= 1e-6 * abs(e_ref), (rep, e_ref)
+    for q in range(2):
+        got = np.sort(to_host(box.view("ritz", q)))
+        want = np.sort(ritz_ref[q])
+        assert np.abs(got - want).max() <= 1e-5, (q, np.abs(got - want).max())
+
+
+_SAT8 = {}
+
+
+def _sat8_converged():
+    """FP64 oracle on the saturation box, iterated to Delta-eps 1e-9 (once)."""
+    if not _SAT8:
+        w = inputs.WORKLOADS["sat8"]
+        raw = inputs.raw_states(w)
+        st = so.initial_state(*raw, Grid(w.n, w.dx), w.params, w.damp_x0, w.damp_e0)
+        for _ in range(3000):
+            ro = so.iterate(st)
+            if ro.de <= 1e-9:
+                break
+        assert ro.de <= 1e-9
+        _SAT8["E"], _SAT8["ritz"] = st.E["total"], ro.ritz
+    return _SAT8["E"], _SAT8["ritz"]
