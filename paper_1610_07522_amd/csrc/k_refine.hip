@@ -75,8 +75,10 @@ __global__ void k_ref_rank(const double* __restrict__ lam, int m, int* __restric
 // reach[rank[i]] = largest sorted position strongly coupled to i (or its own).
 __global__ void __launch_bounds__(256)
 k_ref_reach(const double2* __restrict__ S, const double2* __restrict__ R, const double* __restrict__ lam,
-            const int* __restrict__ rank, int m, double theta, double tau, int* __restrict__ reach) {
+            const int* __restrict__ rank, int m, double theta, const double* __restrict__ taup,
+            int* __restrict__ reach) {
   const int i = blockIdx.x;
+  const double tau = *taup;
   const double li = lam[i];
   const int ri = rank[i];
   int best = ri;
@@ -350,8 +352,9 @@ __global__ void k_ref_lambda2(const double2* __restrict__ S, const double2* __re
 // rotate the pair at random by up to THETA on every step.)
 __global__ void __launch_bounds__(256)
 k_ref_update(const double2* __restrict__ S, const double2* __restrict__ R, int m, Clusters cl,
-             const double* __restrict__ lam2, double tau, double2* __restrict__ E,
-             unsigned long long* __restrict__ emax) {
+             const double* __restrict__ lam2, const double* __restrict__ taup,
+             double2* __restrict__ E, unsigned long long* __restrict__ emax) {
+  const double tau = *taup;
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   const int a = blockIdx.y;
   double mag = 0.0;
@@ -410,8 +413,9 @@ k_ref_build_q(const double2* __restrict__ E, const double2* __restrict__ E2, int
 // rounding, and the update divides the anti-Hermitian part by eigenvalue
 // gaps: without the symmetrisation it stalls the orthonormality near 1e-11.
 __global__ void __launch_bounds__(256)
-k_ref_check(double2* __restrict__ S, double2* __restrict__ R, int m, double tau,
-            double* __restrict__ part) {
+k_ref_check(double2* __restrict__ S, double2* __restrict__ R, int m,
+            const double* __restrict__ taup, double* __restrict__ part) {
+  const double tau = *taup;
   double off = 0.0, dia = 0.0, rmax = 0.0;
   const size_t n = size_t(m) * m;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
@@ -470,9 +474,9 @@ k_ref_check(double2* __restrict__ S, double2* __restrict__ R, int m, double tau,
   }
 }
 
-// Sum of Re A_ii^2 (one workgroup of 256 threads) into out[0].
+// tau = noise * rms of Re A_ii (one workgroup of 256 threads).
 __global__ void __launch_bounds__(256)
-k_ref_diag2(const double2* __restrict__ A, int m, double* __restrict__ out) {
+k_ref_diag2(const double2* __restrict__ A, int m, double noise, double* __restrict__ tau) {
   double v = 0.0;
   for (int i = threadIdx.x; i < m; i += blockDim.x) {
     const double d = A[size_t(i) * m + i].x;
@@ -483,7 +487,13 @@ k_ref_diag2(const double2* __restrict__ A, int m, double* __restrict__ out) {
   __shared__ double red[4];
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  if (threadIdx.x == 0) out[0] = red[0] + red[1] + red[2] + red[3];
+  if (threadIdx.x == 0) tau[0] = noise * sqrt((red[0] + red[1] + red[2] + red[3]) / m);
+}
+
+// tau = noise * rms eigenvalue from the diagonal norm of the last check.
+__global__ void k_ref_tau(const double* __restrict__ norms, int m, double noise,
+                          double* __restrict__ tau) {
+  if (threadIdx.x == 0) tau[0] = noise * sqrt(norms[1] / m);
 }
 
 __global__ void k_ref_check_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
@@ -521,7 +531,7 @@ RefineWork carve(void* work, int m) {
   r.lam = dbl(m);
   r.lam2 = dbl(m);
   r.part = dbl(3 * CHECK_BLOCKS);
-  r.norms = dbl(4);
+  r.norms = dbl(8);   // [0..2] check norms, [4] noise floor tau
   r.emax = reinterpret_cast<unsigned long long*>(dbl(1));
   r.rank = in(m);
   r.order = in(m);
@@ -563,15 +573,8 @@ int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double to
   // term and count as converged.  The residual of the outer iteration then
   // levels off near tau times the square root of the couplings per state,
   // which is where the precision ladder hands over to FP64.
-  double tau = 0.0;
-  {
-    double d2 = 0.0;
-    hipLaunchKernelGGL(k_ref_diag2, dim3(1), dim3(256), 0, st, A, m, r.norms);
-    hipMemcpyAsync(&d2, r.norms, sizeof(double), hipMemcpyDeviceToHost, st);
-    hipStreamSynchronize(st);
-    if (!(d2 == d2)) return -1;
-    tau = noise * sqrt(d2 / m);
-  }
+  double* tau = r.norms + 4;   // on the device: no read-back needed
+  hipLaunchKernelGGL(k_ref_diag2, dim3(1), dim3(256), 0, st, A, m, noise, tau);
   for (int it = 0;; ++it) {
     const double2* Sp = A;
     const double2* Rp = nullptr;
@@ -579,7 +582,8 @@ int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double to
       gemm_square(X, 1, X, 0, R, m, st, r.gpart, 1, sq_split);
       gemm_square(A, 0, X, 0, T, m, st, r.gpart, 0, sq_split);
       gemm_square(X, 1, T, 0, S, m, st, r.gpart, 1, sq_split);
-      hipLaunchKernelGGL(k_ref_check, dim3(ncheck), dim3(256), 0, st, S, R, m, tau, r.part);
+      hipLaunchKernelGGL(k_ref_check, dim3(ncheck), dim3(256), 0, st, S, R, m, (const double*)tau,
+                         r.part);
       hipLaunchKernelGGL(k_ref_check_final, dim3(1), dim3(64), 0, st, (const double*)r.part,
                          int(ncheck), r.norms);
       double h[3];
@@ -596,19 +600,19 @@ int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double to
       if (it >= maxit) return -1;
       Sp = S;
       Rp = R;
-      tau = noise * sqrt(h[1] / m);
+      hipLaunchKernelGGL(k_ref_tau, dim3(1), dim3(64), 0, st, (const double*)r.norms, m, noise, tau);
     }
     hipLaunchKernelGGL(k_ref_lambda, dim3(gm), dim3(256), 0, st, Sp, Rp, m, r.lam, r.emax);
     hipLaunchKernelGGL(k_ref_rank, dim3(gm), dim3(256), 0, st, (const double*)r.lam, m, r.rank, r.order);
     hipLaunchKernelGGL(k_ref_reach, dim3(m), dim3(256), 0, st, Sp, Rp, (const double*)r.lam,
-                       (const int*)r.rank, m, THETA, tau, r.reach);
+                       (const int*)r.rank, m, THETA, (const double*)tau, r.reach);
     hipLaunchKernelGGL(k_ref_clusters, dim3(1), dim3(1024), 0, st, (const int*)r.reach, m, r.pm,
                        r.cstart, r.csize, r.cslot, r.clist, r.info);
     hipLaunchKernelGGL(k_ref_cluster_eig, dim3(unsigned(m / 2 + 1)), dim3(256), 0, st, Sp, Rp, m,
                        (const int*)r.order, (const int2*)r.clist, (const int*)r.info, r.W, tol * 1e-2);
     hipLaunchKernelGGL(k_ref_lambda2, dim3(gm), dim3(256), 0, st, Sp, Rp, m, cl, r.lam2);
     hipLaunchKernelGGL(k_ref_update, dim3(gm, unsigned(m)), dim3(256), 0, st, Sp, Rp, m, cl,
-                       (const double*)r.lam2, tau, E, r.emax);
+                       (const double*)r.lam2, (const double*)tau, E, r.emax);
     // E^2/2 matters while |E| > 1e-8 (below, it is under FP64 rounding of 1 + E);
     // read |E| only once the previous step was already close
     bool second = true;

@@ -372,8 +372,10 @@ int subspace_solve(sky_ctx* c, int q, double* ritz) {
     gemm_square(T, 0, Linv, 1, Hp, m, st, sq, 1, sqs);
   }
   hermitian_fill(Hp, m, st);   // exact Hermitian symmetry of H' before the eigensolver
-  int rc = check_info(c, "cholesky");
-  if (rc) return rc;
+  if (terms <= 0) {   // only the Cholesky path can report a non-positive overlap
+    int rc = check_info(c, "cholesky");
+    if (rc) return rc;
+  }
   double* w = ritz ? ritz : c->at<double>(c->lay.ritz[q]);
   int its = refine_eigh(Hp, m, w, Z, c->at(c->lay.ref_work), JACOBI_TOL, REFINE_ITERS, st, sqs,
                         c->prec ? MIXED_HP_NOISE : 0x1p-49);
