@@ -180,6 +180,28 @@ def cpu_baseline(w, budget_states: int = 8, k_slice: int = 32) -> dict:
                 seconds_per_iter=sec, parts_s={k: round(x, 3) for k, x in t.items()})
 
 
+def copy_bandwidth(dev) -> dict:
+    """Measured device-to-device copy rate (1 GiB, read + write counted), the
+    practical ceiling for the HBM-bound phases next to the 8 TB/s peak."""
+    import torch
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(10):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) / 1e3 / 10
+    gbs = 2.0 * (4 << 28) / sec / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return dict(achieved=gbs, peak=PEAK_HBM_GBS, unit="GB/s", frac=gbs / PEAK_HBM_GBS,
+                note="torch device copy of 1 GiB, bytes read + written")
+
+
 def bench_batch(args) -> int:
     """64 independent uneven boxes (16^3-32^3, 102-512 nucleons, mixed
     precision): box-iterations per second of the batched driver (worker
@@ -455,6 +477,7 @@ def main() -> int:
                                 phases_ms_per_iter={k: round((v["ms_n"] + v["ms_p"]) / args.steps, 3)
                                                     for k, v in t64.items()},
                                 energy_per_a=r64[-1]["energy_per_a"])
+    out["hbm_copy"] = copy_bandwidth(dev)
     del dn, dp
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
