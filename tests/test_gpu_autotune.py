@@ -62,7 +62,8 @@ def test_autotune_parity_and_cache(torch_mod, tmp_path, case, precision, tol):
 
 
 @pytest.mark.parametrize("case,precision", [("n24_13p7_rod", 0), ("n32_70p33_slab", 0),
-                                            ("n16_8p8", 1), ("n24_13p7_rod", 1)])
+                                            ("n16_8p8", 1), ("n24_13p7_rod", 1),
+                                            ("n48_6p3", 1)])
 @pytest.mark.parametrize("h_lines,damp_xy", [(-1, 1), (0, 0)])
 def test_slice_and_pencil_variants_match_oracle(torch_mod, tmp_path, case, precision,
                                                 h_lines, damp_xy):
@@ -73,7 +74,8 @@ def test_slice_and_pencil_variants_match_oracle(torch_mod, tmp_path, case, preci
     from oracle import Grid
     from oracle import physics as ph
     from oracle import solver as so
-    w = CASES[case]
+    w = CASES[case] if case in CASES else inputs.small_workload(case, 48, 6, 3, init="rod",
+                                                                 seed=34, noise=0.05)
     raw = inputs.raw_states(w)
     box = _box(w, precision)
     box.init_box(to_dev(raw[0]), to_dev(raw[1]))
