@@ -200,6 +200,68 @@ template <typename T, int N, int S> struct LineFFT {
   }
 };
 
+// The same two-stage FFT with the exchange done in place, in the line's own
+// N slots: element idx of spin component s lives at base[s * sp + idx * es]
+// (es = 1 for a row, the row pitch for a column of an LDS slice).  Stage A
+// of thread j writes exactly the slots it loaded (k1 * R2 + j), so only the
+// stage boundaries need barriers; the inverse starts with one, since its
+// stage-B writes land on slots other threads have just loaded from.  Every
+// thread of the workgroup must call these (barriers).
+template <typename T, int N, int S> struct LineFFTInPlace {
+  static constexpr int R1 = Fact<N>::R1, R2 = Fact<N>::R2;
+
+  // va[s][j1] at positions j + R2*j1  ->  vb[s][k2] at frequencies j + R1*k2
+  __device__ static inline void forward(cpx<T> (&va)[S][R1], cpx<T> (&vb)[S][R2], cpx<T>* base,
+                                        int sp, int es, int j, const cpx<T>* twN) {
+    if (j < R2) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        DFT<T, R1, false>::run(va[s]);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) base[s * sp + (k1 * R2 + j) * es] = va[s][k1] * twN[j * k1];
+      }
+    }
+    __syncthreads();
+    if (j < R1) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) vb[s][k2] = base[s * sp + (j * R2 + k2) * es];
+        DFT<T, R2, false>::run(vb[s]);
+      }
+    }
+    __syncthreads();
+  }
+
+  // vb[s][k2] at frequencies j + R1*k2  ->  va[s][j1] at positions j + R2*j1
+  __device__ static inline void inverse(cpx<T> (&vb)[S][R2], cpx<T> (&va)[S][R1], cpx<T>* base,
+                                        int sp, int es, int j, const cpx<T>* twN) {
+    __syncthreads();
+    if (j < R1) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        DFT<T, R2, true>::run(vb[s]);
+#pragma unroll
+        for (int j2 = 0; j2 < R2; ++j2)
+          base[s * sp + (j * R2 + j2) * es] = vb[s][j2] * conj(twN[j2 * j]);
+      }
+    }
+    __syncthreads();
+    if (j < R2) {
+      constexpr T inv_n = T(1) / T(N);
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) va[s][k1] = base[s * sp + (k1 * R2 + j) * es];
+        DFT<T, R1, true>::run(va[s]);
+#pragma unroll
+        for (int j1 = 0; j1 < R1; ++j1) va[s][j1] = inv_n * va[s][j1];
+      }
+    }
+    __syncthreads();
+  }
+};
+
 // exp(-2 pi i m / N), m < N, into LDS (all threads of the block help).
 template <typename T, int N> __device__ inline void load_twiddles(cpx<T>* tw) {
   for (int m = threadIdx.x; m < N; m += blockDim.x) {

@@ -176,10 +176,18 @@ template <typename T, int N> constexpr bool plane_fits() {
   return PlaneCfg<N>::THREADS <= 1024 &&
          (2 * PlaneCfg<N>::SPIN + N * LineFFT<T, N, 2>::YSIZE + N) * sizeof(cpx<T>) <= 80 * 1024;
 }
+// The damped step's slice kernels exchange in place in the slice (no line
+// buffers): half the LDS of the h slices.
+template <typename T, int N> constexpr bool damp_slices_fit() {
+  return PlaneCfg<N>::THREADS <= 1024 && (2 * PlaneCfg<N>::SPIN + N) * sizeof(cpx<T>) <= 80 * 1024;
+}
 // Default use: measured on MI355X, the slices win up to 32^3 (damped step
 // 16% faster, h psi even or faster); at 48^3 their 80 KB of LDS leaves two
 // workgroups per CU and the line passes are faster.  The tuner decides per box.
 template <typename T, int N> constexpr bool plane_default() { return plane_fits<T, N>() && N <= 32; }
+template <typename T, int N> constexpr bool damp_slice_default() {
+  return damp_slices_fit<T, N>() && N <= 32;
+}
 
 // Deterministic workgroup sum of one double per thread (any blockDim), using
 // buf[blockDim.x] of LDS; the result is returned to thread 0.
@@ -329,12 +337,11 @@ k_damp_fwd_xy(const cpx<T>* __restrict__ psi, const cpx<T>* __restrict__ hpsi,
               const double* __restrict__ eps, cpx<T>* __restrict__ out, GridArgs g,
               double* __restrict__ r2_part) {
   using C = PlaneCfg<N>;
-  using F = LineFFT<T, N, 2>;
+  using F = LineFFTInPlace<T, N, 2>;
   constexpr int R1 = C::R1, R2 = C::R2, RT = C::RT, PITCH = C::PITCH, SP = C::SPIN;
   constexpr int N2 = N * N, N3 = N * N2;
   __shared__ cpx<T> tw[N];
   __shared__ cpx<T> P[2 * SP];
-  __shared__ cpx<T> Ybuf[N * F::YSIZE];
   load_twiddles<T, N>(tw);
   const int zoff = blockIdx.x * N2;
   const size_t soff = size_t(blockIdx.y) * 2 * N3;
@@ -356,7 +363,7 @@ k_damp_fwd_xy(const cpx<T>* __restrict__ psi, const cpx<T>* __restrict__ hpsi,
       for (int j1 = 0; j1 < R1; ++j1)
 #pragma unroll
         for (int s = 0; s < 2; ++s) va[s][j1] = P[s * SP + ly * PITCH + j + R2 * j1];
-    F::forward(va, vb, Ybuf + ly * F::YSIZE, j, tw);
+    F::forward(va, vb, P + ly * PITCH, SP, 1, j, tw);
     if (j < R1)
 #pragma unroll
       for (int k2 = 0; k2 < R2; ++k2)
@@ -372,7 +379,7 @@ k_damp_fwd_xy(const cpx<T>* __restrict__ psi, const cpx<T>* __restrict__ hpsi,
       for (int j1 = 0; j1 < R1; ++j1)
 #pragma unroll
         for (int s = 0; s < 2; ++s) va[s][j1] = P[s * SP + (j + R2 * j1) * PITCH + lx];
-    F::forward(va, vb, Ybuf + lx * F::YSIZE, j, tw);
+    F::forward(va, vb, P + lx, SP, PITCH, j, tw);
     if (j < R1)
 #pragma unroll
       for (int k2 = 0; k2 < R2; ++k2)
@@ -396,12 +403,11 @@ __global__ void __launch_bounds__(PlaneCfg<N>::THREADS)
 k_damp_inv_xy(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ buf,
               unsigned int* __restrict__ amax) {
   using C = PlaneCfg<N>;
-  using F = LineFFT<T, N, 2>;
+  using F = LineFFTInPlace<T, N, 2>;
   constexpr int R1 = C::R1, R2 = C::R2, RT = C::RT, PITCH = C::PITCH, SP = C::SPIN;
   constexpr int N2 = N * N, N3 = N * N2;
   __shared__ cpx<T> tw[N];
   __shared__ cpx<T> P[2 * SP];
-  __shared__ cpx<T> Ybuf[N * F::YSIZE];
   load_twiddles<T, N>(tw);
   const int zoff = blockIdx.x * N2;
   const size_t soff = size_t(blockIdx.y) * 2 * N3;
@@ -418,7 +424,7 @@ k_damp_inv_xy(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ buf,
       for (int k2 = 0; k2 < R2; ++k2)
 #pragma unroll
         for (int s = 0; s < 2; ++s) vb[s][k2] = P[s * SP + (j + R1 * k2) * PITCH + lx];
-    F::inverse(vb, va, Ybuf + lx * F::YSIZE, j, tw);
+    F::inverse(vb, va, P + lx, SP, PITCH, j, tw);
     if (j < R2)
 #pragma unroll
       for (int j1 = 0; j1 < R1; ++j1)
@@ -434,7 +440,7 @@ k_damp_inv_xy(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ buf,
       for (int k2 = 0; k2 < R2; ++k2)
 #pragma unroll
         for (int s = 0; s < 2; ++s) vb[s][k2] = P[s * SP + ly * PITCH + j + R1 * k2];
-    F::inverse(vb, va, Ybuf + ly * F::YSIZE, j, tw);
+    F::inverse(vb, va, P + ly * PITCH, SP, 1, j, tw);
     if (j < R2)
 #pragma unroll
       for (int j1 = 0; j1 < R1; ++j1)
@@ -917,6 +923,13 @@ int h_pass_lines(int n, int prec, int* out) {
   return k;
 }
 
+int damp_slices_available(int n, int prec) {
+  int v = 0;
+  if (prec == 0) SKY_DISPATCH_N(n, v = (damp_slices_fit<double, NN>() ? 1 : 0))
+  else SKY_DISPATCH_N(n, v = (damp_slices_fit<float, NN>() ? 1 : 0))
+  return v;
+}
+
 int h_pass_default(int n, int prec) {
   int v = 0;
   if (prec == 0) SKY_DISPATCH_N(n, v = (lines_default<double, NN>()))
@@ -950,10 +963,10 @@ static void launch_damp(const void* psi, const void* hpsi, const double* eps, vo
   auto p = reinterpret_cast<const cpx<T>*>(psi);
   auto h = reinterpret_cast<const cpx<T>*>(hpsi);
   auto o = reinterpret_cast<cpx<T>*>(phi);
-  const bool pl = plane_fits<T, N>() && (xy < 0 ? plane_default<T, N>() : xy != 0);
+  const bool pl = damp_slices_fit<T, N>() && (xy < 0 ? damp_slice_default<T, N>() : xy != 0);
   if (stage != 2) {
     if (pl) {
-      if constexpr (plane_fits<T, N>())
+      if constexpr (damp_slices_fit<T, N>())
         hipLaunchKernelGGL((k_damp_fwd_xy<T, N>), pgrid, pblock, 0, st, p, h, eps, o, g, r2_part);
     } else {
       hipLaunchKernelGGL((k_damp_fwd_x<T, N>), grid, block, 0, st, p, h, eps, o, g, r2_part);
@@ -968,7 +981,7 @@ static void launch_damp(const void* psi, const void* hpsi, const double* eps, vo
   else
     hipLaunchKernelGGL((k_damp_z<T, N, 0>), grid, block, 0, st, o, g, d, nullptr, nullptr);
   if (pl) {
-    if constexpr (plane_fits<T, N>())
+    if constexpr (damp_slices_fit<T, N>())
       hipLaunchKernelGGL((k_damp_inv_xy<T, N>), pgrid, pblock, 0, st, p, o, amax);
   } else {
     hipLaunchKernelGGL((k_damp_y<T, N, true>), grid, block, 0, st, o);
@@ -987,9 +1000,9 @@ void damped_step(int n, int prec, const void* psi, const void* hpsi, const doubl
   if (stage == 2) return;
   int nt = 0;
   if (prec == 0)
-    SKY_DISPATCH_N(n, nt = (plane_fits<double, NN>() && (xy < 0 ? plane_default<double, NN>() : xy != 0)) ? NN : ntiles<NN>())
+    SKY_DISPATCH_N(n, nt = (damp_slices_fit<double, NN>() && (xy < 0 ? damp_slice_default<double, NN>() : xy != 0)) ? NN : ntiles<NN>())
   else
-    SKY_DISPATCH_N(n, nt = (plane_fits<float, NN>() && (xy < 0 ? plane_default<float, NN>() : xy != 0)) ? NN : ntiles<NN>())
+    SKY_DISPATCH_N(n, nt = (damp_slices_fit<float, NN>() && (xy < 0 ? damp_slice_default<float, NN>() : xy != 0)) ? NN : ntiles<NN>())
   if (r2)
     hipLaunchKernelGGL(k_sum_partials, dim3((nstate + 127) / 128), dim3(128), 0, st,
                        (const double*)r2_part, nt, nstate, r2);

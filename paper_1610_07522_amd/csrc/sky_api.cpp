@@ -1061,7 +1061,7 @@ int sky_autotune(sky_ctx* c, const char* cache_path, sky_tuning* out) {
     c->tune.lines = v;
     // x and y transforms of the damped step on LDS slices (1) or by pencils (0)
     int dv = cache_has(kv, kdamp) ? cache_get(kv, kdamp) : -1;
-    if (cand[0] != H_PLANE) dv = 1;   // no slice variant on this grid: nothing to pick
+    if (!damp_slices_available(c->n, c->prec)) dv = 0;   // pencils are the only variant
     if (dv != 0 && dv != 1) {
       const int dc[2] = {1, 0};
       const double hb = q ? c->d.hb2m_p : c->d.hb2m_n;

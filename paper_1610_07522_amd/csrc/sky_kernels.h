@@ -15,6 +15,8 @@ int grid_ntiles(int n);  // room for the per-state partials of one pass
 constexpr int H_PLANE = -1;
 int h_pass_lines(int n, int prec, int* out);
 int h_pass_default(int n, int prec);
+// 1 if the damped step has the LDS-slice variant on this grid and precision.
+int damp_slices_available(int n, int prec);
 // amax (optional): the largest |component| of h psi is merged into it (float
 // bits; clear it first), as plane_scale would compute it.
 int apply_h(int n, int prec, const void* psi, void* hpsi, int nstate, MeanFieldPtrs mf,
