@@ -110,3 +110,48 @@ def test_slice_and_pencil_variants_match_oracle(torch_mod, tmp_path, case, preci
     assert rel_err(to_host(hpsi), h_ref) <= th
     assert rel_err(to_host(eps), e_ref) <= th
     assert rel_err(to_host(phi), phi_ref) <= tp
+
+
+@pytest.mark.parametrize("n,nn,np_,precision", [(48, 6, 3, 0), (64, 4, 2, 1)])
+@pytest.mark.parametrize("damp_xy", [1, 0])
+def test_damped_step_slices_large_grids(torch_mod, tmp_path, n, nn, np_, precision, damp_xy):
+    """The damped step's slice kernels where only they fit in LDS with the
+    in-place FFT exchange (48^3 FP64, 64^3 complex64), and the line passes,
+    forced through the tuning cache, against the oracle (FP64 1e-11;
+    complex64 inputs 2e-6)."""
+    import torch
+    from oracle import Grid
+    from oracle import physics as ph
+    from oracle import solver as so
+    w = inputs.small_workload(f"n{n}_{nn}p{np_}", n, nn, np_, init="rod", seed=35, noise=0.05)
+    raw = inputs.raw_states(w)
+    box = _box(w, precision)
+    box.init_box(to_dev(raw[0]), to_dev(raw[1]))
+    prec = "mixed" if precision else "fp64"
+    lines = box.tuning()["h_lines"]
+    cache = tmp_path / "force.json"
+    cache.write_text(json.dumps({f"h_lines/n{n}/{prec}": lines, f"damp_xy/n{n}/{prec}": damp_xy}))
+    t = box.autotune(str(cache))
+    assert t["damp_xy"] == damp_xy
+    g = Grid(w.n, w.dx)
+    cdt = torch.complex64 if precision else torch.complex128
+    for s in range(2):
+        box.view("psi", s).copy_(to_dev(raw[s]).to(cdt))
+    box.densities()
+    xs = [to_host(box.view("psi", s)).astype(np.complex128) for s in range(2)]
+    dens = [ph.densities(xs[0], g), ph.densities(xs[1], g)]
+    mf = ph.mean_field(dens[0], dens[1], g, w.params)[0]
+    psi, hpsi, phi = box.view("psi", 0), box.view("hpsi", 0), box.view("phi", 0)
+    eps = torch.empty(nn, dtype=torch.float64, device=psi.device)
+    box.apply_h(0, psi, hpsi, nn, eps)
+    # the step from the oracle's h psi rounded to the working precision
+    x = xs[0]
+    h_ref = ph.apply_h(x, mf, g)
+    hpsi.copy_(to_dev(h_ref).to(cdt))
+    hr = to_host(hpsi).astype(np.complex128)
+    e_ref, r_ref, _ = so.rayleigh_and_residual(x, hr, g)
+    eps.copy_(to_dev(e_ref))
+    box.damped_step(0, psi, hpsi, eps, phi, nn)
+    torch.cuda.synchronize()
+    phi_ref = x - so.damping(r_ref, g, mf.hb2m, w.damp_x0, w.damp_e0)
+    assert rel_err(to_host(phi), phi_ref) <= (2e-6 if precision else 1e-11)
