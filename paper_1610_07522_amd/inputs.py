@@ -74,10 +74,12 @@ WORKLOADS: Dict[str, Workload] = {
     # 48 fm pasta box, 1600 n + 400 p, rod perturbation (cylinders along z).
     "rod48": Workload("rod48", 48, 1.0, 1600, 400, "rod", seed=2),
     # Saturation-density boxes (closed plane-wave shells, weak slab, small
-    # noise): uniform matter there is stable, so the iteration converges to
-    # Delta-eps 1e-9 in a few hundred iterations.  24 fm, 1030 n + 1030 p
-    # (shells |n|^2 <= 25), 0.149 fm^-3; 8 fm, 38 n + 38 p, 0.148 fm^-3.
+    # noise): uniform matter there is stable, so the iteration converges
+    # (Delta-eps 1e-6 and below).  24 fm, 1030 n + 1030 p (shells
+    # |n|^2 <= 25), 0.149 fm^-3, on a 24^3 grid at 1 fm or a 48^3 grid at
+    # 0.5 fm; 8 fm, 38 n + 38 p, 0.148 fm^-3.
     "sat24": Workload("sat24", 24, 1.0, 1030, 1030, "slab", seed=4, amp=0.1, noise=0.02),
+    "sat48": Workload("sat48", 48, 0.5, 1030, 1030, "slab", seed=4, amp=0.1, noise=0.02),
     "sat8": Workload("sat8", 8, 1.0, 38, 38, "slab", seed=22, amp=0.1, noise=0.02),
 }
 
@@ -173,9 +175,9 @@ def raw_states(w: Workload) -> Tuple[np.ndarray, np.ndarray]:
 
 def small_workload(name: str, n: int, n_neutrons: int, n_protons: int,
                    init: str = "plain", seed: int = 7, noise: float = 0.1,
-                   amp: float = 0.3) -> Workload:
+                   amp: float = 0.3, dx: float = 1.0) -> Workload:
     """A reduced box for fast tests (same force and damping as the others)."""
-    return Workload(name, n, 1.0, n_neutrons, n_protons, init, seed=seed,
+    return Workload(name, n, dx, n_neutrons, n_protons, init, seed=seed,
                     amp=amp if init != "plain" else 0.0, noise=noise)
 
 

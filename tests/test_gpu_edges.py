@@ -1,5 +1,6 @@
 """Edge cases of the iteration against the FP64 oracle: an empty species
-(pure neutron matter), one state per species, and the largest grid (64^3).
+(pure neutron matter), one state per species, the largest grid (64^3) and
+a grid spacing other than 1 fm (0.5 fm).
 FP64 bar: 1e-10 relative on the energy, 1e-8 on Delta-eps; the mixed form
 within 2e-5 relative of the FP64 oracle's energy after one iteration
 (complex64 states, FP32 h psi)."""
@@ -28,6 +29,8 @@ EDGE = {
     "empty_neutrons_n16": inputs.small_workload("e1", 16, 0, 7, init="rod", seed=6, noise=0.05),
     "one_state_each_n8": inputs.small_workload("e2", 8, 1, 1, init="slab", seed=7, noise=0.1),
     "largest_grid_n64": inputs.small_workload("e3", 64, 4, 2, init="rod", seed=5, noise=0.05),
+    "half_fm_spacing_n16": inputs.small_workload("e4", 16, 6, 4, init="slab", seed=8, noise=0.05,
+                                                 dx=0.5),
 }
 
 
@@ -60,7 +63,7 @@ def test_edge_trajectory_fp64(torch_mod, case):
         assert np.abs(ov - np.eye(ov.shape[0])).max() <= 1e-12
 
 
-@pytest.mark.parametrize("case", ["empty_protons_n16", "largest_grid_n64"])
+@pytest.mark.parametrize("case", ["empty_protons_n16", "largest_grid_n64", "half_fm_spacing_n16"])
 def test_edge_mixed(torch_mod, case):
     w = EDGE[case]
     box, rep, st, ro = _run(w, 1, 1)
