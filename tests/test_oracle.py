@@ -515,3 +515,23 @@ def test_dense_h_8cubed_aufbau():
     P = st.psi[0].reshape(nq, -1).T * math.sqrt(g.dV)
     Q = vec[:, :nq]
     np.testing.assert_allclose(P @ P.conj().T, Q @ Q.conj().T, atol=1e-7)
+
+
+@pytest.mark.parametrize("name", ["sat8", "sat24"])
+def test_saturation_box_ground_state_energy(name):
+    """The closed-shell plane-wave determinant of the saturation boxes (the
+    state their iterations converge to: uniform matter there is stable) has
+    the textbook symmetric-matter energy with the box's discrete tau."""
+    import dataclasses
+    w = inputs.WORKLOADS[name]
+    wp = dataclasses.replace(w, init="plain", amp=0.0, noise=0.0)
+    raw = inputs.raw_states(wp)
+    g = Grid(w.n, w.dx)
+    st = so.initial_state(raw[0], raw[1], g, w.params, w.damp_x0, w.damp_e0)
+    L = w.n * w.dx
+    lab = inputs.plane_wave_labels(w.n, w.n_neutrons)
+    k2 = ((2 * math.pi / L) ** 2 * (lab[:, :3] ** 2).sum(axis=1)).sum()
+    rho = (w.n_neutrons + w.n_protons) / L ** 3
+    tau = 2 * k2 / L ** 3
+    p = dict(w.params)
+    assert st.E["total"] == pytest.approx(L ** 3 * _textbook_symmetric(p, rho, tau), rel=1e-12)
