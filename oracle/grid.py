@@ -10,7 +10,13 @@ Readings (the paper does not spell these out):
   (multiplier i*k with k = -pi/dx there), so D^2 = -k^2 everywhere;
 * derivative of a real field zeroes the Nyquist mode so the result stays real;
 * the Laplacian of a real field multiplies by -|k|^2 (Nyquist kept: it is
-  real and even, so the result stays real).
+  real and even, so the result stays real);
+* twisted boundary conditions (Sec. 1 names twist-averaged boundary
+  conditions as the remedy for finite-volume effects): a state obeys
+  psi(r + L e_m) = exp(i theta_m) psi(r).  It is stored as its periodic part
+  u = exp(-i theta.r/L) psi, so every derivative of a state becomes
+  d_m + i theta_m/L, i.e. the multiplier i(k_m + theta_m/L).  Densities and
+  mean fields are periodic, so derivatives of real fields are untouched.
 
 Arrays are indexed [..., z, y, x]; ``axis`` 0/1/2 means x/y/z.
 """
@@ -31,6 +37,11 @@ _WORKERS = int(os.environ.get("SKY_ORACLE_THREADS", "0")) or -1
 class Grid:
     n: int
     dx: float
+    # Bloch phase per axis (x, y, z) in radians; (0, 0, 0) = periodic
+    twist: tuple = (0.0, 0.0, 0.0)
+
+    def with_twist(self, theta) -> "Grid":
+        return Grid(self.n, self.dx, tuple(float(t) for t in theta))
 
     @property
     def L(self) -> float:
@@ -52,10 +63,20 @@ class Grid:
         return k
 
     def k2(self) -> np.ndarray:
-        """|k|^2 on the 3D grid, indexed [z, y, x]."""
+        """|k|^2 on the 3D grid, indexed [z, y, x] (real fields, no twist)."""
         k = self.k()
         return (k[:, None, None] ** 2 + k[None, :, None] ** 2
                 + k[None, None, :] ** 2)
+
+    def k_psi(self, axis: int) -> np.ndarray:
+        """Wave numbers seen by a state along ``axis``: k + theta_axis / L."""
+        return self.k() + self.twist[axis] / self.L
+
+    def k2_psi(self) -> np.ndarray:
+        """|k + theta/L|^2 on the 3D grid, indexed [z, y, x]."""
+        kx, ky, kz = self.k_psi(0), self.k_psi(1), self.k_psi(2)
+        return (kz[:, None, None] ** 2 + ky[None, :, None] ** 2
+                + kx[None, None, :] ** 2)
 
 
 def _array_axis(axis: int) -> int:
@@ -70,10 +91,11 @@ def _bcast(vec: np.ndarray, axis: int, ndim: int) -> np.ndarray:
 
 
 def deriv(f: np.ndarray, g: Grid, axis: int) -> np.ndarray:
-    """Spectral derivative of a complex array along ``axis`` (Nyquist kept)."""
+    """Spectral derivative of a state array along ``axis`` (Nyquist kept),
+    including the grid's twist: multiplier i (k + theta_axis / L)."""
     ax = _array_axis(axis)
     fk = sfft.fft(f, axis=ax, workers=_WORKERS)
-    fk *= 1j * _bcast(g.k(), axis, f.ndim)
+    fk *= 1j * _bcast(g.k_psi(axis), axis, f.ndim)
     return sfft.ifft(fk, axis=ax, workers=_WORKERS)
 
 
@@ -91,7 +113,3 @@ def laplacian_real(f: np.ndarray, g: Grid) -> np.ndarray:
     fk *= -g.k2()
     return sfft.ifftn(fk, axes=(-3, -2, -1), workers=_WORKERS).real
 
-
-def inner(a: np.ndarray, b: np.ndarray, g: Grid) -> complex:
-    """<a|b> = dV * sum over points and spin of conj(a) b (Sec. 3.1's psi(V))."""
-    return g.dV * np.vdot(a.ravel(), b.ravel())

@@ -51,8 +51,17 @@ class Densities:
     j: np.ndarray            # current density (diagnostic), [3][z][y][x]
 
 
-def densities(psi: np.ndarray, g: Grid) -> Densities:
-    """rho, tau, J of one species, all occupations v^2 = 1 (Sec. 2.1)."""
+def densities(psi: np.ndarray, g: Grid, nocc: int = None) -> Densities:
+    """rho, tau, J of one species (Eqs. rho, curr, tau).
+
+    Occupations (Sec. 2.1): v^2 = 1 for the first ``nocc`` states and 0 for
+    the rest (all states when ``nocc`` is None).  The solver keeps its states
+    in ascending order of their subspace eigenvalues, so the first ``nocc``
+    are the occupied ones of the aufbau principle.  Derivatives of the states
+    carry the grid's twist.
+    """
+    if nocc is not None:
+        psi = psi[:nocc]
     shape = psi.shape[2:]
     rho = np.zeros(shape)
     tau = np.zeros(shape)
@@ -76,6 +85,14 @@ def densities(psi: np.ndarray, g: Grid) -> Densities:
                     if EPS[k, l, m] != 0.0:
                         J[k] += EPS[k, l, m] * z.imag
     return Densities(rho, tau, J, s, j)
+
+
+def average(ds) -> Densities:
+    """Twist average of the densities of one species (equal weights): the
+    mean field of twist-averaged boundary conditions is built from it."""
+    t = len(ds)
+    return Densities(*[sum(getattr(d, f) for d in ds) / t
+                       for f in ("rho", "tau", "J", "s", "j")])
 
 
 def skyrme_b(p: Dict[str, float]) -> Dict[str, float]:
