@@ -64,6 +64,14 @@ enum {
 
 enum { SKY_NEUTRON = 0, SKY_PROTON = 1 };
 enum { SKY_FP64 = 0, SKY_MIXED = 1 };
+/* Subspace update of Fig. 1 steps 3b-3e (sky_box_desc.update). */
+enum {
+  SKY_UPDATE_EXACT = 0,   /* generalised Rayleigh-Ritz: psi = phi C Z with C^H I C = 1 */
+                          /* and Z the eigenvectors of H' = C^H H C                */
+  SKY_UPDATE_PAPER = 1    /* Sec. 3.3.3 as printed: Z from H alone (3b), C = I^-1/2  */
+                          /* from I alone (3c), psi = phi Z C (3d-3e)                */
+};
+#define SKY_MAX_TWIST 32
 
 /* Box, force and damping of one solve.  Skyrme parameters in the usual
  * units: t0 MeV fm^3, t1 t2 MeV fm^5, t3 MeV fm^(3+3 alpha), W0 MeV fm^5,
@@ -80,6 +88,29 @@ typedef struct {
   int32_t precision;                /* SKY_FP64 or SKY_MIXED                    */
   double ladder_tol;                /* SKY_MIXED: switch to FP64 once Delta-eps */
                                     /* <= ladder_tol (MeV); <= 0 never          */
+  /* Sec. 2.1: occupations v^2 in {0, 1}, more wave functions than particles
+   * allowed.  Each species carries extra_q states beyond its n_q particles;
+   * after every subspace update the states are in ascending order of their
+   * subspace eigenvalues and the first n_q are occupied (aufbau).  Only the
+   * occupied states enter the densities and Delta-eps. */
+  int32_t extra_n, extra_p;
+  /* Sec. 1, twist-averaged boundary conditions: ntwist (<= 1: one twist)
+   * Bloch phases theta (radians per axis x, y, z; all 0 = periodic).  Every
+   * twist carries its own n_q + extra_q states of each species; the
+   * derivatives of a state of twist t are d_m + i theta_m / L; one mean field,
+   * built from the densities averaged over the twists, serves all of them.
+   * The energy is the functional of the averaged densities. */
+  int32_t ntwist;
+  double twist[SKY_MAX_TWIST][3];
+  int32_t update;                   /* SKY_UPDATE_EXACT or SKY_UPDATE_PAPER     */
+  /* one_h != 0: one h application per iteration.  Sec. 3.4 keeps h psi
+   * (hampsi) for step 3a; here the h phi of step 3a is carried through the
+   * subspace update, h psi_new = (h phi) U, and the next gradient step uses
+   * it, i.e. the Hamiltonian of the previous mean field, with
+   * <psi|h psi> = the subspace eigenvalues.  Same fixed point, one FFT
+   * application fewer, one combination product more.  Needs
+   * SKY_UPDATE_EXACT. */
+  int32_t one_h;
 } sky_box_desc;
 
 typedef struct {
@@ -96,9 +127,19 @@ typedef struct {
                           /* from the refinement to the Jacobi solver           */
   int32_t precond_iters;  /* iterations of this call whose damped step used     */
                           /* the learned gains (sky_precond_use)                */
+  int32_t eig_unconverged;  /* subspace eigensolves of this call that stopped    */
+                            /* at the Jacobi solver's sweep limit above its      */
+                            /* tolerance (the result is then not exact Ritz     */
+                            /* vectors)                                          */
 } sky_report;
 
-/* Views into the context's device buffers (sky_get_view). */
+/* Views into the context's device buffers (sky_get_view).  State sets: the
+ * argument q of the per-species calls and views is a set index, set
+ * q = 2 t + s holding species s (0 = n, 1 = p) of twist t; without twists
+ * it is the species.  A set holds n_s + extra_s states.  Field views
+ * (DENS, MEANFIELD) take the species q & 1; PHI, HPHI and the subspace
+ * matrices are shared by the sets of a species (or of both) and hold the
+ * set last processed. */
 enum {
   SKY_VIEW_PSI = 0,       /* orthonormal states of species q, [n_q][2][n^3]      */
                           /* (complex128, or complex64 in mixed precision)      */
@@ -152,16 +193,19 @@ int sky_create(const sky_box_desc* d, void* workspace_dev, size_t bytes, void* s
                sky_ctx** out);
 
 /* Fig. 1 step 1 (Sec. 2.2: trial plane waves for periodic systems): take
- * caller trial states raw_n_dev [n_neutrons][2][n^3] and raw_p_dev
- * [n_protons][2][n^3] (complex128 in both precisions, need not be
+ * caller trial states raw_n_dev [n_neutrons + extra_n][2][n^3] and raw_p_dev
+ * [n_protons + extra_p][2][n^3] (complex128 in both precisions, need not be
  * orthonormal; read only), orthonormalise them in binary64 by Loewdin's
- * C = I^(-1/2) (Eqs. Loewedin, orthmatvec), round them to complex64 under
- * SKY_MIXED, then build densities, mean field and energy.  Waits for the
- * stream.
- * Errors: INVALID, NOT_POSITIVE_DEFINITE (linearly dependent states), HIP. */
+ * C = I^(-1/2) (Eqs. Loewedin, orthmatvec), give every twist the same
+ * states, round them to complex64 under SKY_MIXED, then build densities
+ * (the first n_q states of each species occupied), mean field and energy.
+ * Waits for the stream.
+ * Errors: INVALID, NOT_POSITIVE_DEFINITE (linearly dependent states: an
+ * overlap eigenvalue at or below 1e-10), NAN, HIP. */
 int sky_init_box(sky_ctx* c, const void* raw_n_dev, const void* raw_p_dev);
 
-/* h psi for `nstates` states of species q with the context's current mean
+/* h psi for `nstates` states of set q (species q & 1, twist q >> 1: its
+ * derivatives carry that twist's Bloch shift) with the context's current mean
  * field (Sec. 2.2: kinetic + Skyrme + Coulomb, FFT derivatives):
  *   h psi = U psi - sum_m d_m(B d_m psi) + (i/2) sum_m [A_m d_m psi + d_m(A_m psi)],
  *   A_m = (W x sigma)_m.
@@ -185,7 +229,8 @@ int sky_damped_step(sky_ctx* c, int32_t q, const void* psi_dev, const void* hpsi
  *   H' = L^-1 H L^-H = Z diag(lam) Z^H (ascending), psi = phi (L^-H Z);
  *   ritz_dev (may be NULL) receives lam (f64, n_q).
  * hphi_dev == NULL: Loewdin, psi = phi I^(-1/2).
- * Waits for the stream.  Errors: NOT_POSITIVE_DEFINITE, HIP. */
+ * Waits for the stream.  Errors: NOT_POSITIVE_DEFINITE (a Cholesky pivot at
+ * or below 1e-10), NAN (a non-finite overlap), HIP. */
 int sky_orthonormalize(sky_ctx* c, int32_t q, const void* phi_dev, const void* hphi_dev,
                        void* psi_out_dev, double* ritz_dev);
 
@@ -200,14 +245,36 @@ int sky_densities(sky_ctx* c);
  * itself to binary64 states after the first iteration whose Delta-eps is
  * <= ladder_tol and continues in FP64 (the precision ladder).  tol_mev > 0: stop once Delta-eps <= tol_mev (returns
  * SKY_OK), else SKY_NOT_CONVERGED after max_iter; tol_mev <= 0: run exactly
- * max_iter iterations.  report (host, may be NULL) is filled.  Waits for the
- * stream.  Errors: NAN, NOT_POSITIVE_DEFINITE, HIP. */
+ * max_iter iterations.  Delta-eps runs over the occupied states of every
+ * set.  report (host, may be NULL) is filled.  Waits for the stream.
+ * Errors: NAN (a non-finite overlap, subspace matrix, residual or energy),
+ * NOT_POSITIVE_DEFINITE (linearly dependent damped states), HIP. */
 int sky_iterate(sky_ctx* c, int32_t max_iter, double tol_mev, sky_report* report);
 
 /* Device pointer and element count (complex or f64 elements, see SKY_VIEW_*)
  * of one of the context's buffers.  The memory stays owned by the caller's
  * workspace. */
 int sky_get_view(sky_ctx* c, int32_t what, int32_t q, void** ptr_dev, int64_t* count);
+
+/* Fig. 1 step 6 and its inverse: state I/O for checkpoint and resume.
+ * sky_set_states copies the n_q + extra_q states of set q from psi_dev
+ * ([states][2][n^3], complex128 when src_precision is SKY_FP64, complex64
+ * when SKY_MIXED; read only) into the context, rounding or widening to the
+ * context's current precision.  The states are taken as they are (they are
+ * expected orthonormal and, with extra states, in ascending order of their
+ * eigenvalues); call sky_densities afterwards to rebuild the mean field
+ * from them.  Asynchronous.  With the same states, iteration counter and
+ * settings, sky_iterate then continues the FP64 trajectory bit for bit.
+ * sky_get_states copies them out the same way (dst_precision).
+ * Errors: INVALID (set index, null pointer, precision). */
+int sky_set_states(sky_ctx* c, int32_t q, const void* psi_dev, int32_t src_precision);
+int sky_get_states(sky_ctx* c, int32_t q, void* psi_dev, int32_t dst_precision);
+
+/* Iterations run on this context (sky_iterate adds to it; the online
+ * retraining cadence of the learned damping and the precision-ladder record
+ * count from it).  A resumed run sets the counter of its checkpoint. */
+int sky_get_iteration(sky_ctx* c, int64_t* iteration);
+int sky_set_iteration(sky_ctx* c, int64_t iteration);
 
 /* Phase timing of sky_iterate: enable != 0 starts recording HIP event pairs
  * on the context stream around every phase (and resets the accumulators);
@@ -314,6 +381,15 @@ int sky_precond_train(sky_ctx* c, int32_t steps, double lr, double* loss);
 int sky_precond_loss_grad(sky_ctx* c, int32_t nsamples, double* loss);
 int sky_precond_set_rows(sky_ctx* c, int32_t nrows);
 int sky_precond_use(sky_ctx* c, int32_t enable, double rise_tol, int32_t retrain_every);
+
+/* Load a trained network into the learned damping: params_dev holds nparams
+ * FP32 master parameters on the device (the layout of SKY_VIEW_PC_PARAMS;
+ * nparams must equal that view's count), read only.  The BF16 copy used by
+ * the kernels is rounded from them, the Adam moments are cleared and the
+ * network counts as trained, so sky_precond_use may enable it at once (a
+ * network trained on other boxes, carried to this one).
+ * Errors: INVALID (count, null pointer). */
+int sky_set_preconditioner(sky_ctx* c, const float* params_dev, int32_t nparams);
 
 /* Wait for all work of the context's stream. */
 int sky_sync(sky_ctx* c);

@@ -182,16 +182,17 @@ template <typename T, int N, int S> struct LineFFT {
     __syncthreads();
   }
 
-  // In-place spectral derivative i*k along the line, Nyquist kept (k = -N/2).
+  // In-place spectral derivative i*(k + kshift) along the line, Nyquist kept
+  // (k = -N/2); kshift is the Bloch shift of twisted boundary conditions.
   __device__ static inline void deriv(cpx<T> (&va)[S][R1], cpx<T>* Y, int j,
-                                      const cpx<T>* twN, T kunit) {
+                                      const cpx<T>* twN, T kunit, T kshift = T(0)) {
     cpx<T> vb[S][R2];
     forward(va, vb, Y, j, twN);
     if (j < R1) {
 #pragma unroll
       for (int k2 = 0; k2 < R2; ++k2) {
         int f = j + R1 * k2;
-        T k = kunit * T(f < N / 2 ? f : f - N);
+        T k = kunit * T(f < N / 2 ? f : f - N) + kshift;
 #pragma unroll
         for (int s = 0; s < S; ++s) vb[s][k2] = mul_i(k * vb[s][k2]);
       }

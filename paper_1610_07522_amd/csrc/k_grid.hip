@@ -85,6 +85,7 @@ k_h_pass(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPtr
   cpx<T>* hp = hpsi + soff;
   cpx<T>* Y = Ybuf + line * F::YSIZE;
   const T kunit = T(g.kunit);
+  const T kshift = T(g.tw[DIR]);
 
   cpx<T> v[2][R1], d[2][R1];
   if (j < R2) {
@@ -97,7 +98,7 @@ k_h_pass(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPtr
       d[1][j1] = v[1][j1];
     }
   }
-  F::deriv(d, Y, j, tw, kunit);
+  F::deriv(d, Y, j, tw, kunit, kshift);
 
   // g (into d) and the accumulated local terms (into acc)
   cpx<T> acc[2][R1];
@@ -122,7 +123,7 @@ k_h_pass(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPtr
       d[1][j1] = T(0.5) * mul_i(bd) - B * d[1][j1];
     }
   }
-  F::deriv(d, Y, j, tw, kunit);
+  F::deriv(d, Y, j, tw, kunit, kshift);
 
   double dot = 0.0;
   float am = 0.0f;
@@ -209,7 +210,8 @@ __device__ inline double tree_sum(double v, double* buf) {
 template <typename T, int N, int DIR>
 __device__ inline void h_dir_line(const cpx<T> (&v)[2][Fact<N>::R1], cpx<T> (&out)[2][Fact<N>::R1],
                                   const int (&r)[Fact<N>::R1], cpx<T>* Y, int j,
-                                  const cpx<T>* tw, T kunit, const MeanFieldPtrs& mf) {
+                                  const cpx<T>* tw, T kunit, T kshift,
+                                  const MeanFieldPtrs& mf) {
   using F = LineFFT<T, N, 2>;
   constexpr int R1 = Fact<N>::R1, R2 = Fact<N>::R2, N3 = N * N * N;
   cpx<T> d[2][R1];
@@ -218,7 +220,7 @@ __device__ inline void h_dir_line(const cpx<T> (&v)[2][Fact<N>::R1], cpx<T> (&ou
     d[0][j1] = v[0][j1];
     d[1][j1] = v[1][j1];
   }
-  F::deriv(d, Y, j, tw, kunit);
+  F::deriv(d, Y, j, tw, kunit, kshift);
   if (j < R2) {
 #pragma unroll
     for (int j1 = 0; j1 < R1; ++j1) {
@@ -235,7 +237,7 @@ __device__ inline void h_dir_line(const cpx<T> (&v)[2][Fact<N>::R1], cpx<T> (&ou
       d[1][j1] = T(0.5) * mul_i(bd) - B * d[1][j1];
     }
   }
-  F::deriv(d, Y, j, tw, kunit);
+  F::deriv(d, Y, j, tw, kunit, kshift);
   if (j < R2) {
 #pragma unroll
     for (int j1 = 0; j1 < R1; ++j1) {
@@ -282,7 +284,7 @@ k_h_plane(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPt
       vx[1][j1] = P[SP + ly * PITCH + x];
     }
   }
-  h_dir_line<T, N, 0>(vx, ax, rx, Ybuf + ly * F::YSIZE, jx, tw, kunit, mf);
+  h_dir_line<T, N, 0>(vx, ax, rx, Ybuf + ly * F::YSIZE, jx, tw, kunit, T(g.tw[0]), mf);
   // y lines: column lx (line fastest: consecutive threads, consecutive x)
   const int lx = threadIdx.x % N, jy = threadIdx.x / N;
   cpx<T> vy[2][R1], ay[2][R1];
@@ -305,7 +307,7 @@ k_h_plane(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPt
     }
   }
   __syncthreads();
-  h_dir_line<T, N, 1>(vy, ay, ry, Ybuf + lx * F::YSIZE, jy, tw, kunit, mf);
+  h_dir_line<T, N, 1>(vy, ay, ry, Ybuf + lx * F::YSIZE, jy, tw, kunit, T(g.tw[1]), mf);
   double dot = 0.0;
   float am = 0.0f;
   if (jy < R2) {
@@ -599,13 +601,13 @@ k_damp_z(cpx<T>* __restrict__ buf, GridArgs g, DampArgs d, const float* __restri
     for (int s = 0; s < PC_SHELLS; ++s) lpow[s] = 0.0;
   if (j < R1) {
     const int ia = a < N / 2 ? a : a - N, ib = b < N / 2 ? b : b - N;
-    double kx = g.kunit * double(ia);
-    double ky = g.kunit * double(ib);
+    double kx = g.kunit * double(ia) + g.tw[0];
+    double ky = g.kunit * double(ib) + g.tw[1];
 #pragma unroll
     for (int k2 = 0; k2 < R2; ++k2) {
       int f = j + R1 * k2;
       const int ic = f < N / 2 ? f : f - N;
-      double kz = g.kunit * double(ic);
+      double kz = g.kunit * double(ic) + g.tw[2];
       const double kk = kx * kx + ky * ky + kz * kz;
       const int m2 = ia * ia + ib * ib + ic * ic;
       if (MODE == 1) {
@@ -713,6 +715,7 @@ k_dens_pass(const cpx<T>* __restrict__ psi, int nstate, int chunk, GridArgs g,
   line_geom<N, DIR>(L, base, stride, a, b);
   cpx<T>* Y = Ybuf + line * F::YSIZE;
   const T kunit = T(g.kunit);
+  const T kshift = T(g.tw[DIR]);
 
   double acc[NS][R1];
 #pragma unroll
@@ -735,7 +738,7 @@ k_dens_pass(const cpx<T>* __restrict__ psi, int nstate, int chunk, GridArgs g,
         d[1][j1] = v[1][j1];
       }
     }
-    F::deriv(d, Y, j, tw, kunit);
+    F::deriv(d, Y, j, tw, kunit, kshift);
     if (j < R2) {
 #pragma unroll
       for (int j1 = 0; j1 < R1; ++j1) {
@@ -783,7 +786,7 @@ k_dens_pass(const cpx<T>* __restrict__ psi, int nstate, int chunk, GridArgs g,
 
 // rho, tau, J[3], s[3], j[3] (11 fields) from the chunk partials.
 __global__ void k_dens_reduce(const double* __restrict__ part, int nchunk, int n3,
-                              double* __restrict__ dens) {
+                              double* __restrict__ dens, double scale) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n3) return;
   double q[16];
@@ -792,6 +795,8 @@ __global__ void k_dens_reduce(const double* __restrict__ part, int nchunk, int n
     const double* p = part + size_t(c) * 16 * n3 + r;
     for (int k = 0; k < 16; ++k) q[k] += p[size_t(k) * n3];
   }
+  if (scale != 1.0)
+    for (int k = 0; k < 16; ++k) q[k] *= scale;
   double* o = dens;
   o[0 * n3 + r] = q[0];                       // rho
   o[1 * n3 + r] = q[4] + q[8] + q[12];        // tau
@@ -1018,19 +1023,24 @@ static void launch_dens(const void* psi, int nstate, int chunk, int nchunk, Grid
   hipLaunchKernelGGL((k_dens_pass<T, N, 2>), grid, block, 0, st, p, nstate, chunk, g, part);
 }
 
-void densities(int n, int prec, const void* psi, int nstate, int nchunk_max, GridArgs g,
-               double* part, double* dens, hipStream_t st) {
+void densities(int n, int prec, const void* const* psi, const GridArgs* g, int ngroup,
+               int nstate, int nchunk_max, double* part, double* dens, hipStream_t st) {
   const int n3 = n * n * n;
-  if (nstate <= 0) {
+  if (nstate <= 0 || ngroup <= 0) {
     zero(dens, size_t(11) * n3, st);
     return;
   }
-  int chunk = (nstate + nchunk_max - 1) / nchunk_max;
-  int nchunk = (nstate + chunk - 1) / chunk;
-  if (prec == 0) SKY_DISPATCH_N(n, launch_dens<double, NN>(psi, nstate, chunk, nchunk, g, part, st))
-  else SKY_DISPATCH_N(n, launch_dens<float, NN>(psi, nstate, chunk, nchunk, g, part, st))
+  // each group (twist) takes an equal share of the chunk partials
+  const int cmax = std::max(1, nchunk_max / ngroup);
+  const int chunk = (nstate + cmax - 1) / cmax;
+  const int nchunk = (nstate + chunk - 1) / chunk;
+  for (int t = 0; t < ngroup; ++t) {
+    double* pt = part + size_t(t) * nchunk * 16 * n3;
+    if (prec == 0) SKY_DISPATCH_N(n, launch_dens<double, NN>(psi[t], nstate, chunk, nchunk, g[t], pt, st))
+    else SKY_DISPATCH_N(n, launch_dens<float, NN>(psi[t], nstate, chunk, nchunk, g[t], pt, st))
+  }
   hipLaunchKernelGGL(k_dens_reduce, dim3((n3 + 255) / 256), dim3(256), 0, st,
-                     (const double*)part, nchunk, n3, dens);
+                     (const double*)part, nchunk * ngroup, n3, dens, 1.0 / ngroup);
 }
 
 }  // namespace sky

@@ -11,6 +11,7 @@
 // every round is fully parallel.
 #include <vector>
 #include <algorithm>
+#include <cmath>
 
 #include "jacobi_rot.h"
 #include "mfma_f64.h"
@@ -34,7 +35,8 @@ constexpr int JACOBI_INNER = 3;
 // Factor the kw x kw diagonal block at (k0, k0) in LDS and invert it:
 // A[k0.., k0..] <- L_kk (lower), Dinv <- L_kk^-1 (CB x CB, lower).
 __global__ void __launch_bounds__(256)
-k_chol_diag(double2* __restrict__ A, int m, int k0, double2* __restrict__ Dinv, int* info) {
+k_chol_diag(double2* __restrict__ A, int m, int k0, double2* __restrict__ Dinv, int* info,
+            double piv_min) {
   __shared__ double2 S[CB][CB + 1];
   __shared__ double2 X[CB][CB + 1];
   __shared__ int bad;
@@ -50,7 +52,7 @@ k_chol_diag(double2* __restrict__ A, int m, int k0, double2* __restrict__ Dinv, 
   for (int j = 0; j < kw; ++j) {
     if (tid == 0) {
       double d = S[j][j].x;
-      if (!(d > 0.0)) { bad = 1; d = 1.0; }
+      if (!(d > piv_min)) { bad = 1; d = 1.0; }
       S[j][j] = make_double2(sqrt(d), 0.0);
     }
     __syncthreads();
@@ -504,11 +506,11 @@ __global__ void k_scale_columns(double2* __restrict__ X, const double* __restric
   X[e] = make_double2(s * X[e].x, s * X[e].y);
 }
 
-__global__ void k_inv_sqrt(double* __restrict__ w, int m, int* info) {
+__global__ void k_inv_sqrt(double* __restrict__ w, int m, int* info, double floor_v) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
   double v = w[i];
-  if (!(v > 0.0)) { atomicExch(info, 1); v = 1.0; }
+  if (!(v > floor_v)) { atomicExch(info, 1); v = 1.0; }
   w[i] = 1.0 / sqrt(v);
 }
 
@@ -525,7 +527,18 @@ void zero(double* p, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_zero, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, p, n);
 }
 
-void cholesky_inverse(void* Av, void* Linvv, int m, void* work, int* info, hipStream_t st) {
+__global__ void k_zero_f32(float* __restrict__ p, size_t n) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0f;
+}
+
+void zero_f32(float* p, size_t n, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_zero_f32, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, p, n);
+}
+
+void cholesky_inverse(void* Av, void* Linvv, int m, void* work, int* info, hipStream_t st,
+                      double piv_min) {
   if (m <= 0) return;
   auto A = (double2*)Av;
   auto Linv = (double2*)Linvv;
@@ -534,7 +547,7 @@ void cholesky_inverse(void* Av, void* Linvv, int m, void* work, int* info, hipSt
   for (int kb = 0; kb < nblk; ++kb) {
     const int k0 = kb * CB;
     hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, A, m, k0,
-                       Dinv + size_t(kb) * CB * CB, info);
+                       Dinv + size_t(kb) * CB * CB, info, piv_min);
     const int rest = m - (k0 + min(CB, m - k0));
     if (rest > 0) {
       const int nb = (rest + CB - 1) / CB;
@@ -591,13 +604,16 @@ int jacobi_eigh(void* Av, int m, double* w, void* Zv, void* work, double tol, in
   const int nrb = 256;
   double host_norm[2];
   int sweeps = 0;
-  for (; sweeps < max_sweeps; ++sweeps) {
+  bool done = false;
+  for (; sweeps <= max_sweeps; ++sweeps) {
     hipLaunchKernelGGL(k_offnorm, dim3(nrb), dim3(256), 0, st, (const double2*)Ap, mp, norms);
     hipLaunchKernelGGL(k_offnorm_final, dim3(1), dim3(64), 0, st, (const double*)norms, nrb,
                        norms + 2 * nrb);
     hipMemcpyAsync(host_norm, norms + 2 * nrb, 2 * sizeof(double), hipMemcpyDeviceToHost, st);
     hipStreamSynchronize(st);
-    if (host_norm[0] <= tol * tol * host_norm[1] || host_norm[0] < 1e-300) break;
+    if (!std::isfinite(host_norm[0]) || !std::isfinite(host_norm[1])) return -2;
+    if (host_norm[0] <= tol * tol * host_norm[1] || host_norm[0] < 1e-300) { done = true; break; }
+    if (sweeps == max_sweeps) break;   // the norm after the last sweep was checked
     for (int r = 0; r < nb - 1; ++r) {
       const int2* pr = pairs + size_t(r) * np;
       hipLaunchKernelGGL(k_jacobi_pair, dim3(np), dim3(JT), 0, st, (const double2*)Ap, mp, pr,
@@ -610,7 +626,7 @@ int jacobi_eigh(void* Av, int m, double* w, void* Zv, void* work, double tol, in
   }
   hipLaunchKernelGGL(k_jacobi_sort, dim3(m), dim3(256), 0, st, (const double2*)Ap,
                      (const double2*)V, m, mp, w, (double2*)Zv);
-  return sweeps;
+  return done ? sweeps : -1;
 }
 
 void eig_sort(const void* D, const void* V, int m, int ld, double* w, void* Z, hipStream_t st) {
@@ -631,6 +647,7 @@ int loewdin_series(const void* Iv, void* Cv, void* Dv, void* Tv, int m, double m
   hipMemcpyAsync(&fro2, scratch + nb, sizeof(double), hipMemcpyDeviceToHost, st);
   hipStreamSynchronize(st);
   const double f = sqrt(fro2);
+  if (!std::isfinite(f)) return -1;
   if (!(f <= max_dev)) return 0;
   // (1 + D)^-1/2 = sum_k c_k D^k, c_k = c_{k-1} (1 - 2k) / (2k); ||D||_2 <= f, so the
   // tail after p terms is below |c_{p+1}| f^{p+1} / (1 - f); stop below 2^-56.
@@ -654,14 +671,49 @@ int loewdin_series(const void* Iv, void* Cv, void* Dv, void* Tv, int m, double m
   return p;
 }
 
+// Gauge of the paper-literal update.  info[3 c .. 3 c + 2] = (start a, size k,
+// offset o) of the cluster holding column c; a cluster's k x k diagonal
+// block lives at packed[o ..] row-major.
+__global__ void k_gauge_gather(const double2* __restrict__ Z, int m, const int* __restrict__ info,
+                               double2* __restrict__ packed) {
+  const int c = blockIdx.y;
+  const int a = info[3 * c], k = info[3 * c + 1], o = info[3 * c + 2];
+  for (int r = threadIdx.x; r < k; r += blockDim.x)
+    packed[size_t(o) + size_t(r) * k + (c - a)] = Z[size_t(a + r) * m + c];
+}
+
+// out[:, c] = sum_l Z[:, a + l] Q[l][c - a] over the cluster of column c.
+__global__ void k_gauge_apply(const double2* __restrict__ Z, int m, const int* __restrict__ info,
+                              const double2* __restrict__ Q, double2* __restrict__ out) {
+  const int c = blockIdx.y;
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= m) return;
+  const int a = info[3 * c], k = info[3 * c + 1], o = info[3 * c + 2];
+  double2 acc = make_double2(0.0, 0.0);
+  for (int l = 0; l < k; ++l) acc = cadd(acc, cmul(Z[size_t(row) * m + a + l], Q[size_t(o) + size_t(l) * k + (c - a)]));
+  out[size_t(row) * m + c] = acc;
+}
+
+void gauge_gather(const void* Z, int m, const int* info, void* packed, hipStream_t st) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_gauge_gather, dim3(1, m), dim3(64), 0, st, (const double2*)Z, m, info,
+                     (double2*)packed);
+}
+
+void gauge_apply(const void* Z, int m, const int* info, const void* Q, void* out, hipStream_t st) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_gauge_apply, dim3((m + 255) / 256, m), dim3(256), 0, st, (const double2*)Z, m,
+                     info, (const double2*)Q, (double2*)out);
+}
+
 void scale_columns(void* X, const double* d, int m, hipStream_t st) {
   const size_t mm = size_t(m) * m;
   hipLaunchKernelGGL(k_scale_columns, dim3(unsigned((mm + 255) / 256)), dim3(256), 0, st,
                      (double2*)X, d, m);
 }
 
-void inv_sqrt(double* w, int m, int* info, hipStream_t st) {
-  hipLaunchKernelGGL(k_inv_sqrt, dim3((m + 255) / 256), dim3(256), 0, st, w, m, info);
+void inv_sqrt(double* w, int m, int* info, hipStream_t st, double floor_v) {
+  hipLaunchKernelGGL(k_inv_sqrt, dim3((m + 255) / 256), dim3(256), 0, st, w, m, info, floor_v);
 }
 
 }  // namespace sky

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -36,6 +37,7 @@ bool grid_ok(int n) {
 constexpr size_t ALIGN = 256;
 size_t al(size_t b) { return (b + ALIGN - 1) / ALIGN * ALIGN; }
 
+constexpr int MAXSET = 2 * SKY_MAX_TWIST;   // state sets: species x twists
 constexpr int DENS_CHUNKS = 32;   // state chunks of the density passes
 constexpr int PC_CAP = 16384;     // sample rows of the learned preconditioner
 constexpr int PC_HOLD = 10;       // iterations on plain damping after a rise of the residual
@@ -48,12 +50,23 @@ constexpr double LOEWDIN_SERIES_MAX = 1e-2;
 // relative precision of H' built from the split-FP16 overlap and Hamiltonian
 // matrices (their representation error is 2^-22 of the largest entries; x2)
 constexpr double MIXED_HP_NOISE = 0x1p-21;
+// smallest Cholesky pivot (or overlap eigenvalue, for Loewdin) of an
+// overlap matrix (unit diagonal): below it the states are linearly
+// dependent for any practical purpose
+constexpr double CHOL_PIVOT_MIN = 1e-10;
+// paper-literal update: eigenvalues of H closer than this (MeV) form one
+// cluster of the gauge of Z
+constexpr double PAPER_CLUSTER_TOL = 1e-3;
 
 // Byte offsets of every buffer inside the caller's workspace.
 struct Layout {
-  size_t psi[2], hpsi[2], phi[2], hphi[2];          // complex128 states
-  size_t psi32[2], hpsi32[2], phi32[2], hphi32[2];  // complex64 states (mixed only)
-  size_t eps[2], r2[2], ritz[2], tiles;
+  // per state set (species x twist): complex128 states, complex64 copies
+  // (mixed only), Rayleigh quotients, residuals, subspace eigenvalues
+  size_t psi[MAXSET], hpsi[MAXSET], psi32[MAXSET], hpsi32[MAXSET];
+  size_t eps[MAXSET], r2[MAXSET], ritz[MAXSET];
+  // per species, shared by its twists (one set is in flight at a time)
+  size_t phi[2], hphi[2], phi32[2], hphi32[2];
+  size_t tiles, gauge;
   size_t matI, matH, matC, matL, matT, matHp, matZ, matU, wtmp, gemm_part, chol_work, jac_work;
   size_t ref_work, nrm, sq_part;
   // learned preconditioner: parameters (FP32 master, BF16-rounded copy),
@@ -67,12 +80,19 @@ struct Layout {
   size_t total;
 };
 
+int ntwist_of(const sky_box_desc& d) { return std::max(1, d.ntwist); }
+// states per set of species q: its particles plus its extra states
+int states_of(const sky_box_desc& d, int q) {
+  return q ? d.n_protons + d.extra_p : d.n_neutrons + d.extra_n;
+}
+
 Layout plan(const sky_box_desc& d) {
   Layout L{};
   const size_t n3 = size_t(d.n) * d.n * d.n;
   const size_t V = 2 * n3;
-  const int nq[2] = {d.n_neutrons, d.n_protons};
-  const int nmax = std::max(1, std::max(d.n_neutrons, d.n_protons));
+  const int nq[2] = {states_of(d, 0), states_of(d, 1)};
+  const int nset = 2 * ntwist_of(d);
+  const int nmax = std::max(1, std::max(nq[0], nq[1]));
   const size_t c16 = 16;  // bytes per complex128
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -81,21 +101,27 @@ Layout plan(const sky_box_desc& d) {
     return o;
   };
   const bool mixed = d.precision == SKY_MIXED;
+  for (int s = 0; s < nset; ++s) {
+    const int q = s & 1;
+    const size_t sb = size_t(nq[q]) * V * c16;
+    L.psi[s] = take(sb);
+    L.hpsi[s] = take(sb);
+    const size_t sb32 = mixed ? sb / 2 : 0;
+    L.psi32[s] = take(sb32);
+    L.hpsi32[s] = take(sb32);
+    L.eps[s] = take(sizeof(double) * nq[q]);
+    L.r2[s] = take(sizeof(double) * nq[q]);
+    L.ritz[s] = take(sizeof(double) * nq[q]);
+  }
   for (int q = 0; q < 2; ++q) {
     const size_t sb = size_t(nq[q]) * V * c16;
-    L.psi[q] = take(sb);
-    L.hpsi[q] = take(sb);
     L.phi[q] = take(sb);
     L.hphi[q] = take(sb);
     const size_t sb32 = mixed ? sb / 2 : 0;
-    L.psi32[q] = take(sb32);
-    L.hpsi32[q] = take(sb32);
     L.phi32[q] = take(sb32);
     L.hphi32[q] = take(sb32);
-    L.eps[q] = take(sizeof(double) * nq[q]);
-    L.r2[q] = take(sizeof(double) * nq[q]);
-    L.ritz[q] = take(sizeof(double) * nq[q]);
   }
+  L.gauge = take(sizeof(int) * 3 * size_t(nmax));
   const int ntile = grid_ntiles(d.n);
   L.pc_nb = std::min(precond_ns_max(), nmax) * PC_SHELLS;
   L.tiles = take(sizeof(double) * size_t(std::max(nmax, L.pc_nb)) * ntile);
@@ -173,8 +199,20 @@ int validate(const sky_box_desc* d) {
   if (!(d->dx > 0.0)) return fail(SKY_ERR_INVALID, "dx must be positive");
   if (d->n_neutrons < 0 || d->n_protons < 0 || d->n_neutrons + d->n_protons == 0)
     return fail(SKY_ERR_INVALID, "need at least one state");
+  if (d->extra_n < 0 || d->extra_p < 0) return fail(SKY_ERR_INVALID, "negative extra states");
+  if ((d->n_neutrons == 0 && d->extra_n > 0) || (d->n_protons == 0 && d->extra_p > 0))
+    return fail(SKY_ERR_INVALID, "extra states of a species without particles");
+  if (d->ntwist < 0 || d->ntwist > SKY_MAX_TWIST)
+    return fail(SKY_ERR_INVALID, "ntwist must be 0..SKY_MAX_TWIST");
+  for (int t = 0; t < std::max(1, d->ntwist); ++t)
+    for (int m = 0; m < 3; ++m)
+      if (!std::isfinite(d->twist[t][m])) return fail(SKY_ERR_INVALID, "non-finite twist");
+  if (d->update != SKY_UPDATE_EXACT && d->update != SKY_UPDATE_PAPER)
+    return fail(SKY_ERR_INVALID, "update must be SKY_UPDATE_EXACT or SKY_UPDATE_PAPER");
+  if (d->one_h && d->update != SKY_UPDATE_EXACT)
+    return fail(SKY_ERR_INVALID, "one_h needs SKY_UPDATE_EXACT");
   const long V = 2L * d->n * d->n * d->n;
-  if (d->n_neutrons > V || d->n_protons > V) return fail(SKY_ERR_INVALID, "more states than grid points");
+  if (states_of(*d, 0) > V || states_of(*d, 1) > V) return fail(SKY_ERR_INVALID, "more states than grid points");
   if (!(d->damp_e0 > 0.0)) return fail(SKY_ERR_INVALID, "damp_e0 must be positive");
   if (d->precision != SKY_FP64 && d->precision != SKY_MIXED)
     return fail(SKY_ERR_INVALID, "precision must be SKY_FP64 or SKY_MIXED");
@@ -189,12 +227,16 @@ struct sky_ctx {
   hipStream_t st;
   int n, n3;
   long V;
-  int nq[2];
+  int nq[2];           // states per set of species q (particles + extra states)
+  int nocc[2];         // occupied states of species q (the first nocc of each set)
+  int ntw, nset;       // twists; state sets = 2 * twists (set s: species s & 1)
   int prec;            // current: 0 = FP64 states, 1 = mixed (complex64 states)
-  GridArgs g;
+  GridArgs g;          // untwisted grid arguments (fields, tuning)
+  bool hpsi_lagged = false;   // one_h: h psi holds (h phi) U of the last update
   Skyrme sk;
   int last_sweeps;     // eigensolver iterations of the last iteration
   int fallbacks;       // refinement -> Jacobi fallbacks in the current call
+  int unconverged;     // Jacobi solves of the current call stopped at the sweep limit
   // launch shapes (0 = the built-in default): h-pass lines per workgroup,
   // overlap and square-product split-K factors per species
   struct Tune {
@@ -221,12 +263,13 @@ struct sky_ctx {
   int pc_iters = 0;        // iterations of the current call with the learned damping
   // HIP graphs of the launch-only segments of an iteration (per species:
   // A plain / A learned, B; F = fields)
+  // A variants: bit 0 = learned damping, bit 1 = h psi carried over (one_h)
   struct Graphs {
     bool on = false;
     int prec = -1;
     int captures = 0;
-    hipGraphExec_t a[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
-    hipGraphExec_t b[2] = {nullptr, nullptr};
+    hipGraphExec_t a[MAXSET][4] = {};
+    hipGraphExec_t b[MAXSET] = {};
     hipGraphExec_t f = nullptr;
   } graphs;
   int64_t iter_count = 0;     // iterations run on this context
@@ -240,15 +283,26 @@ struct sky_ctx {
   int64_t cnt[SKY_NPHASE][2] = {};
 
   template <typename P = char> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
-  // state buffers of the current precision
-  char* psi(int q) const { return at(prec ? lay.psi32[q] : lay.psi[q]); }
-  char* hpsi(int q) const { return at(prec ? lay.hpsi32[q] : lay.hpsi[q]); }
-  char* phi(int q) const { return at(prec ? lay.phi32[q] : lay.phi[q]); }
-  char* hphi(int q) const { return at(prec ? lay.hphi32[q] : lay.hphi[q]); }
-  MeanFieldPtrs mfp(int q) const {
-    const double* m = at<double>(lay.mf[q]);
+  // state buffers of set s in the current precision (phi, h phi: shared by
+  // the twists of a species)
+  char* psi(int s) const { return at(prec ? lay.psi32[s] : lay.psi[s]); }
+  char* hpsi(int s) const { return at(prec ? lay.hpsi32[s] : lay.hpsi[s]); }
+  char* phi(int s) const { return at(prec ? lay.phi32[s & 1] : lay.phi[s & 1]); }
+  char* hphi(int s) const { return at(prec ? lay.hphi32[s & 1] : lay.hphi[s & 1]); }
+  int m_of(int s) const { return nq[s & 1]; }
+  // mean field of the species of set s (shared by every twist)
+  MeanFieldPtrs mfp(int s) const {
+    const double* m = at<double>(lay.mf[s & 1]);
     return MeanFieldPtrs{m, m + n3, m + 2 * n3};
   }
+  // grid arguments of set s: the Bloch shift theta / L of its twist
+  GridArgs gset(int s) const {
+    GridArgs r = g;
+    const double L = n * d.dx;
+    for (int m = 0; m < 3; ++m) r.tw[m] = d.twist[s >> 1][m] / L;
+    return r;
+  }
+  double hb2m(int s) const { return (s & 1) ? d.hb2m_p : d.hb2m_n; }
 };
 
 namespace {
@@ -303,8 +357,9 @@ int check_info(sky_ctx* c, const char* what) {
 
 // Step 3a of species q: I and H (lower triangles by the GEMMs, then
 // mirrored).  Launches only, so that it can be captured in a graph.
-void subspace_matrices(sky_ctx* c, int q, const void* phi, const void* hphi,
+void subspace_matrices(sky_ctx* c, int s, const void* phi, const void* hphi,
                        bool scales_ready = false) {
+  const int q = s & 1;
   const int m = c->nq[q];
   hipStream_t st = c->st;
   void* I = c->at(c->lay.matI);
@@ -340,11 +395,27 @@ void subspace_matrices(sky_ctx* c, int q, const void* phi, const void* hphi,
   hermitian_fill(H, m, st);
 }
 
-// Steps 3b-3d of species q on the host-driven path: an orthonormalising
+// Steps 3b-3d of set s on the host-driven path: an orthonormalising
 // transform C (C^H I C = 1), H' = C^H H C = Z lam Z^H, U = C Z.  Near the
 // identity (every iteration after the start) C is Loewdin's I^-1/2 from its
 // binomial series; otherwise C = L^-H with the Cholesky factor I = L L^H.
-int subspace_solve(sky_ctx* c, int q, double* ritz) {
+// With the paper-literal update Z and C come from H and I separately and
+// U = Z C (paper_solve).
+int paper_solve(sky_ctx* c, int s, double* ritz);
+
+int jacobi_checked(sky_ctx* c, void* A, int m, double* w, void* Z) {
+  const int its = jacobi_eigh(A, m, w, Z, c->at(c->lay.jac_work), JACOBI_TOL, JACOBI_SWEEPS, c->st);
+  if (its == -2) return fail(SKY_ERR_NAN, "non-finite subspace matrix");
+  if (its < 0) {
+    ++c->unconverged;
+    return JACOBI_SWEEPS;
+  }
+  return its;
+}
+
+int subspace_solve(sky_ctx* c, int s, double* ritz) {
+  if (c->d.update == SKY_UPDATE_PAPER) return paper_solve(c, s, ritz);
+  const int q = s & 1;
   const int m = c->nq[q];
   hipStream_t st = c->st;
   void* I = c->at(c->lay.matI);
@@ -362,12 +433,13 @@ int subspace_solve(sky_ctx* c, int q, double* ritz) {
   const int sqs = c->tune.sq[q];
   const int terms = loewdin_series(I, Linv, Cw, T, m, LOEWDIN_SERIES_MAX,
                                    c->at<double>(c->lay.nrm), sq, st, sqs);
+  if (terms < 0) return fail(SKY_ERR_NAN, "non-finite overlap matrix");
   if (terms > 0) {   // C = I^-1/2 (Hermitian) in Linv
     gemm_square(Linv, 0, H, 0, T, m, st, sq, 0, sqs);
     gemm_square(T, 0, Linv, 0, Hp, m, st, sq, 1, sqs);
   } else {           // Linv = L^-1, C = L^-H
     hipMemcpyAsync(Cw, I, size_t(m) * m * 16, hipMemcpyDeviceToDevice, st);
-    cholesky_inverse(Cw, Linv, m, c->at(c->lay.chol_work), info, st);
+    cholesky_inverse(Cw, Linv, m, c->at(c->lay.chol_work), info, st, CHOL_PIVOT_MIN);
     gemm_square(Linv, 0, H, 0, T, m, st, sq, 0, sqs);
     gemm_square(T, 0, Linv, 1, Hp, m, st, sq, 1, sqs);
   }
@@ -376,12 +448,13 @@ int subspace_solve(sky_ctx* c, int q, double* ritz) {
     int rc = check_info(c, "cholesky");
     if (rc) return rc;
   }
-  double* w = ritz ? ritz : c->at<double>(c->lay.ritz[q]);
+  double* w = ritz ? ritz : c->at<double>(c->lay.ritz[s]);
   int its = refine_eigh(Hp, m, w, Z, c->at(c->lay.ref_work), JACOBI_TOL, REFINE_ITERS, st, sqs,
                         c->prec ? MIXED_HP_NOISE : 0x1p-49);
   if (its < 0) {   // a wide cluster or no convergence: blocked Jacobi from H'
     ++c->fallbacks;
-    its = jacobi_eigh(Hp, m, w, Z, c->at(c->lay.jac_work), JACOBI_TOL, JACOBI_SWEEPS, st);
+    its = jacobi_checked(c, Hp, m, w, Z);
+    if (its < 0) return its;
   }
   c->last_sweeps += its;
   gemm_square(Linv, terms > 0 ? 0 : 1, Z, 0, U, m, st, sq, 0, sqs);
@@ -389,8 +462,165 @@ int subspace_solve(sky_ctx* c, int q, double* ritz) {
   return SKY_OK;
 }
 
-// Step 3e of species q: psi = phi U (launches only).
-void subspace_combine(sky_ctx* c, int q, const void* phi, void* psi_out) {
+// Unitary polar factor P of the k x k complex matrix G (row-major; G = P S
+// with S Hermitian positive semi-definite) by Newton's iteration
+// X <- (X + X^-H) / 2 from X = G (quadratic convergence for a non-singular
+// G).  Returns false when G is numerically singular or the iteration does
+// not settle.
+bool polar_unitary(const std::vector<std::complex<double>>& G, int k,
+                   std::vector<std::complex<double>>& P) {
+  using cd = std::complex<double>;
+  P = G;
+  std::vector<cd> A(size_t(k) * 2 * k);
+  for (int it = 0; it < 60; ++it) {
+    // inverse of X by Gauss-Jordan with partial pivoting on [X | 1]
+    for (int r = 0; r < k; ++r)
+      for (int col = 0; col < 2 * k; ++col)
+        A[size_t(r) * 2 * k + col] = col < k ? P[size_t(r) * k + col] : cd(col - k == r ? 1.0 : 0.0);
+    double scale = 0.0;
+    for (int e = 0; e < k * k; ++e) scale = std::max(scale, std::abs(P[e]));
+    for (int col = 0; col < k; ++col) {
+      int piv = col;
+      for (int r = col + 1; r < k; ++r)
+        if (std::abs(A[size_t(r) * 2 * k + col]) > std::abs(A[size_t(piv) * 2 * k + col])) piv = r;
+      if (!(std::abs(A[size_t(piv) * 2 * k + col]) > 1e-10 * scale)) return false;
+      if (piv != col)
+        for (int e = 0; e < 2 * k; ++e) std::swap(A[size_t(piv) * 2 * k + e], A[size_t(col) * 2 * k + e]);
+      const cd inv = 1.0 / A[size_t(col) * 2 * k + col];
+      for (int e = 0; e < 2 * k; ++e) A[size_t(col) * 2 * k + e] *= inv;
+      for (int r = 0; r < k; ++r) {
+        if (r == col) continue;
+        const cd f = A[size_t(r) * 2 * k + col];
+        if (f == cd(0.0)) continue;
+        for (int e = 0; e < 2 * k; ++e) A[size_t(r) * 2 * k + e] -= f * A[size_t(col) * 2 * k + e];
+      }
+    }
+    // X <- (X + X^-H) / 2
+    double change = 0.0;
+    for (int r = 0; r < k; ++r)
+      for (int col = 0; col < k; ++col) {
+        const cd xinvh = std::conj(A[size_t(col) * 2 * k + k + r]);
+        const cd nx = 0.5 * (P[size_t(r) * k + col] + xinvh);
+        change = std::max(change, std::abs(nx - P[size_t(r) * k + col]));
+        P[size_t(r) * k + col] = nx;
+      }
+    if (change < 1e-15) return true;
+  }
+  return false;
+}
+
+// The paper-literal update of Sec. 3.3.3 for set s: Z from the Hermitian
+// eigenproblem of H alone (3b), C = I^-1/2 from I alone (3c), U = Z C (3d).
+// Z is brought to the gauge closest to the identity: within each cluster of
+// eigenvalues closer than PAPER_CLUSTER_TOL the columns are rotated by
+// Q = P^H, P the unitary polar factor of the cluster's diagonal block (a
+// single state: the phase that makes Z_bb real and positive).
+int paper_solve(sky_ctx* c, int s, double* ritz) {
+  const int q = s & 1;
+  const int m = c->nq[q];
+  hipStream_t st = c->st;
+  void* I = c->at(c->lay.matI);
+  void* H = c->at(c->lay.matH);
+  void* C = c->at(c->lay.matL);
+  void* T = c->at(c->lay.matT);
+  void* X = c->at(c->lay.matHp);
+  void* Z = c->at(c->lay.matZ);
+  void* U = c->at(c->lay.matU);
+  void* Cw = c->at(c->lay.matC);
+  void* sq = c->at(c->lay.sq_part);
+  int* info = c->at<int>(c->lay.info);
+  const int sqs = c->tune.sq[q];
+  const int ts = t_begin(c, SKY_PHASE_SUBSPACE, q);
+  hipMemsetAsync(info, 0, sizeof(int), st);
+  // 3c: C = I^-1/2, by the series near the identity, else by the eigenvectors of I
+  const int terms = loewdin_series(I, C, Cw, T, m, LOEWDIN_SERIES_MAX,
+                                   c->at<double>(c->lay.nrm), sq, st, sqs);
+  if (terms < 0) return fail(SKY_ERR_NAN, "non-finite overlap matrix");
+  if (terms == 0) {
+    double* wi = c->at<double>(c->lay.wtmp);
+    hipMemcpyAsync(Cw, I, size_t(m) * m * 16, hipMemcpyDeviceToDevice, st);
+    int rc = jacobi_checked(c, Cw, m, wi, X);
+    if (rc < 0) return rc;
+    hipMemcpyAsync(T, X, size_t(m) * m * 16, hipMemcpyDeviceToDevice, st);
+    inv_sqrt(wi, m, info, st, CHOL_PIVOT_MIN);
+    scale_columns(T, wi, m, st);
+    gemm_square(T, 0, X, 1, C, m, st, sq, 1, sqs);
+    rc = check_info(c, "paper update: overlap");
+    if (rc) return rc;
+  }
+  // 3b: H Z = Z lam (ascending)
+  double* w = ritz ? ritz : c->at<double>(c->lay.ritz[s]);
+  int its = refine_eigh(H, m, w, Z, c->at(c->lay.ref_work), JACOBI_TOL, REFINE_ITERS, st, sqs,
+                        c->prec ? MIXED_HP_NOISE : 0x1p-49);
+  if (its < 0) {
+    ++c->fallbacks;
+    hipMemcpyAsync(X, H, size_t(m) * m * 16, hipMemcpyDeviceToDevice, st);
+    its = jacobi_checked(c, X, m, w, Z);
+    if (its < 0) return its;
+  }
+  c->last_sweeps += its;
+  // gauge of Z: clusters from the eigenvalues, diagonal blocks to the host
+  std::vector<double> lam(m);
+  int rc = hip_check(hipMemcpyAsync(lam.data(), w, sizeof(double) * m, hipMemcpyDeviceToHost, st),
+                     "eigenvalue copy");
+  if (rc) return rc;
+  rc = hip_check(hipStreamSynchronize(st), "paper update");
+  if (rc) return rc;
+  std::vector<int> info3(size_t(3) * m);   // per column: cluster start, size, block offset
+  size_t packed = 0;
+  for (int a = 0; a < m;) {
+    int b = a + 1;
+    while (b < m && lam[b] - lam[b - 1] < PAPER_CLUSTER_TOL) ++b;
+    for (int col = a; col < b; ++col) {
+      info3[3 * col] = a;
+      info3[3 * col + 1] = b - a;
+      info3[3 * col + 2] = int(packed);
+    }
+    packed += size_t(b - a) * (b - a);
+    a = b;
+  }
+  int* dinfo = c->at<int>(c->lay.gauge);
+  hipMemcpyAsync(dinfo, info3.data(), sizeof(int) * info3.size(), hipMemcpyHostToDevice, st);
+  gauge_gather(Z, m, dinfo, T, st);
+  std::vector<std::complex<double>> blocks(packed);
+  rc = hip_check(hipMemcpyAsync(blocks.data(), T, packed * 16, hipMemcpyDeviceToHost, st),
+                 "gauge block copy");
+  if (rc) return rc;
+  rc = hip_check(hipStreamSynchronize(st), "paper update");
+  if (rc) return rc;
+  std::vector<std::complex<double>> G, P;
+  for (int a = 0; a < m;) {
+    const int k = info3[3 * a + 1];
+    const size_t off = size_t(info3[3 * a + 2]);
+    G.assign(blocks.begin() + off, blocks.begin() + off + size_t(k) * k);
+    if (polar_unitary(G, k, P)) {
+      for (int r = 0; r < k; ++r)   // Q = P^H
+        for (int col = 0; col < k; ++col) blocks[off + size_t(r) * k + col] = std::conj(P[size_t(col) * k + r]);
+    } else {                        // singular block: phases only
+      for (int r = 0; r < k; ++r)
+        for (int col = 0; col < k; ++col) {
+          const std::complex<double> z = G[size_t(col) * k + col];
+          blocks[off + size_t(r) * k + col] =
+              r == col ? (std::abs(z) > 0.0 ? std::conj(z) / std::abs(z) : 1.0) : 0.0;
+        }
+    }
+    a += k;
+  }
+  hipMemcpyAsync(T, blocks.data(), packed * 16, hipMemcpyHostToDevice, st);
+  gauge_apply(Z, m, dinfo, T, X, st);     // X = Z Q (block-diagonal Q)
+  // 3d: U = Z C
+  gemm_square(X, 0, C, 0, U, m, st, sq, 0, sqs);
+  rc = hip_check(hipStreamSynchronize(st), "paper update");   // host blocks leave scope
+  if (rc) return rc;
+  t_end(c, ts);
+  return SKY_OK;
+}
+
+// Step 3e of set s: psi = phi U (launches only).  With one_h the h phi of
+// the update is carried along: h psi = (h phi) U.
+void subspace_combine(sky_ctx* c, int s, const void* phi, void* psi_out,
+                      const void* hphi = nullptr, void* hpsi_out = nullptr) {
+  const int q = s & 1;
   const int m = c->nq[q];
   hipStream_t st = c->st;
   void* U = c->at(c->lay.matU);
@@ -400,31 +630,37 @@ void subspace_combine(sky_ctx* c, int q, const void* phi, void* psi_out) {
     plane_scale(U, 1, size_t(m) * m, mx + 2, st);
     split_planes_t(U, 1, m, m, mx + 2, c->at(c->lay.plU), st);
     combine_planes(c->at(c->lay.plU), c->at(c->lay.plT), mx + 2, mx, psi_out, m, c->V, st);
+    if (hphi) {   // the planes of (h phi)^T replace those of phi^T
+      split_planes_t(hphi, 0, m, c->V, mx + 1, c->at(c->lay.plT), st);
+      combine_planes(c->at(c->lay.plU), c->at(c->lay.plT), mx + 2, mx + 1, hpsi_out, m, c->V, st);
+    }
   } else {
     combine(phi, U, psi_out, m, c->V, st);
+    if (hphi) combine(hphi, U, hpsi_out, m, c->V, st);
   }
   t_end(c, tc);
 }
 
-// Generalised Rayleigh-Ritz on phi/hphi of species q -> psi_out (Sec. 3.3).
-int rayleigh_ritz(sky_ctx* c, int q, const void* phi, const void* hphi, void* psi_out,
+// Generalised Rayleigh-Ritz on phi/hphi of set s -> psi_out (Sec. 3.3).
+int rayleigh_ritz(sky_ctx* c, int s, const void* phi, const void* hphi, void* psi_out,
                   double* ritz) {
-  if (c->nq[q] == 0) return SKY_OK;
-  subspace_matrices(c, q, phi, hphi);
-  int rc = subspace_solve(c, q, ritz);
+  if (c->m_of(s) == 0) return SKY_OK;
+  subspace_matrices(c, s, phi, hphi);
+  int rc = subspace_solve(c, s, ritz);
   if (rc) return rc;
-  subspace_combine(c, q, phi, psi_out);
+  subspace_combine(c, s, phi, psi_out);
   return SKY_OK;
 }
 
-int loewdin(sky_ctx* c, int q, const void* phi, void* psi_out) {
+int loewdin(sky_ctx* c, int s, const void* phi, void* psi_out) {
+  const int q = s & 1;
   const int m = c->nq[q];
   if (m == 0) return SKY_OK;
   hipStream_t st = c->st;
   void* I = c->at(c->lay.matI);
   void* X = c->at(c->lay.matZ);
   void* C = c->at(c->lay.matU);
-  double* w = c->at<double>(c->lay.ritz[q]);
+  double* w = c->at<double>(c->lay.ritz[s]);
   int* info = c->at<int>(c->lay.info);
   hipMemsetAsync(info, 0, sizeof(int), st);
   unsigned int* mx = c->at<unsigned int>(c->lay.plS);
@@ -439,12 +675,13 @@ int loewdin(sky_ctx* c, int q, const void* phi, void* psi_out) {
     overlap_lower(phi, phi, nullptr, m, c->V, c->g.dV, I, nullptr, c->at(c->lay.gemm_part), st,
                   nullptr, c->tune.ovl[q]);
   hermitian_fill(I, m, st);
-  jacobi_eigh(I, m, w, X, c->at(c->lay.jac_work), JACOBI_TOL, JACOBI_SWEEPS, st);
+  int its = jacobi_checked(c, I, m, w, X);
+  if (its < 0) return its;
   // C = X diag(w^-1/2) X^H
   double* wi = c->at<double>(c->lay.wtmp);
   hipMemcpyAsync(c->at(c->lay.matT), X, size_t(m) * m * 16, hipMemcpyDeviceToDevice, st);
   hipMemcpyAsync(wi, w, sizeof(double) * m, hipMemcpyDeviceToDevice, st);
-  inv_sqrt(wi, m, info, st);
+  inv_sqrt(wi, m, info, st, CHOL_PIVOT_MIN);
   scale_columns(c->at(c->lay.matT), wi, m, st);
   gemm_square(c->at(c->lay.matT), 0, X, 1, C, m, st, c->at(c->lay.sq_part), 1, c->tune.sq[q]);
   int rc = check_info(c, "loewdin");
@@ -459,11 +696,19 @@ int loewdin(sky_ctx* c, int q, const void* phi, void* psi_out) {
   return SKY_OK;
 }
 
+// Fig. 1 steps 4a, 4b, 5: densities of the occupied states of every set,
+// averaged over the twists, then mean field, Coulomb and energy.
 void fields(sky_ctx* c) {
   hipStream_t st = c->st;
+  const void* ps[SKY_MAX_TWIST];
+  GridArgs gs[SKY_MAX_TWIST];
   for (int q = 0; q < 2; ++q) {
     const int td = t_begin(c, SKY_PHASE_DENSITIES, q);
-    sky::densities(c->n, c->prec, c->psi(q), c->nq[q], DENS_CHUNKS, c->g,
+    for (int t = 0; t < c->ntw; ++t) {
+      ps[t] = c->psi(2 * t + q);
+      gs[t] = c->gset(2 * t + q);
+    }
+    sky::densities(c->n, c->prec, ps, gs, c->ntw, c->nocc[q], DENS_CHUNKS,
                    c->at<double>(c->lay.dens_part), c->at<double>(c->lay.dens[q]), st);
     t_end(c, td);
   }
@@ -480,30 +725,32 @@ double kmax_of(const sky_ctx* c) { return std::sqrt(3.0) * (c->n / 2) * c->g.kun
 
 // Damped step with the learned per-shell gains: forward passes and shell
 // powers, MLP inference of the gains, then the gained filter and inverses.
-void learned_damp(sky_ctx* c, int q, const void* psi, const void* hpsi, const double* eps,
+void learned_damp(sky_ctx* c, int s, const void* psi, const void* hpsi, const double* eps,
                   void* phi, int m, double* r2, hipStream_t st, unsigned int* amax = nullptr) {
-  const double hb = q ? c->d.hb2m_p : c->d.hb2m_n;
+  const double hb = c->hb2m(s);
+  const GridArgs gs = c->gset(s);
   double* pw = c->at<double>(c->lay.pc_pow);
   zero(pw, size_t(m) * PC_SHELLS, st);
-  damped_step(c->n, c->prec, psi, hpsi, eps, phi, m, c->g, c->d.damp_x0, c->d.damp_e0, hb,
+  damped_step(c->n, c->prec, psi, hpsi, eps, phi, m, gs, c->d.damp_x0, c->d.damp_e0, hb,
               c->at<double>(c->lay.tiles), r2, st, nullptr, pw, 1, c->tune.damp_xy);
   float* X = c->at<float>(c->lay.pc_X);
   precond_features(pw, eps, 1, m, c->d.damp_e0, hb, kmax_of(c), X, st);
   precond_forward(c->at<float>(c->lay.pc_Pb), X, m * PC_SHELLS, nullptr, nullptr, nullptr,
                   c->at<float>(c->lay.pc_O), st);
   precond_gains(c->at<float>(c->lay.pc_O), m * PC_SHELLS, c->at<float>(c->lay.pc_gain), st);
-  damped_step(c->n, c->prec, psi, hpsi, eps, phi, m, c->g, c->d.damp_x0, c->d.damp_e0, hb,
+  damped_step(c->n, c->prec, psi, hpsi, eps, phi, m, gs, c->d.damp_x0, c->d.damp_e0, hb,
               nullptr, nullptr, st, c->at<float>(c->lay.pc_gain), nullptr, 2, c->tune.damp_xy,
               amax);
 }
 
-// Training rows from the current states of species q: the shell powers and
+// Training rows from the current states of set s: the shell powers and
 // features of up to NS_MAX evenly spaced states, their one-shell damped
 // directions d_s, h d_s and the target gains.  Rows go to a ring of PC_CAP
 // rows (a collection that does not fit at the end starts again at row 0).
-int pc_collect(sky_ctx* c, int q) {
+int pc_collect(sky_ctx* c, int s) {
   hipStream_t st = c->st;
-  const int m = c->nq[q];
+  const int m = c->m_of(s);
+  const GridArgs gs = c->gset(s);
   const int ns = std::min(precond_ns_max(), m);
   if (ns <= 0) return SKY_OK;
   const int nb = ns * PC_SHELLS;
@@ -512,9 +759,10 @@ int pc_collect(sky_ctx* c, int q) {
   for (int a = 0; a < ns; ++a) idx[a] = int((long(a) * m) / ns);
   int* didx = c->at<int>(c->lay.pc_idx);
   hipMemcpyAsync(didx, idx.data(), sizeof(int) * ns, hipMemcpyHostToDevice, st);
-  double* eps = c->at<double>(c->lay.eps[q]);
+  double* eps = c->at<double>(c->lay.eps[s]);
   double* tiles = c->at<double>(c->lay.tiles);
-  apply_h(c->n, c->prec, c->psi(q), c->hpsi(q), m, c->mfp(q), c->g, tiles, eps, st,
+  c->hpsi_lagged = false;   // h psi is rebuilt with the current mean field here
+  apply_h(c->n, c->prec, c->psi(s), c->hpsi(s), m, c->mfp(s), gs, tiles, eps, st,
           c->tune.lines);
   void* b0 = c->at(c->lay.pc_b[0]);   // psi copies
   void* b1 = c->at(c->lay.pc_b[1]);   // h psi copies
@@ -523,15 +771,15 @@ int pc_collect(sky_ctx* c, int q) {
   double* beps = c->at<double>(c->lay.pc_beps);
   float* onehot = c->at<float>(c->lay.pc_gain);
   double* pw = c->at<double>(c->lay.pc_pow);
-  precond_gather(c->prec, c->psi(q), c->hpsi(q), eps, didx, ns, c->V, b0, b1, beps, onehot, st);
+  precond_gather(c->prec, c->psi(s), c->hpsi(s), eps, didx, ns, c->V, b0, b1, beps, onehot, st);
   zero(pw, size_t(nb) * PC_SHELLS, st);
-  const double hb = q ? c->d.hb2m_p : c->d.hb2m_n;
-  damped_step(c->n, c->prec, b0, b1, beps, b2, nb, c->g, c->d.damp_x0, c->d.damp_e0, hb, tiles,
+  const double hb = c->hb2m(s);
+  damped_step(c->n, c->prec, b0, b1, beps, b2, nb, gs, c->d.damp_x0, c->d.damp_e0, hb, tiles,
               nullptr, st, onehot, pw, 0, c->tune.damp_xy);
   float* rows = c->at<float>(c->lay.pc_S) + size_t(c->pc_wr) * 6;
   precond_features(pw, beps, PC_SHELLS, ns, c->d.damp_e0, hb, kmax_of(c), rows, st);
   precond_dir(c->prec, b0, b2, size_t(nb) * c->V, st);
-  apply_h(c->n, c->prec, b2, b3, nb, c->mfp(q), c->g, nullptr, nullptr, st, c->tune.lines);
+  apply_h(c->n, c->prec, b2, b3, nb, c->mfp(s), gs, nullptr, nullptr, st, c->tune.lines);
   precond_targets(c->prec, b0, b1, b2, b3, beps, ns, c->V, c->at<double>(c->lay.pc_gram), rows,
                   st);
   int rc = hip_check(hipStreamSynchronize(st), "precond_collect");
@@ -576,45 +824,51 @@ double pc_train(sky_ctx* c, int steps, double lr) {
   return l;
 }
 
-// Step 2 and step 3a of species q: h psi and <h>, the damped step (plain or
-// learned), h phi, then I and H.  Launches only.
-void step_a(sky_ctx* c, int q, bool learned) {
+// Step 2 and step 3a of set s: h psi and <h> (or, with one_h after an
+// update, the h psi carried over and <h> = the subspace eigenvalues), the
+// damped step (plain or learned), h phi, then I and H.  Launches only.
+void step_a(sky_ctx* c, int s, bool learned, bool lagged) {
+  const int q = s & 1;
   const int m = c->nq[q];
   hipStream_t st = c->st;
-  void* psi = c->psi(q);
-  void* hpsi = c->hpsi(q);
-  void* phi = c->phi(q);
-  void* hphi = c->hphi(q);
-  double* eps = c->at<double>(c->lay.eps[q]);
+  void* psi = c->psi(s);
+  void* hpsi = c->hpsi(s);
+  void* phi = c->phi(s);
+  void* hphi = c->hphi(s);
+  const GridArgs gs = c->gset(s);
+  double* eps = c->at<double>(c->lay.eps[s]);
   double* tiles = c->at<double>(c->lay.tiles);
   // mixed: the largest |component| of phi and h phi (split-plane scales) is
   // merged by the kernels that write them
   unsigned int* mx = c->prec ? c->at<unsigned int>(c->lay.plS) : nullptr;
   if (mx) clear_scales(mx, 2, st);
-  int t0 = t_begin(c, SKY_PHASE_APPLY_H, q);
-  apply_h(c->n, c->prec, psi, hpsi, m, c->mfp(q), c->g, tiles, eps, st, c->tune.lines);
-  t_end(c, t0);
-  const double hb = q ? c->d.hb2m_p : c->d.hb2m_n;
+  if (lagged) {
+    hipMemcpyAsync(eps, c->at(c->lay.ritz[s]), sizeof(double) * m, hipMemcpyDeviceToDevice, st);
+  } else {
+    int t0 = t_begin(c, SKY_PHASE_APPLY_H, q);
+    apply_h(c->n, c->prec, psi, hpsi, m, c->mfp(s), gs, tiles, eps, st, c->tune.lines);
+    t_end(c, t0);
+  }
+  const double hb = c->hb2m(s);
   int t1 = t_begin(c, SKY_PHASE_DAMP, q);
   if (learned)
-    learned_damp(c, q, psi, hpsi, eps, phi, m, c->at<double>(c->lay.r2[q]), st, mx);
+    learned_damp(c, s, psi, hpsi, eps, phi, m, c->at<double>(c->lay.r2[s]), st, mx);
   else
-    damped_step(c->n, c->prec, psi, hpsi, eps, phi, m, c->g, c->d.damp_x0, c->d.damp_e0, hb,
-                tiles, c->at<double>(c->lay.r2[q]), st, nullptr, nullptr, 0, c->tune.damp_xy, mx);
+    damped_step(c->n, c->prec, psi, hpsi, eps, phi, m, gs, c->d.damp_x0, c->d.damp_e0, hb,
+                tiles, c->at<double>(c->lay.r2[s]), st, nullptr, nullptr, 0, c->tune.damp_xy, mx);
   t_end(c, t1);
   int t2 = t_begin(c, SKY_PHASE_APPLY_H, q);
-  apply_h(c->n, c->prec, phi, hphi, m, c->mfp(q), c->g, nullptr, nullptr, st, c->tune.lines,
+  apply_h(c->n, c->prec, phi, hphi, m, c->mfp(s), gs, nullptr, nullptr, st, c->tune.lines,
           mx ? mx + 1 : nullptr);
   t_end(c, t2);
-  subspace_matrices(c, q, phi, hphi, mx != nullptr);
+  subspace_matrices(c, s, phi, hphi, mx != nullptr);
 }
 
 void graphs_clear(sky_ctx* c) {
   auto drop = [](hipGraphExec_t& g) { if (g) { hipGraphExecDestroy(g); g = nullptr; } };
-  for (int q = 0; q < 2; ++q) {
-    drop(c->graphs.a[q][0]);
-    drop(c->graphs.a[q][1]);
-    drop(c->graphs.b[q]);
+  for (int s = 0; s < MAXSET; ++s) {
+    for (int v = 0; v < 4; ++v) drop(c->graphs.a[s][v]);
+    drop(c->graphs.b[s]);
   }
   drop(c->graphs.f);
 }
@@ -765,12 +1019,17 @@ int sky_create(const sky_box_desc* d, void* workspace, size_t bytes, void* strea
   c->n = d->n;
   c->n3 = d->n * d->n * d->n;
   c->V = 2L * c->n3;
-  c->nq[0] = d->n_neutrons;
-  c->nq[1] = d->n_protons;
+  c->nq[0] = states_of(*d, 0);
+  c->nq[1] = states_of(*d, 1);
+  c->nocc[0] = d->n_neutrons;
+  c->nocc[1] = d->n_protons;
+  c->ntw = ntwist_of(*d);
+  c->nset = 2 * c->ntw;
   c->prec = d->precision == SKY_MIXED ? 1 : 0;
   c->g.dx = d->dx;
   c->g.dV = d->dx * d->dx * d->dx;
   c->g.kunit = 2.0 * M_PI / (d->n * d->dx);
+  c->g.tw[0] = c->g.tw[1] = c->g.tw[2] = 0.0;
   const double t0 = d->t0, t1 = d->t1, t2 = d->t2, t3 = d->t3;
   const double x0 = d->x0, x1 = d->x1, x2 = d->x2, x3 = d->x3;
   // b-coefficients of the Skyrme functional (standard t/x -> b mapping)
@@ -789,6 +1048,8 @@ int sky_create(const sky_box_desc* d, void* workspace, size_t bytes, void* strea
   c->sk.hb2m_p = d->hb2m_p;
   c->sk.e2 = d->e2;
   c->last_sweeps = 0;
+  c->fallbacks = 0;
+  c->unconverged = 0;
   *out = c;
   return SKY_OK;
 }
@@ -811,39 +1072,47 @@ int sky_init_box(sky_ctx* c, const void* raw_n, const void* raw_p) {
     if (!raw[q]) return fail(SKY_ERR_INVALID, "null trial states");
     int rc = loewdin(c, q, raw[q], c->at(c->lay.psi[q]));
     if (rc) return rc;
+    const size_t ne = size_t(c->nq[q]) * c->V;
+    for (int t = 1; t < c->ntw; ++t)   // every twist starts from the same states
+      hipMemcpyAsync(c->at(c->lay.psi[2 * t + q]), c->at(c->lay.psi[q]), ne * 16,
+                     hipMemcpyDeviceToDevice, c->st);
     if (prec)
-      convert_states(c->at(c->lay.psi[q]), 0, c->at(c->lay.psi32[q]), 1,
-                     size_t(c->nq[q]) * c->V, c->st);
+      for (int t = 0; t < c->ntw; ++t)
+        convert_states(c->at(c->lay.psi[2 * t + q]), 0, c->at(c->lay.psi32[2 * t + q]), 1, ne,
+                       c->st);
   }
   c->prec = prec;
+  c->hpsi_lagged = false;
   fields(c);
   return hip_check(hipStreamSynchronize(c->st), "init");
 }
 
 int sky_apply_h(sky_ctx* c, int32_t q, const void* psi, void* hpsi, int32_t nstates,
                 double* eps) {
-  if (!c || q < 0 || q > 1 || !psi || !hpsi || nstates < 0) return fail(SKY_ERR_INVALID, "apply_h arguments");
-  if (nstates > c->nq[q]) return fail(SKY_ERR_INVALID, "apply_h: more states than the species holds");
-  apply_h(c->n, c->prec, psi, hpsi, nstates, c->mfp(q), c->g,
+  if (!c || q < 0 || q >= c->nset || !psi || !hpsi || nstates < 0)
+    return fail(SKY_ERR_INVALID, "apply_h arguments");
+  if (nstates > c->m_of(q)) return fail(SKY_ERR_INVALID, "apply_h: more states than the set holds");
+  apply_h(c->n, c->prec, psi, hpsi, nstates, c->mfp(q), c->gset(q),
           eps ? c->at<double>(c->lay.tiles) : nullptr, eps, c->st, c->tune.lines);
   return hip_check(hipGetLastError(), "apply_h launch");
 }
 
 int sky_damped_step(sky_ctx* c, int32_t q, const void* psi, const void* hpsi, const double* eps,
                     void* phi, int32_t nstates, double* r2) {
-  if (!c || q < 0 || q > 1 || !psi || !hpsi || !eps || !phi || nstates < 0)
+  if (!c || q < 0 || q >= c->nset || !psi || !hpsi || !eps || !phi || nstates < 0)
     return fail(SKY_ERR_INVALID, "damped_step arguments");
-  if (nstates > c->nq[q]) return fail(SKY_ERR_INVALID, "damped_step: more states than the species holds");
+  if (nstates > c->m_of(q)) return fail(SKY_ERR_INVALID, "damped_step: more states than the set holds");
   double* r2o = r2 ? r2 : c->at<double>(c->lay.r2[q]);
-  const double hb = q ? c->d.hb2m_p : c->d.hb2m_n;
-  damped_step(c->n, c->prec, psi, hpsi, eps, phi, nstates, c->g, c->d.damp_x0, c->d.damp_e0,
-              hb, c->at<double>(c->lay.tiles), r2o, c->st, nullptr, nullptr, 0, c->tune.damp_xy);
+  damped_step(c->n, c->prec, psi, hpsi, eps, phi, nstates, c->gset(q), c->d.damp_x0,
+              c->d.damp_e0, c->hb2m(q), c->at<double>(c->lay.tiles), r2o, c->st, nullptr, nullptr,
+              0, c->tune.damp_xy);
   return hip_check(hipGetLastError(), "damped_step launch");
 }
 
 int sky_orthonormalize(sky_ctx* c, int32_t q, const void* phi, const void* hphi, void* psi_out,
                        double* ritz) {
-  if (!c || q < 0 || q > 1 || !phi || !psi_out) return fail(SKY_ERR_INVALID, "orthonormalize arguments");
+  if (!c || q < 0 || q >= c->nset || !phi || !psi_out)
+    return fail(SKY_ERR_INVALID, "orthonormalize arguments");
   c->last_sweeps = 0;
   int rc = hphi ? rayleigh_ritz(c, q, phi, hphi, psi_out, ritz) : loewdin(c, q, phi, psi_out);
   if (rc) return rc;
@@ -863,38 +1132,52 @@ int sky_iterate(sky_ctx* c, int32_t max_iter, double tol, sky_report* rep) {
   double de = 0.0;
   int it = 0, status = SKY_OK;
   c->fallbacks = 0;
+  c->unconverged = 0;
   c->pc_iters = 0;
+  const bool one_h = c->d.one_h != 0;
   for (; it < max_iter; ++it) {
     c->last_sweeps = 0;
     const bool learned = c->pc_on && c->pc_trained && c->pc_hold == 0;
-    for (int q = 0; q < 2; ++q) {
-      if (c->nq[q] == 0) continue;
+    const bool lagged = one_h && c->hpsi_lagged;
+    const int variant = (learned ? 1 : 0) | (lagged ? 2 : 0);
+    for (int s = 0; s < c->nset; ++s) {
+      if (c->m_of(s) == 0) continue;
       // step 2 and step 3a (graph segment A), steps 3b-3d on the host path,
       // step 3e (segment B)
-      int rc = run_segment(c, c->graphs.a[q][learned ? 1 : 0], [&] { step_a(c, q, learned); });
+      int rc = run_segment(c, c->graphs.a[s][variant], [&] { step_a(c, s, learned, lagged); });
       if (rc) return rc;
-      rc = subspace_solve(c, q, c->at<double>(c->lay.ritz[q]));
+      rc = subspace_solve(c, s, c->at<double>(c->lay.ritz[s]));
       if (rc) return rc;
-      rc = run_segment(c, c->graphs.b[q], [&] { subspace_combine(c, q, c->phi(q), c->psi(q)); });
+      rc = run_segment(c, c->graphs.b[s], [&] {
+        if (one_h)
+          subspace_combine(c, s, c->phi(s), c->psi(s), c->hphi(s), c->hpsi(s));
+        else
+          subspace_combine(c, s, c->phi(s), c->psi(s));
+      });
       if (rc) return rc;
     }
+    c->hpsi_lagged = one_h;
     // steps 4a, 4b, 5
     int rcf = run_segment(c, c->graphs.f, [&] { fields(c); });
     if (rcf) return rcf;
-    // Delta-eps of the states that entered this iteration (Eq. convergence)
-    r2h.resize(size_t(c->nq[0]) + c->nq[1]);
-    for (int q = 0; q < 2; ++q) {
-      if (c->nq[q] == 0) continue;
-      int rc = hip_check(hipMemcpyAsync(r2h.data() + (q ? c->nq[0] : 0), c->at(c->lay.r2[q]),
-                                        sizeof(double) * c->nq[q], hipMemcpyDeviceToHost, st),
+    // Delta-eps of the occupied states that entered this iteration (Eq. convergence)
+    r2h.resize(size_t(c->nset) * std::max(c->nq[0], c->nq[1]));
+    for (int s = 0; s < c->nset; ++s) {
+      const int occ = c->nocc[s & 1];
+      if (occ == 0) continue;
+      int rc = hip_check(hipMemcpyAsync(r2h.data() + size_t(s) * std::max(c->nq[0], c->nq[1]),
+                                        c->at(c->lay.r2[s]), sizeof(double) * occ,
+                                        hipMemcpyDeviceToHost, st),
                          "r2 copy");
       if (rc) return rc;
     }
     int rcs = hip_check(hipStreamSynchronize(st), "iterate");
     if (rcs) return rcs;
     double sum = 0.0;
-    for (double v : r2h) sum += v;
-    const int cnt = c->nq[0] + c->nq[1];
+    for (int s = 0; s < c->nset; ++s)
+      for (int a = 0; a < c->nocc[s & 1]; ++a)
+        sum += r2h[size_t(s) * std::max(c->nq[0], c->nq[1]) + a];
+    const int cnt = c->ntw * (c->nocc[0] + c->nocc[1]);
     t_flush(c);
     de = std::sqrt(sum / std::max(1, cnt));
     if (!std::isfinite(de)) return fail(SKY_ERR_NAN, "non-finite residual");
@@ -906,10 +1189,12 @@ int sky_iterate(sky_ctx* c, int32_t max_iter, double tol, sky_report* rep) {
     c->pc_last = learned;
     c->pc_iters += learned ? 1 : 0;
     c->de_prev = de;
-    // online training: fresh rows from both species, then a few Adam steps
+    // online training: fresh rows from both species (first twist), then a
+    // few Adam steps
     if (c->pc_on && c->pc_every > 0 && ++c->pc_since >= c->pc_every) {
       c->pc_since = 0;
       for (int q = 0; q < 2; ++q) {
+        if (c->nq[q] == 0) continue;
         int rc = pc_collect(c, q);
         if (rc) return rc;
       }
@@ -917,10 +1202,11 @@ int sky_iterate(sky_ctx* c, int32_t max_iter, double tol, sky_report* rep) {
     }
     // precision ladder: finish in FP64 once the mixed form has done its part
     if (c->prec == 1 && c->d.ladder_tol > 0.0 && de <= c->d.ladder_tol) {
-      for (int q = 0; q < 2; ++q)
-        convert_states(c->at(c->lay.psi32[q]), 1, c->at(c->lay.psi[q]), 0,
-                       size_t(c->nq[q]) * c->V, st);
+      for (int s = 0; s < c->nset; ++s)
+        convert_states(c->at(c->lay.psi32[s]), 1, c->at(c->lay.psi[s]), 0,
+                       size_t(c->m_of(s)) * c->V, st);
       c->prec = 0;
+      c->hpsi_lagged = false;
       // launch shapes were tuned for the mixed kernels: FP64 defaults from here
       c->tune.lines = 0;
       c->tune.damp_xy = -1;
@@ -944,40 +1230,73 @@ int sky_iterate(sky_ctx* c, int32_t max_iter, double tol, sky_report* rep) {
     rep->iters = it;
     rep->residual = de;
     rep->energy = e[7];
-    rep->energy_per_a = e[7] / double(c->nq[0] + c->nq[1]);
+    rep->energy_per_a = e[7] / double(std::max(1, c->nocc[0] + c->nocc[1]));
     rep->eig_iters = c->last_sweeps;
     rep->eig_fallbacks = c->fallbacks;
     rep->precond_iters = c->pc_iters;
+    rep->eig_unconverged = c->unconverged;
   }
   return status;
 }
 
 int sky_get_view(sky_ctx* c, int32_t what, int32_t q, void** ptr, int64_t* count) {
   if (!c || !ptr || !count) return fail(SKY_ERR_INVALID, "get_view arguments");
-  if (q < 0 || q > 1) return fail(SKY_ERR_INVALID, "species must be 0 or 1");
-  const int64_t st = int64_t(c->nq[q]) * c->V;
+  if (q < 0 || q >= c->nset) return fail(SKY_ERR_INVALID, "set index out of range");
+  const int m = c->m_of(q);
+  const int64_t st = int64_t(m) * c->V;
   switch (what) {
     case SKY_VIEW_PSI: *ptr = c->psi(q); *count = st; break;
     case SKY_VIEW_HPSI: *ptr = c->hpsi(q); *count = st; break;
     case SKY_VIEW_PHI: *ptr = c->phi(q); *count = st; break;
     case SKY_VIEW_HPHI: *ptr = c->hphi(q); *count = st; break;
-    case SKY_VIEW_DENS: *ptr = c->at(c->lay.dens[q]); *count = 11LL * c->n3; break;
-    case SKY_VIEW_MEANFIELD: *ptr = c->at(c->lay.mf[q]); *count = 5LL * c->n3; break;
+    case SKY_VIEW_DENS: *ptr = c->at(c->lay.dens[q & 1]); *count = 11LL * c->n3; break;
+    case SKY_VIEW_MEANFIELD: *ptr = c->at(c->lay.mf[q & 1]); *count = 5LL * c->n3; break;
     case SKY_VIEW_COULOMB: *ptr = c->at(c->lay.vc); *count = c->n3; break;
     case SKY_VIEW_ENERGY: *ptr = c->at(c->lay.energy); *count = 8; break;
-    case SKY_VIEW_EPS: *ptr = c->at(c->lay.eps[q]); *count = c->nq[q]; break;
-    case SKY_VIEW_RITZ: *ptr = c->at(c->lay.ritz[q]); *count = c->nq[q]; break;
-    case SKY_VIEW_R2: *ptr = c->at(c->lay.r2[q]); *count = c->nq[q]; break;
-    case SKY_VIEW_OVERLAP: *ptr = c->at(c->lay.matI); *count = int64_t(c->nq[q]) * c->nq[q]; break;
-    case SKY_VIEW_HSUB: *ptr = c->at(c->lay.matH); *count = int64_t(c->nq[q]) * c->nq[q]; break;
-    case SKY_VIEW_EVEC: *ptr = c->at(c->lay.matZ); *count = int64_t(c->nq[q]) * c->nq[q]; break;
-    case SKY_VIEW_UMAT: *ptr = c->at(c->lay.matU); *count = int64_t(c->nq[q]) * c->nq[q]; break;
+    case SKY_VIEW_EPS: *ptr = c->at(c->lay.eps[q]); *count = m; break;
+    case SKY_VIEW_RITZ: *ptr = c->at(c->lay.ritz[q]); *count = m; break;
+    case SKY_VIEW_R2: *ptr = c->at(c->lay.r2[q]); *count = m; break;
+    case SKY_VIEW_OVERLAP: *ptr = c->at(c->lay.matI); *count = int64_t(m) * m; break;
+    case SKY_VIEW_HSUB: *ptr = c->at(c->lay.matH); *count = int64_t(m) * m; break;
+    case SKY_VIEW_EVEC: *ptr = c->at(c->lay.matZ); *count = int64_t(m) * m; break;
+    case SKY_VIEW_UMAT: *ptr = c->at(c->lay.matU); *count = int64_t(m) * m; break;
     case SKY_VIEW_PC_PARAMS: *ptr = c->at(c->lay.pc_P); *count = precond_nparams(); break;
     case SKY_VIEW_PC_GRAD: *ptr = c->at(c->lay.pc_G); *count = precond_nparams(); break;
     case SKY_VIEW_PC_SAMPLES: *ptr = c->at(c->lay.pc_S); *count = 6LL * PC_CAP; break;
-    case SKY_VIEW_PC_GAINS: *ptr = c->at(c->lay.pc_gain); *count = int64_t(c->nq[q]) * PC_SHELLS; break;
+    case SKY_VIEW_PC_GAINS: *ptr = c->at(c->lay.pc_gain); *count = int64_t(m) * PC_SHELLS; break;
     default: return fail(SKY_ERR_INVALID, "unknown view");
   }
+  return SKY_OK;
+}
+
+int sky_set_states(sky_ctx* c, int32_t q, const void* psi, int32_t src_prec) {
+  if (!c || q < 0 || q >= c->nset || !psi) return fail(SKY_ERR_INVALID, "set_states arguments");
+  if (src_prec != SKY_FP64 && src_prec != SKY_MIXED)
+    return fail(SKY_ERR_INVALID, "set_states: precision must be SKY_FP64 or SKY_MIXED");
+  convert_states(psi, src_prec == SKY_MIXED ? 1 : 0, c->psi(q), c->prec, size_t(c->m_of(q)) * c->V,
+                 c->st);
+  c->hpsi_lagged = false;
+  return hip_check(hipGetLastError(), "set_states");
+}
+
+int sky_get_states(sky_ctx* c, int32_t q, void* psi, int32_t dst_prec) {
+  if (!c || q < 0 || q >= c->nset || !psi) return fail(SKY_ERR_INVALID, "get_states arguments");
+  if (dst_prec != SKY_FP64 && dst_prec != SKY_MIXED)
+    return fail(SKY_ERR_INVALID, "get_states: precision must be SKY_FP64 or SKY_MIXED");
+  convert_states(c->psi(q), c->prec, psi, dst_prec == SKY_MIXED ? 1 : 0, size_t(c->m_of(q)) * c->V,
+                 c->st);
+  return hip_check(hipGetLastError(), "get_states");
+}
+
+int sky_get_iteration(sky_ctx* c, int64_t* iteration) {
+  if (!c || !iteration) return fail(SKY_ERR_INVALID, "get_iteration arguments");
+  *iteration = c->iter_count;
+  return SKY_OK;
+}
+
+int sky_set_iteration(sky_ctx* c, int64_t iteration) {
+  if (!c || iteration < 0) return fail(SKY_ERR_INVALID, "set_iteration arguments");
+  c->iter_count = iteration;
   return SKY_OK;
 }
 
@@ -1146,7 +1465,7 @@ int sky_get_tuning(sky_ctx* c, sky_tuning* out) {
 }
 
 int sky_precond_collect(sky_ctx* c, int32_t q, int32_t* total) {
-  if (!c || q < 0 || q > 1) return fail(SKY_ERR_INVALID, "precond_collect arguments");
+  if (!c || q < 0 || q >= c->nset) return fail(SKY_ERR_INVALID, "precond_collect arguments");
   int rc = pc_collect(c, q);
   if (rc) return rc;
   if (total) *total = c->pc_count;
@@ -1194,6 +1513,22 @@ int sky_precond_use(sky_ctx* c, int32_t enable, double rise_tol, int32_t retrain
   return SKY_OK;
 }
 
+int sky_set_preconditioner(sky_ctx* c, const float* params, int32_t nparams) {
+  if (!c || !params) return fail(SKY_ERR_INVALID, "set_preconditioner arguments");
+  if (nparams != precond_nparams())
+    return fail(SKY_ERR_INVALID, "set_preconditioner: parameter count differs from the network's");
+  const Layout& L = c->lay;
+  const size_t bytes = sizeof(float) * size_t(nparams);
+  hipMemcpyAsync(c->at(L.pc_P), params, bytes, hipMemcpyDeviceToDevice, c->st);
+  zero_f32(c->at<float>(L.pc_M), size_t(nparams), c->st);
+  zero_f32(c->at<float>(L.pc_V), size_t(nparams), c->st);
+  precond_round(c->at<float>(L.pc_P), c->at<float>(L.pc_Pb), c->st);
+  c->pc_step = 0;
+  c->pc_ready = true;
+  c->pc_trained = true;
+  return hip_check(hipStreamSynchronize(c->st), "set_preconditioner");
+}
+
 int sky_set_graphs(sky_ctx* c, int32_t enable) {
   if (!c) return fail(SKY_ERR_INVALID, "null context");
   if (enable && !c->st) return fail(SKY_ERR_INVALID, "graph capture needs a stream other than the null stream");
@@ -1227,7 +1562,8 @@ int sky_batch_iterate(sky_ctx* const* ctxs, int32_t nbox, int32_t nthreads, int3
     const sky_ctx* c = ctxs[i];
     double w = 0.0;
     for (int q = 0; q < 2; ++q)
-      w += double(c->nq[q]) * double(c->V) * (double(c->nq[q]) + 40.0 * std::log2(double(c->V)));
+      w += double(c->ntw) * double(c->nq[q]) * double(c->V) *
+           (double(c->nq[q]) + 40.0 * std::log2(double(c->V)));
     cost[i] = {w, i};
   }
   std::sort(cost.begin(), cost.end(), [](auto& x, auto& y) { return x.first > y.first; });

@@ -42,6 +42,10 @@ struct GridArgs {
   double dx;      // spacing (fm), equal on all axes
   double dV;      // dx^3
   double kunit;   // 2 pi / L
+  // Bloch shift theta_m / L (fm^-1) of the states' wave numbers along x, y, z
+  // (twisted boundary conditions; 0 = periodic).  Derivatives of states use
+  // i (k_m + tw[m]); real fields are periodic and ignore it.
+  double tw[3];
 };
 
 // |k| shells of the learned preconditioner: S equal-width shells of |k| up

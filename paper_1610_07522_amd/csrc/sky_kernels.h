@@ -63,10 +63,12 @@ void precond_dir(int prec, const void* bpsi, void* bphi, size_t n, hipStream_t s
 size_t precond_gram_bytes(int ns);
 void precond_targets(int prec, const void* bpsi, const void* bh, const void* bd, const void* bhd,
                      const double* beps, int ns, long V, double* part, float* S, hipStream_t st);
-// dens = 11 fields [rho, tau, Jx, Jy, Jz, sx, sy, sz, jx, jy, jz][n^3];
-// part holds nchunk_max * 16 * n^3 doubles.
-void densities(int n, int prec, const void* psi, int nstate, int nchunk_max, GridArgs g,
-               double* part, double* dens, hipStream_t st);
+// dens = 11 fields [rho, tau, Jx, Jy, Jz, sx, sy, sz, jx, jy, jz][n^3],
+// summed over the first nstate states of each of ngroup state arrays psi[t]
+// (each with its own grid arguments g[t], i.e. its twist) and divided by
+// ngroup (the twist average); part holds nchunk_max * 16 * n^3 doubles.
+void densities(int n, int prec, const void* const* psi, const GridArgs* g, int ngroup,
+               int nstate, int nchunk_max, double* part, double* dens, hipStream_t st);
 // n complex values between precisions (0 = complex128, 1 = complex64).
 void convert_states(const void* src, int src_prec, void* dst, int dst_prec, size_t n,
                     hipStream_t st);
@@ -165,19 +167,30 @@ int refine_eigh(const void* A, int m, double* w, void* Z, void* work, double tol
 // ---- dense FP64 linear algebra (k_linalg.hip)
 // Cholesky A = L L^H of Hermitian positive definite A (m x m, lower used),
 // then Linv = L^-1 (lower triangular, upper zeroed).  info[0] != 0 when a
-// pivot is not positive.  work >= m*m complex.
-void cholesky_inverse(void* A, void* Linv, int m, void* work, int* info, hipStream_t st);
+// pivot is not above piv_min (or not a number).  work >= m*m complex.
+void cholesky_inverse(void* A, void* Linv, int m, void* work, int* info, hipStream_t st,
+                      double piv_min = 0.0);
 // Hermitian eigen-decomposition by blocked two-sided Jacobi: A (m x m, full
 // Hermitian, destroyed) -> eigenvalues w (ascending) and eigenvectors Z
 // (columns).  work: jacobi_scratch_bytes(m).
+// Returns the sweeps taken, -1 when the off-diagonal norm is still above tol
+// after max_sweeps sweeps (w, Z then hold the last sweep's result), -2 when
+// the matrix holds a non-finite value.
 size_t jacobi_scratch_bytes(int m);
 int jacobi_eigh(void* A, int m, double* w, void* Z, void* work, double tol, int max_sweeps,
                 hipStream_t st);
+// Gauge of the paper-literal update: info[3c..3c+2] = (start, size, packed
+// offset) of the eigenvalue cluster of column c.  gauge_gather packs each
+// cluster's diagonal block of Z (row-major, m x m); gauge_apply writes
+// out = Z Q for the block-diagonal Q whose blocks are packed the same way.
+void gauge_gather(const void* Z, int m, const int* info, void* packed, hipStream_t st);
+void gauge_apply(const void* Z, int m, const int* info, const void* Q, void* out, hipStream_t st);
 // Loewdin transform C = I^-1/2 (Eqs. Loewedin/orthmatvec) of an overlap close
 // to the identity, by the binomial series of (1 + D)^-1/2, D = I - 1, in
 // Horner form on the FP64 matrix cores.  The number of terms p makes the
 // remainder (bounded through ||D||_2 <= ||D||_F) smaller than 2^-56.
-// Returns p, or 0 (nothing written to C) when ||D||_F > max_dev.  D and T
+// Returns p, 0 (nothing written to C) when ||D||_F > max_dev, or -1 when
+// ||D||_F is not a finite number.  D and T
 // are m x m work matrices, scratch >= 257 doubles, part the square-product
 // scratch (gemm_square); synchronises the stream.
 int loewdin_series(const void* I, void* C, void* D, void* T, int m, double max_dev,
@@ -187,9 +200,10 @@ int loewdin_series(const void* I, void* C, void* D, void* T, int m, double max_d
 void eig_sort(const void* D, const void* V, int m, int ld, double* w, void* Z, hipStream_t st);
 // X <- X diag(d) (scale column b by d[b]), d real.
 void scale_columns(void* X, const double* d, int m, hipStream_t st);
-// w <- w^-1/2 elementwise (Loewdin), flags info if any w <= 0.
-void inv_sqrt(double* w, int m, int* info, hipStream_t st);
-// fill n doubles with zero (a kernel, so it can be captured in graphs)
+// w <- w^-1/2 elementwise (Loewdin), flags info if any w <= floor_v.
+void inv_sqrt(double* w, int m, int* info, hipStream_t st, double floor_v = 0.0);
+// fill n doubles (floats) with zero (a kernel, so it can be captured in graphs)
 void zero(double* p, size_t n, hipStream_t st);
+void zero_f32(float* p, size_t n, hipStream_t st);
 
 }  // namespace sky

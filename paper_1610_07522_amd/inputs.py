@@ -48,10 +48,20 @@ class Workload:
     damp_x0: float = 0.45      # damping step delta of the gradient step
     damp_e0: float = 100.0     # damping energy E0 in MeV
     force: Tuple[Tuple[str, float], ...] = tuple(SLY4.items())
+    extra_n: int = 0           # unoccupied (v^2 = 0) states carried beyond the
+    extra_p: int = 0           # particles of each species (Sec. 2.1)
 
     @property
     def params(self) -> Dict[str, float]:
         return dict(self.force)
+
+    @property
+    def states_n(self) -> int:
+        return self.n_neutrons + self.extra_n
+
+    @property
+    def states_p(self) -> int:
+        return self.n_protons + self.extra_p
 
     @property
     def box(self) -> float:
@@ -141,7 +151,8 @@ def _shape_field(w: Workload, rng: np.random.Generator) -> np.ndarray:
 
 
 def raw_states(w: Workload) -> Tuple[np.ndarray, np.ndarray]:
-    """Raw trial spinors (neutrons, protons), complex128, not orthonormal.
+    """Raw trial spinors (neutrons, protons), complex128, not orthonormal:
+    the particles' states followed by the extra states of each species.
 
     psi[alpha, s] = sqrt(f) * exp(i k.r) delta_{s, s_alpha} / sqrt(L^3)
                     (+ noise * (g1 + i g2) / sqrt(2) / sqrt(L^3)),
@@ -157,7 +168,7 @@ def raw_states(w: Workload) -> Tuple[np.ndarray, np.ndarray]:
     phase1d = np.exp(2j * math.pi * np.outer(np.arange(-(n // 2), n // 2),
                                              np.arange(n)) / n)
     out = []
-    for count in (w.n_neutrons, w.n_protons):
+    for count in (w.states_n, w.states_p):
         lab = plane_wave_labels(n, count)
         psi = np.zeros((count, 2, n, n, n), dtype=np.complex128)
         for a, (kx, ky, kz, s) in enumerate(lab):
@@ -175,10 +186,20 @@ def raw_states(w: Workload) -> Tuple[np.ndarray, np.ndarray]:
 
 def small_workload(name: str, n: int, n_neutrons: int, n_protons: int,
                    init: str = "plain", seed: int = 7, noise: float = 0.1,
-                   amp: float = 0.3, dx: float = 1.0) -> Workload:
+                   amp: float = 0.3, dx: float = 1.0, extra_n: int = 0,
+                   extra_p: int = 0) -> Workload:
     """A reduced box for fast tests (same force and damping as the others)."""
     return Workload(name, n, dx, n_neutrons, n_protons, init, seed=seed,
-                    amp=amp if init != "plain" else 0.0, noise=noise)
+                    amp=amp if init != "plain" else 0.0, noise=noise,
+                    extra_n=extra_n, extra_p=extra_p)
+
+
+def special_twists(k: int = 2) -> List[Tuple[float, float, float]]:
+    """A k x k x k grid of Bloch phases theta_m = pi (2 j + 1 - k) / k,
+    j = 0..k-1 per axis, symmetric about zero (k = 2: the eight corners
+    (+-pi/2, +-pi/2, +-pi/2)): the twists of a twist-averaged box."""
+    th = [math.pi * (2 * j + 1 - k) / k for j in range(k)]
+    return [(tx, ty, tz) for tz in th for ty in th for tx in th]
 
 
 def batch_workloads(count: int = 64, seed: int = 3) -> List[Workload]:

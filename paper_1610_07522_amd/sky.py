@@ -25,6 +25,9 @@ SKY_ERR_NOT_POSITIVE_DEFINITE = -5
 SKY_ERR_NAN = -6
 SKY_FP64 = 0
 SKY_MIXED = 1
+SKY_UPDATE_EXACT = 0
+SKY_UPDATE_PAPER = 1
+SKY_MAX_TWIST = 32
 
 VIEW = dict(psi=0, hpsi=1, phi=2, hphi=3, dens=4, meanfield=5, coulomb=6, energy=7,
             eps=8, ritz=9, r2=10, overlap=11, hsub=12, evec=13, umat=14,
@@ -35,10 +38,12 @@ _F32_VIEWS = ("pc_params", "pc_grad", "pc_samples", "pc_gains")
 # Symbols declared in include/sky.h, in order.
 EXPORTS = ("sky_workspace_size", "sky_create", "sky_init_box", "sky_apply_h",
            "sky_damped_step", "sky_orthonormalize", "sky_densities", "sky_iterate",
-           "sky_get_view", "sky_set_timing", "sky_get_timing", "sky_get_precision",
+           "sky_get_view", "sky_set_states", "sky_get_states", "sky_get_iteration",
+           "sky_set_iteration", "sky_set_timing", "sky_get_timing", "sky_get_precision",
            "sky_autotune", "sky_get_tuning", "sky_set_graphs", "sky_batch_iterate",
            "sky_precond_collect", "sky_precond_train",
-           "sky_precond_loss_grad", "sky_precond_set_rows", "sky_precond_use", "sky_sync",
+           "sky_precond_loss_grad", "sky_precond_set_rows", "sky_precond_use",
+           "sky_set_preconditioner", "sky_sync",
            "sky_last_error",
            "sky_destroy")
 PHASES = ("apply_h", "damp", "overlap_gemm", "subspace", "combine_gemm", "densities",
@@ -56,14 +61,19 @@ class BoxDesc(ctypes.Structure):
                 ("hb2m_n", ctypes.c_double), ("hb2m_p", ctypes.c_double),
                 ("e2", ctypes.c_double),
                 ("damp_x0", ctypes.c_double), ("damp_e0", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("ladder_tol", ctypes.c_double)]
+                ("precision", ctypes.c_int32), ("ladder_tol", ctypes.c_double),
+                ("extra_n", ctypes.c_int32), ("extra_p", ctypes.c_int32),
+                ("ntwist", ctypes.c_int32),
+                ("twist", (ctypes.c_double * 3) * SKY_MAX_TWIST),
+                ("update", ctypes.c_int32), ("one_h", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("residual", ctypes.c_double),
                 ("energy", ctypes.c_double), ("energy_per_a", ctypes.c_double),
                 ("eig_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("eig_fallbacks", ctypes.c_int32), ("precond_iters", ctypes.c_int32)]
+                ("eig_fallbacks", ctypes.c_int32), ("precond_iters", ctypes.c_int32),
+                ("eig_unconverged", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):
@@ -110,6 +120,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "sky_iterate": (ctypes.c_int, [vp, i32, dbl, ctypes.POINTER(Report)]),
         "sky_get_view": (ctypes.c_int, [vp, i32, i32, ctypes.POINTER(vp),
                                         ctypes.POINTER(ctypes.c_int64)]),
+        "sky_set_states": (ctypes.c_int, [vp, i32, vp, i32]),
+        "sky_get_states": (ctypes.c_int, [vp, i32, vp, i32]),
+        "sky_get_iteration": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int64)]),
+        "sky_set_iteration": (ctypes.c_int, [vp, ctypes.c_int64]),
         "sky_set_timing": (ctypes.c_int, [vp, i32]),
         "sky_get_timing": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_int64)]),
@@ -124,6 +138,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "sky_precond_loss_grad": (ctypes.c_int, [vp, i32, dp]),
         "sky_precond_set_rows": (ctypes.c_int, [vp, i32]),
         "sky_precond_use": (ctypes.c_int, [vp, i32, dbl, i32]),
+        "sky_set_preconditioner": (ctypes.c_int, [vp, vp, i32]),
         "sky_sync": (ctypes.c_int, [vp]),
         "sky_last_error": (ctypes.c_char_p, []),
         "sky_destroy": (None, [vp]),
@@ -143,13 +158,29 @@ def _check(rc: int, ok=(SKY_OK,)) -> int:
     return rc
 
 
-def desc_from_workload(w, precision: int = SKY_FP64, ladder_tol: float = 0.0) -> BoxDesc:
-    """BoxDesc of a ``paper_1610_07522_amd.inputs.Workload``."""
+def desc_from_workload(w, precision: int = SKY_FP64, ladder_tol: float = 0.0,
+                       twists=None, update: int = SKY_UPDATE_EXACT,
+                       one_h: bool = False) -> BoxDesc:
+    """BoxDesc of a ``paper_1610_07522_amd.inputs.Workload`` (its extra
+    states included); ``twists``: Bloch phases (theta_x, theta_y, theta_z)
+    of twist-averaged boundary conditions, None = periodic."""
     p = w.params
-    return BoxDesc(w.n, w.dx, w.n_neutrons, w.n_protons, p["t0"], p["t1"], p["t2"], p["t3"],
-                   p["x0"], p["x1"], p["x2"], p["x3"], p["alpha"], p["W0"],
-                   p["hb2m_n"], p["hb2m_p"], p["e2"], w.damp_x0, w.damp_e0,
-                   precision, ladder_tol)
+    d = BoxDesc(w.n, w.dx, w.n_neutrons, w.n_protons, p["t0"], p["t1"], p["t2"], p["t3"],
+                p["x0"], p["x1"], p["x2"], p["x3"], p["alpha"], p["W0"],
+                p["hb2m_n"], p["hb2m_p"], p["e2"], w.damp_x0, w.damp_e0,
+                precision, ladder_tol)
+    d.extra_n = getattr(w, "extra_n", 0)
+    d.extra_p = getattr(w, "extra_p", 0)
+    if twists:
+        if len(twists) > SKY_MAX_TWIST:
+            raise ValueError(f"at most {SKY_MAX_TWIST} twists")
+        d.ntwist = len(twists)
+        for t, th in enumerate(twists):
+            for m in range(3):
+                d.twist[t][m] = float(th[m])
+    d.update = update
+    d.one_h = 1 if one_h else 0
+    return d
 
 
 def _ptr(t) -> Optional[int]:
@@ -160,6 +191,7 @@ def _report_dict(rep: Report, rc: int) -> Dict[str, float]:
     return dict(iters=rep.iters, residual=rep.residual, energy=rep.energy,
                 energy_per_a=rep.energy_per_a, eig_iters=rep.eig_iters,
                 eig_fallbacks=rep.eig_fallbacks, precond_iters=rep.precond_iters,
+                eig_unconverged=rep.eig_unconverged,
                 precision=rep.precision, converged=(rc == SKY_OK))
 
 
@@ -227,6 +259,31 @@ class Box:
     def densities(self):
         _check(self.lib.sky_densities(self.ctx))
 
+    @property
+    def nsets(self) -> int:
+        return 2 * max(1, self.desc.ntwist)
+
+    def set_states(self, q, psi, precision=None):
+        """Copy the states of set q from a device tensor (complex128 or complex64)."""
+        import torch
+        if precision is None:
+            precision = SKY_MIXED if psi.dtype == torch.complex64 else SKY_FP64
+        _check(self.lib.sky_set_states(self.ctx, q, _ptr(psi), precision))
+
+    def get_states(self, q, out):
+        """Copy the states of set q into a device tensor (complex128 or complex64)."""
+        import torch
+        precision = SKY_MIXED if out.dtype == torch.complex64 else SKY_FP64
+        _check(self.lib.sky_get_states(self.ctx, q, _ptr(out), precision))
+
+    def iteration(self) -> int:
+        v = ctypes.c_int64()
+        _check(self.lib.sky_get_iteration(self.ctx, ctypes.byref(v)))
+        return v.value
+
+    def set_iteration(self, it: int):
+        _check(self.lib.sky_set_iteration(self.ctx, it))
+
     def iterate(self, max_iter: int, tol: float = 0.0) -> Dict[str, float]:
         rep = Report()
         rc = _check(self.lib.sky_iterate(self.ctx, max_iter, tol, ctypes.byref(rep)),
@@ -272,6 +329,10 @@ class Box:
 
     def precond_use(self, enable: bool, rise_tol: float = 0.05, retrain_every: int = 0):
         _check(self.lib.sky_precond_use(self.ctx, 1 if enable else 0, rise_tol, retrain_every))
+
+    def set_preconditioner(self, params):
+        """Load FP32 master parameters (a device tensor) into the learned damping."""
+        _check(self.lib.sky_set_preconditioner(self.ctx, _ptr(params), params.numel()))
 
     def sync(self):
         _check(self.lib.sky_sync(self.ctx))

@@ -95,3 +95,54 @@ def test_workspace_plan_with_empty_or_single_species(lib, nn, npp, prec):
     fake = 1 << 40   # never dereferenced: creation only records the pointer
     assert lib.sky_create(ctypes.byref(d), fake, nb.value, None, ctypes.byref(ctx)) == sky.SKY_OK
     lib.sky_destroy(ctx)
+
+
+def test_validation_of_extra_states_twists_and_update_forms(lib):
+    nb = ctypes.c_size_t()
+    base = ctypes.c_size_t()
+    assert lib.sky_workspace_size(ctypes.byref(_desc()), ctypes.byref(base)) == sky.SKY_OK
+    bad = [dict(extra_n=-1), dict(n_protons=0, extra_p=3), dict(ntwist=sky.SKY_MAX_TWIST + 1),
+           dict(ntwist=-1), dict(update=2), dict(update=sky.SKY_UPDATE_PAPER, one_h=1)]
+    for kw in bad:
+        assert lib.sky_workspace_size(ctypes.byref(_desc(**kw)), ctypes.byref(nb)) == \
+            sky.SKY_ERR_INVALID, kw
+    d = _desc(extra_n=4, extra_p=2)
+    assert lib.sky_workspace_size(ctypes.byref(d), ctypes.byref(nb)) == sky.SKY_OK
+    assert nb.value > base.value
+    d = _desc()
+    d.twist[0][0] = float("nan")
+    assert lib.sky_workspace_size(ctypes.byref(d), ctypes.byref(nb)) == sky.SKY_ERR_INVALID
+    # every twist holds its own psi and h psi of both species
+    w = inputs.WORKLOADS["fermi16"]
+    d4 = sky.desc_from_workload(w, twists=inputs.special_twists(2)[:4])
+    assert d4.ntwist == 4
+    assert lib.sky_workspace_size(ctypes.byref(d4), ctypes.byref(nb)) == sky.SKY_OK
+    state = 2 * 16 ** 3 * 16
+    assert nb.value - base.value >= 3 * 2 * 16 * state
+
+
+def test_state_sets_and_io_arguments(lib):
+    w = inputs.WORKLOADS["fermi16"]
+    d = sky.desc_from_workload(w, twists=inputs.special_twists(2)[:3])
+    nb = ctypes.c_size_t()
+    lib.sky_workspace_size(ctypes.byref(d), ctypes.byref(nb))
+    ctx = ctypes.c_void_p()
+    fake = 1 << 40   # never dereferenced: only argument checks run
+    assert lib.sky_create(ctypes.byref(d), fake, nb.value, None, ctypes.byref(ctx)) == sky.SKY_OK
+    ptr, cnt = ctypes.c_void_p(), ctypes.c_int64()
+    # 3 twists x 2 species = 6 state sets
+    assert lib.sky_get_view(ctx, sky.VIEW["psi"], 5, ctypes.byref(ptr), ctypes.byref(cnt)) == sky.SKY_OK
+    assert cnt.value == 8 * 2 * 16 ** 3
+    assert lib.sky_get_view(ctx, sky.VIEW["psi"], 6, ctypes.byref(ptr), ctypes.byref(cnt)) == \
+        sky.SKY_ERR_INVALID
+    assert lib.sky_set_states(ctx, 6, fake, sky.SKY_FP64) == sky.SKY_ERR_INVALID
+    assert lib.sky_set_states(ctx, 0, None, sky.SKY_FP64) == sky.SKY_ERR_INVALID
+    assert lib.sky_set_states(ctx, 0, fake, 7) == sky.SKY_ERR_INVALID
+    assert lib.sky_get_states(ctx, -1, fake, sky.SKY_FP64) == sky.SKY_ERR_INVALID
+    assert lib.sky_set_preconditioner(ctx, fake, 12) == sky.SKY_ERR_INVALID
+    assert lib.sky_set_preconditioner(ctx, None, 33793) == sky.SKY_ERR_INVALID
+    it = ctypes.c_int64()
+    assert lib.sky_set_iteration(ctx, 41) == sky.SKY_OK
+    assert lib.sky_get_iteration(ctx, ctypes.byref(it)) == sky.SKY_OK and it.value == 41
+    assert lib.sky_set_iteration(ctx, -1) == sky.SKY_ERR_INVALID
+    lib.sky_destroy(ctx)
