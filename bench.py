@@ -48,6 +48,23 @@ MEASURED_TRAFFIC = {
 }
 
 
+# HBM bytes per neutron launch of each grid phase, summed over its kernels
+# (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, profiles/grid_kernels_rod48_pmc.md),
+# reported while k_grid.hip keeps the hash they were taken on.
+MEASURED_PHASE_TRAFFIC = dict(
+    source="paper_1610_07522_amd/csrc/k_grid.hip", sha256_16="02d7496c24585772",
+    apply_h=23.088e9, damp=22.654e9, densities=9.402e9)
+
+
+def measured_phase_traffic(phase: str):
+    import hashlib
+    e = MEASURED_PHASE_TRAFFIC
+    with open(os.path.join(ROOT, e["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != e["sha256_16"]:
+            return None
+    return e.get(phase)
+
+
 def measured_traffic(kernel: str):
     """Bytes per launch from MEASURED_TRAFFIC, or None if not measured or stale."""
     import hashlib
@@ -73,17 +90,20 @@ def gemm_flops(m: int, v: int) -> dict:
 
 def roofline(timing: dict, w, mixed: bool) -> dict:
     """Roofline of the costlier of the two single-kernel GEMM phases (the
-    I/H overlap GEMM or the recombination GEMM), neutron launches.  FP64:
-    8 flops per complex MAC against the FP64 peak; mixed: the FP16 flops the
-    split algorithm issues (3 split products x 8 per complex MAC) against the
-    FP16 peak."""
+    I/H overlap GEMM or the recombination GEMM), neutron launches.  achieved
+    counts the method's own arithmetic, 8 real flops per complex
+    multiply-add of the contraction (lower triangles of I and H), against
+    the peak of the dtype the kernel runs on: FP64 MFMA for the FP64 form,
+    FP16 MFMA for the mixed form.  The split-FP16 kernel issues 3 FP16
+    products per real product; that issue rate is reported separately
+    ("issued") and is not counted as work."""
     v = 2 * w.n ** 3
     m = w.n_neutrons
     dom = max(("overlap_gemm", "combine_gemm"),
               key=lambda k: timing[k]["ms_n"] + timing[k]["ms_p"])
     t = timing[dom]
     avg_ms = t["ms_n"] / max(1, t["launches_n"])
-    fl = gemm_flops(m, v)[dom] * (SPLIT_PRODUCTS if mixed else 1)
+    fl = gemm_flops(m, v)[dom]
     peak = PEAK_F16_TFLOPS if mixed else PEAK_FP64_TFLOPS
     ach = fl / (avg_ms * 1e-3) / 1e12
     if mixed:
@@ -91,24 +111,86 @@ def roofline(timing: dict, w, mixed: bool) -> dict:
     else:
         name = "k_overlap_lower" if dom == "overlap_gemm" else "k_combine"
     traffic = measured_traffic(name) if w.name == "rod48" else None
-    return dict(kernel=name, bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s",
-                frac=ach / peak, traffic=traffic, traffic_unit="bytes per launch",
-                dtype=("fp16x2-split" if mixed else "fp64"),
-                per_launch=dict(species="neutrons", m=m, k=v, flops=fl, avg_ms=avg_ms,
-                                unique_bytes=2.0 * m * v * (8 if mixed else 16)))
+    out = dict(kernel=name, bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s",
+               frac=ach / peak, traffic=traffic, traffic_unit="bytes per launch",
+               dtype=("fp16 MFMA (two-term split of c64 operands)" if mixed else "fp64"),
+               per_launch=dict(species="neutrons", m=m, k=v, flops=fl, avg_ms=avg_ms,
+                               unique_bytes=2.0 * m * v * (8 if mixed else 16)))
+    if mixed:
+        iss = ach * SPLIT_PRODUCTS
+        out["issued"] = dict(achieved=iss, frac=iss / peak, unit="TFLOP/s",
+                             note=f"{SPLIT_PRODUCTS} FP16 products per real product of the split")
+    return out
+
+
+# HBM bytes a phase must move per launch per state (complex elements V = 2 n^3
+# per state): h psi reads psi and writes h psi; the damped step reads psi and
+# h psi and writes phi; the densities read psi.
+PHASE_STATE_ARRAYS = dict(apply_h=2, damp=3, densities=1)
+
+
+def hbm_phases(timing: dict, w, mixed: bool) -> dict:
+    """Algorithmic HBM rate of each grid phase (neutron launches): compulsory
+    bytes (PHASE_STATE_ARRAYS state arrays) / the phase's mean launch time."""
+    v = 2 * w.n ** 3
+    m = w.n_neutrons
+    out = {}
+    for ph_, arrays in PHASE_STATE_ARRAYS.items():
+        t = timing[ph_]
+        if not t["launches_n"]:
+            continue
+        avg_ms = t["ms_n"] / t["launches_n"]
+        nbytes = arrays * m * v * (8 if mixed else 16)
+        ach = nbytes / (avg_ms * 1e-3) / 1e9
+        out[ph_] = dict(achieved=ach, frac=ach / PEAK_HBM_GBS, avg_ms=avg_ms,
+                        bytes_per_launch=nbytes, state_arrays=arrays)
+        cb = measured_phase_traffic(ph_) if (mixed and w.name == "rod48") else None
+        if cb is not None:
+            out[ph_]["counter_bytes"] = cb
+            out[ph_]["counter_achieved"] = cb / (avg_ms * 1e-3) / 1e9
+            out[ph_]["counter_frac"] = out[ph_]["counter_achieved"] / PEAK_HBM_GBS
+    out["unit"] = "GB/s"
+    out["peak"] = PEAK_HBM_GBS
+    return out
 
 
 def h_phase_hbm(timing: dict, w, mixed: bool) -> dict:
     """Algorithmic HBM rate of one h*psi application (read psi, write h psi),
-    neutron launches (three line-pass kernels per application)."""
+    neutron launches."""
     v = 2 * w.n ** 3
     m = w.n_neutrons
     t = timing["apply_h"]
     avg_ms = t["ms_n"] / max(1, t["launches_n"])
     nbytes = 2.0 * m * v * (8 if mixed else 16)
     ach = nbytes / (avg_ms * 1e-3) / 1e9
-    return dict(phase="apply_h (k_h_pass x3)", bound="hbm", achieved=ach, peak=PEAK_HBM_GBS,
+    return dict(phase="apply_h", bound="hbm", achieved=ach, peak=PEAK_HBM_GBS,
                 unit="GB/s", frac=ach / PEAK_HBM_GBS, bytes_per_launch=nbytes, avg_ms=avg_ms)
+
+
+def oracle_config0(iters: int = 200) -> dict:
+    """The oracle measured in full (not sampled) on the 16^3 box with
+    8 n + 8 p: init plus ``iters`` iterations."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import Grid
+    from oracle import solver as so
+    from paper_1610_07522_amd import inputs
+
+    cores = int(os.environ.get("SKY_ORACLE_THREADS", "0")) or len(os.sched_getaffinity(0))
+    os.environ["SKY_ORACLE_THREADS"] = str(cores)
+    w = inputs.WORKLOADS["fermi16"]
+    raw = inputs.raw_states(w)
+    with threadpool_limits(limits=cores):
+        t0 = time.perf_counter()
+        st = so.initial_state(*raw, Grid(w.n, w.dx), w.params, w.damp_x0, w.damp_e0)
+        t_init = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            rep = so.iterate(st)
+        sec = time.perf_counter() - t0
+    return dict(workload="fermi16: 16^3, 8 n + 8 p, plane waves + noise 0.1", iterations=iters,
+                seconds=sec, iter_per_s=iters / sec, init_seconds=t_init,
+                residual_after=rep.de, energy_after=rep.E["total"], cores=cores)
 
 
 def cpu_baseline(w, budget_states: int = 8, k_slice: int = 32) -> dict:
@@ -464,6 +546,7 @@ def main() -> int:
                     grid=w.n, nucleons=w.n_states, precision=args.precision),
         roofline=roofline(timing, w, mixed),
         h_phase_hbm=h_phase_hbm(timing, w, mixed),
+        hbm_phases=hbm_phases(timing, w, mixed),
         phases_ms_per_iter=phases,
         residual=reps[-1]["residual"], energy_per_a=reps[-1]["energy_per_a"],
         eigensolver=dict(iters_per_step=[r["eig_iters"] for r in reps],
@@ -482,6 +565,8 @@ def main() -> int:
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w)
+        log("timing the CPU oracle in full on the 16^3 box")
+        out["cpu_baseline"]["config_fermi16"] = oracle_config0()
     print(json.dumps(out), flush=True)
     return 0
 
