@@ -151,11 +151,16 @@ def test_precision_ladder_switches_to_fp64(torch_mod):
     assert abs(rep["energy"] - st.E["total"]) <= 1000 * U32 * parts, (e1, rep, st.E)
 
 
-def test_mixed_overlap_fullsize(torch_mod):
+def test_mixed_overlap_and_combine_fullsize(torch_mod):
     """48^3 x 1600 neutrons, the bench configuration: sampled rows of the
     split-FP16 overlap (FP32 accumulation over each split-K chunk of the
-    221184-long contraction, chunks summed in FP64) against complex128
-    products of the same complex64 states, at the 1e-6 bar."""
+    221184-long contraction, chunks summed in FP64) against the oracle's
+    overlap of the same complex64 states (widened to complex128), at the 1e-6
+    bar; then sampled output states of the split-FP16 recombination
+    psi' = psi U (U the Rayleigh-Ritz transform of the states with their own
+    h, a rotation far from the identity; from the planes of U^T and psi^T)
+    against the oracle's combination of the same states and the same U, at
+    the same bar."""
     torch = torch_mod
     w = inputs.WORKLOADS["rod48"]
     rn, rp = inputs.raw_states(w)
@@ -164,19 +169,28 @@ def test_mixed_overlap_fullsize(torch_mod):
     del rn, rp
     q = 0
     psi = box.view("psi", q)
+    hpsi = box.view("hpsi", q)
     m = psi.shape[0]
+    box.apply_h(q, psi, hpsi, m)
     out = torch.empty_like(psi)
-    box.orthonormalize(q, psi, None, out)
+    box.orthonormalize(q, psi, hpsi, out)
     box.sync()
-    I_gpu = box.view("overlap", q)
-    P = psi.reshape(m, -1).to(torch.complex128)
-    dV = w.dx ** 3
+    g = Grid(w.n, w.dx)
+    P = to_host(psi).astype(np.complex128)            # the states both sides use
+    I_gpu = to_host(box.view("overlap", q))
     worst = 0.0
     for r in range(0, m, 97):
-        ref = dV * torch.mv(P, P[r].conj())          # row r: dV sum_k conj(P[r,k]) P[b,k]
-        err = (I_gpu[r] - ref).abs().max().item() / ref.abs().max().item()
-        worst = max(worst, err)
-    assert worst <= 1e-6, worst
+        ref = so.overlap(P[r:r + 1], P, g)[0]
+        worst = max(worst, np.abs(I_gpu[r] - ref).max() / np.abs(ref).max())
+    assert worst <= 1e-6, ("overlap", worst)
+    U = to_host(box.view("umat", q))
+    assert np.abs(U - np.diag(np.diag(U))).max() > 0.1      # a real rotation
+    o = to_host(out)
+    worst = 0.0
+    for b in list(range(0, m, 211)) + [m - 1]:
+        ref = so.combine(P, U[:, b:b + 1])[0]
+        worst = max(worst, np.abs(o[b] - ref).max() / np.abs(ref).max())
+    assert worst <= 1e-6, ("combine", worst)
 
 
 @pytest.mark.parametrize("ladder", [1e-4, 0.0])

@@ -187,7 +187,7 @@ def test_rayleigh_ritz_far_from_orthonormal(torch_mod, case):
         assert rel_err(dg.rho, dr.rho) <= TOL and rel_err(dg.tau, dr.tau) <= TOL, case
 
 
-ITERS = {"n16_8p8": (1, 10, 50), "n24_13p7_rod": (1, 5), "n8_5p3": (1, 10, 40),
+ITERS = {"n16_8p8": (1, 10, 50, 200), "n24_13p7_rod": (1, 5), "n8_5p3": (1, 10, 40),
          "n32_70p33_slab": (1, 3), "n24_200p50_rod": (1, 3)}
 
 
@@ -252,3 +252,38 @@ def test_overlap_matrix_and_eigensolver(torch_mod, case):
         np.testing.assert_allclose(I_ref @ Z, Z * lam,
                                    atol=1e-12 * np.linalg.norm(I_ref))
         assert err is None, err
+
+
+def test_slab32_against_oracle_fixture(torch_mod):
+    """The 32^3 pasta slab box (640 n + 160 p, FP64) against the oracle's
+    own run of the same seeded states, stored by tests/golden/make_slab32.py
+    (oracle only): energy parts, Delta-eps, every Ritz value and rho, tau on
+    256 sampled points after iterations 1, 10 and 100."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "slab32_oracle.json")
+    ref = json.load(open(path))
+    w = inputs.WORKLOADS["slab32"]
+    raw = inputs.raw_states(w)
+    box = _box(w)
+    box.init_box(to_dev(raw[0]), to_dev(raw[1]))
+    del raw
+    pts = np.array(ref["points"])
+    z, y, x = pts[:, 2], pts[:, 1], pts[:, 0]
+    done = 0
+    keys = ["kin", "rho", "rho3", "tau", "lap", "so", "coul", "total"]
+    for it in sorted(int(k) for k in ref["iterations"]):
+        r = ref["iterations"][str(it)]
+        rep = box.iterate(it - done)
+        done = it
+        E = r["energy"]
+        scale = max(abs(E[k]) for k in keys)
+        ge = to_host(box.view("energy"))
+        for i, k in enumerate(keys):
+            assert abs(ge[i] - E[k]) <= TOL * scale, (it, k, ge[i], E[k])
+        assert abs(rep["residual"] - r["de"]) <= 1e-8 * max(1.0, r["de"]), (it, rep, r["de"])
+        for q in range(2):
+            assert rel_err(to_host(box.view("ritz", q)), np.array(r["ritz"][q])) <= TOL, (it, q)
+            gd = to_host(box.view("dens", q))
+            assert rel_err(gd[0][z, y, x], np.array(r["rho"][q])) <= TOL, (it, q)
+            assert rel_err(gd[1][z, y, x], np.array(r["tau"][q])) <= TOL, (it, q)
