@@ -214,6 +214,22 @@ int sky_init_box(sky_ctx* c, const void* raw_n_dev, const void* raw_p_dev);
 int sky_apply_h(sky_ctx* c, int32_t q, const void* psi_dev, void* hpsi_dev, int32_t nstates,
                 double* eps_dev);
 
+/* sky_apply_h for callers that cannot allocate device memory or take it
+ * from a workspace per call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the same kernels and results
+ * (bit for bit), with the per-workgroup partial sums of <psi|h psi> held in
+ * a fixed device array of the library (8 MiB, one per device, kept until the
+ * process ends; its address is looked up once per device, on the first call
+ * there) instead of the context's workspace.  It calls no allocating
+ * routine.  Every call on one device shares that array and the partials are
+ * overwritten in full by each call (nothing needs clearing), so calls that
+ * overlap in time on one device race: issue them on one stream, or order
+ * them.  Limit: nstates x (grid tiles of one pass; 144 at n = 48, 256 at
+ * n = 64) partial sums must fit the array's 2^20 doubles, else
+ * SKY_ERR_INVALID with the sizes in the message.  Errors: INVALID, HIP. */
+int sky_apply_h_noalloc(sky_ctx* c, int32_t q, const void* psi_dev, void* hpsi_dev,
+                        int32_t nstates, double* eps_dev);
+
 /* Damped gradient step, Eq. dampstep:
  *   phi = psi - x0 F^-1[ F(h psi - eps psi) / (E0 + hb2m_q |k|^2) ],
  * eps_dev: <psi|h psi> per state (from sky_apply_h).  r2_dev (f64, nstates)

@@ -24,7 +24,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-I", os.path.join(ROOT, "include"), "-Wno-unused-result"]
 
 SOURCES = ["k_grid.hip", "k_fields.hip", "k_gemm.hip", "k_gemm_mixed.hip", "k_linalg.hip",
-           "k_refine.hip", "k_precond.hip", "sky_api.cpp"]
+           "k_refine.hip", "k_precond.hip", "k_noalloc.hip", "sky_api.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -1097,6 +1097,28 @@ int sky_apply_h(sky_ctx* c, int32_t q, const void* psi, void* hpsi, int32_t nsta
   return hip_check(hipGetLastError(), "apply_h launch");
 }
 
+int sky_apply_h_noalloc(sky_ctx* c, int32_t q, const void* psi, void* hpsi, int32_t nstates,
+                        double* eps) {
+  if (!c || q < 0 || q >= c->nset || !psi || !hpsi || nstates < 0)
+    return fail(SKY_ERR_INVALID, "apply_h_noalloc arguments");
+  if (nstates > c->m_of(q))
+    return fail(SKY_ERR_INVALID, "apply_h_noalloc: more states than the set holds");
+  const size_t need = size_t(nstates) * size_t(grid_ntiles(c->n));
+  if (need > noalloc_scratch_capacity())
+    return fail(SKY_ERR_INVALID, "apply_h_noalloc: " + std::to_string(nstates) +
+                                     " states need " + std::to_string(need) +
+                                     " partial sums, more than the fixed scratch holds (" +
+                                     std::to_string(noalloc_scratch_capacity()) + ")");
+  double* part = nullptr;
+  if (eps) {
+    std::string err;
+    if (noalloc_scratch(&part, &err)) return fail(SKY_ERR_HIP, err);
+  }
+  apply_h(c->n, c->prec, psi, hpsi, nstates, c->mfp(q), c->gset(q), part, eps, c->st,
+          c->tune.lines);
+  return hip_check(hipGetLastError(), "apply_h_noalloc launch");
+}
+
 int sky_damped_step(sky_ctx* c, int32_t q, const void* psi, const void* hpsi, const double* eps,
                     void* phi, int32_t nstates, double* r2) {
   if (!c || q < 0 || q >= c->nset || !psi || !hpsi || !eps || !phi || nstates < 0)

@@ -1,6 +1,8 @@
 // Host-side launchers of the library's kernels (all enqueue on `st`).
 #pragma once
 
+#include <string>
+
 #include "sky_common.h"
 
 namespace sky {
@@ -72,6 +74,12 @@ void densities(int n, int prec, const void* const* psi, const GridArgs* g, int n
 // n complex values between precisions (0 = complex128, 1 = complex64).
 void convert_states(const void* src, int src_prec, void* dst, int dst_prec, size_t n,
                     hipStream_t st);
+
+// ---- allocation-free scratch (k_noalloc.hip): a fixed device array per
+// device; noalloc_scratch returns its address on the current device (looked
+// up once per device), or -1 with a message.
+size_t noalloc_scratch_capacity();   // doubles
+int noalloc_scratch(double** ptr, std::string* err);
 
 // ---- mean field and energy (k_fields.hip)
 struct Skyrme {

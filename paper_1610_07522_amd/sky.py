@@ -37,6 +37,7 @@ _F32_VIEWS = ("pc_params", "pc_grad", "pc_samples", "pc_gains")
 
 # Symbols declared in include/sky.h, in order.
 EXPORTS = ("sky_workspace_size", "sky_create", "sky_init_box", "sky_apply_h",
+           "sky_apply_h_noalloc",
            "sky_damped_step", "sky_orthonormalize", "sky_densities", "sky_iterate",
            "sky_get_view", "sky_set_states", "sky_get_states", "sky_get_iteration",
            "sky_set_iteration", "sky_set_timing", "sky_get_timing", "sky_get_precision",
@@ -114,6 +115,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                       ctypes.POINTER(vp)]),
         "sky_init_box": (ctypes.c_int, [vp, vp, vp]),
         "sky_apply_h": (ctypes.c_int, [vp, i32, vp, vp, i32, vp]),
+        "sky_apply_h_noalloc": (ctypes.c_int, [vp, i32, vp, vp, i32, vp]),
         "sky_damped_step": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, i32, vp]),
         "sky_orthonormalize": (ctypes.c_int, [vp, i32, vp, vp, vp, vp]),
         "sky_densities": (ctypes.c_int, [vp]),
@@ -247,6 +249,10 @@ class Box:
 
     def apply_h(self, q, psi, hpsi, nstates, eps=None):
         _check(self.lib.sky_apply_h(self.ctx, q, _ptr(psi), _ptr(hpsi), nstates, _ptr(eps)))
+
+    def apply_h_noalloc(self, q, psi, hpsi, nstates, eps=None):
+        _check(self.lib.sky_apply_h_noalloc(self.ctx, q, _ptr(psi), _ptr(hpsi), nstates,
+                                            _ptr(eps)))
 
     def damped_step(self, q, psi, hpsi, eps, phi, nstates, r2=None):
         _check(self.lib.sky_damped_step(self.ctx, q, _ptr(psi), _ptr(hpsi), _ptr(eps),
