@@ -284,6 +284,34 @@ def copy_bandwidth(dev) -> dict:
                 note="torch device copy of 1 GiB, bytes read + written")
 
 
+def workload_of(args):
+    """The named workload with the requested extra states (a fraction of each
+    species' particles, rounded up)."""
+    import dataclasses
+
+    from paper_1610_07522_amd import inputs
+    w = inputs.WORKLOADS[args.workload]
+    if args.extra > 0:
+        w = dataclasses.replace(w, extra_n=math.ceil(args.extra * w.n_neutrons),
+                                extra_p=math.ceil(args.extra * w.n_protons))
+    return w
+
+
+def form_kwargs(args) -> dict:
+    """Descriptor options of the iteration form chosen on the command line."""
+    from paper_1610_07522_amd import inputs, sky
+    kw = dict(update=sky.SKY_UPDATE_PAPER if args.update == "paper" else sky.SKY_UPDATE_EXACT,
+              one_h=args.one_h)
+    if args.twists > 1:
+        kw["twists"] = inputs.special_twists(args.twists)
+    return kw
+
+
+def form_config(args, w) -> dict:
+    return dict(extra_states=[w.extra_n, w.extra_p], update=args.update, one_h=args.one_h,
+                twists=(args.twists ** 3 if args.twists > 1 else 1))
+
+
 def bench_batch(args) -> int:
     """64 independent uneven boxes (16^3-32^3, 102-512 nucleons, mixed
     precision): box-iterations per second of the batched driver (worker
@@ -354,17 +382,19 @@ def bench_to_residual(args) -> int:
 
     from paper_1610_07522_amd import inputs, sky
 
-    w = inputs.WORKLOADS[args.workload]
+    w = workload_of(args)
     dev = torch.device("cuda:0")
     rn, rp = inputs.raw_states(w)
     dn, dp = torch.from_numpy(rn).to(dev), torch.from_numpy(rp).to(dev)
     del rn, rp
     tol = args.to_residual
     results = {}
+    t_start = time.perf_counter()
     for mode in args.modes.split(","):
         prec = sky.SKY_FP64 if mode == "fp64" else sky.SKY_MIXED
         ladder = args.ladder if prec == sky.SKY_MIXED else 0.0
-        box = sky.Box(sky.desc_from_workload(w, precision=prec, ladder_tol=ladder), device=dev)
+        box = sky.Box(sky.desc_from_workload(w, precision=prec, ladder_tol=ladder,
+                                             **form_kwargs(args)), device=dev)
         box.init_box(dn, dp)
         if args.tune_cache != "off":
             box.autotune(args.tune_cache)
@@ -397,6 +427,9 @@ def bench_to_residual(args) -> int:
                 f"E {rep['energy']:.6f}, {time.perf_counter() - t0:.1f} s")
             if armed and rep["converged"]:
                 break
+            if args.max_seconds > 0 and time.perf_counter() - t_start > args.max_seconds:
+                log(f"[{mode}] stopped at the wall-time cap of {args.max_seconds:.0f} s")
+                break
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         ritz = [box.view("ritz", q).cpu().tolist() for q in range(2)]
@@ -410,7 +443,7 @@ def bench_to_residual(args) -> int:
         torch.cuda.empty_cache()
     out = dict(metric=f"time to residual {tol:g}", workload=w.name, tol=tol,
                min_iter=args.min_iter, max_iter=args.max_iter, ladder=args.ladder,
-               results=results)
+               form=form_config(args, w), results=results)
     if "mixed" in results and "fp64" in results:
         out["fp64_over_mixed_time"] = results["fp64"]["seconds"] / results["mixed"]["seconds"]
     if "mixed" in results and "learned" in results:
@@ -454,6 +487,16 @@ def main() -> int:
                     help="--to-residual: the tolerance is tested from this iteration on")
     ap.add_argument("--ladder", type=float, default=0.0,
                     help="--to-residual: mixed forms switch to FP64 at this Delta-eps (0: never)")
+    ap.add_argument("--extra", type=float, default=0.0,
+                    help="extra unoccupied states per species, as a fraction of its particles")
+    ap.add_argument("--twists", type=int, default=1,
+                    help="k: twist-averaged boundary conditions over the k^3 special twists")
+    ap.add_argument("--update", choices=("exact", "paper"), default="exact",
+                    help="subspace update: exact Rayleigh-Ritz or the paper-literal Z C")
+    ap.add_argument("--one-h", action="store_true",
+                    help="one h application per iteration (h psi carried through the update)")
+    ap.add_argument("--max-seconds", type=float, default=0.0,
+                    help="--to-residual: stop every form once this much wall time has passed")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three 1 GiB device-to-device copies (HBM counter scale)")
     args = ap.parse_args()
@@ -485,12 +528,13 @@ def main() -> int:
             print("bench.py needs a ROCm GPU", file=sys.stderr)
             return 1
         return bench_batch(args)
-    w = inputs.WORKLOADS[args.workload]
+    w = workload_of(args)
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         return 1
     dev = torch.device("cuda:0")
-    log(f"workload {w.name}: {w.n}^3, {w.n_neutrons} n + {w.n_protons} p; generating inputs")
+    log(f"workload {w.name}: {w.n}^3, {w.n_neutrons} n + {w.n_protons} p "
+        f"(+{w.extra_n} + {w.extra_p} extra states); generating inputs")
     t0 = time.perf_counter()
     raw_n, raw_p = inputs.raw_states(w)
     dn = torch.from_numpy(raw_n).to(dev)
@@ -499,7 +543,8 @@ def main() -> int:
     log(f"inputs on device in {time.perf_counter() - t0:.1f} s")
 
     def run(precision: int):
-        box = sky.Box(sky.desc_from_workload(w, precision=precision), device=dev)
+        box = sky.Box(sky.desc_from_workload(w, precision=precision, **form_kwargs(args)),
+                      device=dev)
         t0 = time.perf_counter()
         box.init_box(dn, dp)
         torch.cuda.synchronize()
@@ -543,7 +588,8 @@ def main() -> int:
         data="synthetic",
         config=dict(workload=(f"{w.name}: {w.n}^3 grid, dx {w.dx} fm, {w.n_neutrons} n + "
                               f"{w.n_protons} p, rod-perturbed plane waves, SLy4"),
-                    grid=w.n, nucleons=w.n_states, precision=args.precision),
+                    grid=w.n, nucleons=w.n_states, precision=args.precision,
+                    **form_config(args, w)),
         roofline=roofline(timing, w, mixed),
         h_phase_hbm=h_phase_hbm(timing, w, mixed),
         hbm_phases=hbm_phases(timing, w, mixed),
