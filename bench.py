@@ -374,6 +374,102 @@ def bench_batch(args) -> int:
     return 0
 
 
+def bench_learned_protocol(args) -> int:
+    """The learned damping trained on other boxes and judged on held-out
+    ones.  Training: for seeds 100-131, the three box shapes of the 16^3
+    (8 n + 8 p, noise 0.1), 32^3 slab (640 n + 160 p) and 48^3 rod
+    (1600 n + 400 p) workloads are each iterated a few times in the mixed
+    form, rows are collected from both species and the network takes Adam
+    steps on them; the network is carried from box to box with
+    sky_set_preconditioner (Adam moments restart per box).  Evaluation: the
+    48^3 rod box with the held-out seeds 200-203, from the same states, plain
+    damping against the carried network (no further training), iterations
+    and wall time until Delta-eps <= tol (tested from min_iter on)."""
+    import dataclasses
+
+    import torch
+
+    from paper_1610_07522_amd import inputs, sky
+
+    dev = torch.device("cuda:0")
+    shapes = [(inputs.WORKLOADS["fermi16"], 20), (inputs.WORKLOADS["slab32"], 30),
+              (inputs.WORKLOADS["rod48"], 30)]
+    params = None
+    t0 = time.perf_counter()
+    losses = []
+    for seed in range(100, 132):
+        for base, warm in shapes:
+            w = dataclasses.replace(base, seed=seed)
+            rn, rp = inputs.raw_states(w)
+            box = sky.Box(sky.desc_from_workload(w, precision=sky.SKY_MIXED), device=dev)
+            box.init_box(torch.from_numpy(rn).to(dev), torch.from_numpy(rp).to(dev))
+            del rn, rp
+            if params is not None:
+                box.set_preconditioner(params)
+            box.iterate(warm)
+            for q in range(2):
+                box.precond_collect(q)
+            losses.append(box.precond_train(args.train_steps, 1e-3))
+            params = box.view("pc_params").clone()
+            box.close()
+            del box
+            torch.cuda.empty_cache()
+        log(f"training: seeds 100-{seed} done, loss {losses[-1]:.4e}, "
+            f"{time.perf_counter() - t0:.0f} s")
+    t_train = time.perf_counter() - t0
+    tol = args.to_residual if args.to_residual > 0 else 0.1
+    evals = []
+    for seed in range(200, 204):
+        w = dataclasses.replace(inputs.WORKLOADS["rod48"], seed=seed)
+        rn, rp = inputs.raw_states(w)
+        dn, dp = torch.from_numpy(rn).to(dev), torch.from_numpy(rp).to(dev)
+        del rn, rp
+        row = dict(seed=seed)
+        for mode in ("plain", "learned"):
+            box = sky.Box(sky.desc_from_workload(w, precision=sky.SKY_MIXED), device=dev)
+            box.init_box(dn, dp)
+            if args.tune_cache != "off":
+                box.autotune(args.tune_cache)
+                box.init_box(dn, dp)
+            if mode == "learned":
+                box.set_preconditioner(params)
+                box.precond_use(True, 0.05, 0)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            its, rep = 0, None
+            while its < args.max_iter:
+                armed = its >= args.min_iter
+                chunk = min(100, args.max_iter - its) if armed else min(100, args.min_iter - its)
+                rep = box.iterate(chunk, tol if armed else 0.0)
+                its += rep["iters"]
+                if armed and rep["converged"]:
+                    break
+            torch.cuda.synchronize()
+            row[mode] = dict(iterations=its, seconds=time.perf_counter() - ts,
+                             converged=bool(rep["converged"]), residual=rep["residual"],
+                             energy=rep["energy"])
+            log(f"eval seed {seed} {mode}: {its} iterations, {row[mode]['seconds']:.1f} s, "
+                f"residual {rep['residual']:.3e}")
+            box.close()
+            del box
+            torch.cuda.empty_cache()
+        evals.append(row)
+    out = dict(metric=f"learned damping trained on other boxes: time to residual {tol:g}, "
+                      "48^3 rod box, held-out seeds",
+               train=dict(seeds="100-131", boxes=3 * 32, shapes=[s[0].name for s in shapes],
+                          warm_iterations=[s[1] for s in shapes], adam_steps_per_box=args.train_steps,
+                          seconds=t_train, last_loss=losses[-1]),
+               tol=tol, min_iter=args.min_iter, max_iter=args.max_iter, evaluation=evals)
+    done = [e for e in evals if e["plain"]["converged"] and e["learned"]["converged"]]
+    if done:
+        out["mean_iterations_ratio"] = sum(e["plain"]["iterations"] / e["learned"]["iterations"]
+                                           for e in done) / len(done)
+        out["mean_time_ratio"] = sum(e["plain"]["seconds"] / e["learned"]["seconds"]
+                                     for e in done) / len(done)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_to_residual(args) -> int:
     """Iterations and wall time until Delta-eps <= tol on one workload, for
     the mixed form, the FP64 form and the mixed form with the learned damping
@@ -495,6 +591,8 @@ def main() -> int:
                     help="subspace update: exact Rayleigh-Ritz or the paper-literal Z C")
     ap.add_argument("--one-h", action="store_true",
                     help="one h application per iteration (h psi carried through the update)")
+    ap.add_argument("--train-steps", type=int, default=20,
+                    help="--workload learned_protocol: Adam steps per training box")
     ap.add_argument("--max-seconds", type=float, default=0.0,
                     help="--to-residual: stop every form once this much wall time has passed")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -518,6 +616,11 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_bytes=4 << 28, copies=3)), flush=True)
         return 0
+    if args.workload == "learned_protocol":
+        if not torch.cuda.is_available():
+            print("bench.py needs a ROCm GPU", file=sys.stderr)
+            return 1
+        return bench_learned_protocol(args)
     if args.to_residual > 0:
         if not torch.cuda.is_available():
             print("bench.py needs a ROCm GPU", file=sys.stderr)

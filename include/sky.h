@@ -318,14 +318,19 @@ typedef struct {
   int32_t overlap_split[2];  /* split-K factor of the I/H product per species    */
   int32_t square_split[2];   /* split-K factor of the subspace products          */
   int32_t from_cache;        /* 1: every shape came from the cache file          */
+  int32_t overlap_waves[2];  /* mixed: waves per 128 x 128 tile of the overlap   */
+                             /* product, 8 (32 x 64 each) or 4 (64 x 64 each)  */
+  int32_t combine_waves[2];  /* mixed: the same for the recombination product    */
 } sky_tuning;
 
 /* Autotuner.  Picks, for this box, the fastest of a few candidate launch
  * shapes of the dominant kernels: the pencils per workgroup of the h passes
  * or their LDS-slice variant, the slice or line variant of the damped step
- * (the FFT line kernels, keyed by grid size and precision), and the split-K
+ * (the FFT line kernels, keyed by grid size and precision), the split-K
  * factors of the overlap/Hamiltonian product and of the square subspace
- * products (keyed by state count, grid points and precision).  Candidates
+ * products, and (mixed) the wave layout of the 128 x 128 output tiles of the
+ * overlap and recombination plane products (keyed by state count, grid
+ * points and precision).  Candidates
  * are timed with HIP events on the context's own buffers: call after
  * sky_init_box; the run overwrites h psi, phi and the subspace matrices (the
  * states are untouched).  Every candidate computes the same result up to

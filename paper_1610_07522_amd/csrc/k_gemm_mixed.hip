@@ -75,44 +75,65 @@ __device__ inline void split8(const float2 (&z)[8], int S, u4 (&w)[NP]) {
   }
 }
 
-// Output tiles of BT x BT per workgroup of 8 waves (4 x 2); each wave owns
-// 32 rows x 64 columns (2 x 4 blocks of 16 x 16).  The MFMA accumulates in
-// FP32 with a bias (its accumulator additions do not round to nearest: a
-// 13824-long contraction in one accumulator is off by ~1e-5), so the MFMA
-// accumulator is folded every FLUSH steps (256 contraction elements) into a
-// second FP32 accumulator by ordinary round-to-nearest additions, whose
-// errors are unbiased; workgroup chunks (at most CHUNK_MAX elements) are
-// summed in FP64 afterwards.
+// Output tiles of BT x BT per workgroup.  Two wave layouts: 8 waves (4 x 2),
+// each owning 32 rows x 64 columns (2 x 4 blocks of 16 x 16, two waves per
+// SIMD), or 4 waves (2 x 2), each owning 64 x 64 (4 x 4 blocks, one wave per
+// SIMD with the MFMA accumulators in the accumulation registers: two thirds
+// of the LDS reads per MFMA).  The MFMA accumulates in FP32 with a bias (its
+// accumulator additions do not round to nearest: a 13824-long contraction in
+// one accumulator is off by ~1e-5), so the MFMA accumulator is folded every
+// FLUSH steps (256 contraction elements) into a second FP32 accumulator by
+// ordinary round-to-nearest additions, whose errors are unbiased; workgroup
+// chunks (at most CHUNK_MAX elements) are summed in FP64 afterwards.
 constexpr int BT = 128;
-constexpr int BG = 512;
 constexpr int FLUSH = 8;
 constexpr long CHUNK_MAX = 16384;
+
+template <int NWM, int NWN> struct Lay {
+  static constexpr int WAVES = NWM * NWN, THREADS = 64 * WAVES;
+  static constexpr int WR = BT / NWM, WC = BT / NWN;   // rows, columns of a wave
+  static constexpr int IB = WR / 16, JB = WC / 16;     // 16 x 16 blocks of a wave
+  static constexpr int CH = BT * 4 / THREADS;          // 8-element chunks per thread per tile
+};
+using Lay8 = Lay<4, 2>;
+using Lay4 = Lay<2, 2>;
 
 // LDS tile: [plane][row][RS] fp16 bit patterns.
 struct Tile {
   unsigned short v[NP][BT][RS];
 };
 
-// One thread's share of a BT-row x KB tile: row tid/4, 8 elements at (tid%4)*8.
-struct Frag {
-  u4 v[NP];
+// One thread's share of a BT-row x KB tile: chunk e = tid + c * THREADS is
+// row e/4, 8 elements at (e%4)*8.
+template <int CH> struct Frag {
+  u4 v[CH][NP];
 };
 
-__device__ inline void gload(Frag& f, const unsigned short* __restrict__ P, size_t psz, long ld,
+template <int CH, int NT>
+__device__ inline void gload(Frag<CH>& f, const unsigned short* __restrict__ P, size_t psz, long ld,
                              int row0, int R, long k0, int tid) {
-  const int row = tid >> 2, kk = (tid & 3) * 8;
-  const bool ok = row0 + row < R;
 #pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    f.v[p] = u4{0, 0, 0, 0};
-    if (ok) f.v[p] = *reinterpret_cast<const u4*>(P + p * psz + size_t(row0 + row) * ld + k0 + kk);
+  for (int c = 0; c < CH; ++c) {
+    const int e = tid + c * NT;
+    const int row = e >> 2, kk = (e & 3) * 8;
+    const bool ok = row0 + row < R;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      f.v[c][p] = u4{0, 0, 0, 0};
+      if (ok) f.v[c][p] = *reinterpret_cast<const u4*>(P + p * psz + size_t(row0 + row) * ld + k0 + kk);
+    }
   }
 }
 
-__device__ inline void sstore(Tile& t, const Frag& f, int tid) {
-  const int row = tid >> 2, kk = (tid & 3) * 8;
+template <int CH, int NT>
+__device__ inline void sstore(Tile& t, const Frag<CH>& f, int tid) {
 #pragma unroll
-  for (int p = 0; p < NP; ++p) *reinterpret_cast<u4*>(&t.v[p][row][kk]) = f.v[p];
+  for (int c = 0; c < CH; ++c) {
+    const int e = tid + c * NT;
+    const int row = e >> 2, kk = (e & 3) * 8;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) *reinterpret_cast<u4*>(&t.v[p][row][kk]) = f.v[c][p];
+  }
 }
 
 __device__ inline h8 ld8(const Tile& t, int p, int row, int k8) {
@@ -125,16 +146,17 @@ __device__ inline h8 neg8(h8 x) {
   return __builtin_bit_cast(h8, u);
 }
 
-struct Acc {
-  f4 re[2][4], im[2][4];   // MFMA accumulators
-  f4 hr[2][4], hi[2][4];   // folded sums
+template <int IB, int JB> struct Acc {
+  f4 re[IB][JB], im[IB][JB];   // MFMA accumulators
+  f4 hr[IB][JB], hi[IB][JB];   // folded sums
 };
 
-__device__ inline void zero(Acc& a) {
+template <int IB, int JB>
+__device__ inline void zero(Acc<IB, JB>& a) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < IB; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < JB; ++j) {
       a.re[i][j] = f4{0, 0, 0, 0};
       a.im[i][j] = f4{0, 0, 0, 0};
       a.hr[i][j] = f4{0, 0, 0, 0};
@@ -142,11 +164,12 @@ __device__ inline void zero(Acc& a) {
     }
 }
 
-__device__ inline void fold(Acc& a) {
+template <int IB, int JB>
+__device__ inline void fold(Acc<IB, JB>& a) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < IB; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < JB; ++j) {
       a.hr[i][j] += a.re[i][j];
       a.hi[i][j] += a.im[i][j];
       a.re[i][j] = f4{0, 0, 0, 0};
@@ -156,42 +179,46 @@ __device__ inline void fold(Acc& a) {
 
 #define MF(a, b, c) c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0)
 
-// acc += op(A) B^T over one KB step; A rows = tile rows of sA, B cols = rows
-// of sB; op(A) = conj(A) if CONJA.  Three split products per real product.
-// MFMA operands: lane l supplies 8 consecutive contraction elements starting
-// at 8*(l/16) of row (or column) l%16.  The A fragments of the wave's two row
-// blocks stay in registers while the four column blocks stream past.
-template <bool CONJA>
-__device__ inline void step(Acc& acc, const Tile& sA, const Tile& sB, int wm, int wn, int lane) {
+// acc += op(A) B^T over one KB step for the wave's block rows starting at
+// row0 (of sA) and block columns starting at col0 (rows of sB); op(A) =
+// conj(A) if CONJA.  Three split products per real product.  MFMA operands:
+// lane l supplies 8 consecutive contraction elements starting at 8*(l/16) of
+// row (or column) l%16.  The A fragments of the wave's row blocks stay in
+// registers while its column blocks stream past; the negated imaginary part
+// of each B fragment is formed once per fragment.
+template <bool CONJA, int IB, int JB>
+__device__ inline void step(Acc<IB, JB>& acc, const Tile& sA, const Tile& sB, int row0, int col0,
+                            int lane) {
   const int r = lane & 15, k8 = (lane >> 4) * 8;
-  h8 ar[2][2], ai[2][2];
+  h8 ar[IB][2], ai[IB][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < IB; ++i)
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      ar[i][s] = ld8(sA, plane(0, s), wm * 32 + i * 16 + r, k8);
-      ai[i][s] = ld8(sA, plane(1, s), wm * 32 + i * 16 + r, k8);
+      ar[i][s] = ld8(sA, plane(0, s), row0 + i * 16 + r, k8);
+      ai[i][s] = ld8(sA, plane(1, s), row0 + i * 16 + r, k8);
       if (CONJA) ai[i][s] = neg8(ai[i][s]);
     }
   // split pairs (p, q): hh, hl, lh
   constexpr int P[3] = {0, 0, 1};
   constexpr int Q[3] = {0, 1, 0};
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    h8 br[2], bi[2];
+  for (int j = 0; j < JB; ++j) {
+    h8 br[2], bi[2], nbi[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      br[s] = ld8(sB, plane(0, s), wn * 64 + j * 16 + r, k8);
-      bi[s] = ld8(sB, plane(1, s), wn * 64 + j * 16 + r, k8);
+      br[s] = ld8(sB, plane(0, s), col0 + j * 16 + r, k8);
+      bi[s] = ld8(sB, plane(1, s), col0 + j * 16 + r, k8);
+      nbi[s] = neg8(bi[s]);
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < IB; ++i)
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
         const int p = P[t], q = Q[t];
         // re += ar br - ai bi ; im += ar bi + ai br   (ai already negated for conj)
         MF(ar[i][p], br[q], acc.re[i][j]);
-        MF(neg8(ai[i][p]), bi[q], acc.re[i][j]);
+        MF(ai[i][p], nbi[q], acc.re[i][j]);
         MF(ar[i][p], bi[q], acc.im[i][j]);
         MF(ai[i][p], br[q], acc.im[i][j]);
       }
@@ -201,16 +228,16 @@ __device__ inline void step(Acc& acc, const Tile& sA, const Tile& sB, int wm, in
 
 // Output element of register e of lane l in a 16x16 block (measured):
 // row 4*(l/16) + e, column l%16.
-template <typename F>
-__device__ inline void foreach_out(const Acc& acc, int wm, int wn, int lane, F f) {
+template <int IB, int JB, typename F>
+__device__ inline void foreach_out(const Acc<IB, JB>& acc, int row0, int col0, int lane, F f) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < IB; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < JB; ++j)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int row = wm * 32 + i * 16 + 4 * (lane >> 4) + e;
-        const int col = wn * 64 + j * 16 + (lane & 15);
+        const int row = row0 + i * 16 + 4 * (lane >> 4) + e;
+        const int col = col0 + j * 16 + (lane & 15);
         f(row, col, acc.hr[i][j][e] + acc.re[i][j][e], acc.hi[i][j][e] + acc.im[i][j][e]);
       }
 }
@@ -336,10 +363,12 @@ k_split_t(const void* __restrict__ xv, int R, long C, long ldr, const unsigned i
 // [p][m][k].  One-dimensional grid of split*npair*nz workgroups; with
 // split % 8 == 0, XCD x computes the chunks s = x mod 8, so that the tiles
 // of one chunk are shared through that XCD's L2.
-__global__ void __launch_bounds__(BG, 1)
+template <int NWM, int NWN>
+__global__ void __launch_bounds__(64 * NWM * NWN, 1)
 k_overlap_planes(const unsigned short* __restrict__ PA, const unsigned short* __restrict__ PB0,
                  const unsigned short* __restrict__ PB1, int m, long k, int npair, int split,
                  int nz, float2* __restrict__ part) {
+  using L = Lay<NWM, NWN>;
   __shared__ Tile sA, sB;
   const int T = npair * nz;
   const int w = blockIdx.x;
@@ -357,33 +386,41 @@ k_overlap_planes(const unsigned short* __restrict__ PA, const unsigned short* __
   int ta, tb;
   tri_pair(pair, ta, tb);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int row0 = (wave / NWN) * L::WR, col0 = (wave % NWN) * L::WC;
   const long nst = k / KB;
   const long c0 = nst * s / split, c1 = nst * (s + 1) / split;
   const long ld = k + NT_PAD;
   const size_t psz = size_t(m) * ld;
-  Acc acc;
+  Acc<L::IB, L::JB> acc;
   zero(acc);
   int nacc = 0;
-  Frag fa, fb;
-  if (c0 < c1) {
-    gload(fa, PA, psz, ld, ta * BT, m, c0 * KB, tid);
-    gload(fb, PB, psz, ld, tb * BT, m, c0 * KB, tid);
+  // two waves per SIMD: the next step's tiles are fetched into registers
+  // while this step's MFMAs run; one wave per SIMD has no registers to spare
+  // for that and fetches each step's tiles right before storing them
+  constexpr bool PREFETCH = L::WAVES == 8;
+  Frag<L::CH> fa, fb;
+  if (PREFETCH && c0 < c1) {
+    gload<L::CH, L::THREADS>(fa, PA, psz, ld, ta * BT, m, c0 * KB, tid);
+    gload<L::CH, L::THREADS>(fb, PB, psz, ld, tb * BT, m, c0 * KB, tid);
   }
   for (long c = c0; c < c1; ++c) {
-    sstore(sA, fa, tid);
-    sstore(sB, fb, tid);
-    __syncthreads();
-    if (c + 1 < c1) {
-      gload(fa, PA, psz, ld, ta * BT, m, (c + 1) * KB, tid);
-      gload(fb, PB, psz, ld, tb * BT, m, (c + 1) * KB, tid);
+    if (!PREFETCH) {
+      gload<L::CH, L::THREADS>(fa, PA, psz, ld, ta * BT, m, c * KB, tid);
+      gload<L::CH, L::THREADS>(fb, PB, psz, ld, tb * BT, m, c * KB, tid);
     }
-    step<true>(acc, sA, sB, wm, wn, lane);
+    sstore<L::CH, L::THREADS>(sA, fa, tid);
+    sstore<L::CH, L::THREADS>(sB, fb, tid);
+    __syncthreads();
+    if (PREFETCH && c + 1 < c1) {
+      gload<L::CH, L::THREADS>(fa, PA, psz, ld, ta * BT, m, (c + 1) * KB, tid);
+      gload<L::CH, L::THREADS>(fb, PB, psz, ld, tb * BT, m, (c + 1) * KB, tid);
+    }
+    step<true>(acc, sA, sB, row0, col0, lane);
     __syncthreads();
     if (++nacc == FLUSH) { fold(acc); nacc = 0; }
   }
   float2* out = part + (size_t(z) * npair + pair) * split * BT * BT + size_t(s) * BT * BT;
-  foreach_out(acc, wm, wn, lane, [&](int row, int col, float re, float im) {
+  foreach_out(acc, row0, col0, lane, [&](int row, int col, float re, float im) {
     out[row * BT + col] = make_float2(re, im);
   });
 }
@@ -423,10 +460,12 @@ k_overlap_reduce_planes(const float2* __restrict__ part, int npair, int split, i
 // tiles); with nv % 8 == 0, XCD x computes the column tiles v = x mod 8, all
 // row tiles of one column tile in a row, so that each X^T tile is fetched
 // from HBM once.
-__global__ void __launch_bounds__(BG, 1)
+template <int NWM, int NWN>
+__global__ void __launch_bounds__(64 * NWM * NWN, 1)
 k_combine_planes(const unsigned short* __restrict__ PU, const unsigned short* __restrict__ PX,
                  const unsigned int* __restrict__ mxU, const unsigned int* __restrict__ mxX,
                  float2* __restrict__ Y, int m, long k, long mpad, int nb) {
+  using L = Lay<NWM, NWN>;
   __shared__ Tile sA, sB;
   const long nv = k / BT;
   const long w = blockIdx.x;
@@ -444,28 +483,35 @@ k_combine_planes(const unsigned short* __restrict__ PU, const unsigned short* __
   const int b0 = bt * BT;
   const int SUX = scale_exp(*mxU) + scale_exp(*mxX);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int row0 = (wave / NWN) * L::WR, col0 = (wave % NWN) * L::WC;
   const size_t pszU = size_t(m) * mpad, pszX = size_t(k) * mpad;
   const unsigned short* PXv = PX + size_t(v0) * mpad;
-  Acc acc;
+  Acc<L::IB, L::JB> acc;
   zero(acc);
   int nacc = 0;
-  Frag fa, fb;
-  gload(fa, PU, pszU, mpad, b0, m, 0, tid);
-  gload(fb, PXv, pszX, mpad, 0, BT, 0, tid);
+  constexpr bool PREFETCH = L::WAVES == 8;   // as in k_overlap_planes
+  Frag<L::CH> fa, fb;
+  if (PREFETCH) {
+    gload<L::CH, L::THREADS>(fa, PU, pszU, mpad, b0, m, 0, tid);
+    gload<L::CH, L::THREADS>(fb, PXv, pszX, mpad, 0, BT, 0, tid);
+  }
   for (long a0 = 0; a0 < mpad; a0 += KB) {
-    sstore(sA, fa, tid);
-    sstore(sB, fb, tid);
-    __syncthreads();
-    if (a0 + KB < mpad) {
-      gload(fa, PU, pszU, mpad, b0, m, a0 + KB, tid);
-      gload(fb, PXv, pszX, mpad, 0, BT, a0 + KB, tid);
+    if (!PREFETCH) {
+      gload<L::CH, L::THREADS>(fa, PU, pszU, mpad, b0, m, a0, tid);
+      gload<L::CH, L::THREADS>(fb, PXv, pszX, mpad, 0, BT, a0, tid);
     }
-    step<false>(acc, sA, sB, wm, wn, lane);
+    sstore<L::CH, L::THREADS>(sA, fa, tid);
+    sstore<L::CH, L::THREADS>(sB, fb, tid);
+    __syncthreads();
+    if (PREFETCH && a0 + KB < mpad) {
+      gload<L::CH, L::THREADS>(fa, PU, pszU, mpad, b0, m, a0 + KB, tid);
+      gload<L::CH, L::THREADS>(fb, PXv, pszX, mpad, 0, BT, a0 + KB, tid);
+    }
+    step<false>(acc, sA, sB, row0, col0, lane);
     __syncthreads();
     if (++nacc == FLUSH) { fold(acc); nacc = 0; }
   }
-  foreach_out(acc, wm, wn, lane, [&](int row, int col, float re, float im) {
+  foreach_out(acc, row0, col0, lane, [&](int row, int col, float re, float im) {
     const int b = b0 + row;
     if (b < m)
       Y[size_t(b) * k + v0 + col] = make_float2(ldexpf(re, -SUX), ldexpf(im, -SUX));
@@ -560,16 +606,24 @@ void split_planes_t(const void* x, int x_is_c128, int rows, long cols, const uns
 void overlap_lower_planes(const void* PA, const void* PB0, const void* PB1,
                           const unsigned int* mxA, const unsigned int* mxB0,
                           const unsigned int* mxB1, int m, long k, double scale, void* C0,
-                          void* C1, void* part, hipStream_t st, hipEvent_t* ev, int split_req) {
+                          void* C1, void* part, hipStream_t st, hipEvent_t* ev, int split_req,
+                          int waves) {
   if (m <= 0) return;
   const int nt = (m + BT - 1) / BT;
   const int npair = nt * (nt + 1) / 2;
   const int split = split_req > 0 ? split_req : overlap_split_mixed(m, k);
   const int nz = PB1 ? 2 : 1;
   if (ev) hipEventRecord(ev[0], st);
-  hipLaunchKernelGGL(k_overlap_planes, dim3(unsigned(split * npair * nz)), dim3(BG), 0, st,
-                     (const unsigned short*)PA, (const unsigned short*)PB0,
-                     (const unsigned short*)PB1, m, k, npair, split, nz, (float2*)part);
+  if (waves == 4)
+    hipLaunchKernelGGL((k_overlap_planes<2, 2>), dim3(unsigned(split * npair * nz)),
+                       dim3(Lay4::THREADS), 0, st, (const unsigned short*)PA,
+                       (const unsigned short*)PB0, (const unsigned short*)PB1, m, k, npair, split,
+                       nz, (float2*)part);
+  else
+    hipLaunchKernelGGL((k_overlap_planes<4, 2>), dim3(unsigned(split * npair * nz)),
+                       dim3(Lay8::THREADS), 0, st, (const unsigned short*)PA,
+                       (const unsigned short*)PB0, (const unsigned short*)PB1, m, k, npair, split,
+                       nz, (float2*)part);
   if (ev) hipEventRecord(ev[1], st);
   hipLaunchKernelGGL(k_overlap_reduce_planes, dim3(npair * RCH, nz), dim3(256), 0, st,
                      (const float2*)part, npair, split, m, scale, mxA, mxB0, PB1 ? mxB1 : mxB0,
@@ -577,13 +631,18 @@ void overlap_lower_planes(const void* PA, const void* PB0, const void* PB1,
 }
 
 void combine_planes(const void* PU, const void* PX, const unsigned int* mxU,
-                    const unsigned int* mxX, void* Y, int m, long k, hipStream_t st) {
+                    const unsigned int* mxX, void* Y, int m, long k, hipStream_t st, int waves) {
   if (m <= 0) return;
   const int nb = (m + BT - 1) / BT;
   const long nv = k / BT;
-  hipLaunchKernelGGL(k_combine_planes, dim3(unsigned(nv * nb)), dim3(BG), 0, st,
-                     (const unsigned short*)PU, (const unsigned short*)PX, mxU, mxX, (float2*)Y,
-                     m, k, planes_pad(m), nb);
+  if (waves == 4)
+    hipLaunchKernelGGL((k_combine_planes<2, 2>), dim3(unsigned(nv * nb)), dim3(Lay4::THREADS), 0,
+                       st, (const unsigned short*)PU, (const unsigned short*)PX, mxU, mxX,
+                       (float2*)Y, m, k, planes_pad(m), nb);
+  else
+    hipLaunchKernelGGL((k_combine_planes<4, 2>), dim3(unsigned(nv * nb)), dim3(Lay8::THREADS), 0,
+                       st, (const unsigned short*)PU, (const unsigned short*)PX, mxU, mxX,
+                       (float2*)Y, m, k, planes_pad(m), nb);
 }
 
 }  // namespace sky

@@ -527,6 +527,18 @@ void zero(double* p, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_zero, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, p, n);
 }
 
+__global__ void k_identity(double2* __restrict__ A, int m) {
+  const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= size_t(m) * m) return;
+  A[e] = make_double2((e / m == e % m) ? 1.0 : 0.0, 0.0);
+}
+
+void identity(void* A, int m, hipStream_t st) {
+  if (m <= 0) return;
+  const size_t mm = size_t(m) * m;
+  hipLaunchKernelGGL(k_identity, dim3(unsigned((mm + 255) / 256)), dim3(256), 0, st, (double2*)A, m);
+}
+
 __global__ void k_zero_f32(float* __restrict__ p, size_t n) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0f;

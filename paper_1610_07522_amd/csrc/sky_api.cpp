@@ -244,6 +244,8 @@ struct sky_ctx {
     int damp_xy = -1;   // -1: the default for the grid and precision
     int ovl[2] = {0, 0};
     int sq[2] = {0, 0};
+    int ovw[2] = {0, 0};   // waves per tile of the mixed overlap product (0: 8)
+    int cbw[2] = {0, 0};   // waves per tile of the mixed recombination (0: 8)
     int from_cache = 0;
   } tune;
   // learned preconditioner state
@@ -306,6 +308,9 @@ struct sky_ctx {
 };
 
 namespace {
+// waves per tile of the mixed plane products: 0 (untuned) selects 8
+int waves_of(int w) { return w == 4 ? 4 : 8; }
+
 hipEvent_t take_event(sky_ctx* c) {
   if (!c->pool.empty()) {
     hipEvent_t e = c->pool.back();
@@ -387,7 +392,7 @@ void subspace_matrices(sky_ctx* c, int s, const void* phi, const void* hphi,
   if (c->prec)
     overlap_lower_planes(c->at(c->lay.plA), c->at(c->lay.plA), c->at(c->lay.plB), mx, mx, mx + 1,
                          m, c->V, c->g.dV, I, H, c->at(c->lay.gemm_part), st,
-                         c->timing ? ev : nullptr, c->tune.ovl[q]);
+                         c->timing ? ev : nullptr, c->tune.ovl[q], waves_of(c->tune.ovw[q]));
   else
     overlap_lower(phi, phi, hphi, m, c->V, c->g.dV, I, H, c->at(c->lay.gemm_part), st,
                   c->timing ? ev : nullptr, c->tune.ovl[q]);
@@ -629,10 +634,12 @@ void subspace_combine(sky_ctx* c, int s, const void* phi, void* psi_out,
   if (c->prec) {
     plane_scale(U, 1, size_t(m) * m, mx + 2, st);
     split_planes_t(U, 1, m, m, mx + 2, c->at(c->lay.plU), st);
-    combine_planes(c->at(c->lay.plU), c->at(c->lay.plT), mx + 2, mx, psi_out, m, c->V, st);
+    combine_planes(c->at(c->lay.plU), c->at(c->lay.plT), mx + 2, mx, psi_out, m, c->V, st,
+                   waves_of(c->tune.cbw[q]));
     if (hphi) {   // the planes of (h phi)^T replace those of phi^T
       split_planes_t(hphi, 0, m, c->V, mx + 1, c->at(c->lay.plT), st);
-      combine_planes(c->at(c->lay.plU), c->at(c->lay.plT), mx + 2, mx + 1, hpsi_out, m, c->V, st);
+      combine_planes(c->at(c->lay.plU), c->at(c->lay.plT), mx + 2, mx + 1, hpsi_out, m, c->V, st,
+                     waves_of(c->tune.cbw[q]));
     }
   } else {
     combine(phi, U, psi_out, m, c->V, st);
@@ -1448,6 +1455,43 @@ int sky_autotune(sky_ctx* c, const char* cache_path, sky_tuning* out) {
       ++timed;
     }
     c->tune.ovl[q] = v;
+    if (c->prec) {
+      // waves per 128 x 128 tile of the overlap and recombination plane products
+      const std::string kow = "plane_waves_overlap/m" + std::to_string(m) + "/k" + std::to_string(c->V);
+      const std::string kcw = "plane_waves_combine/m" + std::to_string(m) + "/k" + std::to_string(c->V);
+      const int wc[2] = {8, 4};
+      unsigned int* mx = c->at<unsigned int>(c->lay.plS);
+      int wv = cache_get(kv, kow);
+      if (wv != 4 && wv != 8) {
+        plane_scale(c->psi(q), 0, size_t(m) * c->V, mx, st);
+        split_planes_nt(c->psi(q), m, c->V, mx, c->at(c->lay.plA), st);
+        wv = pick(st, wc, 2, [&](int wz) {
+          overlap_lower_planes(c->at(c->lay.plA), c->at(c->lay.plA), c->at(c->lay.plA), mx, mx, mx,
+                               m, c->V, c->g.dV, c->at(c->lay.matI), c->at(c->lay.matH),
+                               c->at(c->lay.gemm_part), st, nullptr, c->tune.ovl[q], wz);
+        });
+        cache_put(kv, kow, wv);
+        ++timed;
+      }
+      c->tune.ovw[q] = wv;
+      int cw = cache_get(kv, kcw);
+      if (cw != 4 && cw != 8) {
+        // any m x m transform times the states: the unit matrix's planes are
+        // timed like any other
+        identity(c->at(c->lay.matT), m, st);
+        plane_scale(c->at(c->lay.matT), 1, size_t(m) * m, mx + 2, st);
+        split_planes_t(c->at(c->lay.matT), 1, m, m, mx + 2, c->at(c->lay.plU), st);
+        plane_scale(c->psi(q), 0, size_t(m) * c->V, mx, st);
+        split_planes_t(c->psi(q), 0, m, c->V, mx, c->at(c->lay.plT), st);
+        cw = pick(st, wc, 2, [&](int wz) {
+          combine_planes(c->at(c->lay.plU), c->at(c->lay.plT), mx + 2, mx, c->phi(q), m, c->V, st,
+                         wz);
+        });
+        cache_put(kv, kcw, cw);
+        ++timed;
+      }
+      c->tune.cbw[q] = cw;
+    }
     // square-product split-K
     int cs[4];
     const int ns = square_split_candidates(m, cs);
@@ -1481,6 +1525,8 @@ int sky_get_tuning(sky_ctx* c, sky_tuning* out) {
   for (int q = 0; q < 2; ++q) {
     out->overlap_split[q] = c->tune.ovl[q];
     out->square_split[q] = c->tune.sq[q];
+    out->overlap_waves[q] = waves_of(c->tune.ovw[q]);
+    out->combine_waves[q] = waves_of(c->tune.cbw[q]);
   }
   out->from_cache = c->tune.from_cache;
   return SKY_OK;

@@ -136,11 +136,13 @@ void overlap_lower_planes(const void* PA, const void* PB0, const void* PB1,
                           const unsigned int* mxA, const unsigned int* mxB0,
                           const unsigned int* mxB1, int m, long k, double scale, void* C0,
                           void* C1, void* part, hipStream_t st, hipEvent_t* ev = nullptr,
-                          int split_req = 0);
+                          int split_req = 0, int waves = 8);
 // Y[b][v] = sum_a U[a][b] X[a][v] from the transposed planes of U (m x m)
-// and of X (m x k).
+// and of X (m x k).  waves: 8 (32 x 64 per wave) or 4 (64 x 64 per wave)
+// per 128 x 128 output tile, for both plane products.
 void combine_planes(const void* PU, const void* PX, const unsigned int* mxU,
-                    const unsigned int* mxX, void* Y, int m, long k, hipStream_t st);
+                    const unsigned int* mxX, void* Y, int m, long k, hipStream_t st,
+                    int waves = 8);
 // Fill the upper triangle of Hermitian C from the lower one (and make the
 // diagonal real), in place.
 void hermitian_fill(void* C, int m, hipStream_t st);
@@ -213,5 +215,7 @@ void inv_sqrt(double* w, int m, int* info, hipStream_t st, double floor_v = 0.0)
 // fill n doubles (floats) with zero (a kernel, so it can be captured in graphs)
 void zero(double* p, size_t n, hipStream_t st);
 void zero_f32(float* p, size_t n, hipStream_t st);
+// A = the m x m unit matrix (complex128).
+void identity(void* A, int m, hipStream_t st);
 
 }  // namespace sky

@@ -80,12 +80,15 @@ class Report(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("h_lines", ctypes.c_int32), ("damp_xy", ctypes.c_int32),
                 ("overlap_split", ctypes.c_int32 * 2), ("square_split", ctypes.c_int32 * 2),
-                ("from_cache", ctypes.c_int32)]
+                ("from_cache", ctypes.c_int32), ("overlap_waves", ctypes.c_int32 * 2),
+                ("combine_waves", ctypes.c_int32 * 2)]
 
     def as_dict(self) -> Dict[str, object]:
         return dict(h_lines=self.h_lines, damp_xy=self.damp_xy,
                     overlap_split=list(self.overlap_split),
-                    square_split=list(self.square_split), from_cache=bool(self.from_cache))
+                    square_split=list(self.square_split), from_cache=bool(self.from_cache),
+                    overlap_waves=list(self.overlap_waves),
+                    combine_waves=list(self.combine_waves))
 
 
 class SkyError(RuntimeError):

@@ -155,3 +155,51 @@ def test_damped_step_slices_large_grids(torch_mod, tmp_path, n, nn, np_, precisi
     torch.cuda.synchronize()
     phi_ref = x - so.damping(r_ref, g, mf.hb2m, w.damp_x0, w.damp_e0)
     assert rel_err(to_host(phi), phi_ref) <= (2e-6 if precision else 1e-11)
+
+
+@pytest.mark.parametrize("case", ["n32_70p33_slab", "n24_200p50_rod"])
+def test_plane_product_wave_layouts(torch_mod, tmp_path, case):
+    """The split-FP16 overlap and recombination in both wave layouts of a
+    128 x 128 tile (8 waves of 32 x 64, 4 waves of 64 x 64), forced through
+    the tuning cache: the overlap against the oracle's overlap of the same
+    complex64 states (1e-6), the Rayleigh-Ritz combination against the
+    oracle's combination with the same U (1e-6), and the energies of three
+    iterations of the two layouts against each other (the other launch
+    shapes the tuner times may differ between the two boxes, and raw states
+    depend on eigenvector phases, so only span-invariant results are
+    compared)."""
+    import torch
+    from oracle import Grid
+    from oracle import solver as so
+    from paper_1610_07522_amd import sky
+    w = CASES[case]
+    raw = inputs.raw_states(w)
+    g = Grid(w.n, w.dx)
+    outs = {}
+    for waves in (8, 4):
+        box = _box(w, sky.SKY_MIXED)
+        box.init_box(to_dev(raw[0]), to_dev(raw[1]))
+        cache = tmp_path / f"w{waves}.json"
+        keys = {}
+        for q, m in ((0, w.n_neutrons), (1, w.n_protons)):
+            keys[f"plane_waves_overlap/m{m}/k{2 * w.n ** 3}"] = waves
+            keys[f"plane_waves_combine/m{m}/k{2 * w.n ** 3}"] = waves
+        cache.write_text(json.dumps(keys))
+        t = box.autotune(str(cache))
+        assert t["overlap_waves"] == [waves, waves] and t["combine_waves"] == [waves, waves]
+        box.init_box(to_dev(raw[0]), to_dev(raw[1]))
+        psi, hpsi = box.view("psi", 0), box.view("hpsi", 0)
+        m = psi.shape[0]
+        box.apply_h(0, psi, hpsi, m)
+        out = torch.empty_like(psi)
+        box.orthonormalize(0, psi, hpsi, out)
+        box.sync()
+        P = to_host(psi).astype(np.complex128)
+        I_ref = so.overlap(P, P, g)
+        I_gpu = to_host(box.view("overlap", 0))
+        assert rel_err(I_gpu, I_ref) <= 1e-6, (waves, "overlap")
+        U = to_host(box.view("umat", 0))
+        assert rel_err(to_host(out), so.combine(P, U)) <= 1e-6, (waves, "combine")
+        rep = box.iterate(3)
+        outs[waves] = rep["energy"]
+    assert abs(outs[4] - outs[8]) <= 2e-6 * abs(outs[8])
