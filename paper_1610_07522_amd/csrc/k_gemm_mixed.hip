@@ -184,8 +184,7 @@ __device__ inline void fold(Acc<IB, JB>& a) {
 // conj(A) if CONJA.  Three split products per real product.  MFMA operands:
 // lane l supplies 8 consecutive contraction elements starting at 8*(l/16) of
 // row (or column) l%16.  The A fragments of the wave's row blocks stay in
-// registers while its column blocks stream past; the negated imaginary part
-// of each B fragment is formed once per fragment.
+// registers while its column blocks stream past.
 template <bool CONJA, int IB, int JB>
 __device__ inline void step(Acc<IB, JB>& acc, const Tile& sA, const Tile& sB, int row0, int col0,
                             int lane) {
@@ -204,24 +203,30 @@ __device__ inline void step(Acc<IB, JB>& acc, const Tile& sA, const Tile& sB, in
   constexpr int Q[3] = {0, 1, 0};
 #pragma unroll
   for (int j = 0; j < JB; ++j) {
-    h8 br[2], bi[2], nbi[2];
+    h8 br[2], bi[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       br[s] = ld8(sB, plane(0, s), col0 + j * 16 + r, k8);
       bi[s] = ld8(sB, plane(1, s), col0 + j * 16 + r, k8);
-      nbi[s] = neg8(bi[s]);
     }
+    // re += ar br - ai bi ; im += ar bi + ai br   (ai already negated for
+    // conj).  The row blocks i alternate innermost, so that MFMAs into one
+    // accumulator are 2 IB issues apart instead of back to back; each
+    // accumulator still sums its products in the order hh, hl, lh with the
+    // real part's two terms in a row.  The negation of ai is written at its
+    // use: measured 4% faster than negating each B fragment once.
 #pragma unroll
-    for (int i = 0; i < IB; ++i)
+    for (int t = 0; t < 3; ++t) {
+      const int p = P[t], q = Q[t];
 #pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        const int p = P[t], q = Q[t];
-        // re += ar br - ai bi ; im += ar bi + ai br   (ai already negated for conj)
-        MF(ar[i][p], br[q], acc.re[i][j]);
-        MF(ai[i][p], nbi[q], acc.re[i][j]);
-        MF(ar[i][p], bi[q], acc.im[i][j]);
-        MF(ai[i][p], br[q], acc.im[i][j]);
-      }
+      for (int i = 0; i < IB; ++i) MF(ar[i][p], br[q], acc.re[i][j]);
+#pragma unroll
+      for (int i = 0; i < IB; ++i) MF(ar[i][p], bi[q], acc.im[i][j]);
+#pragma unroll
+      for (int i = 0; i < IB; ++i) MF(neg8(ai[i][p]), bi[q], acc.re[i][j]);
+#pragma unroll
+      for (int i = 0; i < IB; ++i) MF(ai[i][p], br[q], acc.im[i][j]);
+    }
   }
 }
 #undef MF
