@@ -387,6 +387,7 @@ def bench_learned_protocol(args) -> int:
     and wall time until Delta-eps <= tol (tested from min_iter on)."""
     import dataclasses
 
+    import numpy as np
     import torch
 
     from paper_1610_07522_amd import inputs, sky
@@ -396,8 +397,11 @@ def bench_learned_protocol(args) -> int:
               (inputs.WORKLOADS["rod48"], 30)]
     params = None
     t0 = time.perf_counter()
-    losses = []
-    for seed in range(100, 132):
+    losses = [float("nan")]
+    if args.params_in:
+        params = torch.from_numpy(np.load(args.params_in)).to(dev)
+        log(f"network loaded from {args.params_in}")
+    for seed in (range(100, 132) if not args.params_in else ()):
         for base, warm in shapes:
             w = dataclasses.replace(base, seed=seed)
             rn, rp = inputs.raw_states(w)
@@ -417,9 +421,12 @@ def bench_learned_protocol(args) -> int:
         log(f"training: seeds 100-{seed} done, loss {losses[-1]:.4e}, "
             f"{time.perf_counter() - t0:.0f} s")
     t_train = time.perf_counter() - t0
+    if args.params_out:
+        np.save(args.params_out, params.cpu().numpy())
+        log(f"network saved to {args.params_out}")
     tol = args.to_residual if args.to_residual > 0 else 0.1
     evals = []
-    for seed in range(200, 204):
+    for seed in (range(200, 204) if args.eval_seeds > 0 else ())[:args.eval_seeds]:
         w = dataclasses.replace(inputs.WORKLOADS["rod48"], seed=seed)
         rn, rp = inputs.raw_states(w)
         dn, dp = torch.from_numpy(rn).to(dev), torch.from_numpy(rp).to(dev)
@@ -458,7 +465,8 @@ def bench_learned_protocol(args) -> int:
                       "48^3 rod box, held-out seeds",
                train=dict(seeds="100-131", boxes=3 * 32, shapes=[s[0].name for s in shapes],
                           warm_iterations=[s[1] for s in shapes], adam_steps_per_box=args.train_steps,
-                          seconds=t_train, last_loss=losses[-1]),
+                          seconds=t_train, last_loss=losses[-1],
+                          loaded_from=args.params_in or None),
                tol=tol, min_iter=args.min_iter, max_iter=args.max_iter, evaluation=evals)
     done = [e for e in evals if e["plain"]["converged"] and e["learned"]["converged"]]
     if done:
@@ -593,6 +601,12 @@ def main() -> int:
                     help="one h application per iteration (h psi carried through the update)")
     ap.add_argument("--train-steps", type=int, default=20,
                     help="--workload learned_protocol: Adam steps per training box")
+    ap.add_argument("--params-out", default="",
+                    help="--workload learned_protocol: save the trained network (.npy)")
+    ap.add_argument("--params-in", default="",
+                    help="--workload learned_protocol: skip training, load this network")
+    ap.add_argument("--eval-seeds", type=int, default=4,
+                    help="--workload learned_protocol: held-out seeds evaluated (0-4)")
     ap.add_argument("--max-seconds", type=float, default=0.0,
                     help="--to-residual: stop every form once this much wall time has passed")
     ap.add_argument("--calibrate-copy", action="store_true",
