@@ -426,7 +426,8 @@ def bench_learned_protocol(args) -> int:
         log(f"network saved to {args.params_out}")
     tol = args.to_residual if args.to_residual > 0 else 0.1
     evals = []
-    for seed in (range(200, 204) if args.eval_seeds > 0 else ())[:args.eval_seeds]:
+    first = min(max(args.eval_from, 200), 203)
+    for seed in range(first, min(first + max(args.eval_seeds, 0), 204)):
         w = dataclasses.replace(inputs.WORKLOADS["rod48"], seed=seed)
         rn, rp = inputs.raw_states(w)
         dn, dp = torch.from_numpy(rn).to(dev), torch.from_numpy(rp).to(dev)
@@ -443,7 +444,7 @@ def bench_learned_protocol(args) -> int:
                 box.precond_use(True, 0.05, 0)
             torch.cuda.synchronize()
             ts = time.perf_counter()
-            its, rep = 0, None
+            its, rep, shown = 0, None, ts
             while its < args.max_iter:
                 armed = its >= args.min_iter
                 chunk = min(100, args.max_iter - its) if armed else min(100, args.min_iter - its)
@@ -451,6 +452,9 @@ def bench_learned_protocol(args) -> int:
                 its += rep["iters"]
                 if armed and rep["converged"]:
                     break
+                if time.perf_counter() - shown > 30:
+                    shown = time.perf_counter()
+                    log(f"eval seed {seed} {mode}: iteration {its}, residual {rep['residual']:.3e}")
             torch.cuda.synchronize()
             row[mode] = dict(iterations=its, seconds=time.perf_counter() - ts,
                              converged=bool(rep["converged"]), residual=rep["residual"],
@@ -607,6 +611,8 @@ def main() -> int:
                     help="--workload learned_protocol: skip training, load this network")
     ap.add_argument("--eval-seeds", type=int, default=4,
                     help="--workload learned_protocol: held-out seeds evaluated (0-4)")
+    ap.add_argument("--eval-from", type=int, default=200,
+                    help="--workload learned_protocol: first held-out seed (200-203)")
     ap.add_argument("--max-seconds", type=float, default=0.0,
                     help="--to-residual: stop every form once this much wall time has passed")
     ap.add_argument("--calibrate-copy", action="store_true",
