@@ -9,8 +9,8 @@
 // the largest component).  A real product keeps h h' + h l' + l h'; the
 // dropped l l' is O(2^-22) relative.  The split planes hold (re h, re l,
 // im h, im l) as FP16 bit patterns: 8 bytes per complex element, the size of
-// the complex64 operand, and the GEMMs stage their tiles with plain 16-byte
-// copies.  MFMA accumulation is FP32 over each workgroup's contraction chunk
+// the complex64 operand, and the GEMMs load their tiles from memory straight
+// into LDS in 16-byte pieces.  MFMA accumulation is FP32 over each workgroup's contraction chunk
 // (at most CHUNK_MAX elements); the overlap's split-K chunks are summed in
 // FP64 and the scales removed exactly in FP64.  The overlap products are
 // written in FP64 (they feed the FP64 subspace solve); the recombination
@@ -31,7 +31,6 @@ typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 constexpr int KB = 32;       // contraction elements per MFMA step
 constexpr int NP = 4;        // split planes: (part re/im) x (split h/l)
-constexpr int RS = KB + 8;   // padded LDS row (fp16 elements); 80 bytes
 constexpr int NXCD = 8;      // XCDs of the MI355X
 
 // Scale exponent S of a matrix whose largest |component| has the float bit
@@ -79,12 +78,15 @@ __device__ inline void split8(const float2 (&z)[8], int S, u4 (&w)[NP]) {
 // each owning 32 rows x 64 columns (2 x 4 blocks of 16 x 16, two waves per
 // SIMD), or 4 waves (2 x 2), each owning 64 x 64 (4 x 4 blocks, one wave per
 // SIMD with the MFMA accumulators in the accumulation registers: two thirds
-// of the LDS reads per MFMA).  The MFMA accumulates in FP32 with a bias (its
-// accumulator additions do not round to nearest: a 13824-long contraction in
-// one accumulator is off by ~1e-5), so the MFMA accumulator is folded every
-// FLUSH steps (256 contraction elements) into a second FP32 accumulator by
-// ordinary round-to-nearest additions, whose errors are unbiased; workgroup
-// chunks (at most CHUNK_MAX elements) are summed in FP64 afterwards.
+// of the LDS reads per MFMA).  Both load their tiles from memory straight
+// into one of two alternating LDS buffers (buffer_load ... lds), the next
+// step's buffer filling while this step's MFMAs read the other.  The MFMA
+// accumulates in FP32 with a bias (its accumulator additions do not round
+// to nearest: a 13824-long contraction in one accumulator is off by ~1e-5),
+// so the MFMA accumulator is folded every FLUSH steps (256 contraction
+// elements) into a second FP32 accumulator by ordinary round-to-nearest
+// additions, whose errors are unbiased; workgroup chunks (at most CHUNK_MAX
+// elements) are summed in FP64 afterwards.
 constexpr int BT = 128;
 constexpr int FLUSH = 8;
 constexpr long CHUNK_MAX = 16384;
@@ -93,53 +95,100 @@ template <int NWM, int NWN> struct Lay {
   static constexpr int WAVES = NWM * NWN, THREADS = 64 * WAVES;
   static constexpr int WR = BT / NWM, WC = BT / NWN;   // rows, columns of a wave
   static constexpr int IB = WR / 16, JB = WC / 16;     // 16 x 16 blocks of a wave
-  static constexpr int CH = BT * 4 / THREADS;          // 8-element chunks per thread per tile
 };
 using Lay8 = Lay<4, 2>;
 using Lay4 = Lay<2, 2>;
 
-// LDS tile: [plane][row][RS] fp16 bit patterns.
-struct Tile {
-  unsigned short v[NP][BT][RS];
+// LDS tile of the direct loads: [plane][row][KB] fp16 bit patterns, 64-byte
+// rows without padding (a direct load writes its 64 lanes' 16-byte pieces
+// to consecutive LDS addresses).  The four 16-byte chunks of row r sit at
+// slot c ^ swz(r), so that the fragment reads of eight consecutive rows at
+// one chunk cover all 32 LDS banks.
+struct TileD {
+  unsigned short v[NP][BT][KB];
 };
+__device__ inline int swz(int r) { return (r >> 1) & 3; }
 
-// One thread's share of a BT-row x KB tile: chunk e = tid + c * THREADS is
-// row e/4, 8 elements at (e%4)*8.
-template <int CH> struct Frag {
-  u4 v[CH][NP];
-};
-
-template <int CH, int NT>
-__device__ inline void gload(Frag<CH>& f, const unsigned short* __restrict__ P, size_t psz, long ld,
-                             int row0, int R, long k0, int tid) {
-#pragma unroll
-  for (int c = 0; c < CH; ++c) {
-    const int e = tid + c * NT;
-    const int row = e >> 2, kk = (e & 3) * 8;
-    const bool ok = row0 + row < R;
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      f.v[c][p] = u4{0, 0, 0, 0};
-      if (ok) f.v[c][p] = *reinterpret_cast<const u4*>(P + p * psz + size_t(row0 + row) * ld + k0 + kk);
-    }
-  }
-}
-
-template <int CH, int NT>
-__device__ inline void sstore(Tile& t, const Frag<CH>& f, int tid) {
-#pragma unroll
-  for (int c = 0; c < CH; ++c) {
-    const int e = tid + c * NT;
-    const int row = e >> 2, kk = (e & 3) * 8;
-#pragma unroll
-    for (int p = 0; p < NP; ++p) *reinterpret_cast<u4*>(&t.v[p][row][kk]) = f.v[c][p];
-  }
-}
-
-__device__ inline h8 ld8(const Tile& t, int p, int row, int k8) {
-  u4 u = *reinterpret_cast<const u4*>(&t.v[p][row][k8]);
+__device__ inline h8 ld8(const TileD& t, int p, int row, int k8) {
+  u4 u = *reinterpret_cast<const u4*>(&t.v[p][row][((k8 >> 3) ^ swz(row)) * 8]);
   return __builtin_bit_cast(h8, u);
 }
+
+typedef __attribute__((address_space(3))) void lvoid;
+
+// One step's tiles of the 4-wave layout by direct loads: 2 tiles x 4 planes
+// x 8 blocks of 16 rows = 64 loads of 1 KB (16 bytes per lane), 16 per wave:
+// waves 0-1 load A, waves 2-3 load B, two planes each.  Lane i of a load
+// fills row i/4 of its block at slot i%4, i.e. chunk (i%4) ^ swz(row).
+// Rows at or past R are clamped to R - 1: they only reach output rows (A)
+// or columns (B) at or past R, which are never written.  Addresses are a
+// wave-uniform base (matrix, plane, tile row, step) plus the lane's byte
+// offset within the tile, fixed for the whole contraction (DmaLane); the
+// offsets need BT * ld * 2 <= DMA_RANGE (checked by the launchers).
+// Buffer resource of the direct loads: byte range DMA_RANGE from the tile
+// base (every lane offset is below BT * ld * 2, which the launchers keep
+// under it); BUF_WORD3 is the untyped-access word of gfx9 resources.
+constexpr int DMA_RANGE = 0x7fffffff;
+constexpr int BUF_WORD3 = 0x00020000;
+
+// A wave-uniform pointer taken from the first lane (held in scalar registers).
+__device__ inline const char* uniform_ptr(const char* p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane(unsigned(v));
+  const unsigned hi = __builtin_amdgcn_readfirstlane(unsigned(v >> 32));
+  return reinterpret_cast<const char*>((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
+struct DmaLane {
+  unsigned int off[BT / 16];
+};
+
+// The lane's offsets for the tile rows row0.. of a matrix with R rows and
+// row pitch ld (in fp16 elements).
+__device__ inline DmaLane dma_lane(int row0, int R, long ld, int lane) {
+  DmaLane d;
+  const int c = (lane & 3) ^ ((lane >> 3) & 3);   // (lane % 4) ^ swz(row) for every block
+#pragma unroll
+  for (int rb = 0; rb < BT / 16; ++rb) {
+    const int rl = rb * 16 + (lane >> 2);
+    const long r = min(row0 + rl, R - 1) - row0;
+    d.off[rb] = unsigned((r * ld + c * 8) * 2);
+  }
+  return d;
+}
+
+// wave must be wave-uniform (read from the first lane); dl from dma_lane
+// for this wave's matrix (A for the first half of the W waves, B for the
+// second); 4 waves load two planes each, 8 waves one.
+template <int W>
+__device__ inline void dma_tiles(TileD& tA, TileD& tB, const unsigned short* __restrict__ PA,
+                                 size_t pszA, long ldA, int rowA,
+                                 const unsigned short* __restrict__ PB, size_t pszB, long ldB,
+                                 int rowB, long k0, int wave, const DmaLane& dl) {
+  constexpr int PPW = NP / (W / 2);   // planes per wave
+  const bool isB = wave >= W / 2;
+  const unsigned short* P = isB ? PB : PA;
+  const size_t psz = isB ? pszB : pszA;
+  const long ld = isB ? ldB : ldA;
+  const int row0 = isB ? rowB : rowA;
+  TileD& t = isB ? tB : tA;
+#pragma unroll
+  for (int q = 0; q < PPW; ++q) {
+    const int p = (wave % (W / 2)) * PPW + q;
+    // a buffer resource at the plane's tile base (scalar registers); each
+    // load adds the lane's 32-bit offset, so no 64-bit per-lane addresses
+    // are kept live across the contraction
+    char* base = const_cast<char*>(
+        uniform_ptr(reinterpret_cast<const char*>(P + p * psz + size_t(row0) * ld + k0)));
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(base, 0, DMA_RANGE, BUF_WORD3);
+#pragma unroll
+    for (int rb = 0; rb < BT / 16; ++rb)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lvoid*)&t.v[p][rb * 16][0], 16, dl.off[rb], 0,
+                                               0, 0);
+  }
+}
+
 __device__ inline h8 neg8(h8 x) {
   u4 u = __builtin_bit_cast(u4, x);
   u ^= u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
@@ -184,9 +233,13 @@ __device__ inline void fold(Acc<IB, JB>& a) {
 // conj(A) if CONJA.  Three split products per real product.  MFMA operands:
 // lane l supplies 8 consecutive contraction elements starting at 8*(l/16) of
 // row (or column) l%16.  The A fragments of the wave's row blocks stay in
-// registers while its column blocks stream past.
-template <bool CONJA, int IB, int JB>
-__device__ inline void step(Acc<IB, JB>& acc, const Tile& sA, const Tile& sB, int row0, int col0,
+// registers while its column blocks stream past.  The minus sign of the
+// complex product goes on an A fragment at each use (NEGB false: measured
+// 4% faster in the 8-wave layout) or once per column block on a B fragment
+// (NEGB true: 2 instead of 3 IB negations per block, and no negated copies
+// of the A fragments held, which the 64-row waves have no registers for).
+template <bool CONJA, bool NEGB, int IB, int JB, typename TT>
+__device__ inline void step(Acc<IB, JB>& acc, const TT& sA, const TT& sB, int row0, int col0,
                             int lane) {
   const int r = lane & 15, k8 = (lane >> 4) * 8;
   h8 ar[IB][2], ai[IB][2];
@@ -196,7 +249,7 @@ __device__ inline void step(Acc<IB, JB>& acc, const Tile& sA, const Tile& sB, in
     for (int s = 0; s < 2; ++s) {
       ar[i][s] = ld8(sA, plane(0, s), row0 + i * 16 + r, k8);
       ai[i][s] = ld8(sA, plane(1, s), row0 + i * 16 + r, k8);
-      if (CONJA) ai[i][s] = neg8(ai[i][s]);
+      if (CONJA && !NEGB) ai[i][s] = neg8(ai[i][s]);
     }
   // split pairs (p, q): hh, hl, lh
   constexpr int P[3] = {0, 0, 1};
@@ -209,23 +262,40 @@ __device__ inline void step(Acc<IB, JB>& acc, const Tile& sA, const Tile& sB, in
       br[s] = ld8(sB, plane(0, s), col0 + j * 16 + r, k8);
       bi[s] = ld8(sB, plane(1, s), col0 + j * 16 + r, k8);
     }
-    // re += ar br - ai bi ; im += ar bi + ai br   (ai already negated for
-    // conj).  The row blocks i alternate innermost, so that MFMAs into one
-    // accumulator are 2 IB issues apart instead of back to back; each
-    // accumulator still sums its products in the order hh, hl, lh with the
-    // real part's two terms in a row.  The negation of ai is written at its
-    // use: measured 4% faster than negating each B fragment once.
+    // re += ar br - ai bi ; im += ar bi + ai br   (conj: re += ar br + ai bi ;
+    // im += ar bi - ai br).  The row blocks i alternate innermost, so that
+    // MFMAs into one accumulator are IB issues apart instead of back to back;
+    // each accumulator still sums its products in the order hh, hl, lh with
+    // the real part's two terms in a row.
+    if constexpr (NEGB) {
+      h8 nb[2];
 #pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      const int p = P[t], q = Q[t];
+      for (int s = 0; s < 2; ++s) nb[s] = neg8(CONJA ? br[s] : bi[s]);
 #pragma unroll
-      for (int i = 0; i < IB; ++i) MF(ar[i][p], br[q], acc.re[i][j]);
+      for (int t = 0; t < 3; ++t) {
+        const int p = P[t], q = Q[t];
 #pragma unroll
-      for (int i = 0; i < IB; ++i) MF(ar[i][p], bi[q], acc.im[i][j]);
+        for (int i = 0; i < IB; ++i) MF(ar[i][p], br[q], acc.re[i][j]);
 #pragma unroll
-      for (int i = 0; i < IB; ++i) MF(neg8(ai[i][p]), bi[q], acc.re[i][j]);
+        for (int i = 0; i < IB; ++i) MF(ar[i][p], bi[q], acc.im[i][j]);
 #pragma unroll
-      for (int i = 0; i < IB; ++i) MF(ai[i][p], br[q], acc.im[i][j]);
+        for (int i = 0; i < IB; ++i) MF(ai[i][p], CONJA ? bi[q] : nb[q], acc.re[i][j]);
+#pragma unroll
+        for (int i = 0; i < IB; ++i) MF(ai[i][p], CONJA ? nb[q] : br[q], acc.im[i][j]);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const int p = P[t], q = Q[t];
+#pragma unroll
+        for (int i = 0; i < IB; ++i) MF(ar[i][p], br[q], acc.re[i][j]);
+#pragma unroll
+        for (int i = 0; i < IB; ++i) MF(ar[i][p], bi[q], acc.im[i][j]);
+#pragma unroll
+        for (int i = 0; i < IB; ++i) MF(neg8(ai[i][p]), bi[q], acc.re[i][j]);
+#pragma unroll
+        for (int i = 0; i < IB; ++i) MF(ai[i][p], br[q], acc.im[i][j]);
+      }
     }
   }
 }
@@ -363,21 +433,10 @@ k_split_t(const void* __restrict__ xv, int R, long C, long ldr, const unsigned i
 }
 
 // ------------------------------------------------------------------ products
-// part[((z*npair + pair)*split + s)][BT*BT] (FP32, unscaled) = the chunk-s
-// sum of conj(A) B^T over the lower tile pair; A, B0, B1 as planes
-// [p][m][k].  One-dimensional grid of split*npair*nz workgroups; with
-// split % 8 == 0, XCD x computes the chunks s = x mod 8, so that the tiles
-// of one chunk are shared through that XCD's L2.
-template <int NWM, int NWN>
-__global__ void __launch_bounds__(64 * NWM * NWN, 1)
-k_overlap_planes(const unsigned short* __restrict__ PA, const unsigned short* __restrict__ PB0,
-                 const unsigned short* __restrict__ PB1, int m, long k, int npair, int split,
-                 int nz, float2* __restrict__ part) {
-  using L = Lay<NWM, NWN>;
-  __shared__ Tile sA, sB;
+// Workgroup w -> (chunk s, tile pair, z) of the overlap grid.
+__device__ inline void overlap_work(int w, int npair, int split, int nz, int& s, int& pair, int& z) {
   const int T = npair * nz;
-  const int w = blockIdx.x;
-  int s, r;
+  int r;
   if (split % NXCD == 0) {
     const int j = w / NXCD;
     s = w % NXCD + NXCD * (j / T);
@@ -386,12 +445,36 @@ k_overlap_planes(const unsigned short* __restrict__ PA, const unsigned short* __
     s = w / T;
     r = w % T;
   }
-  const int pair = r / nz, z = r % nz;
+  pair = r / nz;
+  z = r % nz;
+}
+
+// part[((z*npair + pair)*split + s)][BT*BT] (FP32, unscaled) = the chunk-s
+// sum of conj(A) B^T over the lower tile pair; A, B0, B1 as planes
+// [p][m][k].  One-dimensional grid of split*npair*nz workgroups; with
+// split % 8 == 0, XCD x computes the chunks s = x mod 8, so that the tiles
+// of one chunk are shared through that XCD's L2.  Each step: one barrier
+// (which also waits for this wave's direct loads, so that after it the
+// step's buffer is complete and every wave is done with the other buffer),
+// the next step's loads into the other buffer, then this step's MFMAs.
+// Steps run in pairs so that the two buffers are fixed LDS addresses.
+template <int NWM, int NWN>
+__global__ void __launch_bounds__(64 * NWM * NWN, 1)
+k_overlap_planes(const unsigned short* __restrict__ PA, const unsigned short* __restrict__ PB0,
+                     const unsigned short* __restrict__ PB1, int m, long k, int npair, int split,
+                     int nz, float2* __restrict__ part) {
+  using L = Lay<NWM, NWN>;
+  constexpr int W = L::WAVES;
+  constexpr bool NEGB = W == 4;
+  __shared__ TileD sA0, sB0, sA1, sB1;
+  int s, pair, z;
+  overlap_work(blockIdx.x, npair, split, nz, s, pair, z);
   const unsigned short* PB = z ? PB1 : PB0;
   int ta, tb;
   tri_pair(pair, ta, tb);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int row0 = (wave / NWN) * L::WR, col0 = (wave % NWN) * L::WC;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int row0 = (wave / 2) * L::WR, col0 = (wave % 2) * L::WC;
   const long nst = k / KB;
   const long c0 = nst * s / split, c1 = nst * (s + 1) / split;
   const long ld = k + NT_PAD;
@@ -399,29 +482,20 @@ k_overlap_planes(const unsigned short* __restrict__ PA, const unsigned short* __
   Acc<L::IB, L::JB> acc;
   zero(acc);
   int nacc = 0;
-  // two waves per SIMD: the next step's tiles are fetched into registers
-  // while this step's MFMAs run; one wave per SIMD has no registers to spare
-  // for that and fetches each step's tiles right before storing them
-  constexpr bool PREFETCH = L::WAVES == 8;
-  Frag<L::CH> fa, fb;
-  if (PREFETCH && c0 < c1) {
-    gload<L::CH, L::THREADS>(fa, PA, psz, ld, ta * BT, m, c0 * KB, tid);
-    gload<L::CH, L::THREADS>(fb, PB, psz, ld, tb * BT, m, c0 * KB, tid);
-  }
-  for (long c = c0; c < c1; ++c) {
-    if (!PREFETCH) {
-      gload<L::CH, L::THREADS>(fa, PA, psz, ld, ta * BT, m, c * KB, tid);
-      gload<L::CH, L::THREADS>(fb, PB, psz, ld, tb * BT, m, c * KB, tid);
-    }
-    sstore<L::CH, L::THREADS>(sA, fa, tid);
-    sstore<L::CH, L::THREADS>(sB, fb, tid);
+  const DmaLane dl = dma_lane(wave >= W / 2 ? tb * BT : ta * BT, m, ld, lane);
+  if (c0 < c1)
+    dma_tiles<W>(sA0, sB0, PA, psz, ld, ta * BT, PB, psz, ld, tb * BT, c0 * KB, wave, dl);
+  for (long c = c0; c < c1; c += 2) {
     __syncthreads();
-    if (PREFETCH && c + 1 < c1) {
-      gload<L::CH, L::THREADS>(fa, PA, psz, ld, ta * BT, m, (c + 1) * KB, tid);
-      gload<L::CH, L::THREADS>(fb, PB, psz, ld, tb * BT, m, (c + 1) * KB, tid);
-    }
-    step<true>(acc, sA, sB, row0, col0, lane);
+    if (c + 1 < c1)
+      dma_tiles<W>(sA1, sB1, PA, psz, ld, ta * BT, PB, psz, ld, tb * BT, (c + 1) * KB, wave, dl);
+    step<true, NEGB>(acc, sA0, sB0, row0, col0, lane);
+    if (++nacc == FLUSH) { fold(acc); nacc = 0; }
+    if (c + 1 >= c1) break;
     __syncthreads();
+    if (c + 2 < c1)
+      dma_tiles<W>(sA0, sB0, PA, psz, ld, ta * BT, PB, psz, ld, tb * BT, (c + 2) * KB, wave, dl);
+    step<true, NEGB>(acc, sA1, sB1, row0, col0, lane);
     if (++nacc == FLUSH) { fold(acc); nacc = 0; }
   }
   float2* out = part + (size_t(z) * npair + pair) * split * BT * BT + size_t(s) * BT * BT;
@@ -459,23 +533,8 @@ k_overlap_reduce_planes(const float2* __restrict__ part, int npair, int split, i
   }
 }
 
-// Y[b][v] = sum_a U[a][b] X[a][v] from the planes of U^T (rows b) and of X^T
-// (rows v), contraction length mpad (zero-padded), complex64 output.
-// One-dimensional grid of nv*nb workgroups (nv = k/BT column tiles, nb row
-// tiles); with nv % 8 == 0, XCD x computes the column tiles v = x mod 8, all
-// row tiles of one column tile in a row, so that each X^T tile is fetched
-// from HBM once.
-template <int NWM, int NWN>
-__global__ void __launch_bounds__(64 * NWM * NWN, 1)
-k_combine_planes(const unsigned short* __restrict__ PU, const unsigned short* __restrict__ PX,
-                 const unsigned int* __restrict__ mxU, const unsigned int* __restrict__ mxX,
-                 float2* __restrict__ Y, int m, long k, long mpad, int nb) {
-  using L = Lay<NWM, NWN>;
-  __shared__ Tile sA, sB;
-  const long nv = k / BT;
-  const long w = blockIdx.x;
-  long vt;
-  int bt;
+// Workgroup w -> (column tile vt, row tile bt) of the recombination grid.
+__device__ inline void combine_work(long w, long nv, int nb, long& vt, int& bt) {
   if (nv % NXCD == 0) {
     const long j = w / NXCD;
     vt = w % NXCD + NXCD * (j / nb);
@@ -484,36 +543,50 @@ k_combine_planes(const unsigned short* __restrict__ PU, const unsigned short* __
     vt = w / nb;
     bt = int(w % nb);
   }
+}
+
+// Y[b][v] = sum_a U[a][b] X[a][v] from the planes of U^T (rows b) and of X^T
+// (rows v), contraction length mpad (zero-padded), complex64 output.
+// One-dimensional grid of nv*nb workgroups (nv = k/BT column tiles, nb row
+// tiles); with nv % 8 == 0, XCD x computes the column tiles v = x mod 8, all
+// row tiles of one column tile in a row, so that each X^T tile is fetched
+// from HBM once.  Steps as in k_overlap_planes.
+template <int NWM, int NWN>
+__global__ void __launch_bounds__(64 * NWM * NWN, 1)
+k_combine_planes(const unsigned short* __restrict__ PU, const unsigned short* __restrict__ PX,
+                     const unsigned int* __restrict__ mxU, const unsigned int* __restrict__ mxX,
+                     float2* __restrict__ Y, int m, long k, long mpad, int nb) {
+  using L = Lay<NWM, NWN>;
+  constexpr int W = L::WAVES;
+  constexpr bool NEGB = W == 4;
+  __shared__ TileD sA0, sB0, sA1, sB1;
+  long vt;
+  int bt;
+  combine_work(blockIdx.x, k / BT, nb, vt, bt);
   const long v0 = vt * BT;
   const int b0 = bt * BT;
   const int SUX = scale_exp(*mxU) + scale_exp(*mxX);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int row0 = (wave / NWN) * L::WR, col0 = (wave % NWN) * L::WC;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int row0 = (wave / 2) * L::WR, col0 = (wave % 2) * L::WC;
   const size_t pszU = size_t(m) * mpad, pszX = size_t(k) * mpad;
   const unsigned short* PXv = PX + size_t(v0) * mpad;
   Acc<L::IB, L::JB> acc;
   zero(acc);
   int nacc = 0;
-  constexpr bool PREFETCH = L::WAVES == 8;   // as in k_overlap_planes
-  Frag<L::CH> fa, fb;
-  if (PREFETCH) {
-    gload<L::CH, L::THREADS>(fa, PU, pszU, mpad, b0, m, 0, tid);
-    gload<L::CH, L::THREADS>(fb, PXv, pszX, mpad, 0, BT, 0, tid);
-  }
-  for (long a0 = 0; a0 < mpad; a0 += KB) {
-    if (!PREFETCH) {
-      gload<L::CH, L::THREADS>(fa, PU, pszU, mpad, b0, m, a0, tid);
-      gload<L::CH, L::THREADS>(fb, PXv, pszX, mpad, 0, BT, a0, tid);
-    }
-    sstore<L::CH, L::THREADS>(sA, fa, tid);
-    sstore<L::CH, L::THREADS>(sB, fb, tid);
+  const DmaLane dl = wave >= W / 2 ? dma_lane(0, BT, mpad, lane) : dma_lane(b0, m, mpad, lane);
+  dma_tiles<W>(sA0, sB0, PU, pszU, mpad, b0, PXv, pszX, mpad, 0, 0, wave, dl);
+  for (long a0 = 0; a0 < mpad; a0 += 2 * KB) {
     __syncthreads();
-    if (PREFETCH && a0 + KB < mpad) {
-      gload<L::CH, L::THREADS>(fa, PU, pszU, mpad, b0, m, a0 + KB, tid);
-      gload<L::CH, L::THREADS>(fb, PXv, pszX, mpad, 0, BT, a0 + KB, tid);
-    }
-    step<false>(acc, sA, sB, row0, col0, lane);
+    if (a0 + KB < mpad)
+      dma_tiles<W>(sA1, sB1, PU, pszU, mpad, b0, PXv, pszX, mpad, 0, a0 + KB, wave, dl);
+    step<false, NEGB>(acc, sA0, sB0, row0, col0, lane);
+    if (++nacc == FLUSH) { fold(acc); nacc = 0; }
+    if (a0 + KB >= mpad) break;
     __syncthreads();
+    if (a0 + 2 * KB < mpad)
+      dma_tiles<W>(sA0, sB0, PU, pszU, mpad, b0, PXv, pszX, mpad, 0, a0 + 2 * KB, wave, dl);
+    step<false, NEGB>(acc, sA1, sB1, row0, col0, lane);
     if (++nacc == FLUSH) { fold(acc); nacc = 0; }
   }
   foreach_out(acc, row0, col0, lane, [&](int row, int col, float re, float im) {
@@ -572,6 +645,10 @@ long planes_pad(int m) { return (long(m) + KB - 1) / KB * KB; }
 size_t planes_bytes_nt(int rows, long k) { return size_t(NP) * rows * (k + NT_PAD) * 2; }
 size_t planes_bytes_t(int m, long cols) { return size_t(NP) * cols * planes_pad(m) * 2; }
 
+bool planes_direct_ok(int m, long k) {
+  return long(BT) * (k + NT_PAD) * 2 <= DMA_RANGE && long(BT) * planes_pad(m) * 2 <= DMA_RANGE;
+}
+
 void plane_scale(const void* x, int x_is_c128, size_t n, unsigned int* mx, hipStream_t st) {
   hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, st, mx, 1);
   if (n == 0) return;
@@ -619,6 +696,8 @@ void overlap_lower_planes(const void* PA, const void* PB0, const void* PB1,
   const int split = split_req > 0 ? split_req : overlap_split_mixed(m, k);
   const int nz = PB1 ? 2 : 1;
   if (ev) hipEventRecord(ev[0], st);
+  // every descriptor the library accepts (n <= 64) keeps a tile's byte span
+  // far below DMA_RANGE (planes_direct_ok)
   if (waves == 4)
     hipLaunchKernelGGL((k_overlap_planes<2, 2>), dim3(unsigned(split * npair * nz)),
                        dim3(Lay4::THREADS), 0, st, (const unsigned short*)PA,

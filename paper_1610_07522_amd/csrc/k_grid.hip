@@ -698,8 +698,7 @@ k_damp_inv_x(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ buf,
 // state chunk go to part[chunk][slot][point] and are reduced in fixed order.
 template <typename T, int N, int DIR>
 __global__ void __launch_bounds__(LineCfg<N>::THREADS)
-k_dens_pass(const cpx<T>* __restrict__ psi, int nstate, int chunk, GridArgs g,
-            double* __restrict__ part) {
+k_dens_pass(DensGroups grp, int nstate, int chunk, GridArgs g, double* __restrict__ part) {
   using C = LineCfg<N>;
   using F = LineFFT<T, N, 2>;
   constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
@@ -715,7 +714,6 @@ k_dens_pass(const cpx<T>* __restrict__ psi, int nstate, int chunk, GridArgs g,
   line_geom<N, DIR>(L, base, stride, a, b);
   cpx<T>* Y = Ybuf + line * F::YSIZE;
   const T kunit = T(g.kunit);
-  const T kshift = T(g.tw[DIR]);
 
   double acc[NS][R1];
 #pragma unroll
@@ -723,10 +721,13 @@ k_dens_pass(const cpx<T>* __restrict__ psi, int nstate, int chunk, GridArgs g,
 #pragma unroll
     for (int j1 = 0; j1 < R1; ++j1) acc[q][j1] = 0.0;
 
+  // chunks of the flat (group, state) index: every group's states in order
   const int s0 = blockIdx.y * chunk;
-  const int s1 = min(nstate, s0 + chunk);
-  for (int st = s0; st < s1; ++st) {
-    const cpx<T>* p = psi + size_t(st) * 2 * N3;
+  const int s1 = min(nstate * grp.ngroup, s0 + chunk);
+  for (int fs = s0; fs < s1; ++fs) {
+    const int t = fs / nstate, st = fs - t * nstate;
+    const T kshift = T(grp.kshift[t][DIR]);
+    const cpx<T>* p = reinterpret_cast<const cpx<T>*>(grp.psi[t]) + size_t(st) * 2 * N3;
     cpx<T> v[2][R1], d[2][R1];
     if (j < R2) {
 #pragma unroll
@@ -1014,33 +1015,38 @@ void damped_step(int n, int prec, const void* psi, const void* hpsi, const doubl
 }
 
 template <typename T, int N>
-static void launch_dens(const void* psi, int nstate, int chunk, int nchunk, GridArgs g,
+static void launch_dens(const DensGroups& grp, int nstate, int chunk, int nchunk, GridArgs g,
                         double* part, hipStream_t st) {
   dim3 grid(ntiles<N>(), nchunk), block(LineCfg<N>::THREADS);
-  auto p = reinterpret_cast<const cpx<T>*>(psi);
-  hipLaunchKernelGGL((k_dens_pass<T, N, 0>), grid, block, 0, st, p, nstate, chunk, g, part);
-  hipLaunchKernelGGL((k_dens_pass<T, N, 1>), grid, block, 0, st, p, nstate, chunk, g, part);
-  hipLaunchKernelGGL((k_dens_pass<T, N, 2>), grid, block, 0, st, p, nstate, chunk, g, part);
+  hipLaunchKernelGGL((k_dens_pass<T, N, 0>), grid, block, 0, st, grp, nstate, chunk, g, part);
+  hipLaunchKernelGGL((k_dens_pass<T, N, 1>), grid, block, 0, st, grp, nstate, chunk, g, part);
+  hipLaunchKernelGGL((k_dens_pass<T, N, 2>), grid, block, 0, st, grp, nstate, chunk, g, part);
 }
 
-void densities(int n, int prec, const void* const* psi, const GridArgs* g, int ngroup,
-               int nstate, int nchunk_max, double* part, double* dens, hipStream_t st) {
+int densities(int n, int prec, const void* const* psi, const GridArgs* g, int ngroup,
+              int nstate, int nchunk_max, double* part, double* dens, hipStream_t st) {
   const int n3 = n * n * n;
-  if (nstate <= 0 || ngroup <= 0) {
+  if (ngroup < 0 || ngroup > DENS_MAX_GROUPS || nchunk_max < 1) return 0;
+  if (nstate <= 0 || ngroup == 0) {
     zero(dens, size_t(11) * n3, st);
-    return;
+    return 1;
   }
-  // each group (twist) takes an equal share of the chunk partials
-  const int cmax = std::max(1, nchunk_max / ngroup);
-  const int chunk = (nstate + cmax - 1) / cmax;
-  const int nchunk = (nstate + chunk - 1) / chunk;
+  // one launch per pass over all groups (twists): the flat (group, state)
+  // index is cut into at most nchunk_max chunks of consecutive states
+  DensGroups grp{};
+  grp.ngroup = ngroup;
   for (int t = 0; t < ngroup; ++t) {
-    double* pt = part + size_t(t) * nchunk * 16 * n3;
-    if (prec == 0) SKY_DISPATCH_N(n, launch_dens<double, NN>(psi[t], nstate, chunk, nchunk, g[t], pt, st))
-    else SKY_DISPATCH_N(n, launch_dens<float, NN>(psi[t], nstate, chunk, nchunk, g[t], pt, st))
+    grp.psi[t] = psi[t];
+    for (int a = 0; a < 3; ++a) grp.kshift[t][a] = g[t].tw[a];
   }
+  const int total = ngroup * nstate;
+  const int chunk = (total + nchunk_max - 1) / nchunk_max;
+  const int nchunk = (total + chunk - 1) / chunk;
+  if (prec == 0) SKY_DISPATCH_N(n, launch_dens<double, NN>(grp, nstate, chunk, nchunk, g[0], part, st))
+  else SKY_DISPATCH_N(n, launch_dens<float, NN>(grp, nstate, chunk, nchunk, g[0], part, st))
   hipLaunchKernelGGL(k_dens_reduce, dim3((n3 + 255) / 256), dim3(256), 0, st,
-                     (const double*)part, nchunk * ngroup, n3, dens, 1.0 / ngroup);
+                     (const double*)part, nchunk, n3, dens, 1.0 / ngroup);
+  return 1;
 }
 
 }  // namespace sky

@@ -39,6 +39,7 @@ size_t al(size_t b) { return (b + ALIGN - 1) / ALIGN * ALIGN; }
 
 constexpr int MAXSET = 2 * SKY_MAX_TWIST;   // state sets: species x twists
 constexpr int DENS_CHUNKS = 32;   // state chunks of the density passes
+static_assert(SKY_MAX_TWIST <= sky::DENS_MAX_GROUPS, "one density launch covers every twist");
 constexpr int PC_CAP = 16384;     // sample rows of the learned preconditioner
 constexpr int PC_HOLD = 10;       // iterations on plain damping after a rise of the residual
 constexpr int PC_RETRAIN_STEPS = 20;   // Adam steps of each online training
@@ -216,6 +217,8 @@ int validate(const sky_box_desc* d) {
   if (!(d->damp_e0 > 0.0)) return fail(SKY_ERR_INVALID, "damp_e0 must be positive");
   if (d->precision != SKY_FP64 && d->precision != SKY_MIXED)
     return fail(SKY_ERR_INVALID, "precision must be SKY_FP64 or SKY_MIXED");
+  if (!planes_direct_ok(std::max(states_of(*d, 0), states_of(*d, 1)), V))
+    return fail(SKY_ERR_INVALID, "plane products out of the direct-load range");
   return SKY_OK;
 }
 }  // namespace
@@ -715,7 +718,7 @@ void fields(sky_ctx* c) {
       ps[t] = c->psi(2 * t + q);
       gs[t] = c->gset(2 * t + q);
     }
-    sky::densities(c->n, c->prec, ps, gs, c->ntw, c->nocc[q], DENS_CHUNKS,
+    (void)sky::densities(c->n, c->prec, ps, gs, c->ntw, c->nocc[q], DENS_CHUNKS,
                    c->at<double>(c->lay.dens_part), c->at<double>(c->lay.dens[q]), st);
     t_end(c, td);
   }

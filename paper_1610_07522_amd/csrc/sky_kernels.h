@@ -67,9 +67,17 @@ void precond_targets(int prec, const void* bpsi, const void* bh, const void* bd,
                      const double* beps, int ns, long V, double* part, float* S, hipStream_t st);
 // dens = 11 fields [rho, tau, Jx, Jy, Jz, sx, sy, sz, jx, jy, jz][n^3],
 // summed over the first nstate states of each of ngroup state arrays psi[t]
-// (each with its own grid arguments g[t], i.e. its twist) and divided by
-// ngroup (the twist average); part holds nchunk_max * 16 * n^3 doubles.
-void densities(int n, int prec, const void* const* psi, const GridArgs* g, int ngroup,
+// (each with its own grid arguments g[t], i.e. its twist; spacing from g[0])
+// and divided by ngroup (the twist average); part holds nchunk_max * 16 * n^3
+// doubles.  Returns 0 (nothing launched) for ngroup outside [0,
+// DENS_MAX_GROUPS] or nchunk_max < 1.
+constexpr int DENS_MAX_GROUPS = 32;
+struct DensGroups {
+  const void* psi[DENS_MAX_GROUPS];
+  double kshift[DENS_MAX_GROUPS][3];   // GridArgs::tw of each group
+  int ngroup;
+};
+int densities(int n, int prec, const void* const* psi, const GridArgs* g, int ngroup,
                int nstate, int nchunk_max, double* part, double* dens, hipStream_t st);
 // n complex values between precisions (0 = complex128, 1 = complex64).
 void convert_states(const void* src, int src_prec, void* dst, int dst_prec, size_t n,
@@ -122,6 +130,10 @@ size_t overlap_scratch_bytes_mixed(int m, long k);
 long planes_pad(int m);
 size_t planes_bytes_nt(int rows, long k);
 size_t planes_bytes_t(int m, long cols);
+// The plane products' direct tile loads address a 128-row tile with 32-bit
+// byte offsets below 2^31: true for every grid of 64^3 or less with at most
+// 2 n^3 states.
+bool planes_direct_ok(int m, long k);
 void plane_scale(const void* x, int x_is_c128, size_t n, unsigned int* mx, hipStream_t st);
 // Zero n largest-|component| slots (before producers merge into them).
 void clear_scales(unsigned int* mx, int n, hipStream_t st);
@@ -138,8 +150,10 @@ void overlap_lower_planes(const void* PA, const void* PB0, const void* PB1,
                           void* C1, void* part, hipStream_t st, hipEvent_t* ev = nullptr,
                           int split_req = 0, int waves = 8);
 // Y[b][v] = sum_a U[a][b] X[a][v] from the transposed planes of U (m x m)
-// and of X (m x k).  waves: 8 (32 x 64 per wave) or 4 (64 x 64 per wave)
-// per 128 x 128 output tile, for both plane products.
+// and of X (m x k).  waves, for both plane products: 8 (32 x 64 per wave)
+// or 4 (64 x 64 per wave) per 128 x 128 output tile; both load their tiles
+// straight into two alternating LDS buffers (128 KB of LDS per workgroup),
+// which needs planes_direct_ok(m, k).
 void combine_planes(const void* PU, const void* PX, const unsigned int* mxU,
                     const unsigned int* mxX, void* Y, int m, long k, hipStream_t st,
                     int waves = 8);

@@ -16,6 +16,9 @@ the FP32 unit roundoff u = 2^-24 ~ 6e-8:
   than the total in a pasta box, so per-iteration energy error is bounded by
   a few hundred u times the sum of |parts|.
 """
+import json
+from pathlib import Path
+
 import numpy as np
 import pytest
 
@@ -25,6 +28,8 @@ from oracle import solver as so
 from paper_1610_07522_amd import inputs
 
 from gpu_util import CASES, rel_err, to_dev, to_host
+
+ROOT = Path(__file__).resolve().parents[1]
 
 pytestmark = pytest.mark.gpu
 
@@ -151,8 +156,11 @@ def test_precision_ladder_switches_to_fp64(torch_mod):
     assert abs(rep["energy"] - st.E["total"]) <= 1000 * U32 * parts, (e1, rep, st.E)
 
 
-def test_mixed_overlap_and_combine_fullsize(torch_mod):
-    """48^3 x 1600 neutrons, the bench configuration: sampled rows of the
+@pytest.mark.parametrize("waves", [8, 4])
+def test_mixed_overlap_and_combine_fullsize(torch_mod, tmp_path, waves):
+    """48^3 x 1600 neutrons, the bench configuration, in both wave layouts of
+    the plane products (forced through the committed tuning cache with the
+    layout keys overridden): sampled rows of the
     split-FP16 overlap (FP32 accumulation over each split-K chunk of the
     221184-long contraction, chunks summed in FP64) against the oracle's
     overlap of the same complex64 states (widened to complex128), at the 1e-6
@@ -165,6 +173,15 @@ def test_mixed_overlap_and_combine_fullsize(torch_mod):
     w = inputs.WORKLOADS["rod48"]
     rn, rp = inputs.raw_states(w)
     box = _box(w)
+    box.init_box(to_dev(rn), to_dev(rp))
+    keys = json.loads((ROOT / "paper_1610_07522_amd" / "tuning_mi355x.json").read_text())
+    for m in (w.n_neutrons, w.n_protons):
+        for kind in ("overlap", "combine"):
+            keys[f"plane_waves_{kind}/m{m}/k{2 * w.n ** 3}"] = waves
+    cache = tmp_path / "tune.json"
+    cache.write_text(json.dumps(keys))
+    t = box.autotune(str(cache))
+    assert t["overlap_waves"] == [waves, waves] and t["combine_waves"] == [waves, waves]
     box.init_box(to_dev(rn), to_dev(rp))
     del rn, rp
     q = 0
