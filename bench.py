@@ -328,7 +328,9 @@ def bench_batch(args) -> int:
     boxes = []
     t0 = time.perf_counter()
     for w in ws:
-        b = sky.Box(sky.desc_from_workload(w, precision=sky.SKY_MIXED), device=dev)
+        d = sky.desc_from_workload(w, precision=sky.SKY_MIXED)
+        d.dev_refine_steps = args.dev_refine_steps
+        b = sky.Box(d, device=dev)
         rn, rp = inputs.raw_states(w)
         dn, dp = torch.from_numpy(rn).to(dev), torch.from_numpy(rp).to(dev)
         del rn, rp
@@ -362,8 +364,9 @@ def bench_batch(args) -> int:
     reps = sky.batch_iterate_graph(boxes, args.threads, k, 0.0, chunk)
     torch.cuda.synchronize()
     t_dev = time.perf_counter() - t0
+    handovers = sum(r["eig_fallbacks"] for r in reps)
     log(f"batched ({args.threads} workers, device-decided iteration graphs, chunks of {chunk}): "
-        f"{64 * k} box-iterations in {t_dev:.3f} s")
+        f"{64 * k} box-iterations in {t_dev:.3f} s; {handovers} iterations finished on the host")
     grids = sorted({w.n for w in ws})
     out = dict(
         metric="box-iterations/s, 64 independent uneven boxes",
@@ -377,6 +380,8 @@ def bench_batch(args) -> int:
                               "slab/rod/random starts, SLy4"),
                     boxes=64, workers=args.threads, chunk=chunk,
                     driver="sky_batch_iterate_graph (device-decided iteration graphs)"),
+        handovers=handovers,
+        dev_refine_steps=args.dev_refine_steps or 4,
         host_decided=dict(value=64 * k / t_bat, unit="box-iter/s",
                           note="sky_batch_iterate: graph segments, subspace solve and "
                                "residual decided on the host every iteration"),
@@ -601,6 +606,9 @@ def main() -> int:
                     help="autotuner cache (launch shapes); 'off' keeps the defaults")
     ap.add_argument("--threads", type=int, default=16,
                     help="host workers of the batched driver (workload batch64)")
+    ap.add_argument("--dev-refine-steps", type=int, default=0,
+                    help="workload batch64: refinement steps of the device-decided iteration "
+                         "before a set is handed to the host (0: the library default)")
     ap.add_argument("--to-residual", type=float, default=0.0,
                     help="instead of iterations/s: iterations and time until Delta-eps <= this")
     ap.add_argument("--modes", default="mixed,fp64,learned",

@@ -111,6 +111,10 @@ typedef struct {
    * application fewer, one combination product more.  Needs
    * SKY_UPDATE_EXACT. */
   int32_t one_h;
+  /* Refinement steps of the device-decided iteration (sky_iterate_graph)
+   * before it hands the set to the host path: 0 = the default (4), else
+   * 1..39. */
+  int32_t dev_refine_steps;
 } sky_box_desc;
 
 typedef struct {
@@ -369,6 +373,37 @@ int sky_set_graphs(sky_ctx* c, int32_t enable);
  * twice.  Returns SKY_OK, or the first box error (message names the box). */
 int sky_batch_iterate(sky_ctx* const* ctxs, int32_t nbox, int32_t nthreads, int32_t max_iter,
                       double tol, sky_report* reps, int32_t* status);
+
+/* The iteration of Fig. 1 with every decision on the device, replayed as
+ * one HIP graph per iteration: chunk iterations are queued without any host
+ * synchronisation, then the host reads the box's flags once.  On the
+ * device: the Loewdin series' term count (Eq. Loewedin), the refinement's
+ * stop test, Delta-eps (Eq. convergence) and the stop at
+ * tol -- every kernel of the iteration reads the box's active flag first
+ * and returns at once when it is cleared, so a converged box does no more
+ * work (device-side convergence mask).  Where the host path would take
+ * another branch (Cholesky far from orthonormality, the Jacobi fallback),
+ * the device masks the rest of the iteration and the host finishes it on
+ * the host path after the chunk (rep->eig_fallbacks counts these).  Results
+ * equal sky_iterate's up to rounding: the series, refinement and residual
+ * sums are the same arithmetic, and the refinement always forms the E^2
+ * term.  The refinement takes at most desc.dev_refine_steps steps on the
+ * device.  Contexts with options whose decisions stay on the host (learned
+ * damping, the precision ladder, the paper-literal update, one_h, phase
+ * timing, the null stream) run sky_iterate.  chunk >= 1.  Errors: as
+ * sky_iterate. */
+int sky_iterate_graph(sky_ctx* c, int32_t max_iter, double tol, int32_t chunk, sky_report* rep);
+
+/* Batched uneven boxes with the device-decided iteration: the boxes are
+ * assigned to nthreads workers as in sky_batch_iterate; each worker queues
+ * a chunk of graph iterations for every unfinished box on its stream, then
+ * drains the stream once and reads every box's flags (one host
+ * synchronisation per worker per chunk, none per iteration).  reps[i] and
+ * status[i] as sky_iterate_graph returns them.  Returns SKY_OK, or the
+ * first box error (message names the box). */
+int sky_batch_iterate_graph(sky_ctx* const* ctxs, int32_t nbox, int32_t nthreads,
+                            int32_t max_iter, double tol, int32_t chunk, sky_report* reps,
+                            int32_t* status);
 
 /* Learned spectral preconditioner (an extension of Eq. dampstep, whose
  * damping x0 / (E0 + T_k) is fixed in the paper).  The learned step scales

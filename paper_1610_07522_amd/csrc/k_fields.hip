@@ -25,7 +25,8 @@ __device__ inline double kval(int f, int n, double kunit) {
 //   c1[d] = (1/n) sum_k -k^2 e^{2 pi i k d / n}  (Nyquist kept): second derivative
 // (both real: the multipliers are odd / even in k), tw[d] = e^{-2 pi i d / n}.
 // out[x] = sum_x' src[x'] c[(x - x') mod n] along a line.
-__global__ void k_field_tables(double* __restrict__ tab, int n, double kunit) {
+__global__ void k_field_tables(double* __restrict__ tab, int n, double kunit, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int d = threadIdx.x;
   if (d >= n) return;
   double a0 = 0.0, a1 = 0.0;
@@ -47,7 +48,8 @@ __global__ void k_field_tables(double* __restrict__ tab, int n, double kunit) {
 // o = [lap rho, d rho/dx, d rho/dy, d rho/dz, div J] at every point.
 __global__ void __launch_bounds__(256)
 k_field_derivs(const double* __restrict__ rho, const double* __restrict__ J, double* __restrict__ o,
-               int n, const double* __restrict__ tab) {
+               int n, const double* __restrict__ tab, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   __shared__ double c0[64], c1[64];
   if (threadIdx.x < n) {
     c0[threadIdx.x] = tab[threadIdx.x];
@@ -85,7 +87,8 @@ k_field_derivs(const double* __restrict__ rho, const double* __restrict__ J, dou
 // (forward e^{-2 pi i k j / n}; inverse the conjugate and s = 1/n).
 __global__ void __launch_bounds__(256)
 k_dft_pass(const double2* __restrict__ src, double2* __restrict__ dst, int n, int dir, int inverse,
-           const double* __restrict__ tab) {
+           const double* __restrict__ tab, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   __shared__ double twr[64], twi[64];
   if (threadIdx.x < n) {
     twr[threadIdx.x] = tab[2 * n + threadIdx.x];
@@ -113,13 +116,15 @@ k_dft_pass(const double2* __restrict__ src, double2* __restrict__ dst, int n, in
   dst[p] = make_double2(sc * sr, sc * si);
 }
 
-__global__ void k_real_to_cpx(const double* __restrict__ src, double2* __restrict__ dst, int n3) {
+__global__ void k_real_to_cpx(const double* __restrict__ src, double2* __restrict__ dst, int n3, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < n3) dst[r] = make_double2(src[r], 0.0);
 }
 
 // V(k) = 4 pi e2 rho(k) / |k|^2, zero at k = 0.
-__global__ void k_coulomb_mult(double2* __restrict__ buf, int n, double kunit, double e2) {
+__global__ void k_coulomb_mult(double2* __restrict__ buf, int n, double kunit, double e2, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n * n * n) return;
   int x = r % n, y = (r / n) % n, z = r / (n * n);
@@ -130,7 +135,8 @@ __global__ void k_coulomb_mult(double2* __restrict__ buf, int n, double kunit, d
   buf[r] = make_double2(f * v.x, f * v.y);
 }
 
-__global__ void k_cpx_real_part(const double2* __restrict__ src, double* __restrict__ dst, int n3) {
+__global__ void k_cpx_real_part(const double2* __restrict__ src, double* __restrict__ dst, int n3, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < n3) dst[r] = src[r].x;
 }
@@ -141,7 +147,8 @@ __global__ void k_mean_field(Skyrme sk, int n3, double dV, const double* __restr
                              const double* __restrict__ dp, const double* __restrict__ gn,
                              const double* __restrict__ gp, const double* __restrict__ vc,
                              double* __restrict__ mn, double* __restrict__ mp,
-                             double* __restrict__ epart) {
+                             double* __restrict__ epart, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   __shared__ double red[NTERM][E_THREADS / 64];
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   double e[NTERM] = {0, 0, 0, 0, 0, 0, 0};
@@ -192,7 +199,8 @@ __global__ void k_mean_field(Skyrme sk, int n3, double dV, const double* __restr
   }
 }
 
-__global__ void k_energy_final(const double* __restrict__ epart, int nblk, double* __restrict__ out) {
+__global__ void k_energy_final(const double* __restrict__ epart, int nblk, double* __restrict__ out, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   if (threadIdx.x != 0) return;
   double tot = 0.0;
   for (int t = 0; t < NTERM; ++t) {
@@ -221,31 +229,31 @@ void mean_field(int n, GridArgs g, const Skyrme& sk, const double* dens_n, const
   double2* bufA = reinterpret_cast<double2*>(scratch);
   double2* bufB = bufA + n3;
   double* tab = reinterpret_cast<double*>(bufB + n3);
-  hipLaunchKernelGGL(k_field_tables, dim3(1), dim3(64), 0, st, tab, n, g.kunit);
+  hipLaunchKernelGGL(k_field_tables, dim3(1), dim3(64), 0, st, tab, n, g.kunit, g_launch_gate);
   const unsigned nb = unsigned((n3 + 255) / 256);
   for (int q = 0; q < 2; ++q)   // lap rho (Nyquist kept), grad rho, div J (Nyquist zeroed)
     hipLaunchKernelGGL(k_field_derivs, dim3(nb), dim3(256), 0, st, dens[q], dens[q] + 2 * n3,
-                       der[q], n, (const double*)tab);
+                       der[q], n, (const double*)tab, g_launch_gate);
   const double* vcp = nullptr;
   if (sk.e2 != 0.0) {
-    hipLaunchKernelGGL(k_real_to_cpx, dim3(nb), dim3(256), 0, st, dens_p, bufA, n3);
-    hipLaunchKernelGGL(k_dft_pass, dim3(nb), dim3(256), 0, st, (const double2*)bufA, bufB, n, 0, 0, (const double*)tab);
-    hipLaunchKernelGGL(k_dft_pass, dim3(nb), dim3(256), 0, st, (const double2*)bufB, bufA, n, 1, 0, (const double*)tab);
-    hipLaunchKernelGGL(k_dft_pass, dim3(nb), dim3(256), 0, st, (const double2*)bufA, bufB, n, 2, 0, (const double*)tab);
-    hipLaunchKernelGGL(k_coulomb_mult, dim3(nb), dim3(256), 0, st, bufB, n, g.kunit, sk.e2);
-    hipLaunchKernelGGL(k_dft_pass, dim3(nb), dim3(256), 0, st, (const double2*)bufB, bufA, n, 2, 1, (const double*)tab);
-    hipLaunchKernelGGL(k_dft_pass, dim3(nb), dim3(256), 0, st, (const double2*)bufA, bufB, n, 1, 1, (const double*)tab);
-    hipLaunchKernelGGL(k_dft_pass, dim3(nb), dim3(256), 0, st, (const double2*)bufB, bufA, n, 0, 1, (const double*)tab);
-    hipLaunchKernelGGL(k_cpx_real_part, dim3(nb), dim3(256), 0, st, (const double2*)bufA, vc, n3);
+    hipLaunchKernelGGL(k_real_to_cpx, dim3(nb), dim3(256), 0, st, dens_p, bufA, n3, g_launch_gate);
+    hipLaunchKernelGGL(k_dft_pass, dim3(nb), dim3(256), 0, st, (const double2*)bufA, bufB, n, 0, 0, (const double*)tab, g_launch_gate);
+    hipLaunchKernelGGL(k_dft_pass, dim3(nb), dim3(256), 0, st, (const double2*)bufB, bufA, n, 1, 0, (const double*)tab, g_launch_gate);
+    hipLaunchKernelGGL(k_dft_pass, dim3(nb), dim3(256), 0, st, (const double2*)bufA, bufB, n, 2, 0, (const double*)tab, g_launch_gate);
+    hipLaunchKernelGGL(k_coulomb_mult, dim3(nb), dim3(256), 0, st, bufB, n, g.kunit, sk.e2, g_launch_gate);
+    hipLaunchKernelGGL(k_dft_pass, dim3(nb), dim3(256), 0, st, (const double2*)bufB, bufA, n, 2, 1, (const double*)tab, g_launch_gate);
+    hipLaunchKernelGGL(k_dft_pass, dim3(nb), dim3(256), 0, st, (const double2*)bufA, bufB, n, 1, 1, (const double*)tab, g_launch_gate);
+    hipLaunchKernelGGL(k_dft_pass, dim3(nb), dim3(256), 0, st, (const double2*)bufB, bufA, n, 0, 1, (const double*)tab, g_launch_gate);
+    hipLaunchKernelGGL(k_cpx_real_part, dim3(nb), dim3(256), 0, st, (const double2*)bufA, vc, n3, g_launch_gate);
     vcp = vc;
   } else {
     zero(vc, n3, st);
   }
   const int nblk = energy_nblocks(n);
   hipLaunchKernelGGL(k_mean_field, dim3(nblk), dim3(E_THREADS), 0, st, sk, n3, g.dV, dens_n,
-                     dens_p, (const double*)der_n, (const double*)der_p, vcp, mf_n, mf_p, epart);
+                     dens_p, (const double*)der_n, (const double*)der_p, vcp, mf_n, mf_p, epart, g_launch_gate);
   hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(64), 0, st, (const double*)epart, nblk,
-                     energy);
+                     energy, g_launch_gate);
 }
 
 }  // namespace sky

@@ -34,7 +34,8 @@ __device__ inline void tri_pair(int p, int& ta, int& tb) {
 // part[(z*npair + pair)*split + s][64*64] = sum over chunk s of conj(A) B^T.
 __global__ void __launch_bounds__(GT)
 k_overlap_lower(const double2* __restrict__ A, const double2* __restrict__ B0,
-                const double2* __restrict__ B1, int m, long k, int split, double2* __restrict__ part) {
+                const double2* __restrict__ B1, int m, long k, int split, double2* __restrict__ part, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   __shared__ double2 sA[TM * KP];
   __shared__ double2 sB[TM * KP];
   const int npair = gridDim.x;
@@ -70,7 +71,8 @@ k_overlap_lower(const double2* __restrict__ A, const double2* __restrict__ B0,
 
 // C[a][b] = scale * sum_s part[..][s][..] for the lower tiles.
 __global__ void k_overlap_reduce(const double2* __restrict__ part, int npair, int split, int m,
-                                 double scale, double2* __restrict__ C0, double2* __restrict__ C1) {
+                                 double scale, double2* __restrict__ C0, double2* __restrict__ C1, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int pair = blockIdx.x, z = blockIdx.y;
   double2* C = z ? C1 : C0;
   int ta, tb;
@@ -89,7 +91,8 @@ __global__ void k_overlap_reduce(const double2* __restrict__ part, int npair, in
   }
 }
 
-__global__ void k_hermitian_fill(double2* __restrict__ C, int m) {
+__global__ void k_hermitian_fill(double2* __restrict__ C, int m, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int row = blockIdx.y * 16 + threadIdx.y, col = blockIdx.x * 16 + threadIdx.x;
   if (row >= m || col >= m) return;
   if (col > row) {
@@ -104,7 +107,8 @@ __global__ void k_hermitian_fill(double2* __restrict__ C, int m) {
 // Y[b][v] = sum_a U[a][b] X[a][v]: M = b (rows of Y), N = v, K = a.
 __global__ void __launch_bounds__(GT)
 k_combine(const double2* __restrict__ X, const double2* __restrict__ U, double2* __restrict__ Y,
-          int m, long k) {
+          int m, long k, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   __shared__ double2 sA[TM * KP];   // [b][a]
   __shared__ double2 sB[TM * KP];   // [v][a]
   const long v0 = long(blockIdx.x) * TM;
@@ -145,7 +149,8 @@ k_combine(const double2* __restrict__ X, const double2* __restrict__ U, double2*
 template <int OPA, int OPB>
 __global__ void __launch_bounds__(GT)
 k_gemm_square(const double2* __restrict__ A, const double2* __restrict__ B,
-              double2* __restrict__ C, int m, int split, int lower) {
+              double2* __restrict__ C, int m, int split, int lower, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   __shared__ double2 sA[TM * KP];   // [row][k] of op(A)
   __shared__ double2 sB[TM * KP];   // [col][k] of op(B)
   constexpr int NE = TM * KC / GT;  // elements per thread and operand
@@ -214,7 +219,8 @@ k_gemm_square(const double2* __restrict__ A, const double2* __restrict__ B,
 
 // C[e] = sum_s part[s][e], in order.
 __global__ void k_sum_splits(const double2* __restrict__ part, int split, size_t n,
-                             double2* __restrict__ C) {
+                             double2* __restrict__ C, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= n) return;
   double2 acc = part[e];
@@ -284,7 +290,7 @@ void overlap_lower(const void* A, const void* B0, const void* B1, int m, long k,
   if (ev) hipEventRecord(ev[0], st);
   hipLaunchKernelGGL(k_overlap_lower, dim3(npair, split, nz), dim3(GT), 0, st,
                      (const double2*)A, (const double2*)B0, (const double2*)B1, m, k, split,
-                     (double2*)part);
+                     (double2*)part, g_launch_gate);
   if (ev) hipEventRecord(ev[1], st);
   overlap_reduce(part, npair, split, m, scale, C0, C1, nz, st);
 }
@@ -292,20 +298,20 @@ void overlap_lower(const void* A, const void* B0, const void* B1, int m, long k,
 void overlap_reduce(const void* part, int npair, int split, int m, double scale, void* C0,
                     void* C1, int nz, hipStream_t st) {
   hipLaunchKernelGGL(k_overlap_reduce, dim3(npair, nz), dim3(256), 0, st, (const double2*)part,
-                     npair, split, m, scale, (double2*)C0, (double2*)C1);
+                     npair, split, m, scale, (double2*)C0, (double2*)C1, g_launch_gate);
 }
 
 void hermitian_fill(void* C, int m, hipStream_t st) {
   if (m <= 0) return;
   dim3 grid((m + 15) / 16, (m + 15) / 16), block(16, 16);
-  hipLaunchKernelGGL(k_hermitian_fill, grid, block, 0, st, (double2*)C, m);
+  hipLaunchKernelGGL(k_hermitian_fill, grid, block, 0, st, (double2*)C, m, g_launch_gate);
 }
 
 void combine(const void* X, const void* U, void* Y, int m, long k, hipStream_t st) {
   if (m <= 0) return;
   dim3 grid(unsigned(k / TM), (m + TM - 1) / TM);
   hipLaunchKernelGGL(k_combine, grid, dim3(GT), 0, st, (const double2*)X, (const double2*)U,
-                     (double2*)Y, m, k);
+                     (double2*)Y, m, k, g_launch_gate);
 }
 
 // Split-K factors tried by the autotuner for square products of size m.
@@ -333,14 +339,14 @@ void gemm_square(const void* A, int opA, const void* B, int opB, void* C, int m,
   auto a = (const double2*)A;
   auto b = (const double2*)B;
   auto c = (double2*)(split > 1 ? part : C);
-  if (opA == 0 && opB == 0) hipLaunchKernelGGL((k_gemm_square<0, 0>), grid, dim3(GT), 0, st, a, b, c, m, split, herm);
-  else if (opA == 0 && opB == 1) hipLaunchKernelGGL((k_gemm_square<0, 1>), grid, dim3(GT), 0, st, a, b, c, m, split, herm);
-  else if (opA == 1 && opB == 0) hipLaunchKernelGGL((k_gemm_square<1, 0>), grid, dim3(GT), 0, st, a, b, c, m, split, herm);
-  else hipLaunchKernelGGL((k_gemm_square<1, 1>), grid, dim3(GT), 0, st, a, b, c, m, split, herm);
+  if (opA == 0 && opB == 0) hipLaunchKernelGGL((k_gemm_square<0, 0>), grid, dim3(GT), 0, st, a, b, c, m, split, herm, g_launch_gate);
+  else if (opA == 0 && opB == 1) hipLaunchKernelGGL((k_gemm_square<0, 1>), grid, dim3(GT), 0, st, a, b, c, m, split, herm, g_launch_gate);
+  else if (opA == 1 && opB == 0) hipLaunchKernelGGL((k_gemm_square<1, 0>), grid, dim3(GT), 0, st, a, b, c, m, split, herm, g_launch_gate);
+  else hipLaunchKernelGGL((k_gemm_square<1, 1>), grid, dim3(GT), 0, st, a, b, c, m, split, herm, g_launch_gate);
   if (split > 1) {
     const size_t n = size_t(m) * m;
     hipLaunchKernelGGL(k_sum_splits, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st,
-                       (const double2*)part, split, n, (double2*)C);
+                       (const double2*)part, split, n, (double2*)C, g_launch_gate);
   }
   if (herm) hermitian_fill(C, m, st);
 }

@@ -326,7 +326,8 @@ __device__ inline void tri_pair(int p, int& ta, int& tb) {
 }
 
 // ------------------------------------------------------------------ scales
-__global__ void k_clear_u32(unsigned int* __restrict__ w, int n) {
+__global__ void k_clear_u32(unsigned int* __restrict__ w, int n, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) w[i] = 0u;
 }
@@ -335,7 +336,8 @@ __global__ void k_clear_u32(unsigned int* __restrict__ w, int n) {
 // (complex128 inputs are first rounded to complex64, as the split rounds them).
 template <bool DOUBLE_IN>
 __global__ void __launch_bounds__(256)
-k_absmax(const void* __restrict__ xv, size_t n, unsigned int* __restrict__ mx) {
+k_absmax(const void* __restrict__ xv, size_t n, unsigned int* __restrict__ mx, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   float m = 0.0f;
   for (size_t i = size_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += size_t(gridDim.x) * 256) {
     float a, b;
@@ -373,7 +375,8 @@ constexpr long NT_PAD = 64;
 // (K % 8 == 0; the pad is never read).
 __global__ void __launch_bounds__(256)
 k_split_nt(const float2* __restrict__ x, int R, long K, const unsigned int* __restrict__ mx,
-           unsigned short* __restrict__ P) {
+           unsigned short* __restrict__ P, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const long nk8 = K / 8;
   const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= size_t(R) * nk8) return;
@@ -397,7 +400,8 @@ k_split_nt(const float2* __restrict__ x, int R, long K, const unsigned int* __re
 template <bool DOUBLE_IN>
 __global__ void __launch_bounds__(256)
 k_split_t(const void* __restrict__ xv, int R, long C, long ldr, const unsigned int* __restrict__ mx,
-          unsigned short* __restrict__ P) {
+          unsigned short* __restrict__ P, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   __shared__ float2 T[64][65];
   const long c0 = long(blockIdx.x) * 64;
   const int r0 = blockIdx.y * 64;
@@ -462,7 +466,8 @@ template <int NWM, int NWN>
 __global__ void __launch_bounds__(64 * NWM * NWN, 1)
 k_overlap_planes(const unsigned short* __restrict__ PA, const unsigned short* __restrict__ PB0,
                      const unsigned short* __restrict__ PB1, int m, long k, int npair, int split,
-                     int nz, float2* __restrict__ part) {
+                     int nz, float2* __restrict__ part, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   using L = Lay<NWM, NWN>;
   constexpr int W = L::WAVES;
   constexpr bool NEGB = W == 4;
@@ -512,7 +517,8 @@ __global__ void __launch_bounds__(256)
 k_overlap_reduce_planes(const float2* __restrict__ part, int npair, int split, int m, double scale,
                         const unsigned int* __restrict__ mxA, const unsigned int* __restrict__ mxB0,
                         const unsigned int* __restrict__ mxB1, double2* __restrict__ C0,
-                        double2* __restrict__ C1) {
+                        double2* __restrict__ C1, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int pair = blockIdx.x / RCH, slice = blockIdx.x % RCH, z = blockIdx.y;
   double2* C = z ? C1 : C0;
   const double sc = ldexp(scale, -(scale_exp(*mxA) + scale_exp(*(z ? mxB1 : mxB0))));
@@ -555,7 +561,8 @@ template <int NWM, int NWN>
 __global__ void __launch_bounds__(64 * NWM * NWN, 1)
 k_combine_planes(const unsigned short* __restrict__ PU, const unsigned short* __restrict__ PX,
                      const unsigned int* __restrict__ mxU, const unsigned int* __restrict__ mxX,
-                     float2* __restrict__ Y, int m, long k, long mpad, int nb) {
+                     float2* __restrict__ Y, int m, long k, long mpad, int nb, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   using L = Lay<NWM, NWN>;
   constexpr int W = L::WAVES;
   constexpr bool NEGB = W == 4;
@@ -650,18 +657,18 @@ bool planes_direct_ok(int m, long k) {
 }
 
 void plane_scale(const void* x, int x_is_c128, size_t n, unsigned int* mx, hipStream_t st) {
-  hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, st, mx, 1);
+  hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, st, mx, 1, g_launch_gate);
   if (n == 0) return;
   size_t nb = (n + 255) / 256;
   if (nb > 4096) nb = 4096;
   if (x_is_c128)
-    hipLaunchKernelGGL(k_absmax<true>, dim3(unsigned(nb)), dim3(256), 0, st, x, n, mx);
+    hipLaunchKernelGGL(k_absmax<true>, dim3(unsigned(nb)), dim3(256), 0, st, x, n, mx, g_launch_gate);
   else
-    hipLaunchKernelGGL(k_absmax<false>, dim3(unsigned(nb)), dim3(256), 0, st, x, n, mx);
+    hipLaunchKernelGGL(k_absmax<false>, dim3(unsigned(nb)), dim3(256), 0, st, x, n, mx, g_launch_gate);
 }
 
 void clear_scales(unsigned int* mx, int n, hipStream_t st) {
-  hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, st, mx, n);
+  hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, st, mx, n, g_launch_gate);
 }
 
 void split_planes_nt(const void* x, int rows, long k, const unsigned int* mx, void* P,
@@ -669,7 +676,7 @@ void split_planes_nt(const void* x, int rows, long k, const unsigned int* mx, vo
   if (rows <= 0) return;
   const size_t n = size_t(rows) * (k / 8);
   hipLaunchKernelGGL(k_split_nt, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st,
-                     (const float2*)x, rows, k, mx, (unsigned short*)P);
+                     (const float2*)x, rows, k, mx, (unsigned short*)P, g_launch_gate);
 }
 
 void split_planes_t(const void* x, int x_is_c128, int rows, long cols, const unsigned int* mx,
@@ -679,10 +686,10 @@ void split_planes_t(const void* x, int x_is_c128, int rows, long cols, const uns
   dim3 grid(unsigned((cols + 63) / 64), unsigned((ldr + 63) / 64));
   if (x_is_c128)
     hipLaunchKernelGGL((k_split_t<true>), grid, dim3(256), 0, st, x, rows, cols, ldr, mx,
-                       (unsigned short*)P);
+                       (unsigned short*)P, g_launch_gate);
   else
     hipLaunchKernelGGL((k_split_t<false>), grid, dim3(256), 0, st, x, rows, cols, ldr, mx,
-                       (unsigned short*)P);
+                       (unsigned short*)P, g_launch_gate);
 }
 
 void overlap_lower_planes(const void* PA, const void* PB0, const void* PB1,
@@ -702,16 +709,16 @@ void overlap_lower_planes(const void* PA, const void* PB0, const void* PB1,
     hipLaunchKernelGGL((k_overlap_planes<2, 2>), dim3(unsigned(split * npair * nz)),
                        dim3(Lay4::THREADS), 0, st, (const unsigned short*)PA,
                        (const unsigned short*)PB0, (const unsigned short*)PB1, m, k, npair, split,
-                       nz, (float2*)part);
+                       nz, (float2*)part, g_launch_gate);
   else
     hipLaunchKernelGGL((k_overlap_planes<4, 2>), dim3(unsigned(split * npair * nz)),
                        dim3(Lay8::THREADS), 0, st, (const unsigned short*)PA,
                        (const unsigned short*)PB0, (const unsigned short*)PB1, m, k, npair, split,
-                       nz, (float2*)part);
+                       nz, (float2*)part, g_launch_gate);
   if (ev) hipEventRecord(ev[1], st);
   hipLaunchKernelGGL(k_overlap_reduce_planes, dim3(npair * RCH, nz), dim3(256), 0, st,
                      (const float2*)part, npair, split, m, scale, mxA, mxB0, PB1 ? mxB1 : mxB0,
-                     (double2*)C0, (double2*)C1);
+                     (double2*)C0, (double2*)C1, g_launch_gate);
 }
 
 void combine_planes(const void* PU, const void* PX, const unsigned int* mxU,
@@ -722,11 +729,11 @@ void combine_planes(const void* PU, const void* PX, const unsigned int* mxU,
   if (waves == 4)
     hipLaunchKernelGGL((k_combine_planes<2, 2>), dim3(unsigned(nv * nb)), dim3(Lay4::THREADS), 0,
                        st, (const unsigned short*)PU, (const unsigned short*)PX, mxU, mxX,
-                       (float2*)Y, m, k, planes_pad(m), nb);
+                       (float2*)Y, m, k, planes_pad(m), nb, g_launch_gate);
   else
     hipLaunchKernelGGL((k_combine_planes<4, 2>), dim3(unsigned(nv * nb)), dim3(Lay8::THREADS), 0,
                        st, (const unsigned short*)PU, (const unsigned short*)PX, mxU, mxX,
-                       (float2*)Y, m, k, planes_pad(m), nb);
+                       (float2*)Y, m, k, planes_pad(m), nb, g_launch_gate);
 }
 
 }  // namespace sky

@@ -66,7 +66,8 @@ template <typename T> __device__ inline float cabs_max(cpx<T> z) {
 template <typename T, int N, int DIR, bool FIRST, bool LAST, int LP>
 __global__ void __launch_bounds__((LineCfg<N, LP>::THREADS))
 k_h_pass(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPtrs mf,
-         GridArgs g, double* __restrict__ eps_part, unsigned int* __restrict__ amax) {
+         GridArgs g, double* __restrict__ eps_part, unsigned int* __restrict__ amax, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   using C = LineCfg<N, LP>;
   using F = LineFFT<T, N, 2>;
   constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
@@ -150,7 +151,8 @@ k_h_pass(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPtr
 
 // Sum the per-workgroup partials of each state: out[s] = sum_t part[s][t].
 __global__ void k_sum_partials(const double* __restrict__ part, int ntile, int nstate,
-                               double* __restrict__ out) {
+                               double* __restrict__ out, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nstate) return;
   double acc = 0.0;
@@ -252,7 +254,8 @@ __device__ inline void h_dir_line(const cpx<T> (&v)[2][Fact<N>::R1], cpx<T> (&ou
 template <typename T, int N>
 __global__ void __launch_bounds__(PlaneCfg<N>::THREADS)
 k_h_plane(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPtrs mf, GridArgs g,
-          double* __restrict__ eps_part, unsigned int* __restrict__ amax) {
+          double* __restrict__ eps_part, unsigned int* __restrict__ amax, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   using C = PlaneCfg<N>;
   using F = LineFFT<T, N, 2>;
   constexpr int R1 = C::R1, R2 = C::R2, RT = C::RT, PITCH = C::PITCH, SP = C::SPIN;
@@ -337,7 +340,8 @@ template <typename T, int N>
 __global__ void __launch_bounds__(PlaneCfg<N>::THREADS)
 k_damp_fwd_xy(const cpx<T>* __restrict__ psi, const cpx<T>* __restrict__ hpsi,
               const double* __restrict__ eps, cpx<T>* __restrict__ out, GridArgs g,
-              double* __restrict__ r2_part) {
+              double* __restrict__ r2_part, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   using C = PlaneCfg<N>;
   using F = LineFFTInPlace<T, N, 2>;
   constexpr int R1 = C::R1, R2 = C::R2, RT = C::RT, PITCH = C::PITCH, SP = C::SPIN;
@@ -403,7 +407,8 @@ k_damp_fwd_xy(const cpx<T>* __restrict__ psi, const cpx<T>* __restrict__ hpsi,
 template <typename T, int N>
 __global__ void __launch_bounds__(PlaneCfg<N>::THREADS)
 k_damp_inv_xy(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ buf,
-              unsigned int* __restrict__ amax) {
+              unsigned int* __restrict__ amax, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   using C = PlaneCfg<N>;
   using F = LineFFTInPlace<T, N, 2>;
   constexpr int R1 = C::R1, R2 = C::R2, RT = C::RT, PITCH = C::PITCH, SP = C::SPIN;
@@ -474,7 +479,8 @@ template <typename T, int N>
 __global__ void __launch_bounds__(LineCfg<N>::THREADS)
 k_damp_fwd_x(const cpx<T>* __restrict__ psi, const cpx<T>* __restrict__ hpsi,
              const double* __restrict__ eps, cpx<T>* __restrict__ out, GridArgs g,
-             double* __restrict__ r2_part) {
+             double* __restrict__ r2_part, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   using C = LineCfg<N>;
   using F = LineFFT<T, N, 2>;
   constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
@@ -520,7 +526,8 @@ k_damp_fwd_x(const cpx<T>* __restrict__ psi, const cpx<T>* __restrict__ hpsi,
 // forward (INV = false) or inverse (INV = true) FFT along y, in place.
 template <typename T, int N, bool INV>
 __global__ void __launch_bounds__(LineCfg<N>::THREADS)
-k_damp_y(cpx<T>* __restrict__ buf) {
+k_damp_y(cpx<T>* __restrict__ buf, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   using C = LineCfg<N>;
   using F = LineFFT<T, N, 2>;
   constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
@@ -572,7 +579,8 @@ k_damp_y(cpx<T>* __restrict__ buf) {
 template <typename T, int N, int MODE>
 __global__ void __launch_bounds__(LineCfg<N>::THREADS)
 k_damp_z(cpx<T>* __restrict__ buf, GridArgs g, DampArgs d, const float* __restrict__ gain,
-         double* __restrict__ pow) {
+         double* __restrict__ pow, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   using C = LineCfg<N>;
   using F = LineFFT<T, N, 2>;
   constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
@@ -653,7 +661,8 @@ k_damp_z(cpx<T>* __restrict__ buf, GridArgs g, DampArgs d, const float* __restri
 template <typename T, int N>
 __global__ void __launch_bounds__(LineCfg<N>::THREADS)
 k_damp_inv_x(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ buf,
-             unsigned int* __restrict__ amax) {
+             unsigned int* __restrict__ amax, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   using C = LineCfg<N>;
   using F = LineFFT<T, N, 2>;
   constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
@@ -698,7 +707,8 @@ k_damp_inv_x(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ buf,
 // state chunk go to part[chunk][slot][point] and are reduced in fixed order.
 template <typename T, int N, int DIR>
 __global__ void __launch_bounds__(LineCfg<N>::THREADS)
-k_dens_pass(DensGroups grp, int nstate, int chunk, GridArgs g, double* __restrict__ part) {
+k_dens_pass(DensGroups grp, int nstate, int chunk, GridArgs g, double* __restrict__ part, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   using C = LineCfg<N>;
   using F = LineFFT<T, N, 2>;
   constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
@@ -787,7 +797,8 @@ k_dens_pass(DensGroups grp, int nstate, int chunk, GridArgs g, double* __restric
 
 // rho, tau, J[3], s[3], j[3] (11 fields) from the chunk partials.
 __global__ void k_dens_reduce(const double* __restrict__ part, int nchunk, int n3,
-                              double* __restrict__ dens, double scale) {
+                              double* __restrict__ dens, double scale, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n3) return;
   double q[16];
@@ -813,11 +824,13 @@ __global__ void k_dens_reduce(const double* __restrict__ part, int nchunk, int n
 }
 
 // ------------------------------------------------------------------ conversion
-__global__ void k_c128_to_c64(const double2* __restrict__ a, float2* __restrict__ b, size_t n) {
+__global__ void k_c128_to_c64(const double2* __restrict__ a, float2* __restrict__ b, size_t n, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) b[i] = make_float2(float(a[i].x), float(a[i].y));
 }
-__global__ void k_c64_to_c128(const float2* __restrict__ a, double2* __restrict__ b, size_t n) {
+__global__ void k_c64_to_c128(const float2* __restrict__ a, double2* __restrict__ b, size_t n, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) b[i] = make_double2(double(a[i].x), double(a[i].y));
 }
@@ -827,9 +840,9 @@ void convert_states(const void* src, int src_prec, void* dst, int dst_prec, size
   if (n == 0) return;
   const unsigned nb = unsigned((n + 255) / 256);
   if (src_prec == 0 && dst_prec == 1)
-    hipLaunchKernelGGL(k_c128_to_c64, dim3(nb), dim3(256), 0, st, (const double2*)src, (float2*)dst, n);
+    hipLaunchKernelGGL(k_c128_to_c64, dim3(nb), dim3(256), 0, st, (const double2*)src, (float2*)dst, n, g_launch_gate);
   else if (src_prec == 1 && dst_prec == 0)
-    hipLaunchKernelGGL(k_c64_to_c128, dim3(nb), dim3(256), 0, st, (const float2*)src, (double2*)dst, n);
+    hipLaunchKernelGGL(k_c64_to_c128, dim3(nb), dim3(256), 0, st, (const float2*)src, (double2*)dst, n, g_launch_gate);
   else
     hipMemcpyAsync(dst, src, n * (src_prec == 0 ? 16 : 8), hipMemcpyDeviceToDevice, st);
 }
@@ -852,11 +865,11 @@ static void launch_h_lp(const void* psi, void* hpsi, int nstate, MeanFieldPtrs m
   auto p = reinterpret_cast<const cpx<T>*>(psi);
   auto h = reinterpret_cast<cpx<T>*>(hpsi);
   hipLaunchKernelGGL((k_h_pass<T, N, 0, true, false, LP>), grid, block, 0, st, p, h, mf, g, nullptr,
-                     nullptr);
+                     nullptr, g_launch_gate);
   hipLaunchKernelGGL((k_h_pass<T, N, 1, false, false, LP>), grid, block, 0, st, p, h, mf, g, nullptr,
-                     nullptr);
+                     nullptr, g_launch_gate);
   hipLaunchKernelGGL((k_h_pass<T, N, 2, false, true, LP>), grid, block, 0, st, p, h, mf, g, eps_part,
-                     amax);
+                     amax, g_launch_gate);
 }
 
 // z pass (with U psi) by line pencils, then the x and y parts on LDS slices.
@@ -867,9 +880,9 @@ static void launch_h_plane(const void* psi, void* hpsi, int nstate, MeanFieldPtr
   auto p = reinterpret_cast<const cpx<T>*>(psi);
   auto h = reinterpret_cast<cpx<T>*>(hpsi);
   hipLaunchKernelGGL((k_h_pass<T, N, 2, true, false, D>), dim3(N * N / D, nstate),
-                     dim3(LineCfg<N>::THREADS), 0, st, p, h, mf, g, nullptr, nullptr);
+                     dim3(LineCfg<N>::THREADS), 0, st, p, h, mf, g, nullptr, nullptr, g_launch_gate);
   hipLaunchKernelGGL((k_h_plane<T, N>), dim3(N, nstate), dim3(PlaneCfg<N>::THREADS), 0, st, p, h,
-                     mf, g, eps_part, amax);
+                     mf, g, eps_part, amax, g_launch_gate);
 }
 
 // lines: 0 = default, H_PLANE = x and y on LDS slices, else pencils per
@@ -953,7 +966,7 @@ int apply_h(int n, int prec, const void* psi, void* hpsi, int nstate, MeanFieldP
   if (nt == 0) return 0;
   if (eps_part && eps)
     hipLaunchKernelGGL(k_sum_partials, dim3((nstate + 127) / 128), dim3(128), 0, st,
-                       (const double*)eps_part, nt, nstate, eps);
+                       (const double*)eps_part, nt, nstate, eps, g_launch_gate);
   return 1;
 }
 
@@ -973,25 +986,25 @@ static void launch_damp(const void* psi, const void* hpsi, const double* eps, vo
   if (stage != 2) {
     if (pl) {
       if constexpr (damp_slices_fit<T, N>())
-        hipLaunchKernelGGL((k_damp_fwd_xy<T, N>), pgrid, pblock, 0, st, p, h, eps, o, g, r2_part);
+        hipLaunchKernelGGL((k_damp_fwd_xy<T, N>), pgrid, pblock, 0, st, p, h, eps, o, g, r2_part, g_launch_gate);
     } else {
-      hipLaunchKernelGGL((k_damp_fwd_x<T, N>), grid, block, 0, st, p, h, eps, o, g, r2_part);
-      hipLaunchKernelGGL((k_damp_y<T, N, false>), grid, block, 0, st, o);
+      hipLaunchKernelGGL((k_damp_fwd_x<T, N>), grid, block, 0, st, p, h, eps, o, g, r2_part, g_launch_gate);
+      hipLaunchKernelGGL((k_damp_y<T, N, false>), grid, block, 0, st, o, g_launch_gate);
     }
     if (shell_pow)
-      hipLaunchKernelGGL((k_damp_z<T, N, 1>), grid, block, 0, st, o, g, d, nullptr, shell_pow);
+      hipLaunchKernelGGL((k_damp_z<T, N, 1>), grid, block, 0, st, o, g, d, nullptr, shell_pow, g_launch_gate);
   }
   if (stage == 1) return;
   if (gain)
-    hipLaunchKernelGGL((k_damp_z<T, N, 2>), grid, block, 0, st, o, g, d, gain, nullptr);
+    hipLaunchKernelGGL((k_damp_z<T, N, 2>), grid, block, 0, st, o, g, d, gain, nullptr, g_launch_gate);
   else
-    hipLaunchKernelGGL((k_damp_z<T, N, 0>), grid, block, 0, st, o, g, d, nullptr, nullptr);
+    hipLaunchKernelGGL((k_damp_z<T, N, 0>), grid, block, 0, st, o, g, d, nullptr, nullptr, g_launch_gate);
   if (pl) {
     if constexpr (damp_slices_fit<T, N>())
-      hipLaunchKernelGGL((k_damp_inv_xy<T, N>), pgrid, pblock, 0, st, p, o, amax);
+      hipLaunchKernelGGL((k_damp_inv_xy<T, N>), pgrid, pblock, 0, st, p, o, amax, g_launch_gate);
   } else {
-    hipLaunchKernelGGL((k_damp_y<T, N, true>), grid, block, 0, st, o);
-    hipLaunchKernelGGL((k_damp_inv_x<T, N>), grid, block, 0, st, p, o, amax);
+    hipLaunchKernelGGL((k_damp_y<T, N, true>), grid, block, 0, st, o, g_launch_gate);
+    hipLaunchKernelGGL((k_damp_inv_x<T, N>), grid, block, 0, st, p, o, amax, g_launch_gate);
   }
 }
 
@@ -1011,16 +1024,16 @@ void damped_step(int n, int prec, const void* psi, const void* hpsi, const doubl
     SKY_DISPATCH_N(n, nt = (damp_slices_fit<float, NN>() && (xy < 0 ? damp_slice_default<float, NN>() : xy != 0)) ? NN : ntiles<NN>())
   if (r2)
     hipLaunchKernelGGL(k_sum_partials, dim3((nstate + 127) / 128), dim3(128), 0, st,
-                       (const double*)r2_part, nt, nstate, r2);
+                       (const double*)r2_part, nt, nstate, r2, g_launch_gate);
 }
 
 template <typename T, int N>
 static void launch_dens(const DensGroups& grp, int nstate, int chunk, int nchunk, GridArgs g,
                         double* part, hipStream_t st) {
   dim3 grid(ntiles<N>(), nchunk), block(LineCfg<N>::THREADS);
-  hipLaunchKernelGGL((k_dens_pass<T, N, 0>), grid, block, 0, st, grp, nstate, chunk, g, part);
-  hipLaunchKernelGGL((k_dens_pass<T, N, 1>), grid, block, 0, st, grp, nstate, chunk, g, part);
-  hipLaunchKernelGGL((k_dens_pass<T, N, 2>), grid, block, 0, st, grp, nstate, chunk, g, part);
+  hipLaunchKernelGGL((k_dens_pass<T, N, 0>), grid, block, 0, st, grp, nstate, chunk, g, part, g_launch_gate);
+  hipLaunchKernelGGL((k_dens_pass<T, N, 1>), grid, block, 0, st, grp, nstate, chunk, g, part, g_launch_gate);
+  hipLaunchKernelGGL((k_dens_pass<T, N, 2>), grid, block, 0, st, grp, nstate, chunk, g, part, g_launch_gate);
 }
 
 int densities(int n, int prec, const void* const* psi, const GridArgs* g, int ngroup,
@@ -1045,7 +1058,7 @@ int densities(int n, int prec, const void* const* psi, const GridArgs* g, int ng
   if (prec == 0) SKY_DISPATCH_N(n, launch_dens<double, NN>(grp, nstate, chunk, nchunk, g[0], part, st))
   else SKY_DISPATCH_N(n, launch_dens<float, NN>(grp, nstate, chunk, nchunk, g[0], part, st))
   hipLaunchKernelGGL(k_dens_reduce, dim3((n3 + 255) / 256), dim3(256), 0, st,
-                     (const double*)part, nchunk, n3, dens, 1.0 / ngroup);
+                     (const double*)part, nchunk, n3, dens, 1.0 / ngroup, g_launch_gate);
   return 1;
 }
 

@@ -19,6 +19,9 @@
 
 namespace sky {
 
+thread_local const int* g_launch_gate = nullptr;
+
+
 namespace {
 using namespace jrot;
 constexpr int CB = 64;    // Cholesky block
@@ -36,7 +39,8 @@ constexpr int JACOBI_INNER = 3;
 // A[k0.., k0..] <- L_kk (lower), Dinv <- L_kk^-1 (CB x CB, lower).
 __global__ void __launch_bounds__(256)
 k_chol_diag(double2* __restrict__ A, int m, int k0, double2* __restrict__ Dinv, int* info,
-            double piv_min) {
+            double piv_min, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   __shared__ double2 S[CB][CB + 1];
   __shared__ double2 X[CB][CB + 1];
   __shared__ int bad;
@@ -90,7 +94,8 @@ k_chol_diag(double2* __restrict__ A, int m, int k0, double2* __restrict__ Dinv, 
 // Panel below the diagonal block: L[i][k0..] = A[i][k0..] * L_kk^-H, for
 // the 64-row block starting at row r0 = k0 + kw + blockIdx.x * CB.
 __global__ void __launch_bounds__(256)
-k_chol_panel(double2* __restrict__ A, int m, int k0, const double2* __restrict__ Dinv) {
+k_chol_panel(double2* __restrict__ A, int m, int k0, const double2* __restrict__ Dinv, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   __shared__ double2 P[CB][CB + 1];
   __shared__ double2 D[CB][CB + 1];
   const int kw = min(CB, m - k0);
@@ -115,7 +120,8 @@ k_chol_panel(double2* __restrict__ A, int m, int k0, const double2* __restrict__
 // Trailing update A[i][j] -= sum_l L[i][k0+l] conj(L[j][k0+l]) on the lower
 // tiles of the trailing matrix (tile pair number -> (ti, tj), ti >= tj).
 __global__ void __launch_bounds__(256)
-k_chol_update(double2* __restrict__ A, int m, int k0) {
+k_chol_update(double2* __restrict__ A, int m, int k0, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   __shared__ double2 Li[CB][CB + 1];
   __shared__ double2 Lj[CB][CB + 1];
   const int kw = min(CB, m - k0);
@@ -147,7 +153,8 @@ k_chol_update(double2* __restrict__ A, int m, int k0) {
 // one workgroup per jb; Linv[ib][ib] = Dinv[ib] is written by jb == ib.
 __global__ void __launch_bounds__(256)
 k_tri_inv_row(const double2* __restrict__ L, double2* __restrict__ Linv, int m, int ib,
-              const double2* __restrict__ Dinv_all) {
+              const double2* __restrict__ Dinv_all, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   using namespace mfma;
   __shared__ double2 sA[TM * KP];
   __shared__ double2 sB[TM * KP];
@@ -200,12 +207,14 @@ k_tri_inv_row(const double2* __restrict__ L, double2* __restrict__ Linv, int m, 
   });
 }
 
-__global__ void k_zero_cpx(double2* __restrict__ p, size_t n) {
+__global__ void k_zero_cpx(double2* __restrict__ p, size_t n, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = make_double2(0, 0);
 }
 
-__global__ void k_zero(double* __restrict__ p, size_t n) {
+__global__ void k_zero(double* __restrict__ p, size_t n, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0;
 }
@@ -214,7 +223,8 @@ __global__ void k_zero(double* __restrict__ p, size_t n) {
 // D = A - 1 and per-block partial sums of |D_ij|^2.
 __global__ void __launch_bounds__(256)
 k_minus_identity(const double2* __restrict__ A, double2* __restrict__ D, int m,
-                 double* __restrict__ part) {
+                 double* __restrict__ part, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   double acc = 0.0;
   const size_t n = size_t(m) * m;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
@@ -232,7 +242,8 @@ k_minus_identity(const double2* __restrict__ A, double2* __restrict__ D, int m,
   if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-__global__ void k_sum_parts(const double* __restrict__ part, int nb, double* __restrict__ out) {
+__global__ void k_sum_parts(const double* __restrict__ part, int nb, double* __restrict__ out, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   if (threadIdx.x) return;
   double s = 0.0;
   for (int b = 0; b < nb; ++b) s += part[b];
@@ -241,7 +252,8 @@ __global__ void k_sum_parts(const double* __restrict__ part, int nb, double* __r
 
 // P = a D + c 1
 __global__ void k_axpy_identity(const double2* __restrict__ D, double a, double c,
-                                double2* __restrict__ P, int m) {
+                                double2* __restrict__ P, int m, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= size_t(m) * m) return;
   const double2 d = D[e];
@@ -249,7 +261,8 @@ __global__ void k_axpy_identity(const double2* __restrict__ D, double a, double 
 }
 
 // P += c 1
-__global__ void k_add_identity(double2* __restrict__ P, double c, int m) {
+__global__ void k_add_identity(double2* __restrict__ P, double c, int m, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) P[size_t(i) * m + i].x += c;
 }
@@ -260,7 +273,8 @@ __global__ void k_add_identity(double2* __restrict__ P, double c, int m) {
 constexpr int JT = 256;    // threads of a pair sub-problem workgroup
 __global__ void __launch_bounds__(JT)
 k_jacobi_pair(const double2* __restrict__ A, int mp, const int2* __restrict__ pairs,
-              double2* __restrict__ Jout, int* __restrict__ rotated, double tol, int max_inner) {
+              double2* __restrict__ Jout, int* __restrict__ rotated, double tol, int max_inner, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   __shared__ double2 S[JP][JP + 1];
   __shared__ double2 J[JP][JP + 1];
   __shared__ Rot rot[JB];
@@ -356,7 +370,8 @@ k_jacobi_pair(const double2* __restrict__ A, int mp, const int2* __restrict__ pa
 // since A stays Hermitian.  Pairs whose J is the identity are skipped.
 __global__ void __launch_bounds__(256)
 k_jacobi_apply_a(double2* __restrict__ A, int mp, const int2* __restrict__ pairs,
-                 const double2* __restrict__ Jall, const int* __restrict__ rotated) {
+                 const double2* __restrict__ Jall, const int* __restrict__ rotated, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   __shared__ double2 X[JP][JP + 1];
   __shared__ double2 M[JP][JP + 1];
   int b = blockIdx.x, u = 0;
@@ -413,7 +428,8 @@ k_jacobi_apply_a(double2* __restrict__ A, int mp, const int2* __restrict__ pairs
 // V[rows][{P,Q}] <- V[rows][{P,Q}] J for an RV-row block and one pair.
 __global__ void __launch_bounds__(256)
 k_jacobi_apply_v(double2* __restrict__ V, int mp, const int2* __restrict__ pairs,
-                 const double2* __restrict__ Jall, const int* __restrict__ rotated) {
+                 const double2* __restrict__ Jall, const int* __restrict__ rotated, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   __shared__ double2 X[RV][JP + 1];
   __shared__ double2 M[JP][JP + 1];
   const int v = blockIdx.y, r0 = blockIdx.x * RV;
@@ -437,7 +453,8 @@ k_jacobi_apply_v(double2* __restrict__ V, int mp, const int2* __restrict__ pairs
 }
 
 // Off-diagonal and diagonal squared norms of A (mp x mp), per block partials.
-__global__ void k_offnorm(const double2* __restrict__ A, int mp, double* __restrict__ part) {
+__global__ void k_offnorm(const double2* __restrict__ A, int mp, double* __restrict__ part, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   __shared__ double red[4][2];
   double off = 0.0, dia = 0.0;
   const size_t n = size_t(mp) * mp;
@@ -461,7 +478,8 @@ __global__ void k_offnorm(const double2* __restrict__ A, int mp, double* __restr
   }
 }
 
-__global__ void k_offnorm_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+__global__ void k_offnorm_final(const double* __restrict__ part, int nb, double* __restrict__ out, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   if (threadIdx.x) return;
   double o = 0.0, d = 0.0;
   for (int b = 0; b < nb; ++b) { o += part[2 * b]; d += part[2 * b + 1]; }
@@ -471,7 +489,8 @@ __global__ void k_offnorm_final(const double* __restrict__ part, int nb, double*
 
 // Pad-copy A (m x m) into Ap (mp x mp) with zero coupling, V = identity.
 __global__ void k_jacobi_init(const double2* __restrict__ A, int m, double2* __restrict__ Ap,
-                              double2* __restrict__ V, int mp) {
+                              double2* __restrict__ V, int mp, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= size_t(mp) * mp) return;
   int i = int(e / mp), j = int(e % mp);
@@ -481,7 +500,8 @@ __global__ void k_jacobi_init(const double2* __restrict__ A, int m, double2* __r
 
 // Sort eigenvalues ascending (ties by index) and gather eigenvector columns.
 __global__ void k_jacobi_sort(const double2* __restrict__ Ap, const double2* __restrict__ V,
-                              int m, int mp, double* __restrict__ w, double2* __restrict__ Z) {
+                              int m, int mp, double* __restrict__ w, double2* __restrict__ Z, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int i = blockIdx.x;   // source column
   const double wi = Ap[size_t(i) * mp + i].x;
   __shared__ int rank_s;
@@ -499,14 +519,16 @@ __global__ void k_jacobi_sort(const double2* __restrict__ Ap, const double2* __r
   for (int r = threadIdx.x; r < m; r += blockDim.x) Z[size_t(r) * m + rk] = V[size_t(r) * mp + i];
 }
 
-__global__ void k_scale_columns(double2* __restrict__ X, const double* __restrict__ d, int m) {
+__global__ void k_scale_columns(double2* __restrict__ X, const double* __restrict__ d, int m, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= size_t(m) * m) return;
   double s = d[e % m];
   X[e] = make_double2(s * X[e].x, s * X[e].y);
 }
 
-__global__ void k_inv_sqrt(double* __restrict__ w, int m, int* info, double floor_v) {
+__global__ void k_inv_sqrt(double* __restrict__ w, int m, int* info, double floor_v, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
   double v = w[i];
@@ -524,10 +546,11 @@ int jacobi_dims(int m, int& nb) {
 
 void zero(double* p, size_t n, hipStream_t st) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_zero, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, p, n);
+  hipLaunchKernelGGL(k_zero, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, p, n, g_launch_gate);
 }
 
-__global__ void k_identity(double2* __restrict__ A, int m) {
+__global__ void k_identity(double2* __restrict__ A, int m, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= size_t(m) * m) return;
   A[e] = make_double2((e / m == e % m) ? 1.0 : 0.0, 0.0);
@@ -536,17 +559,18 @@ __global__ void k_identity(double2* __restrict__ A, int m) {
 void identity(void* A, int m, hipStream_t st) {
   if (m <= 0) return;
   const size_t mm = size_t(m) * m;
-  hipLaunchKernelGGL(k_identity, dim3(unsigned((mm + 255) / 256)), dim3(256), 0, st, (double2*)A, m);
+  hipLaunchKernelGGL(k_identity, dim3(unsigned((mm + 255) / 256)), dim3(256), 0, st, (double2*)A, m, g_launch_gate);
 }
 
-__global__ void k_zero_f32(float* __restrict__ p, size_t n) {
+__global__ void k_zero_f32(float* __restrict__ p, size_t n, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0f;
 }
 
 void zero_f32(float* p, size_t n, hipStream_t st) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_zero_f32, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, p, n);
+  hipLaunchKernelGGL(k_zero_f32, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, p, n, g_launch_gate);
 }
 
 void cholesky_inverse(void* Av, void* Linvv, int m, void* work, int* info, hipStream_t st,
@@ -559,20 +583,20 @@ void cholesky_inverse(void* Av, void* Linvv, int m, void* work, int* info, hipSt
   for (int kb = 0; kb < nblk; ++kb) {
     const int k0 = kb * CB;
     hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, A, m, k0,
-                       Dinv + size_t(kb) * CB * CB, info, piv_min);
+                       Dinv + size_t(kb) * CB * CB, info, piv_min, g_launch_gate);
     const int rest = m - (k0 + min(CB, m - k0));
     if (rest > 0) {
       const int nb = (rest + CB - 1) / CB;
       hipLaunchKernelGGL(k_chol_panel, dim3(nb), dim3(256), 0, st, A, m, k0,
-                         (const double2*)(Dinv + size_t(kb) * CB * CB));
-      hipLaunchKernelGGL(k_chol_update, dim3(nb * (nb + 1) / 2), dim3(256), 0, st, A, m, k0);
+                         (const double2*)(Dinv + size_t(kb) * CB * CB), g_launch_gate);
+      hipLaunchKernelGGL(k_chol_update, dim3(nb * (nb + 1) / 2), dim3(256), 0, st, A, m, k0, g_launch_gate);
     }
   }
   const size_t mm = size_t(m) * m;
-  hipLaunchKernelGGL(k_zero_cpx, dim3(unsigned((mm + 255) / 256)), dim3(256), 0, st, Linv, mm);
+  hipLaunchKernelGGL(k_zero_cpx, dim3(unsigned((mm + 255) / 256)), dim3(256), 0, st, Linv, mm, g_launch_gate);
   for (int ib = 0; ib < nblk; ++ib)
     hipLaunchKernelGGL(k_tri_inv_row, dim3(ib + 1), dim3(256), 0, st, (const double2*)A, Linv, m,
-                       ib, (const double2*)Dinv);
+                       ib, (const double2*)Dinv, g_launch_gate);
 }
 
 size_t jacobi_scratch_bytes(int m) {
@@ -612,15 +636,15 @@ int jacobi_eigh(void* Av, int m, double* w, void* Zv, void* work, double tol, in
   hipMemcpyAsync(pairs, sched.data(), sched.size() * sizeof(int2), hipMemcpyHostToDevice, st);
   const size_t mm = size_t(mp) * mp;
   hipLaunchKernelGGL(k_jacobi_init, dim3(unsigned((mm + 255) / 256)), dim3(256), 0, st,
-                     (const double2*)Av, m, Ap, V, mp);
+                     (const double2*)Av, m, Ap, V, mp, g_launch_gate);
   const int nrb = 256;
   double host_norm[2];
   int sweeps = 0;
   bool done = false;
   for (; sweeps <= max_sweeps; ++sweeps) {
-    hipLaunchKernelGGL(k_offnorm, dim3(nrb), dim3(256), 0, st, (const double2*)Ap, mp, norms);
+    hipLaunchKernelGGL(k_offnorm, dim3(nrb), dim3(256), 0, st, (const double2*)Ap, mp, norms, g_launch_gate);
     hipLaunchKernelGGL(k_offnorm_final, dim3(1), dim3(64), 0, st, (const double*)norms, nrb,
-                       norms + 2 * nrb);
+                       norms + 2 * nrb, g_launch_gate);
     hipMemcpyAsync(host_norm, norms + 2 * nrb, 2 * sizeof(double), hipMemcpyDeviceToHost, st);
     hipStreamSynchronize(st);
     if (!std::isfinite(host_norm[0]) || !std::isfinite(host_norm[1])) return -2;
@@ -629,22 +653,22 @@ int jacobi_eigh(void* Av, int m, double* w, void* Zv, void* work, double tol, in
     for (int r = 0; r < nb - 1; ++r) {
       const int2* pr = pairs + size_t(r) * np;
       hipLaunchKernelGGL(k_jacobi_pair, dim3(np), dim3(JT), 0, st, (const double2*)Ap, mp, pr,
-                         Jall, rotated, tol * 1e-2, JACOBI_INNER);
+                         Jall, rotated, tol * 1e-2, JACOBI_INNER, g_launch_gate);
       hipLaunchKernelGGL(k_jacobi_apply_a, dim3(np * (np + 1) / 2), dim3(256), 0, st, Ap, mp, pr,
-                         (const double2*)Jall, (const int*)rotated);
+                         (const double2*)Jall, (const int*)rotated, g_launch_gate);
       hipLaunchKernelGGL(k_jacobi_apply_v, dim3((mp + RV - 1) / RV, np), dim3(256), 0, st, V, mp, pr,
-                         (const double2*)Jall, (const int*)rotated);
+                         (const double2*)Jall, (const int*)rotated, g_launch_gate);
     }
   }
   hipLaunchKernelGGL(k_jacobi_sort, dim3(m), dim3(256), 0, st, (const double2*)Ap,
-                     (const double2*)V, m, mp, w, (double2*)Zv);
+                     (const double2*)V, m, mp, w, (double2*)Zv, g_launch_gate);
   return done ? sweeps : -1;
 }
 
 void eig_sort(const void* D, const void* V, int m, int ld, double* w, void* Z, hipStream_t st) {
   if (m <= 0) return;
   hipLaunchKernelGGL(k_jacobi_sort, dim3(m), dim3(256), 0, st, (const double2*)D, (const double2*)V,
-                     m, ld, w, (double2*)Z);
+                     m, ld, w, (double2*)Z, g_launch_gate);
 }
 
 int loewdin_series(const void* Iv, void* Cv, void* Dv, void* Tv, int m, double max_dev,
@@ -653,8 +677,8 @@ int loewdin_series(const void* Iv, void* Cv, void* Dv, void* Tv, int m, double m
   auto D = (double2*)Dv;
   const size_t mm = size_t(m) * m;
   const int nb = int(std::min<size_t>(256, (mm + 255) / 256));
-  hipLaunchKernelGGL(k_minus_identity, dim3(nb), dim3(256), 0, st, (const double2*)Iv, D, m, scratch);
-  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, (const double*)scratch, nb, scratch + nb);
+  hipLaunchKernelGGL(k_minus_identity, dim3(nb), dim3(256), 0, st, (const double2*)Iv, D, m, scratch, g_launch_gate);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, (const double*)scratch, nb, scratch + nb, g_launch_gate);
   double fro2 = 0.0;
   hipMemcpyAsync(&fro2, scratch + nb, sizeof(double), hipMemcpyDeviceToHost, st);
   hipStreamSynchronize(st);
@@ -674,20 +698,177 @@ int loewdin_series(const void* Iv, void* Cv, void* Dv, void* Tv, int m, double m
   double2* nxt = (p % 2) ? T : C;
   const unsigned ge = unsigned((mm + 255) / 256);
   hipLaunchKernelGGL(k_axpy_identity, dim3(ge), dim3(256), 0, st, (const double2*)D, c[p], c[p - 1],
-                     cur, m);
+                     cur, m, g_launch_gate);
   for (int k = p - 2; k >= 0; --k) {
     gemm_square(D, 0, cur, 0, nxt, m, st, part, 1, sq_split);   // a polynomial in D: Hermitian
-    hipLaunchKernelGGL(k_add_identity, dim3((m + 255) / 256), dim3(256), 0, st, nxt, c[k], m);
+    hipLaunchKernelGGL(k_add_identity, dim3((m + 255) / 256), dim3(256), 0, st, nxt, c[k], m, g_launch_gate);
     std::swap(cur, nxt);
   }
   return p;
+}
+
+// ------------------------------------------------------------------ device-decided steps
+// The kernels below make the decisions of the host-driven steps on the
+// device; they are launched without a gate and read the box's flags
+// themselves.
+__global__ void k_set_flag(int* __restrict__ flags, int idx, int value) {
+  if (threadIdx.x == 0) flags[idx] = value;
+}
+__global__ void k_set_double(double* __restrict__ d, int idx, double value) {
+  if (threadIdx.x == 0) d[idx] = value;
+}
+
+void set_flag(int* flags, int idx, int value, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(64), 0, st, flags, idx, value);
+}
+void set_double(double* d, int idx, double value, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_double, dim3(1), dim3(64), 0, st, d, idx, value);
+}
+
+constexpr int SERIES_PMAX = 14;   // terms of the series at most (as loewdin_series)
+
+// From ||D||_F^2 (fro2): the term count p of the series and its
+// coefficients (dbl[D_SERIES + 2 ..]), the gates of the Horner steps, or the
+// hand-over to the host.  Same arithmetic as loewdin_series.
+__global__ void k_series_plan(const double* __restrict__ fro2, double max_dev, int pcap,
+                              int* __restrict__ flags, double* __restrict__ dbl, int set) {
+  if (threadIdx.x != 0) return;
+  const bool active = flags[F_ACTIVE] != 0;
+  const double f = sqrt(*fro2);
+  int p = 0;
+  if (active) {
+    if (!isfinite(f) || !(f <= max_dev)) {
+      flags[F_HOST] = HOST_LOEWDIN;
+      flags[F_HOST_SET] = set;
+      flags[F_ACTIVE] = 0;
+    } else {
+      double c[16];
+      c[0] = 1.0;
+      for (int k = 1; k < 16; ++k) c[k] = c[k - 1] * (1.0 - 2.0 * k) / (2.0 * k);
+      p = 1;
+      while (p < pcap && fabs(c[p + 1]) * pow(f, p + 1) / (1.0 - f) > 0x1p-56) ++p;
+      for (int k = 0; k < 16; ++k) dbl[D_SERIES + 2 + k] = c[k];
+    }
+  }
+  dbl[D_SERIES] = f;
+  dbl[D_SERIES + 1] = double(p);
+  for (int k = 0; k <= SERIES_PMAX - 2; ++k) flags[F_SERIES + k] = (active && p > 0 && k <= p - 2) ? 1 : 0;
+}
+
+// Horner start P = c_{p-1} 1 + c_p D, written to the buffer that step p-2
+// reads (buf[(p-1) % 2]); gated by the box's F_ACTIVE and run only if the
+// series was planned (p > 0).
+__global__ void k_series_start(const double2* __restrict__ D, const double* __restrict__ dbl,
+                               double2* __restrict__ buf0, double2* __restrict__ buf1, int m,
+                               const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
+  const int p = int(dbl[D_SERIES + 1]);
+  if (p <= 0) return;
+  const double a = dbl[D_SERIES + 2 + p], c = dbl[D_SERIES + 2 + p - 1];
+  double2* P = ((p - 1) % 2) ? buf1 : buf0;
+  const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= size_t(m) * m) return;
+  const double2 d = D[e];
+  P[e] = make_double2(a * d.x + ((e / m == e % m) ? c : 0.0), a * d.y);
+}
+
+// P += c_k 1 with c_k from the device.
+__global__ void k_add_identity_dev(double2* __restrict__ P, const double* __restrict__ ck, int m,
+                                   const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) P[size_t(i) * m + i].x += *ck;
+}
+
+void loewdin_series_dev(const void* Iv, void* Cv, void* Dv, void* Tv, int m, double max_dev,
+                        double* scratch, void* part, hipStream_t st, int sq_split, int* flags,
+                        double* dbl, int set) {
+  if (m <= 0) return;
+  auto D = (double2*)Dv;
+  const size_t mm = size_t(m) * m;
+  const int nb = int(std::min<size_t>(256, (mm + 255) / 256));
+  const int* active = flags + F_ACTIVE;
+  {
+    GateScope g(active);
+    hipLaunchKernelGGL(k_minus_identity, dim3(nb), dim3(256), 0, st, (const double2*)Iv, D, m, scratch, g_launch_gate);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, (const double*)scratch, nb, scratch + nb, g_launch_gate);
+  }
+  // the most terms any accepted norm (f <= max_dev) can need, plus one:
+  // Horner steps beyond those are never taken and are not captured
+  double c[16];
+  c[0] = 1.0;
+  for (int k = 1; k < 16; ++k) c[k] = c[k - 1] * (1.0 - 2.0 * k) / (2.0 * k);
+  int pmax = 1;
+  while (pmax < SERIES_PMAX && fabs(c[pmax + 1]) * pow(max_dev, pmax + 1) / (1.0 - max_dev) > 0x1p-56)
+    ++pmax;
+  const int pcap = std::min(pmax + 1, SERIES_PMAX);
+  hipLaunchKernelGGL(k_series_plan, dim3(1), dim3(64), 0, st, (const double*)(scratch + nb), max_dev,
+                     pcap, flags, dbl, set);
+  // buf[0] = C receives the last Horner step (k = 0), buf[1] = T
+  auto C = (double2*)Cv, T = (double2*)Tv;
+  double2* buf[2] = {C, T};
+  const unsigned ge = unsigned((mm + 255) / 256);
+  hipLaunchKernelGGL(k_series_start, dim3(ge), dim3(256), 0, st, (const double2*)D,
+                     (const double*)dbl, C, T, m, active);
+  for (int k = pcap - 2; k >= 0; --k) {
+    GateScope g(flags + F_SERIES + k);
+    gemm_square(D, 0, buf[(k + 1) % 2], 0, buf[k % 2], m, st, part, 1, sq_split);
+    hipLaunchKernelGGL(k_add_identity_dev, dim3((m + 255) / 256), dim3(256), 0, st, buf[k % 2],
+                       (const double*)(dbl + D_SERIES + 2 + k), m, g_launch_gate);
+  }
+}
+
+// One workgroup of 256 threads: Delta-eps from the residual norms of the
+// occupied states of every set, in a fixed order.
+struct R2Sets {
+  const double* r2[64];
+  int nocc[64];
+};
+__global__ void __launch_bounds__(256)
+k_iteration_end(R2Sets sets, int nset, int count, int* __restrict__ flags, double* __restrict__ dbl) {
+  if (flags[F_ACTIVE] == 0) return;
+  __shared__ double buf[256];
+  double acc = 0.0;
+  for (int s = 0; s < nset; ++s)
+    for (int a = threadIdx.x; a < sets.nocc[s]; a += 256) acc += sets.r2[s][a];
+  buf[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) buf[threadIdx.x] += buf[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double de = sqrt(buf[0] / double(count > 0 ? count : 1));
+    dbl[D_DE] = de;
+    flags[F_ITER] += 1;
+    if (!isfinite(de)) {
+      flags[F_HOST] = HOST_NAN;
+      flags[F_HOST_SET] = 0;
+      flags[F_ACTIVE] = 0;
+    } else if (dbl[D_TOL] > 0.0 && de <= dbl[D_TOL]) {
+      flags[F_CONV] = 1;
+      flags[F_ACTIVE] = 0;
+    }
+  }
+}
+
+void iteration_end(const double* const* r2, const int* nocc, int nset, int count, int* flags,
+                   double* dbl, hipStream_t st) {
+  R2Sets sets{};
+  const int ns = std::min(nset, 64);
+  for (int s = 0; s < ns; ++s) {
+    sets.r2[s] = r2[s];
+    sets.nocc[s] = nocc[s];
+  }
+  hipLaunchKernelGGL(k_iteration_end, dim3(1), dim3(256), 0, st, sets, ns, count, flags, dbl);
 }
 
 // Gauge of the paper-literal update.  info[3 c .. 3 c + 2] = (start a, size k,
 // offset o) of the cluster holding column c; a cluster's k x k diagonal
 // block lives at packed[o ..] row-major.
 __global__ void k_gauge_gather(const double2* __restrict__ Z, int m, const int* __restrict__ info,
-                               double2* __restrict__ packed) {
+                               double2* __restrict__ packed, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int c = blockIdx.y;
   const int a = info[3 * c], k = info[3 * c + 1], o = info[3 * c + 2];
   for (int r = threadIdx.x; r < k; r += blockDim.x)
@@ -696,7 +877,8 @@ __global__ void k_gauge_gather(const double2* __restrict__ Z, int m, const int* 
 
 // out[:, c] = sum_l Z[:, a + l] Q[l][c - a] over the cluster of column c.
 __global__ void k_gauge_apply(const double2* __restrict__ Z, int m, const int* __restrict__ info,
-                              const double2* __restrict__ Q, double2* __restrict__ out) {
+                              const double2* __restrict__ Q, double2* __restrict__ out, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int c = blockIdx.y;
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= m) return;
@@ -709,23 +891,23 @@ __global__ void k_gauge_apply(const double2* __restrict__ Z, int m, const int* _
 void gauge_gather(const void* Z, int m, const int* info, void* packed, hipStream_t st) {
   if (m <= 0) return;
   hipLaunchKernelGGL(k_gauge_gather, dim3(1, m), dim3(64), 0, st, (const double2*)Z, m, info,
-                     (double2*)packed);
+                     (double2*)packed, g_launch_gate);
 }
 
 void gauge_apply(const void* Z, int m, const int* info, const void* Q, void* out, hipStream_t st) {
   if (m <= 0) return;
   hipLaunchKernelGGL(k_gauge_apply, dim3((m + 255) / 256, m), dim3(256), 0, st, (const double2*)Z, m,
-                     info, (const double2*)Q, (double2*)out);
+                     info, (const double2*)Q, (double2*)out, g_launch_gate);
 }
 
 void scale_columns(void* X, const double* d, int m, hipStream_t st) {
   const size_t mm = size_t(m) * m;
   hipLaunchKernelGGL(k_scale_columns, dim3(unsigned((mm + 255) / 256)), dim3(256), 0, st,
-                     (double2*)X, d, m);
+                     (double2*)X, d, m, g_launch_gate);
 }
 
 void inv_sqrt(double* w, int m, int* info, hipStream_t st, double floor_v) {
-  hipLaunchKernelGGL(k_inv_sqrt, dim3((m + 255) / 256), dim3(256), 0, st, w, m, info, floor_v);
+  hipLaunchKernelGGL(k_inv_sqrt, dim3((m + 255) / 256), dim3(256), 0, st, w, m, info, floor_v, g_launch_gate);
 }
 
 }  // namespace sky

@@ -43,7 +43,8 @@ __device__ inline float bf16_round(float x) {
   return __uint_as_float(u & 0xFFFF0000u);
 }
 
-__global__ void k_round_params(const float* __restrict__ p, float* __restrict__ q, int n) {
+__global__ void k_round_params(const float* __restrict__ p, float* __restrict__ q, int n, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) q[i] = bf16_round(p[i]);
 }
@@ -53,7 +54,8 @@ __global__ void k_round_params(const float* __restrict__ p, float* __restrict__ 
 __global__ void __launch_bounds__(PH)
 k_mlp_fwd(const float* __restrict__ P, const float* __restrict__ X, int ldx, int B,
           float* __restrict__ H1, float* __restrict__ H2, float* __restrict__ H3,
-          float* __restrict__ O) {
+          float* __restrict__ O, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   __shared__ float xs[SB][PIN];
   __shared__ float ha[SB][PH], hb[SB][PH];
   __shared__ float red[SB][PH / 64];
@@ -104,7 +106,8 @@ k_mlp_fwd(const float* __restrict__ P, const float* __restrict__ X, int ldx, int
 // dL/do per sample and the loss terms: g = GMAX sigmoid(o),
 // L = sum_b w_b (g_b - t_b)^2 / sum_b w_b.  S = [x0..x3, t, w] rows.
 __global__ void k_mlp_loss(const float* __restrict__ O, const float* __restrict__ S, int B,
-                           double wsum, float* __restrict__ dO, double* __restrict__ lpart) {
+                           double wsum, float* __restrict__ dO, double* __restrict__ lpart, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   double l = 0.0;
   if (b < B) {
@@ -129,7 +132,8 @@ __global__ void __launch_bounds__(PH)
 k_mlp_bwd_act(const float* __restrict__ P, const float* __restrict__ H1,
               const float* __restrict__ H2, const float* __restrict__ H3,
               const float* __restrict__ dO, int B, float* __restrict__ D1,
-              float* __restrict__ D2, float* __restrict__ D3) {
+              float* __restrict__ D2, float* __restrict__ D3, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   __shared__ float da[SB][PH], db[SB][PH];
   const int j = threadIdx.x, b0 = blockIdx.x * SB;
   for (int s = 0; s < SB; ++s) {
@@ -165,7 +169,8 @@ __global__ void k_mlp_bwd_w(const float* __restrict__ S, const float* __restrict
                             const float* __restrict__ H2, const float* __restrict__ H3,
                             const float* __restrict__ dO, const float* __restrict__ D1,
                             const float* __restrict__ D2, const float* __restrict__ D3, int B,
-                            float* __restrict__ G) {
+                            float* __restrict__ G, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= NPAR) return;
   float acc = 0.0f;
@@ -198,7 +203,8 @@ __global__ void k_mlp_bwd_w(const float* __restrict__ S, const float* __restrict
 
 __global__ void k_adam(float* __restrict__ P, const float* __restrict__ G, float* __restrict__ M,
                        float* __restrict__ V, int n, float lr, float b1, float b2, float c1,
-                       float c2) {
+                       float c2, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float g = G[i];
@@ -209,7 +215,8 @@ __global__ void k_adam(float* __restrict__ P, const float* __restrict__ G, float
   P[i] -= lr * (m / c1) / (sqrtf(v / c2) + 1e-8f);
 }
 
-__global__ void k_sum_d(const double* __restrict__ part, int n, double* __restrict__ out) {
+__global__ void k_sum_d(const double* __restrict__ part, int n, double* __restrict__ out, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   if (threadIdx.x) return;
   double s = 0.0;
   for (int i = 0; i < n; ++i) s += part[i];
@@ -219,7 +226,8 @@ __global__ void k_sum_d(const double* __restrict__ part, int n, double* __restri
 // Features of (state alpha, shell s) rows: X[(a*S + s)][0..3] (row length 6).
 __global__ void k_pc_features(const double* __restrict__ pow, const double* __restrict__ eps,
                               int stride, int ns, double e0, double hb2m, double kmax,
-                              float* __restrict__ X) {
+                              float* __restrict__ X, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= ns * PC_SHELLS) return;
   const int a = r / PC_SHELLS, s = r % PC_SHELLS;
@@ -237,7 +245,8 @@ __global__ void k_pc_features(const double* __restrict__ pow, const double* __re
 }
 
 // gain[r] = GMAX sigmoid(O[r])
-__global__ void k_pc_gains(const float* __restrict__ O, int n, float* __restrict__ gain) {
+__global__ void k_pc_gains(const float* __restrict__ O, int n, float* __restrict__ gain, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < n) gain[r] = GMAX / (1.0f + expf(-O[r]));
 }
@@ -248,7 +257,8 @@ template <typename T>
 __global__ void k_pc_gather(const T* __restrict__ psi, const T* __restrict__ hpsi,
                             const double* __restrict__ eps, const int* __restrict__ idx,
                             long V, T* __restrict__ bpsi, T* __restrict__ bh,
-                            double* __restrict__ beps, float* __restrict__ onehot) {
+                            double* __restrict__ beps, float* __restrict__ onehot, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int b = blockIdx.y, a = b / PC_SHELLS, s = b % PC_SHELLS;
   const size_t src = size_t(idx[a]) * V, dst = size_t(b) * V;
   for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < V; e += long(gridDim.x) * blockDim.x) {
@@ -263,7 +273,8 @@ __global__ void k_pc_gather(const T* __restrict__ psi, const T* __restrict__ hps
 
 // d = psi - phi (in place in phi)
 template <typename T>
-__global__ void k_pc_dir(const T* __restrict__ bpsi, T* __restrict__ bphi, size_t n) {
+__global__ void k_pc_dir(const T* __restrict__ bpsi, T* __restrict__ bphi, size_t n, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e < n) {
     const T a = bpsi[e];
@@ -281,7 +292,8 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 k_pc_gram(const T* __restrict__ bpsi, const T* __restrict__ bh, const T* __restrict__ bd,
           const T* __restrict__ bhd, const double* __restrict__ beps, long V,
-          double* __restrict__ part) {
+          double* __restrict__ part, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int a = blockIdx.y;
   double acc[NG];
 #pragma unroll
@@ -323,7 +335,8 @@ k_pc_gram(const T* __restrict__ bpsi, const T* __restrict__ bh, const T* __restr
 // Per sampled state: sum the Gram partials, solve (G + lam 1) g = c by
 // Cholesky (FP64), clamp to [0, GMAX], write the target column t of the
 // sample rows.  One thread per state.
-__global__ void k_pc_solve(const double* __restrict__ part, int nblk, int ns, float* __restrict__ S) {
+__global__ void k_pc_solve(const double* __restrict__ part, int nblk, int ns, float* __restrict__ S, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= ns) return;
   double Gm[PC_SHELLS][PC_SHELLS], c[PC_SHELLS];
@@ -390,14 +403,14 @@ void precond_init_params(float* P_dev, unsigned seed, hipStream_t st) {
 }
 
 void precond_round(const float* P, float* Pb, hipStream_t st) {
-  hipLaunchKernelGGL(k_round_params, dim3((NPAR + 255) / 256), dim3(256), 0, st, P, Pb, NPAR);
+  hipLaunchKernelGGL(k_round_params, dim3((NPAR + 255) / 256), dim3(256), 0, st, P, Pb, NPAR, g_launch_gate);
 }
 
 void precond_forward(const float* Pb, const float* X, int B, float* H1, float* H2, float* H3,
                      float* O, hipStream_t st) {
   if (B <= 0) return;
   hipLaunchKernelGGL(k_mlp_fwd, dim3((B + SB - 1) / SB), dim3(PH), 0, st, Pb, X, 6, B, H1, H2,
-                     H3, O);
+                     H3, O, g_launch_gate);
 }
 
 void precond_features(const double* pow, const double* eps, int stride, int ns, double e0,
@@ -405,12 +418,12 @@ void precond_features(const double* pow, const double* eps, int stride, int ns, 
   const int n = ns * PC_SHELLS;
   if (n <= 0) return;
   hipLaunchKernelGGL(k_pc_features, dim3((n + 127) / 128), dim3(128), 0, st, pow, eps, stride, ns,
-                     e0, hb2m, kmax, X);
+                     e0, hb2m, kmax, X, g_launch_gate);
 }
 
 void precond_gains(const float* O, int n, float* gain, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_pc_gains, dim3((n + 255) / 256), dim3(256), 0, st, O, n, gain);
+  hipLaunchKernelGGL(k_pc_gains, dim3((n + 255) / 256), dim3(256), 0, st, O, n, gain, g_launch_gate);
 }
 
 double precond_loss_grad(const float* Pb, const float* S, int B, double wsum, float* H1,
@@ -420,14 +433,14 @@ double precond_loss_grad(const float* Pb, const float* S, int B, double wsum, fl
   precond_forward(Pb, S, B, H1, H2, H3, O, st);
   const int nb = (B + 255) / 256;
   hipLaunchKernelGGL(k_mlp_loss, dim3(nb), dim3(256), 0, st, (const float*)O, S, B, wsum, dO,
-                     dscratch);
-  hipLaunchKernelGGL(k_sum_d, dim3(1), dim3(64), 0, st, (const double*)dscratch, nb, dscratch + nb);
+                     dscratch, g_launch_gate);
+  hipLaunchKernelGGL(k_sum_d, dim3(1), dim3(64), 0, st, (const double*)dscratch, nb, dscratch + nb, g_launch_gate);
   hipLaunchKernelGGL(k_mlp_bwd_act, dim3((B + SB - 1) / SB), dim3(PH), 0, st, Pb,
                      (const float*)H1, (const float*)H2, (const float*)H3, (const float*)dO, B,
-                     D1, D2, D3);
+                     D1, D2, D3, g_launch_gate);
   hipLaunchKernelGGL(k_mlp_bwd_w, dim3((NPAR + 255) / 256), dim3(256), 0, st, S,
                      (const float*)H1, (const float*)H2, (const float*)H3, (const float*)dO,
-                     (const float*)D1, (const float*)D2, (const float*)D3, B, G);
+                     (const float*)D1, (const float*)D2, (const float*)D3, B, G, g_launch_gate);
   double loss = 0.0;
   if (want_loss) {
     hipMemcpyAsync(&loss, dscratch + nb, sizeof(double), hipMemcpyDeviceToHost, st);
@@ -441,7 +454,7 @@ void precond_adam(float* P, const float* G, float* M, float* V, int step, float 
   const float b1 = 0.9f, b2 = 0.999f;
   const float c1 = 1.0f - std::pow(b1, float(step)), c2 = 1.0f - std::pow(b2, float(step));
   hipLaunchKernelGGL(k_adam, dim3((NPAR + 255) / 256), dim3(256), 0, st, P, G, M, V, NPAR, lr, b1,
-                     b2, c1, c2);
+                     b2, c1, c2, g_launch_gate);
 }
 
 void precond_gather(int prec, const void* psi, const void* hpsi, const double* eps,
@@ -450,20 +463,20 @@ void precond_gather(int prec, const void* psi, const void* hpsi, const double* e
   dim3 grid(64, unsigned(ns * PC_SHELLS));
   if (prec == 0)
     hipLaunchKernelGGL(k_pc_gather<double2>, grid, dim3(256), 0, st, (const double2*)psi,
-                       (const double2*)hpsi, eps, idx, V, (double2*)bpsi, (double2*)bh, beps, onehot);
+                       (const double2*)hpsi, eps, idx, V, (double2*)bpsi, (double2*)bh, beps, onehot, g_launch_gate);
   else
     hipLaunchKernelGGL(k_pc_gather<float2>, grid, dim3(256), 0, st, (const float2*)psi,
-                       (const float2*)hpsi, eps, idx, V, (float2*)bpsi, (float2*)bh, beps, onehot);
+                       (const float2*)hpsi, eps, idx, V, (float2*)bpsi, (float2*)bh, beps, onehot, g_launch_gate);
 }
 
 void precond_dir(int prec, const void* bpsi, void* bphi, size_t n, hipStream_t st) {
   const unsigned nb = unsigned((n + 255) / 256);
   if (prec == 0)
     hipLaunchKernelGGL(k_pc_dir<double2>, dim3(nb), dim3(256), 0, st, (const double2*)bpsi,
-                       (double2*)bphi, n);
+                       (double2*)bphi, n, g_launch_gate);
   else
     hipLaunchKernelGGL(k_pc_dir<float2>, dim3(nb), dim3(256), 0, st, (const float2*)bpsi,
-                       (float2*)bphi, n);
+                       (float2*)bphi, n, g_launch_gate);
 }
 
 int precond_gram_blocks() { return 128; }
@@ -474,12 +487,12 @@ void precond_targets(int prec, const void* bpsi, const void* bh, const void* bd,
   dim3 grid(nblk, ns);
   if (prec == 0)
     hipLaunchKernelGGL(k_pc_gram<double2>, grid, dim3(256), 0, st, (const double2*)bpsi,
-                       (const double2*)bh, (const double2*)bd, (const double2*)bhd, beps, V, part);
+                       (const double2*)bh, (const double2*)bd, (const double2*)bhd, beps, V, part, g_launch_gate);
   else
     hipLaunchKernelGGL(k_pc_gram<float2>, grid, dim3(256), 0, st, (const float2*)bpsi,
-                       (const float2*)bh, (const float2*)bd, (const float2*)bhd, beps, V, part);
+                       (const float2*)bh, (const float2*)bd, (const float2*)bhd, beps, V, part, g_launch_gate);
   hipLaunchKernelGGL(k_pc_solve, dim3((ns + 63) / 64), dim3(64), 0, st, (const double*)part, nblk,
-                     ns, S);
+                     ns, S, g_launch_gate);
 }
 
 size_t precond_gram_bytes(int ns) { return sizeof(double) * size_t(ns) * precond_gram_blocks() * NG; }

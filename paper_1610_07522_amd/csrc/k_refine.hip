@@ -44,12 +44,12 @@ constexpr int KMAX = 48;            // widest cluster diagonalised in one workgr
 constexpr double THETA = 0.03;      // weak-coupling ratio |coupling| / |gap|
 constexpr double ORTH_TOL = 1e-13;  // max |(X^H X - 1)_ij| at convergence
 constexpr double E_CLAMP = 0.25;    // bound on one update coefficient
-constexpr double E2_SKIP = 1e-8;      // max |E| below which E^2/2 is left out
 constexpr int CHECK_BLOCKS = 256;
 
 // lam[i] = Re S_ii / (1 - Re R_ii)  (R may be null: R = 0); clears *emax.
 __global__ void k_ref_lambda(const double2* __restrict__ S, const double2* __restrict__ R, int m,
-                             double* __restrict__ lam, unsigned long long* __restrict__ emax) {
+                             double* __restrict__ lam, unsigned long long* __restrict__ emax, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) *emax = 0ull;
   if (i >= m) return;
@@ -59,7 +59,8 @@ __global__ void k_ref_lambda(const double2* __restrict__ S, const double2* __res
 
 // rank[i] = position of i in ascending (lam, index) order; order[rank] = i.
 __global__ void k_ref_rank(const double* __restrict__ lam, int m, int* __restrict__ rank,
-                           int* __restrict__ order) {
+                           int* __restrict__ order, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
   const double li = lam[i];
@@ -76,7 +77,8 @@ __global__ void k_ref_rank(const double* __restrict__ lam, int m, int* __restric
 __global__ void __launch_bounds__(256)
 k_ref_reach(const double2* __restrict__ S, const double2* __restrict__ R, const double* __restrict__ lam,
             const int* __restrict__ rank, int m, double theta, const double* __restrict__ taup,
-            int* __restrict__ reach) {
+            int* __restrict__ reach, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int i = blockIdx.x;
   const double tau = *taup;
   const double li = lam[i];
@@ -112,7 +114,8 @@ k_ref_reach(const double2* __restrict__ S, const double2* __restrict__ R, const 
 __global__ void __launch_bounds__(1024)
 k_ref_clusters(const int* __restrict__ reach, int m, int* __restrict__ pm, int* __restrict__ cstart,
                int* __restrict__ csize, int* __restrict__ cslot, int2* __restrict__ clist,
-               int* __restrict__ info) {
+               int* __restrict__ info, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   __shared__ int tmax[1024], tcut[1024];
   __shared__ int ncl, widest;
   const int t = threadIdx.x, T = blockDim.x;
@@ -182,7 +185,8 @@ k_ref_clusters(const int* __restrict__ reach, int m, int* __restrict__ pm, int* 
 __global__ void __launch_bounds__(256)
 k_ref_cluster_eig(const double2* __restrict__ S, const double2* __restrict__ R, int m,
                   const int* __restrict__ order, const int2* __restrict__ clist,
-                  const int* __restrict__ info, double2* __restrict__ W, double tol) {
+                  const int* __restrict__ info, double2* __restrict__ W, double tol, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int c = blockIdx.x;
   if (c >= info[0]) return;
   const int2 cs = clist[c];
@@ -333,7 +337,8 @@ struct Clusters {
 
 // lam2[a] = Re S2_aa / (1 - Re R2_aa) in the cluster-rotated sorted basis.
 __global__ void k_ref_lambda2(const double2* __restrict__ S, const double2* __restrict__ R, int m,
-                              Clusters cl, double* __restrict__ lam2) {
+                              Clusters cl, double* __restrict__ lam2, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= m) return;
   const int s0 = cl.cstart[a], k = cl.csize[a];
@@ -353,7 +358,8 @@ __global__ void k_ref_lambda2(const double2* __restrict__ S, const double2* __re
 __global__ void __launch_bounds__(256)
 k_ref_update(const double2* __restrict__ S, const double2* __restrict__ R, int m, Clusters cl,
              const double* __restrict__ lam2, const double* __restrict__ taup,
-             double2* __restrict__ E, unsigned long long* __restrict__ emax) {
+             double2* __restrict__ E, unsigned long long* __restrict__ emax, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const double tau = *taup;
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   const int a = blockIdx.y;
@@ -391,7 +397,8 @@ k_ref_update(const double2* __restrict__ S, const double2* __restrict__ R, int m
 // (E2 null: the second-order term is below rounding and left out).
 __global__ void __launch_bounds__(256)
 k_ref_build_q(const double2* __restrict__ E, const double2* __restrict__ E2, int m, Clusters cl,
-              double2* __restrict__ Q) {
+              double2* __restrict__ Q, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
   if (b >= m) return;
@@ -414,7 +421,8 @@ k_ref_build_q(const double2* __restrict__ E, const double2* __restrict__ E2, int
 // gaps: without the symmetrisation it stalls the orthonormality near 1e-11.
 __global__ void __launch_bounds__(256)
 k_ref_check(double2* __restrict__ S, double2* __restrict__ R, int m,
-            const double* __restrict__ taup, double* __restrict__ part) {
+            const double* __restrict__ taup, double* __restrict__ part, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   const double tau = *taup;
   double off = 0.0, dia = 0.0, rmax = 0.0;
   const size_t n = size_t(m) * m;
@@ -476,7 +484,8 @@ k_ref_check(double2* __restrict__ S, double2* __restrict__ R, int m,
 
 // tau = noise * rms of Re A_ii (one workgroup of 256 threads).
 __global__ void __launch_bounds__(256)
-k_ref_diag2(const double2* __restrict__ A, int m, double noise, double* __restrict__ tau) {
+k_ref_diag2(const double2* __restrict__ A, int m, double noise, double* __restrict__ tau, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   double v = 0.0;
   for (int i = threadIdx.x; i < m; i += blockDim.x) {
     const double d = A[size_t(i) * m + i].x;
@@ -492,11 +501,13 @@ k_ref_diag2(const double2* __restrict__ A, int m, double noise, double* __restri
 
 // tau = noise * rms eigenvalue from the diagonal norm of the last check.
 __global__ void k_ref_tau(const double* __restrict__ norms, int m, double noise,
-                          double* __restrict__ tau) {
+                          double* __restrict__ tau, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   if (threadIdx.x == 0) tau[0] = noise * sqrt(norms[1] / m);
 }
 
-__global__ void k_ref_check_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+__global__ void k_ref_check_final(const double* __restrict__ part, int nb, double* __restrict__ out, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
   if (threadIdx.x) return;
   double o = 0.0, d = 0.0, r = 0.0;
   for (int b = 0; b < nb; ++b) {
@@ -565,7 +576,6 @@ int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double to
   const size_t mm = size_t(m) * m;
   const unsigned ncheck = unsigned(std::min<size_t>(CHECK_BLOCKS, (mm + 255) / 256));
   Clusters cl{r.order, r.cstart, r.csize, r.cslot, r.W};
-  double off_prev = 1.0;   // relative off-diagonal norm of the last check
   // noise floor of H': couplings at or below tau (noise x the rms eigenvalue)
   // are indistinguishable from the rounding of the products that formed H'
   // (8 ulps in FP64; the split-FP16 subspace matrices carry ~2^-22 of their
@@ -574,7 +584,7 @@ int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double to
   // levels off near tau times the square root of the couplings per state,
   // which is where the precision ladder hands over to FP64.
   double* tau = r.norms + 4;   // on the device: no read-back needed
-  hipLaunchKernelGGL(k_ref_diag2, dim3(1), dim3(256), 0, st, A, m, noise, tau);
+  hipLaunchKernelGGL(k_ref_diag2, dim3(1), dim3(256), 0, st, A, m, noise, tau, g_launch_gate);
   for (int it = 0;; ++it) {
     const double2* Sp = A;
     const double2* Rp = nullptr;
@@ -583,16 +593,15 @@ int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double to
       gemm_square(A, 0, X, 0, T, m, st, r.gpart, 0, sq_split);
       gemm_square(X, 1, T, 0, S, m, st, r.gpart, 1, sq_split);
       hipLaunchKernelGGL(k_ref_check, dim3(ncheck), dim3(256), 0, st, S, R, m, (const double*)tau,
-                         r.part);
+                         r.part, g_launch_gate);
       hipLaunchKernelGGL(k_ref_check_final, dim3(1), dim3(64), 0, st, (const double*)r.part,
-                         int(ncheck), r.norms);
+                         int(ncheck), r.norms, g_launch_gate);
       double h[3];
       int hi[2];
       hipMemcpyAsync(h, r.norms, sizeof(h), hipMemcpyDeviceToHost, st);
       hipMemcpyAsync(hi, r.info, sizeof(hi), hipMemcpyDeviceToHost, st);
       hipStreamSynchronize(st);
       if (!(h[0] == h[0]) || !(h[1] == h[1]) || !(h[2] == h[2]) || hi[1] > KMAX) return -1;
-      off_prev = h[1] > 0.0 ? sqrt(h[0] / h[1]) : 0.0;
       if ((h[0] <= tol * tol * h[1] || h[0] < 1e-300) && h[2] <= ORTH_TOL) {
         eig_sort(S, X, m, m, w, Z, st);
         return it;
@@ -600,33 +609,128 @@ int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double to
       if (it >= maxit) return -1;
       Sp = S;
       Rp = R;
-      hipLaunchKernelGGL(k_ref_tau, dim3(1), dim3(64), 0, st, (const double*)r.norms, m, noise, tau);
+      hipLaunchKernelGGL(k_ref_tau, dim3(1), dim3(64), 0, st, (const double*)r.norms, m, noise, tau, g_launch_gate);
     }
-    hipLaunchKernelGGL(k_ref_lambda, dim3(gm), dim3(256), 0, st, Sp, Rp, m, r.lam, r.emax);
-    hipLaunchKernelGGL(k_ref_rank, dim3(gm), dim3(256), 0, st, (const double*)r.lam, m, r.rank, r.order);
+    hipLaunchKernelGGL(k_ref_lambda, dim3(gm), dim3(256), 0, st, Sp, Rp, m, r.lam, r.emax, g_launch_gate);
+    hipLaunchKernelGGL(k_ref_rank, dim3(gm), dim3(256), 0, st, (const double*)r.lam, m, r.rank, r.order, g_launch_gate);
     hipLaunchKernelGGL(k_ref_reach, dim3(m), dim3(256), 0, st, Sp, Rp, (const double*)r.lam,
-                       (const int*)r.rank, m, THETA, (const double*)tau, r.reach);
+                       (const int*)r.rank, m, THETA, (const double*)tau, r.reach, g_launch_gate);
     hipLaunchKernelGGL(k_ref_clusters, dim3(1), dim3(1024), 0, st, (const int*)r.reach, m, r.pm,
-                       r.cstart, r.csize, r.cslot, r.clist, r.info);
+                       r.cstart, r.csize, r.cslot, r.clist, r.info, g_launch_gate);
     hipLaunchKernelGGL(k_ref_cluster_eig, dim3(unsigned(m / 2 + 1)), dim3(256), 0, st, Sp, Rp, m,
-                       (const int*)r.order, (const int2*)r.clist, (const int*)r.info, r.W, tol * 1e-2);
-    hipLaunchKernelGGL(k_ref_lambda2, dim3(gm), dim3(256), 0, st, Sp, Rp, m, cl, r.lam2);
+                       (const int*)r.order, (const int2*)r.clist, (const int*)r.info, r.W, tol * 1e-2, g_launch_gate);
+    hipLaunchKernelGGL(k_ref_lambda2, dim3(gm), dim3(256), 0, st, Sp, Rp, m, cl, r.lam2, g_launch_gate);
     hipLaunchKernelGGL(k_ref_update, dim3(gm, unsigned(m)), dim3(256), 0, st, Sp, Rp, m, cl,
-                       (const double*)r.lam2, (const double*)tau, E, r.emax);
-    // E^2/2 matters while |E| > 1e-8 (below, it is under FP64 rounding of 1 + E);
-    // read |E| only once the previous step was already close
-    bool second = true;
-    if (off_prev < 1e-6) {
-      unsigned long long eb = 0;
-      hipMemcpyAsync(&eb, r.emax, sizeof(eb), hipMemcpyDeviceToHost, st);
-      hipStreamSynchronize(st);
-      double em;
-      std::memcpy(&em, &eb, sizeof(em));
-      second = !(em <= E2_SKIP);
-    }
-    if (second) gemm_square(E, 0, E, 0, T, m, st, r.gpart, 0, sq_split);
+                       (const double*)r.lam2, (const double*)tau, E, r.emax, g_launch_gate);
+    // the second-order term E^2/2 is always formed (below |E| ~ 1e-8 it is
+    // under FP64 rounding of 1 + E; leaving it out there would need |E| on
+    // the host, and the device-decided refinement forms it too, so that the
+    // two take the same arithmetic)
+    gemm_square(E, 0, E, 0, T, m, st, r.gpart, 0, sq_split);
     hipLaunchKernelGGL(k_ref_build_q, dim3(gm, unsigned(m)), dim3(256), 0, st, (const double2*)E,
-                       second ? (const double2*)T : nullptr, m, cl, Q);
+                       (const double2*)T, m, cl, Q, g_launch_gate);
+    if (it == 0) {
+      std::swap(X, Q);
+    } else {
+      gemm_square(X, 0, Q, 0, Xn, m, st, r.gpart, 0, sq_split);
+      std::swap(X, Xn);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ device-decided
+// The stop test of refine_eigh on the device (ungated; one thread).
+__global__ void k_ref_decide(const double* __restrict__ norms, const int* __restrict__ info,
+                             double tol, int it, int maxit, int* __restrict__ flags, int set) {
+  if (threadIdx.x != 0) return;
+  if (flags[F_REF_RUN] == 0) {
+    flags[F_REF_OK + it] = 0;
+    return;
+  }
+  const double h0 = norms[0], h1 = norms[1], h2 = norms[2];
+  flags[F_REF_STEPS] = it;
+  const bool bad = !(h0 == h0) || !(h1 == h1) || !(h2 == h2) || info[1] > KMAX;
+  const bool conv = !bad && (h0 <= tol * tol * h1 || h0 < 1e-300) && h2 <= ORTH_TOL;
+  flags[F_REF_OK + it] = conv ? 1 : 0;
+  if (conv) {
+    flags[F_REF_RUN] = 0;
+  } else if (bad || it >= maxit) {
+    flags[F_REF_RUN] = 0;
+    flags[F_HOST] = HOST_REFINE;
+    flags[F_HOST_SET] = set;
+    flags[F_ACTIVE] = 0;
+  }
+}
+
+__global__ void k_ref_start(int* __restrict__ flags) {
+  if (threadIdx.x != 0) return;
+  flags[F_REF_RUN] = flags[F_ACTIVE];
+  flags[F_REF_STEPS] = 0;
+}
+
+void refine_eigh_dev(const void* Av, int m, double* w, void* Z, void* work, double tol, int maxit,
+                     hipStream_t st, int sq_split, double noise, int* flags, int set) {
+  if (m <= 0) return;
+  if (maxit > F_NFLAGS - F_REF_OK - 1) maxit = F_NFLAGS - F_REF_OK - 1;
+  RefineWork r = carve(work, m);
+  const double2* A = static_cast<const double2*>(Av);
+  double2 *X = r.mat[0], *Xn = r.mat[1], *Q = r.mat[2], *T = r.mat[3], *S = r.mat[4],
+          *R = r.mat[5], *E = r.mat[6];
+  const unsigned gm = unsigned((m + 255) / 256);
+  const size_t mm = size_t(m) * m;
+  const unsigned ncheck = unsigned(std::min<size_t>(CHECK_BLOCKS, (mm + 255) / 256));
+  Clusters cl{r.order, r.cstart, r.csize, r.cslot, r.W};
+  double* tau = r.norms + 4;
+  const int* run = flags + F_REF_RUN;
+  hipLaunchKernelGGL(k_ref_start, dim3(1), dim3(64), 0, st, flags);
+  {
+    GateScope g(run);
+    hipLaunchKernelGGL(k_ref_diag2, dim3(1), dim3(256), 0, st, A, m, noise, tau, g_launch_gate);
+  }
+  for (int it = 0; it <= maxit; ++it) {
+    const double2* Sp = A;
+    const double2* Rp = nullptr;
+    if (it > 0) {
+      {
+        GateScope g(run);
+        gemm_square(X, 1, X, 0, R, m, st, r.gpart, 1, sq_split);
+        gemm_square(A, 0, X, 0, T, m, st, r.gpart, 0, sq_split);
+        gemm_square(X, 1, T, 0, S, m, st, r.gpart, 1, sq_split);
+        hipLaunchKernelGGL(k_ref_check, dim3(ncheck), dim3(256), 0, st, S, R, m, (const double*)tau,
+                           r.part, g_launch_gate);
+        hipLaunchKernelGGL(k_ref_check_final, dim3(1), dim3(64), 0, st, (const double*)r.part,
+                           int(ncheck), r.norms, g_launch_gate);
+      }
+      hipLaunchKernelGGL(k_ref_decide, dim3(1), dim3(64), 0, st, (const double*)r.norms,
+                         (const int*)r.info, tol, it, maxit, flags, set);
+      {
+        GateScope g(flags + F_REF_OK + it);
+        eig_sort(S, X, m, m, w, Z, st);
+      }
+      if (it == maxit) break;
+      Sp = S;
+      Rp = R;
+      GateScope g(run);
+      hipLaunchKernelGGL(k_ref_tau, dim3(1), dim3(64), 0, st, (const double*)r.norms, m, noise, tau,
+                         g_launch_gate);
+    }
+    GateScope g(run);
+    hipLaunchKernelGGL(k_ref_lambda, dim3(gm), dim3(256), 0, st, Sp, Rp, m, r.lam, r.emax, g_launch_gate);
+    hipLaunchKernelGGL(k_ref_rank, dim3(gm), dim3(256), 0, st, (const double*)r.lam, m, r.rank,
+                       r.order, g_launch_gate);
+    hipLaunchKernelGGL(k_ref_reach, dim3(m), dim3(256), 0, st, Sp, Rp, (const double*)r.lam,
+                       (const int*)r.rank, m, THETA, (const double*)tau, r.reach, g_launch_gate);
+    hipLaunchKernelGGL(k_ref_clusters, dim3(1), dim3(1024), 0, st, (const int*)r.reach, m, r.pm,
+                       r.cstart, r.csize, r.cslot, r.clist, r.info, g_launch_gate);
+    hipLaunchKernelGGL(k_ref_cluster_eig, dim3(unsigned(m / 2 + 1)), dim3(256), 0, st, Sp, Rp, m,
+                       (const int*)r.order, (const int2*)r.clist, (const int*)r.info, r.W,
+                       tol * 1e-2, g_launch_gate);
+    hipLaunchKernelGGL(k_ref_lambda2, dim3(gm), dim3(256), 0, st, Sp, Rp, m, cl, r.lam2, g_launch_gate);
+    hipLaunchKernelGGL(k_ref_update, dim3(gm, unsigned(m)), dim3(256), 0, st, Sp, Rp, m, cl,
+                       (const double*)r.lam2, (const double*)tau, E, r.emax, g_launch_gate);
+    gemm_square(E, 0, E, 0, T, m, st, r.gpart, 0, sq_split);
+    hipLaunchKernelGGL(k_ref_build_q, dim3(gm, unsigned(m)), dim3(256), 0, st, (const double2*)E,
+                       (const double2*)T, m, cl, Q, g_launch_gate);
     if (it == 0) {
       std::swap(X, Q);
     } else {

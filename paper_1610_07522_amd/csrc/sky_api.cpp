@@ -46,6 +46,9 @@ constexpr int PC_RETRAIN_STEPS = 20;   // Adam steps of each online training
 constexpr double JACOBI_TOL = 1e-12;   // relative off-diagonal Frobenius norm
 constexpr int JACOBI_SWEEPS = 30;
 constexpr int REFINE_ITERS = 10;     // refinement steps before the Jacobi fallback
+// refinement steps of the device-decided iteration before it hands the set
+// to the host path (which takes up to REFINE_ITERS, then Jacobi)
+constexpr int REFINE_ITERS_DEV = 4;
 // ||I - 1||_F up to which I^-1/2 comes from its binomial series (<= 8 terms)
 constexpr double LOEWDIN_SERIES_MAX = 1e-2;
 // relative precision of H' built from the split-FP16 overlap and Hamiltonian
@@ -78,6 +81,7 @@ struct Layout {
   int pc_nb;   // largest sampled-state batch (states x shells)
   size_t plA, plB, plT, plU, plS;                  // FP16 split planes, scales (mixed only)
   size_t dens[2], der[2], mf[2], vc, fscratch, dens_part, epart, energy, info;
+  size_t gflags, gdbl;   // flags and doubles of the device-decided iteration
   size_t total;
 };
 
@@ -190,6 +194,8 @@ Layout plan(const sky_box_desc& d) {
   L.epart = take(sizeof(double) * 7 * size_t(energy_nblocks(d.n)));
   L.energy = take(sizeof(double) * 8);
   L.info = take(sizeof(int) * 4);
+  L.gflags = take(sizeof(int) * F_NFLAGS);
+  L.gdbl = take(sizeof(double) * D_NDOUBLES);
   L.total = off;
   return L;
 }
@@ -212,6 +218,8 @@ int validate(const sky_box_desc* d) {
     return fail(SKY_ERR_INVALID, "update must be SKY_UPDATE_EXACT or SKY_UPDATE_PAPER");
   if (d->one_h && d->update != SKY_UPDATE_EXACT)
     return fail(SKY_ERR_INVALID, "one_h needs SKY_UPDATE_EXACT");
+  if (d->dev_refine_steps < 0 || d->dev_refine_steps > F_NFLAGS - F_REF_OK - 1)
+    return fail(SKY_ERR_INVALID, "dev_refine_steps must be 0..39");
   const long V = 2L * d->n * d->n * d->n;
   if (states_of(*d, 0) > V || states_of(*d, 1) > V) return fail(SKY_ERR_INVALID, "more states than grid points");
   if (!(d->damp_e0 > 0.0)) return fail(SKY_ERR_INVALID, "damp_e0 must be positive");
@@ -276,6 +284,8 @@ struct sky_ctx {
     hipGraphExec_t a[MAXSET][4] = {};
     hipGraphExec_t b[MAXSET] = {};
     hipGraphExec_t f = nullptr;
+    // the whole iteration with its decisions on the device (sky_iterate_graph)
+    hipGraphExec_t full = nullptr;
   } graphs;
   int64_t iter_count = 0;     // iterations run on this context
   int64_t switched_at = -1;   // iteration after which the ladder switched to FP64
@@ -468,6 +478,41 @@ int subspace_solve(sky_ctx* c, int s, double* ritz) {
   gemm_square(Linv, terms > 0 ? 0 : 1, Z, 0, U, m, st, sq, 0, sqs);
   t_end(c, ts);
   return SKY_OK;
+}
+
+// Steps 3b-3d of set s with every decision on the device (launches only,
+// for the captured iteration): the Loewdin series with its term count from
+// the device, H', the device-decided refinement, U.  Where the host path
+// would take another branch (Cholesky far from orthonormality, the Jacobi
+// fallback) the box's flags hand the set to the host and mask the rest of
+// the iteration.
+void subspace_solve_dev(sky_ctx* c, int s) {
+  const int q = s & 1;
+  const int m = c->nq[q];
+  hipStream_t st = c->st;
+  int* fl = c->at<int>(c->lay.gflags);
+  double* db = c->at<double>(c->lay.gdbl);
+  void* I = c->at(c->lay.matI);
+  void* H = c->at(c->lay.matH);
+  void* Linv = c->at(c->lay.matL);
+  void* T = c->at(c->lay.matT);
+  void* Hp = c->at(c->lay.matHp);
+  void* Z = c->at(c->lay.matZ);
+  void* U = c->at(c->lay.matU);
+  void* sq = c->at(c->lay.sq_part);
+  const int sqs = c->tune.sq[q];
+  loewdin_series_dev(I, Linv, c->at(c->lay.matC), T, m, LOEWDIN_SERIES_MAX,
+                     c->at<double>(c->lay.nrm), sq, st, sqs, fl, db, s);
+  {
+    GateScope g(fl + F_ACTIVE);
+    gemm_square(Linv, 0, H, 0, T, m, st, sq, 0, sqs);
+    gemm_square(T, 0, Linv, 0, Hp, m, st, sq, 1, sqs);
+    hermitian_fill(Hp, m, st);
+  }
+  refine_eigh_dev(Hp, m, c->at<double>(c->lay.ritz[s]), Z, c->at(c->lay.ref_work), JACOBI_TOL,
+                  c->d.dev_refine_steps > 0 ? c->d.dev_refine_steps : REFINE_ITERS_DEV, st, sqs, c->prec ? MIXED_HP_NOISE : 0x1p-49, fl, s);
+  GateScope g(fl + F_ACTIVE);
+  gemm_square(Linv, 0, Z, 0, U, m, st, sq, 0, sqs);
 }
 
 // Unitary polar factor P of the k x k complex matrix G (row-major; G = P S
@@ -881,6 +926,7 @@ void graphs_clear(sky_ctx* c) {
     drop(c->graphs.b[s]);
   }
   drop(c->graphs.f);
+  drop(c->graphs.full);
 }
 
 // Runs body's launches: directly, or (graphs on, timing off) by replaying the
@@ -1000,6 +1046,189 @@ template <typename F> int pick(hipStream_t st, const int* cand, int nc, F op) {
     if (t < tb) { tb = t; best = cand[i]; }
   }
   return best;
+}
+
+// ------------------------------------------------------------------ device-decided iteration
+// Whether the context can run the captured iteration whose decisions are
+// made on the device.  Options whose decisions stay on the host (the learned
+// damping's fallback rule and online training, the precision ladder, the
+// paper-literal update, one h application, phase timing) and a context on
+// the null stream (no capture there) run sky_iterate instead.
+bool dev_iteration_ok(const sky_ctx* c) {
+  return !c->timing && c->d.update == SKY_UPDATE_EXACT && !c->d.one_h && !c->pc_on &&
+         !(c->prec == 1 && c->d.ladder_tol > 0.0) && c->st != nullptr;
+}
+
+// Delta-eps of the iteration, the iteration count and the convergence test,
+// on the device (k_iteration_end).
+void dev_iteration_end(sky_ctx* c) {
+  const double* r2[MAXSET];
+  int nocc[MAXSET];
+  for (int s = 0; s < c->nset; ++s) {
+    r2[s] = c->at<double>(c->lay.r2[s]);
+    nocc[s] = c->m_of(s) ? c->nocc[s & 1] : 0;
+  }
+  iteration_end(r2, nocc, c->nset, c->ntw * (c->nocc[0] + c->nocc[1]), c->at<int>(c->lay.gflags),
+                c->at<double>(c->lay.gdbl), c->st);
+}
+
+// One iteration (every set, the fields, Delta-eps), each kernel gated by the
+// box's flags: launches only, captured once per context and precision.
+void iteration_dev(sky_ctx* c) {
+  int* fl = c->at<int>(c->lay.gflags);
+  for (int s = 0; s < c->nset; ++s) {
+    if (c->m_of(s) == 0) continue;
+    {
+      GateScope g(fl + F_ACTIVE);
+      step_a(c, s, false, false);
+    }
+    subspace_solve_dev(c, s);
+    GateScope g(fl + F_ACTIVE);
+    subspace_combine(c, s, c->phi(s), c->psi(s));
+  }
+  {
+    GateScope g(fl + F_ACTIVE);
+    fields(c);
+  }
+  dev_iteration_end(c);
+}
+
+// The rest of an iteration on the host path, from the solve of set s0 (its
+// phi, h phi, I and H are in place) when the device handed it over; then
+// the box is active again and Delta-eps is taken on the device.
+int resume_on_host(sky_ctx* c, int s0) {
+  for (int s = s0; s < c->nset; ++s) {
+    if (c->m_of(s) == 0) continue;
+    if (s > s0) step_a(c, s, false, false);
+    int rc = subspace_solve(c, s, c->at<double>(c->lay.ritz[s]));
+    if (rc) return rc;
+    subspace_combine(c, s, c->phi(s), c->psi(s));
+  }
+  fields(c);
+  int* fl = c->at<int>(c->lay.gflags);
+  set_flag(fl, F_HOST, HOST_NONE, c->st);
+  set_flag(fl, F_ACTIVE, 1, c->st);
+  dev_iteration_end(c);
+  return SKY_OK;
+}
+
+int capture_full(sky_ctx* c) {
+  if (c->graphs.prec != c->prec) {
+    hipStreamSynchronize(c->st);
+    graphs_clear(c);
+    c->graphs.prec = c->prec;
+  }
+  if (c->graphs.full) return SKY_OK;
+  hipGraph_t g = nullptr;
+  int rc = hip_check(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal), "graph capture");
+  if (rc) return rc;
+  iteration_dev(c);
+  rc = hip_check(hipStreamEndCapture(c->st, &g), "graph capture");
+  if (rc) return rc;
+  rc = hip_check(hipGraphInstantiate(&c->graphs.full, g, nullptr, nullptr, 0), "graph instantiate");
+  hipGraphDestroy(g);
+  if (rc) return rc;
+  ++c->graphs.captures;
+  return SKY_OK;
+}
+
+// A device-decided run of one context: started, then launched and collected
+// chunk by chunk (the host reads the flags once per chunk).
+struct DevRun {
+  sky_ctx* c = nullptr;
+  int max_iter = 0, chunk = 1;
+  double tol = 0.0;
+  int done = 0;        // iterations completed
+  int handovers = 0;   // iterations finished on the host path
+  bool finished = false;
+  int status = SKY_OK;
+  int flags[F_NFLAGS] = {};
+  double dbl[D_NDOUBLES] = {};
+};
+
+int dev_start(DevRun& r) {
+  sky_ctx* c = r.c;
+  c->fallbacks = 0;
+  c->unconverged = 0;
+  c->pc_iters = 0;
+  int* fl = c->at<int>(c->lay.gflags);
+  for (int f = 0; f < F_NFLAGS; ++f) set_flag(fl, f, f == F_ACTIVE ? 1 : 0, c->st);
+  set_double(c->at<double>(c->lay.gdbl), D_TOL, r.tol > 0.0 ? r.tol : 0.0, c->st);
+  set_double(c->at<double>(c->lay.gdbl), D_DE, 0.0, c->st);
+  if (r.max_iter == 0) r.finished = true;
+  return capture_full(c);
+}
+
+int dev_launch(DevRun& r) {
+  if (r.finished) return SKY_OK;
+  const int k = std::min(r.chunk, r.max_iter - r.done);
+  for (int i = 0; i < k; ++i) {
+    int rc = hip_check(hipGraphLaunch(r.c->graphs.full, r.c->st), "graph launch");
+    if (rc) return rc;
+  }
+  return SKY_OK;
+}
+
+int dev_read(DevRun& r) {
+  sky_ctx* c = r.c;
+  int rc = hip_check(hipMemcpyAsync(r.flags, c->at(c->lay.gflags), sizeof(r.flags),
+                                    hipMemcpyDeviceToHost, c->st), "flags copy");
+  if (rc) return rc;
+  rc = hip_check(hipMemcpyAsync(r.dbl, c->at(c->lay.gdbl), sizeof(r.dbl), hipMemcpyDeviceToHost,
+                                c->st), "flags copy");
+  if (rc) return rc;
+  return hip_check(hipStreamSynchronize(c->st), "iterate_graph");
+}
+
+// After the stream has drained: read the flags, finish a handed-over
+// iteration on the host, decide whether the run is done.
+int dev_collect(DevRun& r) {
+  if (r.finished) return SKY_OK;
+  int rc = dev_read(r);
+  if (rc) return rc;
+  if (r.flags[F_HOST] == HOST_NAN) return fail(SKY_ERR_NAN, "non-finite residual");
+  if (r.flags[F_HOST] != HOST_NONE) {
+    rc = resume_on_host(r.c, r.flags[F_HOST_SET]);
+    if (rc) return rc;
+    ++r.handovers;
+    rc = dev_read(r);
+    if (rc) return rc;
+    if (r.flags[F_HOST] == HOST_NAN) return fail(SKY_ERR_NAN, "non-finite residual");
+  }
+  r.done = r.flags[F_ITER];
+  if (r.flags[F_CONV]) {
+    r.finished = true;
+    r.status = SKY_OK;
+  } else if (r.done >= r.max_iter) {
+    r.finished = true;
+    r.status = r.tol > 0.0 ? SKY_NOT_CONVERGED : SKY_OK;
+  }
+  return SKY_OK;
+}
+
+int dev_finish(DevRun& r, sky_report* rep) {
+  sky_ctx* c = r.c;
+  double e[8] = {0};
+  int rc = hip_check(hipMemcpyAsync(e, c->at(c->lay.energy), sizeof(e), hipMemcpyDeviceToHost, c->st),
+                     "energy copy");
+  if (rc) return rc;
+  rc = hip_check(hipStreamSynchronize(c->st), "iterate_graph");
+  if (rc) return rc;
+  if (!std::isfinite(e[7])) return fail(SKY_ERR_NAN, "non-finite energy");
+  c->iter_count += r.done;
+  c->de_prev = r.dbl[D_DE];
+  if (rep) {
+    rep->precision = c->prec ? SKY_MIXED : SKY_FP64;
+    rep->iters = r.done;
+    rep->residual = r.dbl[D_DE];
+    rep->energy = e[7];
+    rep->energy_per_a = e[7] / double(std::max(1, c->nocc[0] + c->nocc[1]));
+    rep->eig_iters = r.flags[F_REF_STEPS];
+    rep->eig_fallbacks = r.handovers;
+    rep->precond_iters = 0;
+    rep->eig_unconverged = c->unconverged;
+  }
+  return r.status;
 }
 }  // namespace
 
@@ -1607,6 +1836,135 @@ int sky_set_graphs(sky_ctx* c, int32_t enable) {
   if (rc) return rc;
   graphs_clear(c);
   c->graphs.on = enable != 0;
+  return SKY_OK;
+}
+
+int sky_iterate_graph(sky_ctx* c, int32_t max_iter, double tol, int32_t chunk, sky_report* rep) {
+  if (!c || max_iter < 0 || chunk < 1) return fail(SKY_ERR_INVALID, "iterate_graph arguments");
+  if (!dev_iteration_ok(c)) return sky_iterate(c, max_iter, tol, rep);
+  DevRun r;
+  r.c = c;
+  r.max_iter = max_iter;
+  r.chunk = chunk;
+  r.tol = tol;
+  int rc = dev_start(r);
+  if (rc) return rc;
+  while (!r.finished) {
+    rc = dev_launch(r);
+    if (rc) return rc;
+    rc = dev_collect(r);
+    if (rc) return rc;
+  }
+  return dev_finish(r, rep);
+}
+
+int sky_batch_iterate_graph(sky_ctx* const* ctxs, int32_t nbox, int32_t nthreads,
+                            int32_t max_iter, double tol, int32_t chunk, sky_report* reps,
+                            int32_t* status) {
+  if (!ctxs || nbox < 1 || nthreads < 1 || max_iter < 0 || chunk < 1 || !reps || !status)
+    return fail(SKY_ERR_INVALID, "batch_iterate_graph arguments");
+  for (int i = 0; i < nbox; ++i) {
+    if (!ctxs[i]) return fail(SKY_ERR_INVALID, "batch_iterate_graph: null context");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return fail(SKY_ERR_INVALID, "batch_iterate_graph: a context appears twice");
+  }
+  int dev = 0;
+  int rc = hip_check(hipGetDevice(&dev), "batch_iterate_graph");
+  if (rc) return rc;
+  rc = hip_check(hipDeviceSynchronize(), "batch_iterate_graph");
+  if (rc) return rc;
+  // the same longest-processing-time assignment as sky_batch_iterate
+  const int nw = std::min(nthreads, nbox);
+  std::vector<std::pair<double, int>> cost(nbox);
+  for (int i = 0; i < nbox; ++i) {
+    const sky_ctx* c = ctxs[i];
+    double w = 0.0;
+    for (int q = 0; q < 2; ++q)
+      w += double(c->ntw) * double(c->nq[q]) * double(c->V) *
+           (double(c->nq[q]) + 40.0 * std::log2(double(c->V)));
+    cost[i] = {w, i};
+  }
+  std::sort(cost.begin(), cost.end(), [](auto& x, auto& y) { return x.first > y.first; });
+  std::vector<std::vector<int>> mine(nw);
+  std::vector<double> load(nw, 0.0);
+  for (auto& [w, i] : cost) {
+    const int k = int(std::min_element(load.begin(), load.end()) - load.begin());
+    mine[k].push_back(i);
+    load[k] += w;
+  }
+  std::vector<std::string> errs(nw);
+  // each worker drives its boxes round by round: every unfinished box gets a
+  // chunk of captured iterations queued on the worker's stream, then one
+  // drain of the stream and one read of every box's flags
+  auto worker = [&](int k) {
+    hipSetDevice(dev);
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      for (int i : mine[k]) status[i] = SKY_ERR_HIP;
+      errs[k] = "batch_iterate_graph: stream creation failed";
+      return;
+    }
+    std::vector<DevRun> runs(mine[k].size());
+    std::vector<hipStream_t> keep(mine[k].size());
+    std::vector<bool> keep_graphs(mine[k].size());
+    std::vector<bool> dev_ok(mine[k].size());
+    for (size_t b = 0; b < mine[k].size(); ++b) {
+      const int i = mine[k][b];
+      sky_ctx* c = ctxs[i];
+      keep[b] = c->st;
+      keep_graphs[b] = c->graphs.on;
+      c->st = s;
+      c->graphs.on = true;
+      std::memset(&reps[i], 0, sizeof(sky_report));
+      dev_ok[b] = dev_iteration_ok(c);
+      if (!dev_ok[b]) {   // host-decided options: the host path, box by box
+        status[i] = sky_iterate(c, max_iter, tol, &reps[i]);
+        runs[b].finished = true;
+        continue;
+      }
+      runs[b].c = c;
+      runs[b].max_iter = max_iter;
+      runs[b].chunk = chunk;
+      runs[b].tol = tol;
+      status[i] = dev_start(runs[b]);
+      if (status[i]) runs[b].finished = true;
+    }
+    for (;;) {
+      bool any = false;
+      for (size_t b = 0; b < runs.size(); ++b) {
+        if (runs[b].finished || !dev_ok[b]) continue;
+        any = true;
+        const int rc = dev_launch(runs[b]);
+        if (rc) { status[mine[k][b]] = rc; runs[b].finished = true; }
+      }
+      if (!any) break;
+      for (size_t b = 0; b < runs.size(); ++b) {
+        if (runs[b].finished || !dev_ok[b]) continue;
+        const int rc = dev_collect(runs[b]);
+        if (rc) { status[mine[k][b]] = rc; runs[b].finished = true; runs[b].status = rc; }
+      }
+    }
+    for (size_t b = 0; b < runs.size(); ++b) {
+      const int i = mine[k][b];
+      sky_ctx* c = ctxs[i];
+      if (dev_ok[b] && status[i] == SKY_OK) status[i] = dev_finish(runs[b], &reps[i]);
+      if (status[i] != SKY_OK && status[i] != SKY_NOT_CONVERGED && errs[k].empty()) errs[k] = g_err;
+      hipStreamSynchronize(s);
+      c->graphs.on = keep_graphs[b];
+      c->st = keep[b];
+    }
+    hipStreamDestroy(s);
+  };
+  std::vector<std::thread> pool;
+  for (int k = 1; k < nw; ++k) pool.emplace_back(worker, k);
+  worker(0);
+  for (auto& t : pool) t.join();
+  for (int i = 0; i < nbox; ++i)
+    if (status[i] != SKY_OK && status[i] != SKY_NOT_CONVERGED) {
+      std::string msg;
+      for (auto& e : errs) if (!e.empty()) { msg = e; break; }
+      return fail(status[i], "batch_iterate_graph: box " + std::to_string(i) + ": " + msg);
+    }
   return SKY_OK;
 }
 

@@ -7,6 +7,43 @@
 
 namespace sky {
 
+// ---- launch gate
+// Every kernel of the library takes a gate: a device int that it reads first,
+// returning at once if it is 0 (nullptr: always run).  The launchers pass the
+// calling thread's current gate, nullptr unless a GateScope is open, so that
+// a context can mask a box's kernels, or pick between branches of its
+// iteration, from values computed on the device (a captured iteration then
+// needs no host decision).
+extern thread_local const int* g_launch_gate;
+struct GateScope {
+  const int* prev;
+  explicit GateScope(const int* g) : prev(g_launch_gate) { g_launch_gate = g; }
+  ~GateScope() { g_launch_gate = prev; }
+  GateScope(const GateScope&) = delete;
+  GateScope& operator=(const GateScope&) = delete;
+};
+
+// ---- device-decided iteration: flags of one box (ints in device memory)
+// F_ACTIVE: the box's iteration kernels run (cleared at convergence, or
+//   when a decision needs the host); F_HOST: 0, or the stage that stopped
+//   the box (HOST_LOEWDIN: the overlap is too far from the identity for the
+//   series, or not finite; HOST_REFINE: the refinement did not converge;
+//   HOST_NAN: a non-finite residual) and F_HOST_SET its state set;
+//   F_ITER: iterations completed on the device; F_CONV: Delta-eps <= tol;
+//   F_SERIES + k: Horner step k of the Loewdin series runs; F_REF_RUN: the
+//   refinement continues; F_REF_OK + it: it converged at check it (its
+//   eigenpairs are sorted out there); F_REF_STEPS: refinement steps taken.
+enum DevFlag {
+  F_ACTIVE = 0, F_HOST = 1, F_HOST_SET = 2, F_ITER = 3, F_CONV = 4, F_REF_RUN = 5,
+  F_REF_STEPS = 6, F_SERIES = 8, F_REF_OK = 24, F_NFLAGS = 64
+};
+enum HostStage { HOST_NONE = 0, HOST_LOEWDIN = 1, HOST_REFINE = 2, HOST_NAN = 3 };
+// doubles beside the flags: D_TOL (the tolerance), D_DE (the last Delta-eps),
+// D_SERIES.. (norm, term count and the series coefficients of the last solve)
+enum DevDouble { D_TOL = 0, D_DE = 1, D_SERIES = 4, D_NDOUBLES = 32 };
+void set_flag(int* flags, int idx, int value, hipStream_t st);   // ungated
+void set_double(double* d, int idx, double value, hipStream_t st);   // ungated
+
 // ---- grid kernels (k_grid.hip); states are [state][2][n^3], complex128
 // (prec 0) or complex64 (prec 1); reductions are FP64 either way.
 int grid_ntiles(int n);  // room for the per-state partials of one pass
@@ -187,6 +224,15 @@ void gemm_square(const void* A, int opA, const void* B, int opB, void* C, int m,
 size_t refine_scratch_bytes(int m);
 int refine_eigh(const void* A, int m, double* w, void* Z, void* work, double tol, int maxit,
                 hipStream_t st, int sq_split = 0, double noise = 0x1p-49);
+// The same refinement with its decisions on the device (launches only): up
+// to maxit steps, each gated by flags[F_REF_RUN]; the check after step it
+// sorts the eigenpairs out when converged (flags[F_REF_OK + it]); a step
+// that would make the host version give up (maxit reached, a cluster over
+// the limit, a non-finite check) sets F_HOST = HOST_REFINE (set `set`) and
+// clears F_ACTIVE.  The E^2 term of the update is always formed.  maxit <=
+// F_NFLAGS - F_REF_OK - 1.
+void refine_eigh_dev(const void* A, int m, double* w, void* Z, void* work, double tol, int maxit,
+                     hipStream_t st, int sq_split, double noise, int* flags, int set);
 
 // ---- dense FP64 linear algebra (k_linalg.hip)
 // Cholesky A = L L^H of Hermitian positive definite A (m x m, lower used),
@@ -219,6 +265,21 @@ void gauge_apply(const void* Z, int m, const int* info, const void* Q, void* out
 // scratch (gemm_square); synchronises the stream.
 int loewdin_series(const void* I, void* C, void* D, void* T, int m, double max_dev,
                    double* scratch, void* part, hipStream_t st, int sq_split = 0);
+// The series with the decision on the device: the term count from the norm
+// of D = I - 1 (as loewdin_series), Horner steps gated by flags[F_SERIES + k].
+// If the series does not apply (norm above max_dev or not finite), flags
+// get F_HOST = HOST_LOEWDIN (set `set`) and F_ACTIVE = 0.  dbl: the box's
+// doubles (D_SERIES..).  Launches only.
+void loewdin_series_dev(const void* I, void* C, void* D, void* T, int m, double max_dev,
+                        double* scratch, void* part, hipStream_t st, int sq_split, int* flags,
+                        double* dbl, int set);
+// End of a device-decided iteration (one workgroup, ungated): if the box is
+// active, F_ITER += 1 and Delta-eps = sqrt(sum of ||r||^2 over the first
+// nocc[s] states of each set s / count) goes to dbl[D_DE]; Delta-eps <=
+// dbl[D_TOL] sets F_CONV and clears F_ACTIVE; a non-finite one sets
+// F_HOST = HOST_NAN.  Up to 64 sets.
+void iteration_end(const double* const* r2, const int* nocc, int nset, int count, int* flags,
+                   double* dbl, hipStream_t st);
 // w ascending (ties by index) from the diagonal of D (ld = ld) and Z the
 // matching columns of V (ld = ld), Z m x m.
 void eig_sort(const void* D, const void* V, int m, int ld, double* w, void* Z, hipStream_t st);

@@ -42,6 +42,7 @@ EXPORTS = ("sky_workspace_size", "sky_create", "sky_init_box", "sky_apply_h",
            "sky_get_view", "sky_set_states", "sky_get_states", "sky_get_iteration",
            "sky_set_iteration", "sky_set_timing", "sky_get_timing", "sky_get_precision",
            "sky_autotune", "sky_get_tuning", "sky_set_graphs", "sky_batch_iterate",
+           "sky_iterate_graph", "sky_batch_iterate_graph",
            "sky_precond_collect", "sky_precond_train",
            "sky_precond_loss_grad", "sky_precond_set_rows", "sky_precond_use",
            "sky_set_preconditioner", "sky_sync",
@@ -66,7 +67,8 @@ class BoxDesc(ctypes.Structure):
                 ("extra_n", ctypes.c_int32), ("extra_p", ctypes.c_int32),
                 ("ntwist", ctypes.c_int32),
                 ("twist", (ctypes.c_double * 3) * SKY_MAX_TWIST),
-                ("update", ctypes.c_int32), ("one_h", ctypes.c_int32)]
+                ("update", ctypes.c_int32), ("one_h", ctypes.c_int32),
+                ("dev_refine_steps", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -138,6 +140,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "sky_set_graphs": (ctypes.c_int, [vp, i32]),
         "sky_batch_iterate": (ctypes.c_int, [ctypes.POINTER(vp), i32, i32, i32, dbl,
                                              ctypes.POINTER(Report), ctypes.POINTER(ctypes.c_int32)]),
+        "sky_iterate_graph": (ctypes.c_int, [vp, i32, dbl, i32, ctypes.POINTER(Report)]),
+        "sky_batch_iterate_graph": (ctypes.c_int, [ctypes.POINTER(vp), i32, i32, i32, dbl, i32,
+                                                   ctypes.POINTER(Report),
+                                                   ctypes.POINTER(ctypes.c_int32)]),
         "sky_precond_collect": (ctypes.c_int, [vp, i32, ctypes.POINTER(ctypes.c_int32)]),
         "sky_precond_train": (ctypes.c_int, [vp, i32, dbl, dp]),
         "sky_precond_loss_grad": (ctypes.c_int, [vp, i32, dp]),
@@ -210,6 +216,19 @@ def batch_iterate(boxes, nthreads: int, max_iter: int, tol: float = 0.0):
     reps = (Report * n)()
     st = (ctypes.c_int32 * n)()
     _check(lib.sky_batch_iterate(ctxs, n, nthreads, max_iter, tol, reps, st))
+    return [_report_dict(reps[i], st[i]) for i in range(n)]
+
+
+def batch_iterate_graph(boxes, nthreads: int, max_iter: int, tol: float = 0.0, chunk: int = 16):
+    """sky_batch_iterate_graph over ``boxes`` (a list of Box): per-box report dicts."""
+    if not boxes:
+        return []
+    lib = boxes[0].lib
+    n = len(boxes)
+    ctxs = (ctypes.c_void_p * n)(*[b.ctx.value for b in boxes])
+    reps = (Report * n)()
+    st = (ctypes.c_int32 * n)()
+    _check(lib.sky_batch_iterate_graph(ctxs, n, nthreads, max_iter, tol, chunk, reps, st))
     return [_report_dict(reps[i], st[i]) for i in range(n)]
 
 
@@ -296,6 +315,12 @@ class Box:
     def iterate(self, max_iter: int, tol: float = 0.0) -> Dict[str, float]:
         rep = Report()
         rc = _check(self.lib.sky_iterate(self.ctx, max_iter, tol, ctypes.byref(rep)),
+                    ok=(SKY_OK, SKY_NOT_CONVERGED))
+        return _report_dict(rep, rc)
+
+    def iterate_graph(self, max_iter: int, tol: float = 0.0, chunk: int = 16) -> Dict[str, float]:
+        rep = Report()
+        rc = _check(self.lib.sky_iterate_graph(self.ctx, max_iter, tol, chunk, ctypes.byref(rep)),
                     ok=(SKY_OK, SKY_NOT_CONVERGED))
         return _report_dict(rep, rc)
 
