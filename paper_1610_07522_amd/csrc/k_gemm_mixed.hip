@@ -436,6 +436,56 @@ k_split_t(const void* __restrict__ xv, int R, long C, long ldr, const unsigned i
   }
 }
 
+// Both plane layouts of an R x K complex64 matrix from one read of it: the
+// row planes P[p][r][k] (pitch K + NT_PAD, rows r < R) and the transposed
+// planes PT[p][k][r] (row length ldr, rows r >= R zero-filled), one 64 x 64
+// tile per workgroup (grid K/64 x ldr/64).
+__global__ void __launch_bounds__(256)
+k_split_both(const float2* __restrict__ x, int R, long K, long ldr, const unsigned int* __restrict__ mx,
+             unsigned short* __restrict__ P, unsigned short* __restrict__ PT,
+             const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
+  __shared__ float2 T[64][65];
+  const long c0 = long(blockIdx.x) * 64;
+  const int r0 = blockIdx.y * 64;
+  const int tid = threadIdx.x;
+  const int S = scale_exp(*mx);
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int rr = e / 64, cc = e % 64;
+    float2 z = make_float2(0, 0);
+    if (r0 + rr < R && c0 + cc < K) z = x[size_t(r0 + rr) * K + c0 + cc];
+    T[cc][rr] = z;
+  }
+  __syncthreads();
+  const long ld = K + NT_PAD;
+  const size_t psz = size_t(R) * ld;
+  for (int g = tid; g < 64 * 8; g += 256) {   // row planes: row rr, 8 elements at cg
+    const int rr = g / 8, cg = (g % 8) * 8;
+    if (r0 + rr >= R || c0 + cg >= K) continue;
+    float2 z[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) z[e] = T[cg + e][rr];
+    u4 w[NP];
+    split8(z, S, w);
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+      *reinterpret_cast<u4*>(P + p * psz + size_t(r0 + rr) * ld + c0 + cg) = w[p];
+  }
+  const size_t pszT = size_t(K) * ldr;
+  for (int g = tid; g < 64 * 8; g += 256) {   // transposed planes: column cc, 8 rows at rg
+    const int cc = g / 8, rg = (g % 8) * 8;
+    if (c0 + cc >= K || r0 + rg >= ldr) continue;
+    float2 z[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) z[e] = T[cc][rg + e];
+    u4 w[NP];
+    split8(z, S, w);
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+      *reinterpret_cast<u4*>(PT + p * pszT + size_t(c0 + cc) * ldr + r0 + rg) = w[p];
+  }
+}
+
 // ------------------------------------------------------------------ products
 // Workgroup w -> (chunk s, tile pair, z) of the overlap grid.
 __device__ inline void overlap_work(int w, int npair, int split, int nz, int& s, int& pair, int& z) {
@@ -677,6 +727,15 @@ void split_planes_nt(const void* x, int rows, long k, const unsigned int* mx, vo
   const size_t n = size_t(rows) * (k / 8);
   hipLaunchKernelGGL(k_split_nt, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st,
                      (const float2*)x, rows, k, mx, (unsigned short*)P, g_launch_gate);
+}
+
+void split_planes_both(const void* x, int rows, long k, const unsigned int* mx, void* P, void* PT,
+                       hipStream_t st) {
+  if (rows <= 0) return;
+  const long ldr = planes_pad(rows);
+  dim3 grid(unsigned((k + 63) / 64), unsigned((ldr + 63) / 64));
+  hipLaunchKernelGGL(k_split_both, grid, dim3(256), 0, st, (const float2*)x, rows, k, ldr, mx,
+                     (unsigned short*)P, (unsigned short*)PT, g_launch_gate);
 }
 
 void split_planes_t(const void* x, int x_is_c128, int rows, long cols, const unsigned int* mx,

@@ -394,11 +394,13 @@ k_ref_update(const double2* __restrict__ S, const double2* __restrict__ R, int m
 }
 
 // Q[order[s]][b] = sum_{t in cluster(s)} W[s - c][t - c] (delta_tb + E_tb + E2_tb / 2)
-// (E2 null: the second-order term is below rounding and left out).
+// (E2 null, or e2flag pointing at 0: the second-order term is below rounding
+// and left out).
 __global__ void __launch_bounds__(256)
-k_ref_build_q(const double2* __restrict__ E, const double2* __restrict__ E2, int m, Clusters cl,
-              double2* __restrict__ Q, const int* __restrict__ sky_gate) {
+k_ref_build_q(const double2* __restrict__ E, const double2* __restrict__ E2v, const int* __restrict__ e2flag,
+              int m, Clusters cl, double2* __restrict__ Q, const int* __restrict__ sky_gate) {
   if (sky_gate != nullptr && *sky_gate == 0) return;
+  const double2* E2 = (e2flag == nullptr || *e2flag != 0) ? E2v : nullptr;
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
   if (b >= m) return;
@@ -412,6 +414,17 @@ k_ref_build_q(const double2* __restrict__ E, const double2* __restrict__ E2, int
     acc = cadd(acc, Wc ? cmul(Wc[(s - c) * KMAX + t], q) : q);
   }
   Q[size_t(cl.order[s]) * m + b] = acc;
+}
+
+// Whether the step forms E^2/2: |E| above E2_SKIP (below, the term is under
+// FP64 rounding of 1 + E).  Decided on the device (the flag gates the E^2
+// product and tells k_ref_build_q to use it); 0 when the run flag is off.
+constexpr double E2_SKIP = 1e-8;
+__global__ void k_ref_e2_flag(const unsigned long long* __restrict__ emax, const int* __restrict__ run,
+                              int* __restrict__ flag) {
+  if (threadIdx.x != 0) return;
+  const double em = __longlong_as_double((long long)*emax);
+  *flag = ((run == nullptr || *run != 0) && !(em <= E2_SKIP)) ? 1 : 0;
 }
 
 // S <- (S + S^H) / 2 and R <- 1 - (G + G^H) / 2 in place (R holds G = X^H X
@@ -622,13 +635,17 @@ int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double to
     hipLaunchKernelGGL(k_ref_lambda2, dim3(gm), dim3(256), 0, st, Sp, Rp, m, cl, r.lam2, g_launch_gate);
     hipLaunchKernelGGL(k_ref_update, dim3(gm, unsigned(m)), dim3(256), 0, st, Sp, Rp, m, cl,
                        (const double*)r.lam2, (const double*)tau, E, r.emax, g_launch_gate);
-    // the second-order term E^2/2 is always formed (below |E| ~ 1e-8 it is
-    // under FP64 rounding of 1 + E; leaving it out there would need |E| on
-    // the host, and the device-decided refinement forms it too, so that the
-    // two take the same arithmetic)
-    gemm_square(E, 0, E, 0, T, m, st, r.gpart, 0, sq_split);
+    // E^2/2 only while |E| > E2_SKIP, decided on the device (as in the
+    // device-decided refinement, so that the two take the same arithmetic)
+    int* e2 = r.info + 3;
+    hipLaunchKernelGGL(k_ref_e2_flag, dim3(1), dim3(64), 0, st, (const unsigned long long*)r.emax,
+                       g_launch_gate, e2);
+    {
+      GateScope g2(e2);
+      gemm_square(E, 0, E, 0, T, m, st, r.gpart, 0, sq_split);
+    }
     hipLaunchKernelGGL(k_ref_build_q, dim3(gm, unsigned(m)), dim3(256), 0, st, (const double2*)E,
-                       (const double2*)T, m, cl, Q, g_launch_gate);
+                       (const double2*)T, (const int*)e2, m, cl, Q, g_launch_gate);
     if (it == 0) {
       std::swap(X, Q);
     } else {
@@ -728,9 +745,15 @@ void refine_eigh_dev(const void* Av, int m, double* w, void* Z, void* work, doub
     hipLaunchKernelGGL(k_ref_lambda2, dim3(gm), dim3(256), 0, st, Sp, Rp, m, cl, r.lam2, g_launch_gate);
     hipLaunchKernelGGL(k_ref_update, dim3(gm, unsigned(m)), dim3(256), 0, st, Sp, Rp, m, cl,
                        (const double*)r.lam2, (const double*)tau, E, r.emax, g_launch_gate);
-    gemm_square(E, 0, E, 0, T, m, st, r.gpart, 0, sq_split);
+    int* e2 = r.info + 3;
+    hipLaunchKernelGGL(k_ref_e2_flag, dim3(1), dim3(64), 0, st, (const unsigned long long*)r.emax,
+                       run, e2);
+    {
+      GateScope g2(e2);
+      gemm_square(E, 0, E, 0, T, m, st, r.gpart, 0, sq_split);
+    }
     hipLaunchKernelGGL(k_ref_build_q, dim3(gm, unsigned(m)), dim3(256), 0, st, (const double2*)E,
-                       (const double2*)T, m, cl, Q, g_launch_gate);
+                       (const double2*)T, (const int*)e2, m, cl, Q, g_launch_gate);
     if (it == 0) {
       std::swap(X, Q);
     } else {

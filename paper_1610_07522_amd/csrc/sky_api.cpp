@@ -390,9 +390,8 @@ void subspace_matrices(sky_ctx* c, int s, const void* phi, const void* hphi,
       plane_scale(phi, 0, ne, mx, st);
       plane_scale(hphi, 0, ne, mx + 1, st);
     }
-    split_planes_nt(phi, m, c->V, mx, c->at(c->lay.plA), st);
+    split_planes_both(phi, m, c->V, mx, c->at(c->lay.plA), c->at(c->lay.plT), st);
     split_planes_nt(hphi, m, c->V, mx + 1, c->at(c->lay.plB), st);
-    split_planes_t(phi, 0, m, c->V, mx, c->at(c->lay.plT), st);
     t_end(c, tp);
   }
   int tm = -1;
@@ -721,8 +720,7 @@ int loewdin(sky_ctx* c, int s, const void* phi, void* psi_out) {
   unsigned int* mx = c->at<unsigned int>(c->lay.plS);
   if (c->prec) {
     plane_scale(phi, 0, size_t(m) * c->V, mx, st);
-    split_planes_nt(phi, m, c->V, mx, c->at(c->lay.plA), st);
-    split_planes_t(phi, 0, m, c->V, mx, c->at(c->lay.plT), st);
+    split_planes_both(phi, m, c->V, mx, c->at(c->lay.plA), c->at(c->lay.plT), st);
     overlap_lower_planes(c->at(c->lay.plA), c->at(c->lay.plA), nullptr, mx, mx, nullptr, m,
                          c->V, c->g.dV, I, nullptr, c->at(c->lay.gemm_part), st, nullptr,
                          c->tune.ovl[q]);

@@ -178,6 +178,10 @@ void split_planes_nt(const void* x, int rows, long k, const unsigned int* mx, vo
                      hipStream_t st);
 void split_planes_t(const void* x, int x_is_c128, int rows, long cols, const unsigned int* mx,
                     void* P, hipStream_t st);
+// split_planes_nt into P and split_planes_t into PT of the same complex64
+// matrix (rows x k) from one read of it.
+void split_planes_both(const void* x, int rows, long k, const unsigned int* mx, void* P, void* PT,
+                       hipStream_t st);
 // C0 = scale * conj(A) B0^T (and C1 with B1), lower 64-tiles, from NT planes.
 // split_req > 0 overrides the split-K factor (one of overlap_split_candidates_mixed).
 int overlap_split_candidates_mixed(int m, long k, int* out);
