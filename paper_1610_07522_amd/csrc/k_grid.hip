@@ -10,8 +10,19 @@
 namespace sky {
 
 // Spin-orbit matrix A_dir = (W x sigma)_dir = ax*sx + ay*sy + az*sz.
-template <int DIR> __device__ inline void so_coeffs(double wx, double wy, double wz,
-                                                    double& ax, double& ay, double& az) {
+// Field value at point r in the kernel's precision: complex64 kernels read
+// the FP32 copies (the same rounding as converting the FP64 value).
+template <typename T> __device__ inline T fld_U(const MeanFieldPtrs& m, size_t r) {
+  if constexpr (sizeof(T) == 4) return m.U32[r]; else return m.U[r];
+}
+template <typename T> __device__ inline T fld_B(const MeanFieldPtrs& m, size_t r) {
+  if constexpr (sizeof(T) == 4) return m.B32[r]; else return m.B[r];
+}
+template <typename T> __device__ inline T fld_W(const MeanFieldPtrs& m, size_t r) {
+  if constexpr (sizeof(T) == 4) return m.W32[r]; else return m.W[r];
+}
+
+template <int DIR, typename V> __device__ inline void so_coeffs(V wx, V wy, V wz, V& ax, V& ay, V& az) {
   if (DIR == 0) { ax = 0.0; ay = -wz; az = wy; }
   else if (DIR == 1) { ax = wz; ay = 0.0; az = -wx; }
   else { ax = -wy; ay = wx; az = 0.0; }
@@ -107,16 +118,16 @@ k_h_pass(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPtr
 #pragma unroll
     for (int j1 = 0; j1 < R1; ++j1) {
       int r = base + (j + R2 * j1) * stride;
-      T B = T(mf.B[r]);
-      double ax, ay, az;
-      so_coeffs<DIR>(mf.W[r], mf.W[N3 + r], mf.W[2 * N3 + r], ax, ay, az);
+      const T B = fld_B<T>(mf, r);
+      T ax, ay, az;
+      so_coeffs<DIR>(fld_W<T>(mf, r), fld_W<T>(mf, N3 + r), fld_W<T>(mf, 2 * N3 + r), ax, ay, az);
       cpx<T> au, ad, bu, bd;
       sigma_apply<T>(T(ax), T(ay), T(az), d[0][j1], d[1][j1], au, ad);     // A D psi
       sigma_apply<T>(T(ax), T(ay), T(az), v[0][j1], v[1][j1], bu, bd);     // A psi
       acc[0][j1] = T(0.5) * mul_i(au);
       acc[1][j1] = T(0.5) * mul_i(ad);
       if (FIRST) {
-        T U = T(mf.U[r]);
+        const T U = fld_U<T>(mf, r);
         acc[0][j1] = acc[0][j1] + U * v[0][j1];
         acc[1][j1] = acc[1][j1] + U * v[1][j1];
       }
@@ -227,9 +238,9 @@ __device__ inline void h_dir_line(const cpx<T> (&v)[2][Fact<N>::R1], cpx<T> (&ou
 #pragma unroll
     for (int j1 = 0; j1 < R1; ++j1) {
       const int q = r[j1];
-      const T B = T(mf.B[q]);
-      double ax, ay, az;
-      so_coeffs<DIR>(mf.W[q], mf.W[N3 + q], mf.W[2 * N3 + q], ax, ay, az);
+      const T B = fld_B<T>(mf, q);
+      T ax, ay, az;
+      so_coeffs<DIR>(fld_W<T>(mf, q), fld_W<T>(mf, N3 + q), fld_W<T>(mf, 2 * N3 + q), ax, ay, az);
       cpx<T> au, ad, bu, bd;
       sigma_apply<T>(T(ax), T(ay), T(az), d[0][j1], d[1][j1], au, ad);     // A D psi
       sigma_apply<T>(T(ax), T(ay), T(az), v[0][j1], v[1][j1], bu, bd);     // A psi

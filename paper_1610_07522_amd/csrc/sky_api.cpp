@@ -80,7 +80,7 @@ struct Layout {
       pc_gain, pc_dscr, pc_gram, pc_idx, pc_beps, pc_b[4];
   int pc_nb;   // largest sampled-state batch (states x shells)
   size_t plA, plB, plT, plU, plS;                  // FP16 split planes, scales (mixed only)
-  size_t dens[2], der[2], mf[2], vc, fscratch, dens_part, epart, energy, info;
+  size_t dens[2], der[2], mf[2], mf32[2], vc, fscratch, dens_part, epart, energy, info;
   size_t gflags, gdbl;   // flags and doubles of the device-decided iteration
   size_t total;
 };
@@ -187,6 +187,7 @@ Layout plan(const sky_box_desc& d) {
     L.dens[q] = take(sizeof(double) * 11 * n3);
     L.der[q] = take(sizeof(double) * 5 * n3);
     L.mf[q] = take(sizeof(double) * 5 * n3);
+    L.mf32[q] = take(sizeof(float) * 5 * n3);
   }
   L.vc = take(sizeof(double) * n3);
   L.fscratch = take(mean_field_scratch_bytes(d.n));
@@ -308,7 +309,8 @@ struct sky_ctx {
   // mean field of the species of set s (shared by every twist)
   MeanFieldPtrs mfp(int s) const {
     const double* m = at<double>(lay.mf[s & 1]);
-    return MeanFieldPtrs{m, m + n3, m + 2 * n3};
+    const float* f = at<float>(lay.mf32[s & 1]);
+    return MeanFieldPtrs{m, m + n3, m + 2 * n3, f, f + n3, f + 2 * n3};
   }
   // grid arguments of set s: the Bloch shift theta / L of its twist
   GridArgs gset(int s) const {
@@ -771,6 +773,10 @@ void fields(sky_ctx* c) {
              c->at<double>(c->lay.mf[0]), c->at<double>(c->lay.mf[1]),
              c->at<double>(c->lay.vc), c->at(c->lay.fscratch), c->at<double>(c->lay.epart),
              c->at<double>(c->lay.energy), st);
+  // FP32 copies of U, B, W for the complex64 kernels (5 n^3 doubles as
+  // complex pairs: n^3 is even)
+  for (int q = 0; q < 2; ++q)
+    convert_states(c->at(c->lay.mf[q]), 0, c->at(c->lay.mf32[q]), 1, size_t(5) * c->n3 / 2, st);
   t_end(c, tmf);
 }
 // |k| at the corner of the Brillouin zone

@@ -67,6 +67,11 @@ struct MeanFieldPtrs {
   const double* U;
   const double* B;
   const double* W;   // [3][z][y][x]
+  // the same fields rounded to FP32 (read by the complex64 kernels, which
+  // round every field value to FP32 anyway: half the bytes per read)
+  const float* U32;
+  const float* B32;
+  const float* W32;
 };
 
 }  // namespace sky
