@@ -126,7 +126,7 @@ def roofline(timing: dict, w, mixed: bool) -> dict:
 # HBM bytes a phase must move per launch per state (complex elements V = 2 n^3
 # per state): h psi reads psi and writes h psi; the damped step reads psi and
 # h psi and writes phi; the densities read psi.
-PHASE_STATE_ARRAYS = dict(apply_h=22.663e9, damp=22.655e9, densities=9.403e9)
+PHASE_STATE_ARRAYS = dict(apply_h=2, damp=3, densities=1)
 
 
 def hbm_phases(timing: dict, w, mixed: bool) -> dict:
