@@ -672,7 +672,7 @@ void eig_sort(const void* D, const void* V, int m, int ld, double* w, void* Z, h
 }
 
 int loewdin_series(const void* Iv, void* Cv, void* Dv, void* Tv, int m, double max_dev,
-                   double* scratch, void* part, hipStream_t st, int sq_split) {
+                   double* scratch, void* part, hipStream_t st, int sq_split, double eps) {
   if (m <= 0) return 0;
   auto D = (double2*)Dv;
   const size_t mm = size_t(m) * m;
@@ -686,12 +686,12 @@ int loewdin_series(const void* Iv, void* Cv, void* Dv, void* Tv, int m, double m
   if (!std::isfinite(f)) return -1;
   if (!(f <= max_dev)) return 0;
   // (1 + D)^-1/2 = sum_k c_k D^k, c_k = c_{k-1} (1 - 2k) / (2k); ||D||_2 <= f, so the
-  // tail after p terms is below |c_{p+1}| f^{p+1} / (1 - f); stop below 2^-56.
+  // tail after p terms is below |c_{p+1}| f^{p+1} / (1 - f); stop below eps.
   double c[16];
   c[0] = 1.0;
   for (int k = 1; k < 16; ++k) c[k] = c[k - 1] * (1.0 - 2.0 * k) / (2.0 * k);
   int p = 1;
-  while (p < 14 && fabs(c[p + 1]) * pow(f, p + 1) / (1.0 - f) > 0x1p-56) ++p;
+  while (p < 14 && fabs(c[p + 1]) * pow(f, p + 1) / (1.0 - f) > eps) ++p;
   // Horner: P = c_{p-1} 1 + c_p D; P <- c_k 1 + D P for k = p-2 .. 0
   auto C = (double2*)Cv, T = (double2*)Tv;
   double2* cur = (p % 2) ? C : T;   // ping-pong so that the last product lands in C
@@ -730,7 +730,7 @@ constexpr int SERIES_PMAX = 14;   // terms of the series at most (as loewdin_ser
 // From ||D||_F^2 (fro2): the term count p of the series and its
 // coefficients (dbl[D_SERIES + 2 ..]), the gates of the Horner steps, or the
 // hand-over to the host.  Same arithmetic as loewdin_series.
-__global__ void k_series_plan(const double* __restrict__ fro2, double max_dev, int pcap,
+__global__ void k_series_plan(const double* __restrict__ fro2, double max_dev, double eps, int pcap,
                               int* __restrict__ flags, double* __restrict__ dbl, int set) {
   if (threadIdx.x != 0) return;
   const bool active = flags[F_ACTIVE] != 0;
@@ -746,7 +746,7 @@ __global__ void k_series_plan(const double* __restrict__ fro2, double max_dev, i
       c[0] = 1.0;
       for (int k = 1; k < 16; ++k) c[k] = c[k - 1] * (1.0 - 2.0 * k) / (2.0 * k);
       p = 1;
-      while (p < pcap && fabs(c[p + 1]) * pow(f, p + 1) / (1.0 - f) > 0x1p-56) ++p;
+      while (p < pcap && fabs(c[p + 1]) * pow(f, p + 1) / (1.0 - f) > eps) ++p;
       for (int k = 0; k < 16; ++k) dbl[D_SERIES + 2 + k] = c[k];
     }
   }
@@ -781,8 +781,8 @@ __global__ void k_add_identity_dev(double2* __restrict__ P, const double* __rest
 }
 
 void loewdin_series_dev(const void* Iv, void* Cv, void* Dv, void* Tv, int m, double max_dev,
-                        double* scratch, void* part, hipStream_t st, int sq_split, int* flags,
-                        double* dbl, int set) {
+                        double eps, double* scratch, void* part, hipStream_t st, int sq_split,
+                        int* flags, double* dbl, int set) {
   if (m <= 0) return;
   auto D = (double2*)Dv;
   const size_t mm = size_t(m) * m;
@@ -799,11 +799,11 @@ void loewdin_series_dev(const void* Iv, void* Cv, void* Dv, void* Tv, int m, dou
   c[0] = 1.0;
   for (int k = 1; k < 16; ++k) c[k] = c[k - 1] * (1.0 - 2.0 * k) / (2.0 * k);
   int pmax = 1;
-  while (pmax < SERIES_PMAX && fabs(c[pmax + 1]) * pow(max_dev, pmax + 1) / (1.0 - max_dev) > 0x1p-56)
+  while (pmax < SERIES_PMAX && fabs(c[pmax + 1]) * pow(max_dev, pmax + 1) / (1.0 - max_dev) > eps)
     ++pmax;
   const int pcap = std::min(pmax + 1, SERIES_PMAX);
   hipLaunchKernelGGL(k_series_plan, dim3(1), dim3(64), 0, st, (const double*)(scratch + nb), max_dev,
-                     pcap, flags, dbl, set);
+                     eps, pcap, flags, dbl, set);
   // buf[0] = C receives the last Horner step (k = 0), buf[1] = T
   auto C = (double2*)Cv, T = (double2*)Tv;
   double2* buf[2] = {C, T};

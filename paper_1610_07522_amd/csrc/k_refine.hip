@@ -25,7 +25,7 @@
 // term makes the update unitary to second order, so that the off-diagonal
 // norm and the orthonormality defect fall quadratically.  Convergence: the
 // relative off-diagonal Frobenius norm of S below tol and max |R_ij| below
-// ORTH_TOL.  A cluster wider than KMAX, a non-finite value or no convergence
+// orth.  A cluster wider than KMAX, a non-finite value or no convergence
 // within the iteration limit returns a failure, and the caller falls back to
 // the blocked Jacobi solver.
 #include <algorithm>
@@ -42,7 +42,6 @@ using namespace jrot;
 
 constexpr int KMAX = 48;            // widest cluster diagonalised in one workgroup (LDS: 3 x 48 x 49 x 16 B)
 constexpr double THETA = 0.03;      // weak-coupling ratio |coupling| / |gap|
-constexpr double ORTH_TOL = 1e-13;  // max |(X^H X - 1)_ij| at convergence
 constexpr double E_CLAMP = 0.25;    // bound on one update coefficient
 constexpr int CHECK_BLOCKS = 256;
 
@@ -58,19 +57,32 @@ __global__ void k_ref_lambda(const double2* __restrict__ S, const double2* __res
 }
 
 // rank[i] = position of i in ascending (lam, index) order; order[rank] = i.
-__global__ void k_ref_rank(const double* __restrict__ lam, int m, int* __restrict__ rank,
-                           int* __restrict__ order, const int* __restrict__ sky_gate) {
+// A workgroup ranks 64 values; each of its RANK_SPLIT waves counts over one
+// slice of the others, and the slice counts are summed in LDS.
+constexpr int RANK_SPLIT = 16;
+__global__ void __launch_bounds__(64 * RANK_SPLIT)
+k_ref_rank(const double* __restrict__ lam, int m, int* __restrict__ rank,
+           int* __restrict__ order, const int* __restrict__ sky_gate) {
   if (sky_gate != nullptr && *sky_gate == 0) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  const double li = lam[i];
+  __shared__ int cnt[RANK_SPLIT][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const double li = i < m ? lam[i] : 0.0;
+  const int per = (m + RANK_SPLIT - 1) / RANK_SPLIT;
+  const int j0 = min(m, wv * per), j1 = min(m, j0 + per);
   int r = 0;
-  for (int j = 0; j < m; ++j) {
-    const double lj = lam[j];
-    r += (lj < li || (lj == li && j < i)) ? 1 : 0;
-  }
-  rank[i] = r;
-  order[r] = i;
+  if (i < m)
+    for (int j = j0; j < j1; ++j) {
+      const double lj = lam[j];
+      r += (lj < li || (lj == li && j < i)) ? 1 : 0;
+    }
+  cnt[wv][lane] = r;
+  __syncthreads();
+  if (wv != 0 || i >= m) return;
+  int t = 0;
+  for (int k = 0; k < RANK_SPLIT; ++k) t += cnt[k][lane];
+  rank[i] = t;
+  order[t] = i;
 }
 
 // reach[rank[i]] = largest sorted position strongly coupled to i (or its own).
@@ -393,6 +405,104 @@ k_ref_update(const double2* __restrict__ S, const double2* __restrict__ R, int m
   if ((threadIdx.x & 63) == 0) atomicMax(emax, (unsigned long long)__double_as_longlong(mag));
 }
 
+// k_ref_update with one workgroup per sorted row a: the row a of B^H S (and
+// B^H R), in the original column order, is formed once in LDS from the ka
+// rows of a's cluster (coalesced reads), and column b then combines the kb
+// entries of its own cluster from LDS.  Same E and *emax; the two sums of the
+// sandwich are taken in the other order.  Dynamic LDS: (R ? 2 : 1) * m
+// complex values.
+template <bool HAS_R>
+__global__ void __launch_bounds__(256)
+k_ref_update_rows(const double2* __restrict__ S, const double2* __restrict__ R, int m, Clusters cl,
+                  const double* __restrict__ lam2, const double* __restrict__ taup,
+                  double2* __restrict__ E, unsigned long long* __restrict__ emax,
+                  const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
+  extern __shared__ double2 ref_row[];
+  double2* srow = ref_row;
+  double2* rrow = ref_row + m;
+  const double tau = *taup;
+  const int a = blockIdx.x;
+  const int sa = cl.cstart[a], ka = cl.csize[a], ta = a - sa;
+  const double2* Wa = cl.w(a);
+  for (int col = threadIdx.x; col < m; col += blockDim.x) {
+    double2 sv = make_double2(0.0, 0.0), rv = make_double2(0.0, 0.0);
+    for (int t = 0; t < ka; ++t) {
+      const size_t o = size_t(cl.order[sa + t]) * m + col;
+      if (Wa) {
+        const double2 w = Wa[t * KMAX + ta];
+        sv = cadd(sv, cconjmul(w, S[o]));
+        if (HAS_R) rv = cadd(rv, cconjmul(w, R[o]));
+      } else {
+        sv = S[o];
+        if (HAS_R) rv = R[o];
+      }
+    }
+    srow[col] = sv;
+    if (HAS_R) rrow[col] = rv;
+  }
+  __syncthreads();
+  const double la = lam2[a];
+  double mag = 0.0;
+  for (int b = threadIdx.x; b < m; b += blockDim.x) {
+    const int sb = cl.cstart[b], kb = cl.csize[b], tb = b - sb;
+    const double2* Wb = cl.w(b);
+    double2 s2 = make_double2(0.0, 0.0), r2 = make_double2(0.0, 0.0);
+    for (int u = 0; u < kb; ++u) {
+      const int c = cl.order[sb + u];
+      if (Wb) {
+        const double2 w = Wb[u * KMAX + tb];
+        s2 = cadd(s2, cmul(srow[c], w));
+        if (HAS_R) r2 = cadd(r2, cmul(rrow[c], w));
+      } else {
+        s2 = srow[c];
+        if (HAS_R) r2 = rrow[c];
+      }
+    }
+    double2 e = make_double2(0.0, 0.0);
+    if (sa == sb) {
+      if (HAS_R) e = cscale(0.5, r2);
+    } else {
+      const double lb = lam2[b];
+      const double2 gb = cadd(s2, cscale(lb, r2)), ga = cadd(s2, cscale(la, r2));
+      const double den = lb - la;
+      if (fmax(hypot(gb.x, gb.y), hypot(ga.x, ga.y)) <= tau) {
+        e = cscale(0.5, r2);   // coupling at the noise floor: orthonormality only
+      } else if (den != 0.0) {
+        e = cscale(1.0 / den, gb);
+        const double em = hypot(e.x, e.y);
+        if (em > E_CLAMP) e = cscale(E_CLAMP / em, e);
+      }
+    }
+    E[size_t(a) * m + b] = e;
+    mag = fmax(mag, hypot(e.x, e.y));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mag = fmax(mag, __shfl_xor(mag, o));
+  if ((threadIdx.x & 63) == 0) atomicMax(emax, (unsigned long long)__double_as_longlong(mag));
+}
+
+constexpr size_t REF_ROW_LDS_MAX = 65536;   // dynamic LDS of k_ref_update_rows at most
+
+// E and *emax of one refinement step: by rows through LDS where two rows of
+// m complex values fit, else one thread per entry.
+void ref_update(const double2* Sp, const double2* Rp, int m, const Clusters& cl, const double* lam2,
+                const double* tau, double2* E, unsigned long long* emax, hipStream_t st) {
+  const size_t lds = size_t(Rp ? 2 : 1) * m * sizeof(double2);
+  if (lds <= REF_ROW_LDS_MAX) {
+    if (Rp)
+      hipLaunchKernelGGL(k_ref_update_rows<true>, dim3(unsigned(m)), dim3(256), lds, st, Sp, Rp, m, cl,
+                         lam2, tau, E, emax, g_launch_gate);
+    else
+      hipLaunchKernelGGL(k_ref_update_rows<false>, dim3(unsigned(m)), dim3(256), lds, st, Sp, Rp, m, cl,
+                         lam2, tau, E, emax, g_launch_gate);
+  } else {
+    const unsigned gm = unsigned((m + 255) / 256);
+    hipLaunchKernelGGL(k_ref_update, dim3(gm, unsigned(m)), dim3(256), 0, st, Sp, Rp, m, cl, lam2, tau,
+                       E, emax, g_launch_gate);
+  }
+}
+
 // Q[order[s]][b] = sum_{t in cluster(s)} W[s - c][t - c] (delta_tb + E_tb + E2_tb / 2)
 // (E2 null, or e2flag pointing at 0: the second-order term is below rounding
 // and left out).
@@ -416,15 +526,15 @@ k_ref_build_q(const double2* __restrict__ E, const double2* __restrict__ E2v, co
   Q[size_t(cl.order[s]) * m + b] = acc;
 }
 
-// Whether the step forms E^2/2: |E| above E2_SKIP (below, the term is under
-// FP64 rounding of 1 + E).  Decided on the device (the flag gates the E^2
-// product and tells k_ref_build_q to use it); 0 when the run flag is off.
-constexpr double E2_SKIP = 1e-8;
+// Whether the step forms E^2/2: max |E| above e2skip (below, the term is
+// under the precision the refinement works to).  Decided on the device (the
+// flag gates the E^2 product and tells k_ref_build_q to use it); 0 when the
+// run flag is off.
 __global__ void k_ref_e2_flag(const unsigned long long* __restrict__ emax, const int* __restrict__ run,
-                              int* __restrict__ flag) {
+                              double e2skip, int* __restrict__ flag) {
   if (threadIdx.x != 0) return;
   const double em = __longlong_as_double((long long)*emax);
-  *flag = ((run == nullptr || *run != 0) && !(em <= E2_SKIP)) ? 1 : 0;
+  *flag = ((run == nullptr || *run != 0) && !(em <= e2skip)) ? 1 : 0;
 }
 
 // S <- (S + S^H) / 2 and R <- 1 - (G + G^H) / 2 in place (R holds G = X^H X
@@ -519,18 +629,31 @@ __global__ void k_ref_tau(const double* __restrict__ norms, int m, double noise,
   if (threadIdx.x == 0) tau[0] = noise * sqrt(norms[1] / m);
 }
 
+// Sums of the check's block partials over 64 lanes (lane t takes blocks
+// t, t + 64, ... in order, then a fixed butterfly), NaN-propagating max.
 __global__ void k_ref_check_final(const double* __restrict__ part, int nb, double* __restrict__ out, const int* __restrict__ sky_gate) {
   if (sky_gate != nullptr && *sky_gate == 0) return;
-  if (threadIdx.x) return;
+  const int t = threadIdx.x;
+  if (t >= 64) return;
   double o = 0.0, d = 0.0, r = 0.0;
-  for (int b = 0; b < nb; ++b) {
+  for (int b = t; b < nb; b += 64) {
     o += part[3 * b];
     d += part[3 * b + 1];
-    r = (part[3 * b + 2] > r || part[3 * b + 2] != part[3 * b + 2]) ? part[3 * b + 2] : r;
+    const double x = part[3 * b + 2];
+    r = (x > r || x != x) ? x : r;
   }
-  out[0] = o;
-  out[1] = d;
-  out[2] = r;
+#pragma unroll
+  for (int k = 32; k > 0; k >>= 1) {
+    o += __shfl_down(o, k, 64);
+    d += __shfl_down(d, k, 64);
+    const double x = __shfl_down(r, k, 64);
+    r = (x > r || x != x) ? x : r;
+  }
+  if (t == 0) {
+    out[0] = o;
+    out[1] = d;
+    out[2] = r;
+  }
 }
 
 struct RefineWork {
@@ -578,9 +701,10 @@ size_t refine_scratch_bytes(int m) {
   return size_t(reinterpret_cast<char*>(r.gpart)) + al256(gemm_square_scratch_bytes(m));
 }
 
-int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double tol, int maxit,
-                hipStream_t st, int sq_split, double noise) {
+int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, const RefineTargets& tg,
+                int maxit, hipStream_t st, int sq_split) {
   if (m <= 0) return 0;
+  const double tol = tg.tol, noise = tg.noise, orth = tg.orth;
   RefineWork r = carve(work, m);
   const double2* A = static_cast<const double2*>(Av);
   double2 *X = r.mat[0], *Xn = r.mat[1], *Q = r.mat[2], *T = r.mat[3], *S = r.mat[4],
@@ -615,7 +739,7 @@ int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double to
       hipMemcpyAsync(hi, r.info, sizeof(hi), hipMemcpyDeviceToHost, st);
       hipStreamSynchronize(st);
       if (!(h[0] == h[0]) || !(h[1] == h[1]) || !(h[2] == h[2]) || hi[1] > KMAX) return -1;
-      if ((h[0] <= tol * tol * h[1] || h[0] < 1e-300) && h[2] <= ORTH_TOL) {
+      if ((h[0] <= tol * tol * h[1] || h[0] < 1e-300) && h[2] <= orth) {
         eig_sort(S, X, m, m, w, Z, st);
         return it;
       }
@@ -625,7 +749,7 @@ int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double to
       hipLaunchKernelGGL(k_ref_tau, dim3(1), dim3(64), 0, st, (const double*)r.norms, m, noise, tau, g_launch_gate);
     }
     hipLaunchKernelGGL(k_ref_lambda, dim3(gm), dim3(256), 0, st, Sp, Rp, m, r.lam, r.emax, g_launch_gate);
-    hipLaunchKernelGGL(k_ref_rank, dim3(gm), dim3(256), 0, st, (const double*)r.lam, m, r.rank, r.order, g_launch_gate);
+    hipLaunchKernelGGL(k_ref_rank, dim3((m + 63) / 64), dim3(64 * RANK_SPLIT), 0, st, (const double*)r.lam, m, r.rank, r.order, g_launch_gate);
     hipLaunchKernelGGL(k_ref_reach, dim3(m), dim3(256), 0, st, Sp, Rp, (const double*)r.lam,
                        (const int*)r.rank, m, THETA, (const double*)tau, r.reach, g_launch_gate);
     hipLaunchKernelGGL(k_ref_clusters, dim3(1), dim3(1024), 0, st, (const int*)r.reach, m, r.pm,
@@ -633,13 +757,12 @@ int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double to
     hipLaunchKernelGGL(k_ref_cluster_eig, dim3(unsigned(m / 2 + 1)), dim3(256), 0, st, Sp, Rp, m,
                        (const int*)r.order, (const int2*)r.clist, (const int*)r.info, r.W, tol * 1e-2, g_launch_gate);
     hipLaunchKernelGGL(k_ref_lambda2, dim3(gm), dim3(256), 0, st, Sp, Rp, m, cl, r.lam2, g_launch_gate);
-    hipLaunchKernelGGL(k_ref_update, dim3(gm, unsigned(m)), dim3(256), 0, st, Sp, Rp, m, cl,
-                       (const double*)r.lam2, (const double*)tau, E, r.emax, g_launch_gate);
-    // E^2/2 only while |E| > E2_SKIP, decided on the device (as in the
+    ref_update(Sp, Rp, m, cl, r.lam2, tau, E, r.emax, st);
+    // E^2/2 only while |E| > e2skip, decided on the device (as in the
     // device-decided refinement, so that the two take the same arithmetic)
     int* e2 = r.info + 3;
     hipLaunchKernelGGL(k_ref_e2_flag, dim3(1), dim3(64), 0, st, (const unsigned long long*)r.emax,
-                       g_launch_gate, e2);
+                       g_launch_gate, tg.e2skip, e2);
     {
       GateScope g2(e2);
       gemm_square(E, 0, E, 0, T, m, st, r.gpart, 0, sq_split);
@@ -658,7 +781,8 @@ int refine_eigh(const void* Av, int m, double* w, void* Z, void* work, double to
 // ------------------------------------------------------------------ device-decided
 // The stop test of refine_eigh on the device (ungated; one thread).
 __global__ void k_ref_decide(const double* __restrict__ norms, const int* __restrict__ info,
-                             double tol, int it, int maxit, int* __restrict__ flags, int set) {
+                             double tol, double orth, int it, int maxit, int* __restrict__ flags,
+                             int set) {
   if (threadIdx.x != 0) return;
   if (flags[F_REF_RUN] == 0) {
     flags[F_REF_OK + it] = 0;
@@ -667,7 +791,7 @@ __global__ void k_ref_decide(const double* __restrict__ norms, const int* __rest
   const double h0 = norms[0], h1 = norms[1], h2 = norms[2];
   flags[F_REF_STEPS] = it;
   const bool bad = !(h0 == h0) || !(h1 == h1) || !(h2 == h2) || info[1] > KMAX;
-  const bool conv = !bad && (h0 <= tol * tol * h1 || h0 < 1e-300) && h2 <= ORTH_TOL;
+  const bool conv = !bad && (h0 <= tol * tol * h1 || h0 < 1e-300) && h2 <= orth;
   flags[F_REF_OK + it] = conv ? 1 : 0;
   if (conv) {
     flags[F_REF_RUN] = 0;
@@ -685,9 +809,10 @@ __global__ void k_ref_start(int* __restrict__ flags) {
   flags[F_REF_STEPS] = 0;
 }
 
-void refine_eigh_dev(const void* Av, int m, double* w, void* Z, void* work, double tol, int maxit,
-                     hipStream_t st, int sq_split, double noise, int* flags, int set) {
+void refine_eigh_dev(const void* Av, int m, double* w, void* Z, void* work, const RefineTargets& tg,
+                     int maxit, hipStream_t st, int sq_split, int* flags, int set) {
   if (m <= 0) return;
+  const double tol = tg.tol, noise = tg.noise, orth = tg.orth;
   if (maxit > F_NFLAGS - F_REF_OK - 1) maxit = F_NFLAGS - F_REF_OK - 1;
   RefineWork r = carve(work, m);
   const double2* A = static_cast<const double2*>(Av);
@@ -719,7 +844,7 @@ void refine_eigh_dev(const void* Av, int m, double* w, void* Z, void* work, doub
                            int(ncheck), r.norms, g_launch_gate);
       }
       hipLaunchKernelGGL(k_ref_decide, dim3(1), dim3(64), 0, st, (const double*)r.norms,
-                         (const int*)r.info, tol, it, maxit, flags, set);
+                         (const int*)r.info, tol, orth, it, maxit, flags, set);
       {
         GateScope g(flags + F_REF_OK + it);
         eig_sort(S, X, m, m, w, Z, st);
@@ -733,7 +858,7 @@ void refine_eigh_dev(const void* Av, int m, double* w, void* Z, void* work, doub
     }
     GateScope g(run);
     hipLaunchKernelGGL(k_ref_lambda, dim3(gm), dim3(256), 0, st, Sp, Rp, m, r.lam, r.emax, g_launch_gate);
-    hipLaunchKernelGGL(k_ref_rank, dim3(gm), dim3(256), 0, st, (const double*)r.lam, m, r.rank,
+    hipLaunchKernelGGL(k_ref_rank, dim3((m + 63) / 64), dim3(64 * RANK_SPLIT), 0, st, (const double*)r.lam, m, r.rank,
                        r.order, g_launch_gate);
     hipLaunchKernelGGL(k_ref_reach, dim3(m), dim3(256), 0, st, Sp, Rp, (const double*)r.lam,
                        (const int*)r.rank, m, THETA, (const double*)tau, r.reach, g_launch_gate);
@@ -743,11 +868,10 @@ void refine_eigh_dev(const void* Av, int m, double* w, void* Z, void* work, doub
                        (const int*)r.order, (const int2*)r.clist, (const int*)r.info, r.W,
                        tol * 1e-2, g_launch_gate);
     hipLaunchKernelGGL(k_ref_lambda2, dim3(gm), dim3(256), 0, st, Sp, Rp, m, cl, r.lam2, g_launch_gate);
-    hipLaunchKernelGGL(k_ref_update, dim3(gm, unsigned(m)), dim3(256), 0, st, Sp, Rp, m, cl,
-                       (const double*)r.lam2, (const double*)tau, E, r.emax, g_launch_gate);
+    ref_update(Sp, Rp, m, cl, r.lam2, tau, E, r.emax, st);
     int* e2 = r.info + 3;
     hipLaunchKernelGGL(k_ref_e2_flag, dim3(1), dim3(64), 0, st, (const unsigned long long*)r.emax,
-                       run, e2);
+                       run, tg.e2skip, e2);
     {
       GateScope g2(e2);
       gemm_square(E, 0, E, 0, T, m, st, r.gpart, 0, sq_split);

@@ -54,6 +54,18 @@ constexpr double LOEWDIN_SERIES_MAX = 1e-2;
 // relative precision of H' built from the split-FP16 overlap and Hamiltonian
 // matrices (their representation error is 2^-22 of the largest entries; x2)
 constexpr double MIXED_HP_NOISE = 0x1p-21;
+// targets of the eigenvector refinement (off-diagonal norm, noise floor of
+// H', max |Z^H Z - 1|, smallest |E| whose E^2/2 term is formed): FP64, and
+// the mixed form, whose U is rounded to the split-FP16 planes (2^-22
+// relative) by the recombination and whose states are stored in complex64
+// (2^-24): a Z orthonormal beyond 2^-30 would be rounded away there, and an
+// E^2/2 below 2^-33 is an eighth of that target
+const RefineTargets REFINE_FP64{JACOBI_TOL, 0x1p-49, 1e-13, 1e-8};
+const RefineTargets REFINE_MIXED{JACOBI_TOL, MIXED_HP_NOISE, 0x1p-30, 0x1p-16};
+// truncation bound of the Loewdin series (remainder of C = I^-1/2): FP64,
+// and the mixed form, an order of magnitude below its orthonormality target
+constexpr double SERIES_EPS = 0x1p-56;
+constexpr double MIXED_SERIES_EPS = 0x1p-34;
 // smallest Cholesky pivot (or overlap eigenvalue, for Loewdin) of an
 // overlap matrix (unit diagonal): below it the states are linearly
 // dependent for any practical purpose
@@ -451,7 +463,8 @@ int subspace_solve(sky_ctx* c, int s, double* ritz) {
   void* sq = c->at(c->lay.sq_part);
   const int sqs = c->tune.sq[q];
   const int terms = loewdin_series(I, Linv, Cw, T, m, LOEWDIN_SERIES_MAX,
-                                   c->at<double>(c->lay.nrm), sq, st, sqs);
+                                   c->at<double>(c->lay.nrm), sq, st, sqs,
+                                   c->prec ? MIXED_SERIES_EPS : SERIES_EPS);
   if (terms < 0) return fail(SKY_ERR_NAN, "non-finite overlap matrix");
   if (terms > 0) {   // C = I^-1/2 (Hermitian) in Linv
     gemm_square(Linv, 0, H, 0, T, m, st, sq, 0, sqs);
@@ -468,8 +481,8 @@ int subspace_solve(sky_ctx* c, int s, double* ritz) {
     if (rc) return rc;
   }
   double* w = ritz ? ritz : c->at<double>(c->lay.ritz[s]);
-  int its = refine_eigh(Hp, m, w, Z, c->at(c->lay.ref_work), JACOBI_TOL, REFINE_ITERS, st, sqs,
-                        c->prec ? MIXED_HP_NOISE : 0x1p-49);
+  int its = refine_eigh(Hp, m, w, Z, c->at(c->lay.ref_work), c->prec ? REFINE_MIXED : REFINE_FP64,
+                        REFINE_ITERS, st, sqs);
   if (its < 0) {   // a wide cluster or no convergence: blocked Jacobi from H'
     ++c->fallbacks;
     its = jacobi_checked(c, Hp, m, w, Z);
@@ -503,15 +516,17 @@ void subspace_solve_dev(sky_ctx* c, int s) {
   void* sq = c->at(c->lay.sq_part);
   const int sqs = c->tune.sq[q];
   loewdin_series_dev(I, Linv, c->at(c->lay.matC), T, m, LOEWDIN_SERIES_MAX,
-                     c->at<double>(c->lay.nrm), sq, st, sqs, fl, db, s);
+                     c->prec ? MIXED_SERIES_EPS : SERIES_EPS, c->at<double>(c->lay.nrm), sq, st, sqs,
+                     fl, db, s);
   {
     GateScope g(fl + F_ACTIVE);
     gemm_square(Linv, 0, H, 0, T, m, st, sq, 0, sqs);
     gemm_square(T, 0, Linv, 0, Hp, m, st, sq, 1, sqs);
     hermitian_fill(Hp, m, st);
   }
-  refine_eigh_dev(Hp, m, c->at<double>(c->lay.ritz[s]), Z, c->at(c->lay.ref_work), JACOBI_TOL,
-                  c->d.dev_refine_steps > 0 ? c->d.dev_refine_steps : REFINE_ITERS_DEV, st, sqs, c->prec ? MIXED_HP_NOISE : 0x1p-49, fl, s);
+  refine_eigh_dev(Hp, m, c->at<double>(c->lay.ritz[s]), Z, c->at(c->lay.ref_work),
+                  c->prec ? REFINE_MIXED : REFINE_FP64,
+                  c->d.dev_refine_steps > 0 ? c->d.dev_refine_steps : REFINE_ITERS_DEV, st, sqs, fl, s);
   GateScope g(fl + F_ACTIVE);
   gemm_square(Linv, 0, Z, 0, U, m, st, sq, 0, sqs);
 }
@@ -604,8 +619,9 @@ int paper_solve(sky_ctx* c, int s, double* ritz) {
   }
   // 3b: H Z = Z lam (ascending)
   double* w = ritz ? ritz : c->at<double>(c->lay.ritz[s]);
-  int its = refine_eigh(H, m, w, Z, c->at(c->lay.ref_work), JACOBI_TOL, REFINE_ITERS, st, sqs,
-                        c->prec ? MIXED_HP_NOISE : 0x1p-49);
+  const RefineTargets tg{JACOBI_TOL, c->prec ? MIXED_HP_NOISE : 0x1p-49, REFINE_FP64.orth,
+                         REFINE_FP64.e2skip};
+  int its = refine_eigh(H, m, w, Z, c->at(c->lay.ref_work), tg, REFINE_ITERS, st, sqs);
   if (its < 0) {
     ++c->fallbacks;
     hipMemcpyAsync(X, H, size_t(m) * m * 16, hipMemcpyDeviceToDevice, st);

@@ -221,13 +221,20 @@ void gemm_square(const void* A, int opA, const void* B, int opB, void* C, int m,
 // cannot finish (a cluster wider than its limit, a non-finite value, or more
 // than maxit steps); the caller then uses jacobi_eigh.  Converged when the
 // relative off-diagonal Frobenius norm of Z^H A Z is below tol and
-// max |Z^H Z - 1| below 1e-13.  noise: the relative precision of A's entries
+// max |Z^H Z - 1| below orth.  noise: the relative precision of A's entries
 // (x its rms eigenvalue = the coupling floor below which entries are noise:
 // no clusters, no rotation, counted as converged); 8 ulps for A from FP64
 // products.  Synchronises the stream once per step.
 size_t refine_scratch_bytes(int m);
-int refine_eigh(const void* A, int m, double* w, void* Z, void* work, double tol, int maxit,
-                hipStream_t st, int sq_split = 0, double noise = 0x1p-49);
+// Stop and step targets of the refinement.
+struct RefineTargets {
+  double tol;      // relative off-diagonal Frobenius norm of Z^H A Z at convergence
+  double noise;    // relative precision of A's entries (see above)
+  double orth;     // max |Z^H Z - 1| at convergence
+  double e2skip;   // an update forms its E^2/2 term while max |E| > e2skip
+};
+int refine_eigh(const void* A, int m, double* w, void* Z, void* work, const RefineTargets& tg,
+                int maxit, hipStream_t st, int sq_split = 0);
 // The same refinement with its decisions on the device (launches only): up
 // to maxit steps, each gated by flags[F_REF_RUN]; the check after step it
 // sorts the eigenpairs out when converged (flags[F_REF_OK + it]); a step
@@ -235,8 +242,8 @@ int refine_eigh(const void* A, int m, double* w, void* Z, void* work, double tol
 // the limit, a non-finite check) sets F_HOST = HOST_REFINE (set `set`) and
 // clears F_ACTIVE.  The E^2 term of the update is always formed.  maxit <=
 // F_NFLAGS - F_REF_OK - 1.
-void refine_eigh_dev(const void* A, int m, double* w, void* Z, void* work, double tol, int maxit,
-                     hipStream_t st, int sq_split, double noise, int* flags, int set);
+void refine_eigh_dev(const void* A, int m, double* w, void* Z, void* work, const RefineTargets& tg,
+                     int maxit, hipStream_t st, int sq_split, int* flags, int set);
 
 // ---- dense FP64 linear algebra (k_linalg.hip)
 // Cholesky A = L L^H of Hermitian positive definite A (m x m, lower used),
@@ -262,21 +269,21 @@ void gauge_apply(const void* Z, int m, const int* info, const void* Q, void* out
 // Loewdin transform C = I^-1/2 (Eqs. Loewedin/orthmatvec) of an overlap close
 // to the identity, by the binomial series of (1 + D)^-1/2, D = I - 1, in
 // Horner form on the FP64 matrix cores.  The number of terms p makes the
-// remainder (bounded through ||D||_2 <= ||D||_F) smaller than 2^-56.
+// remainder (bounded through ||D||_2 <= ||D||_F) smaller than eps.
 // Returns p, 0 (nothing written to C) when ||D||_F > max_dev, or -1 when
 // ||D||_F is not a finite number.  D and T
 // are m x m work matrices, scratch >= 257 doubles, part the square-product
 // scratch (gemm_square); synchronises the stream.
 int loewdin_series(const void* I, void* C, void* D, void* T, int m, double max_dev,
-                   double* scratch, void* part, hipStream_t st, int sq_split = 0);
+                   double* scratch, void* part, hipStream_t st, int sq_split = 0, double eps = 0x1p-56);
 // The series with the decision on the device: the term count from the norm
 // of D = I - 1 (as loewdin_series), Horner steps gated by flags[F_SERIES + k].
 // If the series does not apply (norm above max_dev or not finite), flags
 // get F_HOST = HOST_LOEWDIN (set `set`) and F_ACTIVE = 0.  dbl: the box's
 // doubles (D_SERIES..).  Launches only.
 void loewdin_series_dev(const void* I, void* C, void* D, void* T, int m, double max_dev,
-                        double* scratch, void* part, hipStream_t st, int sq_split, int* flags,
-                        double* dbl, int set);
+                        double eps, double* scratch, void* part, hipStream_t st, int sq_split,
+                        int* flags, double* dbl, int set);
 // End of a device-decided iteration (one workgroup, ungated): if the box is
 // active, F_ITER += 1 and Delta-eps = sqrt(sum of ||r||^2 over the first
 // nocc[s] states of each set s / count) goes to dbl[D_DE]; Delta-eps <=
