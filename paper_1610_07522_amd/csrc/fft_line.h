@@ -201,6 +201,26 @@ template <typename T, int N, int S> struct LineFFT {
   }
 };
 
+// Distance in LDS between the exchange buffers of consecutive lines of a
+// workgroup (complex values).  Along y and z consecutive lanes hold
+// consecutive lines, which the odd YSIZE spreads over the banks.  Along x a
+// wave holds 64 / RT lines of RT consecutive threads; for those the strides
+// below put the words of every exchange access of a wave in distinct banks,
+// for 32 and for 64 banks of 4 bytes and 8- or 16-byte values (counted on
+// the CPU for each access of the two stages; N = 24, whose lines straddle
+// waves, takes the stride with the fewest shared banks).
+template <int N, int S> constexpr int x_line_stride() {
+  constexpr int one[6] = {12, 20, 38, 40, 56, 72};     // S = 1
+  constexpr int two[6] = {20, 44, 70, 72, 120, 152};   // S = 2
+  constexpr int i = N == 8 ? 0 : N == 16 ? 1 : N == 24 ? 2 : N == 32 ? 3 : N == 48 ? 4 : 5;
+  return S == 1 ? one[i] : two[i];
+}
+template <typename T, int N, int S, int DIR> constexpr int line_stride() {
+  constexpr int v = DIR == 0 ? x_line_stride<N, S>() : LineFFT<T, N, S>::YSIZE;
+  static_assert(v >= S * Fact<N>::R1 * (Fact<N>::R2 + 1), "exchange buffer too small");
+  return v;
+}
+
 // The same two-stage FFT with the exchange done in place, in the line's own
 // N slots: element idx of spin component s lives at base[s * sp + idx * es]
 // (es = 1 for a row, the row pitch for a column of an LDS slice).  Stage A

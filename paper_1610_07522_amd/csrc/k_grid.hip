@@ -81,9 +81,10 @@ k_h_pass(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPtr
   if (sky_gate != nullptr && *sky_gate == 0) return;
   using C = LineCfg<N, LP>;
   using F = LineFFT<T, N, 2>;
+  constexpr int YS = line_stride<T, N, 2, DIR>();
   constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
   __shared__ cpx<T> tw[N];
-  __shared__ cpx<T> Ybuf[C::LPW * F::YSIZE];
+  __shared__ cpx<T> Ybuf[C::LPW * YS];
   __shared__ double red[4];
   load_twiddles<T, N>(tw);
 
@@ -95,7 +96,7 @@ k_h_pass(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPtr
   const size_t soff = size_t(blockIdx.y) * 2 * N3;
   const cpx<T>* p = psi + soff;
   cpx<T>* hp = hpsi + soff;
-  cpx<T>* Y = Ybuf + line * F::YSIZE;
+  cpx<T>* Y = Ybuf + line * YS;
   const T kunit = T(g.kunit);
   const T kshift = T(g.tw[DIR]);
 
@@ -186,9 +187,18 @@ template <int N> struct PlaneCfg {
   static constexpr int SPIN = N * PITCH;   // one spin component of the slice
 };
 
+template <typename T, int N> constexpr int plane_lds(int xs) {
+  const int ys = LineFFT<T, N, 2>::YSIZE;
+  return (2 * PlaneCfg<N>::SPIN + N * (xs > ys ? xs : ys) + N) * int(sizeof(cpx<T>));
+}
+// Stride of the h slice kernel's x-line buffers: the bank-spreading x stride
+// where the slice still fits 80 KB, else the y lines' stride.
+template <typename T, int N> constexpr int plane_xstride() {
+  return plane_lds<T, N>(line_stride<T, N, 2, 0>()) <= 80 * 1024 ? line_stride<T, N, 2, 0>()
+                                                                 : LineFFT<T, N, 2>::YSIZE;
+}
 template <typename T, int N> constexpr bool plane_fits() {
-  return PlaneCfg<N>::THREADS <= 1024 &&
-         (2 * PlaneCfg<N>::SPIN + N * LineFFT<T, N, 2>::YSIZE + N) * sizeof(cpx<T>) <= 80 * 1024;
+  return PlaneCfg<N>::THREADS <= 1024 && plane_lds<T, N>(plane_xstride<T, N>()) <= 80 * 1024;
 }
 // The damped step's slice kernels exchange in place in the slice (no line
 // buffers): half the LDS of the h slices.
@@ -273,7 +283,8 @@ k_h_plane(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPt
   constexpr int N2 = N * N, N3 = N * N2;
   __shared__ cpx<T> tw[N];
   __shared__ cpx<T> P[2 * SP];
-  __shared__ cpx<T> Ybuf[N * F::YSIZE];
+  constexpr int XS = plane_xstride<T, N>(), YS = F::YSIZE;   // x- and y-line buffers
+  __shared__ cpx<T> Ybuf[N * (XS > YS ? XS : YS)];
   load_twiddles<T, N>(tw);
   const int zoff = blockIdx.x * N2;
   const size_t soff = size_t(blockIdx.y) * 2 * N3;
@@ -298,7 +309,7 @@ k_h_plane(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPt
       vx[1][j1] = P[SP + ly * PITCH + x];
     }
   }
-  h_dir_line<T, N, 0>(vx, ax, rx, Ybuf + ly * F::YSIZE, jx, tw, kunit, T(g.tw[0]), mf);
+  h_dir_line<T, N, 0>(vx, ax, rx, Ybuf + ly * XS, jx, tw, kunit, T(g.tw[0]), mf);
   // y lines: column lx (line fastest: consecutive threads, consecutive x)
   const int lx = threadIdx.x % N, jy = threadIdx.x / N;
   cpx<T> vy[2][R1], ay[2][R1];
@@ -321,7 +332,7 @@ k_h_plane(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPt
     }
   }
   __syncthreads();
-  h_dir_line<T, N, 1>(vy, ay, ry, Ybuf + lx * F::YSIZE, jy, tw, kunit, T(g.tw[1]), mf);
+  h_dir_line<T, N, 1>(vy, ay, ry, Ybuf + lx * YS, jy, tw, kunit, T(g.tw[1]), mf);
   double dot = 0.0;
   float am = 0.0f;
   if (jy < R2) {
@@ -372,8 +383,9 @@ k_damp_fwd_xy(const cpx<T>* __restrict__ psi, const cpx<T>* __restrict__ hpsi,
     P[s * SP + (q / N) * PITCH + q % N] = res;
   }
   __syncthreads();
-  {  // x lines, in place (row ly)
-    const int j = threadIdx.x % RT, ly = threadIdx.x / RT;
+  {  // x lines, in place (row ly; rows fastest across the lanes, whose odd
+     // pitch puts a wave's accesses in distinct LDS banks)
+    const int ly = threadIdx.x % N, j = threadIdx.x / N;
     cpx<T> va[2][R1], vb[2][R2];
     if (j < R2)
 #pragma unroll
@@ -450,8 +462,8 @@ k_damp_inv_xy(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ buf,
         for (int s = 0; s < 2; ++s) P[s * SP + (j + R2 * j1) * PITCH + lx] = va[s][j1];
   }
   __syncthreads();
-  {  // x lines (row ly)
-    const int j = threadIdx.x % RT, ly = threadIdx.x / RT;
+  {  // x lines (row ly; rows fastest across the lanes, as in the forward half)
+    const int ly = threadIdx.x % N, j = threadIdx.x / N;
     cpx<T> va[2][R1], vb[2][R2];
     if (j < R1)
 #pragma unroll
@@ -494,9 +506,10 @@ k_damp_fwd_x(const cpx<T>* __restrict__ psi, const cpx<T>* __restrict__ hpsi,
   if (sky_gate != nullptr && *sky_gate == 0) return;
   using C = LineCfg<N>;
   using F = LineFFT<T, N, 2>;
+  constexpr int YS = line_stride<T, N, 2, 0>();
   constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
   __shared__ cpx<T> tw[N];
-  __shared__ cpx<T> Ybuf[C::LPW * F::YSIZE];
+  __shared__ cpx<T> Ybuf[C::LPW * YS];
   __shared__ double red[4];
   load_twiddles<T, N>(tw);
   int line, j;
@@ -521,7 +534,7 @@ k_damp_fwd_x(const cpx<T>* __restrict__ psi, const cpx<T>* __restrict__ hpsi,
       }
     }
   }
-  F::forward(va, vb, Ybuf + line * F::YSIZE, j, tw);
+  F::forward(va, vb, Ybuf + line * YS, j, tw);
   if (j < R1) {
 #pragma unroll
     for (int k2 = 0; k2 < R2; ++k2) {
@@ -541,9 +554,10 @@ k_damp_y(cpx<T>* __restrict__ buf, const int* __restrict__ sky_gate) {
   if (sky_gate != nullptr && *sky_gate == 0) return;
   using C = LineCfg<N>;
   using F = LineFFT<T, N, 2>;
+  constexpr int YS = line_stride<T, N, 2, 1>();
   constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
   __shared__ cpx<T> tw[N];
-  __shared__ cpx<T> Ybuf[C::LPW * F::YSIZE];
+  __shared__ cpx<T> Ybuf[C::LPW * YS];
   load_twiddles<T, N>(tw);
   int line, j;
   thread_role<N, 1>(threadIdx.x, line, j);
@@ -552,7 +566,7 @@ k_damp_y(cpx<T>* __restrict__ buf, const int* __restrict__ sky_gate) {
   line_geom<N, 1>(L, base, stride, a, b);
   cpx<T>* p = buf + size_t(blockIdx.y) * 2 * N3;
   cpx<T> va[2][R1], vb[2][R2];
-  cpx<T>* Y = Ybuf + line * F::YSIZE;
+  cpx<T>* Y = Ybuf + line * YS;
   if (!INV) {
     if (j < R2)
 #pragma unroll
@@ -594,9 +608,10 @@ k_damp_z(cpx<T>* __restrict__ buf, GridArgs g, DampArgs d, const float* __restri
   if (sky_gate != nullptr && *sky_gate == 0) return;
   using C = LineCfg<N>;
   using F = LineFFT<T, N, 2>;
+  constexpr int YS = line_stride<T, N, 2, 2>();
   constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
   __shared__ cpx<T> tw[N];
-  __shared__ cpx<T> Ybuf[C::LPW * F::YSIZE];
+  __shared__ cpx<T> Ybuf[C::LPW * YS];
   __shared__ double spow[PC_SHELLS];
   load_twiddles<T, N>(tw);
   if (MODE == 1 && threadIdx.x < PC_SHELLS) spow[threadIdx.x] = 0.0;
@@ -606,7 +621,7 @@ k_damp_z(cpx<T>* __restrict__ buf, GridArgs g, DampArgs d, const float* __restri
   int base, stride, a, b;
   line_geom<N, 2>(L, base, stride, a, b);
   cpx<T>* p = buf + size_t(blockIdx.y) * 2 * N3;
-  cpx<T>* Y = Ybuf + line * F::YSIZE;
+  cpx<T>* Y = Ybuf + line * YS;
   cpx<T> va[2][R1], vb[2][R2];
   if (j < R2)
 #pragma unroll
@@ -676,9 +691,10 @@ k_damp_inv_x(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ buf,
   if (sky_gate != nullptr && *sky_gate == 0) return;
   using C = LineCfg<N>;
   using F = LineFFT<T, N, 2>;
+  constexpr int YS = line_stride<T, N, 2, 0>();
   constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
   __shared__ cpx<T> tw[N];
-  __shared__ cpx<T> Ybuf[C::LPW * F::YSIZE];
+  __shared__ cpx<T> Ybuf[C::LPW * YS];
   load_twiddles<T, N>(tw);
   int line, j;
   thread_role<N, 0>(threadIdx.x, line, j);
@@ -686,7 +702,7 @@ k_damp_inv_x(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ buf,
   int base, stride, a, b;
   line_geom<N, 0>(L, base, stride, a, b);
   const size_t soff = size_t(blockIdx.y) * 2 * N3;
-  cpx<T>* Y = Ybuf + line * F::YSIZE;
+  cpx<T>* Y = Ybuf + line * YS;
   cpx<T> va[2][R1], vb[2][R2];
   if (j < R1)
 #pragma unroll
@@ -722,18 +738,19 @@ k_dens_pass(DensGroups grp, int nstate, int chunk, GridArgs g, double* __restric
   if (sky_gate != nullptr && *sky_gate == 0) return;
   using C = LineCfg<N>;
   using F = LineFFT<T, N, 2>;
+  constexpr int YS = line_stride<T, N, 2, DIR>();
   constexpr int R1 = C::R1, R2 = C::R2, N3 = N * N * N;
   constexpr int NS = DIR == 0 ? 8 : 4;
   constexpr int SLOT0 = DIR == 0 ? 0 : (DIR == 1 ? 8 : 12);
   __shared__ cpx<T> tw[N];
-  __shared__ cpx<T> Ybuf[C::LPW * F::YSIZE];
+  __shared__ cpx<T> Ybuf[C::LPW * YS];
   load_twiddles<T, N>(tw);
   int line, j;
   thread_role<N, DIR>(threadIdx.x, line, j);
   const int L = blockIdx.x * C::LPW + line;
   int base, stride, a, b;
   line_geom<N, DIR>(L, base, stride, a, b);
-  cpx<T>* Y = Ybuf + line * F::YSIZE;
+  cpx<T>* Y = Ybuf + line * YS;
   const T kunit = T(g.kunit);
 
   double acc[NS][R1];
