@@ -47,20 +47,33 @@ k_overlap_lower(const double2* __restrict__ A, const double2* __restrict__ B0,
   const int wm = wave >> 1, wn = wave & 1;
   const long nck = k / KC;
   const long c0 = nck * s / split, c1 = nck * (s + 1) / split;
-  // loader: thread -> (row, 4 consecutive complex)
+  // loader: thread -> (row, 4 consecutive complex); contraction index kk of a
+  // row is stored at mfma::kperm(kk), so that the 8 lanes of an LDS store
+  // cycle (2 rows x 4 threads) meet 8 different bank groups
   const int lrow = tid >> 2, lk = (tid & 3) * 4;
   const int ga = ta * TM + lrow, gb = tb * TM + lrow;
-  Acc acc;
-  mfma::zero(acc);
-  for (long c = c0; c < c1; ++c) {
+  // chunk c + 1 is loaded into registers while chunk c is multiplied
+  double2 ra[4], rb[4];
+  auto load = [&](long c) {
     const long k0 = c * KC + lk;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      sA[lrow * KP + lk + e] = ga < m ? A[size_t(ga) * k + k0 + e] : make_double2(0, 0);
-      sB[lrow * KP + lk + e] = gb < m ? B[size_t(gb) * k + k0 + e] : make_double2(0, 0);
+      ra[e] = ga < m ? A[size_t(ga) * k + k0 + e] : make_double2(0, 0);
+      rb[e] = gb < m ? B[size_t(gb) * k + k0 + e] : make_double2(0, 0);
+    }
+  };
+  Acc acc;
+  mfma::zero(acc);
+  if (c0 < c1) load(c0);
+  for (long c = c0; c < c1; ++c) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      sA[lrow * KP + mfma::kperm(lk + e)] = ra[e];
+      sB[lrow * KP + mfma::kperm(lk + e)] = rb[e];
     }
     __syncthreads();
-    mfma::tile<true>(acc, sA, sB, wm, wn, lane);
+    if (c + 1 < c1) load(c + 1);
+    mfma::tile<true, true>(acc, sA, sB, wm, wn, lane);
     __syncthreads();
   }
   double2* out = part + (size_t(z) * npair + pair) * split * TM * TM + size_t(s) * TM * TM;
@@ -115,19 +128,33 @@ k_combine(const double2* __restrict__ X, const double2* __restrict__ U, double2*
   const int b0 = blockIdx.y * TM;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  // loader: thread -> (a within chunk = tid/16, 4 consecutive columns)
-  const int la = tid >> 4, lc = (tid & 15) * 4;
-  Acc acc;
-  mfma::zero(acc);
-  for (int a0 = 0; a0 < m; a0 += KC) {
+  // loader: thread -> (a within chunk = tid/16, columns lc + 16 e): 16 lanes
+  // read 256 contiguous bytes, and the transposed LDS stores of 8 lanes land
+  // in 8 different bank groups (KP odd)
+  const int la = tid >> 4, lc = tid & 15;
+  // chunk a0 + KC is loaded into registers while chunk a0 is multiplied
+  double2 ru[4], rx[4];
+  auto load = [&](int a0) {
     const int a = a0 + la;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int b = b0 + lc + e;
-      sA[(lc + e) * KP + la] = (a < m && b < m) ? U[size_t(a) * m + b] : make_double2(0, 0);
-      sB[(lc + e) * KP + la] = (a < m) ? X[size_t(a) * k + v0 + lc + e] : make_double2(0, 0);
+      const int col = lc + 16 * e, b = b0 + col;
+      ru[e] = (a < m && b < m) ? U[size_t(a) * m + b] : make_double2(0, 0);
+      rx[e] = (a < m) ? X[size_t(a) * k + v0 + col] : make_double2(0, 0);
+    }
+  };
+  Acc acc;
+  mfma::zero(acc);
+  if (m > 0) load(0);
+  for (int a0 = 0; a0 < m; a0 += KC) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int col = lc + 16 * e;
+      sA[col * KP + la] = ru[e];
+      sB[col * KP + la] = rx[e];
     }
     __syncthreads();
+    if (a0 + KC < m) load(a0 + KC);
     mfma::tile<false>(acc, sA, sB, wm, wn, lane);
     __syncthreads();
   }

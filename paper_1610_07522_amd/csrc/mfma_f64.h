@@ -37,18 +37,26 @@ __device__ inline void zero(Acc& a) {
     }
 }
 
-// acc += op(A) B^T over one KC chunk staged in LDS; A conjugated if CONJA.
-template <bool CONJA>
+// Position in an LDS row of contraction index kk < 16 for loaders that store
+// 4 consecutive indices per thread: kk = 4 q + e goes to 2 q + (e >> 1) +
+// 8 (e & 1), so that one store (fixed e) of two rows x four threads covers
+// the eight 16-byte bank groups of 32 banks (odd KP shifts the second row).
+__device__ inline int kperm(int kk) { return (kk >> 1) | ((kk & 1) << 3); }
+
+// acc += op(A) B^T over one KC chunk staged in LDS; A conjugated if CONJA;
+// PERM: the rows were stored at kperm positions.
+template <bool CONJA, bool PERM = false>
 __device__ inline void tile(Acc& acc, const double2* sA, const double2* sB, int wm, int wn,
                             int lane) {
   const int r = lane & 15, kq = lane >> 4;
 #pragma unroll
   for (int kk = 0; kk < KC; kk += 4) {
+    const int kc = PERM ? kperm(kk + kq) : kk + kq;
     double2 a[2], b[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) a[i] = sA[(wm * 32 + i * 16 + r) * KP + kk + kq];
+    for (int i = 0; i < 2; ++i) a[i] = sA[(wm * 32 + i * 16 + r) * KP + kc];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) b[j] = sB[(wn * 32 + j * 16 + r) * KP + kk + kq];
+    for (int j = 0; j < 2; ++j) b[j] = sB[(wn * 32 + j * 16 + r) * KP + kc];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
