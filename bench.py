@@ -394,6 +394,44 @@ def bench_batch(args) -> int:
     return 0
 
 
+def bench_mlp(args) -> int:
+    """Training steps of the learned damping's MLP (sky_precond_loss_grad) on
+    args.mlp_rows seeded synthetic rows: features in the ranges the learned
+    step produces, targets and weights; the network as sky_init_box sets it."""
+    import numpy as np
+    import torch
+    from paper_1610_07522_amd import inputs, sky
+    B = args.mlp_rows
+    w = inputs.small_workload("n8", 8, 5, 3, init="slab", seed=32, noise=0.2)
+    box = sky.Box(sky.desc_from_workload(w, precision=sky.SKY_FP64))
+    rn, rp = inputs.raw_states(w)
+    box.init_box(torch.from_numpy(rn).cuda(), torch.from_numpy(rp).cuda())
+    cap = box.view("pc_samples").shape[0]
+    if B > cap:
+        print(f"--mlp-rows at most {cap}", file=sys.stderr)
+        return 2
+    rng = np.random.default_rng(7)
+    rows = np.zeros((B, 6), dtype=np.float32)
+    rows[:, 0] = (rng.integers(0, 8, B) + 0.5) / 8      # shell centre |k| / |k|max
+    rows[:, 1] = rng.uniform(-0.6, 0.1, B)              # <h> / E0
+    rows[:, 2] = rng.uniform(-1, 1, B)                  # shell power share (log scale)
+    rows[:, 3] = rng.uniform(0, 8, B)                   # T_k / E0
+    rows[:, 4] = rng.uniform(0, 4, B)                   # target gain
+    rows[:, 5] = rng.uniform(0, 1, B)                   # weight
+    box.view("pc_samples")[:B].copy_(torch.from_numpy(rows).cuda())
+    for _ in range(args.warmup):
+        box.precond_loss_grad(B)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        loss = box.precond_loss_grad(B)
+    dt = time.perf_counter() - t0
+    print(json.dumps(dict(metric="learned-damping MLP training step (forward, loss, backward, gradient)",
+                          rows=B, steps=args.steps, ms_per_step=1e3 * dt / args.steps,
+                          loss=loss, note="host time per step includes one synchronisation")),
+          flush=True)
+    return 0
+
+
 def bench_learned_protocol(args) -> int:
     """The learned damping trained on other boxes and judged on held-out
     ones.  Training: for seeds 100-131, the three box shapes of the 16^3
@@ -640,6 +678,9 @@ def main() -> int:
                     help="--to-residual: stop every form once this much wall time has passed")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three 1 GiB device-to-device copies (HBM counter scale)")
+    ap.add_argument("--mlp-rows", type=int, default=0,
+                    help="only time --steps training steps (forward, loss, backward, gradient) "
+                         "of the learned damping's MLP on this many synthetic sample rows")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -659,6 +700,11 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_bytes=4 << 28, copies=3)), flush=True)
         return 0
+    if args.mlp_rows > 0:
+        if not torch.cuda.is_available():
+            print("bench.py needs a ROCm GPU", file=sys.stderr)
+            return 1
+        return bench_mlp(args)
     if args.workload == "learned_protocol":
         if not torch.cuda.is_available():
             print("bench.py needs a ROCm GPU", file=sys.stderr)

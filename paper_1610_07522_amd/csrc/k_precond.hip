@@ -34,7 +34,6 @@ constexpr float GMAX = 4.0f;
 constexpr int OW1 = 0, OB1 = OW1 + PH * PIN, OW2 = OB1 + PH, OB2 = OW2 + PH * PH,
               OW3 = OB2 + PH, OB3 = OW3 + PH * PH, OW4 = OB3 + PH, OB4 = OW4 + PH,
               NPAR = OB4 + 1;
-constexpr int SB = 16;   // samples per workgroup in the MLP kernels
 constexpr int NS_MAX = 32;   // sampled states per collection
 
 __device__ inline float bf16_round(float x) {
@@ -49,58 +48,121 @@ __global__ void k_round_params(const float* __restrict__ p, float* __restrict__ 
   if (i < n) q[i] = bf16_round(p[i]);
 }
 
-// Forward pass of SB samples per workgroup (128 threads = neurons).  H1..H3
-// (may be null) keep the activations for the backward pass; O the outputs.
-__global__ void __launch_bounds__(PH)
+// ---- forward pass on the BF16 matrix cores (v_mfma_f32_16x16x32_bf16)
+// One wave carries 16 samples through the MLP.  The two 128 x 128 layers are
+// MFMA products: the weights are BF16 values already (the parameters are
+// rounded by k_round_params), and each FP32 activation is split exactly into
+// three BF16 terms h = t0 + t1 + t2 (8 significant bits each, rounded to
+// nearest at each step), so that every product t_i w is exact in FP32 and
+// the layer is FP32 activations x BF16 weights with FP32 accumulation, as
+// the scalar form, up to the order of the sums.  MFMA operands: lane l
+// supplies 8 consecutive contraction elements starting at 8 (l / 16) of row
+// (A: sample) or column (B: neuron) l % 16; register e of lane l returns
+// sample 4 (l / 16) + e, neuron l % 16.  The first (4 inputs) and last
+// (1 output) layers are scalar.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+constexpr int FR = 16;         // samples per wave
+constexpr int FWV = 4;         // waves per workgroup
+constexpr int FLP = PH + 4;    // LDS row pitch of the activations (floats)
+
+__device__ inline unsigned short bf16_hi(float x) { return (unsigned short)(__float_as_uint(x) >> 16); }
+
+// 128 -> 128 layer of one wave: out = relu(bias + in W^T), in and out in LDS
+// ([FR][FLP]); W row-major [PH][PH] (BF16 values).
+__device__ inline void mlp_layer_mfma(const float* in, float* out, const float* __restrict__ W,
+                                      const float* __restrict__ bias, int lane) {
+  const int r = lane & 15, kg = (lane >> 4) * 8;
+  us8 a[PH / 32][3];
+#pragma unroll
+  for (int ks = 0; ks < PH / 32; ++ks)
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const float x = in[r * FLP + ks * 32 + kg + t];
+      const float x0 = bf16_round(x), x1 = bf16_round(x - x0), x2 = bf16_round(x - x0 - x1);
+      a[ks][0][t] = bf16_hi(x0);
+      a[ks][1][t] = bf16_hi(x1);
+      a[ks][2][t] = bf16_hi(x2);
+    }
+#pragma unroll
+  for (int j = 0; j < PH / 16; ++j) {
+    const int n = j * 16 + r;
+    f4v acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < PH / 32; ++ks) {
+      const float4* wp = reinterpret_cast<const float4*>(W + n * PH + ks * 32 + kg);
+      const float4 w0 = wp[0], w1 = wp[1];
+      const us8 wb = {bf16_hi(w0.x), bf16_hi(w0.y), bf16_hi(w0.z), bf16_hi(w0.w),
+                      bf16_hi(w1.x), bf16_hi(w1.y), bf16_hi(w1.z), bf16_hi(w1.w)};
+      const bf8 b = __builtin_bit_cast(bf8, wb);
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a[ks][t]), b, acc, 0, 0, 0);
+    }
+    const float bn = bias[n];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[(4 * (lane >> 4) + e) * FLP + n] = fmaxf(acc[e] + bn, 0.0f);
+  }
+}
+
+// Forward pass of FR samples per wave, FWV waves per workgroup.  H1..H3 (may
+// be null) keep the activations for the backward pass; O the outputs.
+__global__ void __launch_bounds__(64 * FWV)
 k_mlp_fwd(const float* __restrict__ P, const float* __restrict__ X, int ldx, int B,
           float* __restrict__ H1, float* __restrict__ H2, float* __restrict__ H3,
           float* __restrict__ O, const int* __restrict__ sky_gate) {
   if (sky_gate != nullptr && *sky_gate == 0) return;
-  __shared__ float xs[SB][PIN];
-  __shared__ float ha[SB][PH], hb[SB][PH];
-  __shared__ float red[SB][PH / 64];
-  const int j = threadIdx.x, b0 = blockIdx.x * SB;
-  if (j < SB * PIN) {
-    const int s = j / PIN, i = j % PIN;
-    xs[s][i] = (b0 + s < B) ? X[size_t(b0 + s) * ldx + i] : 0.0f;
+  __shared__ float hs[FWV][2][FR * FLP];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int b0 = (blockIdx.x * FWV + wv) * FR;
+  float* ha = hs[wv][0];
+  float* hb = hs[wv][1];
+  // layer 1: lane -> neurons lane, lane + 64
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int n = lane + 64 * q;
+    float w1[PIN];
+#pragma unroll
+    for (int i = 0; i < PIN; ++i) w1[i] = P[OW1 + n * PIN + i];
+    const float bn = P[OB1 + n];
+    for (int s = 0; s < FR; ++s) {
+      float a = bn;
+      if (b0 + s < B)
+#pragma unroll
+        for (int i = 0; i < PIN; ++i) a += w1[i] * X[size_t(b0 + s) * ldx + i];
+      ha[s * FLP + n] = fmaxf(a, 0.0f);
+    }
   }
   __syncthreads();
-  for (int s = 0; s < SB; ++s) {
-    float a = P[OB1 + j];
-    for (int i = 0; i < PIN; ++i) a += P[OW1 + j * PIN + i] * xs[s][i];
-    ha[s][j] = fmaxf(a, 0.0f);
-  }
-  __syncthreads();
-  for (int s = 0; s < SB; ++s) {
-    float a = P[OB2 + j];
-    for (int i = 0; i < PH; ++i) a += P[OW2 + j * PH + i] * ha[s][i];
-    hb[s][j] = fmaxf(a, 0.0f);
-  }
+  mlp_layer_mfma(ha, hb, P + OW2, P + OB2, lane);
   __syncthreads();
   if (H1)
-    for (int s = 0; s < SB; ++s)
-      if (b0 + s < B) H1[size_t(b0 + s) * PH + j] = ha[s][j];
+    for (int s = 0; s < FR; ++s)
+      if (b0 + s < B) {
+        H1[size_t(b0 + s) * PH + lane] = ha[s * FLP + lane];
+        H1[size_t(b0 + s) * PH + lane + 64] = ha[s * FLP + lane + 64];
+      }
   __syncthreads();
-  for (int s = 0; s < SB; ++s) {
-    float a = P[OB3 + j];
-    for (int i = 0; i < PH; ++i) a += P[OW3 + j * PH + i] * hb[s][i];
-    ha[s][j] = fmaxf(a, 0.0f);
-  }
+  mlp_layer_mfma(hb, ha, P + OW3, P + OB3, lane);
   __syncthreads();
-  if (H2)
-    for (int s = 0; s < SB; ++s)
-      if (b0 + s < B) H2[size_t(b0 + s) * PH + j] = hb[s][j];
-  if (H3)
-    for (int s = 0; s < SB; ++s)
-      if (b0 + s < B) H3[size_t(b0 + s) * PH + j] = ha[s][j];
-  for (int s = 0; s < SB; ++s) {
-    float v = P[OW4 + j] * ha[s][j];
+  if (H2 || H3)
+    for (int s = 0; s < FR; ++s)
+      if (b0 + s < B)
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if ((j & 63) == 0) red[s][j >> 6] = v;
-  }
-  __syncthreads();
-  if (j < SB && b0 + j < B) O[b0 + j] = red[j][0] + red[j][1] + P[OB4];
+        for (int q = 0; q < 2; ++q) {
+          const int n = lane + 64 * q;
+          if (H2) H2[size_t(b0 + s) * PH + n] = hb[s * FLP + n];
+          if (H3) H3[size_t(b0 + s) * PH + n] = ha[s * FLP + n];
+        }
+  // layer 4: sample lane % 16, a quarter of the neurons per lane, then the
+  // four quarters summed in a fixed order
+  const int s = lane & 15, k0 = (lane >> 4) * (PH / 4);
+  float v = 0.0f;
+  for (int k = 0; k < PH / 4; ++k) v += P[OW4 + k0 + k] * ha[s * FLP + k0 + k];
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  if (lane < FR && b0 + s < B) O[b0 + s] = v + P[OB4];
 }
 
 // dL/do per sample and the loss terms: g = GMAX sigmoid(o),
@@ -126,79 +188,227 @@ __global__ void k_mlp_loss(const float* __restrict__ O, const float* __restrict_
   if (threadIdx.x == 0) lpart[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-// Backward through the hidden layers for SB samples per workgroup:
-// D3 = dL/d(pre3), D2 = dL/d(pre2), D1 = dL/d(pre1) (ReLU masks applied).
-__global__ void __launch_bounds__(PH)
+// One backward layer of one wave on the BF16 matrix cores: out[s][j] =
+// relu'(Hp[b0 + s][j]) sum_i in[s][i] W[i][j] (W row-major [PH][PH], BF16
+// values), also stored to Dout for the weight gradients.  Operands and
+// splits as in mlp_layer_mfma, with W's columns as the B operand.
+__device__ inline void mlp_layer_bwd_mfma(const float* in, float* out, const float* __restrict__ W,
+                                          const float* __restrict__ Hp, float* __restrict__ Dout,
+                                          int b0, int B, int lane) {
+  const int r = lane & 15, kg = (lane >> 4) * 8;
+  us8 a[PH / 32][3];
+#pragma unroll
+  for (int ks = 0; ks < PH / 32; ++ks)
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const float x = in[r * FLP + ks * 32 + kg + t];
+      const float x0 = bf16_round(x), x1 = bf16_round(x - x0), x2 = bf16_round(x - x0 - x1);
+      a[ks][0][t] = bf16_hi(x0);
+      a[ks][1][t] = bf16_hi(x1);
+      a[ks][2][t] = bf16_hi(x2);
+    }
+#pragma unroll
+  for (int jb = 0; jb < PH / 16; ++jb) {
+    const int j = jb * 16 + r;
+    f4v acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < PH / 32; ++ks) {
+      us8 wb;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) wb[t] = bf16_hi(W[(ks * 32 + kg + t) * PH + j]);
+      const bf8 b = __builtin_bit_cast(bf8, wb);
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a[ks][t]), b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int sr = 4 * (lane >> 4) + e, b = b0 + sr;
+      float v = 0.0f;
+      if (b < B) {
+        v = Hp[size_t(b) * PH + j] > 0.0f ? acc[e] : 0.0f;
+        Dout[size_t(b) * PH + j] = v;
+      }
+      out[sr * FLP + j] = v;
+    }
+  }
+}
+
+// dL/d(pre-activation) of the three hidden layers, FR samples per wave:
+// D3 = dO W4 relu'(H3), D2 = (D3 W3) relu'(H2), D1 = (D2 W2) relu'(H1).
+__global__ void __launch_bounds__(64 * FWV)
 k_mlp_bwd_act(const float* __restrict__ P, const float* __restrict__ H1,
               const float* __restrict__ H2, const float* __restrict__ H3,
               const float* __restrict__ dO, int B, float* __restrict__ D1,
               float* __restrict__ D2, float* __restrict__ D3, const int* __restrict__ sky_gate) {
   if (sky_gate != nullptr && *sky_gate == 0) return;
-  __shared__ float da[SB][PH], db[SB][PH];
-  const int j = threadIdx.x, b0 = blockIdx.x * SB;
-  for (int s = 0; s < SB; ++s) {
-    const int b = b0 + s;
-    float v = 0.0f;
-    if (b < B) v = (H3[size_t(b) * PH + j] > 0.0f) ? dO[b] * P[OW4 + j] : 0.0f;
-    da[s][j] = v;
-    if (b < B) D3[size_t(b) * PH + j] = v;
-  }
-  __syncthreads();
-  for (int s = 0; s < SB; ++s) {
-    const int b = b0 + s;
-    float v = 0.0f;
-    for (int i = 0; i < PH; ++i) v += P[OW3 + i * PH + j] * da[s][i];
-    if (b < B) v = (H2[size_t(b) * PH + j] > 0.0f) ? v : 0.0f;
-    db[s][j] = v;
-    if (b < B) D2[size_t(b) * PH + j] = v;
-  }
-  __syncthreads();
-  for (int s = 0; s < SB; ++s) {
-    const int b = b0 + s;
-    float v = 0.0f;
-    for (int i = 0; i < PH; ++i) v += P[OW2 + i * PH + j] * db[s][i];
-    if (b < B) {
-      v = (H1[size_t(b) * PH + j] > 0.0f) ? v : 0.0f;
-      D1[size_t(b) * PH + j] = v;
+  __shared__ float hs[FWV][2][FR * FLP];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int b0 = (blockIdx.x * FWV + wv) * FR;
+  float* da = hs[wv][0];
+  float* db = hs[wv][1];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int n = lane + 64 * q;
+    const float w4 = P[OW4 + n];
+    for (int sr = 0; sr < FR; ++sr) {
+      const int b = b0 + sr;
+      float v = 0.0f;
+      if (b < B) {
+        v = H3[size_t(b) * PH + n] > 0.0f ? dO[b] * w4 : 0.0f;
+        D3[size_t(b) * PH + n] = v;
+      }
+      da[sr * FLP + n] = v;
     }
+  }
+  __syncthreads();
+  mlp_layer_bwd_mfma(da, db, P + OW3, H2, D2, b0, B, lane);
+  __syncthreads();
+  mlp_layer_bwd_mfma(db, da, P + OW2, H1, D1, b0, B, lane);
+}
+
+// ---- parameter gradient
+// x = v[0][t] + v[1][t] + v[2][t] as three BF16 bit patterns (exact for
+// normal FP32 x: 8 significant bits per term, rounded to nearest at each step).
+__device__ inline void split3_at(float x, us8 (&v)[3], int t) {
+  const float a = bf16_round(x), b = bf16_round(x - a), c = bf16_round(x - a - b);
+  v[0][t] = bf16_hi(a);
+  v[1][t] = bf16_hi(b);
+  v[2][t] = bf16_hi(c);
+}
+
+constexpr int GCH = 64;    // samples per chunk of the gradient partials
+constexpr int GSUB = 32;   // samples per MFMA step (the contraction of one MFMA)
+
+// Partial gradient of every parameter over the samples of chunk blockIdx.x:
+// part[chunk][p].  The two 128 x 128 weight blocks are D^T H over the chunk
+// on the BF16 matrix cores: both FP32 operands split in three BF16 terms,
+// the six products t_i u_j with i + j <= 2 (the dropped ones are below
+// 2^-24 of the product), FP32 accumulation; wave w owns the output rows
+// 32 w .. 32 w + 31 of both blocks.  W1, the biases, W4 and b4 are FP32
+// sums over the chunk, one thread per parameter.  The chunk goes through LDS
+// GSUB samples at a time.
+__global__ void __launch_bounds__(256)
+k_mlp_grad_part(const float* __restrict__ S, const float* __restrict__ H1,
+                const float* __restrict__ H2, const float* __restrict__ H3,
+                const float* __restrict__ dO, const float* __restrict__ D1,
+                const float* __restrict__ D2, const float* __restrict__ D3, int B,
+                float* __restrict__ part, const int* __restrict__ sky_gate) {
+  if (sky_gate != nullptr && *sky_gate == 0) return;
+  __shared__ float ds[2][GSUB][FLP], hs[2][GSUB][FLP];   // (D2, H1), (D3, H2)
+  __shared__ float d1s[GSUB][FLP], h3s[GSUB][FLP], xs[GSUB][PIN], dos[GSUB];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int c0 = blockIdx.x * GCH, c1 = min(B, c0 + GCH);
+  float* out = part + size_t(blockIdx.x) * NPAR;
+  const int r = lane & 15, kg = (lane >> 4) * 8;
+  f4v acc[2][2][PH / 16];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+      for (int ib = 0; ib < PH / 16; ++ib) acc[m][jb][ib] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+  constexpr int PI[6] = {0, 0, 1, 0, 1, 2};
+  constexpr int PJ[6] = {0, 1, 0, 2, 1, 0};
+  // W1, b1, b2, b3, W4, b4: thread tid owns parameters tid + 256 q
+  constexpr int NSMALL = PH * PIN + 4 * PH + 1;
+  constexpr int NQ = (NSMALL + 255) / 256;
+  float sv[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) sv[q] = 0.0f;
+  for (int s0 = c0; s0 < c1; s0 += GSUB) {
+    __syncthreads();
+    for (int e = tid; e < GSUB * PH; e += 256) {
+      const int sr = e / PH, n = e % PH, b = s0 + sr;
+      const bool ok = b < c1;
+      const size_t o = size_t(b) * PH + n;
+      ds[0][sr][n] = ok ? D2[o] : 0.0f;
+      hs[0][sr][n] = ok ? H1[o] : 0.0f;
+      ds[1][sr][n] = ok ? D3[o] : 0.0f;
+      hs[1][sr][n] = ok ? H2[o] : 0.0f;
+      d1s[sr][n] = ok ? D1[o] : 0.0f;
+      h3s[sr][n] = ok ? H3[o] : 0.0f;
+    }
+    if (tid < GSUB * PIN) {
+      const int sr = tid / PIN, i = tid % PIN, b = s0 + sr;
+      xs[sr][i] = b < c1 ? S[size_t(b) * 6 + i] : 0.0f;
+    }
+    if (tid < GSUB) dos[tid] = s0 + tid < c1 ? dO[s0 + tid] : 0.0f;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      us8 a[2][3];
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) split3_at(ds[m][kg + t][(2 * wv + jb) * 16 + r], a[jb], t);
+#pragma unroll
+      for (int ib = 0; ib < PH / 16; ++ib) {
+        us8 u[3];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) split3_at(hs[m][kg + t][ib * 16 + r], u, t);
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+          for (int q = 0; q < 6; ++q)
+            acc[m][jb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                __builtin_bit_cast(bf8, a[jb][PI[q]]), __builtin_bit_cast(bf8, u[PJ[q]]),
+                acc[m][jb][ib], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int p = tid + 256 * q;
+      float v = 0.0f;
+      if (p < PH * PIN) {                          // W1[j][i]: D1[b][j] x[b][i]
+        const int j = p / PIN, i = p % PIN;
+        for (int sr = 0; sr < GSUB; ++sr) v += d1s[sr][j] * xs[sr][i];
+      } else if (p < PH * PIN + 3 * PH) {          // b1, b2, b3
+        const int l = (p - PH * PIN) / PH, j = (p - PH * PIN) % PH;
+        for (int sr = 0; sr < GSUB; ++sr) v += l == 0 ? d1s[sr][j] : ds[l - 1][sr][j];
+      } else if (p < PH * PIN + 4 * PH) {          // W4[i]: dO[b] H3[b][i]
+        const int i = p - PH * PIN - 3 * PH;
+        for (int sr = 0; sr < GSUB; ++sr) v += dos[sr] * h3s[sr][i];
+      } else if (p < NSMALL) {                     // b4
+        for (int sr = 0; sr < GSUB; ++sr) v += dos[sr];
+      }
+      sv[q] += v;
+    }
+  }
+  // output rows j (neuron of the layer's output) and columns i (its input)
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+      for (int ib = 0; ib < PH / 16; ++ib)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int j = (2 * wv + jb) * 16 + 4 * (lane >> 4) + e, i = ib * 16 + r;
+          out[(m ? OW3 : OW2) + j * PH + i] = acc[m][jb][ib][e];
+        }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int p = tid + 256 * q;
+    if (p < PH * PIN) out[OW1 + p] = sv[q];
+    else if (p < PH * PIN + 3 * PH) {
+      const int l = (p - PH * PIN) / PH, j = (p - PH * PIN) % PH;
+      out[(l == 0 ? OB1 : l == 1 ? OB2 : OB3) + j] = sv[q];
+    } else if (p < PH * PIN + 4 * PH) out[OW4 + p - PH * PIN - 3 * PH] = sv[q];
+    else if (p < NSMALL) out[OB4] = sv[q];
   }
 }
 
-// Weight gradients: one thread per parameter, sums over the batch in FP32.
-__global__ void k_mlp_bwd_w(const float* __restrict__ S, const float* __restrict__ H1,
-                            const float* __restrict__ H2, const float* __restrict__ H3,
-                            const float* __restrict__ dO, const float* __restrict__ D1,
-                            const float* __restrict__ D2, const float* __restrict__ D3, int B,
-                            float* __restrict__ G, const int* __restrict__ sky_gate) {
+// G[p] = sum over the chunks of part[chunk][p], in chunk order.
+__global__ void k_mlp_grad_sum(const float* __restrict__ part, int nchunk, float* __restrict__ G,
+                               const int* __restrict__ sky_gate) {
   if (sky_gate != nullptr && *sky_gate == 0) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= NPAR) return;
-  float acc = 0.0f;
-  if (p < OB1) {                 // W1[j][i]: D1[b][j] x[b][i]
-    const int j = p / PIN, i = p % PIN;
-    for (int b = 0; b < B; ++b) acc += D1[size_t(b) * PH + j] * S[size_t(b) * 6 + i];
-  } else if (p < OW2) {          // b1
-    const int j = p - OB1;
-    for (int b = 0; b < B; ++b) acc += D1[size_t(b) * PH + j];
-  } else if (p < OB2) {          // W2[j][i]: D2[b][j] H1[b][i]
-    const int q = p - OW2, j = q / PH, i = q % PH;
-    for (int b = 0; b < B; ++b) acc += D2[size_t(b) * PH + j] * H1[size_t(b) * PH + i];
-  } else if (p < OW3) {
-    const int j = p - OB2;
-    for (int b = 0; b < B; ++b) acc += D2[size_t(b) * PH + j];
-  } else if (p < OB3) {          // W3[j][i]: D3[b][j] H2[b][i]
-    const int q = p - OW3, j = q / PH, i = q % PH;
-    for (int b = 0; b < B; ++b) acc += D3[size_t(b) * PH + j] * H2[size_t(b) * PH + i];
-  } else if (p < OW4) {
-    const int j = p - OB3;
-    for (int b = 0; b < B; ++b) acc += D3[size_t(b) * PH + j];
-  } else if (p < OB4) {          // W4[i]: dO[b] H3[b][i]
-    const int i = p - OW4;
-    for (int b = 0; b < B; ++b) acc += dO[b] * H3[size_t(b) * PH + i];
-  } else {
-    for (int b = 0; b < B; ++b) acc += dO[b];
-  }
-  G[p] = acc;
+  float v = 0.0f;
+#pragma unroll 8
+  for (int c = 0; c < nchunk; ++c) v += part[size_t(c) * NPAR + p];
+  G[p] = v;
 }
 
 __global__ void k_adam(float* __restrict__ P, const float* __restrict__ G, float* __restrict__ M,
@@ -409,8 +619,8 @@ void precond_round(const float* P, float* Pb, hipStream_t st) {
 void precond_forward(const float* Pb, const float* X, int B, float* H1, float* H2, float* H3,
                      float* O, hipStream_t st) {
   if (B <= 0) return;
-  hipLaunchKernelGGL(k_mlp_fwd, dim3((B + SB - 1) / SB), dim3(PH), 0, st, Pb, X, 6, B, H1, H2,
-                     H3, O, g_launch_gate);
+  hipLaunchKernelGGL(k_mlp_fwd, dim3((B + FR * FWV - 1) / (FR * FWV)), dim3(64 * FWV), 0, st, Pb, X,
+                     6, B, H1, H2, H3, O, g_launch_gate);
 }
 
 void precond_features(const double* pow, const double* eps, int stride, int ns, double e0,
@@ -428,19 +638,23 @@ void precond_gains(const float* O, int n, float* gain, hipStream_t st) {
 
 double precond_loss_grad(const float* Pb, const float* S, int B, double wsum, float* H1,
                          float* H2, float* H3, float* O, float* dO, float* D1, float* D2,
-                         float* D3, float* G, double* dscratch, int want_loss, hipStream_t st) {
+                         float* D3, float* G, float* gpart, double* dscratch, int want_loss,
+                         hipStream_t st) {
   if (B <= 0) return 0.0;
   precond_forward(Pb, S, B, H1, H2, H3, O, st);
   const int nb = (B + 255) / 256;
   hipLaunchKernelGGL(k_mlp_loss, dim3(nb), dim3(256), 0, st, (const float*)O, S, B, wsum, dO,
                      dscratch, g_launch_gate);
   hipLaunchKernelGGL(k_sum_d, dim3(1), dim3(64), 0, st, (const double*)dscratch, nb, dscratch + nb, g_launch_gate);
-  hipLaunchKernelGGL(k_mlp_bwd_act, dim3((B + SB - 1) / SB), dim3(PH), 0, st, Pb,
+  hipLaunchKernelGGL(k_mlp_bwd_act, dim3((B + FR * FWV - 1) / (FR * FWV)), dim3(64 * FWV), 0, st, Pb,
                      (const float*)H1, (const float*)H2, (const float*)H3, (const float*)dO, B,
                      D1, D2, D3, g_launch_gate);
-  hipLaunchKernelGGL(k_mlp_bwd_w, dim3((NPAR + 255) / 256), dim3(256), 0, st, S,
-                     (const float*)H1, (const float*)H2, (const float*)H3, (const float*)dO,
-                     (const float*)D1, (const float*)D2, (const float*)D3, B, G, g_launch_gate);
+  const int nchunk = (B + GCH - 1) / GCH;
+  hipLaunchKernelGGL(k_mlp_grad_part, dim3(nchunk), dim3(256), 0, st, S, (const float*)H1,
+                     (const float*)H2, (const float*)H3, (const float*)dO, (const float*)D1,
+                     (const float*)D2, (const float*)D3, B, gpart, g_launch_gate);
+  hipLaunchKernelGGL(k_mlp_grad_sum, dim3((NPAR + 255) / 256), dim3(256), 0, st, (const float*)gpart,
+                     nchunk, G, g_launch_gate);
   double loss = 0.0;
   if (want_loss) {
     hipMemcpyAsync(&loss, dscratch + nb, sizeof(double), hipMemcpyDeviceToHost, st);
@@ -493,6 +707,10 @@ void precond_targets(int prec, const void* bpsi, const void* bh, const void* bd,
                        (const float2*)bh, (const float2*)bd, (const float2*)bhd, beps, V, part, g_launch_gate);
   hipLaunchKernelGGL(k_pc_solve, dim3((ns + 63) / 64), dim3(64), 0, st, (const double*)part, nblk,
                      ns, S, g_launch_gate);
+}
+
+size_t precond_gpart_bytes(int rows) {
+  return sizeof(float) * size_t(NPAR) * size_t((rows + GCH - 1) / GCH);
 }
 
 size_t precond_gram_bytes(int ns) { return sizeof(double) * size_t(ns) * precond_gram_blocks() * NG; }

@@ -89,7 +89,7 @@ struct Layout {
   // gradient, Adam moments, sample rows, activations, shell powers, gains,
   // sampled-state batch buffers
   size_t pc_P, pc_Pb, pc_G, pc_M, pc_V, pc_S, pc_H[3], pc_D[3], pc_O, pc_dO, pc_X, pc_pow,
-      pc_gain, pc_dscr, pc_gram, pc_idx, pc_beps, pc_b[4];
+      pc_gain, pc_dscr, pc_gram, pc_idx, pc_beps, pc_b[4], pc_gpart;
   int pc_nb;   // largest sampled-state batch (states x shells)
   size_t plA, plB, plT, plU, plS;                  // FP16 split planes, scales (mixed only)
   size_t dens[2], der[2], mf[2], mf32[2], vc, fscratch, dens_part, epart, energy, info;
@@ -189,6 +189,7 @@ Layout plan(const sky_box_desc& d) {
     L.pc_pow = take(sizeof(double) * pw);
     L.pc_gain = take(sizeof(float) * pw);
     L.pc_dscr = take(sizeof(double) * (PC_CAP / 256 + 4));
+    L.pc_gpart = take(precond_gpart_bytes(PC_CAP));
     L.pc_gram = take(precond_gram_bytes(precond_ns_max()));
     L.pc_idx = take(sizeof(int) * precond_ns_max());
     L.pc_beps = take(sizeof(double) * L.pc_nb);
@@ -880,7 +881,7 @@ double precond_pass(sky_ctx* c, double wsum, int want_loss) {
       c->at<float>(c->lay.pc_H[0]), c->at<float>(c->lay.pc_H[1]), c->at<float>(c->lay.pc_H[2]),
       c->at<float>(c->lay.pc_O), c->at<float>(c->lay.pc_dO), c->at<float>(c->lay.pc_D[0]),
       c->at<float>(c->lay.pc_D[1]), c->at<float>(c->lay.pc_D[2]), c->at<float>(c->lay.pc_G),
-      c->at<double>(c->lay.pc_dscr), want_loss, c->st);
+      c->at<float>(c->lay.pc_gpart), c->at<double>(c->lay.pc_dscr), want_loss, c->st);
 }
 
 // Adam over every held row; returns the loss before the last update.

@@ -88,11 +88,14 @@ void precond_forward(const float* Pb, const float* X, int B, float* H1, float* H
 void precond_features(const double* pow, const double* eps, int stride, int ns, double e0,
                       double hb2m, double kmax, float* X, hipStream_t st);
 void precond_gains(const float* O, int n, float* gain, hipStream_t st);
-// loss and parameter gradient G; dscratch >= B/256 + 2 doubles; want_loss:
-// synchronise and return the loss (else 0).
+// loss and parameter gradient G; gpart: precond_gpart_bytes(B) of chunk
+// partials of G; dscratch >= B/256 + 2 doubles; want_loss: synchronise and
+// return the loss (else 0).
 double precond_loss_grad(const float* Pb, const float* S, int B, double wsum, float* H1,
                          float* H2, float* H3, float* O, float* dO, float* D1, float* D2,
-                         float* D3, float* G, double* dscratch, int want_loss, hipStream_t st);
+                         float* D3, float* G, float* gpart, double* dscratch, int want_loss,
+                         hipStream_t st);
+size_t precond_gpart_bytes(int rows);
 void precond_adam(float* P, const float* G, float* M, float* V, int step, float lr,
                   hipStream_t st);
 void precond_gather(int prec, const void* psi, const void* hpsi, const double* eps,
