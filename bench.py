@@ -52,7 +52,7 @@ MEASURED_TRAFFIC = {
 # (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, profiles/grid_kernels_rod48_pmc.md),
 # reported while k_grid.hip keeps the hash they were taken on.
 MEASURED_PHASE_TRAFFIC = dict(
-    source="paper_1610_07522_amd/csrc/k_grid.hip", sha256_16="f9861b29455e899b",
+    source="paper_1610_07522_amd/csrc/k_grid.hip", sha256_16="d6d130e6e9b5ffa4",
     apply_h=22.662e9, damp=22.654e9, densities=9.402e9)
 
 

@@ -290,9 +290,14 @@ k_h_plane(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ hpsi, MeanFieldPt
   const size_t soff = size_t(blockIdx.y) * 2 * N3;
   const cpx<T>* p = psi + soff;
   cpx<T>* hp = hpsi + soff;
-  for (int i = threadIdx.x; i < 2 * N2; i += C::THREADS) {
-    const int s = i / N2, e = i - s * N2;
-    P[s * SP + (e / N) * PITCH + e % N] = p[s * N3 + zoff + e];
+  constexpr int NIT = (2 * N2 + C::THREADS - 1) / C::THREADS;   // unrolled: loads go out together
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int i = threadIdx.x + it * C::THREADS;
+    if (i < 2 * N2) {
+      const int s = i / N2, e = i - s * N2;
+      P[s * SP + (e / N) * PITCH + e % N] = p[s * N3 + zoff + e];
+    }
   }
   __syncthreads();
   const T kunit = T(g.kunit);
@@ -375,12 +380,17 @@ k_damp_fwd_xy(const cpx<T>* __restrict__ psi, const cpx<T>* __restrict__ hpsi,
   const size_t soff = size_t(blockIdx.y) * 2 * N3;
   const T e = T(eps[blockIdx.y]);
   double r2 = 0.0;
-  for (int i = threadIdx.x; i < 2 * N2; i += C::THREADS) {
-    const int s = i / N2, q = i - s * N2;
-    const size_t o = soff + s * N3 + zoff + q;
-    const cpx<T> res = hpsi[o] - e * psi[o];
-    r2 += double(res.re) * double(res.re) + double(res.im) * double(res.im);
-    P[s * SP + (q / N) * PITCH + q % N] = res;
+  constexpr int NIT = (2 * N2 + C::THREADS - 1) / C::THREADS;   // unrolled: loads go out together
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int i = threadIdx.x + it * C::THREADS;
+    if (i < 2 * N2) {
+      const int s = i / N2, q = i - s * N2;
+      const size_t o = soff + s * N3 + zoff + q;
+      const cpx<T> res = hpsi[o] - e * psi[o];
+      r2 += double(res.re) * double(res.re) + double(res.im) * double(res.im);
+      P[s * SP + (q / N) * PITCH + q % N] = res;
+    }
   }
   __syncthreads();
   {  // x lines, in place (row ly; rows fastest across the lanes, whose odd
@@ -416,9 +426,13 @@ k_damp_fwd_xy(const cpx<T>* __restrict__ psi, const cpx<T>* __restrict__ hpsi,
         for (int s = 0; s < 2; ++s) P[s * SP + (j + R1 * k2) * PITCH + lx] = vb[s][k2];
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 2 * N2; i += C::THREADS) {
-    const int s = i / N2, q = i - s * N2;
-    out[soff + s * N3 + zoff + q] = P[s * SP + (q / N) * PITCH + q % N];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int i = threadIdx.x + it * C::THREADS;
+    if (i < 2 * N2) {
+      const int s = i / N2, q = i - s * N2;
+      out[soff + s * N3 + zoff + q] = P[s * SP + (q / N) * PITCH + q % N];
+    }
   }
   __syncthreads();   // P is free again: reuse it for the reduction
   const double sum = tree_sum(r2, reinterpret_cast<double*>(P));
@@ -441,9 +455,15 @@ k_damp_inv_xy(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ buf,
   load_twiddles<T, N>(tw);
   const int zoff = blockIdx.x * N2;
   const size_t soff = size_t(blockIdx.y) * 2 * N3;
-  for (int i = threadIdx.x; i < 2 * N2; i += C::THREADS) {
-    const int s = i / N2, q = i - s * N2;
-    P[s * SP + (q / N) * PITCH + q % N] = buf[soff + s * N3 + zoff + q];
+  // fixed trip counts, unrolled: each thread's loads of a loop go out together
+  constexpr int NIT = (2 * N2 + C::THREADS - 1) / C::THREADS;
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int i = threadIdx.x + it * C::THREADS;
+    if (i < 2 * N2) {
+      const int s = i / N2, q = i - s * N2;
+      P[s * SP + (q / N) * PITCH + q % N] = buf[soff + s * N3 + zoff + q];
+    }
   }
   __syncthreads();
   {  // y lines (column lx): frequencies -> positions
@@ -479,12 +499,16 @@ k_damp_inv_xy(const cpx<T>* __restrict__ psi, cpx<T>* __restrict__ buf,
   }
   __syncthreads();
   float am = 0.0f;
-  for (int i = threadIdx.x; i < 2 * N2; i += C::THREADS) {
-    const int s = i / N2, q = i - s * N2;
-    const size_t o = soff + s * N3 + zoff + q;
-    const cpx<T> t = psi[o] - P[s * SP + (q / N) * PITCH + q % N];
-    buf[o] = t;
-    am = fmaxf(am, cabs_max(t));
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int i = threadIdx.x + it * C::THREADS;
+    if (i < 2 * N2) {
+      const int s = i / N2, q = i - s * N2;
+      const size_t o = soff + s * N3 + zoff + q;
+      const cpx<T> t = psi[o] - P[s * SP + (q / N) * PITCH + q % N];
+      buf[o] = t;
+      am = fmaxf(am, cabs_max(t));
+    }
   }
   if (amax != nullptr) block_amax(am, amax);
 }
@@ -759,24 +783,32 @@ k_dens_pass(DensGroups grp, int nstate, int chunk, GridArgs g, double* __restric
 #pragma unroll
     for (int j1 = 0; j1 < R1; ++j1) acc[q][j1] = 0.0;
 
-  // chunks of the flat (group, state) index: every group's states in order
+  // chunks of the flat (group, state) index: every group's states in order;
+  // the next state's line is loaded into registers while this one is
+  // transformed
   const int s0 = blockIdx.y * chunk;
   const int s1 = min(nstate * grp.ngroup, s0 + chunk);
-  for (int fs = s0; fs < s1; ++fs) {
+  auto load_line = [&](int fs, cpx<T> (&dst)[2][R1]) {
     const int t = fs / nstate, st = fs - t * nstate;
-    const T kshift = T(grp.kshift[t][DIR]);
     const cpx<T>* p = reinterpret_cast<const cpx<T>*>(grp.psi[t]) + size_t(st) * 2 * N3;
-    cpx<T> v[2][R1], d[2][R1];
-    if (j < R2) {
 #pragma unroll
-      for (int j1 = 0; j1 < R1; ++j1) {
-        int r = base + (j + R2 * j1) * stride;
-        v[0][j1] = p[r];
-        v[1][j1] = p[N3 + r];
-        d[0][j1] = v[0][j1];
-        d[1][j1] = v[1][j1];
-      }
+    for (int j1 = 0; j1 < R1; ++j1) {
+      const int r = base + (j + R2 * j1) * stride;
+      dst[0][j1] = p[r];
+      dst[1][j1] = p[N3 + r];
     }
+  };
+  cpx<T> vn[2][R1];
+  if (s0 < s1 && j < R2) load_line(s0, vn);
+  for (int fs = s0; fs < s1; ++fs) {
+    const T kshift = T(grp.kshift[fs / nstate][DIR]);
+    cpx<T> v[2][R1], d[2][R1];
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1) {
+      v[0][j1] = d[0][j1] = vn[0][j1];
+      v[1][j1] = d[1][j1] = vn[1][j1];
+    }
+    if (fs + 1 < s1 && j < R2) load_line(fs + 1, vn);
     F::deriv(d, Y, j, tw, kunit, kshift);
     if (j < R2) {
 #pragma unroll
