@@ -199,17 +199,25 @@ __global__ void k_mean_field(Skyrme sk, int n3, double dV, const double* __restr
   }
 }
 
+// out[t] = sum of the block partials of term t in block order (thread t;
+// the loop unrolled so that the loads overlap), out[NTERM] = sum of the terms.
 __global__ void k_energy_final(const double* __restrict__ epart, int nblk, double* __restrict__ out, const int* __restrict__ sky_gate) {
   if (sky_gate != nullptr && *sky_gate == 0) return;
-  if (threadIdx.x != 0) return;
-  double tot = 0.0;
-  for (int t = 0; t < NTERM; ++t) {
+  __shared__ double term[NTERM];
+  const int t = threadIdx.x;
+  if (t < NTERM) {
     double s = 0.0;
+#pragma unroll 8
     for (int b = 0; b < nblk; ++b) s += epart[b * NTERM + t];
     out[t] = s;
-    tot += s;
+    term[t] = s;
   }
-  out[NTERM] = tot;
+  __syncthreads();
+  if (t == 0) {
+    double tot = 0.0;
+    for (int k = 0; k < NTERM; ++k) tot += term[k];
+    out[NTERM] = tot;
+  }
 }
 
 }  // namespace
