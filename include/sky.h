@@ -340,8 +340,10 @@ typedef struct {
  * states are untouched).  Every candidate computes the same result up to
  * the order of floating-point sums.  cache_path (may be NULL): a flat JSON
  * object {"key": value}; shapes found there are used without timing, and
- * newly timed ones are merged into it.  out (may be NULL) receives the
- * shapes in use.  Synchronises the stream.  Errors: SKY_ERR_INVALID (null
+ * newly timed ones are merged into it.  For a mixed box the cache's FP64
+ * entries for the same box (not timed here) are kept for the FP64 iterations
+ * after a precision-ladder switch; without them those use the defaults.
+ * out (may be NULL) receives the shapes in use.  Synchronises the stream.  Errors: SKY_ERR_INVALID (null
  * context, unwritable cache), SKY_ERR_HIP. */
 int sky_autotune(sky_ctx* c, const char* cache_path, sky_tuning* out);
 

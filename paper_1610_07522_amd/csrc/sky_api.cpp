@@ -272,6 +272,12 @@ struct sky_ctx {
     int ovw[2] = {0, 0};   // waves per tile of the mixed overlap product (0: 8)
     int cbw[2] = {0, 0};   // waves per tile of the mixed recombination (0: 8)
     int from_cache = 0;
+    // the FP64 shapes a mixed box takes when the precision ladder switches:
+    // the cache's FP64 entries for the box when sky_autotune saw them, else
+    // the defaults
+    int lines64 = 0;
+    int damp64 = -1;
+    int ovl64[2] = {0, 0};
   } tune;
   // learned preconditioner state
   int pc_count = 0;        // sample rows held
@@ -1489,10 +1495,12 @@ int sky_iterate(sky_ctx* c, int32_t max_iter, double tol, sky_report* rep) {
                        size_t(c->m_of(s)) * c->V, st);
       c->prec = 0;
       c->hpsi_lagged = false;
-      // launch shapes were tuned for the mixed kernels: FP64 defaults from here
-      c->tune.lines = 0;
-      c->tune.damp_xy = -1;
-      c->tune.ovl[0] = c->tune.ovl[1] = 0;
+      // launch shapes were tuned for the mixed kernels: the FP64 ones the
+      // tuner found in its cache for this box, else the defaults, from here
+      c->tune.lines = c->tune.lines64;
+      c->tune.damp_xy = c->tune.damp64;
+      c->tune.ovl[0] = c->tune.ovl64[0];
+      c->tune.ovl[1] = c->tune.ovl64[1];
       fields(c);
       c->switched_at = c->iter_count + it + 1;
     }
@@ -1643,6 +1651,27 @@ int sky_autotune(sky_ctx* c, const char* cache_path, sky_tuning* out) {
     ksq[q] = "square_split/m" + std::to_string(c->nq[q]);
   }
   int timed = 0;
+  if (c->prec) {   // FP64 shapes for a later ladder switch: cached entries only, not timed
+    const std::string sn = "/n" + std::to_string(c->n) + "/fp64";
+    int cand[4];
+    const int nl = h_pass_lines(c->n, 0, cand);
+    const int lv = cache_get(kv, "h_lines" + sn);
+    c->tune.lines64 = 0;
+    for (int i = 0; i < nl; ++i)
+      if (cand[i] == lv) c->tune.lines64 = lv;
+    const int dv = cache_has(kv, "damp_xy" + sn) ? cache_get(kv, "damp_xy" + sn) : -1;
+    c->tune.damp64 = (dv == 0 || (dv == 1 && damp_slices_available(c->n, 0))) ? dv : -1;
+    for (int q = 0; q < 2; ++q) {
+      c->tune.ovl64[q] = 0;
+      if (c->nq[q] == 0) continue;
+      int oc[3];
+      const int no = overlap_split_candidates(c->nq[q], c->V, oc);
+      const int ov = cache_get(kv, "overlap_split/m" + std::to_string(c->nq[q]) + "/k" +
+                                       std::to_string(c->V) + "/fp64");
+      for (int i = 0; i < no; ++i)
+        if (oc[i] == ov) c->tune.ovl64[q] = ov;
+    }
+  }
   // lines per workgroup of the h passes (species 0, or 1 if 0 is empty)
   {
     const int q = c->nq[0] > 0 ? 0 : 1;

@@ -203,3 +203,24 @@ def test_plane_product_wave_layouts(torch_mod, tmp_path, case):
         rep = box.iterate(3)
         outs[waves] = rep["energy"]
     assert abs(outs[4] - outs[8]) <= 2e-6 * abs(outs[8])
+
+
+def test_ladder_switch_takes_the_cached_fp64_shapes(torch_mod, tmp_path):
+    """A mixed box tuned against a cache that also holds the box's FP64
+    entries runs the precision ladder's FP64 iterations with those shapes."""
+    from paper_1610_07522_amd import sky
+    w = CASES["n32_70p33_slab"]
+    raw = inputs.raw_states(w)
+    cache = tmp_path / "tune.json"
+    b64 = _box(w, 0)
+    b64.init_box(to_dev(raw[0]), to_dev(raw[1]))
+    t64 = b64.autotune(str(cache))
+    mixed = sky.Box(sky.desc_from_workload(w, precision=sky.SKY_MIXED, ladder_tol=10.0))
+    mixed.init_box(to_dev(raw[0]), to_dev(raw[1]))
+    tm = mixed.autotune(str(cache))
+    assert not tm["from_cache"]   # the mixed shapes were timed
+    rep = mixed.iterate(2)
+    assert rep["precision"] == 0   # the ladder switched to FP64
+    t = mixed.tuning()
+    for key in ("h_lines", "damp_xy", "overlap_split"):
+        assert t[key] == t64[key], (key, t[key], t64[key])
