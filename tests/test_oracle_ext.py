@@ -500,3 +500,50 @@ def test_one_h_self_consistent_same_fixed_point():
     rho = (w.n_neutrons + w.n_protons) / L ** 3
     want = L ** 3 * _textbook_symmetric(dict(w.params), rho, 2 * k2 / L ** 3)
     assert st.E["total"] == pytest.approx(want, rel=1e-11)
+
+
+# ------------------------------------------------------------ degenerate subspaces
+def test_rotation_inside_a_degenerate_cluster_leaves_the_step_invariant():
+    """After an exact Rayleigh-Ritz step with the mean field held fixed, the
+    states are Ritz vectors of that h.  Rotating the states of an exactly
+    degenerate cluster (Kramers pairs at least) by any unitary W maps the
+    residuals to r W and the damped states to phi W, so the next step's Ritz
+    values, Delta-eps and densities are those of the unrotated states, while
+    the individual states differ: which basis of a degenerate subspace a
+    trajectory carries does not change what the iteration computes."""
+    import copy
+    g = Grid(8, 1.0)
+    w = inputs.small_workload("dg", 8, 14, 4, init="slab", seed=21, noise=0.0)
+    rn, rp = inputs.raw_states(w)
+    st = so.initial_state(rn, rp, g, SLY4, 0.45, 100.0)
+    lam = so.iterate(st, self_consistent=False).ritz[0]
+    scale = np.abs(lam).max()
+    # clusters of Ritz values equal to rounding
+    clusters, a = [], 0
+    while a < lam.size:
+        b = a + 1
+        while b < lam.size and abs(lam[b] - lam[a]) <= 1e-11 * scale:
+            b += 1
+        if b - a >= 2:
+            clusters.append((a, b))
+        a = b
+    assert clusters, lam   # the test needs a degenerate cluster
+    a, b = max(clusters, key=lambda c: c[1] - c[0])
+    rng = np.random.default_rng(5)
+    k = b - a
+    W, _ = np.linalg.qr(rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k)))
+    rot = copy.deepcopy(st)
+    block = rot.psi[0][a:b].reshape(k, -1)
+    rot.psi[0][a:b] = (W.T @ block).reshape(rot.psi[0][a:b].shape)   # psi_j' = sum_i psi_i W_ij
+    assert np.abs(rot.psi[0][a:b] - st.psi[0][a:b]).max() > 0.1      # the states do differ
+    d_before = ph.densities(st.psi[0], g)
+    d_rot = ph.densities(rot.psi[0], g)
+    assert np.abs(d_rot.rho - d_before.rho).max() <= 1e-12 * np.abs(d_before.rho).max()
+    r1 = so.iterate(st, self_consistent=False)
+    r2 = so.iterate(rot, self_consistent=False)
+    assert np.abs(r2.ritz[0] - r1.ritz[0]).max() <= 1e-10 * scale
+    assert r2.de == pytest.approx(r1.de, rel=1e-10)
+    d1, d2 = ph.densities(st.psi[0], g), ph.densities(rot.psi[0], g)
+    for name in ("rho", "tau", "J"):
+        x1, x2 = getattr(d1, name), getattr(d2, name)
+        assert np.abs(x2 - x1).max() <= 1e-9 * np.abs(x1).max(), name
